@@ -1,0 +1,243 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (oracle/vmc_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the CPU
+baseline leg of bench.py; never by the product package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+OB_PERIODIC_GAUSS, OB_OPEN_GAUSS, OB_OPEN_STO = 0, 1, 2
+OP_EWALD, OP_COULOMB_OPEN, OP_HARMONIC, OP_NONE = 0, 1, 2, 3
+STEP_CFOLD, STEP_NOISE_CORR, STEP_NO_SCORR = 1, 2, 4
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc -O2 (no fast-math) and OpenMP over walkers."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-o", LIB_PATH,
+           os.path.join(HERE, "vmc_oracle.c"), "-lm"]
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    return LIB_PATH
+
+
+class OSys(C.Structure):
+    _fields_ = [("n_p", C.c_int), ("n_up", C.c_int), ("n_dn", C.c_int), ("n_orb", C.c_int),
+                ("L", C.c_double), ("basis_kind", C.c_int), ("pot_kind", C.c_int),
+                ("kappa", C.c_double), ("nmax", C.c_int), ("jastrow_on", C.c_int),
+                ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
+                ("R", C.POINTER(C.c_double)), ("zeta", C.POINTER(C.c_double)),
+                ("C", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        _lib = C.CDLL(LIB_PATH)
+        _setup(_lib)
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _setup(l):
+    P = C.POINTER
+    d, i, u32 = C.c_double, C.c_int, C.c_uint32
+    l.o_philox.argtypes = [P(u32), P(u32), P(u32)]
+    l.o_u01.argtypes = [u32, u32]
+    l.o_u01.restype = d
+    l.o_normals.argtypes = [u32, u32, u32, i, P(d)]
+    l.o_basis.argtypes = [P(OSys), i, P(d), P(d)]
+    l.o_jastrow.argtypes = [P(OSys), P(d), P(d), P(d), P(d)]
+    l.o_potential.argtypes = [P(OSys), P(d), P(d), P(d)]
+    l.o_potential.restype = d
+    l.o_local.argtypes = [P(OSys), P(d), P(d), P(d), P(d), P(d), P(d)]
+    l.o_huckel.argtypes = [i, d, P(d), P(d), i, P(d), P(d)]
+    l.o_vmc_run.argtypes = [P(OSys), i, P(d), i, i, d, u32, u32, u32, P(d), P(C.c_int64), i]
+    l.o_reduce.argtypes = [i, i, i, P(d), P(d), P(d), P(d), P(d), P(d)]
+    l.o_build_S.argtypes = [i, i, P(d), P(d), P(d)]
+    l.o_build_S.restype = None
+    l.o_cholesky.argtypes = [i, P(d), P(d)]
+    l.o_langevin.argtypes = [i, d, P(d), P(d), P(d), P(d), P(d), d, d, d, C.c_uint, u32, u32, u32]
+    l.o_langevin_harmonic_run.argtypes = [i, P(d), P(d), d, d, d, C.c_uint, u32, i, P(d), P(d), i]
+    l.o_toy_run.argtypes = [d, d, d, d, i, d, d, d, i, u32, i, P(d), P(d), P(d)]
+
+
+class System:
+    """Holds the arrays an OSys points to (keeps them alive)."""
+
+    def __init__(self, R, zeta, C_mo, L=0.0, n_up=None, n_dn=None, basis=OB_PERIODIC_GAUSS,
+                 pot=OP_EWALD, kappa=None, nmax=9, jastrow=True, a_par=0.25, a_anti=0.5, b=1.0):
+        self.R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1, 3)
+        n_p = self.R.shape[0]
+        self.zeta = np.ascontiguousarray(zeta, dtype=np.float64).reshape(n_p)
+        self.C = np.ascontiguousarray(C_mo, dtype=np.float64).reshape(n_p, -1)
+        if n_up is None:
+            n_up = n_p // 2
+        if n_dn is None:
+            n_dn = n_p - n_up
+        self.n_up, self.n_dn, self.L = n_up, n_dn, float(L)
+        if kappa is None:
+            kappa = 8.0 / L if L > 0 else 0.0
+        self.s = OSys(n_p, n_up, n_dn, self.C.shape[1], float(L), basis, pot, float(kappa), int(nmax),
+                      int(bool(jastrow)), a_par, a_anti, b, _dp(self.R), _dp(self.zeta), _dp(self.C))
+
+    @property
+    def n_p(self):
+        return self.R.shape[0]
+
+    @property
+    def ne(self):
+        return self.n_up + self.n_dn
+
+    def basis(self, a, r):
+        out = np.zeros(14)
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        lib().o_basis(C.byref(self.s), a, _dp(r), _dp(out))
+        return out
+
+    def jastrow(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        U = np.zeros(1)
+        g = np.zeros((self.ne, 3))
+        lp = np.zeros(self.ne)
+        lib().o_jastrow(C.byref(self.s), _dp(x), _dp(U), _dp(g), _dp(lp))
+        return U[0], g, lp
+
+    def potential(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        dR = np.zeros((self.n_p, 3))
+        dx = np.zeros((self.ne, 3))
+        V = lib().o_potential(C.byref(self.s), _dp(x), _dp(dR), _dp(dx))
+        return V, dR, dx
+
+    def local(self, x, derivs=True):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        lnpsi, sign, EL = np.zeros(1), np.zeros(1), np.zeros(1)
+        dl = np.zeros(3 * self.n_p)
+        de = np.zeros(3 * self.n_p)
+        rc = lib().o_local(C.byref(self.s), _dp(x), _dp(lnpsi), _dp(sign), _dp(EL),
+                           _dp(dl) if derivs else None, _dp(de) if derivs else None)
+        if rc:
+            raise RuntimeError(f"o_local failed rc={rc}")
+        return dict(lnpsi=lnpsi[0], sign=sign[0], EL=EL[0], dlnpsi=dl, dEL=de)
+
+    def vmc_run(self, x, n_equil, n_meas, delta, seed, traj=0, step=0, threads=0):
+        """Runs the Metropolis chains in place on x (W, Ne, 3); returns (sums, n_acc)."""
+        assert x.dtype == np.float64 and x.flags.c_contiguous
+        W = x.shape[0]
+        n3 = 3 * self.n_p
+        sums = np.zeros((W, 2 + 3 * n3))
+        nacc = np.zeros(W, dtype=np.int64)
+        rc = lib().o_vmc_run(C.byref(self.s), W, _dp(x), n_equil, n_meas, delta, seed, traj, step,
+                             _dp(sums), nacc.ctypes.data_as(C.POINTER(C.c_int64)), threads)
+        if rc:
+            raise RuntimeError(f"o_vmc_run failed rc={rc}")
+        return sums, nacc
+
+
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    lib().o_philox(c, k, o)
+    return list(o)
+
+
+def u01(hi, lo):
+    return lib().o_u01(hi, lo)
+
+
+def normals(seed, traj, step, n):
+    xi = np.zeros(n)
+    lib().o_normals(seed, traj, step, n, _dp(xi))
+    return xi
+
+
+def huckel(R, zeta, L, n_orb):
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    zeta = np.ascontiguousarray(zeta, dtype=np.float64)
+    n_p = R.shape[0]
+    Cm = np.zeros((n_p, n_orb))
+    ev = np.zeros(n_p)
+    rc = lib().o_huckel(n_p, L, _dp(R), _dp(zeta), n_orb, _dp(Cm), _dp(ev))
+    if rc:
+        raise RuntimeError("o_huckel failed")
+    return Cm, ev
+
+
+def reduce(sums, M):
+    W, nsum = sums.shape
+    n3 = (nsum - 2) // 3
+    E, sig = np.zeros(1), np.zeros(1)
+    f = np.zeros(n3)
+    fw = np.zeros((W, n3))
+    means = np.zeros((W, 1 + 3 * n3))
+    rc = lib().o_reduce(W, n3, M, _dp(np.ascontiguousarray(sums)), _dp(E), _dp(sig), _dp(f), _dp(fw), _dp(means))
+    if rc:
+        raise RuntimeError("o_reduce failed")
+    return dict(E=E[0], sigma_E=sig[0], f=f, f_w=fw, means=means)
+
+
+def build_S(f_w, f):
+    f_w = np.ascontiguousarray(f_w, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    W, n3 = f_w.shape
+    S = np.zeros((n3, n3))
+    lib().o_build_S(W, n3, _dp(f_w), _dp(f), _dp(S))
+    return S
+
+
+def cholesky(S):
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    Lc = np.zeros_like(S)
+    rc = lib().o_cholesky(S.shape[0], _dp(S), _dp(Lc))
+    return rc, Lc
+
+
+def langevin(R, R_prev, S_prev, f, S, T, Delta, alpha, flags=0, seed=0, traj=0, step=0, L=0.0):
+    """One step; R, R_prev, S_prev are updated in place (float64 contiguous arrays)."""
+    for a in (R, R_prev, S_prev):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    return lib().o_langevin(R.size, L, _dp(R), _dp(R_prev), _dp(S_prev), _dp(f), _dp(S), T, Delta,
+                            alpha, flags, seed, traj, step)
+
+
+def langevin_harmonic_run(K, S, T, Delta, alpha, n_steps, R0, flags=0, seed=0, sample_every=1):
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    n3 = K.shape[0]
+    R = np.ascontiguousarray(R0, dtype=np.float64).copy()
+    ns = n_steps // sample_every
+    samples = np.zeros((ns, n3))
+    rc = lib().o_langevin_harmonic_run(n3, _dp(K), _dp(S), T, Delta, alpha, flags, seed, n_steps,
+                                       _dp(R), _dp(samples), sample_every)
+    if rc:
+        raise RuntimeError(f"harmonic run failed rc={rc}")
+    return samples
+
+
+def toy_run(lam, k, a, mu, s_kind, T, Delta, alpha, scheme, seed, n_steps, R0=(1.4, 0.0), keep=False):
+    R = np.array(R0, dtype=np.float64)
+    Um = np.zeros(1)
+    Us = np.zeros(n_steps) if keep else None
+    rc = lib().o_toy_run(lam, k, a, mu, s_kind, T, Delta, alpha, scheme, seed, n_steps, _dp(R), _dp(Um),
+                         _dp(Us) if keep else None)
+    if rc:
+        raise RuntimeError(f"toy run failed rc={rc}")
+    return (Um[0], Us) if keep else Um[0]

@@ -1,0 +1,69 @@
+/* Plain FP64 CPU oracle for the VMC energy/force estimate and the
+ * covariance-preconditioned Langevin step of Sorella & Mazzola,
+ * "Accelerated ab-initio Molecular Dynamics: probing the weak dispersive
+ * forces in dense liquid hydrogen" (arXiv:1605.08423).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This oracle is slow on purpose and exists to
+ * check the GPU library.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it; the product path never links it and
+ * shares no code with it.
+ *
+ * Parity status per function is listed in the .c file's header.
+ */
+#ifndef VMC_ORACLE_H
+#define VMC_ORACLE_H
+#include <stdint.h>
+
+enum { OB_PERIODIC_GAUSS = 0, OB_OPEN_GAUSS = 1, OB_OPEN_STO = 2 };
+enum { OP_EWALD = 0, OP_COULOMB_OPEN = 1, OP_HARMONIC = 2, OP_NONE = 3 };
+
+typedef struct {
+  int n_p;           /* protons = basis centres, charge +1 */
+  int n_up, n_dn;    /* electrons per spin; electrons 0..n_up-1 are spin up */
+  int n_orb;         /* columns of C (>= max(n_up, n_dn)) */
+  double L;          /* cubic box side (periodic kinds) */
+  int basis_kind;    /* OB_* */
+  int pot_kind;      /* OP_* */
+  double kappa;      /* Ewald splitting parameter */
+  int nmax;          /* Ewald reciprocal cutoff: 0 < |n|^2 <= nmax^2 */
+  int jastrow_on;
+  double a_par, a_anti, b;   /* Pade u = a rho / (1 + b rho) */
+  const double* R;     /* n_p x 3 */
+  const double* zeta;  /* n_p */
+  const double* C;     /* n_p x n_orb, row-major */
+} osys;
+
+/* Philox4x32-10 counter-based generator (Salmon et al., SC'11). */
+void o_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double o_u01(uint32_t hi, uint32_t lo);
+
+void o_basis(const osys* s, int a, const double r[3], double out[14]);
+void o_jastrow(const osys* s, const double* x, double* U, double* gradU, double* lapU);
+double o_potential(const osys* s, const double* x, double* dV_dR, double* dV_dx);
+int o_local(const osys* s, const double* x, double* lnpsi, double* sign, double* EL,
+            double* dlnpsi_dR, double* dEL_dR);
+int o_huckel(int n_p, double L, const double* R, const double* zeta, int n_orb,
+             double* C, double* evals);
+int o_vmc_run(const osys* s, int W, double* x, int n_equil, int n_meas, double delta,
+              uint32_t seed, uint32_t traj, uint32_t step, double* sums, int64_t* n_acc,
+              int n_threads);
+int o_reduce(int W, int n3, int M, const double* sums, double* E, double* sigma_E,
+             double* f, double* f_w, double* means);
+void o_build_S(int W, int n3, const double* f_w, const double* f, double* S);
+int o_cholesky(int n, const double* S, double* Lc);
+int o_langevin(int n3, double L, double* R, double* R_prev, double* S_prev,
+               const double* f, const double* S, double T, double Delta, double alpha,
+               unsigned flags, uint32_t seed, uint32_t traj, uint32_t step);
+int o_langevin_harmonic_run(int n3, const double* K, const double* S, double T, double Delta,
+                            double alpha, unsigned flags, uint32_t seed, int n_steps,
+                            double* R, double* samples, int sample_every);
+int o_toy_run(double lambda, double k, double a, double mu, int s_kind, double T, double Delta,
+              double alpha, int scheme, uint32_t seed, int n_steps, double* R, double* U_mean,
+              double* U_samples);
+void o_normals(uint32_t seed, uint32_t traj, uint32_t step, int n, double* xi);
+
+#define O_STEP_CFOLD 1u
+#define O_STEP_NOISE_CORR 2u
+#define O_STEP_NO_SCORR 4u
+
+#endif

@@ -1,0 +1,106 @@
+"""Pins of the oracle's Metropolis sampler and VMC force estimator.
+
+* Sampling: a single electron in a periodic box with one Gaussian must be
+  distributed as |psi|^2 (its x-marginal is g(x)^2, known in closed form).
+* Zero variance: a hydrogenic orbital in an open box gives E = -1/2, sigma_E = 0.
+* Force estimator: on a FIXED sample set drawn at R, the correlated-sampling
+  energy E(R') = sum_s w_s E_L(s; R') / sum_s w_s with w_s = |psi_R'(s)/psi_R(s)|^2
+  has the exact derivative <dE_L/dR> + 2 (<E_L dln|psi|/dR> - E <dln|psi|/dR>)
+  at R' = R; central differences of E(R +- h) must give -f to O(h^2).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1605_08423_amd.inputs import small_system, workload
+
+
+def _samples(sys_, x0, n_sweeps, delta, seed):
+    """Positions after each of n_sweeps sweeps (one oracle call per sweep)."""
+    x = x0.copy()
+    out = []
+    for s in range(n_sweeps):
+        sys_.vmc_run(x, 1, 0, delta, seed, traj=0, step=s)
+        out.append(x.copy())
+    return np.array(out)   # (n_sweeps, W, Ne, 3)
+
+
+def test_single_electron_samples_psi_squared(oracle):
+    L, z = 4.0, 0.6
+    s = oracle.System(R=[[1.0, 1.5, 2.0]], zeta=[z], C_mo=[[1.0]], L=L, n_up=1, n_dn=0,
+                      pot=oracle.OP_NONE, jastrow=False)
+    W = 64
+    x0 = np.mod(np.random.default_rng(0).uniform(0, L, size=(W, 1, 3)), L)
+    xs = _samples(s, x0, 300, 1.5, seed=3)[20:, :, 0, 0].ravel()
+    edges = np.linspace(0, L, 21)
+    hist, _ = np.histogram(xs, bins=edges)
+    # closed-form marginal g(x - X)^2 with the image sum, integrated per bin
+    fine = np.linspace(0, L, 200001)
+    d = fine - 1.0
+    d = d - L * np.floor(d / L + 0.5)
+    g = sum(np.exp(-z * (d + n * L) ** 2) for n in (-1, 0, 1)) ** 2
+    p = np.array([g[(fine >= a) & (fine < b)].sum() for a, b in zip(edges[:-1], edges[1:])])
+    p /= p.sum()
+    expect = p * xs.size
+    # chains are correlated: inflate the variance by an integrated autocorrelation bound of 6
+    chi2 = ((hist - expect) ** 2 / (6 * expect)).sum()
+    assert chi2 < 40.0
+
+
+def test_hydrogen_atom_zero_variance_chain(oracle):
+    s = oracle.System(R=[[0.0, 0.0, 0.0]], zeta=[1.0], C_mo=[[1.0]], n_up=1, n_dn=0,
+                      basis=oracle.OB_OPEN_STO, pot=oracle.OP_COULOMB_OPEN, jastrow=False)
+    x = np.random.default_rng(1).normal(size=(8, 1, 3))
+    sums, nacc = s.vmc_run(x, 5, 20, 1.0, seed=9)
+    r = oracle.reduce(sums, 20)
+    assert r["E"] == pytest.approx(-0.5, abs=1e-13)
+    assert r["sigma_E"] < 1e-13
+    assert np.all(nacc > 0) and np.all(nacc < 8 * 25)
+
+
+def test_chain_is_deterministic(oracle):
+    wl = workload("h16")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, 8)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L)
+    x1 = wl.electrons(W=4)
+    x2 = x1.copy()
+    a, na = s.vmc_run(x1, 2, 3, wl.delta, seed=1, step=4)
+    b, nb = s.vmc_run(x2, 2, 3, wl.delta, seed=1, step=4)
+    assert np.array_equal(a, b) and np.array_equal(na, nb) and np.array_equal(x1, x2)
+    acc = na.sum() / (4 * 5 * 16)
+    assert 0.2 < acc < 0.9
+
+
+@pytest.mark.parametrize("name", ["h6", "h16"])
+def test_force_estimator_equals_correlated_sampling_derivative(oracle, name):
+    wl = small_system(6, 1.3, seed=4) if name == "h6" else workload("h16")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L)
+    xs = _samples(s, wl.electrons(W=4), 6, wl.delta, seed=5).reshape(-1, wl.n, 3)
+    n3 = 3 * wl.n
+    sums = np.zeros((1, 2 + 3 * n3))
+    base = []
+    for x in xs:
+        r = s.local(x)
+        base.append(r["lnpsi"])
+        sums[0, 0] += r["EL"]; sums[0, 1] += r["EL"] ** 2
+        sums[0, 2:2 + n3] += r["dEL"]
+        sums[0, 2 + n3:2 + 2 * n3] += r["dlnpsi"]
+        sums[0, 2 + 2 * n3:] += r["EL"] * r["dlnpsi"]
+    f = oracle.reduce(sums, len(xs))["f"]
+    base = np.array(base)
+
+    def E_of(Rflat):
+        sp = oracle.System(Rflat.reshape(-1, 3), wl.zeta, Cm, L=wl.L)
+        res = [sp.local(x, False) for x in xs]
+        lw = 2 * (np.array([q["lnpsi"] for q in res]) - base)
+        w = np.exp(lw - lw.max())
+        return float((w * np.array([q["EL"] for q in res])).sum() / w.sum())
+
+    h = 1e-5
+    for t in range(0, n3, 1 if wl.n <= 6 else 7):
+        Rp = wl.R.reshape(-1).copy(); Rm = Rp.copy()
+        Rp[t] += h; Rm[t] -= h
+        fd = (E_of(Rp) - E_of(Rm)) / (2 * h)
+        assert -f[t] == pytest.approx(fd, rel=1e-6, abs=1e-7)
