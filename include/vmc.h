@@ -1,0 +1,165 @@
+/* vmc.h -- C ABI of the MI355X library for the variational Monte Carlo (VMC)
+ * energy/force estimate and the covariance-preconditioned Langevin step of
+ * Sorella & Mazzola, "Accelerated ab-initio Molecular Dynamics: probing the
+ * weak dispersive forces in dense liquid hydrogen" (arXiv:1605.08423).
+ *
+ * Conventions (every entry point):
+ *  - Arrays whose name ends in _dev are DEVICE pointers (hipMalloc'd or torch
+ *    CUDA tensors) on the context's device; all others are host memory.  The
+ *    caller owns every pointer it passes; the library never retains one past
+ *    the call.  Arrays are dense, row-major, FP64, in atomic units (bohr,
+ *    Hartree).  Vectors over ions are laid out [R_0x, R_0y, R_0z, R_1x, ...].
+ *  - Work is queued on the context's stream (vmc_set_stream; default: the
+ *    null stream).  Calls returning a status that depends on device results
+ *    (VMC_ENOTSPD, VMC_ESINGULAR) synchronise that stream.
+ *  - Every call returns VMC_OK (0) or a negative VMC_E* code; no C++ exception
+ *    or abort crosses the ABI.  On failure the caller's state arrays are left
+ *    unchanged unless noted.
+ *  - A context is not thread-safe: one context per host thread.
+ *
+ * System: N protons (charge +1) and N electrons (N even; electrons 0..N/2-1
+ * spin up) in a periodic cube of side L.  Wavefunction psi = D_up D_dn e^U:
+ * one Slater determinant per spin, A_s[i][k] = sum_a phi_a(r_i) C[a][k], on
+ * s-Gaussians phi_a made periodic by the image sum (SI, "Systematic setup"),
+ * times the two-body Pade Jastrow U = sum_{i<j} a rho/(1 + b rho) on the
+ * sin-periodised distance (SI, Jastrow section).  Hamiltonian: all-electron
+ * Coulomb (main text, Eq. for V(R)), evaluated by Ewald summation.
+ */
+#ifndef VMC_H
+#define VMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  VMC_OK = 0,
+  VMC_EINVAL = -1,     /* bad size/argument: odd N, unsupported N, W < 2, Delta <= 0, ... */
+  VMC_ENOMEM = -2,     /* device allocation failed */
+  VMC_ENOTSPD = -3,    /* Cholesky of S failed: S not positive definite */
+  VMC_ESINGULAR = -4,  /* a Slater matrix had a zero pivot at an inverse refresh */
+  VMC_EDEVICE = -5,    /* a HIP runtime error */
+  VMC_ENOTBUILT = -6   /* no device code for this GPU */
+};
+
+enum { VMC_FP64 = 0, VMC_MIXED = 1 };
+
+/* Flags of vmc_langevin_step. */
+#define VMC_STEP_CFOLD 1u       /* S = I: conventional first-order Langevin (main text, Eq. basic with S = I) */
+#define VMC_STEP_NOISE_CORR 2u  /* lower T so that 2 T Db = 2 T_target Db - Dt^2 (SI, "Noise correction") */
+#define VMC_STEP_NO_SCORR 4u    /* drop the S-difference term (SI, Eq. norogna); for tests only */
+
+typedef struct vmc_ctx vmc_ctx;
+typedef struct vmc_traj vmc_traj;
+
+typedef struct {
+  int n_protons;      /* N = number of protons = number of electrons; even */
+  double box_L;       /* side of the periodic cube, bohr */
+  double ewald_kappa; /* Ewald splitting parameter, 1/bohr (real space uses the minimum image) */
+  int ewald_nmax;     /* reciprocal vectors k = 2 pi n / L with 0 < |n|^2 <= nmax^2, half space */
+  double a_par;       /* Pade cusp parameter for parallel spins (1/4) */
+  double a_anti;      /* Pade cusp parameter for anti-parallel spins (1/2) */
+  double b;           /* Pade b (1) */
+  int precision;      /* VMC_FP64: all FP64; VMC_MIXED: orbital, Jastrow and Ewald real-space
+                         terms in FP32, determinant ratios, inverse refresh, reductions and
+                         all accumulators FP64 */
+} vmc_system;
+
+/* ---------------------------------------------------------------- context -- */
+/* Creates a context on HIP device `device`.  Allocates small device scratch. */
+int vmc_create(vmc_ctx** out, int device);
+void vmc_destroy(vmc_ctx* ctx);
+/* hip_stream: a hipStream_t (NULL = null stream).  Not owned. */
+int vmc_set_stream(vmc_ctx* ctx, void* hip_stream);
+const char* vmc_strerror(int code);
+/* Largest supported N (the Slater inverse of one spin must fit one wavefront's
+ * registers) and whether N is supported. */
+int vmc_supported_n(int n_protons);
+/* Per-kernel timing with HIP events on the context stream (0 = off). */
+int vmc_set_profiling(vmc_ctx* ctx, int on);
+/* Fills up to max_n entries: kernel class names (static strings), total
+ * milliseconds and launch counts since the last reset; returns the count. */
+int vmc_kernel_times(vmc_ctx* ctx, const char** names, double* total_ms, long long* launches, int max_n);
+int vmc_reset_kernel_times(vmc_ctx* ctx);
+
+/* ------------------------------------------------------------- trajectory -- */
+/* Device-resident state of one trajectory: W walkers (electron positions,
+ * cached Slater matrices and inverses, accumulators), the per-walker force
+ * means of the last vmc_energy_forces call and the RNG key (seed, traj_id).
+ * Allocates device memory (about W * (16 N^2 + 120 N) bytes + Ewald tables). */
+int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int n_walkers, uint32_t seed,
+                    uint32_t traj_id, vmc_traj** out);
+void vmc_traj_destroy(vmc_traj* traj);
+/* Copies walker positions in/out (pos_dev: W x N x 3, any values; wrapped into
+ * the box on input). */
+int vmc_traj_set_walkers(vmc_traj* traj, const double* pos_dev);
+int vmc_traj_get_walkers(vmc_traj* traj, double* pos_dev);
+
+/* a1-a7 (main text, Eq. for V(R) and f = -dV/dR; SI, alpha paragraph): VMC
+ * estimate of the Born-Oppenheimer energy and ionic forces at proton positions
+ * R_dev (3N) with MO coefficients C_dev (N x N/2, same for both spins) and
+ * Gaussian exponents zeta_dev (N).  Each walker first refreshes its Slater
+ * matrices at R, runs n_equil unmeasured sweeps, then n_sweeps measured sweeps:
+ * a sweep moves electrons 0..N-1 in order by r' = r + step_delta (u - 1/2),
+ * accepted iff u_acc < |psi'/psi|^2; Philox4x32-10 with key (seed, traj_id) and
+ * counter (step, walker, sweep*N + e, 0|1).  The inverse of a spin's Slater
+ * matrix is rebuilt by FP64 LU with partial pivoting before every half-sweep
+ * over that spin (every N/2 moves) and updated by Sherman-Morrison otherwise.
+ * After each measured sweep: E_L, dE_L/dR and dln|psi|/dR.
+ * Output out_dev (3 + 3N doubles): [E, sigma_E, acceptance, f(3N)] with
+ * E = mean_w e_w, sigma_E = sd_w(e_w)/sqrt(W), f = mean_w f_w,
+ * f_w = -(<dE_L/dR>_w + 2(<E_L dln|psi|/dR>_w - E <dln|psi|/dR>_w)).
+ * Per-walker means stay on the device for vmc_build_S / vmc_traj_walker_*.
+ * Returns VMC_ESINGULAR if an inverse refresh hit an exactly zero pivot. */
+int vmc_energy_forces(vmc_traj* traj, const double* R_dev, const double* C_dev, const double* zeta_dev,
+                      int n_equil, int n_sweeps, double step_delta, uint32_t step, double* out_dev);
+/* Per-walker means of the last call: means_dev W x (1 + 9N) = [e_w, d_w(3N), g_w(3N), h_w(3N)]
+ * with d = dE_L/dR, g = dln|psi|/dR, h = E_L dln|psi|/dR; f_w_dev W x 3N. */
+int vmc_traj_walker_means(vmc_traj* traj, double* means_dev);
+int vmc_traj_walker_forces(vmc_traj* traj, double* f_w_dev);
+/* Accepted moves per walker in the last call (int64, W). */
+int vmc_traj_accepts(vmc_traj* traj, int64_t* n_acc_dev);
+
+/* a8 (main text, Eq. for Cov(f); SI, alpha paragraph): the acceleration matrix
+ * S = Cov of the mean force = sum_w (f_w - f)(f_w - f)^T / (W (W - 1)) from the
+ * trajectory's last vmc_energy_forces call.  S_dev: 3N x 3N. */
+int vmc_build_S(vmc_traj* traj, double* S_dev);
+/* The same for caller-provided per-walker forces f_w_dev (W x n3) and their mean f_dev (n3). */
+int vmc_build_S_raw(vmc_ctx* ctx, int W, int n3, const double* f_w_dev, const double* f_dev, double* S_dev);
+
+/* a9-a10 (SI, Eq. finaldyn_new): one step of the adopted scheme
+ *   R' = R + Dt S^-1 [ f - (S_prev - S)(R_prev - R)/(2 Db) ] + sqrt(2 T Db) z,
+ *   <z z^T> = S^-1, Dt = (1 - e^{-alpha Delta})/alpha, Db = (1 - e^{-2 alpha Delta})/(2 alpha),
+ * Dt = Db = Delta at alpha = 0 (Eq. finaldyn).  S = L L^T by FP64 Cholesky,
+ * z = L^-T xi with xi standard normal from Philox4x32-10 (key (seed, traj_id),
+ * counter (step, 0xFFFFFFFF, j, 0), Box-Muller pairs).  box_L > 0 wraps R'
+ * into [0, box_L) and takes R_prev - R by minimum image.  R_dev, R_prev_dev
+ * (n3) and S_prev_dev (n3 x n3) are updated in place ((R_prev, S_prev) <- (R, S));
+ * on the first step pass R_prev = R and S_prev = S.  Units: T and Delta in
+ * Hartree (S in Ha^2/bohr^2 makes alpha 1/Ha).  Returns VMC_ENOTSPD (state
+ * unchanged) if S is not positive definite; VMC_EINVAL if Delta <= 0,
+ * alpha < 0, T < 0 or the noise-corrected T is negative. */
+int vmc_langevin_step(vmc_ctx* ctx, int n3, double box_L, double* R_dev, double* R_prev_dev,
+                      double* S_prev_dev, const double* f_dev, const double* S_dev, double T,
+                      double Delta, double alpha, unsigned flags, uint32_t seed, uint32_t traj_id,
+                      uint32_t step);
+
+/* Per-configuration quantities for K fixed electron configurations pos_dev
+ * (K x N x 3): out_dev K x (2 + 6N) = [ln|psi|, E_L, dln|psi|/dR (3N), dE_L/dR (3N)]
+ * at protons R_dev with C_dev, zeta_dev (main text, Eq. for V(R)). */
+int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R_dev, const double* C_dev,
+                     const double* zeta_dev, int K, const double* pos_dev, double* out_dev);
+
+/* a1 (host helper): Hueckel MO coefficients on the periodic s-Gaussians.
+ * Overlap S_ab of the periodic Gaussians, H = -S_ab / sqrt(S_aa S_bb), its N/2
+ * lowest eigenvectors v (symmetric QR iteration), C_ak = v_ak / sqrt(S_aa).
+ * R, zeta: host (3N, N); C_out: host N x N/2. */
+int vmc_huckel_params(int n_protons, double box_L, const double* R, const double* zeta, double* C_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

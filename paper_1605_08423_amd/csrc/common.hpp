@@ -1,0 +1,117 @@
+// Device helpers shared by the VMC kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define VMC_WAVE 64
+#define VMC_PI 3.14159265358979323846
+
+namespace vmc {
+
+// ------------------------------------------------------------------ Philox --
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+// (hi*, lo*) = M * (c0, c2) mixing with the key, the key bumped by the Weyl
+// constants between rounds.
+struct u32x4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ u32x4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  return {c0, c1, c2, c3};
+}
+
+// 53-bit uniform double in [0, 1) from two words (all 32 bits of hi, top 21 of lo).
+__device__ __forceinline__ double u01(uint32_t hi, uint32_t lo) {
+  uint64_t m = ((uint64_t)hi << 21) | (uint64_t)(lo >> 11);
+  return (double)m * (1.0 / 9007199254740992.0);
+}
+
+// ------------------------------------------------------------ wave helpers --
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_readlane(lo, lane);
+  hi = __builtin_amdgcn_readlane(hi, lane);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+template <class T> __device__ __forceinline__ T readlane(T v, int lane);
+template <> __device__ __forceinline__ double readlane<double>(double v, int lane) { return readlane_d(v, lane); }
+template <> __device__ __forceinline__ float readlane<float>(float v, int lane) { return readlane_f(v, lane); }
+
+// Sum over the 64 lanes of a wave in a fixed butterfly order; every lane gets lane 0's result.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return readlane_d(v, 0);
+}
+
+// Orders the wave's own LDS writes before its later LDS reads (no block barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// --------------------------------------------------------------- geometry --
+__device__ __forceinline__ double min_image(double d, double L, double invL) {
+  return d - L * floor(d * invL + 0.5);
+}
+__device__ __forceinline__ double wrap_box(double x, double L, double invL) {
+  return x - L * floor(x * invL);
+}
+
+template <class Real> __device__ __forceinline__ Real dev_exp(Real x);
+template <> __device__ __forceinline__ double dev_exp<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ float dev_exp<float>(float x) { return __expf(x); }
+
+// Periodic Gaussian factor along one axis at minimum-image offset x in
+// [-L/2, L/2): images n = -1, 0, +1 of e^{-zeta (x + n L)^2} (the far images are
+// below e^{-zeta (1.5 L)^2}).  NDER = number of derivatives wanted (0..3).
+template <class Real, int NDER>
+__device__ __forceinline__ void gauss1d(Real x, Real zeta, Real L, Real g[4]) {
+  g[0] = g[1] = g[2] = g[3] = Real(0);
+#pragma unroll
+  for (int n = -1; n <= 1; ++n) {
+    Real t = x + Real(n) * L;
+    Real e = dev_exp<Real>(-zeta * t * t);
+    g[0] += e;
+    if (NDER >= 1) g[1] += Real(-2) * zeta * t * e;
+    if (NDER >= 2) g[2] += (Real(4) * zeta * zeta * t * t - Real(2) * zeta) * e;
+    if (NDER >= 3) g[3] += (Real(-8) * zeta * zeta * zeta * t * t * t + Real(12) * zeta * zeta * t) * e;
+  }
+}
+
+template <class Real> __device__ __forceinline__ Real dev_sqrt(Real x);
+template <> __device__ __forceinline__ double dev_sqrt<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ float dev_sqrt<float>(float x) { return __fsqrt_rn(x); }
+
+template <class Real> __device__ __forceinline__ void dev_sincospi(Real x, Real* s, Real* c);
+template <> __device__ __forceinline__ void dev_sincospi<double>(double x, double* s, double* c) { sincospi(x, s, c); }
+template <> __device__ __forceinline__ void dev_sincospi<float>(float x, float* s, float* c) { sincospif(x, s, c); }
+
+// Pade pair value u(rho) = a rho / (1 + b rho) of the Jastrow, for the
+// sin-periodised offset built from the trig caches of the two electrons:
+// sin(pi (x_i - x_j)/L) = s_i c_j - c_i s_j.
+template <class Real>
+__device__ __forceinline__ Real pade_u(const Real si[3], const Real ci[3], const Real sj[3], const Real cj[3],
+                                       Real LoverPi, Real a, Real b) {
+  Real r2 = Real(0);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    Real rt = LoverPi * (si[m] * cj[m] - ci[m] * sj[m]);
+    r2 += rt * rt;
+  }
+  Real rho = dev_sqrt<Real>(r2);
+  return a * rho / (Real(1) + b * rho);
+}
+
+}  // namespace vmc

@@ -1,0 +1,494 @@
+// Measurement kernels (a5, a6): per sample and walker, the Ewald potential
+// energy and its real-space gradient on the protons, the local kinetic energy,
+// d ln|psi|/dR and dE_L/dR by the determinant adjoint, accumulated in FP64.
+//
+// Ewald (all 2N charges, protons +1, electrons -1, cubic box of side L):
+//   V = sum_{i<j} q_i q_j erfc(kappa r_ij)/r_ij  (minimum image)
+//     + sum_{k in half space, 0<|n|^2<=nmax^2} W_k |rho(k)|^2,  W_k = (4 pi/V) e^{-k^2/(4 kappa^2)}/k^2
+//     - (kappa/sqrt(pi)) sum_i q_i^2.
+// The reciprocal gradient on proton b, -2 sum_k W_k k Im(conj(rho(k)) e^{i k R_b}),
+// is linear in rho, so its electron part is formed once per walker from the mean
+// electron structure factor (k_finalize) instead of per sample.
+//
+// Local energy with psi = D_up D_dn e^U, B_s = C A_s^-1 (N x NS):
+//   T_L = sum_s sum_{i in s, a} X_ia B_ai - 1/2 sum_i (lap_i U + |grad_i U|^2),
+//   X_ia = -1/2 [lap phi_a(r_i) + 2 grad phi_a(r_i) . grad_i U].
+// With C, zeta and U held fixed, d/dR_b acts on phi_b(r - R_b) only:
+//   d ln|psi|/dR_b = -sum_i B_bi grad phi_b(r_i),
+//   dT_L/dR_b = sum_i [1/2 (grad lap phi_b + 2 Hess phi_b . grad_i U) B_bi + grad phi_b(r_i) W_bi],
+//   M = X B (NS x NS), W = B M, from d A^-1 = -A^-1 dA A^-1 with dA/dR_b = -grad phi_b c_b^T.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace vmc {
+
+template <class Real> __device__ __forceinline__ Real dev_erfc(Real x);
+template <> __device__ __forceinline__ double dev_erfc<double>(double x) { return erfc(x); }
+template <> __device__ __forceinline__ float dev_erfc<float>(float x) { return erfcf(x); }
+
+// Deterministic block sum (blockDim = 256); every thread gets the result.
+__device__ __forceinline__ double block_sum256(double v, double* scratch4) {
+  v = wave_sum(v);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) scratch4[wv] = v;
+  __syncthreads();
+  double r = (scratch4[0] + scratch4[1]) + (scratch4[2] + scratch4[3]);
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------- Ewald ---
+constexpr int NMAXC = 12;   // largest supported ewald_nmax
+
+template <int N, class Real>
+__global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* pe = reinterpret_cast<double*>(smem);   // N x 3 electrons
+  double* pp = pe + 3 * N;                         // N x 3 protons
+  double2* ph = reinterpret_cast<double2*>(pp + 3 * N);   // 3 x N x (nmax+1) phase powers
+  __shared__ double red[4];
+  const int t = threadIdx.x, w = blockIdx.x;
+  const int NP1 = e.nmax + 1;
+  const double L = m.L, invL = m.invL;
+  for (int u = t; u < 3 * N; u += 256) {
+    pe[u] = m.pos[(size_t)w * 3 * N + u];
+    pp[u] = m.R[u];
+  }
+  __syncthreads();
+  // e^{i 2 pi n x / L} for n = 0..nmax, per electron and axis
+  for (int u = t; u < 3 * N; u += 256) {
+    const int i = u / 3, ax = u % 3;
+    double s, c;
+    sincospi(2.0 * pe[3 * i + ax] * invL, &s, &c);
+    double2* row = ph + ((size_t)ax * N + i) * NP1;
+    double2 v = make_double2(1.0, 0.0);
+    row[0] = v;
+    for (int n = 1; n < NP1; ++n) {
+      v = make_double2(v.x * c - v.y * s, v.x * s + v.y * c);
+      row[n] = v;
+    }
+  }
+  __syncthreads();
+  // reciprocal space, one (ny, nz) slot per thread, nx innermost
+  double vrec = 0.0;
+  double* racc = m.rho_acc + (size_t)w * e.nk * 2;
+  for (int sl = t; sl < e.nslot; sl += 256) {
+    const int ny = e.slot[4 * sl], nz = e.slot[4 * sl + 1], k0 = e.slot[4 * sl + 2], cnt = e.slot[4 * sl + 3];
+    const int nx0 = e.slot_nx0[sl];
+    const int ay = ny < 0 ? -ny : ny, az = nz < 0 ? -nz : nz;
+    const double sy = ny < 0 ? -1.0 : 1.0, sz = nz < 0 ? -1.0 : 1.0;
+    double ar[NMAXC + 1], ai[NMAXC + 1];
+#pragma unroll
+    for (int j = 0; j <= NMAXC; ++j) { ar[j] = 0.0; ai[j] = 0.0; }
+    for (int i = 0; i < N; ++i) {
+      const double2 ey = ph[((size_t)1 * N + i) * NP1 + ay];
+      const double2 ez = ph[((size_t)2 * N + i) * NP1 + az];
+      const double yr = ey.x, yi = sy * ey.y, zr = ez.x, zi = sz * ez.y;
+      const double tr = yr * zr - yi * zi, ti = yr * zi + yi * zr;
+      const double2* ex = ph + (size_t)i * NP1 + nx0;
+#pragma unroll
+      for (int j = 0; j <= NMAXC; ++j) {
+        if (j < cnt) {
+          const double2 x = ex[j];
+          ar[j] += x.x * tr - x.y * ti;
+          ai[j] += x.x * ti + x.y * tr;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j <= NMAXC; ++j) {
+      if (j < cnt) {
+        const int k = k0 + j;
+        const double rer = -ar[j], rei = -ai[j];            // electron charge -1
+        const double tr = e.rho_p[2 * k] + rer, ti = e.rho_p[2 * k + 1] + rei;
+        vrec += e.kvec[4 * k + 3] * (tr * tr + ti * ti);
+        racc[2 * k] += rer;
+        racc[2 * k + 1] += rei;
+      }
+    }
+  }
+  // real space: u < N electron-electron (half circulant), N <= u < 2N electron-proton
+  const Real kap = (Real)e.kappa;
+  const Real tkp = (Real)(2.0 * e.kappa / 1.7724538509055160273);
+  double vreal = 0.0;
+  for (int u = t; u < 2 * N; u += 256) {
+    if (u < N) {
+      const int i = u;
+      Real vs = Real(0);
+      for (int dd = 1; dd <= N / 2; ++dd) {
+        if (dd == N / 2 && i >= N / 2) break;
+        const int j = (i + dd) % N;
+        Real r2 = Real(0);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const Real d = (Real)min_image(pe[3 * i + ax] - pe[3 * j + ax], L, invL);
+          r2 += d * d;
+        }
+        const Real r = dev_sqrt<Real>(r2);
+        vs += dev_erfc<Real>(kap * r) / r;
+      }
+      vreal += (double)vs;
+    } else {
+      const int b = u - N;
+      Real vs = Real(0), gx = Real(0), gy = Real(0), gz = Real(0);
+      for (int i = 0; i < N; ++i) {
+        const Real dx = (Real)min_image(pp[3 * b] - pe[3 * i], L, invL);
+        const Real dy = (Real)min_image(pp[3 * b + 1] - pe[3 * i + 1], L, invL);
+        const Real dz = (Real)min_image(pp[3 * b + 2] - pe[3 * i + 2], L, invL);
+        const Real r2 = dx * dx + dy * dy + dz * dz;
+        const Real r = dev_sqrt<Real>(r2);
+        const Real ir = Real(1) / r;
+        const Real ec = dev_erfc<Real>(kap * r);
+        vs -= ec * ir;
+        // d/dR_b of -erfc(kappa r)/r with r = |R_b - r_i|
+        const Real dedr = -ec * ir * ir - tkp * dev_exp<Real>(-kap * kap * r2) * ir;
+        const Real gsc = -dedr * ir;
+        gx += gsc * dx; gy += gsc * dy; gz += gsc * dz;
+      }
+      vreal += (double)vs;
+      double* dv = m.dVs + (size_t)w * 3 * N + 3 * b;
+      dv[0] = (double)gx; dv[1] = (double)gy; dv[2] = (double)gz;
+    }
+  }
+  const double vtot = block_sum256(vrec + vreal, red);
+  if (t == 0) m.Vs[w] = vtot + e.Vconst;
+}
+
+// ------------------------------------------------- Slater and Jastrow ---
+template <int NS, class Real>
+__global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
+  constexpr int N = 2 * NS;
+  constexpr int H = 256 / N;            // threads per basis centre in the pair passes
+  constexpr int NT = H * N;
+  constexpr int IPT = (NS + H - 1) / H; // electrons per thread per spin
+  constexpr int LDB = NS + 1;
+  constexpr int XMS0 = (NS * N > NS * NS ? NS * N : NS * NS);
+  constexpr int XMS = (XMS0 > 6 * NT ? XMS0 : 6 * NT);   // also holds the per-centre partials
+  constexpr int MPT = (NS * NS + 255) / 256;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* pos = reinterpret_cast<double*>(smem);     // N x 3
+  double* gU = pos + 3 * N;                            // N x 3
+  double* lU = gU + 3 * N;                             // N
+  double* Bs = lU + N;                                 // N x LDB
+  double* XM = Bs + N * LDB;                           // XMS
+  Real* trig = reinterpret_cast<Real*>(XM + XMS);      // N x 6 (sin x3, cos x3)
+  __shared__ double red[4];
+  const int t = threadIdx.x, w = blockIdx.x;
+  const double L = m.L, invL = m.invL;
+  for (int u = t; u < 3 * N; u += 256) pos[u] = m.pos[(size_t)w * 3 * N + u];
+  __syncthreads();
+  for (int i = t; i < N; i += 256)
+    for (int ax = 0; ax < 3; ++ax) {
+      Real s, c;
+      dev_sincospi<Real>((Real)(pos[3 * i + ax] * invL), &s, &c);
+      trig[6 * i + ax] = s;
+      trig[6 * i + 3 + ax] = c;
+    }
+  __syncthreads();
+  // Jastrow gradient and Laplacian per electron
+  double tj = 0.0, usum = 0.0;
+  {
+    const Real LoP = (Real)(L / VMC_PI), kf = (Real)((VMC_PI * invL) * (VMC_PI * invL));
+    const Real ap = (Real)m.a_par, aa = (Real)m.a_anti, bb = (Real)m.b;
+    for (int i = t; i < N; i += 256) {
+      Real g0 = 0, g1 = 0, g2 = 0, lp = 0, ui = 0;
+      const Real* ti = trig + 6 * i;
+      for (int j = 0; j < N; ++j) {
+        if (j == i) continue;
+        const Real* tj_ = trig + 6 * j;
+        Real rt[3], cc[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          rt[ax] = LoP * (ti[ax] * tj_[3 + ax] - ti[3 + ax] * tj_[ax]);
+          cc[ax] = ti[3 + ax] * tj_[3 + ax] + ti[ax] * tj_[ax];
+        }
+        const Real r2 = rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2];
+        const Real rho = dev_sqrt<Real>(r2);
+        const Real a = ((i / NS) == (j / NS)) ? ap : aa;
+        const Real den = Real(1) + bb * rho, iden = Real(1) / den;
+        const Real up = a * iden * iden, upp = Real(-2) * a * bb * iden * iden * iden;
+        const Real irho = Real(1) / rho;
+        const Real gr0 = rt[0] * cc[0] * irho, gr1 = rt[1] * cc[1] * irho, gr2 = rt[2] * cc[2] * irho;
+        const Real gg = gr0 * gr0 + gr1 * gr1 + gr2 * gr2;
+        const Real lr = (cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2] - kf * r2) * irho - gg * irho;
+        g0 += up * gr0; g1 += up * gr1; g2 += up * gr2;
+        lp += upp * gg + up * lr;
+        if (j > i) ui += a * rho * iden;
+      }
+      gU[3 * i] = (double)g0; gU[3 * i + 1] = (double)g1; gU[3 * i + 2] = (double)g2;
+      lU[i] = (double)lp;
+      const double gd0 = g0, gd1 = g1, gd2 = g2;
+      tj += -0.5 * ((double)lp + gd0 * gd0 + gd1 * gd1 + gd2 * gd2);
+      usum += (double)ui;
+    }
+  }
+  __syncthreads();
+  const int a = t % N, h = t / N;
+  const bool act = t < NT;
+  double dln0 = 0, dln1 = 0, dln2 = 0, dT0 = 0, dT1 = 0, dT2 = 0, tsl = 0;
+  const double Ra0 = m.R[3 * a], Ra1 = m.R[3 * a + 1], Ra2 = m.R[3 * a + 2];
+  const Real za = (Real)m.zeta[a];
+  for (int sp = 0; sp < 2; ++sp) {
+    const double* Bi = m.Binv + ((size_t)w * 2 + sp) * NS * NS;
+    for (int u = t; u < NS * NS; u += 256) XM[u] = Bi[u];
+    __syncthreads();
+    double Bv[IPT];
+#pragma unroll
+    for (int s = 0; s < IPT; ++s) Bv[s] = 0.0;
+    if (act) {
+      for (int k = 0; k < NS; ++k) {
+        const double c = m.C[a * NS + k];
+#pragma unroll
+        for (int s = 0; s < IPT; ++s) {
+          const int i = h + H * s;
+          if (i < NS) Bv[s] += c * XM[k * NS + i];
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int s = 0; s < IPT; ++s) {
+        const int i = h + H * s;
+        if (i >= NS) continue;
+        Bs[a * LDB + i] = Bv[s];
+        const int e = sp * NS + i;
+        Real g[3][4];
+        gauss1d<Real, 3>((Real)min_image(pos[3 * e] - Ra0, L, invL), za, (Real)L, g[0]);
+        gauss1d<Real, 3>((Real)min_image(pos[3 * e + 1] - Ra1, L, invL), za, (Real)L, g[1]);
+        gauss1d<Real, 3>((Real)min_image(pos[3 * e + 2] - Ra2, L, invL), za, (Real)L, g[2]);
+        const Real p00 = g[1][0] * g[2][0], p01 = g[0][0] * g[2][0], p02 = g[0][0] * g[1][0];
+        const double gx = g[0][1] * p00, gy = g[1][1] * p01, gz = g[2][1] * p02;
+        const double hxx = g[0][2] * p00, hyy = g[1][2] * p01, hzz = g[2][2] * p02;
+        const double hxy = g[0][1] * g[1][1] * g[2][0], hxz = g[0][1] * g[1][0] * g[2][1];
+        const double hyz = g[0][0] * g[1][1] * g[2][1];
+        const double lap = hxx + hyy + hzz;
+        const double glx = g[0][3] * p00 + g[0][1] * (g[1][2] * g[2][0] + g[1][0] * g[2][2]);
+        const double gly = g[1][3] * p01 + g[1][1] * (g[0][2] * g[2][0] + g[0][0] * g[2][2]);
+        const double glz = g[2][3] * p02 + g[2][1] * (g[0][2] * g[1][0] + g[0][0] * g[1][2]);
+        const double u0 = gU[3 * e], u1 = gU[3 * e + 1], u2 = gU[3 * e + 2];
+        const double X = -0.5 * (lap + 2.0 * (gx * u0 + gy * u1 + gz * u2));
+        XM[i * N + a] = X;
+        const double b = Bv[s];
+        tsl += X * b;
+        dln0 -= b * gx; dln1 -= b * gy; dln2 -= b * gz;
+        dT0 += 0.5 * (glx + 2.0 * (hxx * u0 + hxy * u1 + hxz * u2)) * b;
+        dT1 += 0.5 * (gly + 2.0 * (hxy * u0 + hyy * u1 + hyz * u2)) * b;
+        dT2 += 0.5 * (glz + 2.0 * (hxz * u0 + hyz * u1 + hzz * u2)) * b;
+      }
+    }
+    __syncthreads();
+    double Mv[MPT];
+#pragma unroll
+    for (int q = 0; q < MPT; ++q) {
+      const int o = t + 256 * q;
+      Mv[q] = 0.0;
+      if (o < NS * NS) {
+        const int j = o / NS, i = o % NS;
+        double acc = 0.0;
+        for (int c = 0; c < N; ++c) acc += XM[j * N + c] * Bs[c * LDB + i];
+        Mv[q] = acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MPT; ++q) {
+      const int o = t + 256 * q;
+      if (o < NS * NS) XM[o] = Mv[q];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int s = 0; s < IPT; ++s) {
+        const int i = h + H * s;
+        if (i >= NS) continue;
+        double Wv = 0.0;
+        for (int j = 0; j < NS; ++j) Wv += Bs[a * LDB + j] * XM[j * NS + i];
+        const int e = sp * NS + i;
+        Real g[3][4];
+        gauss1d<Real, 1>((Real)min_image(pos[3 * e] - Ra0, L, invL), za, (Real)L, g[0]);
+        gauss1d<Real, 1>((Real)min_image(pos[3 * e + 1] - Ra1, L, invL), za, (Real)L, g[1]);
+        gauss1d<Real, 1>((Real)min_image(pos[3 * e + 2] - Ra2, L, invL), za, (Real)L, g[2]);
+        dT0 += (double)(g[0][1] * g[1][0] * g[2][0]) * Wv;
+        dT1 += (double)(g[0][0] * g[1][1] * g[2][0]) * Wv;
+        dT2 += (double)(g[0][0] * g[1][0] * g[2][1]) * Wv;
+      }
+    }
+    __syncthreads();
+  }
+  // combine the H threads of each centre in a fixed order
+  double* rr = XM;
+  if (act) {
+    double* q = rr + ((size_t)h * N + a) * 6;
+    q[0] = dln0; q[1] = dln1; q[2] = dln2; q[3] = dT0; q[4] = dT1; q[5] = dT2;
+  }
+  const double Tsl = block_sum256(tsl, red);
+  const double Tj = block_sum256(tj, red);
+  const double Us = block_sum256(usum, red);
+  const double EL = Tsl + Tj + m.Vs[w];
+  double* acc = m.acc + (size_t)w * (2 + 9 * N);
+  if (t < N) {
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int hh = 0; hh < H; ++hh)
+      for (int c = 0; c < 6; ++c) v[c] += rr[((size_t)hh * N + t) * 6 + c];
+    const double* dv = m.dVs + (size_t)w * 3 * N + 3 * t;
+    for (int c = 0; c < 3; ++c) {
+      const double d = v[3 + c] + dv[c], g = v[c];
+      acc[2 + 3 * t + c] += d;
+      acc[2 + 3 * N + 3 * t + c] += g;
+      acc[2 + 6 * N + 3 * t + c] += EL * g;
+    }
+  }
+  if (t == 0) {
+    acc[0] += EL;
+    acc[1] += EL * EL;
+    m.Uj[w] = Us;
+  }
+}
+
+// --------------------------------------------------------- finalize ---
+// Per-walker means [e_w, d_w(3N), g_w(3N), h_w(3N)]; d_w gets the constant
+// proton gradient and the reciprocal gradient of the mean electron structure factor.
+__global__ __launch_bounds__(256) void k_finalize(MeasureArgs m, EwaldArgs e, int M, double* means) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* rho = reinterpret_cast<double*>(smem);   // nk x 2
+  const int t = threadIdx.x, w = blockIdx.x, N = m.N;
+  const double invM = 1.0 / (double)M;
+  const double* ra = m.rho_acc + (size_t)w * e.nk * 2;
+  for (int u = t; u < 2 * e.nk; u += 256) rho[u] = ra[u] * invM;
+  __syncthreads();
+  const double* acc = m.acc + (size_t)w * (2 + 9 * N);
+  double* mw = means + (size_t)w * (1 + 9 * N);
+  if (t == 0) mw[0] = acc[0] * invM;
+  for (int b = t; b < N; b += 256) {
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int k = 0; k < e.nk; ++k) {
+      const double pr = e.Ptab[((size_t)k * N + b) * 2], pi = e.Ptab[((size_t)k * N + b) * 2 + 1];
+      const double im = rho[2 * k] * pi - rho[2 * k + 1] * pr;   // Im(conj(rho) e^{i k R_b})
+      const double s = e.kvec[4 * k + 3] * im;
+      fx += e.kvec[4 * k] * s; fy += e.kvec[4 * k + 1] * s; fz += e.kvec[4 * k + 2] * s;
+    }
+    const double fr[3] = {-2.0 * fx, -2.0 * fy, -2.0 * fz};
+    for (int c = 0; c < 3; ++c) {
+      const int u = 3 * b + c;
+      mw[1 + u] = acc[2 + u] * invM + e.Fconst[u] + fr[c];
+      mw[1 + 3 * N + u] = acc[2 + 3 * N + u] * invM;
+      mw[1 + 6 * N + u] = acc[2 + 6 * N + u] * invM;
+    }
+  }
+}
+
+// ------------------------------------------------------- proton setup ---
+// e^{i k R_b} for every (k, b) and rho_p(k) = sum_b e^{i k R_b}.
+__global__ __launch_bounds__(256) void k_proton_phases(int N, EwaldArgs e, const double* R, double* Ptab,
+                                                      double* rho_p) {
+  __shared__ double red[4];
+  const int k = blockIdx.x, t = threadIdx.x;
+  const double kx = e.kvec[4 * k], ky = e.kvec[4 * k + 1], kz = e.kvec[4 * k + 2];
+  double sr = 0.0, si = 0.0;
+  for (int b = t; b < N; b += 256) {
+    const double th = kx * R[3 * b] + ky * R[3 * b + 1] + kz * R[3 * b + 2];
+    double s, c;
+    sincos(th, &s, &c);
+    Ptab[((size_t)k * N + b) * 2] = c;
+    Ptab[((size_t)k * N + b) * 2 + 1] = s;
+    sr += c;
+    si += s;
+  }
+  sr = block_sum256(sr, red);
+  si = block_sum256(si, red);
+  if (t == 0) { rho_p[2 * k] = sr; rho_p[2 * k + 1] = si; }
+}
+
+// Proton-proton real-space energy and the walker-independent gradient on
+// each proton (p-p real space + the rho_p part of the reciprocal gradient).
+__global__ __launch_bounds__(256) void k_proton_const(int N, double L, EwaldArgs e, const double* R,
+                                                     const double* Ptab, const double* rho_p, double* Fconst,
+                                                     double* Vpp) {
+  __shared__ double red[4];
+  const int t = threadIdx.x;
+  const double invL = 1.0 / L, kap = e.kappa, tkp = 2.0 * kap / 1.7724538509055160273;
+  double vs = 0.0;
+  for (int b = t; b < N; b += 256) {
+    double gx = 0, gy = 0, gz = 0;
+    for (int c = 0; c < N; ++c) {
+      if (c == b) continue;
+      const double dx = min_image(R[3 * b] - R[3 * c], L, invL);
+      const double dy = min_image(R[3 * b + 1] - R[3 * c + 1], L, invL);
+      const double dz = min_image(R[3 * b + 2] - R[3 * c + 2], L, invL);
+      const double r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2), ir = 1.0 / r;
+      const double ec = erfc(kap * r);
+      if (c > b) vs += ec * ir;
+      const double dedr = -ec * ir * ir - tkp * exp(-kap * kap * r2) * ir;
+      gx += dedr * dx * ir; gy += dedr * dy * ir; gz += dedr * dz * ir;
+    }
+    double fx = 0, fy = 0, fz = 0;
+    for (int k = 0; k < e.nk; ++k) {
+      const double pr = Ptab[((size_t)k * N + b) * 2], pi = Ptab[((size_t)k * N + b) * 2 + 1];
+      const double s = e.kvec[4 * k + 3] * (rho_p[2 * k] * pi - rho_p[2 * k + 1] * pr);
+      fx += e.kvec[4 * k] * s; fy += e.kvec[4 * k + 1] * s; fz += e.kvec[4 * k + 2] * s;
+    }
+    Fconst[3 * b] = gx - 2.0 * fx;
+    Fconst[3 * b + 1] = gy - 2.0 * fy;
+    Fconst[3 * b + 2] = gz - 2.0 * fz;
+  }
+  vs = block_sum256(vs, red);
+  if (t == 0) *Vpp = vs;
+}
+
+// ----------------------------------------------------------- launchers ---
+template <int N, class Real>
+hipError_t launch_ewald_t(const MeasureArgs& m, const EwaldArgs& e, hipStream_t st) {
+  size_t sm = (size_t)6 * N * sizeof(double) + (size_t)3 * N * (e.nmax + 1) * sizeof(double2);
+  hipLaunchKernelGGL((k_ewald_sample<N, Real>), dim3(m.W), dim3(256), sm, st, m, e);
+  return hipGetLastError();
+}
+template <int NS>
+size_t slater_smem() {
+  constexpr int N = 2 * NS;
+  constexpr int NT = (256 / N) * N;
+  constexpr int XMS0 = (NS * N > NS * NS ? NS * N : NS * NS);
+  constexpr int XMS = (XMS0 > 6 * NT ? XMS0 : 6 * NT);
+  return ((size_t)3 * N + 3 * N + N + (size_t)N * (NS + 1) + XMS) * sizeof(double) + (size_t)6 * N * sizeof(double);
+}
+template <int NS, class Real>
+hipError_t launch_slater_t(const MeasureArgs& m, hipStream_t st) {
+  size_t sm = slater_smem<NS>();
+  hipLaunchKernelGGL((k_slater_sample<NS, Real>), dim3(m.W), dim3(256), sm, st, m);
+  return hipGetLastError();
+}
+
+#define VMC_DISPATCH_NS2(ns, CALL) \
+  switch (ns) {                   \
+    case 8: { constexpr int NSV = 8; CALL; } \
+    case 16: { constexpr int NSV = 16; CALL; } \
+    case 27: { constexpr int NSV = 27; CALL; } \
+    case 32: { constexpr int NSV = 32; CALL; } \
+    case 64: { constexpr int NSV = 64; CALL; } \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_ewald_sample(const MeasureArgs& m, const EwaldArgs& e, int mixed, hipStream_t st) {
+  if (e.nmax > NMAXC) return hipErrorInvalidValue;
+  if (mixed) { VMC_DISPATCH_NS2(m.NS, return (launch_ewald_t<2 * NSV, float>(m, e, st))) }
+  VMC_DISPATCH_NS2(m.NS, return (launch_ewald_t<2 * NSV, double>(m, e, st)))
+}
+hipError_t launch_slater_sample(const MeasureArgs& m, int mixed, hipStream_t st) {
+  if (mixed) { VMC_DISPATCH_NS2(m.NS, return (launch_slater_t<NSV, float>(m, st))) }
+  VMC_DISPATCH_NS2(m.NS, return (launch_slater_t<NSV, double>(m, st)))
+}
+hipError_t launch_finalize(const MeasureArgs& m, const EwaldArgs& e, int M, double* means, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(m.W), dim3(256), (size_t)e.nk * 2 * sizeof(double), st, m, e, M, means);
+  return hipGetLastError();
+}
+hipError_t launch_proton_setup(int N, double L, const double* R, EwaldArgs& e, double* rho_p, double* Ptab,
+                               double* Fconst, double* Vpp, hipStream_t st) {
+  hipLaunchKernelGGL(k_proton_phases, dim3(e.nk), dim3(256), 0, st, N, e, R, Ptab, rho_p);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_proton_const, dim3(1), dim3(256), 0, st, N, L, e, R, Ptab, rho_p, Fconst, Vpp);
+  return hipGetLastError();
+}
+
+}  // namespace vmc

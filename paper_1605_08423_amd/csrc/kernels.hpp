@@ -1,0 +1,85 @@
+// Kernel argument blocks and launchers (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vmc {
+
+struct WalkerArgs {
+  int W, N, NS;
+  double L, invL;
+  const double* R;     // 3N proton positions
+  const double* zeta;  // N Gaussian exponents
+  const double* C;     // N x NS MO coefficients
+  double a_par, a_anti, b;
+  double* pos;         // W x N x 3
+  double* Amat;        // W x 2 x NS x NS
+  double* Binv;        // W x 2 x NS x NS
+  double* ldet;        // W x 2
+  double* sgn;         // W x 2
+  int* status;         // set to 1 on a zero pivot
+  int64_t* nacc;       // W accepted moves
+};
+
+struct SweepArgs {
+  int spin;        // 0 = up (electrons 0..NS-1), 1 = down
+  int sweep;       // sweep index within the call (equilibration sweeps included)
+  uint32_t step, seed, traj;
+  double delta;    // box-move size
+};
+
+// Ewald tables of one box, built at a new R (walker independent).
+struct EwaldArgs {
+  int nk;              // half-space k vectors
+  int nslot;           // (ny, nz) slots, k vectors grouped by slot, nx innermost
+  int nmax;
+  double kappa;
+  const double* kvec;  // nk x 4: kx, ky, kz, W_k = (4 pi / V) e^{-k^2/(4 kappa^2)} / k^2
+  const int* slot;     // nslot x 4: ny, nz, first k index, count (nx from nx0 = first nx)
+  const int* slot_nx0; // nslot: first nx of the slot
+  const double* rho_p; // nk x 2: proton structure factor sum_b e^{i k R_b}
+  const double* Ptab;  // nk x N x 2: e^{i k R_b}
+  double Vconst;       // proton-proton real-space energy + self energy of all 2N charges
+  const double* Fconst;// 3N: walker-independent part of dV/dR (p-p real space + rho_p part of reciprocal)
+};
+
+struct MeasureArgs {
+  int W, N, NS;
+  double L, invL;
+  const double* R;
+  const double* zeta;
+  const double* C;
+  double a_par, a_anti, b;
+  const double* pos;    // W x N x 3
+  const double* Binv;   // W x 2 x NS x NS
+  double* Vs;           // W  per-sample potential energy
+  double* dVs;          // W x 3N per-sample real-space e-p gradient
+  double* Uj;           // W  Jastrow exponent U of the sample
+  double* acc;          // W x (2 + 9N): sum E_L, sum E_L^2, sum dE_L/dR, sum dlnpsi/dR, sum E_L dlnpsi/dR
+  double* rho_acc;      // W x nk x 2: sum of the electron structure factor
+};
+
+hipError_t launch_build_A(const WalkerArgs& a, int mixed, hipStream_t st);
+hipError_t launch_invert(const WalkerArgs& a, int spin_lo, int spin_hi, hipStream_t st);
+hipError_t launch_sweep(const WalkerArgs& a, const SweepArgs& s, int mixed, hipStream_t st);
+
+hipError_t launch_ewald_sample(const MeasureArgs& m, const EwaldArgs& e, int mixed, hipStream_t st);
+hipError_t launch_slater_sample(const MeasureArgs& m, int mixed, hipStream_t st);
+hipError_t launch_finalize(const MeasureArgs& m, const EwaldArgs& e, int M, double* means, hipStream_t st);
+hipError_t launch_proton_setup(int N, double L, const double* R, EwaldArgs& e, double* rho_p, double* Ptab,
+                               double* Fconst, double* Vpp, hipStream_t st);
+
+hipError_t launch_reduce(int W, int n3, const double* means, const int64_t* nacc, double moves_per_walker,
+                         double* f_w, double* partial, double* out, hipStream_t st);
+hipError_t launch_syrk(int W, int n3, const double* f_w, const double* f, double* partial, double* S,
+                       hipStream_t st);
+hipError_t launch_langevin(int n3, double L, double* R, double* R_prev, double* S_prev, const double* f,
+                           const double* S, double* Lwork, double* vwork, double T, double Delta, double alpha,
+                           unsigned flags, uint32_t seed, uint32_t traj, uint32_t step, int* status,
+                           hipStream_t st);
+size_t syrk_partial_doubles(int W, int n3);
+size_t reduce_partial_doubles(int W, int n3);
+hipError_t launch_pack_eval(int K, int N, const double* means, const double* ldet, const double* Uj, double* out,
+                            hipStream_t st);
+
+}  // namespace vmc

@@ -1,0 +1,637 @@
+// C ABI of the VMC / Langevin library: contexts, trajectories and the launch
+// sequence of one force evaluation.  See include/vmc.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/vmc.h"
+#include "kernels.hpp"
+
+using namespace vmc;
+
+namespace {
+
+enum KClass { K_SETUP, K_BUILD_A, K_INVERT, K_SWEEP, K_EWALD, K_SLATER, K_FINALIZE, K_REDUCE, K_SYRK, K_LANGEVIN,
+              K_NCLASS };
+const char* kClassName[K_NCLASS] = {"proton_setup", "build_A", "invert", "sweep_half", "ewald_sample",
+                                    "slater_sample", "finalize", "reduce", "syrk", "langevin"};
+
+struct Pending { int cls; hipEvent_t a, b; };
+
+}  // namespace
+
+struct vmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool profiling = false;
+  double ms[K_NCLASS] = {0};
+  long long launches[K_NCLASS] = {0};
+  std::vector<hipEvent_t> free_events;
+  std::vector<Pending> pending;
+  int* d_status = nullptr;
+  double* lang_work = nullptr;
+  size_t lang_work_n = 0;
+  double* syrk_work = nullptr;
+  size_t syrk_work_n = 0;
+};
+
+struct vmc_traj {
+  vmc_ctx* ctx = nullptr;
+  vmc_system sys{};
+  int W = 0, N = 0, NS = 0;
+  uint32_t seed = 0, traj_id = 0;
+  double *pos = nullptr, *Amat = nullptr, *Binv = nullptr, *ldet = nullptr, *sgn = nullptr;
+  double *acc = nullptr, *rho_acc = nullptr, *Vs = nullptr, *dVs = nullptr, *Uj = nullptr;
+  double *means = nullptr, *f_w = nullptr, *partial = nullptr, *outv = nullptr;
+  int64_t* nacc = nullptr;
+  // Ewald tables
+  int nk = 0, nslot = 0;
+  double *kvec = nullptr, *rho_p = nullptr, *Ptab = nullptr, *Fconst = nullptr, *Vpp = nullptr;
+  int *slot = nullptr, *slot_nx0 = nullptr;
+  double Vself = 0.0;
+  bool have_means = false;
+};
+
+namespace {
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) return map_err(e_);       \
+  } while (0)
+
+int map_err(hipError_t e) {
+  if (e == hipErrorOutOfMemory) return VMC_ENOMEM;
+  if (e == hipErrorInvalidValue) return VMC_EINVAL;
+  if (e == hipErrorNoBinaryForGpu || e == hipErrorInvalidDeviceFunction) return VMC_ENOTBUILT;
+  return VMC_EDEVICE;
+}
+
+hipEvent_t get_event(vmc_ctx* c) {
+  if (!c->free_events.empty()) {
+    hipEvent_t e = c->free_events.back();
+    c->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void flush_timers(vmc_ctx* c) {
+  for (auto& p : c->pending) {
+    (void)hipEventSynchronize(p.b);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->ms[p.cls] += ms;
+      c->launches[p.cls] += 1;
+    }
+    c->free_events.push_back(p.a);
+    c->free_events.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+// Runs one kernel launch, bracketed by events when profiling.
+template <class F>
+int timed(vmc_ctx* c, int cls, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (c->profiling) {
+    if (c->pending.size() > 8192) flush_timers(c);
+    a = get_event(c);
+    b = get_event(c);
+    if (a) (void)hipEventRecord(a, c->stream);
+  }
+  hipError_t e = launch();
+  if (c->profiling && a && b) {
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({cls, a, b});
+  }
+  if (e != hipSuccess) return map_err(e);
+  return VMC_OK;
+}
+
+#define RUN(cls, expr)                                  \
+  do {                                                  \
+    int rc_ = timed(ctx, cls, [&]() { return (expr); }); \
+    if (rc_) return rc_;                                \
+  } while (0)
+
+template <class T>
+int dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  return e == hipSuccess ? VMC_OK : map_err(e);
+}
+
+bool supported_ns(int ns) { return ns == 8 || ns == 16 || ns == 27 || ns == 32 || ns == 64; }
+
+int check_sys(const vmc_system* s) {
+  if (!s) return VMC_EINVAL;
+  if (s->n_protons < 2 || (s->n_protons & 1) || !supported_ns(s->n_protons / 2)) return VMC_EINVAL;
+  if (!(s->box_L > 0.0) || !(s->ewald_kappa > 0.0) || s->ewald_nmax < 1 || s->ewald_nmax > 12) return VMC_EINVAL;
+  if (s->precision != VMC_FP64 && s->precision != VMC_MIXED) return VMC_EINVAL;
+  return VMC_OK;
+}
+
+// Half-space reciprocal vectors grouped by (ny, nz), nx innermost.
+void build_kvectors(const vmc_system& s, std::vector<double>& kv, std::vector<int>& slots, std::vector<int>& nx0) {
+  const int nm = s.ewald_nmax;
+  const double L = s.box_L, V = L * L * L, kap = s.ewald_kappa, tp = 2.0 * M_PI / L;
+  int k = 0;
+  for (int ny = -nm; ny <= nm; ++ny)
+    for (int nz = -nm; nz <= nm; ++nz) {
+      const int r2 = ny * ny + nz * nz;
+      if (r2 > nm * nm) continue;
+      int nxmax = 0;
+      while ((nxmax + 1) * (nxmax + 1) + r2 <= nm * nm) ++nxmax;
+      const bool pos_half = (ny > 0) || (ny == 0 && nz > 0);
+      const int nxmin = pos_half ? 0 : 1;
+      if (nxmin > nxmax) continue;
+      slots.push_back(ny);
+      slots.push_back(nz);
+      slots.push_back(k);
+      slots.push_back(nxmax - nxmin + 1);
+      nx0.push_back(nxmin);
+      for (int nx = nxmin; nx <= nxmax; ++nx, ++k) {
+        const double kx = tp * nx, ky = tp * ny, kz = tp * nz, k2 = kx * kx + ky * ky + kz * kz;
+        kv.push_back(kx);
+        kv.push_back(ky);
+        kv.push_back(kz);
+        kv.push_back(4.0 * M_PI / V * std::exp(-k2 / (4.0 * kap * kap)) / k2);
+      }
+    }
+}
+
+WalkerArgs walker_args(vmc_traj* t, const double* R, const double* C, const double* zeta) {
+  WalkerArgs a{};
+  a.W = t->W; a.N = t->N; a.NS = t->NS;
+  a.L = t->sys.box_L; a.invL = 1.0 / t->sys.box_L;
+  a.R = R; a.zeta = zeta; a.C = C;
+  a.a_par = t->sys.a_par; a.a_anti = t->sys.a_anti; a.b = t->sys.b;
+  a.pos = t->pos; a.Amat = t->Amat; a.Binv = t->Binv; a.ldet = t->ldet; a.sgn = t->sgn;
+  a.status = t->ctx->d_status; a.nacc = t->nacc;
+  return a;
+}
+
+MeasureArgs measure_args(vmc_traj* t, const double* R, const double* C, const double* zeta) {
+  MeasureArgs m{};
+  m.W = t->W; m.N = t->N; m.NS = t->NS;
+  m.L = t->sys.box_L; m.invL = 1.0 / t->sys.box_L;
+  m.R = R; m.zeta = zeta; m.C = C;
+  m.a_par = t->sys.a_par; m.a_anti = t->sys.a_anti; m.b = t->sys.b;
+  m.pos = t->pos; m.Binv = t->Binv; m.Vs = t->Vs; m.dVs = t->dVs; m.Uj = t->Uj;
+  m.acc = t->acc; m.rho_acc = t->rho_acc;
+  return m;
+}
+
+EwaldArgs ewald_args(vmc_traj* t, double Vconst) {
+  EwaldArgs e{};
+  e.nk = t->nk; e.nslot = t->nslot; e.nmax = t->sys.ewald_nmax; e.kappa = t->sys.ewald_kappa;
+  e.kvec = t->kvec; e.slot = t->slot; e.slot_nx0 = t->slot_nx0;
+  e.rho_p = t->rho_p; e.Ptab = t->Ptab; e.Vconst = Vconst; e.Fconst = t->Fconst;
+  return e;
+}
+
+// Proton-only Ewald quantities at R: rho_p, e^{ikR}, constant gradient, V_pp.
+int proton_setup(vmc_traj* t, const double* R, double* Vconst) {
+  vmc_ctx* ctx = t->ctx;
+  EwaldArgs e = ewald_args(t, 0.0);
+  RUN(K_SETUP, launch_proton_setup(t->N, t->sys.box_L, R, e, t->rho_p, t->Ptab, t->Fconst, t->Vpp, ctx->stream));
+  double vpp = 0.0;
+  HIPCHK(hipMemcpyAsync(&vpp, t->Vpp, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *Vconst = vpp + t->Vself;
+  return VMC_OK;
+}
+
+int check_singular(vmc_ctx* ctx) {
+  int st = 0;
+  HIPCHK(hipMemcpyAsync(&st, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return st ? VMC_ESINGULAR : VMC_OK;
+}
+
+// One measured sample for every walker.
+int measure(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e) {
+  vmc_ctx* ctx = t->ctx;
+  const int mixed = t->sys.precision == VMC_MIXED;
+  RUN(K_EWALD, launch_ewald_sample(m, e, mixed, ctx->stream));
+  RUN(K_SLATER, launch_slater_sample(m, mixed, ctx->stream));
+  return VMC_OK;
+}
+
+void free_traj(vmc_traj* t) {
+  if (!t) return;
+  void* ptrs[] = {t->pos, t->Amat, t->Binv, t->ldet, t->sgn, t->acc, t->rho_acc, t->Vs, t->dVs, t->Uj,
+                  t->means, t->f_w, t->partial, t->outv, t->nacc, t->kvec, t->rho_p, t->Ptab, t->Fconst,
+                  t->Vpp, t->slot, t->slot_nx0};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete t;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vmc_strerror(int code) {
+  switch (code) {
+    case VMC_OK: return "ok";
+    case VMC_EINVAL: return "invalid argument";
+    case VMC_ENOMEM: return "device out of memory";
+    case VMC_ENOTSPD: return "S is not positive definite";
+    case VMC_ESINGULAR: return "singular Slater matrix at an inverse refresh";
+    case VMC_EDEVICE: return "HIP runtime error";
+    case VMC_ENOTBUILT: return "no device code for this GPU";
+    default: return "unknown error";
+  }
+}
+
+int vmc_supported_n(int n) { return (n > 0 && !(n & 1) && supported_ns(n / 2)) ? 1 : 0; }
+
+int vmc_create(vmc_ctx** out, int device) {
+  if (!out) return VMC_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return VMC_EINVAL;
+  HIPCHK(hipSetDevice(device));
+  vmc_ctx* c = new (std::nothrow) vmc_ctx();
+  if (!c) return VMC_ENOMEM;
+  c->device = device;
+  if (dalloc(&c->d_status, 1)) { delete c; return VMC_ENOMEM; }
+  *out = c;
+  return VMC_OK;
+}
+
+void vmc_destroy(vmc_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  flush_timers(c);
+  for (hipEvent_t e : c->free_events) (void)hipEventDestroy(e);
+  if (c->d_status) (void)hipFree(c->d_status);
+  if (c->lang_work) (void)hipFree(c->lang_work);
+  if (c->syrk_work) (void)hipFree(c->syrk_work);
+  delete c;
+}
+
+int vmc_set_stream(vmc_ctx* c, void* s) {
+  if (!c) return VMC_EINVAL;
+  c->stream = (hipStream_t)s;
+  return VMC_OK;
+}
+
+int vmc_set_profiling(vmc_ctx* c, int on) {
+  if (!c) return VMC_EINVAL;
+  if (!on) flush_timers(c);
+  c->profiling = on != 0;
+  return VMC_OK;
+}
+
+int vmc_kernel_times(vmc_ctx* c, const char** names, double* total_ms, long long* launches, int max_n) {
+  if (!c) return VMC_EINVAL;
+  flush_timers(c);
+  int n = std::min(max_n, (int)K_NCLASS);
+  for (int i = 0; i < n; ++i) {
+    if (names) names[i] = kClassName[i];
+    if (total_ms) total_ms[i] = c->ms[i];
+    if (launches) launches[i] = c->launches[i];
+  }
+  return n;
+}
+
+int vmc_reset_kernel_times(vmc_ctx* c) {
+  if (!c) return VMC_EINVAL;
+  flush_timers(c);
+  for (int i = 0; i < K_NCLASS; ++i) { c->ms[i] = 0; c->launches[i] = 0; }
+  return VMC_OK;
+}
+
+int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int W, uint32_t seed, uint32_t traj_id, vmc_traj** out) {
+  if (!ctx || !out || W < 1) return VMC_EINVAL;
+  *out = nullptr;
+  int rc = check_sys(sys);
+  if (rc) return rc;
+  HIPCHK(hipSetDevice(ctx->device));
+  vmc_traj* t = new (std::nothrow) vmc_traj();
+  if (!t) return VMC_ENOMEM;
+  t->ctx = ctx; t->sys = *sys; t->W = W; t->N = sys->n_protons; t->NS = t->N / 2;
+  t->seed = seed; t->traj_id = traj_id;
+  std::vector<double> kv;
+  std::vector<int> slots, nx0;
+  build_kvectors(*sys, kv, slots, nx0);
+  t->nk = (int)(kv.size() / 4);
+  t->nslot = (int)nx0.size();
+  t->Vself = -sys->ewald_kappa / std::sqrt(M_PI) * (2.0 * t->N);
+  const size_t N = t->N, NS = t->NS, n3 = 3 * N;
+  bool ok = !dalloc(&t->pos, W * N * 3) && !dalloc(&t->Amat, (size_t)W * 2 * NS * NS) &&
+            !dalloc(&t->Binv, (size_t)W * 2 * NS * NS) && !dalloc(&t->ldet, (size_t)W * 2) &&
+            !dalloc(&t->sgn, (size_t)W * 2) && !dalloc(&t->acc, (size_t)W * (2 + 9 * N)) &&
+            !dalloc(&t->rho_acc, (size_t)W * t->nk * 2) && !dalloc(&t->Vs, (size_t)W) &&
+            !dalloc(&t->dVs, (size_t)W * n3) && !dalloc(&t->Uj, (size_t)W) &&
+            !dalloc(&t->means, (size_t)W * (1 + 3 * n3)) && !dalloc(&t->f_w, (size_t)W * n3) &&
+            !dalloc(&t->partial, reduce_partial_doubles(W, (int)n3)) && !dalloc(&t->outv, 3 + n3) &&
+            !dalloc(&t->nacc, (size_t)W) && !dalloc(&t->kvec, kv.size()) && !dalloc(&t->rho_p, 2 * t->nk) &&
+            !dalloc(&t->Ptab, (size_t)t->nk * N * 2) && !dalloc(&t->Fconst, n3) && !dalloc(&t->Vpp, 1) &&
+            !dalloc(&t->slot, slots.size()) && !dalloc(&t->slot_nx0, nx0.size());
+  if (!ok) { free_traj(t); return VMC_ENOMEM; }
+  if (hipMemcpy(t->kvec, kv.data(), kv.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t->slot, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t->slot_nx0, nx0.data(), nx0.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(t->nacc, 0, W * sizeof(int64_t)) != hipSuccess) {
+    free_traj(t);
+    return VMC_EDEVICE;
+  }
+  *out = t;
+  return VMC_OK;
+}
+
+void vmc_traj_destroy(vmc_traj* t) { free_traj(t); }
+
+int vmc_traj_set_walkers(vmc_traj* t, const double* pos_dev) {
+  if (!t || !pos_dev) return VMC_EINVAL;
+  HIPCHK(hipMemcpyAsync(t->pos, pos_dev, (size_t)t->W * t->N * 3 * sizeof(double), hipMemcpyDeviceToDevice,
+                        t->ctx->stream));
+  return VMC_OK;
+}
+
+int vmc_traj_get_walkers(vmc_traj* t, double* pos_dev) {
+  if (!t || !pos_dev) return VMC_EINVAL;
+  HIPCHK(hipMemcpyAsync(pos_dev, t->pos, (size_t)t->W * t->N * 3 * sizeof(double), hipMemcpyDeviceToDevice,
+                        t->ctx->stream));
+  return VMC_OK;
+}
+
+int vmc_energy_forces(vmc_traj* t, const double* R, const double* C, const double* zeta, int n_equil,
+                      int n_sweeps, double step_delta, uint32_t step, double* out_dev) {
+  if (!t || !R || !C || !zeta || !out_dev || n_equil < 0 || n_sweeps < 1 || !(step_delta > 0.0)) return VMC_EINVAL;
+  vmc_ctx* ctx = t->ctx;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const int mixed = t->sys.precision == VMC_MIXED;
+  const size_t N = t->N, n3 = 3 * N, W = t->W;
+  double Vconst = 0.0;
+  int rc = proton_setup(t, R, &Vconst);
+  if (rc) return rc;
+  HIPCHK(hipMemsetAsync(t->acc, 0, W * (2 + 9 * N) * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(t->rho_acc, 0, W * t->nk * 2 * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(t->nacc, 0, W * sizeof(int64_t), st));
+  HIPCHK(hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
+  WalkerArgs a = walker_args(t, R, C, zeta);
+  MeasureArgs m = measure_args(t, R, C, zeta);
+  EwaldArgs e = ewald_args(t, Vconst);
+  RUN(K_BUILD_A, launch_build_A(a, mixed, st));
+  const int total = n_equil + n_sweeps;
+  for (int s = 0; s < total; ++s) {
+    for (int sp = 0; sp < 2; ++sp) {
+      RUN(K_INVERT, launch_invert(a, sp, sp + 1, st));
+      SweepArgs sa{sp, s, step, t->seed, t->traj_id, step_delta};
+      RUN(K_SWEEP, launch_sweep(a, sa, mixed, st));
+    }
+    if (s >= n_equil) {
+      rc = measure(t, m, e);
+      if (rc) return rc;
+    }
+  }
+  RUN(K_FINALIZE, launch_finalize(m, e, n_sweeps, t->means, st));
+  RUN(K_REDUCE, launch_reduce((int)W, (int)n3, t->means, t->nacc, (double)N * total, t->f_w, t->partial, t->outv, st));
+  HIPCHK(hipMemcpyAsync(out_dev, t->outv, (3 + n3) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  t->have_means = true;
+  return check_singular(ctx);
+}
+
+int vmc_traj_walker_means(vmc_traj* t, double* means_dev) {
+  if (!t || !means_dev || !t->have_means) return VMC_EINVAL;
+  HIPCHK(hipMemcpyAsync(means_dev, t->means, (size_t)t->W * (1 + 9 * t->N) * sizeof(double),
+                        hipMemcpyDeviceToDevice, t->ctx->stream));
+  return VMC_OK;
+}
+
+int vmc_traj_walker_forces(vmc_traj* t, double* f_w_dev) {
+  if (!t || !f_w_dev || !t->have_means) return VMC_EINVAL;
+  HIPCHK(hipMemcpyAsync(f_w_dev, t->f_w, (size_t)t->W * 3 * t->N * sizeof(double), hipMemcpyDeviceToDevice,
+                        t->ctx->stream));
+  return VMC_OK;
+}
+
+int vmc_traj_accepts(vmc_traj* t, int64_t* n_acc_dev) {
+  if (!t || !n_acc_dev) return VMC_EINVAL;
+  HIPCHK(hipMemcpyAsync(n_acc_dev, t->nacc, (size_t)t->W * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                        t->ctx->stream));
+  return VMC_OK;
+}
+
+int vmc_build_S_raw(vmc_ctx* ctx, int W, int n3, const double* f_w, const double* f, double* S) {
+  if (!ctx || W < 2 || n3 < 1 || !f_w || !f || !S) return VMC_EINVAL;
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t need = syrk_partial_doubles(W, n3);
+  if (ctx->syrk_work_n < need) {
+    if (ctx->syrk_work) (void)hipFree(ctx->syrk_work);
+    ctx->syrk_work = nullptr;
+    ctx->syrk_work_n = 0;
+    if (dalloc(&ctx->syrk_work, need)) return VMC_ENOMEM;
+    ctx->syrk_work_n = need;
+  }
+  RUN(K_SYRK, launch_syrk(W, n3, f_w, f, ctx->syrk_work, S, ctx->stream));
+  return VMC_OK;
+}
+
+int vmc_build_S(vmc_traj* t, double* S) {
+  if (!t || !S || !t->have_means) return VMC_EINVAL;
+  return vmc_build_S_raw(t->ctx, t->W, 3 * t->N, t->f_w, t->outv + 3, S);
+}
+
+int vmc_langevin_step(vmc_ctx* ctx, int n3, double L, double* R, double* R_prev, double* S_prev, const double* f,
+                      const double* S, double T, double Delta, double alpha, unsigned flags, uint32_t seed,
+                      uint32_t traj_id, uint32_t step) {
+  if (!ctx || n3 < 1 || n3 > 1536 || !R || !R_prev || !S_prev || !f || !S) return VMC_EINVAL;
+  if (!(Delta > 0.0) || alpha < 0.0 || T < 0.0 || !(L >= 0.0) || (flags & ~7u)) return VMC_EINVAL;
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t need = (size_t)n3 * n3;
+  if (ctx->lang_work_n < need) {
+    if (ctx->lang_work) (void)hipFree(ctx->lang_work);
+    ctx->lang_work = nullptr;
+    ctx->lang_work_n = 0;
+    if (dalloc(&ctx->lang_work, need)) return VMC_ENOMEM;
+    ctx->lang_work_n = need;
+  }
+  HIPCHK(hipMemsetAsync(ctx->d_status, 0, sizeof(int), ctx->stream));
+  RUN(K_LANGEVIN, launch_langevin(n3, L, R, R_prev, S_prev, f, S, ctx->lang_work, nullptr, T, Delta, alpha, flags,
+                                  seed, traj_id, step, ctx->d_status, ctx->stream));
+  int st = 0;
+  HIPCHK(hipMemcpyAsync(&st, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (st == 3) return VMC_ENOTSPD;
+  if (st == 1) return VMC_EINVAL;
+  return VMC_OK;
+}
+
+int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R, const double* C, const double* zeta,
+                     int K, const double* pos, double* out) {
+  if (!ctx || K < 1 || !R || !C || !zeta || !pos || !out) return VMC_EINVAL;
+  vmc_traj* t = nullptr;
+  int rc = vmc_traj_create(ctx, sys, K, 0, 0, &t);
+  if (rc) return rc;
+  hipStream_t st = ctx->stream;
+  const int mixed = t->sys.precision == VMC_MIXED;
+  const size_t N = t->N;
+  double Vconst = 0.0;
+  rc = vmc_traj_set_walkers(t, pos);
+  if (!rc) rc = proton_setup(t, R, &Vconst);
+  if (!rc) {
+    auto body = [&]() -> int {
+      HIPCHK(hipMemsetAsync(t->acc, 0, (size_t)K * (2 + 9 * N) * sizeof(double), st));
+      HIPCHK(hipMemsetAsync(t->rho_acc, 0, (size_t)K * t->nk * 2 * sizeof(double), st));
+      HIPCHK(hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
+      WalkerArgs a = walker_args(t, R, C, zeta);
+      MeasureArgs m = measure_args(t, R, C, zeta);
+      EwaldArgs e = ewald_args(t, Vconst);
+      RUN(K_BUILD_A, launch_build_A(a, mixed, st));
+      RUN(K_INVERT, launch_invert(a, 0, 2, st));
+      int r2 = measure(t, m, e);
+      if (r2) return r2;
+      RUN(K_FINALIZE, launch_finalize(m, e, 1, t->means, st));
+      HIPCHK(launch_pack_eval(K, (int)N, t->means, t->ldet, t->Uj, out, st));
+      return check_singular(ctx);
+    };
+    rc = body();
+  }
+  (void)hipStreamSynchronize(st);
+  vmc_traj_destroy(t);
+  return rc;
+}
+
+// ---------------------------------------------------------------- Hueckel --
+// Symmetric eigen-decomposition A = Q T Q^T: Householder reflections reduce A
+// to tridiagonal T, then implicit QR steps with a Wilkinson shift (Givens
+// rotations chasing the bulge, deflation of negligible sub-diagonals) drive T
+// to diagonal.  Q accumulates every transformation; its columns are eigenvectors.
+static void householder_tridiag(int n, std::vector<double>& A, std::vector<double>& Q) {
+  Q.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  std::vector<double> v(n), p(n), w(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1, o = k + 1;
+    const double x0 = A[(size_t)o * n + k];
+    double sigma = 0.0;
+    for (int i = 1; i < m; ++i) sigma += A[(size_t)(o + i) * n + k] * A[(size_t)(o + i) * n + k];
+    if (sigma == 0.0) continue;
+    const double mu = std::sqrt(x0 * x0 + sigma);
+    const double v0 = (x0 <= 0.0) ? x0 - mu : -sigma / (x0 + mu);
+    const double beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
+    v[0] = 1.0;
+    for (int i = 1; i < m; ++i) v[i] = A[(size_t)(o + i) * n + k] / v0;
+    double pv = 0.0;
+    for (int i = 0; i < m; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += A[(size_t)(o + i) * n + o + j] * v[j];
+      p[i] = beta * acc;
+      pv += p[i] * v[i];
+    }
+    for (int i = 0; i < m; ++i) w[i] = p[i] - 0.5 * beta * pv * v[i];
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) A[(size_t)(o + i) * n + o + j] -= v[i] * w[j] + w[i] * v[j];
+    A[(size_t)o * n + k] = A[(size_t)k * n + o] = mu;
+    for (int i = 1; i < m; ++i) A[(size_t)(o + i) * n + k] = A[(size_t)k * n + o + i] = 0.0;
+    for (int r = 0; r < n; ++r) {
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += Q[(size_t)r * n + o + j] * v[j];
+      for (int j = 0; j < m; ++j) Q[(size_t)r * n + o + j] -= beta * acc * v[j];
+    }
+  }
+}
+
+static int tridiag_qr(int n, std::vector<double>& T, std::vector<double>& Q) {
+  const double eps = 2.220446049250313e-16;
+  auto small = [&](int i) {   // sub-diagonal entry (i, i-1) negligible?
+    return std::fabs(T[(size_t)i * n + i - 1]) <=
+           eps * (std::fabs(T[(size_t)i * n + i]) + std::fabs(T[(size_t)(i - 1) * n + i - 1]));
+  };
+  auto rot = [&](int k, int lo, int hi, double c, double s) {
+    const int j0 = std::max(lo, k - 1), j1 = std::min(hi, k + 2);
+    for (int j = j0; j <= j1; ++j) {
+      const double t1 = T[(size_t)k * n + j], t2 = T[(size_t)(k + 1) * n + j];
+      T[(size_t)k * n + j] = c * t1 + s * t2;
+      T[(size_t)(k + 1) * n + j] = -s * t1 + c * t2;
+    }
+    for (int i = j0; i <= j1; ++i) {
+      const double t1 = T[(size_t)i * n + k], t2 = T[(size_t)i * n + k + 1];
+      T[(size_t)i * n + k] = c * t1 + s * t2;
+      T[(size_t)i * n + k + 1] = -s * t1 + c * t2;
+    }
+    for (int i = 0; i < n; ++i) {
+      const double t1 = Q[(size_t)i * n + k], t2 = Q[(size_t)i * n + k + 1];
+      Q[(size_t)i * n + k] = c * t1 + s * t2;
+      Q[(size_t)i * n + k + 1] = -s * t1 + c * t2;
+    }
+  };
+  int hi = n - 1, iter = 0;
+  while (hi > 0) {
+    if (++iter > 60 * n) return VMC_EDEVICE;
+    if (small(hi)) {
+      T[(size_t)hi * n + hi - 1] = T[(size_t)(hi - 1) * n + hi] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && !small(lo)) --lo;
+    if (lo > 0) T[(size_t)lo * n + lo - 1] = T[(size_t)(lo - 1) * n + lo] = 0.0;
+    const double a = T[(size_t)(hi - 1) * n + hi - 1], b = T[(size_t)hi * n + hi - 1], c = T[(size_t)hi * n + hi];
+    const double dd = 0.5 * (a - c);
+    const double mu = c - b * b / (dd + (dd >= 0.0 ? 1.0 : -1.0) * std::hypot(dd, b));
+    double x = T[(size_t)lo * n + lo] - mu, z = T[(size_t)(lo + 1) * n + lo];
+    for (int k = lo; k < hi; ++k) {
+      if (k > lo) {
+        x = T[(size_t)k * n + k - 1];
+        z = T[(size_t)(k + 1) * n + k - 1];
+      }
+      const double r = std::hypot(x, z);
+      const double cs = r == 0.0 ? 1.0 : x / r, sn = r == 0.0 ? 0.0 : z / r;
+      rot(k, lo, hi, cs, sn);
+      if (k > lo) T[(size_t)(k + 1) * n + k - 1] = T[(size_t)(k - 1) * n + k + 1] = 0.0;
+    }
+  }
+  return VMC_OK;
+}
+
+int vmc_huckel_params(int n, double L, const double* R, const double* zeta, double* C_out) {
+  if (n < 2 || (n & 1) || !(L > 0.0) || !R || !zeta || !C_out) return VMC_EINVAL;
+  std::vector<double> S((size_t)n * n), H((size_t)n * n), Q;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const double za = zeta[a], zb = zeta[b], mu = za * zb / (za + zb);
+      double v = std::pow(M_PI / (za + zb), 1.5);
+      for (int ax = 0; ax < 3; ++ax) {
+        double dd = R[3 * a + ax] - R[3 * b + ax];
+        dd -= L * std::floor(dd / L + 0.5);
+        double s = 0.0;
+        for (int k = -3; k <= 3; ++k) s += std::exp(-mu * (dd + k * L) * (dd + k * L));
+        v *= s;
+      }
+      S[(size_t)a * n + b] = v;
+    }
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b)
+      H[(size_t)a * n + b] = -S[(size_t)a * n + b] / std::sqrt(S[(size_t)a * n + a] * S[(size_t)b * n + b]);
+  householder_tridiag(n, H, Q);
+  int rc = tridiag_qr(n, H, Q);
+  if (rc) return rc;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return H[(size_t)x * n + x] < H[(size_t)y * n + y]; });
+  const int no = n / 2;
+  for (int k = 0; k < no; ++k)
+    for (int a = 0; a < n; ++a)
+      C_out[(size_t)a * no + k] = Q[(size_t)a * n + order[k]] / std::sqrt(S[(size_t)a * n + a]);
+  return VMC_OK;
+}
+
+}  // extern "C"

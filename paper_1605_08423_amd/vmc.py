@@ -1,0 +1,255 @@
+"""Thin ctypes binding of libvmc.so (include/vmc.h).  Argument marshalling only:
+every step of the computation runs in the library's HIP kernels.  Device arrays
+are torch CUDA float64 tensors; the library runs on torch's current stream.
+
+Raises RuntimeError if the HIP library has not been built -- there is no
+fallback implementation."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvmc.so")
+
+VMC_OK, VMC_EINVAL, VMC_ENOMEM, VMC_ENOTSPD, VMC_ESINGULAR, VMC_EDEVICE, VMC_ENOTBUILT = 0, -1, -2, -3, -4, -5, -6
+VMC_FP64, VMC_MIXED = 0, 1
+VMC_STEP_CFOLD, VMC_STEP_NOISE_CORR, VMC_STEP_NO_SCORR = 1, 2, 4
+
+EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_supported_n",
+            "vmc_set_profiling", "vmc_kernel_times", "vmc_reset_kernel_times", "vmc_traj_create",
+            "vmc_traj_destroy", "vmc_traj_set_walkers", "vmc_traj_get_walkers", "vmc_energy_forces",
+            "vmc_traj_walker_means", "vmc_traj_walker_forces", "vmc_traj_accepts", "vmc_build_S",
+            "vmc_build_S_raw", "vmc_langevin_step", "vmc_eval_configs", "vmc_huckel_params"]
+
+
+class VMCError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {_lib().vmc_strerror(code).decode()} ({code})")
+
+
+class vmc_system(C.Structure):
+    _fields_ = [("n_protons", C.c_int), ("box_L", C.c_double), ("ewald_kappa", C.c_double),
+                ("ewald_nmax", C.c_int), ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
+                ("precision", C.c_int)]
+
+
+_L = None
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built (run __graft_entry__.build())")
+        _L = C.CDLL(LIB_PATH)
+        _declare(_L)
+    return _L
+
+
+def _declare(l):
+    P, vp, d, i, u32 = C.POINTER, C.c_void_p, C.c_double, C.c_int, C.c_uint32
+    l.vmc_strerror.restype = C.c_char_p
+    l.vmc_strerror.argtypes = [i]
+    l.vmc_create.argtypes = [P(vp), i]
+    l.vmc_destroy.argtypes = [vp]
+    l.vmc_destroy.restype = None
+    l.vmc_set_stream.argtypes = [vp, vp]
+    l.vmc_supported_n.argtypes = [i]
+    l.vmc_set_profiling.argtypes = [vp, i]
+    l.vmc_kernel_times.argtypes = [vp, P(C.c_char_p), P(d), P(C.c_longlong), i]
+    l.vmc_reset_kernel_times.argtypes = [vp]
+    l.vmc_traj_create.argtypes = [vp, P(vmc_system), i, u32, u32, P(vp)]
+    l.vmc_traj_destroy.argtypes = [vp]
+    l.vmc_traj_destroy.restype = None
+    l.vmc_traj_set_walkers.argtypes = [vp, vp]
+    l.vmc_traj_get_walkers.argtypes = [vp, vp]
+    l.vmc_energy_forces.argtypes = [vp, vp, vp, vp, i, i, d, u32, vp]
+    l.vmc_traj_walker_means.argtypes = [vp, vp]
+    l.vmc_traj_walker_forces.argtypes = [vp, vp]
+    l.vmc_traj_accepts.argtypes = [vp, vp]
+    l.vmc_build_S.argtypes = [vp, vp]
+    l.vmc_build_S_raw.argtypes = [vp, i, i, vp, vp, vp]
+    l.vmc_langevin_step.argtypes = [vp, i, d, vp, vp, vp, vp, vp, d, d, d, C.c_uint, u32, u32, u32]
+    l.vmc_eval_configs.argtypes = [vp, P(vmc_system), vp, vp, vp, i, vp, vp]
+    l.vmc_huckel_params.argtypes = [i, d, P(d), P(d), P(d)]
+
+
+def _check(rc, where):
+    if rc != VMC_OK:
+        raise VMCError(rc, where)
+
+
+def _dev(t, n=None):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous CUDA float64 tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def make_system(n, L, kappa=None, nmax=9, a_par=0.25, a_anti=0.5, b=1.0, precision=VMC_FP64):
+    return vmc_system(int(n), float(L), float(8.0 / L if kappa is None else kappa), int(nmax), a_par, a_anti, b,
+                      int(precision))
+
+
+class Context:
+    def __init__(self, device=0):
+        import torch
+        self.h = C.c_void_p()
+        _check(_lib().vmc_create(C.byref(self.h), device), "vmc_create")
+        self.sync_stream()
+
+    def sync_stream(self):
+        import torch
+        _check(_lib().vmc_set_stream(self.h, C.c_void_p(torch.cuda.current_stream().cuda_stream)), "vmc_set_stream")
+
+    def set_profiling(self, on=True):
+        _check(_lib().vmc_set_profiling(self.h, int(on)), "vmc_set_profiling")
+
+    def kernel_times(self):
+        n = 16
+        names = (C.c_char_p * n)()
+        ms = (C.c_double * n)()
+        cnt = (C.c_longlong * n)()
+        k = _lib().vmc_kernel_times(self.h, names, ms, cnt, n)
+        return {names[j].decode(): (ms[j], cnt[j]) for j in range(k)}
+
+    def reset_kernel_times(self):
+        _check(_lib().vmc_reset_kernel_times(self.h), "vmc_reset_kernel_times")
+
+    def close(self):
+        if self.h:
+            _lib().vmc_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Trajectory:
+    def __init__(self, ctx: Context, system: vmc_system, n_walkers: int, seed: int = 0, traj_id: int = 0):
+        self.ctx, self.sys, self.W, self.N = ctx, system, n_walkers, system.n_protons
+        self.h = C.c_void_p()
+        _check(_lib().vmc_traj_create(ctx.h, C.byref(system), n_walkers, seed, traj_id, C.byref(self.h)),
+               "vmc_traj_create")
+
+    def set_walkers(self, pos):
+        _check(_lib().vmc_traj_set_walkers(self.h, _dev(pos, self.W * self.N * 3)), "vmc_traj_set_walkers")
+
+    def get_walkers(self):
+        import torch
+        out = torch.empty((self.W, self.N, 3), dtype=torch.float64, device="cuda")
+        _check(_lib().vmc_traj_get_walkers(self.h, _dev(out)), "vmc_traj_get_walkers")
+        return out
+
+    def energy_forces(self, R, Cmo, zeta, n_equil, n_sweeps, delta, step=0, out=None):
+        return vmc_energy_forces(self, R, Cmo, zeta, n_equil, n_sweeps, delta, step, out)
+
+    def walker_means(self):
+        import torch
+        out = torch.empty((self.W, 1 + 9 * self.N), dtype=torch.float64, device="cuda")
+        _check(_lib().vmc_traj_walker_means(self.h, _dev(out)), "vmc_traj_walker_means")
+        return out
+
+    def walker_forces(self):
+        import torch
+        out = torch.empty((self.W, 3 * self.N), dtype=torch.float64, device="cuda")
+        _check(_lib().vmc_traj_walker_forces(self.h, _dev(out)), "vmc_traj_walker_forces")
+        return out
+
+    def accepts(self):
+        import torch
+        out = torch.empty(self.W, dtype=torch.int64, device="cuda")
+        _check(_lib().vmc_traj_accepts(self.h, C.c_void_p(out.data_ptr())), "vmc_traj_accepts")
+        return out
+
+    def build_S(self, S=None):
+        return vmc_build_S(self, S)
+
+    def close(self):
+        if self.h:
+            _lib().vmc_traj_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def vmc_energy_forces(traj: Trajectory, R, Cmo, zeta, n_equil, n_sweeps, delta, step=0, out=None):
+    import torch
+    N = traj.N
+    if out is None:
+        out = torch.empty(3 + 3 * N, dtype=torch.float64, device="cuda")
+    _check(_lib().vmc_energy_forces(traj.h, _dev(R, 3 * N), _dev(Cmo, N * (N // 2)), _dev(zeta, N), int(n_equil),
+                                    int(n_sweeps), float(delta), int(step), _dev(out, 3 + 3 * N)),
+           "vmc_energy_forces")
+    return out
+
+
+def vmc_build_S(traj: Trajectory, S=None):
+    import torch
+    n3 = 3 * traj.N
+    if S is None:
+        S = torch.empty((n3, n3), dtype=torch.float64, device="cuda")
+    _check(_lib().vmc_build_S(traj.h, _dev(S, n3 * n3)), "vmc_build_S")
+    return S
+
+
+def vmc_build_S_raw(ctx: Context, f_w, f, S=None):
+    import torch
+    W, n3 = f_w.shape
+    if S is None:
+        S = torch.empty((n3, n3), dtype=torch.float64, device="cuda")
+    _check(_lib().vmc_build_S_raw(ctx.h, W, n3, _dev(f_w), _dev(f, n3), _dev(S, n3 * n3)), "vmc_build_S_raw")
+    return S
+
+
+def vmc_langevin_step(ctx: Context, R, R_prev, S_prev, f, S, T, Delta, alpha, flags=0, seed=0, traj_id=0, step=0,
+                      box_L=0.0):
+    """One adopted-scheme step; R, R_prev, S_prev are updated in place.  Returns the status code
+    (VMC_OK or VMC_ENOTSPD/VMC_EINVAL) instead of raising, so callers can test failure handling."""
+    n3 = R.numel()
+    return _lib().vmc_langevin_step(ctx.h, n3, float(box_L), _dev(R), _dev(R_prev, n3), _dev(S_prev, n3 * n3),
+                                    _dev(f, n3), _dev(S, n3 * n3), float(T), float(Delta), float(alpha), int(flags),
+                                    int(seed), int(traj_id), int(step))
+
+
+def vmc_eval_configs(ctx: Context, system: vmc_system, R, Cmo, zeta, pos, out=None):
+    import torch
+    N = system.n_protons
+    K = pos.shape[0]
+    if out is None:
+        out = torch.empty((K, 2 + 6 * N), dtype=torch.float64, device="cuda")
+    _check(_lib().vmc_eval_configs(ctx.h, C.byref(system), _dev(R, 3 * N), _dev(Cmo, N * (N // 2)), _dev(zeta, N),
+                                   K, _dev(pos, K * N * 3), _dev(out, K * (2 + 6 * N))), "vmc_eval_configs")
+    return out
+
+
+def vmc_huckel_params(R, zeta, L):
+    """Host helper (numpy in, numpy out)."""
+    import numpy as np
+    R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
+    zeta = np.ascontiguousarray(zeta, dtype=np.float64)
+    n = zeta.size
+    Cm = np.zeros((n, n // 2))
+    P = C.POINTER(C.c_double)
+    _check(_lib().vmc_huckel_params(n, float(L), R.ctypes.data_as(P), zeta.ctypes.data_as(P), Cm.ctypes.data_as(P)),
+           "vmc_huckel_params")
+    return Cm
+
+
+def supported_n(n):
+    return bool(_lib().vmc_supported_n(int(n)))
+
+
+def library_path():
+    return LIB_PATH
