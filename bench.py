@@ -1,0 +1,182 @@
+"""Benchmark: VMC walker-sweeps/s with forces at N = 128 H (mixed precision), one
+MI355X.  A step is one full pass of the hot path: Hueckel orbitals and proton
+Ewald tables at R, the VMC energy/force estimate (5 re-equilibration + M measured
+sweeps on every walker), S = Cov of the mean force, and the Langevin update.
+
+Prints ONE JSON line (see the keys below).  Inputs are synthetic and seeded and
+already resident on the device when the timed region starts."""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "VMC walker-sweeps/s with forces at N=128 H; Langevin steps/s, p99 latency"
+PEAK_FP64_TFLOPS = 78.6      # MI355X vector / matrix FP64
+PEAK_FP32_TFLOPS = 157.3
+
+
+def algorithmic_flops(cls: str, N: int, W: int, nk: int) -> float:
+    """Algorithmic FP64/FP32 arithmetic per launch of a kernel class (FMA = 2 flops,
+    each exp/erfc/sqrt/div/sincos counted as 1).  The per-walker counts are those of
+    the method at this N (one launch processes all W walkers)."""
+    NS = N // 2
+    if cls == "slater_sample":
+        gemm = 3 * 2 * (2 * N * NS * NS)                      # B = C A^-1, M = X B, W = B M per spin
+        pass1 = N * N * (3 * 3 * 6 + 60 + 9)                  # 9 Gaussian images (5 ops + exp), products, X, adjoint terms
+        pass2 = N * N * (3 * 3 * 4 + 9 + 6)
+        wterm = N * NS * 2                                     # dot lengths of W are counted in gemm
+        jas = N * (N - 1) * 45
+        return float(W) * (gemm + pass1 + pass2 + jas - wterm)
+    if cls == "sweep_half":
+        per_move = 2 * N * NS + 2 * NS + N * 9 * 6 + (N - 1) * 2 * 16 + 0.5 * 2 * NS * NS
+        return float(W) * NS * per_move
+    if cls == "ewald_sample":
+        recip = nk * N * 8 + (N * N) // 3 * 6
+        real = (N * (N - 1) // 2) * 15 + N * N * 30
+        return float(W) * (recip + real)
+    return 0.0
+
+
+def run_cpu_baseline(wl, Cm, walkers: int, sweeps: int, threads: int):
+    from oracle import oracle as O
+    s = O.System(wl.R, wl.zeta, Cm, L=wl.L)
+    x = wl.electrons(W=walkers, seed_offset=99)
+    t0 = time.perf_counter()
+    s.vmc_run(x, 1, sweeps, wl.delta, seed=3, traj=0, step=0, threads=threads)
+    dt = time.perf_counter() - t0
+    return walkers * sweeps / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--walkers", type=int, default=16384)
+    ap.add_argument("--sweeps", type=int, default=100)
+    ap.add_argument("--rs", type=float, default=1.34)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--cpu-walkers", type=int, default=192)
+    ap.add_argument("--cpu-sweeps", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true", help="print per-kernel times to stderr")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the walker-sharded multi-GPU path is a design "
+              f"(see DESIGN.md), so --gpus {args.gpus} is not supported.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1605_08423_amd import vmc
+    from paper_1605_08423_amd.inputs import workload
+
+    wl = workload("h128", rs=args.rs)
+    N, W, M = wl.n, args.walkers, args.sweeps
+    prec = vmc.VMC_MIXED if args.precision == "mixed" else vmc.VMC_FP64
+    ctx = vmc.Context(0)
+    sysd = vmc.make_system(N, wl.L, precision=prec)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    traj = vmc.Trajectory(ctx, sysd, W, seed=wl.seed, traj_id=0)
+    traj.set_walkers(dev(wl.electrons(W=W)))
+    R = dev(wl.R.reshape(-1))
+    R_prev = R.clone()
+    zeta = dev(wl.zeta)
+    n3 = 3 * N
+    S_prev = torch.empty((n3, n3), dtype=torch.float64, device="cuda")
+    T_ha = wl.T_hartree
+    alpha = 0.122 * W * M             # N_c = W M samples per step
+    Delta = 1.0 / alpha               # alpha Delta = 1
+    kb = []
+    state = {"first": True}
+
+    def one_step(k: int, n_equil: int):
+        Rh = R.cpu().numpy()
+        Cm = vmc.vmc_huckel_params(Rh, wl.zeta, wl.L)
+        out = traj.energy_forces(R, dev(Cm), zeta, n_equil, M, wl.delta, step=k)
+        S = traj.build_S()
+        if state["first"]:
+            S_prev.copy_(S)
+            R_prev.copy_(R)
+            state["first"] = False
+        rc = vmc.vmc_langevin_step(ctx, R, R_prev, S_prev, out[3:], S, T_ha, Delta, alpha, 0, wl.seed, 0, k, wl.L)
+        if rc != 0:
+            raise RuntimeError(f"langevin step failed: {vmc._lib().vmc_strerror(rc).decode()}")
+        return out
+
+    for k in range(args.warmup):
+        one_step(k, 20 if k == 0 else 5)
+    torch.cuda.synchronize()
+    ctx.reset_kernel_times()
+    ctx.set_profiling(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        ts = time.perf_counter()
+        out = one_step(k, 20 if k == 0 else 5)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    times = ctx.kernel_times()
+    ctx.set_profiling(False)
+    out_h = out.cpu().numpy()
+
+    value = W * M * args.steps / elapsed
+    nk = traj_nk = None
+    # number of half-space k vectors (for the Ewald flop count)
+    nm = sysd.ewald_nmax
+    nk = sum(1 for nx in range(0, nm + 1) for ny in range(-nm, nm + 1) for nz in range(-nm, nm + 1)
+             if 0 < nx * nx + ny * ny + nz * nz <= nm * nm and (nx > 0 or (nx == 0 and (ny > 0 or (ny == 0 and nz > 0)))))
+    dom = max(times.items(), key=lambda kv: kv[1][0])
+    dom_name, (dom_ms, dom_n) = dom[0], dom[1]
+    flops = algorithmic_flops(dom_name, N, W, nk)
+    avg_s = dom_ms / max(dom_n, 1) / 1e3
+    achieved = flops / avg_s / 1e12 if avg_s > 0 else 0.0
+    peak = PEAK_FP64_TFLOPS
+    roofline = {"bound": "alu", "kernel": dom_name, "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "avg_launch_ms": round(avg_s * 1e3, 4), "algorithmic_flop_per_launch": flops}
+    if args.profile:
+        for kname, (ms, n) in sorted(times.items(), key=lambda kv: -kv[1][0]):
+            print(f"{kname:16s} {ms:10.2f} ms  {n:6d} launches  {ms / max(n, 1):9.4f} ms/launch", file=sys.stderr)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        Cm0, _ = O.huckel(wl.R, wl.zeta, wl.L, N // 2)
+        threads = min(os.cpu_count() or 1, 16)
+        v, dt = run_cpu_baseline(wl, Cm0, args.cpu_walkers, args.cpu_sweeps, threads)
+        cpu = {"value": round(v, 3), "unit": "walker-sweeps/s", "cores": threads, "kind": "oracle",
+               "sample": f"{args.cpu_walkers} walkers x (1 unmeasured + {args.cpu_sweeps} measured) sweeps of the "
+                         f"same N=128 box in FP64, {dt:.1f} s"}
+    lat_ms = sorted(1e3 * x for x in lat)
+    p = lambda q: lat_ms[min(len(lat_ms) - 1, int(math.ceil(q * len(lat_ms))) - 1)]
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "walker-sweeps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32/f64" if prec == vmc.VMC_MIXED else "f64", "data": "synthetic",
+        "config": {"workload": f"h128: 128 H + 128 e-, r_s={args.rs}, T=1000 K, {W} walkers x {M} measured "
+                               f"(+5 re-equilibration) sweeps per Langevin step, {args.precision} precision",
+                   "N": N, "walkers": W, "sweeps": M, "precision": args.precision},
+        "langevin_steps_per_s": round(args.steps / elapsed, 4),
+        "step_latency_ms": {"p50": round(p(0.5), 1), "p99": round(p(0.99), 1)},
+        "E_Ha": float(out_h[0]), "sigma_E_Ha": float(out_h[1]), "acceptance": float(out_h[2]),
+        "roofline": roofline, "cpu_baseline": cpu,
+        "kernel_ms": {k: round(v[0], 2) for k, v in times.items()},
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
