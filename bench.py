@@ -46,6 +46,30 @@ def algorithmic_flops(cls: str, N: int, W: int, nk: int) -> float:
     return 0.0
 
 
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources; a committed traffic measurement applies only to this hash."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1605_08423_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy), if taken on these sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    k = d.get("kernels", {}).get(kernel)
+    if not k or d.get("source_hash") != kernel_source_hash():
+        return None
+    return k["bytes_per_launch"]
+
+
 def run_cpu_baseline(wl, Cm, walkers: int, sweeps: int, threads: int):
     from oracle import oracle as O
     s = O.System(wl.R, wl.zeta, Cm, L=wl.L)
@@ -69,7 +93,18 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", help="print per-kernel times to stderr")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the walker-sharded multi-GPU path is a design "
               f"(see DESIGN.md), so --gpus {args.gpus} is not supported.", file=sys.stderr)
@@ -144,7 +179,7 @@ def main():
     achieved = flops / avg_s / 1e12 if avg_s > 0 else 0.0
     peak = PEAK_FP64_TFLOPS
     roofline = {"bound": "alu", "kernel": dom_name, "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom_name),
                 "avg_launch_ms": round(avg_s * 1e3, 4), "algorithmic_flop_per_launch": flops}
     if args.profile:
         for kname, (ms, n) in sorted(times.items(), key=lambda kv: -kv[1][0]):

@@ -41,12 +41,13 @@ __device__ __forceinline__ double block_sum256(double v, double* scratch4) {
 // ------------------------------------------------------------- Ewald ---
 constexpr int NMAXC = 12;   // largest supported ewald_nmax
 
-template <int N, class Real>
+template <int N, class Real, int NMX>
 __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* pe = reinterpret_cast<double*>(smem);   // N x 3 electrons
   double* pp = pe + 3 * N;                         // N x 3 protons
-  double2* ph = reinterpret_cast<double2*>(pp + 3 * N);   // 3 x N x (nmax+1) phase powers
+  double* part = pp + 3 * N;                       // 4 x N x 3 partial e-p gradients
+  double2* ph = reinterpret_cast<double2*>(part + 12 * N);   // 3 x N x (nmax+1) phase powers
   __shared__ double red[4];
   const int t = threadIdx.x, w = blockIdx.x;
   const int NP1 = e.nmax + 1;
@@ -78,9 +79,9 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
     const int nx0 = e.slot_nx0[sl];
     const int ay = ny < 0 ? -ny : ny, az = nz < 0 ? -nz : nz;
     const double sy = ny < 0 ? -1.0 : 1.0, sz = nz < 0 ? -1.0 : 1.0;
-    double ar[NMAXC + 1], ai[NMAXC + 1];
+    double ar[NMX + 1], ai[NMX + 1];
 #pragma unroll
-    for (int j = 0; j <= NMAXC; ++j) { ar[j] = 0.0; ai[j] = 0.0; }
+    for (int j = 0; j <= NMX; ++j) { ar[j] = 0.0; ai[j] = 0.0; }
     for (int i = 0; i < N; ++i) {
       const double2 ey = ph[((size_t)1 * N + i) * NP1 + ay];
       const double2 ez = ph[((size_t)2 * N + i) * NP1 + az];
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
       const double tr = yr * zr - yi * zi, ti = yr * zi + yi * zr;
       const double2* ex = ph + (size_t)i * NP1 + nx0;
 #pragma unroll
-      for (int j = 0; j <= NMAXC; ++j) {
+      for (int j = 0; j <= NMX; ++j) {
         if (j < cnt) {
           const double2 x = ex[j];
           ar[j] += x.x * tr - x.y * ti;
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
       }
     }
 #pragma unroll
-    for (int j = 0; j <= NMAXC; ++j) {
+    for (int j = 0; j <= NMX; ++j) {
       if (j < cnt) {
         const int k = k0 + j;
         const double rer = -ar[j], rei = -ai[j];            // electron charge -1
@@ -108,15 +109,17 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
       }
     }
   }
-  // real space: u < N electron-electron (half circulant), N <= u < 2N electron-proton
+  // real space in 6N tasks of about N/4 pairs: u < 2N electron-electron (half
+  // circulant offsets split in two), 2N <= u < 6N electron-proton (electrons split in four)
   const Real kap = (Real)e.kappa;
   const Real tkp = (Real)(2.0 * e.kappa / 1.7724538509055160273);
   double vreal = 0.0;
-  for (int u = t; u < 2 * N; u += 256) {
-    if (u < N) {
-      const int i = u;
+  for (int u = t; u < 6 * N; u += 256) {
+    if (u < 2 * N) {
+      const int i = u % N, hh = u / N;
+      const int d0 = hh == 0 ? 1 : N / 4 + 1, d1 = hh == 0 ? N / 4 : N / 2;
       Real vs = Real(0);
-      for (int dd = 1; dd <= N / 2; ++dd) {
+      for (int dd = d0; dd <= d1; ++dd) {
         if (dd == N / 2 && i >= N / 2) break;
         const int j = (i + dd) % N;
         Real r2 = Real(0);
@@ -130,9 +133,10 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
       }
       vreal += (double)vs;
     } else {
-      const int b = u - N;
+      const int b = (u - 2 * N) % N, qd = (u - 2 * N) / N;
+      const int i0 = qd * N / 4, i1 = (qd + 1) * N / 4;
       Real vs = Real(0), gx = Real(0), gy = Real(0), gz = Real(0);
-      for (int i = 0; i < N; ++i) {
+      for (int i = i0; i < i1; ++i) {
         const Real dx = (Real)min_image(pp[3 * b] - pe[3 * i], L, invL);
         const Real dy = (Real)min_image(pp[3 * b + 1] - pe[3 * i + 1], L, invL);
         const Real dz = (Real)min_image(pp[3 * b + 2] - pe[3 * i + 2], L, invL);
@@ -147,34 +151,60 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
         gx += gsc * dx; gy += gsc * dy; gz += gsc * dz;
       }
       vreal += (double)vs;
-      double* dv = m.dVs + (size_t)w * 3 * N + 3 * b;
-      dv[0] = (double)gx; dv[1] = (double)gy; dv[2] = (double)gz;
+      double* pq = part + ((size_t)qd * N + b) * 3;
+      pq[0] = (double)gx; pq[1] = (double)gy; pq[2] = (double)gz;
     }
+  }
+  __syncthreads();
+  for (int b = t; b < N; b += 256) {
+    double* dv = m.dVs + (size_t)w * 3 * N + 3 * b;
+    for (int c = 0; c < 3; ++c)
+      dv[c] = (part[(0 * N + b) * 3 + c] + part[(1 * N + b) * 3 + c]) +
+              (part[(2 * N + b) * 3 + c] + part[(3 * N + b) * 3 + c]);
   }
   const double vtot = block_sum256(vrec + vreal, red);
   if (t == 0) m.Vs[w] = vtot + e.Vconst;
 }
 
 // ------------------------------------------------- Slater and Jastrow ---
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// One 16x16x4 FP64 matrix-core step: D += A(16x4) B(4x16).  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; element v of its result is
+// D[l / 16 + 4 v][l % 16] (the row interleave was read off the hardware).
+__device__ __forceinline__ d4_t mfma16(double av, double bv, d4_t acc) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+}
+
+// Per walker (one 256-thread block): Jastrow gradient/Laplacian per electron;
+// per spin the three contractions B = C A^-1, M = X B, W = B M on the FP64
+// matrix cores (dimensions padded to multiples of 16 with zeros), and the
+// elementwise basis passes that build X and the d/dR terms.
 template <int NS, class Real>
 __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
   constexpr int N = 2 * NS;
+  constexpr int NSP = (NS + 15) / 16 * 16, NP = (N + 15) / 16 * 16;
   constexpr int H = 256 / N;            // threads per basis centre in the pair passes
   constexpr int NT = H * N;
   constexpr int IPT = (NS + H - 1) / H; // electrons per thread per spin
-  constexpr int LDB = NS + 1;
-  constexpr int XMS0 = (NS * N > NS * NS ? NS * N : NS * NS);
-  constexpr int XMS = (XMS0 > 6 * NT ? XMS0 : 6 * NT);   // also holds the per-centre partials
-  constexpr int MPT = (NS * NS + 255) / 256;
+  constexpr int LDB = NSP + 1;          // row stride of B / W   (NP rows)
+  constexpr int LDX = NP + 1;           // row stride of X       (NSP rows)
+  constexpr int LDI = NSP + 1;          // row stride of A^-1 and M (NSP rows)
+  constexpr int XMS0 = (NSP * LDX > NSP * LDI ? NSP * LDX : NSP * LDI);
+  constexpr int XMS = (XMS0 > 6 * NT ? XMS0 : 6 * NT);
+  constexpr int TI = NSP / 16, TA = NP / 16;      // tile counts along electrons / centres
+  constexpr int TPW_B = (TA * TI + 3) / 4;        // N x NS outputs per wave
+  constexpr int TPW_M = (TI * TI + 3) / 4;        // NS x NS outputs per wave
   extern __shared__ __align__(16) unsigned char smem[];
   double* pos = reinterpret_cast<double*>(smem);     // N x 3
   double* gU = pos + 3 * N;                            // N x 3
   double* lU = gU + 3 * N;                             // N
-  double* Bs = lU + N;                                 // N x LDB
-  double* XM = Bs + N * LDB;                           // XMS
+  double* Bs = lU + N;                                 // NP x LDB : B, later W
+  double* XM = Bs + NP * LDB;                          // A^-1, X, M, partials
   Real* trig = reinterpret_cast<Real*>(XM + XMS);      // N x 6 (sin x3, cos x3)
   __shared__ double red[4];
   const int t = threadIdx.x, w = blockIdx.x;
+  const int lane = t & 63, wave = t >> 6, l16 = lane & 15, l4 = lane >> 4;
   const double L = m.L, invL = m.invL;
   for (int u = t; u < 3 * N; u += 256) pos[u] = m.pos[(size_t)w * 3 * N + u];
   __syncthreads();
@@ -230,29 +260,50 @@ __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
   const double Ra0 = m.R[3 * a], Ra1 = m.R[3 * a + 1], Ra2 = m.R[3 * a + 2];
   const Real za = (Real)m.zeta[a];
   for (int sp = 0; sp < 2; ++sp) {
+    // A^-1 of this spin into XM (NSP x LDI, zero padded)
     const double* Bi = m.Binv + ((size_t)w * 2 + sp) * NS * NS;
-    for (int u = t; u < NS * NS; u += 256) XM[u] = Bi[u];
+    for (int u = t; u < NSP * NSP; u += 256) {
+      const int k = u / NSP, j = u % NSP;
+      XM[k * LDI + j] = (k < NS && j < NS) ? Bi[k * NS + j] : 0.0;
+    }
     __syncthreads();
-    double Bv[IPT];
+    // B = C A^-1 (NP x NSP) on the matrix cores -> Bs
+    {
+      d4_t acc[TPW_B];
 #pragma unroll
-    for (int s = 0; s < IPT; ++s) Bv[s] = 0.0;
-    if (act) {
-      for (int k = 0; k < NS; ++k) {
-        const double c = m.C[a * NS + k];
+      for (int q = 0; q < TPW_B; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int s = 0; s < IPT; ++s) {
-          const int i = h + H * s;
-          if (i < NS) Bv[s] += c * XM[k * NS + i];
+      for (int q = 0; q < TPW_B; ++q) {
+        const int tt = wave + 4 * q;
+        if (tt < TA * TI) {
+          const int ta = tt / TI, tc = tt % TI;
+          const int arow = ta * 16 + l16;
+#pragma unroll 4
+          for (int kk = 0; kk < NSP / 4; ++kk) {
+            const int k = kk * 4 + l4;
+            const double av = (arow < N && k < NS) ? m.C[arow * NS + k] : 0.0;
+            const double bv = XM[k * LDI + tc * 16 + l16];
+            acc[q] = mfma16(av, bv, acc[q]);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < TPW_B; ++q) {
+        const int tt = wave + 4 * q;
+        if (tt < TA * TI) {
+          const int ta = tt / TI, tc = tt % TI;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Bs[(ta * 16 + l4 + 4 * v) * LDB + tc * 16 + l16] = acc[q][v];
         }
       }
     }
     __syncthreads();
+    // pass 1: basis derivatives -> X, and the terms that need only B
     if (act) {
 #pragma unroll
       for (int s = 0; s < IPT; ++s) {
         const int i = h + H * s;
         if (i >= NS) continue;
-        Bs[a * LDB + i] = Bv[s];
         const int e = sp * NS + i;
         Real g[3][4];
         gauss1d<Real, 3>((Real)min_image(pos[3 * e] - Ra0, L, invL), za, (Real)L, g[0]);
@@ -269,8 +320,8 @@ __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
         const double glz = g[2][3] * p02 + g[2][1] * (g[0][2] * g[1][0] + g[0][0] * g[1][2]);
         const double u0 = gU[3 * e], u1 = gU[3 * e + 1], u2 = gU[3 * e + 2];
         const double X = -0.5 * (lap + 2.0 * (gx * u0 + gy * u1 + gz * u2));
-        XM[i * N + a] = X;
-        const double b = Bv[s];
+        XM[i * LDX + a] = X;
+        const double b = Bs[a * LDB + i];
         tsl += X * b;
         dln0 -= b * gx; dln1 -= b * gy; dln2 -= b * gz;
         dT0 += 0.5 * (glx + 2.0 * (hxx * u0 + hxy * u1 + hxz * u2)) * b;
@@ -279,32 +330,77 @@ __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
       }
     }
     __syncthreads();
-    double Mv[MPT];
+    // M = X B (NSP x NSP), K = centres
+    {
+      d4_t acc[TPW_M];
 #pragma unroll
-    for (int q = 0; q < MPT; ++q) {
-      const int o = t + 256 * q;
-      Mv[q] = 0.0;
-      if (o < NS * NS) {
-        const int j = o / NS, i = o % NS;
-        double acc = 0.0;
-        for (int c = 0; c < N; ++c) acc += XM[j * N + c] * Bs[c * LDB + i];
-        Mv[q] = acc;
+      for (int q = 0; q < TPW_M; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < TPW_M; ++q) {
+        const int tt = wave + 4 * q;
+        if (tt < TI * TI) {
+          const int tr = tt / TI, tc = tt % TI;
+          const int irow = tr * 16 + l16;
+#pragma unroll 4
+          for (int kk = 0; kk < NP / 4; ++kk) {
+            const int k = kk * 4 + l4;
+            const double av = (irow < NS && k < N) ? XM[irow * LDX + k] : 0.0;
+            const double bv = (k < N) ? Bs[k * LDB + tc * 16 + l16] : 0.0;
+            acc[q] = mfma16(av, bv, acc[q]);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < TPW_M; ++q) {
+        const int tt = wave + 4 * q;
+        if (tt < TI * TI) {
+          const int tr = tt / TI, tc = tt % TI;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) XM[(tr * 16 + l4 + 4 * v) * LDI + tc * 16 + l16] = acc[q][v];
+        }
       }
     }
     __syncthreads();
+    // W = B M (NP x NSP), K = orbitals; B is the A operand, W replaces it in Bs
+    {
+      d4_t acc[TPW_B];
 #pragma unroll
-    for (int q = 0; q < MPT; ++q) {
-      const int o = t + 256 * q;
-      if (o < NS * NS) XM[o] = Mv[q];
+      for (int q = 0; q < TPW_B; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < TPW_B; ++q) {
+        const int tt = wave + 4 * q;
+        if (tt < TA * TI) {
+          const int ta = tt / TI, tc = tt % TI;
+          const int arow = ta * 16 + l16;
+#pragma unroll 4
+          for (int kk = 0; kk < NSP / 4; ++kk) {
+            const int k = kk * 4 + l4;
+            const double av = (arow < N) ? Bs[arow * LDB + k] : 0.0;
+            const double bv = XM[k * LDI + tc * 16 + l16];
+            acc[q] = mfma16(av, bv, acc[q]);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < TPW_B; ++q) {
+        const int tt = wave + 4 * q;
+        if (tt < TA * TI) {
+          const int ta = tt / TI, tc = tt % TI;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Bs[(ta * 16 + l4 + 4 * v) * LDB + tc * 16 + l16] = acc[q][v];
+        }
+      }
     }
     __syncthreads();
+    // pass 2: dT/dR_a += grad phi_a(r_i) W_ai
     if (act) {
 #pragma unroll
       for (int s = 0; s < IPT; ++s) {
         const int i = h + H * s;
         if (i >= NS) continue;
-        double Wv = 0.0;
-        for (int j = 0; j < NS; ++j) Wv += Bs[a * LDB + j] * XM[j * NS + i];
+        const double Wv = Bs[a * LDB + i];
         const int e = sp * NS + i;
         Real g[3][4];
         gauss1d<Real, 1>((Real)min_image(pos[3 * e] - Ra0, L, invL), za, (Real)L, g[0]);
@@ -440,17 +536,22 @@ __global__ __launch_bounds__(256) void k_proton_const(int N, double L, EwaldArgs
 // ----------------------------------------------------------- launchers ---
 template <int N, class Real>
 hipError_t launch_ewald_t(const MeasureArgs& m, const EwaldArgs& e, hipStream_t st) {
-  size_t sm = (size_t)6 * N * sizeof(double) + (size_t)3 * N * (e.nmax + 1) * sizeof(double2);
-  hipLaunchKernelGGL((k_ewald_sample<N, Real>), dim3(m.W), dim3(256), sm, st, m, e);
+  size_t sm = (size_t)18 * N * sizeof(double) + (size_t)3 * N * (e.nmax + 1) * sizeof(double2);
+  if (e.nmax <= 9)
+    hipLaunchKernelGGL((k_ewald_sample<N, Real, 9>), dim3(m.W), dim3(256), sm, st, m, e);
+  else
+    hipLaunchKernelGGL((k_ewald_sample<N, Real, NMAXC>), dim3(m.W), dim3(256), sm, st, m, e);
   return hipGetLastError();
 }
 template <int NS>
 size_t slater_smem() {
   constexpr int N = 2 * NS;
+  constexpr int NSP = (NS + 15) / 16 * 16, NP = (N + 15) / 16 * 16;
   constexpr int NT = (256 / N) * N;
-  constexpr int XMS0 = (NS * N > NS * NS ? NS * N : NS * NS);
+  constexpr int LDB = NSP + 1, LDX = NP + 1, LDI = NSP + 1;
+  constexpr int XMS0 = (NSP * LDX > NSP * LDI ? NSP * LDX : NSP * LDI);
   constexpr int XMS = (XMS0 > 6 * NT ? XMS0 : 6 * NT);
-  return ((size_t)3 * N + 3 * N + N + (size_t)N * (NS + 1) + XMS) * sizeof(double) + (size_t)6 * N * sizeof(double);
+  return ((size_t)3 * N + 3 * N + N + (size_t)NP * LDB + XMS) * sizeof(double) + (size_t)6 * N * sizeof(double);
 }
 template <int NS, class Real>
 hipError_t launch_slater_t(const MeasureArgs& m, hipStream_t st) {

@@ -41,87 +41,84 @@ __global__ __launch_bounds__(256) void k_build_A(WalkerArgs a) {
       phi_s[wv][c] = phi_value<Real>(rx, ry, rz, a.R + 3 * c, (Real)a.zeta[c], a.L, a.invL);
     wave_lds_sync();
     if (lane < NS) {
-      Real m = Real(0);
-      for (int c = 0; c < N; ++c) m += phi_s[wv][c] * (Real)a.C[c * NS + lane];
+      double m = 0.0;
+      for (int c = 0; c < N; ++c) m += (double)phi_s[wv][c] * a.C[c * NS + lane];
       int sp = e / NS, i = e % NS;
-      a.Amat[(((size_t)w * 2 + sp) * NS + i) * NS + lane] = (double)m;
+      a.Amat[(((size_t)w * 2 + sp) * NS + i) * NS + lane] = m;
     }
     wave_lds_sync();
   }
 }
 
 // ------------------------------------------------------- inverse refresh ---
-// In-place Gauss-Jordan inversion with partial (row) pivoting, one wave per
-// matrix in LDS; columns are unscrambled in reverse pivot order at the end.
-// Also records ln|det| and the sign.  A zero pivot sets *status = 1.
+// Gauss-Jordan inversion with partial pivoting, one wave per matrix, entirely
+// in registers: lane i holds row i of A.  Pivoting is implicit (the pivot row
+// of column p is the unused row with the largest |A[i][p]|, ties to the lowest
+// row); the pivot row is broadcast by readlane and every other row is updated
+// with one FMA per column.  The in-place inverse ends with rows and columns
+// permuted: the row that pivoted column k holds row k of A^-1 with column c
+// stored at position pi(c).  ln|det A| = sum ln|pivot|, sign from the pivots
+// and the parity of pi.  A zero pivot sets *status = 1.
 template <int NS>
-__global__ __launch_bounds__(64) void k_invert(WalkerArgs a, int spin_lo, int spin_hi) {
-  constexpr int LD = NS + 1;
-  __shared__ double m[NS * LD];
-  __shared__ int pivots[NS];
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(256) void k_invert(WalkerArgs a, int spin_lo, int spin_hi) {
+  constexpr int BC = 16, NB = (NS + BC - 1) / BC;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nsp = spin_hi - spin_lo;
-  const int w = blockIdx.x / nsp, sp = spin_lo + blockIdx.x % nsp;
+  const int mat = blockIdx.x * 4 + wv;
+  const int w = mat / nsp, sp = spin_lo + mat % nsp;
   if (w >= a.W) return;
   const size_t base = ((size_t)w * 2 + sp) * NS * NS;
-  for (int t = lane; t < NS * NS; t += 64) m[(t / NS) * LD + t % NS] = a.Amat[base + t];
-  wave_lds_sync();
+  const bool isrow = lane < NS;
+  double r[NB][BC];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) {
+      const int c = b * BC + j;
+      r[b][j] = (isrow && c < NS) ? a.Amat[base + (size_t)lane * NS + c] : 0.0;
+    }
+  bool used = !isrow;
+  int myk = 0, mypi = 0;
   double logdet = 0.0, sgn = 1.0;
   bool singular = false;
-  for (int p = 0; p < NS; ++p) {
-    double bv = -1.0;
-    int bi = NS;
-    for (int r = lane; r < NS; r += 64)
-      if (r >= p) {
-        double v = fabs(m[r * LD + p]);
-        if (v > bv) { bv = v; bi = r; }
-      }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      double ov = __shfl_xor(bv, off, 64);
-      int oi = __shfl_xor(bi, off, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    const int piv = __builtin_amdgcn_readfirstlane(bi);
-    const double pv = readlane_d(m[piv * LD + p], 0);
-    if (pv == 0.0) { singular = true; break; }
-    if (piv != p) {
-      for (int c = lane; c < NS; c += 64) {
-        double t0 = m[p * LD + c], t1 = m[piv * LD + c];
-        m[p * LD + c] = t1;
-        m[piv * LD + c] = t0;
-      }
-      sgn = -sgn;
-    }
-    if (lane == 0) pivots[p] = piv;
-    logdet += log(fabs(pv));
-    if (pv < 0.0) sgn = -sgn;
-    const double pinv = 1.0 / pv;
-    wave_lds_sync();
-    double prow[(NS + 63) / 64];
+  for (int pb = 0; pb < NB; ++pb) {
+    const int qmax = (NS - pb * BC) < BC ? (NS - pb * BC) : BC;
+    for (int q = 0; q < qmax; ++q) {
+      const int p = pb * BC + q;
+      double rp = r[pb][0];
 #pragma unroll
-    for (int t = 0; t < (NS + 63) / 64; ++t) {
-      int c = lane + 64 * t;
-      if (c < NS) {
-        double v = (c == p) ? pinv : m[p * LD + c] * pinv;
-        m[p * LD + c] = v;
-        prow[t] = v;
-      }
-    }
-    wave_lds_sync();
-    // column p of every row (lane r holds row r's multiplier; NS <= 64)
-    const double fcol = (lane < NS) ? m[lane * LD + p] : 0.0;
-    wave_lds_sync();
-    for (int r = 0; r < NS; ++r) {
-      if (r == p) continue;
-      const double f = readlane_d(fcol, r);
+      for (int j = 1; j < BC; ++j) rp = (j == q) ? r[pb][j] : rp;
+      double bv = used ? -1.0 : fabs(rp);
+      int bi = lane;
 #pragma unroll
-      for (int t = 0; t < (NS + 63) / 64; ++t) {
-        int c = lane + 64 * t;
-        if (c < NS) m[r * LD + c] = ((c == p) ? 0.0 : m[r * LD + c]) - f * prow[t];
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
       }
+      const int piv = __builtin_amdgcn_readfirstlane(bi);
+      const double pv = readlane_d(rp, piv);
+      if (pv == 0.0) { singular = true; break; }
+      logdet += log(fabs(pv));
+      if (pv < 0.0) sgn = -sgn;
+      const double pinv = 1.0 / pv;
+      const bool me = lane == piv;
+      if (me) { used = true; myk = p; }
+      if (lane == p) mypi = piv;
+      const double g = (me ? (pv - 1.0) : rp) * pinv;
+      const double diag = (me ? 1.0 : 0.0) - g;
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int j = 0; j < BC; ++j) {
+          if (b * BC + j >= NS) continue;
+          const double pc = readlane_d(r[b][j], piv);
+          const double upd = fma(-g, pc, r[b][j]);
+          r[b][j] = (b == pb && j == q) ? diag : upd;
+        }
     }
-    wave_lds_sync();
+    if (singular) break;
   }
   if (singular) {
     if (lane == 0) {
@@ -131,17 +128,24 @@ __global__ __launch_bounds__(64) void k_invert(WalkerArgs a, int spin_lo, int sp
     }
     return;
   }
-  for (int p = NS - 1; p >= 0; --p) {
-    const int q = pivots[p];
-    if (q != p)
-      for (int r = lane; r < NS; r += 64) {
-        double t0 = m[r * LD + p], t1 = m[r * LD + q];
-        m[r * LD + p] = t1;
-        m[r * LD + q] = t0;
-      }
-    wave_lds_sync();
+  // parity of pi: lane p counts q > p with pi(q) < pi(p)
+  int inv_cnt = 0;
+  for (int q = 0; q < NS; ++q) {
+    const int pq = __builtin_amdgcn_readlane(mypi, q);
+    if (isrow && q > lane && pq < mypi) ++inv_cnt;
   }
-  for (int t = lane; t < NS * NS; t += 64) a.Binv[base + t] = m[(t / NS) * LD + t % NS];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) inv_cnt += __shfl_xor(inv_cnt, off, 64);
+  if (inv_cnt & 1) sgn = -sgn;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) {
+      const int c = b * BC + j;
+      if (c >= NS) continue;
+      const int col = __builtin_amdgcn_readlane(mypi, c);
+      if (isrow) a.Binv[base + (size_t)myk * NS + col] = r[b][j];
+    }
   if (lane == 0) {
     a.ldet[(size_t)w * 2 + sp] = logdet;
     a.sgn[(size_t)w * 2 + sp] = sgn;
@@ -159,22 +163,18 @@ __device__ __forceinline__ T pick(const T (&v)[E], int s) {
 
 // Moves the NS electrons of spin `sp` of every walker once, in order.
 template <int NS, class Real>
-__global__ __launch_bounds__(256, (NS >= 64 ? 1 : 2)) void k_sweep_half(WalkerArgs a, SweepArgs s) {
+__global__ __launch_bounds__(256, ((sizeof(Real) == 8 && NS >= 27) || NS >= 64) ? 1 : 2) void k_sweep_half(WalkerArgs a, SweepArgs s) {
   constexpr int N = 2 * NS;
   constexpr int WPB = 4;
   constexpr int EPL = (N + 63) / 64;     // electrons (and centres) per lane
   extern __shared__ __align__(16) unsigned char smem[];
-  Real* Cs = reinterpret_cast<Real*>(smem);                      // N x NS
-  Real* phi_s = Cs + N * NS;                                       // WPB x N
-  double* m_s = reinterpret_cast<double*>(smem + ((N * NS + WPB * N) * sizeof(Real) + 15) / 16 * 16);  // WPB x NS
-  for (int t = threadIdx.x; t < N * NS; t += blockDim.x) Cs[t] = (Real)a.C[t];
+  double* Cs = reinterpret_cast<double*>(smem);                  // N x NS (FP64 in both modes)
+  for (int t = threadIdx.x; t < N * NS; t += blockDim.x) Cs[t] = a.C[t];
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int w = blockIdx.x * WPB + wv;
   if (w >= a.W) return;
   const int sp = s.spin;
-  Real* phi = phi_s + wv * N;
-  double* mrow = m_s + wv * NS;
   const double L = a.L, invL = a.invL;
   const Real LoverPi = (Real)(L / VMC_PI);
 
@@ -225,16 +225,18 @@ __global__ __launch_bounds__(256, (NS >= 64 ? 1 : 2)) void k_sweep_half(WalkerAr
     const double xn = wrap_box(xo + delta * (ux - 0.5), L, invL);
     const double yn = wrap_box(yo + delta * (uy - 0.5), L, invL);
     const double zn = wrap_box(zo + delta * (uz - 0.5), L, invL);
-    // basis row at the proposed position
+    // basis row at the proposed position: lane keeps phi of its own centres
+    Real phv[EPL];
 #pragma unroll
     for (int t = 0; t < EPL; ++t) {
       int c = lane + 64 * t;
+      phv[t] = Real(0);
       if (c < N) {
         Real g[3][4];
         gauss1d<Real, 0>((Real)min_image(xn - Rc[t][0], L, invL), zc[t], (Real)L, g[0]);
         gauss1d<Real, 0>((Real)min_image(yn - Rc[t][1], L, invL), zc[t], (Real)L, g[1]);
         gauss1d<Real, 0>((Real)min_image(zn - Rc[t][2], L, invL), zc[t], (Real)L, g[2]);
-        phi[c] = g[0][0] * g[1][0] * g[2][0];
+        phv[t] = g[0][0] * g[1][0] * g[2][0];
       }
     }
     // trig cache of the proposed position: lanes 0..2 compute one axis each
@@ -252,20 +254,20 @@ __global__ __launch_bounds__(256, (NS >= 64 ? 1 : 2)) void k_sweep_half(WalkerAr
       so[m] = readlane<Real>(slot == 0 ? ts[0][m] : ts[EPL - 1][m], owner);
       co[m] = readlane<Real>(slot == 0 ? tc[0][m] : tc[EPL - 1][m], owner);
     }
-    wave_lds_sync();
-    // MO row m_k = sum_a phi_a C[a][k]
-    double mk = 0.0;
-    if (lane < NS) {
-      Real acc = Real(0);
-      for (int c = 0; c < N; ++c) acc += phi[c] * Cs[c * NS + lane];
-      mk = (double)acc;
-      mrow[lane] = mk;
+    // MO row m_k = sum_a phi_a C[a][k] in FP64: phi_a broadcast from its lane
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) {
+      const int cmax = (N - 64 * t) < 64 ? (N - 64 * t) : 64;
+#pragma unroll 8
+      for (int l = 0; l < cmax; ++l)
+        acc += (double)readlane<Real>(phv[t], l) * Cs[(64 * t + l) * NS + (lane < NS ? lane : 0)];
     }
-    wave_lds_sync();
+    const double mk = (lane < NS) ? acc : 0.0;
     // v_j = sum_k m_k (A^-1)[k][j]; the ratio is q = v_i
     double vj = 0.0;
 #pragma unroll
-    for (int k = 0; k < NS; ++k) vj += mrow[k] * bcol[k];
+    for (int k = 0; k < NS; ++k) vj += readlane_d(mk, k) * bcol[k];
     const double q = readlane_d(vj, i);
     // Jastrow change sum_j u(r', r_j) - u(r_e, r_j)
     Real du = Real(0);
@@ -294,7 +296,6 @@ __global__ __launch_bounds__(256, (NS >= 64 ? 1 : 2)) void k_sweep_half(WalkerAr
       if (lane < NS) a.Amat[bbase + (size_t)i * NS + lane] = mk;
       ++nacc;
     }
-    wave_lds_sync();
   }
   if (lane < NS) {
 #pragma unroll
@@ -317,14 +318,14 @@ hipError_t launch_build_A_t(const WalkerArgs& a, hipStream_t st) {
 }
 template <int NS>
 hipError_t launch_invert_t(const WalkerArgs& a, int spin_lo, int spin_hi, hipStream_t st) {
-  dim3 grid(a.W * (spin_hi - spin_lo));
-  hipLaunchKernelGGL((k_invert<NS>), grid, dim3(64), 0, st, a, spin_lo, spin_hi);
+  dim3 grid((a.W * (spin_hi - spin_lo) + 3) / 4);
+  hipLaunchKernelGGL((k_invert<NS>), grid, dim3(256), 0, st, a, spin_lo, spin_hi);
   return hipGetLastError();
 }
 template <int NS, class Real>
 size_t sweep_smem() {
   constexpr int N = 2 * NS;
-  return ((N * NS + 4 * N) * sizeof(Real) + 15) / 16 * 16 + 4 * NS * sizeof(double);
+  return (size_t)N * NS * sizeof(double);
 }
 template <int NS, class Real>
 hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t st) {
