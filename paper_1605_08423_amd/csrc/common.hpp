@@ -76,11 +76,13 @@ template <> __device__ __forceinline__ float dev_exp<float>(float x) { return __
 // Periodic Gaussian factor along one axis at minimum-image offset x in
 // [-L/2, L/2): images n = -1, 0, +1 of e^{-zeta (x + n L)^2} (the far images are
 // below e^{-zeta (1.5 L)^2}).  NDER = number of derivatives wanted (0..3).
-template <class Real, int NDER>
-__device__ __forceinline__ void gauss1d(Real x, Real zeta, Real L, Real g[4]) {
+// nimg = 0 keeps only n = 0; the caller uses it only where every dropped image is
+// below e^{-zeta_min (L/2)^2} <= e^{-23}, i.e. under FP32 resolution.
+template <class Real, int NDER, int NIMG>
+__device__ __forceinline__ void gauss1d_n(Real x, Real zeta, Real L, Real g[4]) {
   g[0] = g[1] = g[2] = g[3] = Real(0);
 #pragma unroll
-  for (int n = -1; n <= 1; ++n) {
+  for (int n = -NIMG; n <= NIMG; ++n) {
     Real t = x + Real(n) * L;
     Real e = dev_exp<Real>(-zeta * t * t);
     g[0] += e;
@@ -89,6 +91,10 @@ __device__ __forceinline__ void gauss1d(Real x, Real zeta, Real L, Real g[4]) {
     if (NDER >= 3) g[3] += (Real(-8) * zeta * zeta * zeta * t * t * t + Real(12) * zeta * zeta * t) * e;
   }
 }
+
+// Orders this wave's LDS writes before its later LDS reads (the wave's LDS
+// operations complete in order; the clobber keeps the compiler from moving them).
+__device__ __forceinline__ void lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 template <class Real> __device__ __forceinline__ Real dev_sqrt(Real x);
 template <> __device__ __forceinline__ double dev_sqrt<double>(double x) { return sqrt(x); }

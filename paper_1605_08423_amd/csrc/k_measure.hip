@@ -180,18 +180,36 @@ __device__ __forceinline__ d4_t mfma16(double av, double bv, d4_t acc) {
 // per spin the three contractions B = C A^-1, M = X B, W = B M on the FP64
 // matrix cores (dimensions padded to multiples of 16 with zeros), and the
 // elementwise basis passes that build X and the d/dR terms.
+// LDS layout of k_slater_sample (bytes), shared with the launcher.  B/W and X are
+// stored as Real (FP32 in mixed mode: they carry FP32-level errors already); the
+// inverse staging, M and the partial sums are FP64.
 template <int NS, class Real>
-__global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
+struct SlaterLds {
+  static constexpr int N = 2 * NS;
+  static constexpr int NSP = (NS + 15) / 16 * 16, NP = (N + 15) / 16 * 16;
+  static constexpr int NT = (256 / N) * N;
+  static constexpr int LDB = NSP + 1, LDX = NP + 1, LDI = NSP + 1;
+  static constexpr size_t head = (size_t)(3 * N + 3 * N + N) * sizeof(double) + (size_t)6 * N * sizeof(Real);
+  static constexpr size_t bs = (size_t)NP * LDB * sizeof(Real);
+  static constexpr size_t xm0 = (size_t)NSP * LDX * sizeof(Real);
+  static constexpr size_t xm1 = (size_t)NSP * LDI * sizeof(double);
+  static constexpr size_t xm2 = (size_t)6 * NT * sizeof(double);
+  static constexpr size_t xm3 = (size_t)5 * 256 * sizeof(double);
+  static constexpr size_t xm01 = xm0 > xm1 ? xm0 : xm1, xm23 = xm2 > xm3 ? xm2 : xm3;
+  static constexpr size_t xm = xm01 > xm23 ? xm01 : xm23;
+  static constexpr size_t pad(size_t v) { return (v + 15) / 16 * 16; }
+  static constexpr size_t bytes = pad(head) + pad(bs) + xm;
+};
+
+template <int NS, class Real, int NIMG>
+__global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sample(MeasureArgs m) {
+  using Lay = SlaterLds<NS, Real>;
   constexpr int N = 2 * NS;
-  constexpr int NSP = (NS + 15) / 16 * 16, NP = (N + 15) / 16 * 16;
+  constexpr int NSP = Lay::NSP, NP = Lay::NP;
   constexpr int H = 256 / N;            // threads per basis centre in the pair passes
   constexpr int NT = H * N;
   constexpr int IPT = (NS + H - 1) / H; // electrons per thread per spin
-  constexpr int LDB = NSP + 1;          // row stride of B / W   (NP rows)
-  constexpr int LDX = NP + 1;           // row stride of X       (NSP rows)
-  constexpr int LDI = NSP + 1;          // row stride of A^-1 and M (NSP rows)
-  constexpr int XMS0 = (NSP * LDX > NSP * LDI ? NSP * LDX : NSP * LDI);
-  constexpr int XMS = (XMS0 > 6 * NT ? XMS0 : 6 * NT);
+  constexpr int LDB = Lay::LDB, LDX = Lay::LDX, LDI = Lay::LDI;
   constexpr int TI = NSP / 16, TA = NP / 16;      // tile counts along electrons / centres
   constexpr int TPW_B = (TA * TI + 3) / 4;        // N x NS outputs per wave
   constexpr int TPW_M = (TI * TI + 3) / 4;        // NS x NS outputs per wave
@@ -199,9 +217,11 @@ __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
   double* pos = reinterpret_cast<double*>(smem);     // N x 3
   double* gU = pos + 3 * N;                            // N x 3
   double* lU = gU + 3 * N;                             // N
-  double* Bs = lU + N;                                 // NP x LDB : B, later W
-  double* XM = Bs + NP * LDB;                          // A^-1, X, M, partials
-  Real* trig = reinterpret_cast<Real*>(XM + XMS);      // N x 6 (sin x3, cos x3)
+  Real* trig = reinterpret_cast<Real*>(lU + N);        // N x 6 (sin x3, cos x3)
+  Real* Bs = reinterpret_cast<Real*>(smem + Lay::pad(Lay::head));              // NP x LDB : B, later W
+  unsigned char* xmb = smem + Lay::pad(Lay::head) + Lay::pad(Lay::bs);
+  Real* Xr = reinterpret_cast<Real*>(xmb);             // NSP x LDX : X
+  double* XM = reinterpret_cast<double*>(xmb);         // NSP x LDI : A^-1, then M; partial sums
   __shared__ double red[4];
   const int t = threadIdx.x, w = blockIdx.x;
   const int lane = t & 63, wave = t >> 6, l16 = lane & 15, l4 = lane >> 4;
@@ -216,15 +236,19 @@ __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
       trig[6 * i + 3 + ax] = c;
     }
   __syncthreads();
-  // Jastrow gradient and Laplacian per electron
+  // Jastrow gradient and Laplacian per electron; HJ threads share an electron's pairs
+  constexpr int HJ = (256 / N) > 0 ? (256 / N) : 1;
   double tj = 0.0, usum = 0.0;
   {
     const Real LoP = (Real)(L / VMC_PI), kf = (Real)((VMC_PI * invL) * (VMC_PI * invL));
     const Real ap = (Real)m.a_par, aa = (Real)m.a_anti, bb = (Real)m.b;
-    for (int i = t; i < N; i += 256) {
+    double* jp = XM;                                   // HJ x N x 5 partial sums
+    for (int u = t; u < HJ * N; u += 256) {
+      const int i = u % N, hj = u / N;
+      const int j0 = hj * N / HJ, j1 = (hj + 1) * N / HJ;
       Real g0 = 0, g1 = 0, g2 = 0, lp = 0, ui = 0;
       const Real* ti = trig + 6 * i;
-      for (int j = 0; j < N; ++j) {
+      for (int j = j0; j < j1; ++j) {
         if (j == i) continue;
         const Real* tj_ = trig + 6 * j;
         Real rt[3], cc[3];
@@ -246,11 +270,20 @@ __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
         lp += upp * gg + up * lr;
         if (j > i) ui += a * rho * iden;
       }
-      gU[3 * i] = (double)g0; gU[3 * i + 1] = (double)g1; gU[3 * i + 2] = (double)g2;
-      lU[i] = (double)lp;
-      const double gd0 = g0, gd1 = g1, gd2 = g2;
-      tj += -0.5 * ((double)lp + gd0 * gd0 + gd1 * gd1 + gd2 * gd2);
-      usum += (double)ui;
+      double* q = jp + ((size_t)hj * N + i) * 5;
+      q[0] = (double)g0; q[1] = (double)g1; q[2] = (double)g2; q[3] = (double)lp; q[4] = (double)ui;
+    }
+    __syncthreads();
+    for (int i = t; i < N; i += 256) {
+      double g0 = 0, g1 = 0, g2 = 0, lp = 0, ui = 0;
+      for (int hj = 0; hj < HJ; ++hj) {
+        const double* q = jp + ((size_t)hj * N + i) * 5;
+        g0 += q[0]; g1 += q[1]; g2 += q[2]; lp += q[3]; ui += q[4];
+      }
+      gU[3 * i] = g0; gU[3 * i + 1] = g1; gU[3 * i + 2] = g2;
+      lU[i] = lp;
+      tj += -0.5 * (lp + g0 * g0 + g1 * g1 + g2 * g2);
+      usum += ui;
     }
   }
   __syncthreads();
@@ -272,15 +305,14 @@ __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
       d4_t acc[TPW_B];
 #pragma unroll
       for (int q = 0; q < TPW_B; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+      for (int kk = 0; kk < NSP / 4; ++kk) {
+        const int k = kk * 4 + l4;
 #pragma unroll
-      for (int q = 0; q < TPW_B; ++q) {
-        const int tt = wave + 4 * q;
-        if (tt < TA * TI) {
-          const int ta = tt / TI, tc = tt % TI;
-          const int arow = ta * 16 + l16;
-#pragma unroll 4
-          for (int kk = 0; kk < NSP / 4; ++kk) {
-            const int k = kk * 4 + l4;
+        for (int q = 0; q < TPW_B; ++q) {
+          const int tt = wave + 4 * q;
+          if (tt < TA * TI) {
+            const int ta = tt / TI, tc = tt % TI;
+            const int arow = ta * 16 + l16;
             const double av = (arow < N && k < NS) ? m.C[arow * NS + k] : 0.0;
             const double bv = XM[k * LDI + tc * 16 + l16];
             acc[q] = mfma16(av, bv, acc[q]);
@@ -293,22 +325,22 @@ __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
         if (tt < TA * TI) {
           const int ta = tt / TI, tc = tt % TI;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Bs[(ta * 16 + l4 + 4 * v) * LDB + tc * 16 + l16] = acc[q][v];
+          for (int v = 0; v < 4; ++v) Bs[(ta * 16 + l4 + 4 * v) * LDB + tc * 16 + l16] = (Real)acc[q][v];
         }
       }
     }
     __syncthreads();
     // pass 1: basis derivatives -> X, and the terms that need only B
     if (act) {
-#pragma unroll
+#pragma unroll 2
       for (int s = 0; s < IPT; ++s) {
         const int i = h + H * s;
         if (i >= NS) continue;
         const int e = sp * NS + i;
         Real g[3][4];
-        gauss1d<Real, 3>((Real)min_image(pos[3 * e] - Ra0, L, invL), za, (Real)L, g[0]);
-        gauss1d<Real, 3>((Real)min_image(pos[3 * e + 1] - Ra1, L, invL), za, (Real)L, g[1]);
-        gauss1d<Real, 3>((Real)min_image(pos[3 * e + 2] - Ra2, L, invL), za, (Real)L, g[2]);
+        gauss1d_n<Real, 3, NIMG>((Real)min_image(pos[3 * e] - Ra0, L, invL), za, (Real)L, g[0]);
+        gauss1d_n<Real, 3, NIMG>((Real)min_image(pos[3 * e + 1] - Ra1, L, invL), za, (Real)L, g[1]);
+        gauss1d_n<Real, 3, NIMG>((Real)min_image(pos[3 * e + 2] - Ra2, L, invL), za, (Real)L, g[2]);
         const Real p00 = g[1][0] * g[2][0], p01 = g[0][0] * g[2][0], p02 = g[0][0] * g[1][0];
         const double gx = g[0][1] * p00, gy = g[1][1] * p01, gz = g[2][1] * p02;
         const double hxx = g[0][2] * p00, hyy = g[1][2] * p01, hzz = g[2][2] * p02;
@@ -320,8 +352,8 @@ __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
         const double glz = g[2][3] * p02 + g[2][1] * (g[0][2] * g[1][0] + g[0][0] * g[1][2]);
         const double u0 = gU[3 * e], u1 = gU[3 * e + 1], u2 = gU[3 * e + 2];
         const double X = -0.5 * (lap + 2.0 * (gx * u0 + gy * u1 + gz * u2));
-        XM[i * LDX + a] = X;
-        const double b = Bs[a * LDB + i];
+        Xr[i * LDX + a] = (Real)X;
+        const double b = (double)Bs[a * LDB + i];
         tsl += X * b;
         dln0 -= b * gx; dln1 -= b * gy; dln2 -= b * gz;
         dT0 += 0.5 * (glx + 2.0 * (hxx * u0 + hxy * u1 + hxz * u2)) * b;
@@ -335,17 +367,16 @@ __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
       d4_t acc[TPW_M];
 #pragma unroll
       for (int q = 0; q < TPW_M; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+      for (int kk = 0; kk < NP / 4; ++kk) {
+        const int k = kk * 4 + l4;
 #pragma unroll
-      for (int q = 0; q < TPW_M; ++q) {
-        const int tt = wave + 4 * q;
-        if (tt < TI * TI) {
-          const int tr = tt / TI, tc = tt % TI;
-          const int irow = tr * 16 + l16;
-#pragma unroll 4
-          for (int kk = 0; kk < NP / 4; ++kk) {
-            const int k = kk * 4 + l4;
-            const double av = (irow < NS && k < N) ? XM[irow * LDX + k] : 0.0;
-            const double bv = (k < N) ? Bs[k * LDB + tc * 16 + l16] : 0.0;
+        for (int q = 0; q < TPW_M; ++q) {
+          const int tt = wave + 4 * q;
+          if (tt < TI * TI) {
+            const int tr = tt / TI, tc = tt % TI;
+            const int irow = tr * 16 + l16;
+            const double av = (irow < NS && k < N) ? (double)Xr[irow * LDX + k] : 0.0;
+            const double bv = (k < N) ? (double)Bs[k * LDB + tc * 16 + l16] : 0.0;
             acc[q] = mfma16(av, bv, acc[q]);
           }
         }
@@ -367,16 +398,15 @@ __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
       d4_t acc[TPW_B];
 #pragma unroll
       for (int q = 0; q < TPW_B; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+      for (int kk = 0; kk < NSP / 4; ++kk) {
+        const int k = kk * 4 + l4;
 #pragma unroll
-      for (int q = 0; q < TPW_B; ++q) {
-        const int tt = wave + 4 * q;
-        if (tt < TA * TI) {
-          const int ta = tt / TI, tc = tt % TI;
-          const int arow = ta * 16 + l16;
-#pragma unroll 4
-          for (int kk = 0; kk < NSP / 4; ++kk) {
-            const int k = kk * 4 + l4;
-            const double av = (arow < N) ? Bs[arow * LDB + k] : 0.0;
+        for (int q = 0; q < TPW_B; ++q) {
+          const int tt = wave + 4 * q;
+          if (tt < TA * TI) {
+            const int ta = tt / TI, tc = tt % TI;
+            const int arow = ta * 16 + l16;
+            const double av = (arow < N) ? (double)Bs[arow * LDB + k] : 0.0;
             const double bv = XM[k * LDI + tc * 16 + l16];
             acc[q] = mfma16(av, bv, acc[q]);
           }
@@ -389,23 +419,23 @@ __global__ __launch_bounds__(256) void k_slater_sample(MeasureArgs m) {
         if (tt < TA * TI) {
           const int ta = tt / TI, tc = tt % TI;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Bs[(ta * 16 + l4 + 4 * v) * LDB + tc * 16 + l16] = acc[q][v];
+          for (int v = 0; v < 4; ++v) Bs[(ta * 16 + l4 + 4 * v) * LDB + tc * 16 + l16] = (Real)acc[q][v];
         }
       }
     }
     __syncthreads();
     // pass 2: dT/dR_a += grad phi_a(r_i) W_ai
     if (act) {
-#pragma unroll
+#pragma unroll 2
       for (int s = 0; s < IPT; ++s) {
         const int i = h + H * s;
         if (i >= NS) continue;
-        const double Wv = Bs[a * LDB + i];
+        const double Wv = (double)Bs[a * LDB + i];
         const int e = sp * NS + i;
         Real g[3][4];
-        gauss1d<Real, 1>((Real)min_image(pos[3 * e] - Ra0, L, invL), za, (Real)L, g[0]);
-        gauss1d<Real, 1>((Real)min_image(pos[3 * e + 1] - Ra1, L, invL), za, (Real)L, g[1]);
-        gauss1d<Real, 1>((Real)min_image(pos[3 * e + 2] - Ra2, L, invL), za, (Real)L, g[2]);
+        gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e] - Ra0, L, invL), za, (Real)L, g[0]);
+        gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e + 1] - Ra1, L, invL), za, (Real)L, g[1]);
+        gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e + 2] - Ra2, L, invL), za, (Real)L, g[2]);
         dT0 += (double)(g[0][1] * g[1][0] * g[2][0]) * Wv;
         dT1 += (double)(g[0][0] * g[1][1] * g[2][0]) * Wv;
         dT2 += (double)(g[0][0] * g[1][0] * g[2][1]) * Wv;
@@ -543,20 +573,13 @@ hipError_t launch_ewald_t(const MeasureArgs& m, const EwaldArgs& e, hipStream_t 
     hipLaunchKernelGGL((k_ewald_sample<N, Real, NMAXC>), dim3(m.W), dim3(256), sm, st, m, e);
   return hipGetLastError();
 }
-template <int NS>
-size_t slater_smem() {
-  constexpr int N = 2 * NS;
-  constexpr int NSP = (NS + 15) / 16 * 16, NP = (N + 15) / 16 * 16;
-  constexpr int NT = (256 / N) * N;
-  constexpr int LDB = NSP + 1, LDX = NP + 1, LDI = NSP + 1;
-  constexpr int XMS0 = (NSP * LDX > NSP * LDI ? NSP * LDX : NSP * LDI);
-  constexpr int XMS = (XMS0 > 6 * NT ? XMS0 : 6 * NT);
-  return ((size_t)3 * N + 3 * N + N + (size_t)NP * LDB + XMS) * sizeof(double) + (size_t)6 * N * sizeof(double);
-}
 template <int NS, class Real>
 hipError_t launch_slater_t(const MeasureArgs& m, hipStream_t st) {
-  size_t sm = slater_smem<NS>();
-  hipLaunchKernelGGL((k_slater_sample<NS, Real>), dim3(m.W), dim3(256), sm, st, m);
+  size_t sm = SlaterLds<NS, Real>::bytes;
+  if (m.nimg)
+    hipLaunchKernelGGL((k_slater_sample<NS, Real, 1>), dim3(m.W), dim3(256), sm, st, m);
+  else
+    hipLaunchKernelGGL((k_slater_sample<NS, Real, 0>), dim3(m.W), dim3(256), sm, st, m);
   return hipGetLastError();
 }
 
@@ -575,9 +598,15 @@ hipError_t launch_ewald_sample(const MeasureArgs& m, const EwaldArgs& e, int mix
   if (mixed) { VMC_DISPATCH_NS2(m.NS, return (launch_ewald_t<2 * NSV, float>(m, e, st))) }
   VMC_DISPATCH_NS2(m.NS, return (launch_ewald_t<2 * NSV, double>(m, e, st)))
 }
+template <int NS>
+hipError_t launch_slater_fp64(const MeasureArgs& m, hipStream_t st) {
+  hipLaunchKernelGGL((k_slater_sample<NS, double, 1>), dim3(m.W), dim3(256), (SlaterLds<NS, double>::bytes), st, m);
+  return hipGetLastError();
+}
 hipError_t launch_slater_sample(const MeasureArgs& m, int mixed, hipStream_t st) {
   if (mixed) { VMC_DISPATCH_NS2(m.NS, return (launch_slater_t<NSV, float>(m, st))) }
-  VMC_DISPATCH_NS2(m.NS, return (launch_slater_t<NSV, double>(m, st)))
+  if (!m.nimg) return hipErrorInvalidValue;   // FP64 keeps every Gaussian image
+  VMC_DISPATCH_NS2(m.NS, return (launch_slater_fp64<NSV>(m, st)))
 }
 hipError_t launch_finalize(const MeasureArgs& m, const EwaldArgs& e, int M, double* means, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(m.W), dim3(256), (size_t)e.nk * 2 * sizeof(double), st, m, e, M, means);

@@ -14,19 +14,19 @@
 
 namespace vmc {
 
-template <class Real>
+template <class Real, int NIMG>
 __device__ __forceinline__ Real phi_value(double rx, double ry, double rz, const double* Ra, Real zeta,
                                           double L, double invL) {
   Real g[3][4];
-  gauss1d<Real, 0>((Real)min_image(rx - Ra[0], L, invL), zeta, (Real)L, g[0]);
-  gauss1d<Real, 0>((Real)min_image(ry - Ra[1], L, invL), zeta, (Real)L, g[1]);
-  gauss1d<Real, 0>((Real)min_image(rz - Ra[2], L, invL), zeta, (Real)L, g[2]);
+  gauss1d_n<Real, 0, NIMG>((Real)min_image(rx - Ra[0], L, invL), zeta, (Real)L, g[0]);
+  gauss1d_n<Real, 0, NIMG>((Real)min_image(ry - Ra[1], L, invL), zeta, (Real)L, g[1]);
+  gauss1d_n<Real, 0, NIMG>((Real)min_image(rz - Ra[2], L, invL), zeta, (Real)L, g[2]);
   return g[0][0] * g[1][0] * g[2][0];
 }
 
 // --------------------------------------------------------------- build A ---
 // One wave per walker; electrons in order, lanes over centres then orbitals.
-template <int NS, class Real>
+template <int NS, class Real, int NIMG>
 __global__ __launch_bounds__(256) void k_build_A(WalkerArgs a) {
   constexpr int N = 2 * NS;
   constexpr int WPB = 4;
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_build_A(WalkerArgs a) {
   for (int e = 0; e < N; ++e) {
     double rx = p[3 * e], ry = p[3 * e + 1], rz = p[3 * e + 2];
     for (int c = lane; c < N; c += 64)
-      phi_s[wv][c] = phi_value<Real>(rx, ry, rz, a.R + 3 * c, (Real)a.zeta[c], a.L, a.invL);
+      phi_s[wv][c] = phi_value<Real, NIMG>(rx, ry, rz, a.R + 3 * c, (Real)a.zeta[c], a.L, a.invL);
     wave_lds_sync();
     if (lane < NS) {
       double m = 0.0;
@@ -62,6 +62,7 @@ __global__ __launch_bounds__(256) void k_build_A(WalkerArgs a) {
 template <int NS>
 __global__ __launch_bounds__(256) void k_invert(WalkerArgs a, int spin_lo, int spin_hi) {
   constexpr int BC = 16, NB = (NS + BC - 1) / BC;
+  __shared__ double stage[4 * NS * 17];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nsp = spin_hi - spin_lo;
   const int mat = blockIdx.x * 4 + wv;
@@ -137,15 +138,28 @@ __global__ __launch_bounds__(256) void k_invert(WalkerArgs a, int spin_lo, int s
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) inv_cnt += __shfl_xor(inv_cnt, off, 64);
   if (inv_cnt & 1) sgn = -sgn;
+  // Lane myk's row of A^-1 has column pi(c) in r[c].  Stage 16 columns at a time in
+  // LDS (row stride 17) and write whole row segments, so stores are coalesced.
+  constexpr int CH = 16, NCH = (NS + CH - 1) / CH;
+  double* st = stage + (size_t)wv * NS * (CH + 1);
+  for (int ch = 0; ch < NCH; ++ch) {
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int j = 0; j < BC; ++j) {
-      const int c = b * BC + j;
-      if (c >= NS) continue;
-      const int col = __builtin_amdgcn_readlane(mypi, c);
-      if (isrow) a.Binv[base + (size_t)myk * NS + col] = r[b][j];
+      for (int j = 0; j < BC; ++j) {
+        const int c = b * BC + j;
+        if (c >= NS) continue;
+        const int col = __builtin_amdgcn_readlane(mypi, c);
+        if (col / CH == ch && isrow) st[myk * (CH + 1) + col % CH] = r[b][j];
+      }
+    wave_lds_sync();
+    const int ncol = (NS - ch * CH) < CH ? (NS - ch * CH) : CH;
+    for (int idx = lane; idx < NS * CH; idx += 64) {
+      const int row = idx / CH, cc = idx % CH;
+      if (cc < ncol) a.Binv[base + (size_t)row * NS + ch * CH + cc] = st[row * (CH + 1) + cc];
     }
+    wave_lds_sync();
+  }
   if (lane == 0) {
     a.ldet[(size_t)w * 2 + sp] = logdet;
     a.sgn[(size_t)w * 2 + sp] = sgn;
@@ -162,7 +176,7 @@ __device__ __forceinline__ T pick(const T (&v)[E], int s) {
 }
 
 // Moves the NS electrons of spin `sp` of every walker once, in order.
-template <int NS, class Real>
+template <int NS, class Real, int NIMG>
 __global__ __launch_bounds__(256, ((sizeof(Real) == 8 && NS >= 27) || NS >= 64) ? 1 : 2) void k_sweep_half(WalkerArgs a, SweepArgs s) {
   constexpr int N = 2 * NS;
   constexpr int WPB = 4;
@@ -233,9 +247,9 @@ __global__ __launch_bounds__(256, ((sizeof(Real) == 8 && NS >= 27) || NS >= 64) 
       phv[t] = Real(0);
       if (c < N) {
         Real g[3][4];
-        gauss1d<Real, 0>((Real)min_image(xn - Rc[t][0], L, invL), zc[t], (Real)L, g[0]);
-        gauss1d<Real, 0>((Real)min_image(yn - Rc[t][1], L, invL), zc[t], (Real)L, g[1]);
-        gauss1d<Real, 0>((Real)min_image(zn - Rc[t][2], L, invL), zc[t], (Real)L, g[2]);
+        gauss1d_n<Real, 0, NIMG>((Real)min_image(xn - Rc[t][0], L, invL), zc[t], (Real)L, g[0]);
+        gauss1d_n<Real, 0, NIMG>((Real)min_image(yn - Rc[t][1], L, invL), zc[t], (Real)L, g[1]);
+        gauss1d_n<Real, 0, NIMG>((Real)min_image(zn - Rc[t][2], L, invL), zc[t], (Real)L, g[2]);
         phv[t] = g[0][0] * g[1][0] * g[2][0];
       }
     }
@@ -313,7 +327,10 @@ __global__ __launch_bounds__(256, ((sizeof(Real) == 8 && NS >= 27) || NS >= 64) 
 template <int NS, class Real>
 hipError_t launch_build_A_t(const WalkerArgs& a, hipStream_t st) {
   dim3 grid((a.W + 3) / 4);
-  hipLaunchKernelGGL((k_build_A<NS, Real>), grid, dim3(256), 0, st, a);
+  if (a.nimg || sizeof(Real) == 8)
+    hipLaunchKernelGGL((k_build_A<NS, Real, 1>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_build_A<NS, Real, 0>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 template <int NS>
@@ -331,7 +348,10 @@ template <int NS, class Real>
 hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t st) {
   dim3 grid((a.W + 3) / 4);
   size_t sm = sweep_smem<NS, Real>();
-  hipLaunchKernelGGL((k_sweep_half<NS, Real>), grid, dim3(256), sm, st, a, s);
+  if (a.nimg || sizeof(Real) == 8)
+    hipLaunchKernelGGL((k_sweep_half<NS, Real, 1>), grid, dim3(256), sm, st, a, s);
+  else
+    hipLaunchKernelGGL((k_sweep_half<NS, Real, 0>), grid, dim3(256), sm, st, a, s);
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@ namespace vmc {
 
 struct WalkerArgs {
   int W, N, NS;
+  int nimg;            // 1: images n = -1, 0, 1 of each Gaussian; 0: n = 0 only
   double L, invL;
   const double* R;     // 3N proton positions
   const double* zeta;  // N Gaussian exponents
@@ -45,6 +46,7 @@ struct EwaldArgs {
 
 struct MeasureArgs {
   int W, N, NS;
+  int nimg;
   double L, invL;
   const double* R;
   const double* zeta;

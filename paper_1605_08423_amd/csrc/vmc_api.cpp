@@ -169,9 +169,24 @@ void build_kvectors(const vmc_system& s, std::vector<double>& kv, std::vector<in
     }
 }
 
-WalkerArgs walker_args(vmc_traj* t, const double* R, const double* C, const double* zeta) {
+// Gaussian images kept per axis: all three (n = -1, 0, 1) unless the mode is mixed and
+// every dropped image is below e^{-zeta_min (L/2)^2} <= e^{-23} (under FP32 resolution).
+int image_count(vmc_traj* t, const double* zeta_dev, int* nimg) {
+  *nimg = 1;
+  if (t->sys.precision != VMC_MIXED) return VMC_OK;
+  std::vector<double> z(t->N);
+  HIPCHK(hipMemcpyAsync(z.data(), zeta_dev, t->N * sizeof(double), hipMemcpyDeviceToHost, t->ctx->stream));
+  HIPCHK(hipStreamSynchronize(t->ctx->stream));
+  double zmin = z[0];
+  for (double v : z) zmin = std::min(zmin, v);
+  const double h = 0.5 * t->sys.box_L;
+  if (zmin * h * h >= 23.0) *nimg = 0;
+  return VMC_OK;
+}
+
+WalkerArgs walker_args(vmc_traj* t, const double* R, const double* C, const double* zeta, int nimg) {
   WalkerArgs a{};
-  a.W = t->W; a.N = t->N; a.NS = t->NS;
+  a.W = t->W; a.N = t->N; a.NS = t->NS; a.nimg = nimg;
   a.L = t->sys.box_L; a.invL = 1.0 / t->sys.box_L;
   a.R = R; a.zeta = zeta; a.C = C;
   a.a_par = t->sys.a_par; a.a_anti = t->sys.a_anti; a.b = t->sys.b;
@@ -180,9 +195,9 @@ WalkerArgs walker_args(vmc_traj* t, const double* R, const double* C, const doub
   return a;
 }
 
-MeasureArgs measure_args(vmc_traj* t, const double* R, const double* C, const double* zeta) {
+MeasureArgs measure_args(vmc_traj* t, const double* R, const double* C, const double* zeta, int nimg) {
   MeasureArgs m{};
-  m.W = t->W; m.N = t->N; m.NS = t->NS;
+  m.W = t->W; m.N = t->N; m.NS = t->NS; m.nimg = nimg;
   m.L = t->sys.box_L; m.invL = 1.0 / t->sys.box_L;
   m.R = R; m.zeta = zeta; m.C = C;
   m.a_par = t->sys.a_par; m.a_anti = t->sys.a_anti; m.b = t->sys.b;
@@ -380,12 +395,15 @@ int vmc_energy_forces(vmc_traj* t, const double* R, const double* C, const doubl
   double Vconst = 0.0;
   int rc = proton_setup(t, R, &Vconst);
   if (rc) return rc;
+  int nimg = 1;
+  rc = image_count(t, zeta, &nimg);
+  if (rc) return rc;
   HIPCHK(hipMemsetAsync(t->acc, 0, W * (2 + 9 * N) * sizeof(double), st));
   HIPCHK(hipMemsetAsync(t->rho_acc, 0, W * t->nk * 2 * sizeof(double), st));
   HIPCHK(hipMemsetAsync(t->nacc, 0, W * sizeof(int64_t), st));
   HIPCHK(hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
-  WalkerArgs a = walker_args(t, R, C, zeta);
-  MeasureArgs m = measure_args(t, R, C, zeta);
+  WalkerArgs a = walker_args(t, R, C, zeta, nimg);
+  MeasureArgs m = measure_args(t, R, C, zeta, nimg);
   EwaldArgs e = ewald_args(t, Vconst);
   RUN(K_BUILD_A, launch_build_A(a, mixed, st));
   const int total = n_equil + n_sweeps;
@@ -483,15 +501,17 @@ int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R, const
   const int mixed = t->sys.precision == VMC_MIXED;
   const size_t N = t->N;
   double Vconst = 0.0;
+  int nimg = 1;
   rc = vmc_traj_set_walkers(t, pos);
   if (!rc) rc = proton_setup(t, R, &Vconst);
+  if (!rc) rc = image_count(t, zeta, &nimg);
   if (!rc) {
     auto body = [&]() -> int {
       HIPCHK(hipMemsetAsync(t->acc, 0, (size_t)K * (2 + 9 * N) * sizeof(double), st));
       HIPCHK(hipMemsetAsync(t->rho_acc, 0, (size_t)K * t->nk * 2 * sizeof(double), st));
       HIPCHK(hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
-      WalkerArgs a = walker_args(t, R, C, zeta);
-      MeasureArgs m = measure_args(t, R, C, zeta);
+      WalkerArgs a = walker_args(t, R, C, zeta, nimg);
+      MeasureArgs m = measure_args(t, R, C, zeta, nimg);
       EwaldArgs e = ewald_args(t, Vconst);
       RUN(K_BUILD_A, launch_build_A(a, mixed, st));
       RUN(K_INVERT, launch_invert(a, 0, 2, st));
