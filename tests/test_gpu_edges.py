@@ -1,0 +1,89 @@
+"""Edge cases of the HIP path through the C ABI: ragged walker counts (the sweep
+kernels pack four walkers per work-group), a single walker/configuration, the
+smallest covariance (W = 2), a one-coordinate Langevin step and argument errors."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1605_08423_amd.inputs import workload
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    from paper_1605_08423_amd import vmc
+    return torch, vmc, vmc.Context(0)
+
+
+def T(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("W", [1, 5, 7, 13])
+def test_ragged_walker_counts_fp64_chain(oracle, dev, W):
+    torch, vmc, ctx = dev
+    wl = workload("h16")
+    say(f"[ragged chain] W={W}")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, 8)
+    x0 = wl.electrons(W=W, seed_offset=40 + W)
+    tr = vmc.Trajectory(ctx, vmc.make_system(16, wl.L), W, seed=9, traj_id=2)
+    tr.set_walkers(T(torch, x0))
+    out = tr.energy_forces(T(torch, wl.R.reshape(-1)), T(torch, Cm), T(torch, wl.zeta), 1, 3, wl.delta, 5).cpu().numpy()
+    acc = tr.accepts().cpu().numpy()
+    means = tr.walker_means().cpu().numpy()
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L)
+    sums, nacc = s.vmc_run(x0.copy(), 1, 3, wl.delta, seed=9, traj=2, step=5)
+    red = oracle.reduce(sums, 3)
+    assert np.array_equal(acc, nacc)
+    assert rel(means, red["means"]) < 1e-10
+    assert rel(out[0], red["E"]) < 1e-10
+    if W > 1:
+        assert rel(out[3:], red["f"]) < 1e-10
+
+
+def test_single_configuration(oracle, dev):
+    torch, vmc, ctx = dev
+    wl = workload("h54")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, 27)
+    pos = wl.electrons(W=1, seed_offset=3)
+    g = vmc.vmc_eval_configs(ctx, vmc.make_system(54, wl.L), T(torch, wl.R.reshape(-1)), T(torch, Cm),
+                             T(torch, wl.zeta), T(torch, pos)).cpu().numpy()
+    r = oracle.System(wl.R, wl.zeta, Cm, L=wl.L).local(pos[0])
+    assert rel(g[0, 1], r["EL"]) < 1e-10 and rel(g[0, 2 + 162:], r["dEL"]) < 1e-10
+
+
+def test_build_S_two_walkers_and_1d_langevin(oracle, dev):
+    torch, vmc, ctx = dev
+    fw = np.array([[1.0, 2.0, -1.0], [0.5, -1.0, 3.0]])
+    f = fw.mean(0)
+    S = vmc.vmc_build_S_raw(ctx, T(torch, fw), T(torch, f)).cpu().numpy()
+    np.testing.assert_allclose(S, oracle.build_S(fw, f), rtol=1e-14)
+    R, Rp, Sp = T(torch, [0.3]), T(torch, [0.3]), T(torch, [[2.0]])
+    assert vmc.vmc_langevin_step(ctx, R, Rp, Sp, T(torch, [0.5]), T(torch, [[2.0]]), 0.1, 0.2, 0.0, 0, 1, 0, 3) == 0
+    Ro, Rpo, Spo = np.array([0.3]), np.array([0.3]), np.array([[2.0]])
+    oracle.langevin(Ro, Rpo, Spo, np.array([0.5]), np.array([[2.0]]), 0.1, 0.2, 0.0, seed=1, traj=0, step=3)
+    assert rel(R.cpu().numpy(), Ro) < 1e-14
+
+
+def test_argument_errors(dev):
+    torch, vmc, ctx = dev
+    with pytest.raises(vmc.VMCError) as e:
+        vmc.Trajectory(ctx, vmc.make_system(17, 6.0), 4)
+    assert e.value.code == vmc.VMC_EINVAL
+    with pytest.raises(vmc.VMCError):
+        vmc.Trajectory(ctx, vmc.make_system(100, 10.0), 4)         # unsupported size
+    with pytest.raises(vmc.VMCError):
+        vmc.vmc_build_S_raw(ctx, T(torch, np.ones((1, 3))), T(torch, np.ones(3)))   # W < 2
