@@ -1,14 +1,15 @@
 // Walker kernels: Slater matrices at new proton positions (a2), the FP64 inverse
-// refresh (a4) and the Metropolis half-sweep with Sherman-Morrison updates (a3).
+// refresh (a4) and the Metropolis half-sweep with delayed Sherman-Morrison
+// updates (a3).
 //
 // Layout in HBM (per trajectory, W walkers, N electrons, NS = N/2 per spin):
 //   pos  [W][N][3]            electron positions, wrapped into [0, L)
 //   Amat [W][2][NS][NS]       Slater matrix rows A[i][k] = sum_a phi_a(r_i) C[a][k]
 //   Binv [W][2][NS][NS]       inverse, row-major (A^-1)[k][i]
 //   ldet [W][2], sgn[W][2]    ln|det A| and sign at the last refresh
-// A wavefront (64 lanes) owns one walker in the sweep: lane j keeps column j of
-// the active spin's inverse in registers, lanes also own electrons and basis
-// centres j, j+64, ...; the MO coefficients C are shared through LDS.
+// A wavefront (64 lanes) owns one walker in the sweep: the active spin's inverse
+// stays in matrix-core accumulator registers, lanes own electrons j, j+64, ...;
+// the MO coefficients C are read through the caches.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -175,149 +176,287 @@ __device__ __forceinline__ T pick(const T (&v)[E], int s) {
   return r;
 }
 
-// Moves the NS electrons of spin `sp` of every walker once, in order.
+typedef double d4w_t __attribute__((ext_vector_type(4)));
+// 16x16x4 FP64 matrix-core step D += A B: lane l gives A[l % 16][l / 16] and
+// B[l / 16][l % 16] and holds D[l / 16 + 4 v][l % 16] in element v.
+__device__ __forceinline__ d4w_t mfma_w(double av, double bv, d4w_t acc) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+}
+
+// LDS per wave of the half-sweep (doubles): M' block (16 x LDM), later reused for
+// the 16 inverse columns G (NSP x 17), and the P / Z block (16 x LDM).
+template <int NS>
+struct SweepLds {
+  static constexpr int NSP = (NS + 15) / 16 * 16, LDM = NSP + 1, LDG = 17;
+  static constexpr int MB = (16 * LDM > NSP * LDG) ? 16 * LDM : NSP * LDG;
+  static constexpr int WAVE = MB + 16 * LDM;
+  static constexpr size_t bytes(int N) { return ((size_t)4 * WAVE + 4 * (size_t)N) * sizeof(double); }
+};
+
+// Moves the NS electrons of spin `sp` of every walker once, in order, with
+// delayed updates of the inverse in blocks of 16 moves.  A proposal depends only
+// on the electron's own position, which no earlier move of the half-sweep
+// changes, so the 16 proposals of a block are drawn together:
+//   M' = Phi' C          MO rows of the proposals (16 x NS, FP64 matrix cores)
+//   P  = M' A^-1         their products with the inverse at the block start
+// Move j then needs t = m'_j (A^-1 after the accepted moves j' < j of the block),
+// obtained from P_j by the left-looking recursion t -= t[i_j'] z_j' over the
+// accepted j', with z_j' = (t_j' - e_i_j') / q_j' the Sherman-Morrison row of j';
+// the ratio is q_j = t[i_j].  After the block the inverse takes all accepted
+// updates at once: A^-1 -= A^-1[:, block] Z with Z = (I + Y)^-1 [z rows], Y the
+// strictly upper coupling Y[j''][j'] = z_j''[i_j'], solved by back-substitution.
+// Every LDS row access of the recursion is lane-private (lane = column).
+// One wave per walker; the inverse lives in matrix-core accumulator layout
+// (tile (tr, tc), element v of lane l = A^-1[16 tr + 4 v + l/16][16 tc + l%16]).
 template <int NS, class Real, int NIMG>
-__global__ __launch_bounds__(256, ((sizeof(Real) == 8 && NS >= 27) || NS >= 64) ? 1 : 2) void k_sweep_half(WalkerArgs a, SweepArgs s) {
+__global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s) {
   constexpr int N = 2 * NS;
-  constexpr int WPB = 4;
-  constexpr int EPL = (N + 63) / 64;     // electrons (and centres) per lane
-  extern __shared__ __align__(16) unsigned char smem[];
-  double* Cs = reinterpret_cast<double*>(smem);                  // N x NS (FP64 in both modes)
-  for (int t = threadIdx.x; t < N * NS; t += blockDim.x) Cs[t] = a.C[t];
+  using LY = SweepLds<NS>;
+  constexpr int NSP = LY::NSP, NT = NSP / 16, NB = (NS + 15) / 16, KC = (N + 3) / 4;
+  constexpr int LDM = LY::LDM, LDG = LY::LDG;
+  constexpr int EPL = (N + 63) / 64;
+  static_assert(NS == 64 || N <= 64, "the electrons of one spin must share a slot");
+  extern __shared__ __align__(16) double smem_d[];
+  double* Rs = smem_d + 4 * LY::WAVE;     // centres x, y, z, zeta
+  for (int t = threadIdx.x; t < N; t += blockDim.x) {
+    Rs[4 * t] = a.R[3 * t]; Rs[4 * t + 1] = a.R[3 * t + 1]; Rs[4 * t + 2] = a.R[3 * t + 2];
+    Rs[4 * t + 3] = a.zeta[t];
+  }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int w = blockIdx.x * WPB + wv;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int w = blockIdx.x * 4 + wv;
   if (w >= a.W) return;
+  double* MB = smem_d + (size_t)wv * LY::WAVE;
+  double* PB = MB + LY::MB;
   const int sp = s.spin;
+  const int slot = (sp * NS) >> 6;
   const double L = a.L, invL = a.invL;
   const Real LoverPi = (Real)(L / VMC_PI);
-
-  double bcol[NS];
   const size_t bbase = ((size_t)w * 2 + sp) * NS * NS;
+
+  // element (r, c) of the inverse at Bw[(16 tr + 4 v) NS] (wave-uniform) + lane offset
+  double* Bw = a.Binv + bbase;
+  const int loff = l4 * NS + l16;
+  d4w_t binv[NT][NT];
 #pragma unroll
-  for (int k = 0; k < NS; ++k) bcol[k] = (lane < NS) ? a.Binv[bbase + (size_t)k * NS + lane] : 0.0;
+  for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double* rowp = Bw + (16 * tr + 4 * v) * NS;
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc) {
+        const bool ok = (16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS);
+        const double val = rowp[ok ? loff + 16 * tc : -(16 * tr + 4 * v) * NS];   // in range either way
+        binv[tr][tc][v] = ok ? val : 0.0;
+      }
+    }
 
   double px[EPL], py[EPL], pz[EPL];
-  Real ts[EPL][3], tc[EPL][3];
-  double Rc[EPL][3];
-  Real zc[EPL];
+  Real ts[EPL][3], tc_[EPL][3];
   double* pw = a.pos + (size_t)w * N * 3;
 #pragma unroll
   for (int t = 0; t < EPL; ++t) {
-    int e = lane + 64 * t;
+    const int e = lane + 64 * t;
     px[t] = py[t] = pz[t] = 0.0;
-    zc[t] = Real(1);
-    Rc[t][0] = Rc[t][1] = Rc[t][2] = 0.0;
-    for (int m = 0; m < 3; ++m) { ts[t][m] = Real(0); tc[t][m] = Real(1); }
+    for (int m = 0; m < 3; ++m) { ts[t][m] = Real(0); tc_[t][m] = Real(1); }
     if (e < N) {
       px[t] = pw[3 * e]; py[t] = pw[3 * e + 1]; pz[t] = pw[3 * e + 2];
-      dev_sincospi<Real>((Real)(px[t] * invL), &ts[t][0], &tc[t][0]);
-      dev_sincospi<Real>((Real)(py[t] * invL), &ts[t][1], &tc[t][1]);
-      dev_sincospi<Real>((Real)(pz[t] * invL), &ts[t][2], &tc[t][2]);
-      Rc[t][0] = a.R[3 * e]; Rc[t][1] = a.R[3 * e + 1]; Rc[t][2] = a.R[3 * e + 2];
-      zc[t] = (Real)a.zeta[e];
+      dev_sincospi<Real>((Real)(px[t] * invL), &ts[t][0], &tc_[t][0]);
+      dev_sincospi<Real>((Real)(py[t] * invL), &ts[t][1], &tc_[t][1]);
+      dev_sincospi<Real>((Real)(pz[t] * invL), &ts[t][2], &tc_[t][2]);
     }
-  }
-  // This half-sweep's random numbers: lane i holds those of move i.
-  double ru0 = 0, ru1 = 0, ru2 = 0, ru3 = 0;
-  if (lane < NS) {
-    const uint32_t ctr2 = (uint32_t)(s.sweep * N + sp * NS + lane);
-    u32x4 o0 = philox(s.step, (uint32_t)w, ctr2, 0u, s.seed, s.traj);
-    u32x4 o1 = philox(s.step, (uint32_t)w, ctr2, 1u, s.seed, s.traj);
-    ru0 = u01(o0.x, o0.y); ru1 = u01(o0.z, o0.w); ru2 = u01(o1.x, o1.y); ru3 = u01(o1.z, o1.w);
   }
   const Real a_same = (Real)a.a_par, a_anti = (Real)a.a_anti, bj = (Real)a.b;
   const double delta = s.delta;
   int nacc = 0;
-  for (int i = 0; i < NS; ++i) {
-    const int e = sp * NS + i, owner = e & 63, slot = e >> 6;
-    const double ux = readlane_d(ru0, i), uy = readlane_d(ru1, i), uz = readlane_d(ru2, i);
-    const double uacc = readlane_d(ru3, i);
-    const double xo = readlane_d(pick(px, slot), owner);
-    const double yo = readlane_d(pick(py, slot), owner);
-    const double zo = readlane_d(pick(pz, slot), owner);
-    const double xn = wrap_box(xo + delta * (ux - 0.5), L, invL);
-    const double yn = wrap_box(yo + delta * (uy - 0.5), L, invL);
-    const double zn = wrap_box(zo + delta * (uz - 0.5), L, invL);
-    // basis row at the proposed position: lane keeps phi of its own centres
-    Real phv[EPL];
-#pragma unroll
-    for (int t = 0; t < EPL; ++t) {
-      int c = lane + 64 * t;
-      phv[t] = Real(0);
-      if (c < N) {
-        Real g[3][4];
-        gauss1d_n<Real, 0, NIMG>((Real)min_image(xn - Rc[t][0], L, invL), zc[t], (Real)L, g[0]);
-        gauss1d_n<Real, 0, NIMG>((Real)min_image(yn - Rc[t][1], L, invL), zc[t], (Real)L, g[1]);
-        gauss1d_n<Real, 0, NIMG>((Real)min_image(zn - Rc[t][2], L, invL), zc[t], (Real)L, g[2]);
-        phv[t] = g[0][0] * g[1][0] * g[2][0];
-      }
-    }
-    // trig cache of the proposed position: lanes 0..2 compute one axis each
-    Real sv, cv;
+
+  for (int b = 0; b < NB; ++b) {
+    const int jmax = (NS - 16 * b) < 16 ? (NS - 16 * b) : 16;
+    // proposal of move 16 b + l16 (lanes with equal l16 hold the same one)
+    const int ip = 16 * b + l16;
+    const bool pvalid = ip < NS;
+    const int ipc = pvalid ? ip : 0;
+    const int owner_p = (sp * NS + ipc) & 63;
+    const double xo_p = __shfl(pick(px, slot), owner_p, 64);
+    const double yo_p = __shfl(pick(py, slot), owner_p, 64);
+    const double zo_p = __shfl(pick(pz, slot), owner_p, 64);
+    // the move's four uniforms: displacement x, y, z and the acceptance test
+    double xn, yn, zn, ru3;
     {
-      const int ax = lane % 3;
-      const double comp = (ax == 0) ? xn : ((ax == 1) ? yn : zn);
+      const uint32_t ctr2 = (uint32_t)(s.sweep * N + sp * NS + ipc);
+      const u32x4 o0 = philox(s.step, (uint32_t)w, ctr2, 0u, s.seed, s.traj);
+      const u32x4 o1 = philox(s.step, (uint32_t)w, ctr2, 1u, s.seed, s.traj);
+      xn = wrap_box(xo_p + delta * (u01(o0.x, o0.y) - 0.5), L, invL);
+      yn = wrap_box(yo_p + delta * (u01(o0.z, o0.w) - 0.5), L, invL);
+      zn = wrap_box(zo_p + delta * (u01(o1.x, o1.y) - 0.5), L, invL);
+      ru3 = u01(o1.z, o1.w);
+    }
+    // trig cache of proposal l16 along axis l4 (l4 < 3)
+    Real sv = Real(0), cv = Real(1);
+    {
+      const double comp = (l4 == 0) ? xn : ((l4 == 1) ? yn : zn);
       dev_sincospi<Real>((Real)(comp * invL), &sv, &cv);
     }
-    Real sn[3], cn[3], so[3], co[3];
+    // M' = Phi' C on the matrix cores: lane l supplies phi of proposal l%16 at centre 4k + l/16
+    d4w_t acc[NT];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      sn[m] = readlane<Real>(sv, m);
-      cn[m] = readlane<Real>(cv, m);
-      so[m] = readlane<Real>(slot == 0 ? ts[0][m] : ts[EPL - 1][m], owner);
-      co[m] = readlane<Real>(slot == 0 ? tc[0][m] : tc[EPL - 1][m], owner);
-    }
-    // MO row m_k = sum_a phi_a C[a][k] in FP64: phi_a broadcast from its lane
-    double acc = 0.0;
+    for (int tc = 0; tc < NT; ++tc) acc[tc] = d4w_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int k = 0; k < KC; ++k) {
+      const int c = 4 * k + l4;
+      const bool cv_ok = c < N;
+      const int cc = cv_ok ? c : 0;
+      double bvs[NT];
 #pragma unroll
-    for (int t = 0; t < EPL; ++t) {
-      const int cmax = (N - 64 * t) < 64 ? (N - 64 * t) : 64;
-#pragma unroll 8
-      for (int l = 0; l < cmax; ++l)
-        acc += (double)readlane<Real>(phv[t], l) * Cs[(64 * t + l) * NS + (lane < NS ? lane : 0)];
-    }
-    const double mk = (lane < NS) ? acc : 0.0;
-    // v_j = sum_k m_k (A^-1)[k][j]; the ratio is q = v_i
-    double vj = 0.0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) vj += readlane_d(mk, k) * bcol[k];
-    const double q = readlane_d(vj, i);
-    // Jastrow change sum_j u(r', r_j) - u(r_e, r_j)
-    Real du = Real(0);
-#pragma unroll
-    for (int t = 0; t < EPL; ++t) {
-      int j = lane + 64 * t;
-      if (j < N && j != e) {
-        const Real aa = ((j / NS) == sp) ? a_same : a_anti;
-        du += pade_u<Real>(sn, cn, ts[t], tc[t], LoverPi, aa, bj) - pade_u<Real>(so, co, ts[t], tc[t], LoverPi, aa, bj);
+      for (int tc = 0; tc < NT; ++tc) {
+        const int col = 16 * tc + l16;
+        const bool ok = cv_ok && col < NS;
+        const double val = a.C[ok ? cc * NS + col : 0];
+        bvs[tc] = ok ? val : 0.0;
       }
-    }
-    const double dU = wave_sum((double)du);
-    const double pacc = q * q * exp(2.0 * dU);
-    if (uacc < pacc) {
-      const double coef = (vj - (lane == i ? 1.0 : 0.0)) / q;
-#pragma unroll
-      for (int k = 0; k < NS; ++k) bcol[k] -= readlane_d(bcol[k], i) * coef;
-      if (lane == owner) {
-#pragma unroll
-        for (int t = 0; t < EPL; ++t)
-          if (t == slot) {
-            px[t] = xn; py[t] = yn; pz[t] = zn;
-            for (int m = 0; m < 3; ++m) { ts[t][m] = sn[m]; tc[t][m] = cn[m]; }
-          }
+      double ph = 0.0;
+      if (cv_ok && pvalid) {
+        const double* Rc = Rs + 4 * cc;
+        ph = (double)phi_value<Real, NIMG>(xn, yn, zn, Rc, (Real)Rc[3], L, invL);
       }
-      if (lane < NS) a.Amat[bbase + (size_t)i * NS + lane] = mk;
-      ++nacc;
-    }
-  }
-  if (lane < NS) {
 #pragma unroll
-    for (int k = 0; k < NS; ++k) a.Binv[bbase + (size_t)k * NS + lane] = bcol[k];
+      for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_w(ph, bvs[tc], acc[tc]);
+    }
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) MB[(4 * v + l4) * LDM + 16 * tc + l16] = acc[tc][v];
+    wave_lds_sync();
+    // P = M' A^-1: the inverse registers are the B operand of k step 4 tr + v
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc) acc[tc] = d4w_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double av = MB[l16 * LDM + 16 * tr + 4 * v + l4];
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_w(av, binv[tr][tc][v], acc[tc]);
+      }
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) PB[(4 * v + l4) * LDM + 16 * tc + l16] = acc[tc][v];
+    wave_lds_sync();
+
+    // the moves of the block, in order
+    const bool col_ok = lane < NSP;
+    const int lc = col_ok ? lane : 0;
+    uint32_t amask = 0;
+    for (int j = 0; j < jmax; ++j) {
+      const int i = 16 * b + j, e = sp * NS + i, owner = e & 63;
+      double t = col_ok ? PB[j * LDM + lc] : 0.0;
+      for (uint32_t mm = amask; mm; mm &= mm - 1) {
+        const int jp = __builtin_ctz(mm);
+        const double cf = readlane_d(t, 16 * b + jp);
+        t = fma(-cf, col_ok ? PB[jp * LDM + lc] : 0.0, t);
+      }
+      const double q = readlane_d(t, i);
+      Real sn[3], cn[3], so[3], co[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        sn[m] = readlane<Real>(sv, j + 16 * m);
+        cn[m] = readlane<Real>(cv, j + 16 * m);
+        so[m] = readlane<Real>(slot == 0 ? ts[0][m] : ts[EPL - 1][m], owner);
+        co[m] = readlane<Real>(slot == 0 ? tc_[0][m] : tc_[EPL - 1][m], owner);
+      }
+      Real du = Real(0);
+#pragma unroll
+      for (int tt = 0; tt < EPL; ++tt) {
+        const int jj = lane + 64 * tt;
+        if (jj < N && jj != e) {
+          const Real aa = ((jj / NS) == sp) ? a_same : a_anti;
+          du += pade_u<Real>(sn, cn, ts[tt], tc_[tt], LoverPi, aa, bj) -
+                pade_u<Real>(so, co, ts[tt], tc_[tt], LoverPi, aa, bj);
+        }
+      }
+      const double dU = wave_sum((double)du);
+      const double pacc = q * q * exp(2.0 * dU);
+      double zrow = 0.0;
+      if (readlane_d(ru3, j) < pacc) {
+        zrow = (t - (lane == i ? 1.0 : 0.0)) * (1.0 / q);
+        amask |= 1u << j;
+        const double xnj = readlane_d(xn, j), ynj = readlane_d(yn, j), znj = readlane_d(zn, j);
+        if (lane == owner) {
+#pragma unroll
+          for (int tt = 0; tt < EPL; ++tt)
+            if (tt == slot) {
+              px[tt] = xnj; py[tt] = ynj; pz[tt] = znj;
+              for (int m = 0; m < 3; ++m) { ts[tt][m] = sn[m]; tc_[tt][m] = cn[m]; }
+            }
+        }
+        ++nacc;
+      }
+      if (col_ok) PB[j * LDM + lc] = zrow;
+    }
+    for (int j = jmax; j < 16; ++j)
+      if (col_ok) PB[j * LDM + lc] = 0.0;
+    if (amask == 0) { wave_lds_sync(); continue; }
+    // accepted MO rows into A
+    if (lane < NS)
+      for (uint32_t mm = amask; mm; mm &= mm - 1) {
+        const int j = __builtin_ctz(mm);
+        a.Amat[bbase + (size_t)(16 * b + j) * NS + lane] = MB[j * LDM + lane];
+      }
+    // Z = (I + Y)^-1 [z rows]: back-substitution from the last accepted move
+    for (int j = 15; j >= 0; --j) {
+      if (!((amask >> j) & 1u)) continue;
+      const double zo = col_ok ? PB[j * LDM + lc] : 0.0;
+      double z = zo;
+      for (uint32_t mm = amask & ~((2u << j) - 1u); mm; mm &= mm - 1) {
+        const int jp = __builtin_ctz(mm);
+        const double cf = readlane_d(zo, 16 * b + jp);
+        z = fma(-cf, col_ok ? PB[jp * LDM + lc] : 0.0, z);
+      }
+      if (col_ok) PB[j * LDM + lc] = z;
+    }
+    // G = the inverse's columns of this block (column tile b) into the M' buffer
+    wave_lds_sync();
+#pragma unroll
+    for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double g = binv[tr][0][v];
+#pragma unroll
+        for (int tc = 1; tc < NT; ++tc) g = (tc == b) ? binv[tr][tc][v] : g;
+        MB[(16 * tr + 4 * v + l4) * LDG + l16] = g;
+      }
+    wave_lds_sync();
+    // A^-1 -= G Z
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      double zb[NT], ga[NT];
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc) zb[tc] = PB[(4 * kk + l4) * LDM + 16 * tc + l16];
+#pragma unroll
+      for (int tr = 0; tr < NT; ++tr) ga[tr] = -MB[(16 * tr + l16) * LDG + 4 * kk + l4];
+#pragma unroll
+      for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc) binv[tr][tc] = mfma_w(ga[tr], zb[tc], binv[tr][tc]);
+      asm volatile("" ::: "memory");
+    }
+    wave_lds_sync();
   }
+  Bw = a.Binv + ((size_t)(blockIdx.x * 4 + wv) * 2 + sp) * NS * NS;
+#pragma unroll
+  for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double* rowp = Bw + (16 * tr + 4 * v) * NS;
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc)
+        if ((16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS)) rowp[loff + 16 * tc] = binv[tr][tc][v];
+    }
 #pragma unroll
   for (int t = 0; t < EPL; ++t) {
-    int e = lane + 64 * t;
+    const int e = lane + 64 * t;
     if (e < N) { pw[3 * e] = px[t]; pw[3 * e + 1] = py[t]; pw[3 * e + 2] = pz[t]; }
   }
   if (lane == 0) a.nacc[w] += nacc;
@@ -341,8 +480,7 @@ hipError_t launch_invert_t(const WalkerArgs& a, int spin_lo, int spin_hi, hipStr
 }
 template <int NS, class Real>
 size_t sweep_smem() {
-  constexpr int N = 2 * NS;
-  return (size_t)N * NS * sizeof(double);
+  return SweepLds<NS>::bytes(2 * NS);
 }
 template <int NS, class Real>
 hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t st) {
