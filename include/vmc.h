@@ -66,6 +66,10 @@ typedef struct {
   int precision;      /* VMC_FP64: all FP64; VMC_MIXED: orbital, Jastrow and Ewald real-space
                          terms in FP32, determinant ratios, inverse refresh, reductions and
                          all accumulators FP64 */
+  double refine_tol;  /* inverse refresh after the first sweep: one Newton-Schulz step
+                         X <- X + X (I - A X) in FP64, and Gauss-Jordan elimination for
+                         every matrix with max|I - A X| > refine_tol (or not finite).
+                         0 = default (1e-7); < 0 = elimination for every matrix */
 } vmc_system;
 
 /* ---------------------------------------------------------------- context -- */
@@ -106,8 +110,10 @@ int vmc_traj_get_walkers(vmc_traj* traj, double* pos_dev);
  * a sweep moves electrons 0..N-1 in order by r' = r + step_delta (u - 1/2),
  * accepted iff u_acc < |psi'/psi|^2; Philox4x32-10 with key (seed, traj_id) and
  * counter (step, walker, sweep*N + e, 0|1).  The inverse of a spin's Slater
- * matrix is rebuilt by FP64 LU with partial pivoting before every half-sweep
- * over that spin (every N/2 moves) and updated by Sherman-Morrison otherwise.
+ * matrix is built by FP64 Gauss-Jordan elimination with partial pivoting before
+ * the first half-sweep over that spin, refreshed before every later one (see
+ * refine_tol) and carried through the N/2 moves of a half-sweep by Sherman-
+ * Morrison updates applied in blocks of 16 moves (delayed, same ratios).
  * After each measured sweep: E_L, dE_L/dR and dln|psi|/dR.
  * Output out_dev (3 + 3N doubles): [E, sigma_E, acceptance, f(3N)] with
  * E = mean_w e_w, sigma_E = sd_w(e_w)/sqrt(W), f = mean_w f_w,

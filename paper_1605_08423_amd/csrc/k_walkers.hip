@@ -10,6 +10,8 @@
 // A wavefront (64 lanes) owns one walker in the sweep: the active spin's inverse
 // stays in matrix-core accumulator registers, lanes own electrons j, j+64, ...;
 // the MO coefficients C are read through the caches.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(256) void k_build_A(WalkerArgs a) {
 // stored at position pi(c).  ln|det A| = sum ln|pivot|, sign from the pivots
 // and the parity of pi.  A zero pivot sets *status = 1.
 template <int NS>
-__global__ __launch_bounds__(256) void k_invert(WalkerArgs a, int spin_lo, int spin_hi) {
+__global__ __launch_bounds__(256) void k_invert(WalkerArgs a, int spin_lo, int spin_hi, int only_flagged) {
   constexpr int BC = 16, NB = (NS + BC - 1) / BC;
   __shared__ double stage[4 * NS * 17];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -69,6 +71,10 @@ __global__ __launch_bounds__(256) void k_invert(WalkerArgs a, int spin_lo, int s
   const int mat = blockIdx.x * 4 + wv;
   const int w = mat / nsp, sp = spin_lo + mat % nsp;
   if (w >= a.W) return;
+  if (only_flagged) {
+    if (a.rflag[(size_t)w * 2 + sp] == 0) return;
+    if (lane == 0) a.rflag[(size_t)w * 2 + sp] = 0;
+  }
   const size_t base = ((size_t)w * 2 + sp) * NS * NS;
   const bool isrow = lane < NS;
   double r[NB][BC];
@@ -332,13 +338,16 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
 #pragma unroll
     for (int tc = 0; tc < NT; ++tc) acc[tc] = d4w_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int tr = 0; tr < NT; ++tr)
+    for (int tr = 0; tr < NT; ++tr) {
+      double av[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double av = MB[l16 * LDM + 16 * tr + 4 * v + l4];
+      for (int v = 0; v < 4; ++v) av[v] = MB[l16 * LDM + 16 * tr + 4 * v + l4];
 #pragma unroll
-        for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_w(av, binv[tr][tc][v], acc[tc]);
-      }
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_w(av[v], binv[tr][tc][v], acc[tc]);
+      asm volatile("" ::: "memory");
+    }
 #pragma unroll
     for (int tc = 0; tc < NT; ++tc)
 #pragma unroll
@@ -405,6 +414,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
         a.Amat[bbase + (size_t)(16 * b + j) * NS + lane] = MB[j * LDM + lane];
       }
     // Z = (I + Y)^-1 [z rows]: back-substitution from the last accepted move
+#pragma unroll 1
     for (int j = 15; j >= 0; --j) {
       if (!((amask >> j) & 1u)) continue;
       const double zo = col_ok ? PB[j * LDM + lc] : 0.0;
@@ -418,15 +428,19 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
     }
     // G = the inverse's columns of this block (column tile b) into the M' buffer
     wave_lds_sync();
+    auto snap = [&](auto tcc) {
+      constexpr int TC = decltype(tcc)::value;
 #pragma unroll
-    for (int tr = 0; tr < NT; ++tr)
+      for (int tr = 0; tr < NT; ++tr)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double g = binv[tr][0][v];
-#pragma unroll
-        for (int tc = 1; tc < NT; ++tc) g = (tc == b) ? binv[tr][tc][v] : g;
-        MB[(16 * tr + 4 * v + l4) * LDG + l16] = g;
-      }
+        for (int v = 0; v < 4; ++v) MB[(16 * tr + 4 * v + l4) * LDG + l16] = binv[tr][TC][v];
+    };
+    switch (b) {
+      case 0: snap(std::integral_constant<int, 0>{}); break;
+      case 1: if constexpr (NT > 1) snap(std::integral_constant<int, (NT > 1 ? 1 : 0)>{}); break;
+      case 2: if constexpr (NT > 2) snap(std::integral_constant<int, (NT > 2 ? 2 : 0)>{}); break;
+      default: if constexpr (NT > 3) snap(std::integral_constant<int, (NT > 3 ? 3 : 0)>{}); break;
+    }
     wave_lds_sync();
     // A^-1 -= G Z
 #pragma unroll
@@ -462,6 +476,105 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
   if (lane == 0) a.nacc[w] += nacc;
 }
 
+// ------------------------------------------------- refinement refresh ---
+// One Newton-Schulz step X <- X + X (I - A X) on the FP64 matrix cores, one
+// wave per matrix.  X (the inverse carried through the previous half-sweep)
+// differs from A^-1 only by accumulated rounding E, and the step leaves an error
+// of order E^2, so it restores the inverse to working precision at a quarter of
+// the elimination's issue cost.  If max |I - A X| over the matrix exceeds tol
+// (or is not finite) the matrix is flagged for elimination instead.
+// X sits in accumulator layout (tile (tr, tc), element v of lane l =
+// X[16 tr + 4 v + l/16][16 tc + l%16]) and, as the left operand of X R, in LDS.
+template <int NS>
+struct RefineLds {
+  static constexpr int NSP = (NS + 15) / 16 * 16, LDX = NSP + 1;
+  static constexpr size_t bytes = (size_t)4 * NSP * LDX * sizeof(double);
+};
+
+template <int NS>
+__global__ __launch_bounds__(256, 1) void k_refine(WalkerArgs a, int sp, double tol) {
+  constexpr int NSP = RefineLds<NS>::NSP, NT = NSP / 16, LDX = RefineLds<NS>::LDX;
+  extern __shared__ __align__(16) double smem_r[];
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int w = blockIdx.x * 4 + wv;
+  if (w >= a.W) return;
+  double* xs = smem_r + (size_t)wv * NSP * LDX;
+  const size_t base = ((size_t)w * 2 + sp) * NS * NS;
+  const double* Ag = a.Amat + base;
+  double* Xg = a.Binv + base;
+  const int loff = l4 * NS + l16;
+  d4w_t xr[NT][NT];
+#pragma unroll
+  for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double* rowp = Xg + (16 * tr + 4 * v) * NS;
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc) {
+        const bool ok = (16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS);
+        const double val = rowp[ok ? loff + 16 * tc : -(16 * tr + 4 * v) * NS];
+        xr[tr][tc][v] = ok ? val : 0.0;
+        xs[(16 * tr + 4 * v + l4) * LDX + 16 * tc + l16] = ok ? val : 0.0;
+      }
+    }
+  wave_lds_sync();
+  // R = I - A X (real rows and columns only)
+  d4w_t rr[NT][NT];
+  double rmax = 0.0;
+#pragma unroll
+  for (int tr = 0; tr < NT; ++tr) {
+    d4w_t acc[NT];
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc) acc[tc] = d4w_t{0.0, 0.0, 0.0, 0.0};
+    const int arow = 16 * tr + l16;
+#pragma unroll
+    for (int ks = 0; ks < NSP / 4; ++ks) {
+      const int acol = 4 * ks + l4;
+      const bool ok = arow < NS && acol < NS;
+      const double val = Ag[ok ? arow * NS + acol : 0];
+      const double av = ok ? val : 0.0;
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_w(av, xr[ks / 4][tc][ks % 4], acc[tc]);
+    }
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * tr + 4 * v + l4, col = 16 * tc + l16;
+        const double r = (row < NS && col < NS) ? ((row == col ? 1.0 : 0.0) - acc[tc][v]) : 0.0;
+        rr[tr][tc][v] = r;
+        rmax = fmax(rmax, fabs(r)) + (r - r);     // NaN propagates
+      }
+  }
+  // X + X R, written back in place
+#pragma unroll
+  for (int tr = 0; tr < NT; ++tr) {
+    d4w_t acc[NT];
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc) acc[tc] = xr[tr][tc];
+#pragma unroll
+    for (int ks = 0; ks < NSP / 4; ++ks) {
+      const double av = xs[(16 * tr + l16) * LDX + 4 * ks + l4];
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_w(av, rr[ks / 4][tc][ks % 4], acc[tc]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double* rowp = Xg + (16 * tr + 4 * v) * NS;
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc)
+        if ((16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS)) rowp[loff + 16 * tc] = acc[tc][v];
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double o = __shfl_xor(rmax, off, 64);
+    rmax = (o > rmax || o != o) ? o : rmax;
+  }
+  if (lane == 0 && !(rmax <= tol)) a.rflag[(size_t)w * 2 + sp] = 1;
+}
+
 // ----------------------------------------------------------- launchers ---
 template <int NS, class Real>
 hipError_t launch_build_A_t(const WalkerArgs& a, hipStream_t st) {
@@ -473,9 +586,15 @@ hipError_t launch_build_A_t(const WalkerArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 template <int NS>
-hipError_t launch_invert_t(const WalkerArgs& a, int spin_lo, int spin_hi, hipStream_t st) {
+hipError_t launch_invert_t(const WalkerArgs& a, int spin_lo, int spin_hi, int only_flagged, hipStream_t st) {
   dim3 grid((a.W * (spin_hi - spin_lo) + 3) / 4);
-  hipLaunchKernelGGL((k_invert<NS>), grid, dim3(256), 0, st, a, spin_lo, spin_hi);
+  hipLaunchKernelGGL((k_invert<NS>), grid, dim3(256), 0, st, a, spin_lo, spin_hi, only_flagged);
+  return hipGetLastError();
+}
+template <int NS>
+hipError_t launch_refine_t(const WalkerArgs& a, int spin, double tol, hipStream_t st) {
+  dim3 grid((a.W + 3) / 4);
+  hipLaunchKernelGGL((k_refine<NS>), grid, dim3(256), RefineLds<NS>::bytes, st, a, spin, tol);
   return hipGetLastError();
 }
 template <int NS, class Real>
@@ -507,8 +626,11 @@ hipError_t launch_build_A(const WalkerArgs& a, int mixed, hipStream_t st) {
   if (mixed) { VMC_DISPATCH_NS(a.NS, return (launch_build_A_t<NSV, float>(a, st))) }
   VMC_DISPATCH_NS(a.NS, return (launch_build_A_t<NSV, double>(a, st)))
 }
-hipError_t launch_invert(const WalkerArgs& a, int spin_lo, int spin_hi, hipStream_t st) {
-  VMC_DISPATCH_NS(a.NS, return (launch_invert_t<NSV>(a, spin_lo, spin_hi, st)))
+hipError_t launch_invert(const WalkerArgs& a, int spin_lo, int spin_hi, int only_flagged, hipStream_t st) {
+  VMC_DISPATCH_NS(a.NS, return (launch_invert_t<NSV>(a, spin_lo, spin_hi, only_flagged, st)))
+}
+hipError_t launch_refine(const WalkerArgs& a, int spin, double tol, hipStream_t st) {
+  VMC_DISPATCH_NS(a.NS, return (launch_refine_t<NSV>(a, spin, tol, st)))
 }
 hipError_t launch_sweep(const WalkerArgs& a, const SweepArgs& s, int mixed, hipStream_t st) {
   if (mixed) { VMC_DISPATCH_NS(a.NS, return (launch_sweep_t<NSV, float>(a, s, st))) }

@@ -20,6 +20,7 @@ struct WalkerArgs {
   double* sgn;         // W x 2
   int* status;         // set to 1 on a zero pivot
   int64_t* nacc;       // W accepted moves
+  int* rflag;          // W x 2: 1 = the refinement step left a large residual, redo by elimination
 };
 
 struct SweepArgs {
@@ -62,7 +63,8 @@ struct MeasureArgs {
 };
 
 hipError_t launch_build_A(const WalkerArgs& a, int mixed, hipStream_t st);
-hipError_t launch_invert(const WalkerArgs& a, int spin_lo, int spin_hi, hipStream_t st);
+hipError_t launch_invert(const WalkerArgs& a, int spin_lo, int spin_hi, int only_flagged, hipStream_t st);
+hipError_t launch_refine(const WalkerArgs& a, int spin, double tol, hipStream_t st);
 hipError_t launch_sweep(const WalkerArgs& a, const SweepArgs& s, int mixed, hipStream_t st);
 
 hipError_t launch_ewald_sample(const MeasureArgs& m, const EwaldArgs& e, int mixed, hipStream_t st);

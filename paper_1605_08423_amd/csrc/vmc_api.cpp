@@ -16,9 +16,9 @@ using namespace vmc;
 
 namespace {
 
-enum KClass { K_SETUP, K_BUILD_A, K_INVERT, K_SWEEP, K_EWALD, K_SLATER, K_FINALIZE, K_REDUCE, K_SYRK, K_LANGEVIN,
-              K_NCLASS };
-const char* kClassName[K_NCLASS] = {"proton_setup", "build_A", "invert", "sweep_half", "ewald_sample",
+enum KClass { K_SETUP, K_BUILD_A, K_INVERT, K_REFINE, K_SWEEP, K_EWALD, K_SLATER, K_FINALIZE, K_REDUCE, K_SYRK,
+              K_LANGEVIN, K_NCLASS };
+const char* kClassName[K_NCLASS] = {"proton_setup", "build_A", "invert", "refine", "sweep_half", "ewald_sample",
                                     "slater_sample", "finalize", "reduce", "syrk", "langevin"};
 
 struct Pending { int cls; hipEvent_t a, b; };
@@ -49,6 +49,7 @@ struct vmc_traj {
   double *acc = nullptr, *rho_acc = nullptr, *Vs = nullptr, *dVs = nullptr, *Uj = nullptr;
   double *means = nullptr, *f_w = nullptr, *partial = nullptr, *outv = nullptr;
   int64_t* nacc = nullptr;
+  int* rflag = nullptr;
   // Ewald tables
   int nk = 0, nslot = 0;
   double *kvec = nullptr, *rho_p = nullptr, *Ptab = nullptr, *Fconst = nullptr, *Vpp = nullptr;
@@ -137,6 +138,7 @@ int check_sys(const vmc_system* s) {
   if (s->n_protons < 2 || (s->n_protons & 1) || !supported_ns(s->n_protons / 2)) return VMC_EINVAL;
   if (!(s->box_L > 0.0) || !(s->ewald_kappa > 0.0) || s->ewald_nmax < 1 || s->ewald_nmax > 12) return VMC_EINVAL;
   if (s->precision != VMC_FP64 && s->precision != VMC_MIXED) return VMC_EINVAL;
+  if (s->refine_tol != s->refine_tol) return VMC_EINVAL;
   return VMC_OK;
 }
 
@@ -191,7 +193,7 @@ WalkerArgs walker_args(vmc_traj* t, const double* R, const double* C, const doub
   a.R = R; a.zeta = zeta; a.C = C;
   a.a_par = t->sys.a_par; a.a_anti = t->sys.a_anti; a.b = t->sys.b;
   a.pos = t->pos; a.Amat = t->Amat; a.Binv = t->Binv; a.ldet = t->ldet; a.sgn = t->sgn;
-  a.status = t->ctx->d_status; a.nacc = t->nacc;
+  a.status = t->ctx->d_status; a.nacc = t->nacc; a.rflag = t->rflag;
   return a;
 }
 
@@ -246,7 +248,7 @@ void free_traj(vmc_traj* t) {
   if (!t) return;
   void* ptrs[] = {t->pos, t->Amat, t->Binv, t->ldet, t->sgn, t->acc, t->rho_acc, t->Vs, t->dVs, t->Uj,
                   t->means, t->f_w, t->partial, t->outv, t->nacc, t->kvec, t->rho_p, t->Ptab, t->Fconst,
-                  t->Vpp, t->slot, t->slot_nx0};
+                  t->Vpp, t->slot, t->slot_nx0, t->rflag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete t;
@@ -353,7 +355,7 @@ int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int W, uint32_t seed, u
             !dalloc(&t->dVs, (size_t)W * n3) && !dalloc(&t->Uj, (size_t)W) &&
             !dalloc(&t->means, (size_t)W * (1 + 3 * n3)) && !dalloc(&t->f_w, (size_t)W * n3) &&
             !dalloc(&t->partial, reduce_partial_doubles(W, (int)n3)) && !dalloc(&t->outv, 3 + n3) &&
-            !dalloc(&t->nacc, (size_t)W) && !dalloc(&t->kvec, kv.size()) && !dalloc(&t->rho_p, 2 * t->nk) &&
+            !dalloc(&t->nacc, (size_t)W) && !dalloc(&t->rflag, (size_t)W * 2) && !dalloc(&t->kvec, kv.size()) && !dalloc(&t->rho_p, 2 * t->nk) &&
             !dalloc(&t->Ptab, (size_t)t->nk * N * 2) && !dalloc(&t->Fconst, n3) && !dalloc(&t->Vpp, 1) &&
             !dalloc(&t->slot, slots.size()) && !dalloc(&t->slot_nx0, nx0.size());
   if (!ok) { free_traj(t); return VMC_ENOMEM; }
@@ -401,15 +403,22 @@ int vmc_energy_forces(vmc_traj* t, const double* R, const double* C, const doubl
   HIPCHK(hipMemsetAsync(t->acc, 0, W * (2 + 9 * N) * sizeof(double), st));
   HIPCHK(hipMemsetAsync(t->rho_acc, 0, W * t->nk * 2 * sizeof(double), st));
   HIPCHK(hipMemsetAsync(t->nacc, 0, W * sizeof(int64_t), st));
+  HIPCHK(hipMemsetAsync(t->rflag, 0, W * 2 * sizeof(int), st));
   HIPCHK(hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
   WalkerArgs a = walker_args(t, R, C, zeta, nimg);
   MeasureArgs m = measure_args(t, R, C, zeta, nimg);
   EwaldArgs e = ewald_args(t, Vconst);
   RUN(K_BUILD_A, launch_build_A(a, mixed, st));
+  const double rtol = t->sys.refine_tol == 0.0 ? 1e-7 : t->sys.refine_tol;
   const int total = n_equil + n_sweeps;
   for (int s = 0; s < total; ++s) {
     for (int sp = 0; sp < 2; ++sp) {
-      RUN(K_INVERT, launch_invert(a, sp, sp + 1, st));
+      if (s == 0 || rtol < 0.0) {
+        RUN(K_INVERT, launch_invert(a, sp, sp + 1, 0, st));
+      } else {
+        RUN(K_REFINE, launch_refine(a, sp, rtol, st));
+        RUN(K_INVERT, launch_invert(a, sp, sp + 1, 1, st));
+      }
       SweepArgs sa{sp, s, step, t->seed, t->traj_id, step_delta};
       RUN(K_SWEEP, launch_sweep(a, sa, mixed, st));
     }
@@ -514,7 +523,7 @@ int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R, const
       MeasureArgs m = measure_args(t, R, C, zeta, nimg);
       EwaldArgs e = ewald_args(t, Vconst);
       RUN(K_BUILD_A, launch_build_A(a, mixed, st));
-      RUN(K_INVERT, launch_invert(a, 0, 2, st));
+      RUN(K_INVERT, launch_invert(a, 0, 2, 0, st));
       int r2 = measure(t, m, e);
       if (r2) return r2;
       RUN(K_FINALIZE, launch_finalize(m, e, 1, t->means, st));

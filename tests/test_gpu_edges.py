@@ -87,3 +87,46 @@ def test_argument_errors(dev):
         vmc.Trajectory(ctx, vmc.make_system(100, 10.0), 4)         # unsupported size
     with pytest.raises(vmc.VMCError):
         vmc.vmc_build_S_raw(ctx, T(torch, np.ones((1, 3))), T(torch, np.ones(3)))   # W < 2
+
+
+def _chain(torch, vmc, ctx, wl, Cm, x0, W, ne, ns, refine_tol, precision=None):
+    prec = vmc.VMC_FP64 if precision is None else precision
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=prec, refine_tol=refine_tol), W, seed=4,
+                        traj_id=3)
+    tr.set_walkers(T(torch, x0))
+    out = tr.energy_forces(T(torch, wl.R.reshape(-1)), T(torch, Cm), T(torch, wl.zeta), ne, ns, wl.delta, 2)
+    res = out.cpu().numpy(), tr.accepts().cpu().numpy(), tr.walker_means().cpu().numpy()
+    tr.close()
+    return res
+
+
+@pytest.mark.parametrize("name,W,ne,ns", [("h54", 8, 1, 4), ("h128", 4, 1, 3)])
+def test_refinement_refresh_matches_elimination_and_oracle(oracle, dev, name, W, ne, ns):
+    """The Newton-Schulz refresh (default), elimination for every matrix (refine_tol < 0)
+    and the oracle's fresh determinants give the same chain: identical acceptances and
+    FP64-level agreement of the estimates.  A tolerance no residual can meet sends every
+    matrix through the refinement's elimination fallback, which must reproduce the
+    elimination path bit for bit."""
+    torch, vmc, ctx = dev
+    wl = workload(name)
+    say(f"[refresh paths] {name} W={W} sweeps={ne}+{ns}")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
+    x0 = wl.electrons(W=W, seed_offset=61)
+    o_ref, a_ref, m_ref = _chain(torch, vmc, ctx, wl, Cm, x0, W, ne, ns, 0.0)
+    o_gj, a_gj, m_gj = _chain(torch, vmc, ctx, wl, Cm, x0, W, ne, ns, -1.0)
+    o_fb, a_fb, m_fb = _chain(torch, vmc, ctx, wl, Cm, x0, W, ne, ns, 1e-300)
+    assert np.array_equal(a_ref, a_gj) and np.array_equal(a_fb, a_gj)
+    assert np.array_equal(m_fb, m_gj) and np.array_equal(o_fb, o_gj)
+    assert rel(m_ref, m_gj) < 1e-11
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L)
+    sums, nacc = s.vmc_run(x0.copy(), ne, ns, wl.delta, seed=4, traj=3, step=2)
+    red = oracle.reduce(sums, ns)
+    assert np.array_equal(a_ref, nacc)
+    assert rel(m_ref, red["means"]) < 1e-10
+    say(f"  refine vs elimination {rel(m_ref, m_gj):.2e}  refine vs oracle {rel(m_ref, red['means']):.2e}")
+
+
+def test_refine_tol_nan_rejected(dev):
+    torch, vmc, ctx = dev
+    with pytest.raises(vmc.VMCError):
+        vmc.Trajectory(ctx, vmc.make_system(16, 6.0, refine_tol=float("nan")), 4)
