@@ -71,49 +71,105 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
     }
   }
   __syncthreads();
-  // reciprocal space, one (ny, nz) slot per thread, nx innermost
-  double vrec = 0.0;
+  // Reciprocal space.  The (ny, nz) slots come sorted longest first; thread u of
+  // an electron half (u = t mod 128) accumulates the slots of rank base + u and
+  // base + u + 128, nx counted from 0 (the k of (slot, nx) is k0 + nx - nx0), so
+  // one load of an electron's x phases serves both slots and every lane of a wave
+  // runs the wave's longest slot length, which its first lane holds.  When all
+  // slots fit one pass, waves 2 and 3 take electrons N/2..N-1 and hand their
+  // partial sums to waves 0 and 1 through LDS (over the phase table, no longer
+  // needed); otherwise waves 0 and 1 take every electron in passes of 256 slots.
+  double vrec = 0.0, vreal = 0.0;
   double* racc = m.rho_acc + (size_t)w * e.nk * 2;
-  for (int sl = t; sl < e.nslot; sl += 256) {
-    const int ny = e.slot[4 * sl], nz = e.slot[4 * sl + 1], k0 = e.slot[4 * sl + 2], cnt = e.slot[4 * sl + 3];
-    const int nx0 = e.slot_nx0[sl];
-    const int ay = ny < 0 ? -ny : ny, az = nz < 0 ? -nz : nz;
-    const double sy = ny < 0 ? -1.0 : 1.0, sz = nz < 0 ? -1.0 : 1.0;
-    double ar[NMX + 1], ai[NMX + 1];
+  const bool split = e.nslot <= 256;
+  const int u = t & 127, hf = t >> 7;
+  if (split || hf == 0) {
+    for (int base = 0; base < e.nslot; base += 256) {
+      int ay[2], az[2], k0[2], nx0[2], nb[2];
+      double sy[2], sz[2];
 #pragma unroll
-    for (int j = 0; j <= NMX; ++j) { ar[j] = 0.0; ai[j] = 0.0; }
-    for (int i = 0; i < N; ++i) {
-      const double2 ey = ph[((size_t)1 * N + i) * NP1 + ay];
-      const double2 ez = ph[((size_t)2 * N + i) * NP1 + az];
-      const double yr = ey.x, yi = sy * ey.y, zr = ez.x, zi = sz * ez.y;
-      const double tr = yr * zr - yi * zi, ti = yr * zi + yi * zr;
-      const double2* ex = ph + (size_t)i * NP1 + nx0;
-#pragma unroll
-      for (int j = 0; j <= NMX; ++j) {
-        if (j < cnt) {
-          const double2 x = ex[j];
-          ar[j] += x.x * tr - x.y * ti;
-          ai[j] += x.x * ti + x.y * tr;
+      for (int q = 0; q < 2; ++q) {
+        const int sl = base + u + 128 * q;
+        ay[q] = az[q] = k0[q] = nx0[q] = nb[q] = 0;
+        sy[q] = sz[q] = 1.0;
+        if (sl < e.nslot) {
+          const int ny = e.slot[4 * sl], nz = e.slot[4 * sl + 1];
+          ay[q] = ny < 0 ? -ny : ny; az[q] = nz < 0 ? -nz : nz;
+          sy[q] = ny < 0 ? -1.0 : 1.0; sz[q] = nz < 0 ? -1.0 : 1.0;
+          k0[q] = e.slot[4 * sl + 2];
+          nx0[q] = e.slot_nx0[sl];
+          nb[q] = nx0[q] + e.slot[4 * sl + 3];
         }
       }
-    }
+      const int ba = __builtin_amdgcn_readfirstlane(nb[0]), bb = __builtin_amdgcn_readfirstlane(nb[1]);
+      double ar[NMX + 1], ai[NMX + 1], br[NMX + 1], bi[NMX + 1];
 #pragma unroll
-    for (int j = 0; j <= NMX; ++j) {
-      if (j < cnt) {
-        const int k = k0 + j;
-        const double rer = -ar[j], rei = -ai[j];            // electron charge -1
-        const double tr = e.rho_p[2 * k] + rer, ti = e.rho_p[2 * k + 1] + rei;
-        vrec += e.kvec[4 * k + 3] * (tr * tr + ti * ti);
-        racc[2 * k] += rer;
-        racc[2 * k + 1] += rei;
+      for (int j = 0; j <= NMX; ++j) { ar[j] = ai[j] = br[j] = bi[j] = 0.0; }
+      const int i_lo = split ? hf * (N / 2) : 0, i_hi = split ? (hf + 1) * (N / 2) : N;
+      for (int i = i_lo; i < i_hi; ++i) {
+        const double2 eya = ph[((size_t)1 * N + i) * NP1 + ay[0]], eza = ph[((size_t)2 * N + i) * NP1 + az[0]];
+        const double2 eyb = ph[((size_t)1 * N + i) * NP1 + ay[1]], ezb = ph[((size_t)2 * N + i) * NP1 + az[1]];
+        const double ya_r = eya.x, ya_i = sy[0] * eya.y, za_r = eza.x, za_i = sz[0] * eza.y;
+        const double yb_r = eyb.x, yb_i = sy[1] * eyb.y, zb_r = ezb.x, zb_i = sz[1] * ezb.y;
+        const double tar = ya_r * za_r - ya_i * za_i, tai = ya_r * za_i + ya_i * za_r;
+        const double tbr = yb_r * zb_r - yb_i * zb_i, tbi = yb_r * zb_i + yb_i * zb_r;
+        const double2* ex = ph + (size_t)i * NP1;
+#pragma unroll
+        for (int j = 0; j <= NMX; ++j) {
+          if (j < ba) {
+            const double2 x = ex[j];
+            ar[j] += x.x * tar - x.y * tai;
+            ai[j] += x.x * tai + x.y * tar;
+            if (j < bb) {
+              br[j] += x.x * tbr - x.y * tbi;
+              bi[j] += x.x * tbi + x.y * tbr;
+            }
+          }
+        }
       }
+      if (split) {
+        // the second half's sums go to comb[k] (over the phase table), the first half adds them
+        double2* comb = ph;
+        __syncthreads();
+        if (hf == 1) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int j = 0; j <= NMX; ++j)
+              if (j >= nx0[q] && j < nb[q])
+                comb[k0[q] + j - nx0[q]] = q == 0 ? make_double2(ar[j], ai[j]) : make_double2(br[j], bi[j]);
+        }
+        __syncthreads();
+        if (hf == 1) break;
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int j = 0; j <= NMX; ++j)
+            if (j >= nx0[q] && j < nb[q]) {
+              const double2 c = comb[k0[q] + j - nx0[q]];
+              if (q == 0) { ar[j] += c.x; ai[j] += c.y; } else { br[j] += c.x; bi[j] += c.y; }
+            }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int j = 0; j <= NMX; ++j) {
+          if (j >= nx0[q] && j < nb[q]) {
+            const int k = k0[q] + j - nx0[q];
+            const double rer = -(q == 0 ? ar[j] : br[j]), rei = -(q == 0 ? ai[j] : bi[j]);   // electron charge -1
+            const double tr = e.rho_p[2 * k] + rer, ti = e.rho_p[2 * k + 1] + rei;
+            vrec += e.kvec[4 * k + 3] * (tr * tr + ti * ti);
+            racc[2 * k] += rer;
+            racc[2 * k + 1] += rei;
+          }
+        }
     }
   }
+  {
   // real space in 6N tasks of about N/4 pairs: u < 2N electron-electron (half
   // circulant offsets split in two), 2N <= u < 6N electron-proton (electrons split in four)
   const Real kap = (Real)e.kappa;
   const Real tkp = (Real)(2.0 * e.kappa / 1.7724538509055160273);
-  double vreal = 0.0;
   for (int u = t; u < 6 * N; u += 256) {
     if (u < 2 * N) {
       const int i = u % N, hh = u / N;
@@ -154,6 +210,7 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
       double* pq = part + ((size_t)qd * N + b) * 3;
       pq[0] = (double)gx; pq[1] = (double)gy; pq[2] = (double)gz;
     }
+  }
   }
   __syncthreads();
   for (int b = t; b < N; b += 256) {
@@ -566,7 +623,9 @@ __global__ __launch_bounds__(256) void k_proton_const(int N, double L, EwaldArgs
 // ----------------------------------------------------------- launchers ---
 template <int N, class Real>
 hipError_t launch_ewald_t(const MeasureArgs& m, const EwaldArgs& e, hipStream_t st) {
-  size_t sm = (size_t)18 * N * sizeof(double) + (size_t)3 * N * (e.nmax + 1) * sizeof(double2);
+  // the phase table region also holds the nk partial sums of the reciprocal combine
+  const size_t tab = (size_t)3 * N * (e.nmax + 1), cmb = (size_t)e.nk;
+  size_t sm = (size_t)18 * N * sizeof(double) + (tab > cmb ? tab : cmb) * sizeof(double2);
   if (e.nmax <= 9)
     hipLaunchKernelGGL((k_ewald_sample<N, Real, 9>), dim3(m.W), dim3(256), sm, st, m, e);
   else

@@ -143,9 +143,14 @@ int check_sys(const vmc_system* s) {
 }
 
 // Half-space reciprocal vectors grouped by (ny, nz), nx innermost.
-void build_kvectors(const vmc_system& s, std::vector<double>& kv, std::vector<int>& slots, std::vector<int>& nx0) {
+// Half-space k = 2 pi n / L, 0 < |n|^2 <= nmax^2, grouped in (ny, nz) slots with nx
+// innermost; the slot list is sorted by nx range (longest first, stable) so that
+// the reciprocal-space lanes of a wave get slots of about equal length.
+void build_kvectors(const vmc_system& s, std::vector<double>& kv, std::vector<int>& slots_out,
+                    std::vector<int>& nx0_out) {
   const int nm = s.ewald_nmax;
   const double L = s.box_L, V = L * L * L, kap = s.ewald_kappa, tp = 2.0 * M_PI / L;
+  std::vector<int> slots, nx0;
   int k = 0;
   for (int ny = -nm; ny <= nm; ++ny)
     for (int nz = -nm; nz <= nm; ++nz) {
@@ -169,6 +174,17 @@ void build_kvectors(const vmc_system& s, std::vector<double>& kv, std::vector<in
         kv.push_back(4.0 * M_PI / V * std::exp(-k2 / (4.0 * kap * kap)) / k2);
       }
     }
+  std::vector<int> order(nx0.size());
+  for (size_t q = 0; q < order.size(); ++q) order[q] = (int)q;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return nx0[x] + slots[4 * x + 3] > nx0[y] + slots[4 * y + 3];
+  });
+  slots_out.clear();
+  nx0_out.clear();
+  for (int q : order) {
+    for (int c = 0; c < 4; ++c) slots_out.push_back(slots[4 * q + c]);
+    nx0_out.push_back(nx0[q]);
+  }
 }
 
 // Gaussian images kept per axis: all three (n = -1, 0, 1) unless the mode is mixed and
