@@ -98,7 +98,39 @@ __device__ __forceinline__ void lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)"
 
 template <class Real> __device__ __forceinline__ Real dev_sqrt(Real x);
 template <> __device__ __forceinline__ double dev_sqrt<double>(double x) { return sqrt(x); }
-template <> __device__ __forceinline__ float dev_sqrt<float>(float x) { return __fsqrt_rn(x); }
+template <> __device__ __forceinline__ float dev_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Reciprocal and reciprocal square root: exact in FP64, the hardware estimates
+// (about 1 ulp) in FP32, where the mixed mode accepts FP32-level errors.
+template <class Real> __device__ __forceinline__ Real dev_rcp(Real x);
+template <> __device__ __forceinline__ double dev_rcp<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ float dev_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <class Real> __device__ __forceinline__ Real dev_rsqrt(Real x);
+template <> __device__ __forceinline__ double dev_rsqrt<double>(double x) { return 1.0 / sqrt(x); }
+template <> __device__ __forceinline__ float dev_rsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// erfc(x) for x >= 0 and e^{-x^2}.  FP64: the library functions.  FP32, without
+// branches: erfc(x) = t Q(t) e^{-x^2}, t = 1 / (1 + 0.4 x), Q of degree 9 fitted to
+// erfcx(x) / t on [0, 10] (relative error of the fit below 1e-8, so FP32 rounding
+// dominates; csrc/fit_erfc.py makes the coefficients); e^{-x^2} takes the rounding
+// error of x^2 into account to first order.
+template <class Real> __device__ __forceinline__ Real dev_erfc_exp(Real x, Real* ex2);
+template <> __device__ __forceinline__ double dev_erfc_exp<double>(double x, double* ex2) {
+  *ex2 = exp(-x * x);
+  return erfc(x);
+}
+template <> __device__ __forceinline__ float dev_erfc_exp<float>(float x, float* ex2) {
+  constexpr float Q0 = 0.22570692f, Q1 = 0.22495188f, Q2 = 0.21491995f, Q3 = 0.12967727f, Q4 = 0.27206808f;
+  constexpr float Q5 = -0.28436062f, Q6 = 0.54741645f, Q7 = -0.49878836f, Q8 = 0.19799955f, Q9 = -0.029591113f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.4f, x, 1.0f));
+  float q = fmaf(Q9, t, Q8);
+  q = fmaf(q, t, Q7); q = fmaf(q, t, Q6); q = fmaf(q, t, Q5); q = fmaf(q, t, Q4);
+  q = fmaf(q, t, Q3); q = fmaf(q, t, Q2); q = fmaf(q, t, Q1); q = fmaf(q, t, Q0);
+  const float hi = x * x, lo = fmaf(x, x, -hi);
+  const float e = __expf(-hi) * (1.0f - lo);
+  *ex2 = e;
+  return t * q * e;
+}
 
 template <class Real> __device__ __forceinline__ void dev_sincospi(Real x, Real* s, Real* c);
 template <> __device__ __forceinline__ void dev_sincospi<double>(double x, double* s, double* c) { sincospi(x, s, c); }
@@ -117,7 +149,7 @@ __device__ __forceinline__ Real pade_u(const Real si[3], const Real ci[3], const
     r2 += rt * rt;
   }
   Real rho = dev_sqrt<Real>(r2);
-  return a * rho / (Real(1) + b * rho);
+  return a * rho * dev_rcp<Real>(Real(1) + b * rho);
 }
 
 }  // namespace vmc

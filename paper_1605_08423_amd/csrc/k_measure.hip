@@ -22,9 +22,6 @@
 
 namespace vmc {
 
-template <class Real> __device__ __forceinline__ Real dev_erfc(Real x);
-template <> __device__ __forceinline__ double dev_erfc<double>(double x) { return erfc(x); }
-template <> __device__ __forceinline__ float dev_erfc<float>(float x) { return erfcf(x); }
 
 // Deterministic block sum (blockDim = 256); every thread gets the result.
 __device__ __forceinline__ double block_sum256(double v, double* scratch4) {
@@ -184,8 +181,9 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
           const Real d = (Real)min_image(pe[3 * i + ax] - pe[3 * j + ax], L, invL);
           r2 += d * d;
         }
-        const Real r = dev_sqrt<Real>(r2);
-        vs += dev_erfc<Real>(kap * r) / r;
+        const Real ir = dev_rsqrt<Real>(r2);
+        Real e2;
+        vs += dev_erfc_exp<Real>(kap * (r2 * ir), &e2) * ir;
       }
       vreal += (double)vs;
     } else {
@@ -197,12 +195,12 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
         const Real dy = (Real)min_image(pp[3 * b + 1] - pe[3 * i + 1], L, invL);
         const Real dz = (Real)min_image(pp[3 * b + 2] - pe[3 * i + 2], L, invL);
         const Real r2 = dx * dx + dy * dy + dz * dz;
-        const Real r = dev_sqrt<Real>(r2);
-        const Real ir = Real(1) / r;
-        const Real ec = dev_erfc<Real>(kap * r);
+        const Real ir = dev_rsqrt<Real>(r2);
+        Real e2;
+        const Real ec = dev_erfc_exp<Real>(kap * (r2 * ir), &e2);
         vs -= ec * ir;
         // d/dR_b of -erfc(kappa r)/r with r = |R_b - r_i|
-        const Real dedr = -ec * ir * ir - tkp * dev_exp<Real>(-kap * kap * r2) * ir;
+        const Real dedr = -ec * ir * ir - tkp * e2 * ir;
         const Real gsc = -dedr * ir;
         gx += gsc * dx; gy += gsc * dy; gz += gsc * dz;
       }
@@ -315,11 +313,11 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
           cc[ax] = ti[3 + ax] * tj_[3 + ax] + ti[ax] * tj_[ax];
         }
         const Real r2 = rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2];
-        const Real rho = dev_sqrt<Real>(r2);
+        const Real irho = dev_rsqrt<Real>(r2);
+        const Real rho = r2 * irho;
         const Real a = ((i / NS) == (j / NS)) ? ap : aa;
-        const Real den = Real(1) + bb * rho, iden = Real(1) / den;
+        const Real den = Real(1) + bb * rho, iden = dev_rcp<Real>(den);
         const Real up = a * iden * iden, upp = Real(-2) * a * bb * iden * iden * iden;
-        const Real irho = Real(1) / rho;
         const Real gr0 = rt[0] * cc[0] * irho, gr1 = rt[1] * cc[1] * irho, gr2 = rt[2] * cc[2] * irho;
         const Real gg = gr0 * gr0 + gr1 * gr1 + gr2 * gr2;
         const Real lr = (cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2] - kf * r2) * irho - gg * irho;
