@@ -258,19 +258,19 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
       }
     }
 
-  double px[EPL], py[EPL], pz[EPL];
+  // positions stay in HBM: a block reads the current positions of its 16 electrons
+  // (no earlier move of the half-sweep touches them) and an accepted move writes
+  // its electron's new position; lanes keep the trig caches of electrons lane, lane+64
   Real ts[EPL][3], tc_[EPL][3];
   double* pw = a.pos + (size_t)w * N * 3;
 #pragma unroll
   for (int t = 0; t < EPL; ++t) {
     const int e = lane + 64 * t;
-    px[t] = py[t] = pz[t] = 0.0;
     for (int m = 0; m < 3; ++m) { ts[t][m] = Real(0); tc_[t][m] = Real(1); }
     if (e < N) {
-      px[t] = pw[3 * e]; py[t] = pw[3 * e + 1]; pz[t] = pw[3 * e + 2];
-      dev_sincospi<Real>((Real)(px[t] * invL), &ts[t][0], &tc_[t][0]);
-      dev_sincospi<Real>((Real)(py[t] * invL), &ts[t][1], &tc_[t][1]);
-      dev_sincospi<Real>((Real)(pz[t] * invL), &ts[t][2], &tc_[t][2]);
+      dev_sincospi<Real>((Real)(pw[3 * e] * invL), &ts[t][0], &tc_[t][0]);
+      dev_sincospi<Real>((Real)(pw[3 * e + 1] * invL), &ts[t][1], &tc_[t][1]);
+      dev_sincospi<Real>((Real)(pw[3 * e + 2] * invL), &ts[t][2], &tc_[t][2]);
     }
   }
   const Real a_same = (Real)a.a_par, a_anti = (Real)a.a_anti, bj = (Real)a.b;
@@ -283,10 +283,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
     const int ip = 16 * b + l16;
     const bool pvalid = ip < NS;
     const int ipc = pvalid ? ip : 0;
-    const int owner_p = (sp * NS + ipc) & 63;
-    const double xo_p = __shfl(pick(px, slot), owner_p, 64);
-    const double yo_p = __shfl(pick(py, slot), owner_p, 64);
-    const double zo_p = __shfl(pick(pz, slot), owner_p, 64);
+    const double* po = pw + 3 * (sp * NS + ipc);
+    const double xo_p = po[0], yo_p = po[1], zo_p = po[2];
     // the move's four uniforms: displacement x, y, z and the acceptance test
     double xn, yn, zn, ru3;
     {
@@ -385,20 +383,24 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
                 pade_u<Real>(so, co, ts[tt], tc_[tt], LoverPi, aa, bj);
         }
       }
-      const double dU = wave_sum((double)du);
+      // xor-butterfly sum kept in vector registers: every lane adds the same two
+      // partial sums at every step, so all lanes hold the identical total and the
+      // acceptance test below takes the same branch in every lane
+      double dU = (double)du;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) dU += __shfl_xor(dU, off, 64);
       const double pacc = q * q * exp(2.0 * dU);
       double zrow = 0.0;
       if (readlane_d(ru3, j) < pacc) {
         zrow = (t - (lane == i ? 1.0 : 0.0)) * (1.0 / q);
         amask |= 1u << j;
-        const double xnj = readlane_d(xn, j), ynj = readlane_d(yn, j), znj = readlane_d(zn, j);
+        // lanes j, j + 16, j + 32 hold move j's proposal; each writes one coordinate
+        if (l16 == j && l4 < 3) pw[3 * e + l4] = (l4 == 0) ? xn : ((l4 == 1) ? yn : zn);
         if (lane == owner) {
 #pragma unroll
           for (int tt = 0; tt < EPL; ++tt)
-            if (tt == slot) {
-              px[tt] = xnj; py[tt] = ynj; pz[tt] = znj;
+            if (tt == slot)
               for (int m = 0; m < 3; ++m) { ts[tt][m] = sn[m]; tc_[tt][m] = cn[m]; }
-            }
         }
         ++nacc;
       }
@@ -468,11 +470,6 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
       for (int tc = 0; tc < NT; ++tc)
         if ((16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS)) rowp[loff + 16 * tc] = binv[tr][tc][v];
     }
-#pragma unroll
-  for (int t = 0; t < EPL; ++t) {
-    const int e = lane + 64 * t;
-    if (e < N) { pw[3 * e] = px[t]; pw[3 * e + 1] = py[t]; pw[3 * e + 2] = pz[t]; }
-  }
   if (lane == 0) a.nacc[w] += nacc;
 }
 
