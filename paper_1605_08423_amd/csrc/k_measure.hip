@@ -231,13 +231,35 @@ __device__ __forceinline__ d4_t mfma16(double av, double bv, d4_t acc) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
 }
 
+// 16x16x4 step of the products whose operands are stored as Real: FP64 matrix
+// cores for Real = double, FP32 ones (twice the rate) in mixed mode.  Element v of
+// lane l's result is row l/16 + 4 v (FP64) or 4 (l/16) + v (FP32) of D, column l % 16
+// (both read off the hardware); the operands follow the same layout in both.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+template <class Real> struct MM16;
+template <> struct MM16<double> {
+  typedef d4_t acc_t;
+  static __device__ __forceinline__ acc_t zero() { return d4_t{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) { return mfma16(a, b, c); }
+  static __device__ __forceinline__ int row(int l4, int v) { return l4 + 4 * v; }
+};
+template <> struct MM16<float> {
+  typedef f4_t acc_t;
+  static __device__ __forceinline__ acc_t zero() { return f4_t{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l4, int v) { return 4 * l4 + v; }
+};
+
 // Per walker (one 256-thread block): Jastrow gradient/Laplacian per electron;
-// per spin the three contractions B = C A^-1, M = X B, W = B M on the FP64
-// matrix cores (dimensions padded to multiples of 16 with zeros), and the
-// elementwise basis passes that build X and the d/dR terms.
-// LDS layout of k_slater_sample (bytes), shared with the launcher.  B/W and X are
-// stored as Real (FP32 in mixed mode: they carry FP32-level errors already); the
-// inverse staging, M and the partial sums are FP64.
+// per spin the three contractions B = C A^-1 (FP64 matrix cores), M = X B and
+// W = B M (matrix cores in Real: their operands are stored as Real), dimensions
+// padded to multiples of 16 with zeros, and the elementwise basis passes that
+// build X and the d/dR terms.
+// LDS layout of k_slater_sample (bytes), shared with the launcher.  B/W, X and M
+// are stored as Real (FP32 in mixed mode: they carry FP32-level errors already);
+// the inverse staging and the partial sums are FP64.
 template <int NS, class Real>
 struct SlaterLds {
   static constexpr int N = 2 * NS;
@@ -397,31 +419,33 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         gauss1d_n<Real, 3, NIMG>((Real)min_image(pos[3 * e + 1] - Ra1, L, invL), za, (Real)L, g[1]);
         gauss1d_n<Real, 3, NIMG>((Real)min_image(pos[3 * e + 2] - Ra2, L, invL), za, (Real)L, g[2]);
         const Real p00 = g[1][0] * g[2][0], p01 = g[0][0] * g[2][0], p02 = g[0][0] * g[1][0];
-        const double gx = g[0][1] * p00, gy = g[1][1] * p01, gz = g[2][1] * p02;
-        const double hxx = g[0][2] * p00, hyy = g[1][2] * p01, hzz = g[2][2] * p02;
-        const double hxy = g[0][1] * g[1][1] * g[2][0], hxz = g[0][1] * g[1][0] * g[2][1];
-        const double hyz = g[0][0] * g[1][1] * g[2][1];
-        const double lap = hxx + hyy + hzz;
-        const double glx = g[0][3] * p00 + g[0][1] * (g[1][2] * g[2][0] + g[1][0] * g[2][2]);
-        const double gly = g[1][3] * p01 + g[1][1] * (g[0][2] * g[2][0] + g[0][0] * g[2][2]);
-        const double glz = g[2][3] * p02 + g[2][1] * (g[0][2] * g[1][0] + g[0][0] * g[1][2]);
-        const double u0 = gU[3 * e], u1 = gU[3 * e + 1], u2 = gU[3 * e + 2];
-        const double X = -0.5 * (lap + 2.0 * (gx * u0 + gy * u1 + gz * u2));
-        Xr[i * LDX + a] = (Real)X;
+        // per-pair brackets in Real (FP32 in mixed mode, from FP32 basis values), sums in FP64
+        const Real gx = g[0][1] * p00, gy = g[1][1] * p01, gz = g[2][1] * p02;
+        const Real hxx = g[0][2] * p00, hyy = g[1][2] * p01, hzz = g[2][2] * p02;
+        const Real hxy = g[0][1] * g[1][1] * g[2][0], hxz = g[0][1] * g[1][0] * g[2][1];
+        const Real hyz = g[0][0] * g[1][1] * g[2][1];
+        const Real lap = hxx + hyy + hzz;
+        const Real glx = g[0][3] * p00 + g[0][1] * (g[1][2] * g[2][0] + g[1][0] * g[2][2]);
+        const Real gly = g[1][3] * p01 + g[1][1] * (g[0][2] * g[2][0] + g[0][0] * g[2][2]);
+        const Real glz = g[2][3] * p02 + g[2][1] * (g[0][2] * g[1][0] + g[0][0] * g[1][2]);
+        const Real u0 = (Real)gU[3 * e], u1 = (Real)gU[3 * e + 1], u2 = (Real)gU[3 * e + 2];
+        const Real X = Real(-0.5) * (lap + Real(2) * (gx * u0 + gy * u1 + gz * u2));
+        Xr[i * LDX + a] = X;
         const double b = (double)Bs[a * LDB + i];
-        tsl += X * b;
-        dln0 -= b * gx; dln1 -= b * gy; dln2 -= b * gz;
-        dT0 += 0.5 * (glx + 2.0 * (hxx * u0 + hxy * u1 + hxz * u2)) * b;
-        dT1 += 0.5 * (gly + 2.0 * (hxy * u0 + hyy * u1 + hyz * u2)) * b;
-        dT2 += 0.5 * (glz + 2.0 * (hxz * u0 + hyz * u1 + hzz * u2)) * b;
+        tsl += (double)X * b;
+        dln0 -= b * (double)gx; dln1 -= b * (double)gy; dln2 -= b * (double)gz;
+        dT0 += (double)(Real(0.5) * (glx + Real(2) * (hxx * u0 + hxy * u1 + hxz * u2))) * b;
+        dT1 += (double)(Real(0.5) * (gly + Real(2) * (hxy * u0 + hyy * u1 + hyz * u2))) * b;
+        dT2 += (double)(Real(0.5) * (glz + Real(2) * (hxz * u0 + hyz * u1 + hzz * u2))) * b;
       }
     }
     __syncthreads();
-    // M = X B (NSP x NSP), K = centres
+    // M = X B (NSP x NSP), K = centres; stored as Real over the inverse staging
+    Real* Mr = reinterpret_cast<Real*>(XM);
     {
-      d4_t acc[TPW_M];
+      typename MM16<Real>::acc_t acc[TPW_M];
 #pragma unroll
-      for (int q = 0; q < TPW_M; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < TPW_M; ++q) acc[q] = MM16<Real>::zero();
       for (int kk = 0; kk < NP / 4; ++kk) {
         const int k = kk * 4 + l4;
 #pragma unroll
@@ -430,9 +454,9 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
           if (tt < TI * TI) {
             const int tr = tt / TI, tc = tt % TI;
             const int irow = tr * 16 + l16;
-            const double av = (irow < NS && k < N) ? (double)Xr[irow * LDX + k] : 0.0;
-            const double bv = (k < N) ? (double)Bs[k * LDB + tc * 16 + l16] : 0.0;
-            acc[q] = mfma16(av, bv, acc[q]);
+            const Real av = (irow < NS && k < N) ? Xr[irow * LDX + k] : Real(0);
+            const Real bv = (k < N) ? Bs[k * LDB + tc * 16 + l16] : Real(0);
+            acc[q] = MM16<Real>::step(av, bv, acc[q]);
           }
         }
       }
@@ -443,16 +467,16 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         if (tt < TI * TI) {
           const int tr = tt / TI, tc = tt % TI;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) XM[(tr * 16 + l4 + 4 * v) * LDI + tc * 16 + l16] = acc[q][v];
+          for (int v = 0; v < 4; ++v) Mr[(tr * 16 + MM16<Real>::row(l4, v)) * LDI + tc * 16 + l16] = (Real)acc[q][v];
         }
       }
     }
     __syncthreads();
     // W = B M (NP x NSP), K = orbitals; B is the A operand, W replaces it in Bs
     {
-      d4_t acc[TPW_B];
+      typename MM16<Real>::acc_t acc[TPW_B];
 #pragma unroll
-      for (int q = 0; q < TPW_B; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < TPW_B; ++q) acc[q] = MM16<Real>::zero();
       for (int kk = 0; kk < NSP / 4; ++kk) {
         const int k = kk * 4 + l4;
 #pragma unroll
@@ -461,9 +485,9 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
           if (tt < TA * TI) {
             const int ta = tt / TI, tc = tt % TI;
             const int arow = ta * 16 + l16;
-            const double av = (arow < N) ? (double)Bs[arow * LDB + k] : 0.0;
-            const double bv = XM[k * LDI + tc * 16 + l16];
-            acc[q] = mfma16(av, bv, acc[q]);
+            const Real av = (arow < N) ? Bs[arow * LDB + k] : Real(0);
+            const Real bv = Mr[k * LDI + tc * 16 + l16];
+            acc[q] = MM16<Real>::step(av, bv, acc[q]);
           }
         }
       }
@@ -474,7 +498,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         if (tt < TA * TI) {
           const int ta = tt / TI, tc = tt % TI;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Bs[(ta * 16 + l4 + 4 * v) * LDB + tc * 16 + l16] = (Real)acc[q][v];
+          for (int v = 0; v < 4; ++v) Bs[(ta * 16 + MM16<Real>::row(l4, v)) * LDB + tc * 16 + l16] = (Real)acc[q][v];
         }
       }
     }
