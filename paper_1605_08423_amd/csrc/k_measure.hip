@@ -372,39 +372,70 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
   for (int sp = 0; sp < 2; ++sp) {
     // A^-1 of this spin into XM (NSP x LDI, zero padded)
     const double* Bi = m.Binv + ((size_t)w * 2 + sp) * NS * NS;
-    for (int u = t; u < NSP * NSP; u += 256) {
-      const int k = u / NSP, j = u % NSP;
-      XM[k * LDI + j] = (k < NS && j < NS) ? Bi[k * NS + j] : 0.0;
+    {
+      constexpr int PER = (NSP * NSP + 255) / 256;   // all loads issued before the stores
+      double v[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int u = t + 256 * q, k = u / NSP, j = u % NSP;
+        const bool ok = u < NSP * NSP && k < NS && j < NS;
+        const double x = Bi[ok ? k * NS + j : 0];
+        v[q] = ok ? x : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int u = t + 256 * q, k = u / NSP, j = u % NSP;
+        if (u < NSP * NSP) XM[k * LDI + j] = v[q];
+      }
     }
     __syncthreads();
-    // B = C A^-1 (NP x NSP) on the matrix cores -> Bs
+    // B = C A^-1 (NP x NSP) on the FP64 matrix cores -> Bs.  Wave w takes the row
+    // tiles w, w + 4, ... against every column tile, so each element of C is loaded
+    // by one wave; the next k step's C values are loaded ahead of this step's products.
     {
-      d4_t acc[TPW_B];
+      constexpr int RT = (TA + 3) / 4;
+      d4_t acc[RT][TI];
 #pragma unroll
-      for (int q = 0; q < TPW_B; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int tc = 0; tc < TI; ++tc) acc[r][tc] = d4_t{0.0, 0.0, 0.0, 0.0};
+      auto cload = [&](int kk, int r) -> double {
+        const int arow = (wave + 4 * r) * 16 + l16, k = kk * 4 + l4;
+        const bool ok = (wave + 4 * r) < TA && arow < N && k < NS;
+        const double v = m.C[ok ? arow * NS + k : 0];
+        return ok ? v : 0.0;
+      };
+      double avn[RT];
+#pragma unroll
+      for (int r = 0; r < RT; ++r) avn[r] = cload(0, r);
       for (int kk = 0; kk < NSP / 4; ++kk) {
+        double av[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) av[r] = avn[r];
+        if (kk + 1 < NSP / 4) {
+#pragma unroll
+          for (int r = 0; r < RT; ++r) avn[r] = cload(kk + 1, r);
+        }
         const int k = kk * 4 + l4;
+        double bv[TI];
 #pragma unroll
-        for (int q = 0; q < TPW_B; ++q) {
-          const int tt = wave + 4 * q;
-          if (tt < TA * TI) {
-            const int ta = tt / TI, tc = tt % TI;
-            const int arow = ta * 16 + l16;
-            const double av = (arow < N && k < NS) ? m.C[arow * NS + k] : 0.0;
-            const double bv = XM[k * LDI + tc * 16 + l16];
-            acc[q] = mfma16(av, bv, acc[q]);
+        for (int tc = 0; tc < TI; ++tc) bv[tc] = XM[k * LDI + tc * 16 + l16];
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+          if (wave + 4 * r < TA) {
+#pragma unroll
+            for (int tc = 0; tc < TI; ++tc) acc[r][tc] = mfma16(av[r], bv[tc], acc[r][tc]);
           }
-        }
       }
 #pragma unroll
-      for (int q = 0; q < TPW_B; ++q) {
-        const int tt = wave + 4 * q;
-        if (tt < TA * TI) {
-          const int ta = tt / TI, tc = tt % TI;
+      for (int r = 0; r < RT; ++r)
+        if (wave + 4 * r < TA) {
+          const int ta = wave + 4 * r;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Bs[(ta * 16 + l4 + 4 * v) * LDB + tc * 16 + l16] = (Real)acc[q][v];
+          for (int tc = 0; tc < TI; ++tc)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Bs[(ta * 16 + l4 + 4 * v) * LDB + tc * 16 + l16] = (Real)acc[r][tc][v];
         }
-      }
     }
     __syncthreads();
     // pass 1: basis derivatives -> X, and the terms that need only B
