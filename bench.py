@@ -20,30 +20,47 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "VMC walker-sweeps/s with forces at N=128 H; Langevin steps/s, p99 latency"
-PEAK_FP64_TFLOPS = 78.6      # MI355X vector / matrix FP64
-PEAK_FP32_TFLOPS = 157.3
+# MI355X peaks per execution unit, TFLOP/s.  Packed FP32 is not used, so FP32 vector
+# arithmetic issues at the FP64 vector rate.
+PEAK = {"mfma_f64": 78.6, "mfma_f32": 157.3, "valu": 78.6}
 
 
-def algorithmic_flops(cls: str, N: int, W: int, nk: int) -> float:
-    """Algorithmic FP64/FP32 arithmetic per launch of a kernel class (FMA = 2 flops,
-    each exp/erfc/sqrt/div/sincos counted as 1).  The per-walker counts are those of
-    the method at this N (one launch processes all W walkers)."""
+def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool) -> dict:
+    """Algorithmic arithmetic of one walker's share of a launch, split by the unit that
+    executes it: {unit: flops} (FMA = 2 flops; exp, erfc, sqrt, rcp, sincos count 1).
+    img = Gaussian images evaluated per axis (3, or 1 when the dropped ones are below
+    FP32 resolution)."""
     NS = N // 2
+    img = 3 if nimg else 1
     if cls == "slater_sample":
-        gemm = 3 * 2 * (2 * N * NS * NS)                      # B = C A^-1, M = X B, W = B M per spin
-        pass1 = N * N * (3 * 3 * 6 + 60 + 9)                  # 9 Gaussian images (5 ops + exp), products, X, adjoint terms
-        pass2 = N * N * (3 * 3 * 4 + 9 + 6)
-        wterm = N * NS * 2                                     # dot lengths of W are counted in gemm
-        jas = N * (N - 1) * 45
-        return float(W) * (gemm + pass1 + pass2 + jas - wterm)
+        gemm = 2 * N * NS * NS                                   # one of B = C A^-1, M = X B, W = B M, one spin
+        pair1 = 3 * (3 + 9 * img) + 29 + 8 + 32                  # Gaussian with 3 derivatives, products, X, sums
+        pair2 = 3 * (3 + 5 * img) + 12                           # Gaussian gradient, W term
+        valu = N * N * (pair1 + pair2) + N * (N - 1) * 45        # both spins' (electron, centre) pairs; Jastrow
+        if mixed:
+            return {"mfma_f64": 2 * gemm, "mfma_f32": 4 * gemm, "valu": valu}
+        return {"mfma_f64": 6 * gemm, "valu": valu}
     if cls == "sweep_half":
-        per_move = 2 * N * NS + 2 * NS + N * 9 * 6 + (N - 1) * 2 * 16 + 0.5 * 2 * NS * NS
-        return float(W) * NS * per_move
+        mfma = 2 * NS * N * NS + 2 * NS ** 3 + 2 * NS ** 3       # M' = Phi' C, P = M' A^-1, rank-16 updates
+        per_move = N * (3 * (3 + 2 * img) + 2) + 2 * (N - 1) * 16 + 2 * 0.58 * 7.5 * 2 * NS
+        return {"mfma_f64": mfma, "valu": NS * per_move}
     if cls == "ewald_sample":
-        recip = nk * N * 8 + (N * N) // 3 * 6
-        real = (N * (N - 1) // 2) * 15 + N * N * 30
-        return float(W) * (recip + real)
-    return 0.0
+        recip = nk * N * 8 + nslot * N * 6
+        real = (N * (N - 1) // 2) * 30 + N * N * 40
+        return {"valu": recip + real}
+    if cls == "refine":
+        return {"mfma_f64": 4 * NS ** 3}
+    return {}
+
+
+def roofline_numbers(parts: dict, walkers: int, avg_s: float):
+    """Achieved TFLOP/s of a launch and the peak it is measured against: the
+    time-weighted combination of the unit peaks, sum(f) / sum(f_u / peak_u)."""
+    total = sum(parts.values()) * walkers
+    t_peak = sum(f * walkers / (PEAK[u] * 1e12) for u, f in parts.items())
+    achieved = total / avg_s / 1e12 if avg_s > 0 else 0.0
+    peak = total / t_peak / 1e12 if t_peak > 0 else PEAK["valu"]
+    return total, achieved, peak
 
 
 def kernel_source_hash() -> str:
@@ -167,20 +184,21 @@ def main():
     out_h = out.cpu().numpy()
 
     value = W * M * args.steps / elapsed
-    nk = traj_nk = None
-    # number of half-space k vectors (for the Ewald flop count)
     nm = sysd.ewald_nmax
-    nk = sum(1 for nx in range(0, nm + 1) for ny in range(-nm, nm + 1) for nz in range(-nm, nm + 1)
-             if 0 < nx * nx + ny * ny + nz * nz <= nm * nm and (nx > 0 or (nx == 0 and (ny > 0 or (ny == 0 and nz > 0)))))
+    kset = [(nx, ny, nz) for nx in range(0, nm + 1) for ny in range(-nm, nm + 1) for nz in range(-nm, nm + 1)
+            if 0 < nx * nx + ny * ny + nz * nz <= nm * nm and (nx > 0 or (nx == 0 and (ny > 0 or (ny == 0 and nz > 0))))]
+    nk, nslot = len(kset), len({(ny, nz) for _, ny, nz in kset})
+    nimg = int(not (prec == vmc.VMC_MIXED and float(np.min(wl.zeta)) * (wl.L / 2) ** 2 >= 23.0))
     dom = max(times.items(), key=lambda kv: kv[1][0])
     dom_name, (dom_ms, dom_n) = dom[0], dom[1]
-    flops = algorithmic_flops(dom_name, N, W, nk)
+    parts = work_model(dom_name, N, nk, nslot, nimg, prec == vmc.VMC_MIXED)
     avg_s = dom_ms / max(dom_n, 1) / 1e3
-    achieved = flops / avg_s / 1e12 if avg_s > 0 else 0.0
-    peak = PEAK_FP64_TFLOPS
-    roofline = {"bound": "alu", "kernel": dom_name, "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom_name),
-                "avg_launch_ms": round(avg_s * 1e3, 4), "algorithmic_flop_per_launch": flops}
+    flops, achieved, peak = roofline_numbers(parts, W, avg_s)
+    roofline = {"bound": "alu", "kernel": dom_name, "achieved": round(achieved, 3), "peak": round(peak, 2),
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4) if peak else None,
+                "traffic": measured_traffic(dom_name), "avg_launch_ms": round(avg_s * 1e3, 4),
+                "algorithmic_flop_per_launch": flops,
+                "flop_per_walker_by_unit": {u: round(f) for u, f in parts.items()}}
     if args.profile:
         for kname, (ms, n) in sorted(times.items(), key=lambda kv: -kv[1][0]):
             print(f"{kname:16s} {ms:10.2f} ms  {n:6d} launches  {ms / max(n, 1):9.4f} ms/launch", file=sys.stderr)

@@ -12,11 +12,18 @@ def test_multi_gpu_request_exits_with_message():
     assert "one GPU" in r.stderr
 
 
-def test_flop_model_scales_with_walkers():
+def test_work_model_and_effective_peak():
     sys.path.insert(0, ROOT)
     import bench
-    a = bench.algorithmic_flops("slater_sample", 128, 1, 1535)
-    b = bench.algorithmic_flops("slater_sample", 128, 16384, 1535)
-    assert b == 16384 * a
-    # the three contractions alone: 3 x 2 x (2 N NS^2) flops per walker and sample
-    assert a > 3 * 2 * 2 * 128 * 64 * 64
+    mixed = bench.work_model("slater_sample", 128, 1527, 253, 0, True)
+    fp64 = bench.work_model("slater_sample", 128, 1527, 253, 1, False)
+    gemm = 2 * 128 * 64 * 64
+    # the three contractions of both spins: 6 x (2 N NS^2) flops per walker and sample
+    assert mixed["mfma_f64"] + mixed["mfma_f32"] == 6 * gemm == fp64["mfma_f64"]
+    assert fp64["valu"] > mixed["valu"]          # three Gaussian images per axis instead of one
+    tot1, _, pk = bench.roofline_numbers(mixed, 1, 1e-3)
+    tot2, ach, pk2 = bench.roofline_numbers(mixed, 16384, 1e-3)
+    assert tot2 == 16384 * tot1 and pk == pk2
+    assert bench.PEAK["valu"] < pk < bench.PEAK["mfma_f32"]
+    # the sweep's matrix-core work: M' = Phi' C, P = M' A^-1 and the rank-16 updates, 4 N NS^2
+    assert bench.work_model("sweep_half", 128, 1527, 253, 0, True)["mfma_f64"] == 4 * 128 * 64 * 64
