@@ -165,6 +165,68 @@ int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R_dev, c
  * R, zeta: host (3N, N); C_out: host N x N/2. */
 int vmc_huckel_params(int n_protons, double box_L, const double* R, const double* zeta, double* C_out);
 
+/* ---------------------------------------------------------------- serving --
+ * Many independent trajectories (different N, r_s, T, walker counts) on one context,
+ * with continuous batching: requests are admitted as HBM budget frees up, walker and
+ * S state stay resident on the device between Langevin steps, and each tick runs
+ * one sweep of every resident trajectory, trajectories of equal (N, precision,
+ * Gaussian images, Ewald cut-off) sharing one launch per kernel.  A trajectory's
+ * step is the same sequence as vmc_energy_forces (n_equil then n_sweeps sweeps),
+ * vmc_build_S and vmc_langevin_step (S_prev = S and R_prev = R at its first step),
+ * with C from vmc_huckel_params at its current R, so its results do not depend on
+ * what else is being served.  Host pointers in a request are read during
+ * vmc_server_submit only.  A server drives its context's stream; do not use the
+ * context for anything else between ticks. */
+typedef struct vmc_server vmc_server;
+
+typedef struct {
+  vmc_system sys;
+  int n_walkers;        /* W >= 2 */
+  int n_equil_first;    /* sweeps before the first measured sweep of the first step */
+  int n_equil;          /* re-equilibration sweeps of every later step */
+  int n_sweeps;         /* measured sweeps per step (M) */
+  int n_steps;          /* Langevin steps to run */
+  double step_delta;    /* electron move size */
+  double T, Delta, alpha;   /* Langevin temperature (Ha), time step, alpha (vmc_langevin_step) */
+  unsigned flags;       /* VMC_STEP_* */
+  uint32_t seed, traj_id;
+  const double* R0;     /* host, 3N initial proton positions */
+  const double* zeta;   /* host, N Gaussian exponents */
+  const double* pos0;   /* host, W x N x 3 initial electron positions */
+} vmc_request;
+
+enum { VMC_REQ_QUEUED = 0, VMC_REQ_RUNNING = 1, VMC_REQ_DONE = 2, VMC_REQ_FAILED = 3, VMC_REQ_CANCELLED = 4 };
+
+/* Device bytes a request holds while resident (0 if the request is invalid). */
+size_t vmc_request_bytes(const vmc_request* req);
+/* Admission rule (host only): how many requests at the head of a queue with these
+ * byte counts are admitted, first come first served, without overtaking. */
+int vmc_server_admit_count(size_t budget, size_t resident, int n_queued, const size_t* bytes);
+int vmc_server_create(vmc_ctx* ctx, size_t hbm_budget_bytes, vmc_server** out);
+/* Waits for the context stream, then frees every trajectory and the server. */
+void vmc_server_destroy(vmc_server* srv);
+/* Queues a request (inputs copied).  VMC_EINVAL if invalid (including W <= 3N
+ * without VMC_STEP_CFOLD: S of W walker means would be singular), VMC_ENOMEM if it
+ * can never fit the budget.  *id_out identifies it in the calls below. */
+int vmc_server_submit(vmc_server* srv, const vmc_request* req, int* id_out);
+/* Removes a queued request, or stops a running one and frees its memory (waits for
+ * the stream). */
+int vmc_server_cancel(vmc_server* srv, int id);
+/* Collects finished steps, admits, sets up the trajectories that start a step and
+ * queues one sweep of every resident trajectory (returns without waiting for it). */
+int vmc_server_tick(vmc_server* srv, int* n_active, int* n_queued);
+/* state: VMC_REQ_*; error: the VMC_E* code of a failed request (singular matrix,
+ * S not positive definite, ...); a failure affects that request only. */
+int vmc_server_status(vmc_server* srv, int id, int* state, int* steps_done, int* error);
+/* Host outputs (any may be NULL): R after the completed steps (3N), E and sigma_E
+ * of every completed step, each step's latency in ms (from the step becoming
+ * runnable: admission or the previous step's end, to its result being on the host),
+ * and the queue wait (submit to admission, ms; -1 while queued). */
+int vmc_server_result(vmc_server* srv, int id, double* R_out, double* E_out, double* sigma_out, double* latency_ms,
+                      double* wait_ms);
+int vmc_server_info(vmc_server* srv, size_t* resident, size_t* peak_resident, int* n_active, int* n_queued,
+                    long long* ticks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,15 +38,23 @@ __device__ __forceinline__ double block_sum256(double v, double* scratch4) {
 // ------------------------------------------------------------- Ewald ---
 constexpr int NMAXC = 12;   // largest supported ewald_nmax
 
-template <int N, class Real, int NMX>
-__global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e) {
+template <int N, class Real, int NMX, bool BATCH>
+__global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e, Batch bt) {
   extern __shared__ __align__(16) unsigned char smem[];
+  int bblk = 0;
+  if constexpr (BATCH) {
+    const int j = batch_job(bt, blockIdx.x);
+    m = bt.jobs[j].m;
+    e = bt.jobs[j].e;
+    bblk = (int)blockIdx.x - bt.off[j];
+  }
+  const int blk = BATCH ? bblk : (int)blockIdx.x;
   double* pe = reinterpret_cast<double*>(smem);   // N x 3 electrons
   double* pp = pe + 3 * N;                         // N x 3 protons
   double* part = pp + 3 * N;                       // 4 x N x 3 partial e-p gradients
   double2* ph = reinterpret_cast<double2*>(part + 12 * N);   // 3 x N x (nmax+1) phase powers
   __shared__ double red[4];
-  const int t = threadIdx.x, w = blockIdx.x;
+  const int t = threadIdx.x, w = blk;
   const int NP1 = e.nmax + 1;
   const double L = m.L, invL = m.invL;
   for (int u = t; u < 3 * N; u += 256) {
@@ -218,7 +226,7 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
               (part[(2 * N + b) * 3 + c] + part[(3 * N + b) * 3 + c]);
   }
   const double vtot = block_sum256(vrec + vreal, red);
-  if (t == 0) m.Vs[w] = vtot + e.Vconst;
+  if (t == 0) m.Vs[w] = vtot + (*e.Vpp + e.Vself);
 }
 
 // ------------------------------------------------- Slater and Jastrow ---
@@ -278,8 +286,8 @@ struct SlaterLds {
   static constexpr size_t bytes = pad(head) + pad(bs) + xm;
 };
 
-template <int NS, class Real, int NIMG>
-__global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sample(MeasureArgs m) {
+template <int NS, class Real, int NIMG, bool BATCH>
+__global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sample(MeasureArgs m, Batch bt) {
   using Lay = SlaterLds<NS, Real>;
   constexpr int N = 2 * NS;
   constexpr int NSP = Lay::NSP, NP = Lay::NP;
@@ -291,6 +299,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
   constexpr int TPW_B = (TA * TI + 3) / 4;        // N x NS outputs per wave
   constexpr int TPW_M = (TI * TI + 3) / 4;        // NS x NS outputs per wave
   extern __shared__ __align__(16) unsigned char smem[];
+  if constexpr (BATCH) m = bt.jobs[batch_job(bt, blockIdx.x)].m;
   double* pos = reinterpret_cast<double*>(smem);     // N x 3
   double* gU = pos + 3 * N;                            // N x 3
   double* lU = gU + 3 * N;                             // N
@@ -300,10 +309,14 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
   Real* Xr = reinterpret_cast<Real*>(xmb);             // NSP x LDX : X
   double* XM = reinterpret_cast<double*>(xmb);         // NSP x LDI : A^-1, then M; partial sums
   __shared__ double red[4];
-  const int t = threadIdx.x, w = blockIdx.x;
+  const int t = threadIdx.x;
+  // the walker index is re-derived from the block index at its uses (a long-lived copy costs registers)
+  auto walker = [&]() -> int {
+    return BATCH ? (int)blockIdx.x - bt.off[batch_job(bt, blockIdx.x)] : (int)blockIdx.x;
+  };
   const int lane = t & 63, wave = t >> 6, l16 = lane & 15, l4 = lane >> 4;
   const double L = m.L, invL = m.invL;
-  for (int u = t; u < 3 * N; u += 256) pos[u] = m.pos[(size_t)w * 3 * N + u];
+  for (int u = t; u < 3 * N; u += 256) pos[u] = m.pos[(size_t)walker() * 3 * N + u];
   __syncthreads();
   for (int i = t; i < N; i += 256)
     for (int ax = 0; ax < 3; ++ax) {
@@ -371,7 +384,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
   const Real za = (Real)m.zeta[a];
   for (int sp = 0; sp < 2; ++sp) {
     // A^-1 of this spin into XM (NSP x LDI, zero padded)
-    const double* Bi = m.Binv + ((size_t)w * 2 + sp) * NS * NS;
+    const double* Bi = m.Binv + ((size_t)walker() * 2 + sp) * NS * NS;
     {
       constexpr int PER = (NSP * NSP + 255) / 256;   // all loads issued before the stores
       double v[PER];
@@ -562,6 +575,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
   const double Tsl = block_sum256(tsl, red);
   const double Tj = block_sum256(tj, red);
   const double Us = block_sum256(usum, red);
+  const int w = walker();
   const double EL = Tsl + Tj + m.Vs[w];
   double* acc = m.acc + (size_t)w * (2 + 9 * N);
   if (t < N) {
@@ -675,23 +689,35 @@ __global__ __launch_bounds__(256) void k_proton_const(int N, double L, EwaldArgs
 
 // ----------------------------------------------------------- launchers ---
 template <int N, class Real>
-hipError_t launch_ewald_t(const MeasureArgs& m, const EwaldArgs& e, hipStream_t st) {
+hipError_t launch_ewald_t(const MeasureArgs& m, const EwaldArgs& e, hipStream_t st, const Batch* bt, int nblk) {
   // the phase table region also holds the nk partial sums of the reciprocal combine
   const size_t tab = (size_t)3 * N * (e.nmax + 1), cmb = (size_t)e.nk;
   size_t sm = (size_t)18 * N * sizeof(double) + (tab > cmb ? tab : cmb) * sizeof(double2);
-  if (e.nmax <= 9)
-    hipLaunchKernelGGL((k_ewald_sample<N, Real, 9>), dim3(m.W), dim3(256), sm, st, m, e);
+  const Batch b = bt ? *bt : Batch{nullptr, nullptr, 0};
+  dim3 grid(bt ? nblk : m.W);
+  if (e.nmax <= 9 && bt)
+    hipLaunchKernelGGL((k_ewald_sample<N, Real, 9, true>), grid, dim3(256), sm, st, m, e, b);
+  else if (e.nmax <= 9)
+    hipLaunchKernelGGL((k_ewald_sample<N, Real, 9, false>), grid, dim3(256), sm, st, m, e, b);
+  else if (bt)
+    hipLaunchKernelGGL((k_ewald_sample<N, Real, NMAXC, true>), grid, dim3(256), sm, st, m, e, b);
   else
-    hipLaunchKernelGGL((k_ewald_sample<N, Real, NMAXC>), dim3(m.W), dim3(256), sm, st, m, e);
+    hipLaunchKernelGGL((k_ewald_sample<N, Real, NMAXC, false>), grid, dim3(256), sm, st, m, e, b);
   return hipGetLastError();
 }
 template <int NS, class Real>
-hipError_t launch_slater_t(const MeasureArgs& m, hipStream_t st) {
+hipError_t launch_slater_t(const MeasureArgs& m, hipStream_t st, const Batch* bt, int nblk) {
   size_t sm = SlaterLds<NS, Real>::bytes;
-  if (m.nimg)
-    hipLaunchKernelGGL((k_slater_sample<NS, Real, 1>), dim3(m.W), dim3(256), sm, st, m);
+  const Batch b = bt ? *bt : Batch{nullptr, nullptr, 0};
+  dim3 grid(bt ? nblk : m.W);
+  if (m.nimg && bt)
+    hipLaunchKernelGGL((k_slater_sample<NS, Real, 1, true>), grid, dim3(256), sm, st, m, b);
+  else if (m.nimg)
+    hipLaunchKernelGGL((k_slater_sample<NS, Real, 1, false>), grid, dim3(256), sm, st, m, b);
+  else if (bt)
+    hipLaunchKernelGGL((k_slater_sample<NS, Real, 0, true>), grid, dim3(256), sm, st, m, b);
   else
-    hipLaunchKernelGGL((k_slater_sample<NS, Real, 0>), dim3(m.W), dim3(256), sm, st, m);
+    hipLaunchKernelGGL((k_slater_sample<NS, Real, 0, false>), grid, dim3(256), sm, st, m, b);
   return hipGetLastError();
 }
 
@@ -705,20 +731,26 @@ hipError_t launch_slater_t(const MeasureArgs& m, hipStream_t st) {
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_ewald_sample(const MeasureArgs& m, const EwaldArgs& e, int mixed, hipStream_t st) {
+hipError_t launch_ewald_sample(const MeasureArgs& m, const EwaldArgs& e, int mixed, hipStream_t st, const Batch* bt,
+                               int nblk) {
   if (e.nmax > NMAXC) return hipErrorInvalidValue;
-  if (mixed) { VMC_DISPATCH_NS2(m.NS, return (launch_ewald_t<2 * NSV, float>(m, e, st))) }
-  VMC_DISPATCH_NS2(m.NS, return (launch_ewald_t<2 * NSV, double>(m, e, st)))
+  if (mixed) { VMC_DISPATCH_NS2(m.NS, return (launch_ewald_t<2 * NSV, float>(m, e, st, bt, nblk))) }
+  VMC_DISPATCH_NS2(m.NS, return (launch_ewald_t<2 * NSV, double>(m, e, st, bt, nblk)))
 }
 template <int NS>
-hipError_t launch_slater_fp64(const MeasureArgs& m, hipStream_t st) {
-  hipLaunchKernelGGL((k_slater_sample<NS, double, 1>), dim3(m.W), dim3(256), (SlaterLds<NS, double>::bytes), st, m);
+hipError_t launch_slater_fp64(const MeasureArgs& m, hipStream_t st, const Batch* bt, int nblk) {
+  const Batch b = bt ? *bt : Batch{nullptr, nullptr, 0};
+  dim3 grid(bt ? nblk : m.W);
+  if (bt)
+    hipLaunchKernelGGL((k_slater_sample<NS, double, 1, true>), grid, dim3(256), (SlaterLds<NS, double>::bytes), st, m, b);
+  else
+    hipLaunchKernelGGL((k_slater_sample<NS, double, 1, false>), grid, dim3(256), (SlaterLds<NS, double>::bytes), st, m, b);
   return hipGetLastError();
 }
-hipError_t launch_slater_sample(const MeasureArgs& m, int mixed, hipStream_t st) {
-  if (mixed) { VMC_DISPATCH_NS2(m.NS, return (launch_slater_t<NSV, float>(m, st))) }
+hipError_t launch_slater_sample(const MeasureArgs& m, int mixed, hipStream_t st, const Batch* bt, int nblk) {
+  if (mixed) { VMC_DISPATCH_NS2(m.NS, return (launch_slater_t<NSV, float>(m, st, bt, nblk))) }
   if (!m.nimg) return hipErrorInvalidValue;   // FP64 keeps every Gaussian image
-  VMC_DISPATCH_NS2(m.NS, return (launch_slater_fp64<NSV>(m, st)))
+  VMC_DISPATCH_NS2(m.NS, return (launch_slater_fp64<NSV>(m, st, bt, nblk)))
 }
 hipError_t launch_finalize(const MeasureArgs& m, const EwaldArgs& e, int M, double* means, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(m.W), dim3(256), (size_t)e.nk * 2 * sizeof(double), st, m, e, M, means);

@@ -62,13 +62,20 @@ __global__ __launch_bounds__(256) void k_build_A(WalkerArgs a) {
 // permuted: the row that pivoted column k holds row k of A^-1 with column c
 // stored at position pi(c).  ln|det A| = sum ln|pivot|, sign from the pivots
 // and the parity of pi.  A zero pivot sets *status = 1.
-template <int NS>
-__global__ __launch_bounds__(256) void k_invert(WalkerArgs a, int spin_lo, int spin_hi, int only_flagged) {
+template <int NS, bool BATCH>
+__global__ __launch_bounds__(256) void k_invert(WalkerArgs a, int spin_lo, int spin_hi, int only_flagged, Batch bt) {
   constexpr int BC = 16, NB = (NS + BC - 1) / BC;
   __shared__ double stage[4 * NS * 17];
+  int bblk = 0;
+  if constexpr (BATCH) {
+    const int j = batch_job(bt, blockIdx.x);
+    a = bt.jobs[j].a;
+    bblk = (int)blockIdx.x - bt.off[j];
+  }
+  const int blk = BATCH ? bblk : (int)blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nsp = spin_hi - spin_lo;
-  const int mat = blockIdx.x * 4 + wv;
+  const int mat = blk * 4 + wv;
   const int w = mat / nsp, sp = spin_lo + mat % nsp;
   if (w >= a.W) return;
   if (only_flagged) {
@@ -214,8 +221,8 @@ struct SweepLds {
 // Every LDS row access of the recursion is lane-private (lane = column).
 // One wave per walker; the inverse lives in matrix-core accumulator layout
 // (tile (tr, tc), element v of lane l = A^-1[16 tr + 4 v + l/16][16 tc + l%16]).
-template <int NS, class Real, int NIMG>
-__global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s) {
+template <int NS, class Real, int NIMG, bool BATCH>
+__global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s, Batch bt) {
   constexpr int N = 2 * NS;
   using LY = SweepLds<NS>;
   constexpr int NSP = LY::NSP, NT = NSP / 16, NB = (NS + 15) / 16, KC = (N + 3) / 4;
@@ -223,6 +230,15 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
   constexpr int EPL = (N + 63) / 64;
   static_assert(NS == 64 || N <= 64, "the electrons of one spin must share a slot");
   extern __shared__ __align__(16) double smem_d[];
+  int bblk = 0;
+  if constexpr (BATCH) {
+    const int j = batch_job(bt, blockIdx.x);
+    const int spin = s.spin;
+    a = bt.jobs[j].a;
+    s = bt.jobs[j].s;
+    s.spin = spin;
+    bblk = (int)blockIdx.x - bt.off[j];
+  }
   double* Rs = smem_d + 4 * LY::WAVE;     // centres x, y, z, zeta
   for (int t = threadIdx.x; t < N; t += blockDim.x) {
     Rs[4 * t] = a.R[3 * t]; Rs[4 * t + 1] = a.R[3 * t + 1]; Rs[4 * t + 2] = a.R[3 * t + 2];
@@ -231,7 +247,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, l4 = lane >> 4;
-  const int w = blockIdx.x * 4 + wv;
+  // (the block index is read at its uses: a long-lived copy costs registers here)
+  const int w = (BATCH ? bblk : (int)blockIdx.x) * 4 + wv;
   if (w >= a.W) return;
   double* MB = smem_d + (size_t)wv * LY::WAVE;
   double* PB = MB + LY::MB;
@@ -460,7 +477,9 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
     }
     wave_lds_sync();
   }
-  Bw = a.Binv + ((size_t)(blockIdx.x * 4 + wv) * 2 + sp) * NS * NS;
+  // the block's walker again from the block index (the lookup is redone rather than kept live)
+  const int blk_end = BATCH ? (int)blockIdx.x - bt.off[batch_job(bt, blockIdx.x)] : (int)blockIdx.x;
+  Bw = a.Binv + ((size_t)(blk_end * 4 + wv) * 2 + sp) * NS * NS;
 #pragma unroll
   for (int tr = 0; tr < NT; ++tr)
 #pragma unroll
@@ -488,13 +507,21 @@ struct RefineLds {
   static constexpr size_t bytes = (size_t)4 * NSP * LDX * sizeof(double);
 };
 
-template <int NS>
-__global__ __launch_bounds__(256, 1) void k_refine(WalkerArgs a, int sp, double tol) {
+template <int NS, bool BATCH>
+__global__ __launch_bounds__(256, 1) void k_refine(WalkerArgs a, int sp, double tol, Batch bt) {
   constexpr int NSP = RefineLds<NS>::NSP, NT = NSP / 16, LDX = RefineLds<NS>::LDX;
   extern __shared__ __align__(16) double smem_r[];
+  int bblk = 0;
+  if constexpr (BATCH) {
+    const int j = batch_job(bt, blockIdx.x);
+    a = bt.jobs[j].a;
+    tol = bt.jobs[j].tol;
+    bblk = (int)blockIdx.x - bt.off[j];
+  }
+  const int blk = BATCH ? bblk : (int)blockIdx.x;
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, l4 = lane >> 4;
-  const int w = blockIdx.x * 4 + wv;
+  const int w = blk * 4 + wv;
   if (w >= a.W) return;
   double* xs = smem_r + (size_t)wv * NSP * LDX;
   const size_t base = ((size_t)w * 2 + sp) * NS * NS;
@@ -582,16 +609,25 @@ hipError_t launch_build_A_t(const WalkerArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_build_A<NS, Real, 0>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
+inline Batch batch_or_none(const Batch* bt) { return bt ? *bt : Batch{nullptr, nullptr, 0}; }
+
 template <int NS>
-hipError_t launch_invert_t(const WalkerArgs& a, int spin_lo, int spin_hi, int only_flagged, hipStream_t st) {
-  dim3 grid((a.W * (spin_hi - spin_lo) + 3) / 4);
-  hipLaunchKernelGGL((k_invert<NS>), grid, dim3(256), 0, st, a, spin_lo, spin_hi, only_flagged);
+hipError_t launch_invert_t(const WalkerArgs& a, int spin_lo, int spin_hi, int only_flagged, hipStream_t st,
+                           const Batch* bt, int nblk) {
+  dim3 grid(bt ? nblk : (a.W * (spin_hi - spin_lo) + 3) / 4);
+  if (bt)
+    hipLaunchKernelGGL((k_invert<NS, true>), grid, dim3(256), 0, st, a, spin_lo, spin_hi, only_flagged, *bt);
+  else
+    hipLaunchKernelGGL((k_invert<NS, false>), grid, dim3(256), 0, st, a, spin_lo, spin_hi, only_flagged, batch_or_none(bt));
   return hipGetLastError();
 }
 template <int NS>
-hipError_t launch_refine_t(const WalkerArgs& a, int spin, double tol, hipStream_t st) {
-  dim3 grid((a.W + 3) / 4);
-  hipLaunchKernelGGL((k_refine<NS>), grid, dim3(256), RefineLds<NS>::bytes, st, a, spin, tol);
+hipError_t launch_refine_t(const WalkerArgs& a, int spin, double tol, hipStream_t st, const Batch* bt, int nblk) {
+  dim3 grid(bt ? nblk : (a.W + 3) / 4);
+  if (bt)
+    hipLaunchKernelGGL((k_refine<NS, true>), grid, dim3(256), RefineLds<NS>::bytes, st, a, spin, tol, *bt);
+  else
+    hipLaunchKernelGGL((k_refine<NS, false>), grid, dim3(256), RefineLds<NS>::bytes, st, a, spin, tol, batch_or_none(bt));
   return hipGetLastError();
 }
 template <int NS, class Real>
@@ -599,13 +635,18 @@ size_t sweep_smem() {
   return SweepLds<NS>::bytes(2 * NS);
 }
 template <int NS, class Real>
-hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t st) {
-  dim3 grid((a.W + 3) / 4);
+hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t st, const Batch* bt, int nblk) {
+  dim3 grid(bt ? nblk : (a.W + 3) / 4);
   size_t sm = sweep_smem<NS, Real>();
-  if (a.nimg || sizeof(Real) == 8)
-    hipLaunchKernelGGL((k_sweep_half<NS, Real, 1>), grid, dim3(256), sm, st, a, s);
+  const bool img = a.nimg || sizeof(Real) == 8;
+  if (bt && img)
+    hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, true>), grid, dim3(256), sm, st, a, s, *bt);
+  else if (bt)
+    hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, true>), grid, dim3(256), sm, st, a, s, *bt);
+  else if (img)
+    hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, false>), grid, dim3(256), sm, st, a, s, batch_or_none(bt));
   else
-    hipLaunchKernelGGL((k_sweep_half<NS, Real, 0>), grid, dim3(256), sm, st, a, s);
+    hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, false>), grid, dim3(256), sm, st, a, s, batch_or_none(bt));
   return hipGetLastError();
 }
 
@@ -623,15 +664,17 @@ hipError_t launch_build_A(const WalkerArgs& a, int mixed, hipStream_t st) {
   if (mixed) { VMC_DISPATCH_NS(a.NS, return (launch_build_A_t<NSV, float>(a, st))) }
   VMC_DISPATCH_NS(a.NS, return (launch_build_A_t<NSV, double>(a, st)))
 }
-hipError_t launch_invert(const WalkerArgs& a, int spin_lo, int spin_hi, int only_flagged, hipStream_t st) {
-  VMC_DISPATCH_NS(a.NS, return (launch_invert_t<NSV>(a, spin_lo, spin_hi, only_flagged, st)))
+hipError_t launch_invert(const WalkerArgs& a, int spin_lo, int spin_hi, int only_flagged, hipStream_t st,
+                         const Batch* bt, int nblk) {
+  VMC_DISPATCH_NS(a.NS, return (launch_invert_t<NSV>(a, spin_lo, spin_hi, only_flagged, st, bt, nblk)))
 }
-hipError_t launch_refine(const WalkerArgs& a, int spin, double tol, hipStream_t st) {
-  VMC_DISPATCH_NS(a.NS, return (launch_refine_t<NSV>(a, spin, tol, st)))
+hipError_t launch_refine(const WalkerArgs& a, int spin, double tol, hipStream_t st, const Batch* bt, int nblk) {
+  VMC_DISPATCH_NS(a.NS, return (launch_refine_t<NSV>(a, spin, tol, st, bt, nblk)))
 }
-hipError_t launch_sweep(const WalkerArgs& a, const SweepArgs& s, int mixed, hipStream_t st) {
-  if (mixed) { VMC_DISPATCH_NS(a.NS, return (launch_sweep_t<NSV, float>(a, s, st))) }
-  VMC_DISPATCH_NS(a.NS, return (launch_sweep_t<NSV, double>(a, s, st)))
+hipError_t launch_sweep(const WalkerArgs& a, const SweepArgs& s, int mixed, hipStream_t st, const Batch* bt,
+                        int nblk) {
+  if (mixed) { VMC_DISPATCH_NS(a.NS, return (launch_sweep_t<NSV, float>(a, s, st, bt, nblk))) }
+  VMC_DISPATCH_NS(a.NS, return (launch_sweep_t<NSV, double>(a, s, st, bt, nblk)))
 }
 
 }  // namespace vmc

@@ -41,7 +41,8 @@ struct EwaldArgs {
   const int* slot_nx0; // nslot: first nx of the slot
   const double* rho_p; // nk x 2: proton structure factor sum_b e^{i k R_b}
   const double* Ptab;  // nk x N x 2: e^{i k R_b}
-  double Vconst;       // proton-proton real-space energy + self energy of all 2N charges
+  const double* Vpp;   // device: proton-proton real-space energy (k_proton_const)
+  double Vself;        // self energy of all 2N charges, -kappa/sqrt(pi) * 2N
   const double* Fconst;// 3N: walker-independent part of dV/dR (p-p real space + rho_p part of reciprocal)
 };
 
@@ -62,13 +63,44 @@ struct MeasureArgs {
   double* rho_acc;      // W x nk x 2: sum of the electron structure factor
 };
 
-hipError_t launch_build_A(const WalkerArgs& a, int mixed, hipStream_t st);
-hipError_t launch_invert(const WalkerArgs& a, int spin_lo, int spin_hi, int only_flagged, hipStream_t st);
-hipError_t launch_refine(const WalkerArgs& a, int spin, double tol, hipStream_t st);
-hipError_t launch_sweep(const WalkerArgs& a, const SweepArgs& s, int mixed, hipStream_t st);
+// Several trajectories of one bucket (N, precision, Gaussian images, Ewald cut-off)
+// in one grid: blocks [off[j], off[j+1]) belong to jobs[j], with the kernel's usual
+// block-to-walker map inside each range.  jobs == nullptr: the launch serves the
+// trajectory passed by value.  Per-launch values (spin, fallback mode) stay those
+// passed by value.
+struct TrajJob {
+  WalkerArgs a;
+  SweepArgs s;
+  MeasureArgs m;
+  EwaldArgs e;
+  double tol;
+};
+struct Batch {
+  const TrajJob* jobs;
+  const int* off;     // njobs + 1 block offsets
+  int njobs;
+};
+__device__ __forceinline__ int batch_job(const Batch& b, int blk) {
+  int lo = 0, hi = b.njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.off[mid] <= blk) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
 
-hipError_t launch_ewald_sample(const MeasureArgs& m, const EwaldArgs& e, int mixed, hipStream_t st);
-hipError_t launch_slater_sample(const MeasureArgs& m, int mixed, hipStream_t st);
+hipError_t launch_build_A(const WalkerArgs& a, int mixed, hipStream_t st);
+hipError_t launch_invert(const WalkerArgs& a, int spin_lo, int spin_hi, int only_flagged, hipStream_t st,
+                         const Batch* bt = nullptr, int nblk = 0);
+hipError_t launch_refine(const WalkerArgs& a, int spin, double tol, hipStream_t st, const Batch* bt = nullptr,
+                         int nblk = 0);
+hipError_t launch_sweep(const WalkerArgs& a, const SweepArgs& s, int mixed, hipStream_t st, const Batch* bt = nullptr,
+                        int nblk = 0);
+
+hipError_t launch_ewald_sample(const MeasureArgs& m, const EwaldArgs& e, int mixed, hipStream_t st,
+                               const Batch* bt = nullptr, int nblk = 0);
+hipError_t launch_slater_sample(const MeasureArgs& m, int mixed, hipStream_t st, const Batch* bt = nullptr,
+                                int nblk = 0);
 hipError_t launch_finalize(const MeasureArgs& m, const EwaldArgs& e, int M, double* means, hipStream_t st);
 hipError_t launch_proton_setup(int N, double L, const double* R, EwaldArgs& e, double* rho_p, double* Ptab,
                                double* Fconst, double* Vpp, hipStream_t st);

@@ -3,10 +3,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "../../include/vmc.h"
@@ -189,16 +193,20 @@ void build_kvectors(const vmc_system& s, std::vector<double>& kv, std::vector<in
 
 // Gaussian images kept per axis: all three (n = -1, 0, 1) unless the mode is mixed and
 // every dropped image is below e^{-zeta_min (L/2)^2} <= e^{-23} (under FP32 resolution).
+int image_rule(const vmc_system& s, const double* zeta_host) {
+  if (s.precision != VMC_MIXED) return 1;
+  double zmin = zeta_host[0];
+  for (int i = 0; i < s.n_protons; ++i) zmin = std::min(zmin, zeta_host[i]);
+  const double h = 0.5 * s.box_L;
+  return (zmin * h * h >= 23.0) ? 0 : 1;
+}
 int image_count(vmc_traj* t, const double* zeta_dev, int* nimg) {
   *nimg = 1;
   if (t->sys.precision != VMC_MIXED) return VMC_OK;
   std::vector<double> z(t->N);
   HIPCHK(hipMemcpyAsync(z.data(), zeta_dev, t->N * sizeof(double), hipMemcpyDeviceToHost, t->ctx->stream));
   HIPCHK(hipStreamSynchronize(t->ctx->stream));
-  double zmin = z[0];
-  for (double v : z) zmin = std::min(zmin, v);
-  const double h = 0.5 * t->sys.box_L;
-  if (zmin * h * h >= 23.0) *nimg = 0;
+  *nimg = image_rule(t->sys, z.data());
   return VMC_OK;
 }
 
@@ -224,23 +232,19 @@ MeasureArgs measure_args(vmc_traj* t, const double* R, const double* C, const do
   return m;
 }
 
-EwaldArgs ewald_args(vmc_traj* t, double Vconst) {
+EwaldArgs ewald_args(vmc_traj* t) {
   EwaldArgs e{};
   e.nk = t->nk; e.nslot = t->nslot; e.nmax = t->sys.ewald_nmax; e.kappa = t->sys.ewald_kappa;
   e.kvec = t->kvec; e.slot = t->slot; e.slot_nx0 = t->slot_nx0;
-  e.rho_p = t->rho_p; e.Ptab = t->Ptab; e.Vconst = Vconst; e.Fconst = t->Fconst;
+  e.rho_p = t->rho_p; e.Ptab = t->Ptab; e.Vpp = t->Vpp; e.Vself = t->Vself; e.Fconst = t->Fconst;
   return e;
 }
 
-// Proton-only Ewald quantities at R: rho_p, e^{ikR}, constant gradient, V_pp.
-int proton_setup(vmc_traj* t, const double* R, double* Vconst) {
+// Proton-only Ewald quantities at R: rho_p, e^{ikR}, constant gradient, V_pp (all on the device).
+int proton_setup(vmc_traj* t, const double* R) {
   vmc_ctx* ctx = t->ctx;
-  EwaldArgs e = ewald_args(t, 0.0);
+  EwaldArgs e = ewald_args(t);
   RUN(K_SETUP, launch_proton_setup(t->N, t->sys.box_L, R, e, t->rho_p, t->Ptab, t->Fconst, t->Vpp, ctx->stream));
-  double vpp = 0.0;
-  HIPCHK(hipMemcpyAsync(&vpp, t->Vpp, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  *Vconst = vpp + t->Vself;
   return VMC_OK;
 }
 
@@ -410,8 +414,7 @@ int vmc_energy_forces(vmc_traj* t, const double* R, const double* C, const doubl
   hipStream_t st = ctx->stream;
   const int mixed = t->sys.precision == VMC_MIXED;
   const size_t N = t->N, n3 = 3 * N, W = t->W;
-  double Vconst = 0.0;
-  int rc = proton_setup(t, R, &Vconst);
+  int rc = proton_setup(t, R);
   if (rc) return rc;
   int nimg = 1;
   rc = image_count(t, zeta, &nimg);
@@ -423,7 +426,7 @@ int vmc_energy_forces(vmc_traj* t, const double* R, const double* C, const doubl
   HIPCHK(hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
   WalkerArgs a = walker_args(t, R, C, zeta, nimg);
   MeasureArgs m = measure_args(t, R, C, zeta, nimg);
-  EwaldArgs e = ewald_args(t, Vconst);
+  EwaldArgs e = ewald_args(t);
   RUN(K_BUILD_A, launch_build_A(a, mixed, st));
   const double rtol = t->sys.refine_tol == 0.0 ? 1e-7 : t->sys.refine_tol;
   const int total = n_equil + n_sweeps;
@@ -525,10 +528,9 @@ int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R, const
   hipStream_t st = ctx->stream;
   const int mixed = t->sys.precision == VMC_MIXED;
   const size_t N = t->N;
-  double Vconst = 0.0;
   int nimg = 1;
   rc = vmc_traj_set_walkers(t, pos);
-  if (!rc) rc = proton_setup(t, R, &Vconst);
+  if (!rc) rc = proton_setup(t, R);
   if (!rc) rc = image_count(t, zeta, &nimg);
   if (!rc) {
     auto body = [&]() -> int {
@@ -537,7 +539,7 @@ int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R, const
       HIPCHK(hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
       WalkerArgs a = walker_args(t, R, C, zeta, nimg);
       MeasureArgs m = measure_args(t, R, C, zeta, nimg);
-      EwaldArgs e = ewald_args(t, Vconst);
+      EwaldArgs e = ewald_args(t);
       RUN(K_BUILD_A, launch_build_A(a, mixed, st));
       RUN(K_INVERT, launch_invert(a, 0, 2, 0, st));
       int r2 = measure(t, m, e);
@@ -676,6 +678,544 @@ int vmc_huckel_params(int n, double L, const double* R, const double* zeta, doub
   for (int k = 0; k < no; ++k)
     for (int a = 0; a < n; ++a)
       C_out[(size_t)a * no + k] = Q[(size_t)a * n + order[k]] / std::sqrt(S[(size_t)a * n + a]);
+  return VMC_OK;
+}
+
+}  // extern "C"
+
+// ==================================================================== serving ==
+// Continuous batching of independent trajectories on one context stream.  A tick
+// admits queued requests while the HBM budget allows (FIFO, no overtaking), runs
+// the set-up of every trajectory that starts a Langevin step (host Hueckel at its
+// current R, proton tables, Slater rows, elimination), then one sweep for every
+// sweeping trajectory: per bucket of equal (N, precision, Gaussian images, Ewald
+// cut-off) one launch per kernel serves all of them (job tables, see Batch), and a
+// trajectory whose last sweep this was gets its reduction, S, Langevin update and
+// an asynchronous copy of the new R and E to pinned host memory.  The host polls
+// that copy's event at later ticks, so no trajectory waits on another.  Every
+// walker computes in a batched launch exactly what it computes alone.
+
+namespace {
+
+enum { SV_QUEUED = 0, SV_RUNNING = 1, SV_DONE = 2, SV_FAILED = 3, SV_CANCELLED = 4 };
+enum { PH_SETUP = 0, PH_SWEEP = 1, PH_WAIT = 2 };
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Served {
+  int id = 0;
+  vmc_request req{};
+  std::vector<double> R0, zeta, pos0, Rh;
+  size_t bytes = 0;
+  int state = SV_QUEUED, phase = PH_SETUP, err = VMC_OK;
+  vmc_traj* t = nullptr;
+  double *R = nullptr, *R_prev = nullptr, *S = nullptr, *S_prev = nullptr, *C = nullptr, *zeta_d = nullptr;
+  int* status = nullptr;       // [0]: a refresh hit a zero pivot, [1]: the Langevin update failed (3 = S not SPD)
+  double* hbuf = nullptr;      // pinned: R (3N), E, sigma_E, the two status words
+  double* hC = nullptr;        // pinned: C staging (N x N/2)
+  hipEvent_t done = nullptr;
+  int nimg = 1, steps_done = 0, sweep = 0, n_equil_cur = 0;
+  double t_submit = 0, t_admit = 0, t_step = 0;
+  std::vector<double> E, sigE, lat;
+};
+
+struct BucketKey {
+  int n, prec, nimg, nmax;
+  bool operator<(const BucketKey& o) const {
+    return std::tie(n, prec, nimg, nmax) < std::tie(o.n, o.prec, o.nimg, o.nmax);
+  }
+};
+
+// Device bytes a request holds while resident: the trajectory's walker state and
+// Ewald tables (as vmc_traj_create allocates them) plus the server's R, R_prev, S,
+// S_prev, C, zeta and status.
+size_t request_bytes(const vmc_system& s, int W) {
+  std::vector<double> kv;
+  std::vector<int> slots, nx0;
+  build_kvectors(s, kv, slots, nx0);
+  const size_t N = s.n_protons, NS = N / 2, n3 = 3 * N, nk = kv.size() / 4, Wz = W;
+  size_t d = Wz * N * 3 + 2 * Wz * 2 * NS * NS + 2 * Wz * 2 + Wz * (2 + 9 * N) + Wz * nk * 2 + Wz + Wz * n3 + Wz +
+             Wz * (1 + 3 * n3) + Wz * n3 + reduce_partial_doubles(W, (int)n3) + 3 + n3 + kv.size() + 2 * nk +
+             nk * N * 2 + n3 + 1;
+  d += 2 * n3 + 2 * n3 * n3 + N * NS + N;                     // R, R_prev, S, S_prev, C, zeta
+  size_t b = d * sizeof(double) + Wz * sizeof(int64_t) + Wz * 2 * sizeof(int) +
+             (slots.size() + nx0.size() + 1) * sizeof(int);
+  return b;
+}
+
+// Number of queue-head requests admitted: FIFO while the running total fits.
+int admit_count(size_t budget, size_t resident, int n, const size_t* bytes) {
+  int k = 0;
+  for (; k < n; ++k) {
+    if (resident + bytes[k] > budget) break;
+    resident += bytes[k];
+  }
+  return k;
+}
+
+}  // namespace
+
+struct vmc_server {
+  vmc_ctx* ctx = nullptr;
+  size_t budget = 0, resident = 0, peak = 0;
+  int next_id = 1;
+  std::deque<Served*> queue;
+  std::vector<Served*> active;
+  std::map<int, Served*> all;
+  // job tables: ring of pinned host buffers and device buffers, one per tick in flight
+  static constexpr int RING = 4;
+  unsigned char* htab[RING] = {nullptr};
+  unsigned char* dtab[RING] = {nullptr};
+  size_t tab_cap = 0;
+  hipEvent_t tab_ev[RING] = {nullptr};
+  bool tab_used[RING] = {false};
+  int ring = 0;
+  long long ticks = 0;
+};
+
+namespace {
+
+void release(vmc_server* s, Served* q) {
+  if (q->t) {
+    vmc_traj_destroy(q->t);
+    q->t = nullptr;
+    s->resident -= q->bytes;
+  }
+  double** ds[] = {&q->R, &q->R_prev, &q->S, &q->S_prev, &q->C, &q->zeta_d};
+  for (double** p : ds)
+    if (*p) { (void)hipFree(*p); *p = nullptr; }
+  if (q->status) { (void)hipFree(q->status); q->status = nullptr; }
+  if (q->hbuf) { (void)hipHostFree(q->hbuf); q->hbuf = nullptr; }
+  if (q->hC) { (void)hipHostFree(q->hC); q->hC = nullptr; }
+  if (q->done) { (void)hipEventDestroy(q->done); q->done = nullptr; }
+}
+
+int ensure_workspaces(vmc_ctx* ctx, int W, int n3) {
+  const size_t need_s = syrk_partial_doubles(W, n3);
+  if (ctx->syrk_work_n < need_s || ctx->lang_work_n < (size_t)n3 * n3)
+    HIPCHK(hipStreamSynchronize(ctx->stream));       // queued kernels may still use the old buffers
+  if (ctx->syrk_work_n < need_s) {
+    if (ctx->syrk_work) (void)hipFree(ctx->syrk_work);
+    ctx->syrk_work = nullptr;
+    ctx->syrk_work_n = 0;
+    if (dalloc(&ctx->syrk_work, need_s)) return VMC_ENOMEM;
+    ctx->syrk_work_n = need_s;
+  }
+  const size_t need_l = (size_t)n3 * n3;
+  if (ctx->lang_work_n < need_l) {
+    if (ctx->lang_work) (void)hipFree(ctx->lang_work);
+    ctx->lang_work = nullptr;
+    ctx->lang_work_n = 0;
+    if (dalloc(&ctx->lang_work, need_l)) return VMC_ENOMEM;
+    ctx->lang_work_n = need_l;
+  }
+  return VMC_OK;
+}
+
+// Allocates and fills a trajectory's device state (admission).
+int admit(vmc_server* s, Served* q) {
+  vmc_ctx* ctx = s->ctx;
+  const vmc_request& r = q->req;
+  const int N = r.sys.n_protons, NS = N / 2, n3 = 3 * N;
+  int rc = vmc_traj_create(ctx, &r.sys, r.n_walkers, r.seed, r.traj_id, &q->t);
+  if (rc) return rc;
+  s->resident += q->bytes;
+  s->peak = std::max(s->peak, s->resident);
+  if (dalloc(&q->R, n3) || dalloc(&q->R_prev, n3) || dalloc(&q->S, (size_t)n3 * n3) ||
+      dalloc(&q->S_prev, (size_t)n3 * n3) || dalloc(&q->C, (size_t)N * NS) || dalloc(&q->zeta_d, N) ||
+      dalloc(&q->status, 2))
+    return VMC_ENOMEM;
+  if (hipHostMalloc((void**)&q->hbuf, (n3 + 3) * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&q->hC, (size_t)N * NS * sizeof(double)) != hipSuccess)
+    return VMC_ENOMEM;
+  if (hipEventCreateWithFlags(&q->done, hipEventDisableTiming) != hipSuccess) return VMC_EDEVICE;
+  rc = ensure_workspaces(ctx, r.n_walkers, n3);
+  if (rc) return rc;
+  hipStream_t st = ctx->stream;
+  HIPCHK(hipMemcpyAsync(q->zeta_d, q->zeta.data(), N * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(q->t->pos, q->pos0.data(), q->pos0.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(q->R, q->R0.data(), n3 * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));            // the host vectors are pageable
+  q->nimg = image_rule(r.sys, q->zeta.data());
+  q->Rh = q->R0;
+  q->state = SV_RUNNING;
+  q->phase = PH_SETUP;
+  q->t_admit = now_ms();
+  q->t_step = q->t_admit;
+  return VMC_OK;
+}
+
+// Start of a Langevin step: C at the current R, proton tables, Slater rows, elimination.
+int setup_step(vmc_server* s, Served* q) {
+  vmc_ctx* ctx = s->ctx;
+  vmc_traj* t = q->t;
+  const vmc_request& r = q->req;
+  const int N = r.sys.n_protons, NS = N / 2;
+  hipStream_t st = ctx->stream;
+  std::vector<double> Cv((size_t)N * NS);
+  int rc = vmc_huckel_params(N, r.sys.box_L, q->Rh.data(), q->zeta.data(), Cv.data());
+  if (rc) return rc;
+  std::memcpy(q->hC, Cv.data(), Cv.size() * sizeof(double));   // the previous copy from hC has completed
+  HIPCHK(hipMemcpyAsync(q->C, q->hC, Cv.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  rc = proton_setup(t, q->R);
+  if (rc) return rc;
+  const size_t W = t->W, Nz = N;
+  HIPCHK(hipMemsetAsync(t->acc, 0, W * (2 + 9 * Nz) * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(t->rho_acc, 0, W * t->nk * 2 * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(t->nacc, 0, W * sizeof(int64_t), st));
+  HIPCHK(hipMemsetAsync(t->rflag, 0, W * 2 * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(q->status, 0, 2 * sizeof(int), st));
+  WalkerArgs a = walker_args(t, q->R, q->C, q->zeta_d, q->nimg);
+  a.status = q->status;
+  RUN(K_BUILD_A, launch_build_A(a, r.sys.precision == VMC_MIXED, st));
+  RUN(K_INVERT, launch_invert(a, 0, 2, 0, st));
+  q->sweep = 0;
+  q->n_equil_cur = q->steps_done == 0 ? r.n_equil_first : r.n_equil;
+  q->phase = PH_SWEEP;
+  return VMC_OK;
+}
+
+TrajJob make_job(Served* q, int sweep) {
+  vmc_traj* t = q->t;
+  TrajJob j{};
+  j.a = walker_args(t, q->R, q->C, q->zeta_d, q->nimg);
+  j.a.status = q->status;
+  j.m = measure_args(t, q->R, q->C, q->zeta_d, q->nimg);
+  j.e = ewald_args(t);
+  j.s = SweepArgs{0, sweep, (uint32_t)q->steps_done, t->seed, t->traj_id, q->req.step_delta};
+  j.tol = q->req.sys.refine_tol == 0.0 ? 1e-7 : q->req.sys.refine_tol;
+  return j;
+}
+
+// End of a Langevin step: reduction, S, update, result copy to the host.
+int finish_step(vmc_server* s, Served* q) {
+  vmc_ctx* ctx = s->ctx;
+  vmc_traj* t = q->t;
+  const vmc_request& r = q->req;
+  const int N = r.sys.n_protons, n3 = 3 * N, W = t->W;
+  hipStream_t st = ctx->stream;
+  MeasureArgs m = measure_args(t, q->R, q->C, q->zeta_d, q->nimg);
+  EwaldArgs e = ewald_args(t);
+  const int total = q->n_equil_cur + r.n_sweeps;
+  RUN(K_FINALIZE, launch_finalize(m, e, r.n_sweeps, t->means, st));
+  RUN(K_REDUCE, launch_reduce(W, n3, t->means, t->nacc, (double)N * total, t->f_w, t->partial, t->outv, st));
+  RUN(K_SYRK, launch_syrk(W, n3, t->f_w, t->outv + 3, ctx->syrk_work, q->S, st));
+  if (q->steps_done == 0) {
+    HIPCHK(hipMemcpyAsync(q->S_prev, q->S, (size_t)n3 * n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(q->R_prev, q->R, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  RUN(K_LANGEVIN, launch_langevin(n3, r.sys.box_L, q->R, q->R_prev, q->S_prev, t->outv + 3, q->S, ctx->lang_work,
+                                  nullptr, r.T, r.Delta, r.alpha, r.flags, t->seed, t->traj_id,
+                                  (uint32_t)q->steps_done, q->status + 1, st));
+  HIPCHK(hipMemcpyAsync(q->hbuf, q->R, n3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(q->hbuf + n3, t->outv, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(q->hbuf + n3 + 2, q->status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipEventRecord(q->done, st));
+  q->phase = PH_WAIT;
+  return VMC_OK;
+}
+
+// One batched sweep of the sweeping trajectories of one bucket.
+int bucket_sweep(vmc_server* s, const std::vector<Served*>& qs) {
+  vmc_ctx* ctx = s->ctx;
+  hipStream_t st = ctx->stream;
+  const int nq = (int)qs.size();
+  // host tables: [jobs sweep | jobs refresh | jobs measure] then offsets
+  std::vector<TrajJob> js, jr, jm;
+  std::vector<int> os{0}, orf{0}, om{0};
+  for (Served* q : qs) {
+    const TrajJob j = make_job(q, q->sweep);
+    js.push_back(j);
+    os.push_back(os.back() + (q->t->W + 3) / 4);
+    if (q->sweep >= 1) { jr.push_back(j); orf.push_back(orf.back() + (q->t->W + 3) / 4); }
+    if (q->sweep >= q->n_equil_cur) { jm.push_back(j); om.push_back(om.back() + q->t->W); }
+  }
+  const size_t nj = js.size() + jr.size() + jm.size();
+  const size_t bytes_jobs = nj * sizeof(TrajJob);
+  const size_t bytes = bytes_jobs + (os.size() + orf.size() + om.size()) * sizeof(int) + 64;
+  const int k = s->ring;
+  s->ring = (s->ring + 1) % vmc_server::RING;
+  if (s->tab_used[k]) HIPCHK(hipEventSynchronize(s->tab_ev[k]));      // its previous upload has been consumed
+  if (s->tab_cap < bytes) {
+    HIPCHK(hipStreamSynchronize(st));                 // queued kernels may still read the old tables
+    for (int i = 0; i < vmc_server::RING; ++i) {
+      if (s->tab_used[i]) HIPCHK(hipEventSynchronize(s->tab_ev[i]));
+      if (s->htab[i]) (void)hipHostFree(s->htab[i]);
+      if (s->dtab[i]) (void)hipFree(s->dtab[i]);
+      s->htab[i] = s->dtab[i] = nullptr;
+      s->tab_used[i] = false;
+    }
+    const size_t cap = bytes * 2;
+    for (int i = 0; i < vmc_server::RING; ++i) {
+      if (hipHostMalloc((void**)&s->htab[i], cap) != hipSuccess) return VMC_ENOMEM;
+      if (hipMalloc((void**)&s->dtab[i], cap) != hipSuccess) return VMC_ENOMEM;
+    }
+    s->tab_cap = cap;
+  }
+  unsigned char* h = s->htab[k];
+  unsigned char* d = s->dtab[k];
+  size_t off = 0;
+  auto put = [&](const void* src, size_t n) -> size_t {
+    const size_t o = off;
+    if (n) std::memcpy(h + o, src, n);
+    off += (n + 15) / 16 * 16;
+    return o;
+  };
+  const size_t o_js = put(js.data(), js.size() * sizeof(TrajJob));
+  const size_t o_jr = put(jr.data(), jr.size() * sizeof(TrajJob));
+  const size_t o_jm = put(jm.data(), jm.size() * sizeof(TrajJob));
+  const size_t o_os = put(os.data(), os.size() * sizeof(int));
+  const size_t o_or = put(orf.data(), orf.size() * sizeof(int));
+  const size_t o_om = put(om.data(), om.size() * sizeof(int));
+  HIPCHK(hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(s->tab_ev[k], st));
+  s->tab_used[k] = true;
+  const Batch bsw{(const TrajJob*)(d + o_js), (const int*)(d + o_os), (int)js.size()};
+  const Batch brf{(const TrajJob*)(d + o_jr), (const int*)(d + o_or), (int)jr.size()};
+  const Batch bms{(const TrajJob*)(d + o_jm), (const int*)(d + o_om), (int)jm.size()};
+  const int mixed = qs[0]->req.sys.precision == VMC_MIXED;
+  const TrajJob& j0 = js[0];
+  for (int sp = 0; sp < 2; ++sp) {
+    if (!jr.empty()) {
+      RUN(K_REFINE, launch_refine(j0.a, sp, j0.tol, st, &brf, orf.back()));
+      RUN(K_INVERT, launch_invert(j0.a, sp, sp + 1, 1, st, &brf, orf.back()));
+    }
+    SweepArgs sa = j0.s;
+    sa.spin = sp;
+    RUN(K_SWEEP, launch_sweep(j0.a, sa, mixed, st, &bsw, os.back()));
+  }
+  if (!jm.empty()) {
+    RUN(K_EWALD, launch_ewald_sample(jm[0].m, jm[0].e, mixed, st, &bms, om.back()));
+    RUN(K_SLATER, launch_slater_sample(jm[0].m, mixed, st, &bms, om.back()));
+  }
+  (void)nq;
+  return VMC_OK;
+}
+
+int check_request(const vmc_request* r) {
+  if (!r || check_sys(&r->sys)) return VMC_EINVAL;
+  if (r->n_walkers < 2 || r->n_sweeps < 1 || r->n_equil < 0 || r->n_equil_first < 0 || r->n_steps < 1)
+    return VMC_EINVAL;
+  if (!(r->step_delta > 0.0) || !(r->Delta > 0.0) || r->alpha < 0.0 || r->T < 0.0 || (r->flags & ~7u))
+    return VMC_EINVAL;
+  if (!r->R0 || !r->zeta || !r->pos0 || 3 * r->sys.n_protons > 1536) return VMC_EINVAL;
+  // S from W walker means has rank <= W - 1: it can be positive definite only if W > 3N
+  if (!(r->flags & VMC_STEP_CFOLD) && r->n_walkers <= 3 * r->sys.n_protons) return VMC_EINVAL;
+  return VMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vmc_request_bytes(const vmc_request* r) {
+  if (check_request(r)) return 0;
+  return request_bytes(r->sys, r->n_walkers);
+}
+
+int vmc_server_admit_count(size_t budget, size_t resident, int n_queued, const size_t* bytes) {
+  if (n_queued < 0 || (n_queued > 0 && !bytes)) return -1;
+  return admit_count(budget, resident, n_queued, bytes);
+}
+
+int vmc_server_create(vmc_ctx* ctx, size_t hbm_budget_bytes, vmc_server** out) {
+  if (!ctx || !out || hbm_budget_bytes == 0) return VMC_EINVAL;
+  vmc_server* s = new (std::nothrow) vmc_server();
+  if (!s) return VMC_ENOMEM;
+  s->ctx = ctx;
+  s->budget = hbm_budget_bytes;
+  for (int i = 0; i < vmc_server::RING; ++i)
+    if (hipEventCreateWithFlags(&s->tab_ev[i], hipEventDisableTiming) != hipSuccess) {
+      vmc_server_destroy(s);
+      return VMC_EDEVICE;
+    }
+  *out = s;
+  return VMC_OK;
+}
+
+void vmc_server_destroy(vmc_server* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->ctx->stream);
+  for (auto& kv : s->all) {
+    release(s, kv.second);
+    delete kv.second;
+  }
+  for (int i = 0; i < vmc_server::RING; ++i) {
+    if (s->htab[i]) (void)hipHostFree(s->htab[i]);
+    if (s->dtab[i]) (void)hipFree(s->dtab[i]);
+    if (s->tab_ev[i]) (void)hipEventDestroy(s->tab_ev[i]);
+  }
+  delete s;
+}
+
+int vmc_server_submit(vmc_server* s, const vmc_request* r, int* id_out) {
+  if (!s || !id_out) return VMC_EINVAL;
+  int rc = check_request(r);
+  if (rc) return rc;
+  const size_t b = request_bytes(r->sys, r->n_walkers);
+  if (b > s->budget) return VMC_ENOMEM;
+  Served* q = new (std::nothrow) Served();
+  if (!q) return VMC_ENOMEM;
+  const int N = r->sys.n_protons;
+  q->id = s->next_id++;
+  q->req = *r;
+  q->R0.assign(r->R0, r->R0 + 3 * N);
+  q->zeta.assign(r->zeta, r->zeta + N);
+  q->pos0.assign(r->pos0, r->pos0 + (size_t)r->n_walkers * N * 3);
+  q->req.R0 = q->req.zeta = q->req.pos0 = nullptr;
+  q->req.sys.refine_tol = r->sys.refine_tol;
+  q->bytes = b;
+  q->t_submit = now_ms();
+  s->queue.push_back(q);
+  s->all[q->id] = q;
+  *id_out = q->id;
+  return VMC_OK;
+}
+
+int vmc_server_cancel(vmc_server* s, int id) {
+  if (!s) return VMC_EINVAL;
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return VMC_EINVAL;
+  Served* q = it->second;
+  if (q->state == SV_QUEUED) {
+    s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), q), s->queue.end());
+    q->state = SV_CANCELLED;
+  } else if (q->state == SV_RUNNING) {
+    HIPCHK(hipStreamSynchronize(s->ctx->stream));   // its queued work finishes before its memory goes
+    s->active.erase(std::remove(s->active.begin(), s->active.end(), q), s->active.end());
+    release(s, q);
+    q->state = SV_CANCELLED;
+  }
+  return VMC_OK;
+}
+
+int vmc_server_tick(vmc_server* s, int* n_active, int* n_queued) {
+  if (!s) return VMC_EINVAL;
+  vmc_ctx* ctx = s->ctx;
+  HIPCHK(hipSetDevice(ctx->device));
+  ++s->ticks;
+  // 1. finished steps
+  for (size_t i = 0; i < s->active.size();) {
+    Served* q = s->active[i];
+    bool drop = false;
+    if (q->phase == PH_WAIT) {
+      const hipError_t e = hipEventQuery(q->done);
+      if (e == hipSuccess) {
+        const int n3 = 3 * q->req.sys.n_protons;
+        int stv[2] = {0, 0};
+        std::memcpy(stv, q->hbuf + n3 + 2, 2 * sizeof(int));
+        if (stv[0] != 0 || stv[1] != 0) {
+          q->state = SV_FAILED;
+          q->err = stv[0] ? VMC_ESINGULAR : (stv[1] == 3 ? VMC_ENOTSPD : VMC_EINVAL);
+          drop = true;
+        } else {
+          q->Rh.assign(q->hbuf, q->hbuf + n3);
+          q->E.push_back(q->hbuf[n3]);
+          q->sigE.push_back(q->hbuf[n3 + 1]);
+          q->lat.push_back(now_ms() - q->t_step);
+          q->steps_done += 1;
+          if (q->steps_done == q->req.n_steps) {
+            q->state = SV_DONE;
+            drop = true;
+          } else {
+            q->phase = PH_SETUP;
+            q->t_step = now_ms();
+          }
+        }
+      } else if (e != hipErrorNotReady) {
+        return map_err(e);
+      }
+    }
+    if (drop) {
+      release(s, q);
+      s->active.erase(s->active.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+  // 2. admission, FIFO within the budget
+  {
+    std::vector<size_t> b;
+    for (Served* q : s->queue) b.push_back(q->bytes);
+    const int k = admit_count(s->budget, s->resident, (int)b.size(), b.data());
+    for (int i = 0; i < k; ++i) {
+      Served* q = s->queue.front();
+      s->queue.pop_front();
+      const int rc = admit(s, q);
+      if (rc) {
+        q->state = SV_FAILED;
+        q->err = rc;
+        release(s, q);
+        continue;
+      }
+      s->active.push_back(q);
+    }
+  }
+  // 3. set-up of trajectories starting a step
+  for (Served* q : s->active)
+    if (q->phase == PH_SETUP) {
+      const int rc = setup_step(s, q);
+      if (rc) return rc;
+    }
+  // 4. one batched sweep per bucket, then the steps that end here
+  std::map<BucketKey, std::vector<Served*>> buckets;
+  for (Served* q : s->active)
+    if (q->phase == PH_SWEEP)
+      buckets[BucketKey{q->req.sys.n_protons, q->req.sys.precision, q->nimg, q->req.sys.ewald_nmax}].push_back(q);
+  for (auto& kv : buckets) {
+    const int rc = bucket_sweep(s, kv.second);
+    if (rc) return rc;
+    for (Served* q : kv.second) {
+      q->sweep += 1;
+      if (q->sweep == q->n_equil_cur + q->req.n_sweeps) {
+        const int r2 = finish_step(s, q);
+        if (r2) return r2;
+      }
+    }
+  }
+  if (n_active) *n_active = (int)s->active.size();
+  if (n_queued) *n_queued = (int)s->queue.size();
+  return VMC_OK;
+}
+
+int vmc_server_status(vmc_server* s, int id, int* state, int* steps_done, int* error) {
+  if (!s) return VMC_EINVAL;
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return VMC_EINVAL;
+  if (state) *state = it->second->state;
+  if (steps_done) *steps_done = it->second->steps_done;
+  if (error) *error = it->second->err;
+  return VMC_OK;
+}
+
+int vmc_server_result(vmc_server* s, int id, double* R_out, double* E_out, double* sigma_out, double* latency_ms,
+                      double* wait_ms) {
+  if (!s) return VMC_EINVAL;
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return VMC_EINVAL;
+  Served* q = it->second;
+  const int n3 = 3 * q->req.sys.n_protons, k = q->steps_done;
+  if (R_out) std::memcpy(R_out, (k ? q->Rh : q->R0).data(), n3 * sizeof(double));
+  for (int i = 0; i < k; ++i) {
+    if (E_out) E_out[i] = q->E[i];
+    if (sigma_out) sigma_out[i] = q->sigE[i];
+    if (latency_ms) latency_ms[i] = q->lat[i];
+  }
+  if (wait_ms) *wait_ms = q->t_admit > 0 ? q->t_admit - q->t_submit : -1.0;
+  return VMC_OK;
+}
+
+int vmc_server_info(vmc_server* s, size_t* resident, size_t* peak_resident, int* n_active, int* n_queued,
+                    long long* ticks) {
+  if (!s) return VMC_EINVAL;
+  if (resident) *resident = s->resident;
+  if (peak_resident) *peak_resident = s->peak;
+  if (n_active) *n_active = (int)s->active.size();
+  if (n_queued) *n_queued = (int)s->queue.size();
+  if (ticks) *ticks = s->ticks;
   return VMC_OK;
 }
 

@@ -20,7 +20,11 @@ EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_
             "vmc_set_profiling", "vmc_kernel_times", "vmc_reset_kernel_times", "vmc_traj_create",
             "vmc_traj_destroy", "vmc_traj_set_walkers", "vmc_traj_get_walkers", "vmc_energy_forces",
             "vmc_traj_walker_means", "vmc_traj_walker_forces", "vmc_traj_accepts", "vmc_build_S",
-            "vmc_build_S_raw", "vmc_langevin_step", "vmc_eval_configs", "vmc_huckel_params"]
+            "vmc_build_S_raw", "vmc_langevin_step", "vmc_eval_configs", "vmc_huckel_params",
+            "vmc_request_bytes", "vmc_server_admit_count", "vmc_server_create", "vmc_server_destroy",
+            "vmc_server_submit", "vmc_server_cancel", "vmc_server_tick", "vmc_server_status",
+            "vmc_server_result", "vmc_server_info"]
+VMC_REQ_QUEUED, VMC_REQ_RUNNING, VMC_REQ_DONE, VMC_REQ_FAILED, VMC_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
 class VMCError(RuntimeError):
@@ -33,6 +37,14 @@ class vmc_system(C.Structure):
     _fields_ = [("n_protons", C.c_int), ("box_L", C.c_double), ("ewald_kappa", C.c_double),
                 ("ewald_nmax", C.c_int), ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
                 ("precision", C.c_int), ("refine_tol", C.c_double)]
+
+
+class vmc_request(C.Structure):
+    _fields_ = [("sys", vmc_system), ("n_walkers", C.c_int), ("n_equil_first", C.c_int), ("n_equil", C.c_int),
+                ("n_sweeps", C.c_int), ("n_steps", C.c_int), ("step_delta", C.c_double), ("T", C.c_double),
+                ("Delta", C.c_double), ("alpha", C.c_double), ("flags", C.c_uint), ("seed", C.c_uint32),
+                ("traj_id", C.c_uint32), ("R0", C.POINTER(C.c_double)), ("zeta", C.POINTER(C.c_double)),
+                ("pos0", C.POINTER(C.c_double))]
 
 
 _L = None
@@ -74,6 +86,19 @@ def _declare(l):
     l.vmc_langevin_step.argtypes = [vp, i, d, vp, vp, vp, vp, vp, d, d, d, C.c_uint, u32, u32, u32]
     l.vmc_eval_configs.argtypes = [vp, P(vmc_system), vp, vp, vp, i, vp, vp]
     l.vmc_huckel_params.argtypes = [i, d, P(d), P(d), P(d)]
+    sz = C.c_size_t
+    l.vmc_request_bytes.restype = sz
+    l.vmc_request_bytes.argtypes = [P(vmc_request)]
+    l.vmc_server_admit_count.argtypes = [sz, sz, i, P(sz)]
+    l.vmc_server_create.argtypes = [vp, sz, P(vp)]
+    l.vmc_server_destroy.argtypes = [vp]
+    l.vmc_server_destroy.restype = None
+    l.vmc_server_submit.argtypes = [vp, P(vmc_request), P(i)]
+    l.vmc_server_cancel.argtypes = [vp, i]
+    l.vmc_server_tick.argtypes = [vp, P(i), P(i)]
+    l.vmc_server_status.argtypes = [vp, i, P(i), P(i), P(i)]
+    l.vmc_server_result.argtypes = [vp, i, P(d), P(d), P(d), P(d), P(d)]
+    l.vmc_server_info.argtypes = [vp, P(sz), P(sz), P(i), P(i), P(C.c_longlong)]
 
 
 def _check(rc, where):
@@ -253,3 +278,99 @@ def supported_n(n):
 
 def library_path():
     return LIB_PATH
+
+
+def _host(a, n):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    if a.size != n:
+        raise ValueError(f"expected {n} elements, got {a.size}")
+    return a
+
+
+def make_request(sysd, W, R0, zeta, pos0, n_steps, n_sweeps, T, Delta, alpha, n_equil_first=20, n_equil=5,
+                 step_delta=1.0, flags=0, seed=1, traj_id=0):
+    """A vmc_request (the arrays are kept alive on the returned object until submit)."""
+    n = sysd.n_protons
+    R0, zeta, pos0 = _host(R0, 3 * n), _host(zeta, n), _host(pos0, W * n * 3)
+    P = C.POINTER(C.c_double)
+    r = vmc_request(sysd, int(W), int(n_equil_first), int(n_equil), int(n_sweeps), int(n_steps), float(step_delta),
+                    float(T), float(Delta), float(alpha), int(flags), int(seed), int(traj_id),
+                    R0.ctypes.data_as(P), zeta.ctypes.data_as(P), pos0.ctypes.data_as(P))
+    r._keep = (R0, zeta, pos0)
+    return r
+
+
+def request_bytes(req):
+    return int(_lib().vmc_request_bytes(C.byref(req)))
+
+
+def admit_count(budget, resident, queued_bytes):
+    arr = (C.c_size_t * max(len(queued_bytes), 1))(*[int(b) for b in queued_bytes])
+    return int(_lib().vmc_server_admit_count(int(budget), int(resident), len(queued_bytes), arr))
+
+
+class Server:
+    """Continuous-batching request loop over one context (vmc_server_*)."""
+
+    def __init__(self, ctx, hbm_budget_bytes):
+        self.ctx = ctx
+        self.h = C.c_void_p()
+        _check(_lib().vmc_server_create(ctx.h, int(hbm_budget_bytes), C.byref(self.h)), "vmc_server_create")
+        self._n = {}
+
+    def submit(self, req):
+        i = C.c_int()
+        _check(_lib().vmc_server_submit(self.h, C.byref(req), C.byref(i)), "vmc_server_submit")
+        self._n[i.value] = (req.sys.n_protons, req.n_steps)
+        return i.value
+
+    def cancel(self, rid):
+        _check(_lib().vmc_server_cancel(self.h, int(rid)), "vmc_server_cancel")
+
+    def tick(self):
+        a, q = C.c_int(), C.c_int()
+        _check(_lib().vmc_server_tick(self.h, C.byref(a), C.byref(q)), "vmc_server_tick")
+        return a.value, q.value
+
+    def status(self, rid):
+        s, k, e = C.c_int(), C.c_int(), C.c_int()
+        _check(_lib().vmc_server_status(self.h, int(rid), C.byref(s), C.byref(k), C.byref(e)), "vmc_server_status")
+        return s.value, k.value, e.value
+
+    def result(self, rid):
+        import numpy as np
+        n, steps = self._n[rid]
+        R = np.zeros(3 * n)
+        E, sg, lat = np.zeros(steps), np.zeros(steps), np.zeros(steps)
+        w = C.c_double()
+        P = C.POINTER(C.c_double)
+        _check(_lib().vmc_server_result(self.h, int(rid), R.ctypes.data_as(P), E.ctypes.data_as(P),
+                                        sg.ctypes.data_as(P), lat.ctypes.data_as(P), C.byref(w)),
+               "vmc_server_result")
+        k = self.status(rid)[1]
+        return dict(R=R, E=E[:k], sigma_E=sg[:k], latency_ms=lat[:k], wait_ms=w.value)
+
+    def info(self):
+        r, p, a, q, t = C.c_size_t(), C.c_size_t(), C.c_int(), C.c_int(), C.c_longlong()
+        _check(_lib().vmc_server_info(self.h, C.byref(r), C.byref(p), C.byref(a), C.byref(q), C.byref(t)),
+               "vmc_server_info")
+        return dict(resident=r.value, peak_resident=p.value, active=a.value, queued=q.value, ticks=t.value)
+
+    def run_until_idle(self, max_ticks=10 ** 7):
+        for _ in range(max_ticks):
+            a, q = self.tick()
+            if a == 0 and q == 0:
+                return
+        raise RuntimeError("server did not drain")
+
+    def close(self):
+        if self.h:
+            _lib().vmc_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

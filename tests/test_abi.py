@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "vmc.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(vmc_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|void|size_t|const char\*)\s+(vmc_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():

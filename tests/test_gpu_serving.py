@@ -1,0 +1,168 @@
+"""Serving (vmc_server_*): a served trajectory equals the same chain through the
+single-trajectory calls, bit for bit; its results are the same alone and in a mix
+of other trajectories (different N, precision and walker counts); admission keeps
+the resident bytes within the budget; bad requests are refused at submit; a
+request can be cancelled; a failing request fails alone."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1605_08423_amd.inputs import small_system, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    from paper_1605_08423_amd import vmc
+    return torch, vmc, vmc.Context(0)
+
+
+def T(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def spec(name, W, precision, steps=2, M=4, ne1=2, ne=1, seed=5, traj=7, flags=0, Tfac=1.0):
+    wl = workload(name) if name in ("h16", "h54", "h128") else small_system(int(name[1:]), 1.35, seed=21)
+    return dict(wl=wl, W=W, precision=precision, steps=steps, M=M, ne1=ne1, ne=ne, seed=seed, traj=traj, flags=flags,
+                T=wl.T_hartree * Tfac, alpha=0.122 * W * M)
+
+
+def make_req(vmc, s):
+    wl = s["wl"]
+    sysd = vmc.make_system(wl.n, wl.L, precision=s["precision"])
+    return vmc.make_request(sysd, s["W"], wl.R, wl.zeta, wl.electrons(W=s["W"], seed_offset=s["traj"]),
+                            n_steps=s["steps"], n_sweeps=s["M"], T=s["T"], Delta=1.0 / s["alpha"],
+                            alpha=s["alpha"], n_equil_first=s["ne1"], n_equil=s["ne"], step_delta=wl.delta,
+                            flags=s["flags"], seed=s["seed"], traj_id=s["traj"])
+
+
+def serve(vmc, ctx, specs, budget=64 << 30):
+    srv = vmc.Server(ctx, budget)
+    ids = [srv.submit(make_req(vmc, s)) for s in specs]
+    srv.run_until_idle()
+    out = [(srv.status(i), srv.result(i)) for i in ids]
+    info = srv.info()
+    srv.close()
+    return out, info
+
+
+def single_path(torch, vmc, ctx, s):
+    """The same trajectory through vmc_energy_forces / vmc_build_S / vmc_langevin_step."""
+    wl = s["wl"]
+    sysd = vmc.make_system(wl.n, wl.L, precision=s["precision"])
+    tr = vmc.Trajectory(ctx, sysd, s["W"], seed=s["seed"], traj_id=s["traj"])
+    tr.set_walkers(T(torch, wl.electrons(W=s["W"], seed_offset=s["traj"])))
+    R = T(torch, wl.R.reshape(-1))
+    zeta = T(torch, wl.zeta)
+    Rp, Sp = R.clone(), None
+    Es = []
+    for k in range(s["steps"]):
+        Cm = vmc.vmc_huckel_params(R.cpu().numpy(), wl.zeta, wl.L)
+        out = tr.energy_forces(R, T(torch, Cm), zeta, s["ne1"] if k == 0 else s["ne"], s["M"], wl.delta, k)
+        S = tr.build_S()
+        if k == 0:
+            Sp = S.clone()
+            Rp.copy_(R)
+        rc = vmc.vmc_langevin_step(ctx, R, Rp, Sp, out[3:], S, s["T"], 1.0 / s["alpha"], s["alpha"], s["flags"],
+                                   s["seed"], s["traj"], k, wl.L)
+        assert rc == 0
+        Es.append(float(out[0]))
+    tr.close()
+    return R.cpu().numpy(), np.array(Es)
+
+
+@pytest.mark.parametrize("name,W,precision", [("h16", 64, 0), ("h54", 176, 1)])
+def test_served_equals_single_trajectory_calls(dev, name, W, precision):
+    torch, vmc, ctx = dev
+    s = spec(name, W, precision)
+    say(f"[served vs single] {name} W={W} precision={precision}")
+    (st, res), = serve(vmc, ctx, [s])[0]
+    assert st[0] == vmc.VMC_REQ_DONE and st[1] == s["steps"]
+    R1, E1 = single_path(torch, vmc, ctx, s)
+    assert np.array_equal(res["R"], R1)
+    assert np.array_equal(res["E"], E1)
+
+
+def test_alone_equals_in_mix(dev):
+    torch, vmc, ctx = dev
+    # W > 3N for each (S must be positive definite)
+    target = [spec("h16", 64, 0, traj=3), spec("h54", 176, 1, traj=4, steps=3)]
+    others = [spec("h32", 100, 0, traj=11), spec("h16", 80, 1, traj=12, M=6), spec("h54", 200, 1, traj=13, steps=1),
+              spec("h64", 200, 1, traj=14), spec("h16", 52, 0, traj=15, steps=3)]
+    say("[alone vs mix] 2 targets in a mix of 7 trajectories")
+    alone = [serve(vmc, ctx, [t])[0][0] for t in target]
+    mixed, info = serve(vmc, ctx, others[:3] + [target[0]] + others[3:] + [target[1]])
+    mix_t = [mixed[3], mixed[6]]
+    for (sa, ra), (sm, rm) in zip(alone, mix_t):
+        assert sa[0] == sm[0] == vmc.VMC_REQ_DONE
+        assert np.array_equal(ra["R"], rm["R"]) and np.array_equal(ra["E"], rm["E"])
+    assert all(st[0] == vmc.VMC_REQ_DONE for st, _ in mixed)
+    assert all(len(r["latency_ms"]) == s["steps"] for (st, r), s in zip(mixed, others[:3] + [target[0]] + others[3:] + [target[1]]))
+    say(f"  ticks {info['ticks']}, peak resident {info['peak_resident'] / 1e6:.1f} MB")
+
+
+def test_budget_bounds_residency(dev):
+    torch, vmc, ctx = dev
+    specs = [spec("h16", 256, 0, traj=20 + i, steps=1) for i in range(5)]
+    one = vmc.request_bytes(make_req(vmc, specs[0]))
+    budget = 2 * one + one // 2                          # two fit at a time
+    say(f"[budget] 5 requests of {one / 1e6:.2f} MB, budget {budget / 1e6:.2f} MB")
+    srv = vmc.Server(ctx, budget)
+    ids = [srv.submit(make_req(vmc, s)) for s in specs]
+    peak = 0
+    for _ in range(100000):
+        a, q = srv.tick()
+        inf = srv.info()
+        peak = max(peak, inf["resident"])
+        assert inf["resident"] <= budget and a <= 2
+        if a == 0 and q == 0:
+            break
+    assert peak == 2 * one and srv.info()["peak_resident"] == 2 * one
+    res = [srv.result(i) for i in ids]
+    assert all(srv.status(i)[0] == vmc.VMC_REQ_DONE for i in ids)
+    assert res[0]["wait_ms"] >= 0 and res[4]["wait_ms"] > res[0]["wait_ms"]
+    srv.close()
+
+
+def test_refusals_cancel_and_failure_isolation(dev):
+    torch, vmc, ctx = dev
+    say("[refusals, cancel, failure]")
+    s_ok = spec("h16", 64, 0, traj=30)
+    one = vmc.request_bytes(make_req(vmc, s_ok))
+    srv = vmc.Server(ctx, 3 * one)
+    with pytest.raises(vmc.VMCError) as e:
+        srv.submit(make_req(vmc, spec("h16", 4096, 0)))          # can never fit the budget
+    assert e.value.code == vmc.VMC_ENOMEM
+    bad = make_req(vmc, s_ok)
+    bad.n_sweeps = 0
+    with pytest.raises(vmc.VMCError) as e:
+        srv.submit(bad)
+    assert e.value.code == vmc.VMC_EINVAL
+    with pytest.raises(vmc.VMCError) as e:                      # W <= 3N: S would be singular
+        srv.submit(make_req(vmc, spec("h16", 48, 0)))
+    assert e.value.code == vmc.VMC_EINVAL
+    # noise correction with a temperature too low for it: the Langevin update fails (corrected T < 0)
+    s_fail = spec("h16", 64, 0, traj=31, flags=vmc.VMC_STEP_NOISE_CORR, Tfac=1e-9)
+    ids = [srv.submit(make_req(vmc, s)) for s in (s_ok, s_fail, spec("h16", 64, 0, traj=32), spec("h16", 64, 0, traj=33))]
+    srv.tick()
+    srv.cancel(ids[2])                                          # running
+    srv.cancel(ids[3])                                          # still queued (budget of 3)
+    srv.run_until_idle()
+    st = [srv.status(i) for i in ids]
+    survivor = srv.result(ids[0])
+    assert st[0][0] == vmc.VMC_REQ_DONE
+    assert st[1][0] == vmc.VMC_REQ_FAILED and st[1][2] == vmc.VMC_EINVAL
+    assert st[2][0] == vmc.VMC_REQ_CANCELLED and st[3][0] == vmc.VMC_REQ_CANCELLED
+    assert srv.info()["resident"] == 0
+    srv.close()
+    # the surviving request equals its run alone
+    (sa, ra), = serve(vmc, ctx, [s_ok])[0]
+    assert np.array_equal(ra["R"], survivor["R"]) and np.array_equal(ra["E"], survivor["E"])
