@@ -97,6 +97,87 @@ def run_cpu_baseline(wl, Cm, walkers: int, sweeps: int, threads: int):
     return walkers * sweeps / dt, dt
 
 
+SERVE_WALKERS = {16: 1024, 32: 2048, 54: 4096, 128: 16384}
+
+
+def run_serve(args):
+    """Served stream: independent trajectories with N in {16, 32, 54, 128}, r_s ~ U[1.25, 1.50],
+    T ~ U[600, 3000] K and walker counts scaling with N, arriving as a Poisson stream;
+    continuous batching on one GPU (vmc_server_*).  Prints one JSON line."""
+    import torch
+    from paper_1605_08423_amd import vmc
+    from paper_1605_08423_amd.inputs import KB_HA_PER_K, small_system
+    rng = np.random.default_rng(20240605)
+    n_req = args.serve
+    ctx = vmc.Context(0)
+    reqs, meta = [], []
+    for i in range(n_req):
+        n = int(rng.choice([16, 32, 54, 128]))
+        rs = float(rng.uniform(1.25, 1.50))
+        T_k = float(rng.uniform(600.0, 3000.0))
+        W = SERVE_WALKERS[n]
+        wl = small_system(n, rs, seed=1000 + i)
+        prec = vmc.VMC_MIXED if n == 128 else vmc.VMC_FP64
+        sysd = vmc.make_system(n, wl.L, precision=prec)
+        alpha = 0.122 * W * args.serve_sweeps
+        reqs.append(vmc.make_request(sysd, W, wl.R, wl.zeta, wl.electrons(W=W, seed_offset=i), n_steps=args.serve_steps,
+                                     n_sweeps=args.serve_sweeps, T=T_k * KB_HA_PER_K, Delta=1.0 / alpha, alpha=alpha,
+                                     n_equil_first=5, n_equil=5, step_delta=rs, seed=77, traj_id=i))
+        meta.append((n, W, prec))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, size=n_req))
+    budget = int(args.serve_budget_gb * 1e9)
+    srv = vmc.Server(ctx, budget)
+    ids = [None] * n_req
+    nxt = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < n_req and arrivals[nxt] <= now:
+            ids[nxt] = srv.submit(reqs[nxt])
+            nxt += 1
+        a, q = srv.tick()
+        if a == 0 and q == 0:
+            if nxt == n_req:
+                break
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat, waits, steps, wsweeps, failed = [], [], 0, 0, 0
+    by_n = {}
+    for i, rid in enumerate(ids):
+        st, k, err = srv.status(rid)
+        r = srv.result(rid)
+        if st != vmc.VMC_REQ_DONE:
+            failed += 1
+        lat.extend(r["latency_ms"].tolist())
+        waits.append(r["wait_ms"])
+        steps += k
+        n, W, _ = meta[i]
+        wsweeps += k * W * (args.serve_sweeps + 5)
+        by_n.setdefault(n, []).extend(r["latency_ms"].tolist())
+    info = srv.info()
+    srv.close()
+    pct = lambda v, q: float(np.percentile(np.asarray(v), q)) if len(v) else None
+    line = {
+        "metric": "served stream: Langevin steps/s and step latency p50/p99",
+        "value": round(steps / wall, 3), "unit": "Langevin steps/s", "n_gpus": 1, "higher_is_better": True,
+        "data": "synthetic", "dtype": "f64 (N<128) / f32+f64 mixed (N=128)",
+        "config": {"workload": f"{n_req} trajectories, N in {{16,32,54,128}}, r_s~U[1.25,1.50], T~U[600,3000] K, "
+                               f"W = 1024/2048/4096/16384 by N, {args.serve_steps} Langevin steps x "
+                               f"(5 + {args.serve_sweeps}) sweeps each, Poisson arrivals at {args.serve_rate}/s",
+                   "hbm_budget_GB": args.serve_budget_gb},
+        "wall_s": round(wall, 3), "steps": steps, "failed": failed,
+        "walker_sweeps_per_s": round(wsweeps / wall, 1),
+        "step_latency_ms": {"p50": round(pct(lat, 50), 1), "p99": round(pct(lat, 99), 1)},
+        "step_latency_ms_by_N": {str(n): {"p50": round(pct(v, 50), 1), "p99": round(pct(v, 99), 1), "steps": len(v)}
+                                 for n, v in sorted(by_n.items())},
+        "queue_wait_ms": {"p50": round(pct(waits, 50), 1), "p99": round(pct(waits, 99), 1)},
+        "peak_resident_GB": round(info["peak_resident"] / 1e9, 2), "ticks": info["ticks"],
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,7 +193,19 @@ def main():
     ap.add_argument("--profile", action="store_true", help="print per-kernel times to stderr")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration) and exit")
+    ap.add_argument("--serve", type=int, default=0, metavar="K",
+                    help="served-stream benchmark of K trajectories instead of the single-trajectory step")
+    ap.add_argument("--serve-rate", type=float, default=16.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-steps", type=int, default=3)
+    ap.add_argument("--serve-sweeps", type=int, default=20)
+    ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     args = ap.parse_args()
+    if args.serve:
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only.", file=sys.stderr)
+            sys.exit(2)
+        run_serve(args)
+        return
     if args.copy_probe:
         import torch
         src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")

@@ -213,7 +213,9 @@ int vmc_server_submit(vmc_server* srv, const vmc_request* req, int* id_out);
  * the stream). */
 int vmc_server_cancel(vmc_server* srv, int id);
 /* Collects finished steps, admits, sets up the trajectories that start a step and
- * queues one sweep of every resident trajectory (returns without waiting for it). */
+ * queues sweeps of every resident trajectory (returns without waiting for them):
+ * one per tick for the bucket with the most work per sweep (sum of W N^2), up to 32
+ * for lighter buckets, in proportion. */
 int vmc_server_tick(vmc_server* srv, int* n_active, int* n_queued);
 /* state: VMC_REQ_*; error: the VMC_E* code of a failed request (singular matrix,
  * S not positive definite, ...); a failure affects that request only. */

@@ -708,7 +708,8 @@ double now_ms() {
 struct Served {
   int id = 0;
   vmc_request req{};
-  std::vector<double> R0, zeta, pos0, Rh;
+  std::vector<double> R0, zeta, Rh;
+  double* stage = nullptr;     // pinned: pos0 (W x N x 3), copied to the device at admission
   size_t bytes = 0;
   int state = SV_QUEUED, phase = PH_SETUP, err = VMC_OK;
   vmc_traj* t = nullptr;
@@ -790,6 +791,7 @@ void release(vmc_server* s, Served* q) {
   if (q->status) { (void)hipFree(q->status); q->status = nullptr; }
   if (q->hbuf) { (void)hipHostFree(q->hbuf); q->hbuf = nullptr; }
   if (q->hC) { (void)hipHostFree(q->hC); q->hC = nullptr; }
+  if (q->stage) { (void)hipHostFree(q->stage); q->stage = nullptr; }
   if (q->done) { (void)hipEventDestroy(q->done); q->done = nullptr; }
 }
 
@@ -835,10 +837,11 @@ int admit(vmc_server* s, Served* q) {
   rc = ensure_workspaces(ctx, r.n_walkers, n3);
   if (rc) return rc;
   hipStream_t st = ctx->stream;
-  HIPCHK(hipMemcpyAsync(q->zeta_d, q->zeta.data(), N * sizeof(double), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(q->t->pos, q->pos0.data(), q->pos0.size() * sizeof(double), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(q->R, q->R0.data(), n3 * sizeof(double), hipMemcpyHostToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));            // the host vectors are pageable
+  // zeta and R0 follow the electrons in the pinned staging buffer, so the copies need no wait
+  double* zs = q->stage + (size_t)r.n_walkers * N * 3;
+  HIPCHK(hipMemcpyAsync(q->t->pos, q->stage, (size_t)r.n_walkers * N * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(q->zeta_d, zs, N * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(q->R, zs + N, n3 * sizeof(double), hipMemcpyHostToDevice, st));
   q->nimg = image_rule(r.sys, q->zeta.data());
   q->Rh = q->R0;
   q->state = SV_RUNNING;
@@ -1064,7 +1067,14 @@ int vmc_server_submit(vmc_server* s, const vmc_request* r, int* id_out) {
   q->req = *r;
   q->R0.assign(r->R0, r->R0 + 3 * N);
   q->zeta.assign(r->zeta, r->zeta + N);
-  q->pos0.assign(r->pos0, r->pos0 + (size_t)r->n_walkers * N * 3);
+  const size_t npos = (size_t)r->n_walkers * N * 3;
+  if (hipHostMalloc((void**)&q->stage, (npos + 4 * N) * sizeof(double)) != hipSuccess) {
+    delete q;
+    return VMC_ENOMEM;
+  }
+  std::memcpy(q->stage, r->pos0, npos * sizeof(double));
+  std::memcpy(q->stage + npos, r->zeta, N * sizeof(double));
+  std::memcpy(q->stage + npos + N, r->R0, 3 * N * sizeof(double));
   q->req.R0 = q->req.zeta = q->req.pos0 = nullptr;
   q->req.sys.refine_tol = r->sys.refine_tol;
   q->bytes = b;
@@ -1160,20 +1170,39 @@ int vmc_server_tick(vmc_server* s, int* n_active, int* n_queued) {
       const int rc = setup_step(s, q);
       if (rc) return rc;
     }
-  // 4. one batched sweep per bucket, then the steps that end here
+  // 4. batched sweeps per bucket, then the steps that end here.  A bucket runs
+  // k = clamp(c_max / c, 1, 32) sweeps per tick, c = sum of W N^2 over its
+  // trajectories (their work per sweep), so a tick advances every bucket by about
+  // the same device time and small systems are not held to the pace of large ones.
   std::map<BucketKey, std::vector<Served*>> buckets;
   for (Served* q : s->active)
     if (q->phase == PH_SWEEP)
       buckets[BucketKey{q->req.sys.n_protons, q->req.sys.precision, q->nimg, q->req.sys.ewald_nmax}].push_back(q);
+  double cmax = 0.0;
+  std::map<BucketKey, double> cost;
   for (auto& kv : buckets) {
-    const int rc = bucket_sweep(s, kv.second);
-    if (rc) return rc;
-    for (Served* q : kv.second) {
-      q->sweep += 1;
-      if (q->sweep == q->n_equil_cur + q->req.n_sweeps) {
-        const int r2 = finish_step(s, q);
-        if (r2) return r2;
+    double c = 0.0;
+    for (Served* q : kv.second) c += (double)q->req.n_walkers * q->req.sys.n_protons * q->req.sys.n_protons;
+    cost[kv.first] = c;
+    cmax = std::max(cmax, c);
+  }
+  for (auto& kv : buckets) {
+    const int reps = (int)std::min(32.0, std::max(1.0, std::floor(cmax / cost[kv.first])));
+    std::vector<Served*> live = kv.second;
+    for (int rep = 0; rep < reps && !live.empty(); ++rep) {
+      const int rc = bucket_sweep(s, live);
+      if (rc) return rc;
+      std::vector<Served*> still;
+      for (Served* q : live) {
+        q->sweep += 1;
+        if (q->sweep == q->n_equil_cur + q->req.n_sweeps) {
+          const int r2 = finish_step(s, q);
+          if (r2) return r2;
+        } else {
+          still.push_back(q);
+        }
       }
+      live.swap(still);
     }
   }
   if (n_active) *n_active = (int)s->active.size();
