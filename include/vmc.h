@@ -69,7 +69,8 @@ typedef struct {
   double refine_tol;  /* inverse refresh after the first sweep: one Newton-Schulz step
                          X <- X + X (I - A X) in FP64, and Gauss-Jordan elimination for
                          every matrix with max|I - A X| > refine_tol (or not finite).
-                         0 = default (1e-7); < 0 = elimination for every matrix */
+                         0 = default (1e-7); < 0 = elimination for every matrix.
+                         N = 256 (128 x 128 matrices) always refreshes by elimination */
 } vmc_system;
 
 /* ---------------------------------------------------------------- context -- */
@@ -79,8 +80,9 @@ void vmc_destroy(vmc_ctx* ctx);
 /* hip_stream: a hipStream_t (NULL = null stream).  Not owned. */
 int vmc_set_stream(vmc_ctx* ctx, void* hip_stream);
 const char* vmc_strerror(int code);
-/* Largest supported N (the Slater inverse of one spin must fit one wavefront's
- * registers) and whether N is supported. */
+/* Whether N is supported: N = 2 N_sigma with N_sigma in {8, 16, 27, 32, 64, 128}.
+ * Up to N_sigma = 64 a spin's inverse is held in one wavefront's registers during a
+ * sweep; at 128 it stays in device memory. */
 int vmc_supported_n(int n_protons);
 /* Per-kernel timing with HIP events on the context stream (0 = off). */
 int vmc_set_profiling(vmc_ctx* ctx, int on);
@@ -93,7 +95,9 @@ int vmc_reset_kernel_times(vmc_ctx* ctx);
 /* Device-resident state of one trajectory: W walkers (electron positions,
  * cached Slater matrices and inverses, accumulators), the per-walker force
  * means of the last vmc_energy_forces call and the RNG key (seed, traj_id).
- * Allocates device memory (about W * (16 N^2 + 120 N) bytes + Ewald tables). */
+ * Allocates device memory (about W * (16 N^2 + 120 N) bytes + Ewald tables; at N = 256
+ * also a per-walker region for the measurement's matrix products, 323 KiB in
+ * mixed precision and 645 KiB in FP64). */
 int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int n_walkers, uint32_t seed,
                     uint32_t traj_id, vmc_traj** out);
 void vmc_traj_destroy(vmc_traj* traj);

@@ -283,8 +283,49 @@ struct SlaterLds {
   static constexpr size_t xm01 = xm0 > xm1 ? xm0 : xm1, xm23 = xm2 > xm3 ? xm2 : xm3;
   static constexpr size_t xm = xm01 > xm23 ? xm01 : xm23;
   static constexpr size_t pad(size_t v) { return (v + 15) / 16 * 16; }
-  static constexpr size_t bytes = pad(head) + pad(bs) + xm;
+  // NS > 64: B, X (later W) and M do not fit in LDS beside each other; they live in a
+  // per-walker region of device memory and LDS keeps the per-electron data and the
+  // partial sums only
+  static constexpr bool GSCR = NS > 64;
+  static constexpr size_t jpart = (size_t)((256 / N) > 0 ? (256 / N) : 1) * N * 5 * sizeof(double);
+  static constexpr size_t small = xm23 > jpart ? xm23 : jpart;
+  static constexpr size_t mreg = (size_t)NSP * LDI * sizeof(Real);
+  static constexpr size_t bytes = GSCR ? pad(head) + small : pad(head) + pad(bs) + xm;
+  static constexpr size_t scr_bytes = GSCR ? pad(bs) + pad(bs > xm0 ? bs : xm0) + pad(mreg) : 0;
 };
+
+// One wave's share of D = A B (TR x TC tiles of 16 x 16, K a multiple of 4, no padding)
+// with operands in device memory: tiles wave, wave + 4, ..., QC of them per pass over K.
+template <class Op, class Out, int TR, int TC, int K, int QC>
+__device__ __forceinline__ void wave_gemm(const Op* A, int lda, const Op* B, int ldb, Out* D, int ldd, int wave,
+                                          int l16, int l4) {
+  constexpr int TPW = (TR * TC + 3) / 4;
+  for (int q0 = 0; q0 < TPW; q0 += QC) {
+    typename MM16<Op>::acc_t acc[QC];
+#pragma unroll
+    for (int q = 0; q < QC; ++q) acc[q] = MM16<Op>::zero();
+    for (int kk = 0; kk < K / 4; ++kk) {
+      const int k = 4 * kk + l4;
+#pragma unroll
+      for (int q = 0; q < QC; ++q) {
+        const int tt = wave + 4 * (q0 + q);
+        if (q0 + q < TPW && tt < TR * TC) {
+          const int tr = tt / TC, tc = tt % TC;
+          acc[q] = MM16<Op>::step(A[(tr * 16 + l16) * lda + k], B[k * ldb + tc * 16 + l16], acc[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < QC; ++q) {
+      const int tt = wave + 4 * (q0 + q);
+      if (q0 + q < TPW && tt < TR * TC) {
+        const int tr = tt / TC, tc = tt % TC;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) D[(tr * 16 + MM16<Op>::row(l4, v)) * ldd + tc * 16 + l16] = (Out)acc[q][v];
+      }
+    }
+  }
+}
 
 template <int NS, class Real, int NIMG, bool BATCH>
 __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sample(MeasureArgs m, Batch bt) {
@@ -304,16 +345,21 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
   double* gU = pos + 3 * N;                            // N x 3
   double* lU = gU + 3 * N;                             // N
   Real* trig = reinterpret_cast<Real*>(lU + N);        // N x 6 (sin x3, cos x3)
-  Real* Bs = reinterpret_cast<Real*>(smem + Lay::pad(Lay::head));              // NP x LDB : B, later W
-  unsigned char* xmb = smem + Lay::pad(Lay::head) + Lay::pad(Lay::bs);
-  Real* Xr = reinterpret_cast<Real*>(xmb);             // NSP x LDX : X
-  double* XM = reinterpret_cast<double*>(xmb);         // NSP x LDI : A^-1, then M; partial sums
+  constexpr bool GSCR = Lay::GSCR;
   __shared__ double red[4];
   const int t = threadIdx.x;
   // the walker index is re-derived from the block index at its uses (a long-lived copy costs registers)
   auto walker = [&]() -> int {
     return BATCH ? (int)blockIdx.x - bt.off[batch_job(bt, blockIdx.x)] : (int)blockIdx.x;
   };
+  unsigned char* gsc = GSCR ? m.scr + (size_t)walker() * Lay::scr_bytes : nullptr;
+  unsigned char* lds2 = smem + Lay::pad(Lay::head);
+  Real* Bs = reinterpret_cast<Real*>(GSCR ? gsc : lds2);                          // NP x LDB : B (later W)
+  unsigned char* xmb = GSCR ? gsc + Lay::pad(Lay::bs) : lds2 + Lay::pad(Lay::bs);
+  Real* Xr = reinterpret_cast<Real*>(xmb);             // NSP x LDX : X (GSCR: later W)
+  double* XM = reinterpret_cast<double*>(xmb);         // NSP x LDI : A^-1, then M
+  double* SM = GSCR ? reinterpret_cast<double*>(lds2) : XM;   // partial sums
+  Real* Ws = GSCR ? Xr : Bs;
   const int lane = t & 63, wave = t >> 6, l16 = lane & 15, l4 = lane >> 4;
   const double L = m.L, invL = m.invL;
   for (int u = t; u < 3 * N; u += 256) pos[u] = m.pos[(size_t)walker() * 3 * N + u];
@@ -332,7 +378,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
   {
     const Real LoP = (Real)(L / VMC_PI), kf = (Real)((VMC_PI * invL) * (VMC_PI * invL));
     const Real ap = (Real)m.a_par, aa = (Real)m.a_anti, bb = (Real)m.b;
-    double* jp = XM;                                   // HJ x N x 5 partial sums
+    double* jp = SM;                                   // HJ x N x 5 partial sums
     for (int u = t; u < HJ * N; u += 256) {
       const int i = u % N, hj = u / N;
       const int j0 = hj * N / HJ, j1 = (hj + 1) * N / HJ;
@@ -385,7 +431,10 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
   for (int sp = 0; sp < 2; ++sp) {
     // A^-1 of this spin into XM (NSP x LDI, zero padded)
     const double* Bi = m.Binv + ((size_t)walker() * 2 + sp) * NS * NS;
-    {
+    if constexpr (GSCR) {
+      // B = C A^-1 with both operands read from device memory
+      wave_gemm<double, Real, TA, TI, NS, 8>(m.C, NS, Bi, NS, Bs, LDB, wave, l16, l4);
+    } else {
       constexpr int PER = (NSP * NSP + 255) / 256;   // all loads issued before the stores
       double v[PER];
 #pragma unroll
@@ -400,7 +449,6 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         const int u = t + 256 * q, k = u / NSP, j = u % NSP;
         if (u < NSP * NSP) XM[k * LDI + j] = v[q];
       }
-    }
     __syncthreads();
     // B = C A^-1 (NP x NSP) on the FP64 matrix cores -> Bs.  Wave w takes the row
     // tiles w, w + 4, ... against every column tile, so each element of C is loaded
@@ -450,6 +498,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
             for (int v = 0; v < 4; ++v) Bs[(ta * 16 + l4 + 4 * v) * LDB + tc * 16 + l16] = (Real)acc[r][tc][v];
         }
     }
+    }
     __syncthreads();
     // pass 1: basis derivatives -> X, and the terms that need only B
     if (act) {
@@ -485,7 +534,13 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
     }
     __syncthreads();
     // M = X B (NSP x NSP), K = centres; stored as Real over the inverse staging
-    Real* Mr = reinterpret_cast<Real*>(XM);
+    Real* Mr = GSCR ? reinterpret_cast<Real*>(gsc + Lay::pad(Lay::bs) + Lay::pad(Lay::bs > Lay::xm0 ? Lay::bs : Lay::xm0))
+                    : reinterpret_cast<Real*>(XM);
+    if constexpr (GSCR) {
+      wave_gemm<Real, Real, TI, TI, N, 8>(Xr, LDX, Bs, LDB, Mr, LDI, wave, l16, l4);
+      __syncthreads();
+      wave_gemm<Real, Real, TA, TI, NS, 8>(Bs, LDB, Mr, LDI, Ws, LDB, wave, l16, l4);
+    } else {
     {
       typename MM16<Real>::acc_t acc[TPW_M];
 #pragma unroll
@@ -546,6 +601,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         }
       }
     }
+    }
     __syncthreads();
     // pass 2: dT/dR_a += grad phi_a(r_i) W_ai
     if (act) {
@@ -553,7 +609,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
       for (int s = 0; s < IPT; ++s) {
         const int i = h + H * s;
         if (i >= NS) continue;
-        const double Wv = (double)Bs[a * LDB + i];
+        const double Wv = (double)Ws[a * LDB + i];
         const int e = sp * NS + i;
         Real g[3][4];
         gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e] - Ra0, L, invL), za, (Real)L, g[0]);
@@ -567,7 +623,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
     __syncthreads();
   }
   // combine the H threads of each centre in a fixed order
-  double* rr = XM;
+  double* rr = SM;
   if (act) {
     double* q = rr + ((size_t)h * N + a) * 6;
     q[0] = dln0; q[1] = dln1; q[2] = dln2; q[3] = dT0; q[4] = dT1; q[5] = dT2;
@@ -728,8 +784,14 @@ hipError_t launch_slater_t(const MeasureArgs& m, hipStream_t st, const Batch* bt
     case 27: { constexpr int NSV = 27; CALL; } \
     case 32: { constexpr int NSV = 32; CALL; } \
     case 64: { constexpr int NSV = 64; CALL; } \
+    case 128: { constexpr int NSV = 128; CALL; } \
     default: return hipErrorInvalidValue; \
   }
+
+size_t slater_scratch_bytes(int NS, int mixed) {
+  if (NS == 128) return mixed ? SlaterLds<128, float>::scr_bytes : SlaterLds<128, double>::scr_bytes;
+  return 0;
+}
 
 hipError_t launch_ewald_sample(const MeasureArgs& m, const EwaldArgs& e, int mixed, hipStream_t st, const Batch* bt,
                                int nblk) {

@@ -43,11 +43,11 @@ __global__ __launch_bounds__(256) void k_build_A(WalkerArgs a) {
     for (int c = lane; c < N; c += 64)
       phi_s[wv][c] = phi_value<Real, NIMG>(rx, ry, rz, a.R + 3 * c, (Real)a.zeta[c], a.L, a.invL);
     wave_lds_sync();
-    if (lane < NS) {
+    for (int k = lane; k < NS; k += 64) {
       double m = 0.0;
-      for (int c = 0; c < N; ++c) m += (double)phi_s[wv][c] * a.C[c * NS + lane];
+      for (int c = 0; c < N; ++c) m += (double)phi_s[wv][c] * a.C[c * NS + k];
       int sp = e / NS, i = e % NS;
-      a.Amat[(((size_t)w * 2 + sp) * NS + i) * NS + lane] = m;
+      a.Amat[(((size_t)w * 2 + sp) * NS + i) * NS + k] = m;
     }
     wave_lds_sync();
   }
@@ -180,6 +180,123 @@ __global__ __launch_bounds__(256) void k_invert(WalkerArgs a, int spin_lo, int s
   }
 }
 
+// Gauss-Jordan for NS > 64 (the register version holds one row per lane): one
+// 256-thread work-group per matrix, the matrix in LDS (row stride NS + 1).  The same
+// implicit-pivot elimination as k_invert -- pivot of column p is the unused row with
+// the largest |A[i][p]|, ties to the lowest row -- with the pivot row and the
+// multipliers staged in LDS before each rank-1 step, and the same output: row r,
+// which pivoted column myk(r), holds row myk(r) of A^-1 with column c at pi(c).
+template <int NS>
+struct InvLds {
+  static constexpr int LD = NS + 1;
+  static constexpr size_t bytes = ((size_t)NS * LD + 2 * NS) * sizeof(double);
+};
+
+template <int NS, bool BATCH>
+__global__ __launch_bounds__(256) void k_invert_lds(WalkerArgs a, int spin_lo, int spin_hi, int only_flagged,
+                                                   Batch bt) {
+  constexpr int LD = InvLds<NS>::LD;
+  extern __shared__ __align__(16) double sm_inv[];
+  double* M = sm_inv;                  // NS x LD
+  double* prow = M + (size_t)NS * LD;  // pivot row before the step
+  double* gcol = prow + NS;            // multipliers of the step
+  __shared__ int used[NS], myk[NS], pi_[NS];
+  __shared__ double wv_v[4];
+  __shared__ int wv_i[4], s_piv, s_flag;
+  __shared__ double s_pv;
+  int blk = blockIdx.x;
+  if constexpr (BATCH) {
+    const int j = batch_job(bt, blk);
+    a = bt.jobs[j].a;
+    blk -= bt.off[j];
+  }
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int nsp = spin_hi - spin_lo;
+  const int w = blk / nsp, sp = spin_lo + blk % nsp;
+  if (w >= a.W) return;
+  if (only_flagged) {
+    const int fl = a.rflag[(size_t)w * 2 + sp];
+    __syncthreads();
+    if (fl == 0) return;
+    if (t == 0) a.rflag[(size_t)w * 2 + sp] = 0;
+  }
+  const size_t base = ((size_t)w * 2 + sp) * NS * NS;
+  for (int u = t; u < NS * NS; u += 256) M[(u / NS) * LD + u % NS] = a.Amat[base + u];
+  for (int i = t; i < NS; i += 256) used[i] = 0;
+  double logdet = 0.0, sgn = 1.0;
+  __syncthreads();
+  for (int p = 0; p < NS; ++p) {
+    double bv = -1.0;
+    int bi = t;
+    if (t < NS && !used[t]) bv = fabs(M[t * LD + p]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { wv_v[wave] = bv; wv_i[wave] = bi; }
+    __syncthreads();
+    if (t == 0) {
+      double v = wv_v[0];
+      int i0 = wv_i[0];
+      for (int k = 1; k < 4; ++k)
+        if (wv_v[k] > v || (wv_v[k] == v && wv_i[k] < i0)) { v = wv_v[k]; i0 = wv_i[k]; }
+      s_piv = i0;
+      s_pv = M[i0 * LD + p];
+    }
+    __syncthreads();
+    const int piv = s_piv;
+    const double pv = s_pv;
+    if (pv == 0.0) break;                              // uniform: singular
+    if (t == 0) {
+      logdet += log(fabs(pv));
+      if (pv < 0.0) sgn = -sgn;
+      used[piv] = 1;
+      myk[piv] = p;
+      pi_[p] = piv;
+    }
+    const double pinv = 1.0 / pv;
+    for (int i = t; i < NS; i += 256) {
+      prow[i] = M[piv * LD + i];
+      const double mp = M[i * LD + p];
+      gcol[i] = (i == piv ? mp - 1.0 : mp) * pinv;
+    }
+    __syncthreads();
+    for (int u = t; u < NS * NS; u += 256) {
+      const int i = u / NS, j = u % NS;
+      const double g = gcol[i];
+      M[i * LD + j] = (j == p) ? ((i == piv ? 1.0 : 0.0) - g) : fma(-g, prow[j], M[i * LD + j]);
+    }
+    __syncthreads();
+  }
+  if (s_pv == 0.0) {
+    if (t == 0) {
+      *a.status = 1;
+      a.ldet[(size_t)w * 2 + sp] = -INFINITY;
+      a.sgn[(size_t)w * 2 + sp] = 0.0;
+    }
+    return;
+  }
+  // parity of pi: inversions counted per row, summed in a fixed order
+  int inv_cnt = 0;
+  if (t < NS)
+    for (int q = t + 1; q < NS; ++q) inv_cnt += pi_[q] < pi_[t] ? 1 : 0;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) inv_cnt += __shfl_xor(inv_cnt, off, 64);
+  if (lane == 0) wv_i[wave] = inv_cnt;
+  __syncthreads();
+  for (int u = t; u < NS * NS; u += 256) {
+    const int r = u / NS, c = u % NS;
+    a.Binv[base + (size_t)myk[r] * NS + pi_[c]] = M[r * LD + c];
+  }
+  if (t == 0) {
+    if ((wv_i[0] + wv_i[1] + wv_i[2] + wv_i[3]) & 1) sgn = -sgn;
+    a.ldet[(size_t)w * 2 + sp] = logdet;
+    a.sgn[(size_t)w * 2 + sp] = sgn;
+  }
+}
+
 // ---------------------------------------------------------- half sweep ---
 template <class T, int E>
 __device__ __forceinline__ T pick(const T (&v)[E], int s) {
@@ -187,6 +304,12 @@ __device__ __forceinline__ T pick(const T (&v)[E], int s) {
 #pragma unroll
   for (int t = 1; t < E; ++t) r = (s == t) ? v[t] : r;
   return r;
+}
+
+// Column c (wave-uniform) of a vector spread as element c / 64 of lane c % 64.
+template <int E>
+__device__ __forceinline__ double colread(const double (&v)[E], int c) {
+  return readlane_d(pick(v, c >> 6), c & 63);
 }
 
 typedef double d4w_t __attribute__((ext_vector_type(4)));
@@ -222,13 +345,18 @@ struct SweepLds {
 // One wave per walker; the inverse lives in matrix-core accumulator layout
 // (tile (tr, tc), element v of lane l = A^-1[16 tr + 4 v + l/16][16 tc + l%16]).
 template <int NS, class Real, int NIMG, bool BATCH>
-__global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s, Batch bt) {
+__global__ __launch_bounds__(256, NS > 64 ? 1 : 2) void k_sweep_half(WalkerArgs a, SweepArgs s, Batch bt) {
   constexpr int N = 2 * NS;
   using LY = SweepLds<NS>;
   constexpr int NSP = LY::NSP, NT = NSP / 16, NB = (NS + 15) / 16, KC = (N + 3) / 4;
   constexpr int LDM = LY::LDM, LDG = LY::LDG;
   constexpr int EPL = (N + 63) / 64;
-  static_assert(NS == 64 || N <= 64, "the electrons of one spin must share a slot");
+  constexpr int CPL = (NSP + 63) / 64;   // columns of the recursion vectors per lane
+  // NS > 64: the inverse stays in HBM (each lane reads and writes only the elements it
+  // would hold in registers, so no other lane's accesses are involved) and a spin's
+  // electrons span two lane slots (the slot is then per block of 16)
+  constexpr bool GINV = NS > 64;
+  static_assert(GINV || NS == 64 || N <= 64, "the electrons of one spin must share a slot");
   extern __shared__ __align__(16) double smem_d[];
   int bblk = 0;
   if constexpr (BATCH) {
@@ -261,19 +389,21 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
   // element (r, c) of the inverse at Bw[(16 tr + 4 v) NS] (wave-uniform) + lane offset
   double* Bw = a.Binv + bbase;
   const int loff = l4 * NS + l16;
-  d4w_t binv[NT][NT];
+  d4w_t binv[GINV ? 1 : NT][GINV ? 1 : NT];
+  if constexpr (!GINV) {
 #pragma unroll
-  for (int tr = 0; tr < NT; ++tr)
+    for (int tr = 0; tr < NT; ++tr)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const double* rowp = Bw + (16 * tr + 4 * v) * NS;
+      for (int v = 0; v < 4; ++v) {
+        const double* rowp = Bw + (16 * tr + 4 * v) * NS;
 #pragma unroll
-      for (int tc = 0; tc < NT; ++tc) {
-        const bool ok = (16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS);
-        const double val = rowp[ok ? loff + 16 * tc : -(16 * tr + 4 * v) * NS];   // in range either way
-        binv[tr][tc][v] = ok ? val : 0.0;
+        for (int tc = 0; tc < NT; ++tc) {
+          const bool ok = (16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS);
+          const double val = rowp[ok ? loff + 16 * tc : -(16 * tr + 4 * v) * NS];   // in range either way
+          binv[tr][tc][v] = ok ? val : 0.0;
+        }
       }
-    }
+  }
 
   // positions stay in HBM: a block reads the current positions of its 16 electrons
   // (no earlier move of the half-sweep touches them) and an accepted move writes
@@ -296,6 +426,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
 
   for (int b = 0; b < NB; ++b) {
     const int jmax = (NS - 16 * b) < 16 ? (NS - 16 * b) : 16;
+    const int slotb = GINV ? ((sp * NS + 16 * b) >> 6) : slot;   // lane slot of this block's electrons
     // proposal of move 16 b + l16 (lanes with equal l16 hold the same one)
     const int ip = 16 * b + l16;
     const bool pvalid = ip < NS;
@@ -352,7 +483,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
     // P = M' A^-1: the inverse registers are the B operand of k step 4 tr + v
 #pragma unroll
     for (int tc = 0; tc < NT; ++tc) acc[tc] = d4w_t{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
+#pragma unroll (GINV ? 1 : NT)
     for (int tr = 0; tr < NT; ++tr) {
       double av[4];
 #pragma unroll
@@ -360,7 +491,12 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_w(av[v], binv[tr][tc][v], acc[tc]);
+        for (int tc = 0; tc < NT; ++tc) {
+          if constexpr (GINV)
+            acc[tc] = mfma_w(av[v], Bw[(16 * tr + 4 * v + l4) * NS + 16 * tc + l16], acc[tc]);
+          else
+            acc[tc] = mfma_w(av[v], binv[tr][tc][v], acc[tc]);
+        }
       asm volatile("" ::: "memory");
     }
 #pragma unroll
@@ -369,26 +505,37 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
       for (int v = 0; v < 4; ++v) PB[(4 * v + l4) * LDM + 16 * tc + l16] = acc[tc][v];
     wave_lds_sync();
 
-    // the moves of the block, in order
-    const bool col_ok = lane < NSP;
-    const int lc = col_ok ? lane : 0;
+    // the moves of the block, in order; column c of the recursion vectors is element
+    // c / 64 of lane c % 64
     uint32_t amask = 0;
     for (int j = 0; j < jmax; ++j) {
       const int i = 16 * b + j, e = sp * NS + i, owner = e & 63;
-      double t = col_ok ? PB[j * LDM + lc] : 0.0;
+      double t[CPL];
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) t[u] = (lane + 64 * u < NSP) ? PB[j * LDM + lane + 64 * u] : 0.0;
       for (uint32_t mm = amask; mm; mm &= mm - 1) {
         const int jp = __builtin_ctz(mm);
-        const double cf = readlane_d(t, 16 * b + jp);
-        t = fma(-cf, col_ok ? PB[jp * LDM + lc] : 0.0, t);
+        const double cf = colread(t, 16 * b + jp);
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+          t[u] = fma(-cf, (lane + 64 * u < NSP) ? PB[jp * LDM + lane + 64 * u] : 0.0, t[u]);
       }
-      const double q = readlane_d(t, i);
+      const double q = colread(t, i);
       Real sn[3], cn[3], so[3], co[3];
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
         sn[m] = readlane<Real>(sv, j + 16 * m);
         cn[m] = readlane<Real>(cv, j + 16 * m);
-        so[m] = readlane<Real>(slot == 0 ? ts[0][m] : ts[EPL - 1][m], owner);
-        co[m] = readlane<Real>(slot == 0 ? tc_[0][m] : tc_[EPL - 1][m], owner);
+        if constexpr (GINV) {
+          Real s0 = ts[0][m], c0 = tc_[0][m];
+#pragma unroll
+          for (int tt = 1; tt < EPL; ++tt) { s0 = (tt == slotb) ? ts[tt][m] : s0; c0 = (tt == slotb) ? tc_[tt][m] : c0; }
+          so[m] = readlane<Real>(s0, owner);
+          co[m] = readlane<Real>(c0, owner);
+        } else {
+          so[m] = readlane<Real>(slot == 0 ? ts[0][m] : ts[EPL - 1][m], owner);
+          co[m] = readlane<Real>(slot == 0 ? tc_[0][m] : tc_[EPL - 1][m], owner);
+        }
       }
       Real du = Real(0);
 #pragma unroll
@@ -407,88 +554,131 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) dU += __shfl_xor(dU, off, 64);
       const double pacc = q * q * exp(2.0 * dU);
-      double zrow = 0.0;
+      double zrow[CPL];
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) zrow[u] = 0.0;
       if (readlane_d(ru3, j) < pacc) {
-        zrow = (t - (lane == i ? 1.0 : 0.0)) * (1.0 / q);
+        const double iq = 1.0 / q;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) zrow[u] = (t[u] - (lane + 64 * u == i ? 1.0 : 0.0)) * iq;
         amask |= 1u << j;
         // lanes j, j + 16, j + 32 hold move j's proposal; each writes one coordinate
         if (l16 == j && l4 < 3) pw[3 * e + l4] = (l4 == 0) ? xn : ((l4 == 1) ? yn : zn);
         if (lane == owner) {
 #pragma unroll
           for (int tt = 0; tt < EPL; ++tt)
-            if (tt == slot)
+            if (tt == slotb)
               for (int m = 0; m < 3; ++m) { ts[tt][m] = sn[m]; tc_[tt][m] = cn[m]; }
         }
         ++nacc;
       }
-      if (col_ok) PB[j * LDM + lc] = zrow;
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        if (lane + 64 * u < NSP) PB[j * LDM + lane + 64 * u] = zrow[u];
     }
     for (int j = jmax; j < 16; ++j)
-      if (col_ok) PB[j * LDM + lc] = 0.0;
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        if (lane + 64 * u < NSP) PB[j * LDM + lane + 64 * u] = 0.0;
     if (amask == 0) { wave_lds_sync(); continue; }
     // accepted MO rows into A
-    if (lane < NS)
-      for (uint32_t mm = amask; mm; mm &= mm - 1) {
-        const int j = __builtin_ctz(mm);
-        a.Amat[bbase + (size_t)(16 * b + j) * NS + lane] = MB[j * LDM + lane];
-      }
+    for (uint32_t mm = amask; mm; mm &= mm - 1) {
+      const int j = __builtin_ctz(mm);
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        if (lane + 64 * u < NS) a.Amat[bbase + (size_t)(16 * b + j) * NS + lane + 64 * u] = MB[j * LDM + lane + 64 * u];
+    }
     // Z = (I + Y)^-1 [z rows]: back-substitution from the last accepted move
 #pragma unroll 1
     for (int j = 15; j >= 0; --j) {
       if (!((amask >> j) & 1u)) continue;
-      const double zo = col_ok ? PB[j * LDM + lc] : 0.0;
-      double z = zo;
+      double zo[CPL], z[CPL];
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) {
+        zo[u] = (lane + 64 * u < NSP) ? PB[j * LDM + lane + 64 * u] : 0.0;
+        z[u] = zo[u];
+      }
       for (uint32_t mm = amask & ~((2u << j) - 1u); mm; mm &= mm - 1) {
         const int jp = __builtin_ctz(mm);
-        const double cf = readlane_d(zo, 16 * b + jp);
-        z = fma(-cf, col_ok ? PB[jp * LDM + lc] : 0.0, z);
+        const double cf = colread(zo, 16 * b + jp);
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+          z[u] = fma(-cf, (lane + 64 * u < NSP) ? PB[jp * LDM + lane + 64 * u] : 0.0, z[u]);
       }
-      if (col_ok) PB[j * LDM + lc] = z;
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        if (lane + 64 * u < NSP) PB[j * LDM + lane + 64 * u] = z[u];
     }
     // G = the inverse's columns of this block (column tile b) into the M' buffer
     wave_lds_sync();
-    auto snap = [&](auto tcc) {
-      constexpr int TC = decltype(tcc)::value;
-#pragma unroll
+    if constexpr (GINV) {
+#pragma unroll 1
       for (int tr = 0; tr < NT; ++tr)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) MB[(16 * tr + 4 * v + l4) * LDG + l16] = binv[tr][TC][v];
-    };
-    switch (b) {
-      case 0: snap(std::integral_constant<int, 0>{}); break;
-      case 1: if constexpr (NT > 1) snap(std::integral_constant<int, (NT > 1 ? 1 : 0)>{}); break;
-      case 2: if constexpr (NT > 2) snap(std::integral_constant<int, (NT > 2 ? 2 : 0)>{}); break;
-      default: if constexpr (NT > 3) snap(std::integral_constant<int, (NT > 3 ? 3 : 0)>{}); break;
+        for (int v = 0; v < 4; ++v)
+          MB[(16 * tr + 4 * v + l4) * LDG + l16] = Bw[(16 * tr + 4 * v + l4) * NS + 16 * b + l16];
+    } else {
+      auto snap = [&](auto tcc) {
+        constexpr int TC = decltype(tcc)::value;
+#pragma unroll
+        for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) MB[(16 * tr + 4 * v + l4) * LDG + l16] = binv[tr][TC][v];
+      };
+      switch (b) {
+        case 0: snap(std::integral_constant<int, 0>{}); break;
+        case 1: if constexpr (NT > 1) snap(std::integral_constant<int, (NT > 1 ? 1 : 0)>{}); break;
+        case 2: if constexpr (NT > 2) snap(std::integral_constant<int, (NT > 2 ? 2 : 0)>{}); break;
+        default: if constexpr (NT > 3) snap(std::integral_constant<int, (NT > 3 ? 3 : 0)>{}); break;
+      }
     }
     wave_lds_sync();
     // A^-1 -= G Z
+    if constexpr (GINV) {
+      for (int tr = 0; tr < NT; ++tr) {
+        double ga[4];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      double zb[NT], ga[NT];
+        for (int kk = 0; kk < 4; ++kk) ga[kk] = -MB[(16 * tr + l16) * LDG + 4 * kk + l4];
+#pragma unroll 2
+        for (int tc = 0; tc < NT; ++tc) {
+          double* tp = Bw + (16 * tr + l4) * NS + 16 * tc + l16;
+          d4w_t tile = {tp[0], tp[4 * NS], tp[8 * NS], tp[12 * NS]};
 #pragma unroll
-      for (int tc = 0; tc < NT; ++tc) zb[tc] = PB[(4 * kk + l4) * LDM + 16 * tc + l16];
+          for (int kk = 0; kk < 4; ++kk) tile = mfma_w(ga[kk], PB[(4 * kk + l4) * LDM + 16 * tc + l16], tile);
+          tp[0] = tile[0]; tp[4 * NS] = tile[1]; tp[8 * NS] = tile[2]; tp[12 * NS] = tile[3];
+        }
+      }
+    } else {
 #pragma unroll
-      for (int tr = 0; tr < NT; ++tr) ga[tr] = -MB[(16 * tr + l16) * LDG + 4 * kk + l4];
+      for (int kk = 0; kk < 4; ++kk) {
+        double zb[NT], ga[NT];
 #pragma unroll
-      for (int tr = 0; tr < NT; ++tr)
+        for (int tc = 0; tc < NT; ++tc) zb[tc] = PB[(4 * kk + l4) * LDM + 16 * tc + l16];
 #pragma unroll
-        for (int tc = 0; tc < NT; ++tc) binv[tr][tc] = mfma_w(ga[tr], zb[tc], binv[tr][tc]);
-      asm volatile("" ::: "memory");
+        for (int tr = 0; tr < NT; ++tr) ga[tr] = -MB[(16 * tr + l16) * LDG + 4 * kk + l4];
+#pragma unroll
+        for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+          for (int tc = 0; tc < NT; ++tc) binv[tr][tc] = mfma_w(ga[tr], zb[tc], binv[tr][tc]);
+        asm volatile("" ::: "memory");
+      }
     }
     wave_lds_sync();
   }
-  // the block's walker again from the block index (the lookup is redone rather than kept live)
-  const int blk_end = BATCH ? (int)blockIdx.x - bt.off[batch_job(bt, blockIdx.x)] : (int)blockIdx.x;
-  Bw = a.Binv + ((size_t)(blk_end * 4 + wv) * 2 + sp) * NS * NS;
+  if constexpr (!GINV) {
+    // the block's walker again from the block index (the lookup is redone rather than kept live)
+    const int blk_end = BATCH ? (int)blockIdx.x - bt.off[batch_job(bt, blockIdx.x)] : (int)blockIdx.x;
+    Bw = a.Binv + ((size_t)(blk_end * 4 + wv) * 2 + sp) * NS * NS;
 #pragma unroll
-  for (int tr = 0; tr < NT; ++tr)
+    for (int tr = 0; tr < NT; ++tr)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      double* rowp = Bw + (16 * tr + 4 * v) * NS;
+      for (int v = 0; v < 4; ++v) {
+        double* rowp = Bw + (16 * tr + 4 * v) * NS;
 #pragma unroll
-      for (int tc = 0; tc < NT; ++tc)
-        if ((16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS)) rowp[loff + 16 * tc] = binv[tr][tc][v];
-    }
+        for (int tc = 0; tc < NT; ++tc)
+          if ((16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS)) rowp[loff + 16 * tc] = binv[tr][tc][v];
+      }
+  }
   if (lane == 0) a.nacc[w] += nacc;
 }
 
@@ -614,21 +804,36 @@ inline Batch batch_or_none(const Batch* bt) { return bt ? *bt : Batch{nullptr, n
 template <int NS>
 hipError_t launch_invert_t(const WalkerArgs& a, int spin_lo, int spin_hi, int only_flagged, hipStream_t st,
                            const Batch* bt, int nblk) {
-  dim3 grid(bt ? nblk : (a.W * (spin_hi - spin_lo) + 3) / 4);
-  if (bt)
-    hipLaunchKernelGGL((k_invert<NS, true>), grid, dim3(256), 0, st, a, spin_lo, spin_hi, only_flagged, *bt);
-  else
-    hipLaunchKernelGGL((k_invert<NS, false>), grid, dim3(256), 0, st, a, spin_lo, spin_hi, only_flagged, batch_or_none(bt));
-  return hipGetLastError();
+  if constexpr (NS > 64) {          // one work-group per matrix
+    dim3 g(bt ? nblk : a.W * (spin_hi - spin_lo));
+    if (bt)
+      hipLaunchKernelGGL((k_invert_lds<NS, true>), g, dim3(256), InvLds<NS>::bytes, st, a, spin_lo, spin_hi,
+                         only_flagged, *bt);
+    else
+      hipLaunchKernelGGL((k_invert_lds<NS, false>), g, dim3(256), InvLds<NS>::bytes, st, a, spin_lo, spin_hi,
+                         only_flagged, batch_or_none(bt));
+    return hipGetLastError();
+  } else {
+    dim3 grid(bt ? nblk : (a.W * (spin_hi - spin_lo) + 3) / 4);
+    if (bt)
+      hipLaunchKernelGGL((k_invert<NS, true>), grid, dim3(256), 0, st, a, spin_lo, spin_hi, only_flagged, *bt);
+    else
+      hipLaunchKernelGGL((k_invert<NS, false>), grid, dim3(256), 0, st, a, spin_lo, spin_hi, only_flagged, batch_or_none(bt));
+    return hipGetLastError();
+  }
 }
 template <int NS>
 hipError_t launch_refine_t(const WalkerArgs& a, int spin, double tol, hipStream_t st, const Batch* bt, int nblk) {
-  dim3 grid(bt ? nblk : (a.W + 3) / 4);
-  if (bt)
-    hipLaunchKernelGGL((k_refine<NS, true>), grid, dim3(256), RefineLds<NS>::bytes, st, a, spin, tol, *bt);
-  else
-    hipLaunchKernelGGL((k_refine<NS, false>), grid, dim3(256), RefineLds<NS>::bytes, st, a, spin, tol, batch_or_none(bt));
-  return hipGetLastError();
+  if constexpr (NS > 64) {
+    return hipErrorInvalidValue;   // no register-resident refinement: refresh by elimination
+  } else {
+    dim3 grid(bt ? nblk : (a.W + 3) / 4);
+    if (bt)
+      hipLaunchKernelGGL((k_refine<NS, true>), grid, dim3(256), RefineLds<NS>::bytes, st, a, spin, tol, *bt);
+    else
+      hipLaunchKernelGGL((k_refine<NS, false>), grid, dim3(256), RefineLds<NS>::bytes, st, a, spin, tol, batch_or_none(bt));
+    return hipGetLastError();
+  }
 }
 template <int NS, class Real>
 size_t sweep_smem() {
@@ -657,6 +862,7 @@ hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t s
     case 27: { constexpr int NSV = 27; CALL; } \
     case 32: { constexpr int NSV = 32; CALL; } \
     case 64: { constexpr int NSV = 64; CALL; } \
+    case 128: { constexpr int NSV = 128; CALL; } \
     default: return hipErrorInvalidValue; \
   }
 

@@ -61,6 +61,7 @@ struct MeasureArgs {
   double* Uj;           // W  Jastrow exponent U of the sample
   double* acc;          // W x (2 + 9N): sum E_L, sum E_L^2, sum dE_L/dR, sum dlnpsi/dR, sum E_L dlnpsi/dR
   double* rho_acc;      // W x nk x 2: sum of the electron structure factor
+  unsigned char* scr;   // W x slater_scratch_bytes(NS, mixed): matrix products that do not fit in LDS
 };
 
 // Several trajectories of one bucket (N, precision, Gaussian images, Ewald cut-off)
@@ -99,6 +100,8 @@ hipError_t launch_sweep(const WalkerArgs& a, const SweepArgs& s, int mixed, hipS
 
 hipError_t launch_ewald_sample(const MeasureArgs& m, const EwaldArgs& e, int mixed, hipStream_t st,
                                const Batch* bt = nullptr, int nblk = 0);
+// Per-walker device scratch of the measurement kernel (0 where everything fits in LDS).
+size_t slater_scratch_bytes(int NS, int mixed);
 hipError_t launch_slater_sample(const MeasureArgs& m, int mixed, hipStream_t st, const Batch* bt = nullptr,
                                 int nblk = 0);
 hipError_t launch_finalize(const MeasureArgs& m, const EwaldArgs& e, int M, double* means, hipStream_t st);

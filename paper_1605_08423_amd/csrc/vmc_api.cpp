@@ -54,6 +54,7 @@ struct vmc_traj {
   double *means = nullptr, *f_w = nullptr, *partial = nullptr, *outv = nullptr;
   int64_t* nacc = nullptr;
   int* rflag = nullptr;
+  unsigned char* scr = nullptr;   // per-walker scratch of the measurement kernel (N_sigma > 64)
   // Ewald tables
   int nk = 0, nslot = 0;
   double *kvec = nullptr, *rho_p = nullptr, *Ptab = nullptr, *Fconst = nullptr, *Vpp = nullptr;
@@ -135,7 +136,7 @@ int dalloc(T** p, size_t n) {
   return e == hipSuccess ? VMC_OK : map_err(e);
 }
 
-bool supported_ns(int ns) { return ns == 8 || ns == 16 || ns == 27 || ns == 32 || ns == 64; }
+bool supported_ns(int ns) { return ns == 8 || ns == 16 || ns == 27 || ns == 32 || ns == 64 || ns == 128; }
 
 int check_sys(const vmc_system* s) {
   if (!s) return VMC_EINVAL;
@@ -228,7 +229,7 @@ MeasureArgs measure_args(vmc_traj* t, const double* R, const double* C, const do
   m.R = R; m.zeta = zeta; m.C = C;
   m.a_par = t->sys.a_par; m.a_anti = t->sys.a_anti; m.b = t->sys.b;
   m.pos = t->pos; m.Binv = t->Binv; m.Vs = t->Vs; m.dVs = t->dVs; m.Uj = t->Uj;
-  m.acc = t->acc; m.rho_acc = t->rho_acc;
+  m.acc = t->acc; m.rho_acc = t->rho_acc; m.scr = t->scr;
   return m;
 }
 
@@ -268,7 +269,7 @@ void free_traj(vmc_traj* t) {
   if (!t) return;
   void* ptrs[] = {t->pos, t->Amat, t->Binv, t->ldet, t->sgn, t->acc, t->rho_acc, t->Vs, t->dVs, t->Uj,
                   t->means, t->f_w, t->partial, t->outv, t->nacc, t->kvec, t->rho_p, t->Ptab, t->Fconst,
-                  t->Vpp, t->slot, t->slot_nx0, t->rflag};
+                  t->Vpp, t->slot, t->slot_nx0, t->rflag, t->scr};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete t;
@@ -378,6 +379,8 @@ int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int W, uint32_t seed, u
             !dalloc(&t->nacc, (size_t)W) && !dalloc(&t->rflag, (size_t)W * 2) && !dalloc(&t->kvec, kv.size()) && !dalloc(&t->rho_p, 2 * t->nk) &&
             !dalloc(&t->Ptab, (size_t)t->nk * N * 2) && !dalloc(&t->Fconst, n3) && !dalloc(&t->Vpp, 1) &&
             !dalloc(&t->slot, slots.size()) && !dalloc(&t->slot_nx0, nx0.size());
+  const size_t scr = slater_scratch_bytes(t->NS, sys->precision == VMC_MIXED);
+  if (ok && scr) ok = !dalloc(&t->scr, (size_t)W * scr);
   if (!ok) { free_traj(t); return VMC_ENOMEM; }
   if (hipMemcpy(t->kvec, kv.data(), kv.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(t->slot, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
@@ -432,7 +435,8 @@ int vmc_energy_forces(vmc_traj* t, const double* R, const double* C, const doubl
   const int total = n_equil + n_sweeps;
   for (int s = 0; s < total; ++s) {
     for (int sp = 0; sp < 2; ++sp) {
-      if (s == 0 || rtol < 0.0) {
+      // N_sigma > 64: no register-resident refinement, the inverse is refreshed by elimination
+      if (s == 0 || rtol < 0.0 || t->NS > 64) {
         RUN(K_INVERT, launch_invert(a, sp, sp + 1, 0, st));
       } else {
         RUN(K_REFINE, launch_refine(a, sp, rtol, st));
@@ -743,7 +747,8 @@ size_t request_bytes(const vmc_system& s, int W) {
              nk * N * 2 + n3 + 1;
   d += 2 * n3 + 2 * n3 * n3 + N * NS + N;                     // R, R_prev, S, S_prev, C, zeta
   size_t b = d * sizeof(double) + Wz * sizeof(int64_t) + Wz * 2 * sizeof(int) +
-             (slots.size() + nx0.size() + 1) * sizeof(int);
+             (slots.size() + nx0.size() + 1) * sizeof(int) +
+             Wz * slater_scratch_bytes((int)NS, s.precision == VMC_MIXED);
   return b;
 }
 
@@ -933,7 +938,8 @@ int bucket_sweep(vmc_server* s, const std::vector<Served*>& qs) {
     const TrajJob j = make_job(q, q->sweep);
     js.push_back(j);
     os.push_back(os.back() + (q->t->W + 3) / 4);
-    if (q->sweep >= 1) { jr.push_back(j); orf.push_back(orf.back() + (q->t->W + 3) / 4); }
+    // refresh blocks: four walkers each (refinement), or one matrix each (elimination, N_sigma > 64)
+    if (q->sweep >= 1) { jr.push_back(j); orf.push_back(orf.back() + (q->t->NS > 64 ? q->t->W : (q->t->W + 3) / 4)); }
     if (q->sweep >= q->n_equil_cur) { jm.push_back(j); om.push_back(om.back() + q->t->W); }
   }
   const size_t nj = js.size() + jr.size() + jm.size();
@@ -982,7 +988,9 @@ int bucket_sweep(vmc_server* s, const std::vector<Served*>& qs) {
   const int mixed = qs[0]->req.sys.precision == VMC_MIXED;
   const TrajJob& j0 = js[0];
   for (int sp = 0; sp < 2; ++sp) {
-    if (!jr.empty()) {
+    if (!jr.empty() && j0.a.NS > 64) {
+      RUN(K_INVERT, launch_invert(j0.a, sp, sp + 1, 0, st, &brf, orf.back()));
+    } else if (!jr.empty()) {
       RUN(K_REFINE, launch_refine(j0.a, sp, j0.tol, st, &brf, orf.back()));
       RUN(K_INVERT, launch_invert(j0.a, sp, sp + 1, 1, st, &brf, orf.back()));
     }

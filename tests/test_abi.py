@@ -29,7 +29,7 @@ def test_error_strings_and_supported_sizes():
     from paper_1605_08423_amd import vmc
     lib = vmc._lib()
     assert lib.vmc_strerror(vmc.VMC_ENOTSPD).decode() == "S is not positive definite"
-    assert vmc.supported_n(16) and vmc.supported_n(54) and vmc.supported_n(128)
+    assert vmc.supported_n(16) and vmc.supported_n(54) and vmc.supported_n(128) and vmc.supported_n(256)
     assert not vmc.supported_n(17) and not vmc.supported_n(100)
 
 

@@ -1,0 +1,111 @@
+"""The 256-proton box (128 x 128 Slater matrices per spin) against the CPU oracle,
+through the C ABI.  At this size the inverse does not fit in registers: the sweep
+keeps it in device memory, the refresh is Gauss-Jordan elimination in LDS at
+every half-sweep, and the measurement keeps its matrix products in a per-walker
+device region.  Bars as for the smaller boxes: 1e-10 relative in FP64, the
+per-quantity mixed-precision tolerances otherwise.  The oracle takes a few seconds
+per configuration here, so the cases are small (W = 3 also leaves one lane group
+of the four-walker sweep blocks empty)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1605_08423_amd.inputs import workload
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-10
+TOLMIX = {"lnpsi": 1e-6, "EL": 5e-5, "dlnpsi": 2e-5, "dEL": 2e-5}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    from paper_1605_08423_amd import vmc
+    return torch, vmc, vmc.Context(0)
+
+
+@pytest.fixture(scope="module")
+def h256(oracle):
+    wl = workload("h256")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
+    return wl, Cm, oracle.System(wl.R, wl.zeta, Cm, L=wl.L), oracle
+
+
+def T(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_eval_configs_h256(dev, h256, precision):
+    torch, vmc, ctx = dev
+    wl, Cm, s, _ = h256
+    K = 2
+    say(f"[eval_configs h256] precision={precision} K={K}")
+    pos = wl.electrons(W=K, seed_offset=13)
+    g = vmc.vmc_eval_configs(ctx, vmc.make_system(wl.n, wl.L, precision=precision), T(torch, wl.R.reshape(-1)),
+                             T(torch, Cm), T(torch, wl.zeta), T(torch, pos)).cpu().numpy()
+    n3 = 3 * wl.n
+    worst = dict.fromkeys(TOLMIX, 0.0)
+    for k in range(K):
+        r = s.local(pos[k])
+        worst["lnpsi"] = max(worst["lnpsi"], rel(g[k, 0], r["lnpsi"]))
+        worst["EL"] = max(worst["EL"], rel(g[k, 1], r["EL"]))
+        worst["dlnpsi"] = max(worst["dlnpsi"], rel(g[k, 2:2 + n3], r["dlnpsi"]))
+        worst["dEL"] = max(worst["dEL"], rel(g[k, 2 + n3:], r["dEL"]))
+    say("  worst relative errors", {k: f"{v:.2e}" for k, v in worst.items()})
+    for q, v in worst.items():
+        assert v < (TOL64 if precision == 0 else TOLMIX[q]), (q, v)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_chain_h256(dev, h256, precision):
+    """Two sweeps (one equilibration, one measured) of three walkers on the oracle's
+    Philox stream: the second sweep starts from the elimination refresh."""
+    torch, vmc, ctx = dev
+    wl, Cm, s, oracle = h256
+    W, ne, ns = 3, 1, 1
+    say(f"[chain h256] precision={precision} W={W} sweeps={ne}+{ns}")
+    x0 = wl.electrons(W=W, seed_offset=17)
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=precision), W, seed=8, traj_id=4)
+    tr.set_walkers(T(torch, x0))
+    out = tr.energy_forces(T(torch, wl.R.reshape(-1)), T(torch, Cm), T(torch, wl.zeta), ne, ns, wl.delta, 1)
+    out = out.cpu().numpy()
+    acc = tr.accepts().cpu().numpy()
+    means = tr.walker_means().cpu().numpy()
+    posg = tr.get_walkers().cpu().numpy()
+    tr.close()
+    xo = x0.copy()
+    sums, nacc = s.vmc_run(xo, ne, ns, wl.delta, seed=8, traj=4, step=1)
+    red = oracle.reduce(sums, ns)
+    flips = int(np.sum(acc != nacc))
+    say(f"  accepted gpu/oracle {acc.sum()}/{nacc.sum()}  walkers with a flipped decision: {flips}")
+    n3 = 3 * wl.n
+    mo = red["means"]
+    errs = {}
+    for q, sl in [("e_w", slice(0, 1)), ("d_w", slice(1, 1 + n3)), ("g_w", slice(1 + n3, 1 + 2 * n3)),
+                  ("h_w", slice(1 + 2 * n3, 1 + 3 * n3))]:
+        errs[q] = max(rel(means[w, sl], mo[w, sl]) for w in range(W))
+    errs["E"] = rel(out[0], red["E"])
+    errs["f"] = rel(out[3:], red["f"])
+    say("  worst relative errors", {k: f"{v:.2e}" for k, v in errs.items()})
+    if precision == 0:
+        assert flips == 0
+        assert rel(posg, xo) < 1e-12
+        for q, v in errs.items():
+            assert v < TOL64, (q, v)
+    elif flips == 0:
+        # chain-level mixed bars: E 1e-6, forces 1e-5; per-walker means at the per-configuration bars
+        assert errs["E"] < 1e-6 and errs["f"] < 1e-5
+        assert errs["e_w"] < TOLMIX["EL"] and errs["g_w"] < TOLMIX["dlnpsi"] and errs["d_w"] < TOLMIX["dEL"]
+

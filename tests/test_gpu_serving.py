@@ -30,7 +30,7 @@ def T(torch, a):
 
 
 def spec(name, W, precision, steps=2, M=4, ne1=2, ne=1, seed=5, traj=7, flags=0, Tfac=1.0):
-    wl = workload(name) if name in ("h16", "h54", "h128") else small_system(int(name[1:]), 1.35, seed=21)
+    wl = workload(name) if name in ("h16", "h54", "h128", "h256") else small_system(int(name[1:]), 1.35, seed=21)
     return dict(wl=wl, W=W, precision=precision, steps=steps, M=M, ne1=ne1, ne=ne, seed=seed, traj=traj, flags=flags,
                 T=wl.T_hartree * Tfac, alpha=0.122 * W * M)
 
@@ -79,7 +79,7 @@ def single_path(torch, vmc, ctx, s):
     return R.cpu().numpy(), np.array(Es)
 
 
-@pytest.mark.parametrize("name,W,precision", [("h16", 64, 0), ("h54", 176, 1)])
+@pytest.mark.parametrize("name,W,precision", [("h16", 64, 0), ("h54", 176, 1), ("h256", 800, 1)])
 def test_served_equals_single_trajectory_calls(dev, name, W, precision):
     torch, vmc, ctx = dev
     s = spec(name, W, precision)
