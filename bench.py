@@ -106,18 +106,26 @@ def run_serve(args):
     continuous batching on one GPU (vmc_server_*).  Prints one JSON line."""
     import torch
     from paper_1605_08423_amd import vmc
-    from paper_1605_08423_amd.inputs import KB_HA_PER_K, small_system
+    from paper_1605_08423_amd.inputs import KB_HA_PER_K, small_system, workload
     rng = np.random.default_rng(20240605)
-    n_req = args.serve
+    large = args.serve_mix == "large"
+    n_req = 9 if large else args.serve
     ctx = vmc.Context(0)
     reqs, meta = [], []
     for i in range(n_req):
-        n = int(rng.choice([16, 32, 54, 128]))
-        rs = float(rng.uniform(1.25, 1.50))
-        T_k = float(rng.uniform(600.0, 3000.0))
-        W = SERVE_WALKERS[n]
-        wl = small_system(n, rs, seed=1000 + i)
-        prec = vmc.VMC_MIXED if n == 128 else vmc.VMC_FP64
+        if large:
+            # one 256-proton box (r_s 1.36, 900 K, 32768 walkers) and eight 54-proton boxes
+            n = 256 if i == 0 else 54
+            rs = 1.36 if i == 0 else float(rng.uniform(1.25, 1.50))
+            T_k = 900.0 if i == 0 else float(rng.uniform(600.0, 3000.0))
+            W = 32768 if i == 0 else SERVE_WALKERS[54]
+        else:
+            n = int(rng.choice([16, 32, 54, 128]))
+            rs = float(rng.uniform(1.25, 1.50))
+            T_k = float(rng.uniform(600.0, 3000.0))
+            W = SERVE_WALKERS[n]
+        wl = workload("h256") if (large and i == 0) else small_system(n, rs, seed=1000 + i)
+        prec = vmc.VMC_MIXED if (n >= 128 or large) else vmc.VMC_FP64
         sysd = vmc.make_system(n, wl.L, precision=prec)
         alpha = 0.122 * W * args.serve_sweeps
         reqs.append(vmc.make_request(sysd, W, wl.R, wl.zeta, wl.electrons(W=W, seed_offset=i), n_steps=args.serve_steps,
@@ -162,10 +170,14 @@ def run_serve(args):
     line = {
         "metric": "served stream: Langevin steps/s and step latency p50/p99",
         "value": round(steps / wall, 3), "unit": "Langevin steps/s", "n_gpus": 1, "higher_is_better": True,
-        "data": "synthetic", "dtype": "f64 (N<128) / f32+f64 mixed (N=128)",
-        "config": {"workload": f"{n_req} trajectories, N in {{16,32,54,128}}, r_s~U[1.25,1.50], T~U[600,3000] K, "
-                               f"W = 1024/2048/4096/16384 by N, {args.serve_steps} Langevin steps x "
-                               f"(5 + {args.serve_sweeps}) sweeps each, Poisson arrivals at {args.serve_rate}/s",
+        "data": "synthetic",
+        "dtype": "f32+f64 mixed" if large else "f64 (N<128) / f32+f64 mixed (N=128)",
+        "config": {"workload": (f"one N=256 box (r_s 1.36, 900 K, 32768 walkers) with eight N=54 boxes (r_s~U[1.25,1.50], "
+                                f"T~U[600,3000] K, 4096 walkers), all mixed precision, " if large else
+                                f"{n_req} trajectories, N in {{16,32,54,128}}, r_s~U[1.25,1.50], T~U[600,3000] K, "
+                                f"W = 1024/2048/4096/16384 by N, ") +
+                               f"{args.serve_steps} Langevin steps x (5 + {args.serve_sweeps}) sweeps each, "
+                               f"Poisson arrivals at {args.serve_rate}/s",
                    "hbm_budget_GB": args.serve_budget_gb},
         "wall_s": round(wall, 3), "steps": steps, "failed": failed,
         "walker_sweeps_per_s": round(wsweeps / wall, 1),
@@ -183,24 +195,29 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--walkers", type=int, default=16384)
+    ap.add_argument("--workload", choices=["h128", "h256"], default="h128",
+                    help="h128: 128 H, r_s 1.34, T 1000 K, 16384 walkers (the headline); "
+                         "h256: 256 H, r_s 1.36, T 900 K, 32768 walkers")
+    ap.add_argument("--walkers", type=int, default=None, help="default: the workload's walker count")
     ap.add_argument("--sweeps", type=int, default=100)
-    ap.add_argument("--rs", type=float, default=1.34)
+    ap.add_argument("--rs", type=float, default=None, help="default: the workload's r_s")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--cpu-walkers", type=int, default=192)
-    ap.add_argument("--cpu-sweeps", type=int, default=6)
+    ap.add_argument("--cpu-walkers", type=int, default=None, help="default: 192 (h128), 16 (h256)")
+    ap.add_argument("--cpu-sweeps", type=int, default=None, help="default: 6 (h128), 2 (h256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", help="print per-kernel times to stderr")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration) and exit")
     ap.add_argument("--serve", type=int, default=0, metavar="K",
                     help="served-stream benchmark of K trajectories instead of the single-trajectory step")
+    ap.add_argument("--serve-mix", choices=["stream", "large"], default="stream",
+                    help="stream: K trajectories with N in {16,32,54,128}; large: one N=256 box and eight N=54 boxes")
     ap.add_argument("--serve-rate", type=float, default=16.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-steps", type=int, default=3)
     ap.add_argument("--serve-sweeps", type=int, default=20)
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     args = ap.parse_args()
-    if args.serve:
+    if args.serve or args.serve_mix == "large":
         if args.gpus != 1:
             print("bench.py runs on one GPU only.", file=sys.stderr)
             sys.exit(2)
@@ -224,8 +241,9 @@ def main():
     from paper_1605_08423_amd import vmc
     from paper_1605_08423_amd.inputs import workload
 
-    wl = workload("h128", rs=args.rs)
-    N, W, M = wl.n, args.walkers, args.sweeps
+    wl = workload(args.workload, rs=args.rs)
+    rs = wl.rs
+    N, W, M = wl.n, args.walkers or wl.walkers, args.sweeps
     prec = vmc.VMC_MIXED if args.precision == "mixed" else vmc.VMC_FP64
     ctx = vmc.Context(0)
     sysd = vmc.make_system(N, wl.L, precision=prec)
@@ -301,10 +319,12 @@ def main():
         from oracle import oracle as O
         Cm0, _ = O.huckel(wl.R, wl.zeta, wl.L, N // 2)
         threads = min(os.cpu_count() or 1, 16)
-        v, dt = run_cpu_baseline(wl, Cm0, args.cpu_walkers, args.cpu_sweeps, threads)
+        cw = args.cpu_walkers or (192 if N <= 128 else 16)
+        cs = args.cpu_sweeps or (6 if N <= 128 else 2)
+        v, dt = run_cpu_baseline(wl, Cm0, cw, cs, threads)
         cpu = {"value": round(v, 3), "unit": "walker-sweeps/s", "cores": threads, "kind": "oracle",
-               "sample": f"{args.cpu_walkers} walkers x (1 unmeasured + {args.cpu_sweeps} measured) sweeps of the "
-                         f"same N=128 box in FP64, {dt:.1f} s"}
+               "sample": f"{cw} walkers x (1 unmeasured + {cs} measured) sweeps of the "
+                         f"same N={N} box in FP64, {dt:.1f} s"}
     lat_ms = sorted(1e3 * x for x in lat)
     p = lambda q: lat_ms[min(len(lat_ms) - 1, int(math.ceil(q * len(lat_ms))) - 1)]
     line = {
@@ -312,8 +332,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32/f64" if prec == vmc.VMC_MIXED else "f64", "data": "synthetic",
-        "config": {"workload": f"h128: 128 H + 128 e-, r_s={args.rs}, T=1000 K, {W} walkers x {M} measured "
-                               f"(+5 re-equilibration) sweeps per Langevin step, {args.precision} precision",
+        "config": {"workload": f"{args.workload}: {N} H + {N} e-, r_s={rs}, T={wl.T_kelvin:g} K, {W} walkers x {M} "
+                               f"measured (+5 re-equilibration) sweeps per Langevin step, {args.precision} precision",
                    "N": N, "walkers": W, "sweeps": M, "precision": args.precision},
         "langevin_steps_per_s": round(args.steps / elapsed, 4),
         "step_latency_ms": {"p50": round(p(0.5), 1), "p99": round(p(0.99), 1)},

@@ -180,30 +180,28 @@ __global__ __launch_bounds__(256) void k_invert(WalkerArgs a, int spin_lo, int s
   }
 }
 
-// Gauss-Jordan for NS > 64 (the register version holds one row per lane): one
-// 256-thread work-group per matrix, the matrix in LDS (row stride NS + 1).  The same
-// implicit-pivot elimination as k_invert -- pivot of column p is the unused row with
-// the largest |A[i][p]|, ties to the lowest row -- with the pivot row and the
-// multipliers staged in LDS before each rank-1 step, and the same output: row r,
-// which pivoted column myk(r), holds row myk(r) of A^-1 with column c at pi(c).
-template <int NS>
-struct InvLds {
-  static constexpr int LD = NS + 1;
-  static constexpr size_t bytes = ((size_t)NS * LD + 2 * NS) * sizeof(double);
-};
-
+// Gauss-Jordan for NS = 128: one 256-thread work-group per matrix, registers
+// resident.  Thread (h, r) = (t / 128, t % 128) holds row r, columns 64 h .. 64 h + 63,
+// in 4 blocks of 16.  The same implicit-pivot elimination as k_invert (pivot of
+// column p: the unused row with the largest |A[i][p]|, ties to the lowest row) and
+// the same output: row r, which pivoted column myk(r), holds row myk(r) of A^-1 with
+// column c at pi(c).  Each step: the two waves that hold column p propose their best
+// row; every thread takes the same pivot from LDS; the pivot row (column p set to 1)
+// and the multipliers g_i go through LDS; then M[i][j] -= g_i prow[j] everywhere,
+// with column p first set to e_piv so that the rank-1 step also forms the new column.
 template <int NS, bool BATCH>
-__global__ __launch_bounds__(256) void k_invert_lds(WalkerArgs a, int spin_lo, int spin_hi, int only_flagged,
-                                                   Batch bt) {
-  constexpr int LD = InvLds<NS>::LD;
-  extern __shared__ __align__(16) double sm_inv[];
-  double* M = sm_inv;                  // NS x LD
-  double* prow = M + (size_t)NS * LD;  // pivot row before the step
-  double* gcol = prow + NS;            // multipliers of the step
-  __shared__ int used[NS], myk[NS], pi_[NS];
-  __shared__ double wv_v[4];
-  __shared__ int wv_i[4], s_piv, s_flag;
-  __shared__ double s_pv;
+__global__ __launch_bounds__(256, 2) void k_invert_big(WalkerArgs a, int spin_lo, int spin_hi, int only_flagged,
+                                                       Batch bt) {
+  static_assert(NS == 128, "two column halves of 64 per row");
+  constexpr int HALF = NS / 2, BC = 16, NBL = HALF / BC;
+  __shared__ __align__(16) double prow[NS];
+  __shared__ double gcol[NS];
+  __shared__ double cand_v[2], cand_s[2];
+  __shared__ int cand_i[2];
+  __shared__ int pi_s[NS];
+  __shared__ double pv_s[NS];
+  __shared__ int wv_cnt[4];
+  __shared__ double wv_ld[4];
   int blk = blockIdx.x;
   if constexpr (BATCH) {
     const int j = batch_job(bt, blk);
@@ -211,6 +209,7 @@ __global__ __launch_bounds__(256) void k_invert_lds(WalkerArgs a, int spin_lo, i
     blk -= bt.off[j];
   }
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int h = t >> 7, r = t & (NS - 1);
   const int nsp = spin_hi - spin_lo;
   const int w = blk / nsp, sp = spin_lo + blk % nsp;
   if (w >= a.W) return;
@@ -221,56 +220,79 @@ __global__ __launch_bounds__(256) void k_invert_lds(WalkerArgs a, int spin_lo, i
     if (t == 0) a.rflag[(size_t)w * 2 + sp] = 0;
   }
   const size_t base = ((size_t)w * 2 + sp) * NS * NS;
-  for (int u = t; u < NS * NS; u += 256) M[(u / NS) * LD + u % NS] = a.Amat[base + u];
-  for (int i = t; i < NS; i += 256) used[i] = 0;
-  double logdet = 0.0, sgn = 1.0;
-  __syncthreads();
-  for (int p = 0; p < NS; ++p) {
-    double bv = -1.0;
-    int bi = t;
-    if (t < NS && !used[t]) bv = fabs(M[t * LD + p]);
+  double x[NBL][BC];
+  {
+    const double* src = a.Amat + base + (size_t)r * NS + HALF * h;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ov = __shfl_xor(bv, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    if (lane == 0) { wv_v[wave] = bv; wv_i[wave] = bi; }
-    __syncthreads();
-    if (t == 0) {
-      double v = wv_v[0];
-      int i0 = wv_i[0];
-      for (int k = 1; k < 4; ++k)
-        if (wv_v[k] > v || (wv_v[k] == v && wv_i[k] < i0)) { v = wv_v[k]; i0 = wv_i[k]; }
-      s_piv = i0;
-      s_pv = M[i0 * LD + p];
-    }
-    __syncthreads();
-    const int piv = s_piv;
-    const double pv = s_pv;
-    if (pv == 0.0) break;                              // uniform: singular
-    if (t == 0) {
-      logdet += log(fabs(pv));
-      if (pv < 0.0) sgn = -sgn;
-      used[piv] = 1;
-      myk[piv] = p;
-      pi_[p] = piv;
-    }
-    const double pinv = 1.0 / pv;
-    for (int i = t; i < NS; i += 256) {
-      prow[i] = M[piv * LD + i];
-      const double mp = M[i * LD + p];
-      gcol[i] = (i == piv ? mp - 1.0 : mp) * pinv;
-    }
-    __syncthreads();
-    for (int u = t; u < NS * NS; u += 256) {
-      const int i = u / NS, j = u % NS;
-      const double g = gcol[i];
-      M[i * LD + j] = (j == p) ? ((i == piv ? 1.0 : 0.0) - g) : fma(-g, prow[j], M[i * LD + j]);
-    }
-    __syncthreads();
+    for (int b = 0; b < NBL; ++b)
+#pragma unroll
+      for (int j = 0; j < BC; ++j) x[b][j] = src[b * BC + j];
   }
-  if (s_pv == 0.0) {
+  bool used = false;
+  int myk = 0;
+  bool singular = false;
+#pragma unroll
+  for (int pb = 0; pb < 2 * NBL; ++pb) {
+    const int ph = pb / NBL, lb = pb % NBL;   // column half and block of the pivot columns
+    for (int q = 0; q < BC; ++q) {
+      const int p = pb * BC + q;
+      // column p of this thread's row (meaningful where h == ph)
+      double rp = x[lb][0];
+#pragma unroll
+      for (int j = 1; j < BC; ++j) rp = (j == q) ? x[lb][j] : rp;
+      if (h == ph) {                                    // wave-uniform
+        double bv = used ? -1.0 : fabs(rp);
+        int bi = r;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          const double ov = __shfl_xor(bv, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        const int wr = __builtin_amdgcn_readfirstlane(bi);
+        const double sv = readlane_d(rp, wr & 63);
+        if (lane == 0) {
+          cand_v[wave & 1] = bv;
+          cand_i[wave & 1] = wr;
+          cand_s[wave & 1] = sv;
+        }
+      }
+      __syncthreads();
+      const int hi = cand_v[1] > cand_v[0] ? 1 : 0;   // ties to the lower rows
+      const int piv = cand_i[hi];
+      const double pv = cand_s[hi];
+      if (pv == 0.0) { singular = true; break; }      // uniform
+      const bool me = r == piv;
+      if (me) { used = true; myk = p; }
+      if (h == 0 && r == p) { pi_s[p] = piv; pv_s[p] = pv; }
+      if (h == ph) {
+        gcol[r] = (me ? (pv - 1.0) : rp) * (1.0 / pv);
+        const double dv = me ? 1.0 : 0.0;
+#pragma unroll
+        for (int j = 0; j < BC; ++j) x[lb][j] = (j == q) ? dv : x[lb][j];
+      }
+      if (me) {
+        double2* pw2 = reinterpret_cast<double2*>(prow + HALF * h);
+#pragma unroll
+        for (int b = 0; b < NBL; ++b)
+#pragma unroll
+          for (int j = 0; j < BC; j += 2) pw2[(b * BC + j) / 2] = make_double2(x[b][j], x[b][j + 1]);
+      }
+      __syncthreads();
+      const double g = gcol[r];
+      const double2* pr2 = reinterpret_cast<const double2*>(prow + HALF * h);
+#pragma unroll
+      for (int b = 0; b < NBL; ++b)
+#pragma unroll
+        for (int j = 0; j < BC; j += 2) {
+          const double2 pv2 = pr2[(b * BC + j) / 2];
+          x[b][j] = fma(-g, pv2.x, x[b][j]);
+          x[b][j + 1] = fma(-g, pv2.y, x[b][j + 1]);
+        }
+    }
+    if (singular) break;
+  }
+  if (singular) {
     if (t == 0) {
       *a.status = 1;
       a.ldet[(size_t)w * 2 + sp] = -INFINITY;
@@ -278,22 +300,33 @@ __global__ __launch_bounds__(256) void k_invert_lds(WalkerArgs a, int spin_lo, i
     }
     return;
   }
-  // parity of pi: inversions counted per row, summed in a fixed order
-  int inv_cnt = 0;
-  if (t < NS)
-    for (int q = t + 1; q < NS; ++q) inv_cnt += pi_[q] < pi_[t] ? 1 : 0;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) inv_cnt += __shfl_xor(inv_cnt, off, 64);
-  if (lane == 0) wv_i[wave] = inv_cnt;
   __syncthreads();
-  for (int u = t; u < NS * NS; u += 256) {
-    const int r = u / NS, c = u % NS;
-    a.Binv[base + (size_t)myk[r] * NS + pi_[c]] = M[r * LD + c];
+  // parity of pi (thread r < NS counts q > r with pi(q) < pi(r)), the signs and the
+  // logarithms of the pivots, summed over the waves in a fixed order
+  int inv_cnt = 0;
+  double lsum = 0.0;
+  if (h == 0) {
+    const int mine = pi_s[r];
+    for (int q = r + 1; q < NS; ++q) inv_cnt += pi_s[q] < mine ? 1 : 0;
+    inv_cnt += pv_s[r] < 0.0 ? 1 : 0;
+    lsum = log(fabs(pv_s[r]));
   }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    inv_cnt += __shfl_xor(inv_cnt, off, 64);
+    lsum += __shfl_xor(lsum, off, 64);
+  }
+  if (lane == 0) { wv_cnt[wave] = inv_cnt; wv_ld[wave] = lsum; }
+  // row myk of A^-1: column pi(c) from x at c (pi(c) is the same for every lane of a wave)
+  double* dst = a.Binv + base + (size_t)myk * NS;
+#pragma unroll
+  for (int b = 0; b < NBL; ++b)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) dst[pi_s[HALF * h + b * BC + j]] = x[b][j];
+  __syncthreads();
   if (t == 0) {
-    if ((wv_i[0] + wv_i[1] + wv_i[2] + wv_i[3]) & 1) sgn = -sgn;
-    a.ldet[(size_t)w * 2 + sp] = logdet;
-    a.sgn[(size_t)w * 2 + sp] = sgn;
+    a.ldet[(size_t)w * 2 + sp] = (wv_ld[0] + wv_ld[1]) + (wv_ld[2] + wv_ld[3]);
+    a.sgn[(size_t)w * 2 + sp] = ((wv_cnt[0] + wv_cnt[1] + wv_cnt[2] + wv_cnt[3]) & 1) ? -1.0 : 1.0;
   }
 }
 
@@ -807,11 +840,10 @@ hipError_t launch_invert_t(const WalkerArgs& a, int spin_lo, int spin_hi, int on
   if constexpr (NS > 64) {          // one work-group per matrix
     dim3 g(bt ? nblk : a.W * (spin_hi - spin_lo));
     if (bt)
-      hipLaunchKernelGGL((k_invert_lds<NS, true>), g, dim3(256), InvLds<NS>::bytes, st, a, spin_lo, spin_hi,
-                         only_flagged, *bt);
+      hipLaunchKernelGGL((k_invert_big<NS, true>), g, dim3(256), 0, st, a, spin_lo, spin_hi, only_flagged, *bt);
     else
-      hipLaunchKernelGGL((k_invert_lds<NS, false>), g, dim3(256), InvLds<NS>::bytes, st, a, spin_lo, spin_hi,
-                         only_flagged, batch_or_none(bt));
+      hipLaunchKernelGGL((k_invert_big<NS, false>), g, dim3(256), 0, st, a, spin_lo, spin_hi, only_flagged,
+                         batch_or_none(bt));
     return hipGetLastError();
   } else {
     dim3 grid(bt ? nblk : (a.W * (spin_hi - spin_lo) + 3) / 4);
