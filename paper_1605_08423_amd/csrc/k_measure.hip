@@ -273,7 +273,9 @@ struct SlaterLds {
   static constexpr int N = 2 * NS;
   static constexpr int NSP = (NS + 15) / 16 * 16, NP = (N + 15) / 16 * 16;
   static constexpr int NT = (256 / N) * N;
-  static constexpr int LDB = NSP + 1, LDX = NP + 1, LDI = NSP + 1;
+  // X rows are read four consecutive k at a time; a stride of 4 mod 32 words keeps the
+  // 16 rows of such a read on disjoint LDS banks
+  static constexpr int LDB = NSP + 1, LDX = NP + 4, LDI = NSP + 1;
   static constexpr size_t head = (size_t)(3 * N + 3 * N + N) * sizeof(double) + (size_t)6 * N * sizeof(Real);
   static constexpr size_t bs = (size_t)NP * LDB * sizeof(Real);
   static constexpr size_t xm0 = (size_t)NSP * LDX * sizeof(Real);
@@ -293,6 +295,16 @@ struct SlaterLds {
   static constexpr size_t bytes = GSCR ? pad(head) + small : pad(head) + pad(bs) + xm;
   static constexpr size_t scr_bytes = GSCR ? pad(bs) + pad(bs > xm0 ? bs : xm0) + pad(mreg) : 0;
 };
+
+// Four consecutive values from a 16-byte aligned LDS address.
+__device__ __forceinline__ void load4(const float* p, float (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double* p, double (&o)[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+  o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
 
 // One wave's share of D = A B (TR x TC tiles of 16 x 16, K a multiple of 4, no padding)
 // with operands in device memory: tiles wave, wave + 4, ..., QC of them per pass over K.
@@ -545,17 +557,28 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
       typename MM16<Real>::acc_t acc[TPW_M];
 #pragma unroll
       for (int q = 0; q < TPW_M; ++q) acc[q] = MM16<Real>::zero();
-      for (int kk = 0; kk < NP / 4; ++kk) {
-        const int k = kk * 4 + l4;
+      // K in blocks of 16: step s of a block takes k = 16 kb + 4 (l / 16) + s in lane l, so
+      // each lane reads its four X values of the block at once.  Every tile of a wave has
+      // the same column tile (wave mod TI), so the B values are shared by the wave's tiles.
+      const int tcw = wave % TI;
+#pragma unroll 2
+      for (int kb = 0; kb < NP / 16; ++kb) {
+        const int k0 = 16 * kb + 4 * l4;
+        Real bq[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) bq[s] = (k0 + s < N) ? Bs[(k0 + s) * LDB + tcw * 16 + l16] : Real(0);
 #pragma unroll
         for (int q = 0; q < TPW_M; ++q) {
           const int tt = wave + 4 * q;
           if (tt < TI * TI) {
-            const int tr = tt / TI, tc = tt % TI;
-            const int irow = tr * 16 + l16;
-            const Real av = (irow < NS && k < N) ? Xr[irow * LDX + k] : Real(0);
-            const Real bv = (k < N) ? Bs[k * LDB + tc * 16 + l16] : Real(0);
-            acc[q] = MM16<Real>::step(av, bv, acc[q]);
+            const int irow = (tt / TI) * 16 + l16;
+            Real xa[4];
+            load4(Xr + irow * LDX + k0, xa);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              const Real av = (irow < NS && k0 + s < N) ? xa[s] : Real(0);
+              acc[q] = MM16<Real>::step(av, bq[s], acc[q]);
+            }
           }
         }
       }
