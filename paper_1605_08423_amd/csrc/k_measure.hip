@@ -78,12 +78,14 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
   __syncthreads();
   // Reciprocal space.  The (ny, nz) slots come sorted longest first; thread u of
   // an electron half (u = t mod 128) accumulates the slots of rank base + u and
-  // base + u + 128, nx counted from 0 (the k of (slot, nx) is k0 + nx - nx0), so
-  // one load of an electron's x phases serves both slots and every lane of a wave
-  // runs the wave's longest slot length, which its first lane holds.  When all
-  // slots fit one pass, waves 2 and 3 take electrons N/2..N-1 and hand their
-  // partial sums to waves 0 and 1 through LDS (over the phase table, no longer
-  // needed); otherwise waves 0 and 1 take every electron in passes of 256 slots.
+  // base + 255 - u (a long and a short one, so the two waves of a half get about the
+  // same work), nx counted from 0 (the k of (slot, nx) is k0 + nx - nx0), so one load
+  // of an electron's x phases serves both slots.  Every lane of a wave runs the wave's
+  // longest length of each slot, taken from a few compiled trip counts so the loop has
+  // no branches and its phase loads are issued together.  When all slots fit one
+  // pass, waves 2 and 3 take electrons N/2..N-1 and hand their partial sums to waves
+  // 0 and 1 through LDS (over the phase table, no longer needed); otherwise waves 0
+  // and 1 take every electron in passes of 256 slots.
   double vrec = 0.0, vreal = 0.0;
   double* racc = m.rho_acc + (size_t)w * e.nk * 2;
   const bool split = e.nslot <= 256;
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
       double sy[2], sz[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int sl = base + u + 128 * q;
+        const int sl = q == 0 ? base + u : base + 255 - u;
         ay[q] = az[q] = k0[q] = nx0[q] = nb[q] = 0;
         sy[q] = sz[q] = 1.0;
         if (sl < e.nslot) {
@@ -106,32 +108,52 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
           nb[q] = nx0[q] + e.slot[4 * sl + 3];
         }
       }
-      const int ba = __builtin_amdgcn_readfirstlane(nb[0]), bb = __builtin_amdgcn_readfirstlane(nb[1]);
+      int ma = nb[0], mb = nb[1];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        ma = max(ma, __shfl_xor(ma, off, 64));
+        mb = max(mb, __shfl_xor(mb, off, 64));
+      }
+      const int ba = __builtin_amdgcn_readfirstlane(ma), bb = __builtin_amdgcn_readfirstlane(mb);
       double ar[NMX + 1], ai[NMX + 1], br[NMX + 1], bi[NMX + 1];
 #pragma unroll
       for (int j = 0; j <= NMX; ++j) { ar[j] = ai[j] = br[j] = bi[j] = 0.0; }
       const int i_lo = split ? hf * (N / 2) : 0, i_hi = split ? (hf + 1) * (N / 2) : N;
-      for (int i = i_lo; i < i_hi; ++i) {
-        const double2 eya = ph[((size_t)1 * N + i) * NP1 + ay[0]], eza = ph[((size_t)2 * N + i) * NP1 + az[0]];
-        const double2 eyb = ph[((size_t)1 * N + i) * NP1 + ay[1]], ezb = ph[((size_t)2 * N + i) * NP1 + az[1]];
-        const double ya_r = eya.x, ya_i = sy[0] * eya.y, za_r = eza.x, za_i = sz[0] * eza.y;
-        const double yb_r = eyb.x, yb_i = sy[1] * eyb.y, zb_r = ezb.x, zb_i = sz[1] * ezb.y;
-        const double tar = ya_r * za_r - ya_i * za_i, tai = ya_r * za_i + ya_i * za_r;
-        const double tbr = yb_r * zb_r - yb_i * zb_i, tbi = yb_r * zb_i + yb_i * zb_r;
-        const double2* ex = ph + (size_t)i * NP1;
+      // NA, NBB: compiled trip counts of the two slots (>= the wave's ba, bb).  Phases
+      // past a row's end fall in the next row of the table (still inside it) and feed
+      // only accumulators that are never read.
+      auto electrons = [&](auto na_c, auto nb_c) {
+        constexpr int NA = decltype(na_c)::value, NBB = decltype(nb_c)::value;
+        constexpr int NX = NA > NBB ? NA : NBB;
+        for (int i = i_lo; i < i_hi; ++i) {
+          const double2* ex = ph + (size_t)i * NP1;
+          double2 xv[NX];
 #pragma unroll
-        for (int j = 0; j <= NMX; ++j) {
-          if (j < ba) {
-            const double2 x = ex[j];
-            ar[j] += x.x * tar - x.y * tai;
-            ai[j] += x.x * tai + x.y * tar;
-            if (j < bb) {
-              br[j] += x.x * tbr - x.y * tbi;
-              bi[j] += x.x * tbi + x.y * tbr;
-            }
+          for (int j = 0; j < NX; ++j) xv[j] = ex[j];
+          const double2 eya = ph[((size_t)1 * N + i) * NP1 + ay[0]], eza = ph[((size_t)2 * N + i) * NP1 + az[0]];
+          const double2 eyb = ph[((size_t)1 * N + i) * NP1 + ay[1]], ezb = ph[((size_t)2 * N + i) * NP1 + az[1]];
+          const double ya_r = eya.x, ya_i = sy[0] * eya.y, za_r = eza.x, za_i = sz[0] * eza.y;
+          const double yb_r = eyb.x, yb_i = sy[1] * eyb.y, zb_r = ezb.x, zb_i = sz[1] * ezb.y;
+          const double tar = ya_r * za_r - ya_i * za_i, tai = ya_r * za_i + ya_i * za_r;
+          const double tbr = yb_r * zb_r - yb_i * zb_i, tbi = yb_r * zb_i + yb_i * zb_r;
+#pragma unroll
+          for (int j = 0; j < NA; ++j) {
+            ar[j] += xv[j].x * tar - xv[j].y * tai;
+            ai[j] += xv[j].x * tai + xv[j].y * tar;
+          }
+#pragma unroll
+          for (int j = 0; j < NBB; ++j) {
+            br[j] += xv[j].x * tbr - xv[j].y * tbi;
+            bi[j] += xv[j].x * tbi + xv[j].y * tbr;
           }
         }
-      }
+      };
+      if (ba <= 8 && bb <= 7)
+        electrons(std::integral_constant<int, 8>{}, std::integral_constant<int, 7>{});
+      else if (ba <= 10 && bb <= 5)
+        electrons(std::integral_constant<int, 10>{}, std::integral_constant<int, 5>{});
+      else
+        electrons(std::integral_constant<int, NMX + 1>{}, std::integral_constant<int, NMX + 1>{});
       if (split) {
         // the second half's sums go to comb[k] (over the phase table), the first half adds them
         double2* comb = ph;
