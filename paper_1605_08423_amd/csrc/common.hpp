@@ -47,6 +47,71 @@ template <class T> __device__ __forceinline__ T readlane(T v, int lane);
 template <> __device__ __forceinline__ double readlane<double>(double v, int lane) { return readlane_d(v, lane); }
 template <> __device__ __forceinline__ float readlane<float>(float v, int lane) { return readlane_f(v, lane); }
 
+// Value held by lane (l ^ M) for M in {1, 2, 7, 15, 16, 32}: quad permutations and row
+// (half-)mirrors (i -> 7 - i, 15 - i, which are xor 7, xor 15 inside a row) by DPP, and the
+// gfx950 row-swap instructions across rows; all are register moves, no LDS round trip.
+// The six masks span all lane bits, so a butterfly over them reaches every lane.
+template <int M>
+__device__ __forceinline__ int xor_lane(int v) {
+  if constexpr (M == 1) {
+    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);    // quad_perm [1,0,3,2]
+  } else if constexpr (M == 2) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);    // quad_perm [2,3,0,1]
+  } else if constexpr (M == 7) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);   // row_half_mirror
+  } else if constexpr (M == 15) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);   // row_mirror
+  } else if constexpr (M == 16) {
+    // element 0: even rows keep theirs, odd rows get the even row's; element 1: the reverse
+    const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)((__lane_id() & 16) ? r[0] : r[1]);
+  } else {
+    static_assert(M == 32, "unsupported lane mask");
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)((__lane_id() & 32) ? r[0] : r[1]);
+  }
+}
+template <int M>
+__device__ __forceinline__ double xor_lane(double v) {
+  const int lo = xor_lane<M>(__double2loint(v)), hi = xor_lane<M>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+template <int M>
+__device__ __forceinline__ float xor_lane(float v) {
+  return __int_as_float(xor_lane<M>(__float_as_int(v)));
+}
+
+// Sum over the 64 lanes by the xor butterfly above.  Each step adds a lane's value and its
+// partner's (the same two operands in both lanes), so every lane ends with bit-identical
+// totals.
+template <class T>
+__device__ __forceinline__ T wave_allsum(T v) {
+  v += xor_lane<32>(v);
+  v += xor_lane<16>(v);
+  v += xor_lane<15>(v);
+  v += xor_lane<7>(v);
+  v += xor_lane<2>(v);
+  v += xor_lane<1>(v);
+  return v;
+}
+
+// Largest value over the 64 lanes and its index, ties to the lowest index (a total order,
+// so every lane ends with the same pair).
+template <int M>
+__device__ __forceinline__ void argmax_step(double& bv, int& bi) {
+  const double ov = xor_lane<M>(bv);
+  const int oi = xor_lane<M>(bi);
+  if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+}
+__device__ __forceinline__ void wave_argmax(double& bv, int& bi) {
+  argmax_step<32>(bv, bi);
+  argmax_step<16>(bv, bi);
+  argmax_step<15>(bv, bi);
+  argmax_step<7>(bv, bi);
+  argmax_step<2>(bv, bi);
+  argmax_step<1>(bv, bi);
+}
+
 // Sum over the 64 lanes of a wave in a fixed butterfly order; every lane gets lane 0's result.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

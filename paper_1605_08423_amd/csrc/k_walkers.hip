@@ -243,12 +243,7 @@ __global__ __launch_bounds__(256, 2) void k_invert_big(WalkerArgs a, int spin_lo
       if (h == ph) {                                    // wave-uniform
         double bv = used ? -1.0 : fabs(rp);
         int bi = r;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-          const double ov = __shfl_xor(bv, off, 64);
-          const int oi = __shfl_xor(bi, off, 64);
-          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-        }
+        wave_argmax(bv, bi);
         const int wr = __builtin_amdgcn_readfirstlane(bi);
         const double sv = readlane_d(rp, wr & 63);
         if (lane == 0) {
@@ -583,10 +578,9 @@ __global__ __launch_bounds__(256, NS > 64 ? 1 : 2) void k_sweep_half(WalkerArgs 
       // xor-butterfly sum kept in vector registers: every lane adds the same two
       // partial sums at every step, so all lanes hold the identical total and the
       // acceptance test below takes the same branch in every lane
-      double dU = (double)du;
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) dU += __shfl_xor(dU, off, 64);
-      const double pacc = q * q * exp(2.0 * dU);
+      const double dU = wave_allsum((double)du);
+      // the Jastrow factor in the working precision of the Jastrow terms
+      const double pacc = q * q * (double)dev_exp<Real>((Real)(2.0 * dU));
       double zrow[CPL];
 #pragma unroll
       for (int u = 0; u < CPL; ++u) zrow[u] = 0.0;
