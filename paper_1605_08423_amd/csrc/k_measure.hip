@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_ewald_sample(MeasureArgs m, EwaldArgs e
   double* part = pp + 3 * N;                       // 4 x N x 3 partial e-p gradients
   double2* ph = reinterpret_cast<double2*>(part + 12 * N);   // 3 x N x (nmax+1) phase powers
   __shared__ double red[4];
-  const int t = threadIdx.x, w = blk;
+  const int t = threadIdx.x & 255, w = blk;   // 256-thread launch
   const int NP1 = e.nmax + 1;
   const double L = m.L, invL = m.invL;
   for (int u = t; u < 3 * N; u += 256) {
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
   Real* trig = reinterpret_cast<Real*>(lU + N);        // N x 6 (sin x3, cos x3)
   constexpr bool GSCR = Lay::GSCR;
   __shared__ double red[4];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x & 255;   // (the launch has 256 threads; the mask lets the compiler bound t)
   // the walker index is re-derived from the block index at its uses (a long-lived copy costs registers)
   auto walker = [&]() -> int {
     return BATCH ? (int)blockIdx.x - bt.off[batch_job(bt, blockIdx.x)] : (int)blockIdx.x;
