@@ -109,6 +109,23 @@ def test_alone_equals_in_mix(dev):
     say(f"  ticks {info['ticks']}, peak resident {info['peak_resident'] / 1e6:.1f} MB")
 
 
+def test_large_box_alone_equals_in_mix(dev):
+    """The 256-proton box served beside smaller boxes (the large mixed form: one N = 256
+    trajectory in the same request loop as N = 54 ones, all mixed precision) gives the same
+    result as served alone, and so do the small ones."""
+    torch, vmc, ctx = dev
+    big = spec("h256", 800, 1, traj=30, steps=2, M=2, ne1=1)
+    small = [spec("h54", 176 + 8 * i, 1, traj=31 + i, steps=2, M=3) for i in range(3)]
+    say("[large box alone vs mix] N=256 W=800 with three N=54")
+    alone = [serve(vmc, ctx, [s])[0][0] for s in [big, small[0]]]
+    mixed, info = serve(vmc, ctx, [small[0], big, small[1], small[2]])
+    assert all(st[0] == vmc.VMC_REQ_DONE for st, _ in mixed)
+    for (sa, ra), (sm, rm) in zip(alone, [mixed[1], mixed[0]]):
+        assert sa[0] == sm[0] == vmc.VMC_REQ_DONE
+        assert np.array_equal(ra["R"], rm["R"]) and np.array_equal(ra["E"], rm["E"])
+    say(f"  ticks {info['ticks']}, peak resident {info['peak_resident'] / 1e9:.2f} GB")
+
+
 def test_budget_bounds_residency(dev):
     torch, vmc, ctx = dev
     specs = [spec("h16", 256, 0, traj=20 + i, steps=1) for i in range(5)]
