@@ -73,7 +73,7 @@ def _setup(l):
     l.o_cholesky.argtypes = [i, P(d), P(d)]
     l.o_langevin.argtypes = [i, d, P(d), P(d), P(d), P(d), P(d), d, d, d, C.c_uint, u32, u32, u32]
     l.o_langevin_harmonic_run.argtypes = [i, P(d), P(d), d, d, d, C.c_uint, u32, i, P(d), P(d), i]
-    l.o_toy_run.argtypes = [d, d, d, d, i, d, d, d, i, u32, i, P(d), P(d), P(d)]
+    l.o_toy_run.argtypes = [d, d, d, d, i, d, d, d, i, u32, u32, i, P(d), P(d), P(d)]
 
 
 class System:
@@ -232,12 +232,18 @@ def langevin_harmonic_run(K, S, T, Delta, alpha, n_steps, R0, flags=0, seed=0, s
     return samples
 
 
-def toy_run(lam, k, a, mu, s_kind, T, Delta, alpha, scheme, seed, n_steps, R0=(1.4, 0.0), keep=False):
+def toy_run(lam, k, a, mu, s_kind, T, Delta, alpha, scheme, seed, n_steps, R0=(1.4, 0.0), keep=False, traj=0,
+            final=False):
+    """The rotating spring of the SI: s_kind 0 S = G_lambda, 1 S = H + mu G_lambda, 2 S = I;
+    scheme 0 Eq. finaldyn_new (alpha = 0: Eq. finaldyn), 1 Eq. norogna, 2 Eq. standard with the
+    Gamma term by central differences.  Noise key (seed, traj), counter = step.  Returns the
+    mean U over the last 90% of the steps (and the U samples with keep, the final R with final)."""
     R = np.array(R0, dtype=np.float64)
     Um = np.zeros(1)
     Us = np.zeros(n_steps) if keep else None
-    rc = lib().o_toy_run(lam, k, a, mu, s_kind, T, Delta, alpha, scheme, seed, n_steps, _dp(R), _dp(Um),
+    rc = lib().o_toy_run(lam, k, a, mu, s_kind, T, Delta, alpha, scheme, seed, traj, n_steps, _dp(R), _dp(Um),
                          _dp(Us) if keep else None)
     if rc:
         raise RuntimeError(f"toy run failed rc={rc}")
-    return (Um[0], Us) if keep else Um[0]
+    out = (Um[0], Us) if keep else Um[0]
+    return (out, R) if final else out

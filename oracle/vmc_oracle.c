@@ -816,6 +816,11 @@ int o_langevin_harmonic_run(int n3, const double* K, const double* S, double T, 
  * G_lambda = n n^T / lambda + t t^T (radial eigenvalue 1/lambda, tangential 1).
  * s_kind 0: S = G_lambda; s_kind 1: S = H + mu G_lambda, H the Hessian of U. */
 static void toy_S(double lambda, double k, double a, double mu, int s_kind, const double x[2], double S[4]) {
+  if (s_kind == 2) {   /* S = I: the conventional first-order dynamics (black points of Fig. toy) */
+    S[0] = S[3] = 1.0;
+    S[1] = S[2] = 0.0;
+    return;
+  }
   double r = sqrt(x[0] * x[0] + x[1] * x[1]);
   double n[2] = {x[0] / r, x[1] / r}, t[2] = {-n[1], n[0]};
   for (int i = 0; i < 2; ++i)
@@ -839,7 +844,7 @@ static void inv2(const double S[4], double Si[4]) {
  * term Gamma_j = sum_i d_i S^-1_ji by central differences.  Returns the mean of
  * U over the last 90% of n_steps; U_samples (optional) gets U after every step. */
 int o_toy_run(double lambda, double k, double a, double mu, int s_kind, double T, double Delta,
-              double alpha, int scheme, uint32_t seed, int n_steps, double* R, double* U_mean,
+              double alpha, int scheme, uint32_t seed, uint32_t traj, int n_steps, double* R, double* U_mean,
               double* U_samples) {
   double Rp[2] = {R[0], R[1]}, S[4], Sp[4];
   toy_S(lambda, k, a, mu, s_kind, R, Sp);
@@ -852,7 +857,7 @@ int o_toy_run(double lambda, double k, double a, double mu, int s_kind, double T
     int rc;
     if (scheme == 0 || scheme == 1) {
       rc = o_langevin(2, 0.0, R, Rp, Sp, f, S, T, Delta, scheme == 0 ? alpha : 0.0,
-                      scheme == 1 ? O_STEP_NO_SCORR : 0u, seed, 0u, (uint32_t)t);
+                      scheme == 1 ? O_STEP_NO_SCORR : 0u, seed, traj, (uint32_t)t);
       if (rc) return rc;
     } else {
       double Si[4], Gam[2] = {0, 0}, h = 1e-6;
@@ -867,7 +872,7 @@ int o_toy_run(double lambda, double k, double a, double mu, int s_kind, double T
       }
       double Lc[4], xi[2], z[2];
       if (o_cholesky(2, S, Lc)) return O_ENOTSPD;
-      o_normals(seed, 0u, (uint32_t)t, 2, xi);
+      o_normals(seed, traj, (uint32_t)t, 2, xi);
       z[1] = xi[1] / Lc[3];
       z[0] = (xi[0] - Lc[2] * z[1]) / Lc[0];
       double amp = sqrt(2.0 * T * Delta);

@@ -58,7 +58,7 @@ int o_langevin_harmonic_run(int n3, const double* K, const double* S, double T, 
                             double alpha, unsigned flags, uint32_t seed, int n_steps,
                             double* R, double* samples, int sample_every);
 int o_toy_run(double lambda, double k, double a, double mu, int s_kind, double T, double Delta,
-              double alpha, int scheme, uint32_t seed, int n_steps, double* R, double* U_mean,
+              double alpha, int scheme, uint32_t seed, uint32_t traj, int n_steps, double* R, double* U_mean,
               double* U_samples);
 void o_normals(uint32_t seed, uint32_t traj, uint32_t step, int n, double* xi);
 

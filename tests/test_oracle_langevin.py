@@ -234,3 +234,25 @@ def test_toy_model_without_S_term_samples_wrong_distribution(oracle):
     assert wrong / (tm["T"] / 2) - 1.0 > 0.15
     un = np.mean([_toy(oracle, 1, 0.02, seed=s) for s in range(4)])
     assert un == pytest.approx(wrong, rel=0.04)
+
+
+def test_toy_model_conventional_dynamics_time_step_error(oracle):
+    """S = I (the conventional dynamics, black points of Fig. toy): the radial Euler step of an
+    Ornstein-Uhlenbeck mode of stiffness k has stationary variance T / (k (1 - k D / 2)), so <U>
+    exceeds T/2 by the factor 1 / (1 - k D / 2), up to corrections of order T / (k a^2) from the
+    planar geometry."""
+    tm = PAPER["toy_model"]
+    T, k = tm["T"], tm["k"]
+    for D in (0.01, 0.05, 0.2):
+        u = np.mean([_toy(oracle, 0, D, 0.0, seed=10 + s, s_kind=2) for s in range(4)])
+        assert u / (T / 2) == pytest.approx(1.0 / (1.0 - k * D / 2), rel=0.03), (D, u)
+
+
+def test_toy_noise_stream_follows_the_trajectory_id(oracle):
+    """Trajectory ids key the noise: equal ids give equal paths, different ids different ones."""
+    tm = PAPER["toy_model"]
+    args = (tm["lambda_used"], tm["k"], tm["a"], tm["mu"], 0, tm["T"], 0.3, 0.2, 0, 5, 50)
+    (_, r0) = oracle.toy_run(*args, traj=0, final=True)
+    (_, r0b) = oracle.toy_run(*args, traj=0, final=True)
+    (_, r1) = oracle.toy_run(*args, traj=1, final=True)
+    assert np.array_equal(r0, r0b) and not np.allclose(r0, r1)
