@@ -157,6 +157,29 @@ int vmc_langevin_step(vmc_ctx* ctx, int n3, double box_L, double* R_dev, double*
                       double Delta, double alpha, unsigned flags, uint32_t seed, uint32_t traj_id,
                       uint32_t step);
 
+/* The rotating-spring toy model (SI, "A simple toy model"; main text, figure of the toy
+ * model): U = k (|x| - a)^2 / 2 in the plane; S = G_lambda (radial eigenvalue 1/lambda,
+ * tangential 1; s_kind 0), S = H + mu G_lambda with H the Hessian of U (s_kind 1) or S = I
+ * (s_kind 2).  scheme 0: Eq. finaldyn_new (alpha = 0 is Eq. finaldyn); 1: Eq. norogna (no
+ * S-difference term); 2: Eq. standard with gamma = 0 and the drift-diffusion term of
+ * Eq. e:cumber, Gamma_j = sum_i d_i (S^-1)_ji, by central differences (h = 1e-6). */
+typedef struct {
+  double lambda, k, a, mu; /* G_lambda parameter, spring constant, ring radius, regulariser of H */
+  int s_kind;              /* 0 G_lambda, 1 H + mu G_lambda, 2 identity */
+  double T, Delta, alpha;  /* temperature, time step, alpha of Eq. finaldyn_new (scheme 0) */
+  int scheme;              /* 0 finaldyn_new, 1 norogna, 2 explicit Gamma */
+} vmc_toy_params;
+
+/* n_traj independent trajectories of n_steps steps, one GPU thread each.  R0_dev (n_traj x 2,
+ * device, read) are the starting points; R_dev (n_traj x 2, device, written) the end points;
+ * U_mean_dev (n_traj, device, written) the mean of U over the last 90% of the steps;
+ * status_dev (n_traj ints, device, written) 0, or 3 if S stopped being positive definite (the
+ * trajectory then stops there).  Trajectory i draws its step-t noise from the counter-based
+ * generator with key (seed, i) and counter t, like vmc_langevin_step with traj_id i.
+ * Asynchronous on the context stream; VMC_EINVAL for bad sizes or parameters. */
+int vmc_toy_run(vmc_ctx* ctx, const vmc_toy_params* params, int n_traj, int n_steps, uint32_t seed,
+                const double* R0_dev, double* R_dev, double* U_mean_dev, int* status_dev);
+
 /* Per-configuration quantities for K fixed electron configurations pos_dev
  * (K x N x 3): out_dev K x (2 + 6N) = [ln|psi|, E_L, dln|psi|/dR (3N), dE_L/dR (3N)]
  * at protons R_dev with C_dev, zeta_dev (main text, Eq. for V(R)). */

@@ -284,6 +284,124 @@ hipError_t launch_langevin(int n3, double L, double* R, double* R_prev, double* 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------- toy model ---
+// The rotating spring of the SI ("A simple toy model"): U = k (|x| - a)^2 / 2 in the plane,
+// with S = G_lambda (radial eigenvalue 1/lambda, tangential 1), S = H + mu G_lambda (H the
+// Hessian of U) or S = I.  One thread per independent trajectory; trajectory i draws its
+// noise with key (seed, i) at counter step t, the numbers of the single-trajectory step.
+// Schemes: 0 Eq. finaldyn_new (alpha = 0 gives Eq. finaldyn), 1 Eq. norogna (no
+// S-difference term), 2 Eq. standard with gamma = 0 and the drift-diffusion term
+// Gamma_j = sum_i d_i (S^-1)_ji by central differences.
+struct ToyArgs {
+  double lambda, k, a, mu, T, Delta, alpha;
+  int s_kind, scheme, n_steps, n_traj;
+  uint32_t seed;
+};
+
+__device__ __forceinline__ void toy_metric(const ToyArgs& p, double x, double y, double S[3]) {
+  if (p.s_kind == 2) { S[0] = 1.0; S[1] = 0.0; S[2] = 1.0; return; }
+  const double r = sqrt(x * x + y * y), nx = x / r, ny = y / r;
+  const double il = 1.0 / p.lambda;
+  // n n^T / lambda + t t^T with t = (-ny, nx)
+  S[0] = nx * nx * il + ny * ny;
+  S[1] = nx * ny * (il - 1.0);
+  S[2] = ny * ny * il + nx * nx;
+  if (p.s_kind == 1) {
+    // H = k n n^T + k (r - a) / r (I - n n^T)
+    const double c = p.k * (r - p.a) / r;
+    S[0] = p.k * nx * nx + c * (1.0 - nx * nx) + p.mu * S[0];
+    S[1] = p.k * nx * ny - c * nx * ny + p.mu * S[1];
+    S[2] = p.k * ny * ny + c * (1.0 - ny * ny) + p.mu * S[2];
+  }
+}
+
+// S^-1 of a symmetric 2 x 2 matrix (s00, s01, s11)
+__device__ __forceinline__ void toy_inv(const double S[3], double Si[3]) {
+  const double det = S[0] * S[2] - S[1] * S[1];
+  Si[0] = S[2] / det; Si[1] = -S[1] / det; Si[2] = S[0] / det;
+}
+
+__global__ __launch_bounds__(256) void k_toy(ToyArgs p, const double* R0, double* Rout, double* Umean,
+                                            int* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n_traj) return;
+  double x = R0[2 * i], y = R0[2 * i + 1], xp = x, yp = y;
+  double Sp[3];
+  toy_metric(p, x, y, Sp);
+  double Dt = p.Delta, Db = p.Delta;
+  if (p.scheme == 0 && p.alpha > 0.0) {
+    Dt = -expm1(-p.alpha * p.Delta) / p.alpha;
+    Db = -expm1(-2.0 * p.alpha * p.Delta) / (2.0 * p.alpha);
+  }
+  const int burn = p.n_steps / 10;
+  double usum = 0.0;
+  int st = 0;
+  for (int t = 0; t < p.n_steps; ++t) {
+    const double r = sqrt(x * x + y * y);
+    const double fx = -p.k * (r - p.a) * x / r, fy = -p.k * (r - p.a) * y / r;
+    double S[3];
+    toy_metric(p, x, y, S);
+    // S = L L^T and the two unit normals of step t
+    const double l00 = sqrt(S[0]), l10 = S[1] / l00, d11 = S[2] - l10 * l10;
+    if (!(S[0] > 0.0) || !(d11 > 0.0)) { st = 3; break; }
+    const double l11 = sqrt(d11);
+    const u32x4 o = philox((uint32_t)t, 0xFFFFFFFFu, 0u, 0u, p.seed, (uint32_t)i);
+    const double u1 = u01(o.x, o.y), u2 = u01(o.z, o.w);
+    const double rad = sqrt(-2.0 * log(1.0 - u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    // L^T z = xi: <z z^T> = S^-1
+    const double z1 = rad * sn / l11, z0 = (rad * cs - l10 * z1) / l00;
+    double dx, dy;
+    if (p.scheme == 2) {
+      double Si[3];
+      toy_inv(S, Si);
+      // Gamma_j = sum_i d/dx_i (S^-1)_ji, central differences of step h
+      const double h = 1e-6;
+      double Spx[3], Smx[3], Spy[3], Smy[3], Ipx[3], Imx[3], Ipy[3], Imy[3];
+      toy_metric(p, x + h, y, Spx); toy_metric(p, x - h, y, Smx);
+      toy_metric(p, x, y + h, Spy); toy_metric(p, x, y - h, Smy);
+      toy_inv(Spx, Ipx); toy_inv(Smx, Imx); toy_inv(Spy, Ipy); toy_inv(Smy, Imy);
+      const double g0 = (Ipx[0] - Imx[0]) / (2.0 * h) + (Ipy[1] - Imy[1]) / (2.0 * h);
+      const double g1 = (Ipx[1] - Imx[1]) / (2.0 * h) + (Ipy[2] - Imy[2]) / (2.0 * h);
+      const double amp = sqrt(2.0 * p.T * p.Delta);
+      dx = p.Delta * (Si[0] * fx + Si[1] * fy) + p.T * p.Delta * g0 + amp * z0;
+      dy = p.Delta * (Si[1] * fx + Si[2] * fy) + p.T * p.Delta * g1 + amp * z1;
+    } else {
+      // v = f - (S_prev - S)(R_prev - R) / (2 Db), then y = S^-1 v through L
+      double vx = fx, vy = fy;
+      if (p.scheme == 0) {
+        const double ex = xp - x, ey = yp - y;
+        vx -= ((Sp[0] - S[0]) * ex + (Sp[1] - S[1]) * ey) / (2.0 * Db);
+        vy -= ((Sp[1] - S[1]) * ex + (Sp[2] - S[2]) * ey) / (2.0 * Db);
+      }
+      const double w0 = vx / l00, w1 = (vy - l10 * w0) / l11;
+      const double y1 = w1 / l11, y0 = (w0 - l10 * y1) / l00;
+      const double amp = sqrt(2.0 * p.T * Db);
+      dx = Dt * y0 + amp * z0;
+      dy = Dt * y1 + amp * z1;
+    }
+    xp = x; yp = y;
+    Sp[0] = S[0]; Sp[1] = S[1]; Sp[2] = S[2];
+    x += dx; y += dy;
+    const double rn = sqrt(x * x + y * y);
+    if (t >= burn) usum += 0.5 * p.k * (rn - p.a) * (rn - p.a);
+  }
+  Rout[2 * i] = x;
+  Rout[2 * i + 1] = y;
+  const int cnt = p.n_steps - burn;
+  Umean[i] = usum / (double)(cnt > 0 ? cnt : 1);
+  status[i] = st;
+}
+
+hipError_t launch_toy(double lambda, double k, double a, double mu, int s_kind, double T, double Delta,
+                      double alpha, int scheme, uint32_t seed, int n_traj, int n_steps, const double* R0,
+                      double* Rout, double* Umean, int* status, hipStream_t st) {
+  ToyArgs p{lambda, k, a, mu, T, Delta, alpha, s_kind, scheme, n_steps, n_traj, seed};
+  hipLaunchKernelGGL(k_toy, dim3((n_traj + 255) / 256), dim3(256), 0, st, p, R0, Rout, Umean, status);
+  return hipGetLastError();
+}
+
 // Packs per-configuration results: [ln|psi|, E_L, dln|psi|/dR, dE_L/dR].
 __global__ void k_pack_eval(int K, int N, const double* means, const double* ldet, const double* Uj, double* out) {
   const int k = blockIdx.x;

@@ -118,6 +118,10 @@ hipError_t launch_langevin(int n3, double L, double* R, double* R_prev, double* 
                            hipStream_t st);
 size_t syrk_partial_doubles(int W, int n3);
 size_t reduce_partial_doubles(int W, int n3);
+// Independent toy-model trajectories (the rotating spring of the SI), one thread each.
+hipError_t launch_toy(double lambda, double k, double a, double mu, int s_kind, double T, double Delta,
+                      double alpha, int scheme, uint32_t seed, int n_traj, int n_steps, const double* R0,
+                      double* Rout, double* Umean, int* status, hipStream_t st);
 hipError_t launch_pack_eval(int K, int N, const double* means, const double* ldet, const double* Uj, double* out,
                             hipStream_t st);
 

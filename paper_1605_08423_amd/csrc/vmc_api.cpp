@@ -21,9 +21,9 @@ using namespace vmc;
 namespace {
 
 enum KClass { K_SETUP, K_BUILD_A, K_INVERT, K_REFINE, K_SWEEP, K_EWALD, K_SLATER, K_FINALIZE, K_REDUCE, K_SYRK,
-              K_LANGEVIN, K_NCLASS };
+              K_LANGEVIN, K_TOY, K_NCLASS };
 const char* kClassName[K_NCLASS] = {"proton_setup", "build_A", "invert", "refine", "sweep_half", "ewald_sample",
-                                    "slater_sample", "finalize", "reduce", "syrk", "langevin"};
+                                    "slater_sample", "finalize", "reduce", "syrk", "langevin", "toy"};
 
 struct Pending { int cls; hipEvent_t a, b; };
 
@@ -520,6 +520,18 @@ int vmc_langevin_step(vmc_ctx* ctx, int n3, double L, double* R, double* R_prev,
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (st == 3) return VMC_ENOTSPD;
   if (st == 1) return VMC_EINVAL;
+  return VMC_OK;
+}
+
+int vmc_toy_run(vmc_ctx* ctx, const vmc_toy_params* p, int n_traj, int n_steps, uint32_t seed, const double* R0,
+                double* R, double* U_mean, int* status) {
+  if (!ctx || !p || n_traj < 1 || n_steps < 1 || !R0 || !R || !U_mean || !status) return VMC_EINVAL;
+  if (!(p->lambda > 0.0) || !(p->k >= 0.0) || !(p->mu >= 0.0) || !(p->T >= 0.0) || !(p->Delta > 0.0) ||
+      !(p->alpha >= 0.0) || p->s_kind < 0 || p->s_kind > 2 || p->scheme < 0 || p->scheme > 2)
+    return VMC_EINVAL;
+  HIPCHK(hipSetDevice(ctx->device));
+  RUN(K_TOY, launch_toy(p->lambda, p->k, p->a, p->mu, p->s_kind, p->T, p->Delta, p->alpha, p->scheme, seed, n_traj,
+                        n_steps, R0, R, U_mean, status, ctx->stream));
   return VMC_OK;
 }
 

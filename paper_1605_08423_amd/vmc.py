@@ -23,7 +23,7 @@ EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_
             "vmc_build_S_raw", "vmc_langevin_step", "vmc_eval_configs", "vmc_huckel_params",
             "vmc_request_bytes", "vmc_server_admit_count", "vmc_server_create", "vmc_server_destroy",
             "vmc_server_submit", "vmc_server_cancel", "vmc_server_tick", "vmc_server_status",
-            "vmc_server_result", "vmc_server_info"]
+            "vmc_server_result", "vmc_server_info", "vmc_toy_run"]
 VMC_REQ_QUEUED, VMC_REQ_RUNNING, VMC_REQ_DONE, VMC_REQ_FAILED, VMC_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
@@ -85,6 +85,7 @@ def _declare(l):
     l.vmc_build_S_raw.argtypes = [vp, i, i, vp, vp, vp]
     l.vmc_langevin_step.argtypes = [vp, i, d, vp, vp, vp, vp, vp, d, d, d, C.c_uint, u32, u32, u32]
     l.vmc_eval_configs.argtypes = [vp, P(vmc_system), vp, vp, vp, i, vp, vp]
+    l.vmc_toy_run.argtypes = [vp, P(vmc_toy_params), i, i, u32, vp, vp, vp, vp]
     l.vmc_huckel_params.argtypes = [i, d, P(d), P(d), P(d)]
     sz = C.c_size_t
     l.vmc_request_bytes.restype = sz
@@ -246,6 +247,31 @@ def vmc_langevin_step(ctx: Context, R, R_prev, S_prev, f, S, T, Delta, alpha, fl
     return _lib().vmc_langevin_step(ctx.h, n3, float(box_L), _dev(R), _dev(R_prev, n3), _dev(S_prev, n3 * n3),
                                     _dev(f, n3), _dev(S, n3 * n3), float(T), float(Delta), float(alpha), int(flags),
                                     int(seed), int(traj_id), int(step))
+
+
+class vmc_toy_params(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("k", C.c_double), ("a", C.c_double), ("mu", C.c_double),
+                ("s_kind", C.c_int), ("T", C.c_double), ("Delta", C.c_double), ("alpha", C.c_double),
+                ("scheme", C.c_int)]
+
+
+TOY_S_G, TOY_S_HESSIAN, TOY_S_IDENTITY = 0, 1, 2
+TOY_FINALDYN_NEW, TOY_NOROGNA, TOY_EXPLICIT_GAMMA = 0, 1, 2
+
+
+def vmc_toy_run(ctx: Context, R0, n_steps, lam, k, a, mu, s_kind, T, Delta, alpha, scheme, seed=0):
+    """Independent toy-model trajectories (one GPU thread each) from R0 (n x 2 CUDA float64).
+    Returns (R, U_mean, status) tensors on the device."""
+    import torch
+    n = R0.shape[0]
+    R = torch.empty_like(R0)
+    U = torch.empty(n, dtype=torch.float64, device=R0.device)
+    st = torch.empty(n, dtype=torch.int32, device=R0.device)
+    p = vmc_toy_params(float(lam), float(k), float(a), float(mu), int(s_kind), float(T), float(Delta),
+                       float(alpha), int(scheme))
+    _check(_lib().vmc_toy_run(ctx.h, C.byref(p), n, int(n_steps), int(seed), _dev(R0, 2 * n), _dev(R, 2 * n),
+                              _dev(U, n), C.c_void_p(st.data_ptr())), "vmc_toy_run")
+    return R, U, st
 
 
 def vmc_eval_configs(ctx: Context, system: vmc_system, R, Cmo, zeta, pos, out=None):
