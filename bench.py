@@ -97,6 +97,86 @@ def run_cpu_baseline(wl, Cm, walkers: int, sweeps: int, threads: int):
     return walkers * sweeps / dt, dt
 
 
+# FP64 operations of one toy-model trajectory step (FMA = 2; sqrt, division, log and sincos
+# count 1): metric and force 30, 2 x 2 Cholesky and solves 20, Box-Muller 8, S-difference
+# term and update 22, U 6; Philox's integer rounds are not counted.
+TOY_FLOP_PER_STEP = 86
+# the series of the toy figure: (label, s_kind, scheme, alpha)
+TOY_SERIES = [("S=I, Eq. finaldyn", 2, 0, 0.0), ("S=G, Eq. finaldyn", 0, 0, 0.0),
+              ("S=G, explicit Gamma", 0, 2, 0.0), ("S=G, Eq. finaldyn_new a=0.2", 0, 0, 0.2),
+              ("S=H+mu G, Eq. finaldyn_new a=0.2", 1, 0, 0.2), ("S=G, Eq. norogna", 0, 1, 0.0)]
+TOY_DELTAS = [0.05, 0.1, 0.2, 0.4, 0.7, 1.0]
+
+
+def run_toy(args):
+    """The toy figure as a GPU workload: every (series, Delta) point is an ensemble of
+    independent trajectories; prints one JSON line with the trajectory-step rate and the
+    figure's data (<U>/(T/2) - 1 with its standard error)."""
+    import torch
+    from paper_1605_08423_amd import vmc
+    tm = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_constants.json")))["toy_model"]
+    ctx = vmc.Context(0)
+    n, steps = args.toy_traj, args.toy_steps
+    rng = np.random.default_rng(7)
+    th = rng.uniform(0.0, 2.0 * np.pi, n)
+    R0 = torch.tensor(np.stack([tm["a"] * np.cos(th), tm["a"] * np.sin(th)], axis=1), dtype=torch.float64,
+                      device="cuda")
+    half_T = tm["T"] / 2
+    run = lambda sk, sc, D, al, seed: vmc.vmc_toy_run(ctx, R0, steps, tm["lambda_used"], tm["k"], tm["a"],
+                                                       tm["mu"], sk, tm["T"], D, al, sc, seed)
+    run(0, 0, 0.1, 0.2, 1)                     # warm-up
+    torch.cuda.synchronize()
+    ctx.reset_kernel_times()
+    ctx.set_profiling(True)
+    figure, unstable = {}, {}
+    t0 = time.perf_counter()
+    outs = []
+    for label, sk, sc, al in TOY_SERIES:
+        for D in TOY_DELTAS:
+            outs.append((label, D, run(sk, sc, D, al, 1000 + len(outs))))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    times = ctx.kernel_times()
+    ctx.set_profiling(False)
+    for label, D, (_, U, st) in outs:
+        Uh, sth = U.cpu().numpy(), st.cpu().numpy()
+        ok = (sth == 0) & np.isfinite(Uh) & (Uh < 1e3 * half_T)
+        key = f"{D:g}"
+        figure.setdefault(label, {})[key] = (
+            [round(float(Uh[ok].mean() / half_T - 1.0), 5), round(float(Uh[ok].std() / np.sqrt(ok.sum()) / half_T), 5)]
+            if ok.sum() > 1 else None)
+        if (~ok).sum():
+            unstable.setdefault(label, {})[key] = int((~ok).sum())
+    n_points = len(outs)
+    total_steps = n_points * n * steps
+    ms, nl = times["toy"]
+    avg_s = ms / max(nl, 1) / 1e3
+    achieved = TOY_FLOP_PER_STEP * n * steps / avg_s / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        ncpu, t1 = 40000, time.perf_counter()       # about 10 s of one CPU thread
+        for i in range(ncpu):
+            O.toy_run(tm["lambda_used"], tm["k"], tm["a"], tm["mu"], 0, tm["T"], 0.2, 0.2, 0, 3, steps, traj=i)
+        dt = time.perf_counter() - t1
+        cpu = {"value": round(ncpu * steps / dt, 1), "unit": "trajectory-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{ncpu} trajectories x {steps} steps (S=G, Eq. finaldyn_new), one thread, {dt:.1f} s"}
+    line = {
+        "metric": "toy-model Langevin trajectory-steps/s (rotating spring, SI)", "value": round(total_steps / wall, 1),
+        "unit": "trajectory-steps/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"toy figure: {len(TOY_SERIES)} series x {len(TOY_DELTAS)} time steps, {n} independent "
+                               f"trajectories x {steps} steps per point, T={tm['T']}, k={tm['k']}, a={tm['a']}, "
+                               f"lambda={tm['lambda_used']}, mu={tm['mu']}"},
+        "wall_s": round(wall, 3),
+        "roofline": {"bound": "alu", "kernel": "toy", "achieved": round(achieved, 3), "peak": PEAK["valu"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["valu"], 4), "traffic": None,
+                     "avg_launch_ms": round(avg_s * 1e3, 3), "flop_per_trajectory_step": TOY_FLOP_PER_STEP},
+        "cpu_baseline": cpu,
+        "figure_U_over_half_T_minus_1": figure, "unstable_trajectories": unstable,
+    }
+    print(json.dumps(line))
+
+
 SERVE_WALKERS = {16: 1024, 32: 2048, 54: 4096, 128: 16384}
 
 
@@ -216,7 +296,16 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=3)
     ap.add_argument("--serve-sweeps", type=int, default=20)
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
+    ap.add_argument("--toy", action="store_true", help="the toy-model figure as a GPU workload instead")
+    ap.add_argument("--toy-traj", type=int, default=65536)
+    ap.add_argument("--toy-steps", type=int, default=2000)
     args = ap.parse_args()
+    if args.toy:
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only.", file=sys.stderr)
+            sys.exit(2)
+        run_toy(args)
+        return
     if args.serve or args.serve_mix == "large":
         if args.gpus != 1:
             print("bench.py runs on one GPU only.", file=sys.stderr)
