@@ -314,7 +314,9 @@ struct SlaterLds {
   static constexpr size_t jpart = (size_t)((256 / N) > 0 ? (256 / N) : 1) * N * 5 * sizeof(double);
   static constexpr size_t small = xm23 > jpart ? xm23 : jpart;
   static constexpr size_t mreg = (size_t)NSP * LDI * sizeof(Real);
-  static constexpr size_t bytes = GSCR ? pad(head) + small : pad(head) + pad(bs) + xm;
+  // staging of one 16-row tile of a left operand: 16 x (K + pad) elements, K <= 2 NSP
+  static constexpr size_t stage = (size_t)16 * (2 * NSP + 2) * sizeof(double);
+  static constexpr size_t bytes = GSCR ? pad(head) + pad(small) + stage : pad(head) + pad(bs) + xm;
   static constexpr size_t scr_bytes = GSCR ? pad(bs) + pad(bs > xm0 ? bs : xm0) + pad(mreg) : 0;
 };
 
@@ -328,37 +330,33 @@ __device__ __forceinline__ void load4(const double* p, double (&o)[4]) {
   o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
 }
 
-// One wave's share of D = A B (TR x TC tiles of 16 x 16, K a multiple of 4, no padding)
-// with operands in device memory: tiles wave, wave + 4, ..., QC of them per pass over K.
-template <class Op, class Out, int TR, int TC, int K, int QC>
-__device__ __forceinline__ void wave_gemm(const Op* A, int lda, const Op* B, int ldb, Out* D, int ldd, int wave,
-                                          int l16, int l4) {
-  constexpr int TPW = (TR * TC + 3) / 4;
-  for (int q0 = 0; q0 < TPW; q0 += QC) {
-    typename MM16<Op>::acc_t acc[QC];
+// D = A B for TC = 8 column tiles: wave w computes tiles 2w and 2w + 1, one at a time, keeping
+// that tile's B columns for the whole K in registers (B operand layout, read once per pass),
+// while the work-group stages A one 16-row tile at a time in LDS (coalesced reads; rows padded
+// to K + 1 doubles or K + 2 floats so the 16 rows of an A-operand read fall on distinct banks).
+// All threads of the work-group call it.
+template <class Op, class Out, int TR, int K>
+__device__ __forceinline__ void gemm_stage_a(const Op* A, int lda, const Op* B, int ldb, Out* D, int ldd, Op* stage,
+                                             int t, int wave, int l16, int l4) {
+  constexpr int KK = K / 4, LDA_S = K + (sizeof(Op) == 8 ? 1 : 2);
+  for (int c = 0; c < 2; ++c) {
+    const int col = 16 * (2 * wave + c) + l16;
+    Op breg[KK];
 #pragma unroll
-    for (int q = 0; q < QC; ++q) acc[q] = MM16<Op>::zero();
-    for (int kk = 0; kk < K / 4; ++kk) {
-      const int k = 4 * kk + l4;
+    for (int kk = 0; kk < KK; ++kk) breg[kk] = B[(4 * kk + l4) * ldb + col];
+    for (int rt = 0; rt < TR; ++rt) {
+      __syncthreads();                       // the previous tile is consumed
+      for (int u = t; u < 16 * K; u += 256)
+        stage[(u / K) * LDA_S + u % K] = A[(size_t)(16 * rt + u / K) * lda + u % K];
+      __syncthreads();
+      typename MM16<Op>::acc_t acc = MM16<Op>::zero();
 #pragma unroll
-      for (int q = 0; q < QC; ++q) {
-        const int tt = wave + 4 * (q0 + q);
-        if (q0 + q < TPW && tt < TR * TC) {
-          const int tr = tt / TC, tc = tt % TC;
-          acc[q] = MM16<Op>::step(A[(tr * 16 + l16) * lda + k], B[k * ldb + tc * 16 + l16], acc[q]);
-        }
-      }
-    }
+      for (int kk = 0; kk < KK; ++kk) acc = MM16<Op>::step(stage[l16 * LDA_S + 4 * kk + l4], breg[kk], acc);
 #pragma unroll
-    for (int q = 0; q < QC; ++q) {
-      const int tt = wave + 4 * (q0 + q);
-      if (q0 + q < TPW && tt < TR * TC) {
-        const int tr = tt / TC, tc = tt % TC;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) D[(tr * 16 + MM16<Op>::row(l4, v)) * ldd + tc * 16 + l16] = (Out)acc[q][v];
-      }
+      for (int v = 0; v < 4; ++v) D[(size_t)(16 * rt + MM16<Op>::row(l4, v)) * ldd + col] = (Out)acc[v];
     }
   }
+  __syncthreads();
 }
 
 template <int NS, class Real, int NIMG, bool BATCH>
@@ -393,6 +391,8 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
   Real* Xr = reinterpret_cast<Real*>(xmb);             // NSP x LDX : X (GSCR: later W)
   double* XM = reinterpret_cast<double*>(xmb);         // NSP x LDI : A^-1, then M
   double* SM = GSCR ? reinterpret_cast<double*>(lds2) : XM;   // partial sums
+  double* stg_d = reinterpret_cast<double*>(lds2 + Lay::pad(Lay::small));   // GSCR operand staging
+  Real* stg_r = reinterpret_cast<Real*>(stg_d);
   Real* Ws = GSCR ? Xr : Bs;
   const int lane = t & 63, wave = t >> 6, l16 = lane & 15, l4 = lane >> 4;
   const double L = m.L, invL = m.invL;
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
     const double* Bi = m.Binv + ((size_t)walker() * 2 + sp) * NS * NS;
     if constexpr (GSCR) {
       // B = C A^-1 with both operands read from device memory
-      wave_gemm<double, Real, TA, TI, NS, 8>(m.C, NS, Bi, NS, Bs, LDB, wave, l16, l4);
+      gemm_stage_a<double, Real, TA, NS>(m.C, NS, Bi, NS, Bs, LDB, stg_d, t, wave, l16, l4);
     } else {
       constexpr int PER = (NSP * NSP + 255) / 256;   // all loads issued before the stores
       double v[PER];
@@ -571,9 +571,9 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
     Real* Mr = GSCR ? reinterpret_cast<Real*>(gsc + Lay::pad(Lay::bs) + Lay::pad(Lay::bs > Lay::xm0 ? Lay::bs : Lay::xm0))
                     : reinterpret_cast<Real*>(XM);
     if constexpr (GSCR) {
-      wave_gemm<Real, Real, TI, TI, N, 8>(Xr, LDX, Bs, LDB, Mr, LDI, wave, l16, l4);
+      gemm_stage_a<Real, Real, TI, N>(Xr, LDX, Bs, LDB, Mr, LDI, stg_r, t, wave, l16, l4);
       __syncthreads();
-      wave_gemm<Real, Real, TA, TI, NS, 8>(Bs, LDB, Mr, LDI, Ws, LDB, wave, l16, l4);
+      gemm_stage_a<Real, Real, TA, NS>(Bs, LDB, Mr, LDI, Ws, LDB, stg_r, t, wave, l16, l4);
     } else {
     {
       typename MM16<Real>::acc_t acc[TPW_M];
