@@ -70,7 +70,7 @@ typedef struct {
                          X <- X + X (I - A X) in FP64, and Gauss-Jordan elimination for
                          every matrix with max|I - A X| > refine_tol (or not finite).
                          0 = default (1e-7); < 0 = elimination for every matrix.
-                         N = 256 (128 x 128 matrices) always refreshes by elimination */
+                         At N = 256 the step uses the walker's measurement scratch for I - A X */
 } vmc_system;
 
 /* ---------------------------------------------------------------- context -- */

@@ -816,6 +816,83 @@ __global__ __launch_bounds__(256, 1) void k_refine(WalkerArgs a, int sp, double 
   if (lane == 0 && !(rmax <= tol)) a.rflag[(size_t)w * 2 + sp] = 1;
 }
 
+// The refinement step for NS = 128, where X and A do not fit in registers: one 512-thread
+// work-group per matrix.  Both products take the right operand's column tile w of wave w in
+// registers (read once) and stage the left operand 16 rows at a time in LDS, row tiles in
+// the outer loop so X can be updated in place (row tile rt of X + X R needs only row tile rt
+// of X).  R = I - A X goes to the walker's scratch between the two products.
+template <int NS, bool BATCH>
+__global__ __launch_bounds__(512, 1) void k_refine_big(WalkerArgs a, int sp, double tol, Batch bt) {
+  static_assert(NS == 128, "eight column tiles, one per wave");
+  constexpr int KK = NS / 4, NRT = NS / 16, LDS_S = NS + 1, NTH = 512;
+  __shared__ double stage[16 * LDS_S];
+  __shared__ double wmax[8];
+  int blk = blockIdx.x;
+  if constexpr (BATCH) {
+    const int j = batch_job(bt, blk);
+    a = bt.jobs[j].a;
+    tol = bt.jobs[j].tol;
+    blk -= bt.off[j];
+  }
+  const int t = threadIdx.x & (NTH - 1), lane = t & 63, wave = t >> 6, l16 = lane & 15, l4 = lane >> 4;
+  const int w = blk;
+  if (w >= a.W) return;                      // the whole work-group
+  const size_t base = ((size_t)w * 2 + sp) * NS * NS;
+  double* Xg = a.Binv + base;
+  const double* Ag = a.Amat + base;
+  double* Rg = a.rscr + (size_t)w * a.rscr_stride;
+  const int col = 16 * wave + l16;
+  double breg[KK];
+  auto stage_rows = [&](const double* src, int rt) {
+    __syncthreads();                          // the previous tile is consumed
+    for (int u = t; u < 16 * NS; u += NTH) stage[(u / NS) * LDS_S + u % NS] = src[(size_t)(16 * rt + u / NS) * NS + u % NS];
+    __syncthreads();
+  };
+  // R = I - A X
+#pragma unroll
+  for (int kk = 0; kk < KK; ++kk) breg[kk] = Xg[(4 * kk + l4) * NS + col];
+  double rmax = 0.0;
+  for (int rt = 0; rt < NRT; ++rt) {
+    stage_rows(Ag, rt);
+    d4w_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) acc = mfma_w(stage[l16 * LDS_S + 4 * kk + l4], breg[kk], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * rt + l4 + 4 * v;
+      const double r = (row == col ? 1.0 : 0.0) - acc[v];
+      Rg[(size_t)row * NS + col] = r;
+      rmax = fmax(rmax, fabs(r)) + (r - r);     // NaN propagates
+    }
+  }
+  // X + X R, row tile by row tile, in place (each wave reads back only its own columns of R)
+#pragma unroll
+  for (int kk = 0; kk < KK; ++kk) breg[kk] = Rg[(size_t)(4 * kk + l4) * NS + col];
+  for (int rt = 0; rt < NRT; ++rt) {
+    stage_rows(Xg, rt);
+    d4w_t acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = stage[(l4 + 4 * v) * LDS_S + col];
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) acc = mfma_w(stage[l16 * LDS_S + 4 * kk + l4], breg[kk], acc);
+    // row tile rt is in LDS for every wave before any wave writes it back
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Xg[(size_t)(16 * rt + l4 + 4 * v) * NS + col] = acc[v];
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double o = __shfl_xor(rmax, off, 64);
+    rmax = (o > rmax || o != o) ? o : rmax;
+  }
+  if (lane == 0) wmax[wave] = rmax;
+  __syncthreads();
+  if (t == 0) {
+    double m = wmax[0];
+    for (int q = 1; q < 8; ++q) m = (wmax[q] > m || wmax[q] != wmax[q]) ? wmax[q] : m;
+    if (!(m <= tol)) a.rflag[(size_t)w * 2 + sp] = 1;
+  }
+}
+
 // ----------------------------------------------------------- launchers ---
 template <int NS, class Real>
 hipError_t launch_build_A_t(const WalkerArgs& a, hipStream_t st) {
@@ -850,8 +927,14 @@ hipError_t launch_invert_t(const WalkerArgs& a, int spin_lo, int spin_hi, int on
 }
 template <int NS>
 hipError_t launch_refine_t(const WalkerArgs& a, int spin, double tol, hipStream_t st, const Batch* bt, int nblk) {
-  if constexpr (NS > 64) {
-    return hipErrorInvalidValue;   // no register-resident refinement: refresh by elimination
+  if constexpr (NS > 64) {          // one work-group per matrix, scratch for R
+    if (!a.rscr) return hipErrorInvalidValue;
+    dim3 g(bt ? nblk : a.W);
+    if (bt)
+      hipLaunchKernelGGL((k_refine_big<NS, true>), g, dim3(512), 0, st, a, spin, tol, *bt);
+    else
+      hipLaunchKernelGGL((k_refine_big<NS, false>), g, dim3(512), 0, st, a, spin, tol, batch_or_none(bt));
+    return hipGetLastError();
   } else {
     dim3 grid(bt ? nblk : (a.W + 3) / 4);
     if (bt)

@@ -21,6 +21,8 @@ struct WalkerArgs {
   int* status;         // set to 1 on a zero pivot
   int64_t* nacc;       // W accepted moves
   int* rflag;          // W x 2: 1 = the refinement step left a large residual, redo by elimination
+  double* rscr;        // N_sigma > 64: per-walker scratch of the refinement (N_sigma^2 doubles at rscr_stride)
+  size_t rscr_stride;
 };
 
 struct SweepArgs {

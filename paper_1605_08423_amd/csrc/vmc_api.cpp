@@ -219,6 +219,10 @@ WalkerArgs walker_args(vmc_traj* t, const double* R, const double* C, const doub
   a.a_par = t->sys.a_par; a.a_anti = t->sys.a_anti; a.b = t->sys.b;
   a.pos = t->pos; a.Amat = t->Amat; a.Binv = t->Binv; a.ldet = t->ldet; a.sgn = t->sgn;
   a.status = t->ctx->d_status; a.nacc = t->nacc; a.rflag = t->rflag;
+  // N_sigma > 64: the refinement's R uses the first N_sigma^2 doubles of the walker's
+  // measurement scratch (the measurement never runs during a refresh)
+  a.rscr = reinterpret_cast<double*>(t->scr);
+  a.rscr_stride = slater_scratch_bytes(t->NS, t->sys.precision == VMC_MIXED) / sizeof(double);
   return a;
 }
 
@@ -435,8 +439,7 @@ int vmc_energy_forces(vmc_traj* t, const double* R, const double* C, const doubl
   const int total = n_equil + n_sweeps;
   for (int s = 0; s < total; ++s) {
     for (int sp = 0; sp < 2; ++sp) {
-      // N_sigma > 64: no register-resident refinement, the inverse is refreshed by elimination
-      if (s == 0 || rtol < 0.0 || t->NS > 64) {
+      if (s == 0 || rtol < 0.0) {
         RUN(K_INVERT, launch_invert(a, sp, sp + 1, 0, st));
       } else {
         RUN(K_REFINE, launch_refine(a, sp, rtol, st));
@@ -950,7 +953,7 @@ int bucket_sweep(vmc_server* s, const std::vector<Served*>& qs) {
     const TrajJob j = make_job(q, q->sweep);
     js.push_back(j);
     os.push_back(os.back() + (q->t->W + 3) / 4);
-    // refresh blocks: four walkers each (refinement), or one matrix each (elimination, N_sigma > 64)
+    // refresh blocks: four walkers each, or one matrix each for N_sigma > 64
     if (q->sweep >= 1) { jr.push_back(j); orf.push_back(orf.back() + (q->t->NS > 64 ? q->t->W : (q->t->W + 3) / 4)); }
     if (q->sweep >= q->n_equil_cur) { jm.push_back(j); om.push_back(om.back() + q->t->W); }
   }
@@ -1000,9 +1003,7 @@ int bucket_sweep(vmc_server* s, const std::vector<Served*>& qs) {
   const int mixed = qs[0]->req.sys.precision == VMC_MIXED;
   const TrajJob& j0 = js[0];
   for (int sp = 0; sp < 2; ++sp) {
-    if (!jr.empty() && j0.a.NS > 64) {
-      RUN(K_INVERT, launch_invert(j0.a, sp, sp + 1, 0, st, &brf, orf.back()));
-    } else if (!jr.empty()) {
+    if (!jr.empty()) {
       RUN(K_REFINE, launch_refine(j0.a, sp, j0.tol, st, &brf, orf.back()));
       RUN(K_INVERT, launch_invert(j0.a, sp, sp + 1, 1, st, &brf, orf.back()));
     }

@@ -100,7 +100,7 @@ def _chain(torch, vmc, ctx, wl, Cm, x0, W, ne, ns, refine_tol, precision=None):
     return res
 
 
-@pytest.mark.parametrize("name,W,ne,ns", [("h54", 8, 1, 4), ("h128", 4, 1, 3)])
+@pytest.mark.parametrize("name,W,ne,ns", [("h54", 8, 1, 4), ("h128", 4, 1, 3), ("h256", 3, 1, 1)])
 def test_refinement_refresh_matches_elimination_and_oracle(oracle, dev, name, W, ne, ns):
     """The Newton-Schulz refresh (default), elimination for every matrix (refine_tol < 0)
     and the oracle's fresh determinants give the same chain: identical acceptances and

@@ -1,8 +1,8 @@
 """The 256-proton box (128 x 128 Slater matrices per spin) against the CPU oracle,
 through the C ABI.  At this size the inverse does not fit in registers: the sweep
-keeps it in device memory, the refresh is Gauss-Jordan elimination in LDS at
-every half-sweep, and the measurement keeps its matrix products in a per-walker
-device region.  Bars as for the smaller boxes: 1e-10 relative in FP64, the
+keeps it in device memory, the refresh after the first sweep is the Newton-Schulz
+step with staged operands (elimination as its fallback), and the measurement keeps
+its matrix products in a per-walker device region.  Bars as for the smaller boxes: 1e-10 relative in FP64, the
 per-quantity mixed-precision tolerances otherwise.  The oracle takes a few seconds
 per configuration here, so the cases are small (W = 3 also leaves one lane group
 of the four-walker sweep blocks empty)."""
@@ -71,7 +71,7 @@ def test_eval_configs_h256(dev, h256, precision):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_chain_h256(dev, h256, precision):
     """Two sweeps (one equilibration, one measured) of three walkers on the oracle's
-    Philox stream: the second sweep starts from the elimination refresh."""
+    Philox stream: the second sweep starts from the refinement refresh."""
     torch, vmc, ctx = dev
     wl, Cm, s, oracle = h256
     W, ne, ns = 3, 1, 1
