@@ -373,18 +373,14 @@ struct SweepLds {
 // One wave per walker; the inverse lives in matrix-core accumulator layout
 // (tile (tr, tc), element v of lane l = A^-1[16 tr + 4 v + l/16][16 tc + l%16]).
 template <int NS, class Real, int NIMG, bool BATCH>
-__global__ __launch_bounds__(256, NS > 64 ? 1 : 2) void k_sweep_half(WalkerArgs a, SweepArgs s, Batch bt) {
+__global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s, Batch bt) {
   constexpr int N = 2 * NS;
   using LY = SweepLds<NS>;
   constexpr int NSP = LY::NSP, NT = NSP / 16, NB = (NS + 15) / 16, KC = (N + 3) / 4;
   constexpr int LDM = LY::LDM, LDG = LY::LDG;
   constexpr int EPL = (N + 63) / 64;
   constexpr int CPL = (NSP + 63) / 64;   // columns of the recursion vectors per lane
-  // NS > 64: the inverse stays in HBM (each lane reads and writes only the elements it
-  // would hold in registers, so no other lane's accesses are involved) and a spin's
-  // electrons span two lane slots (the slot is then per block of 16)
-  constexpr bool GINV = NS > 64;
-  static_assert(GINV || NS == 64 || N <= 64, "the electrons of one spin must share a slot");
+  static_assert(NS <= 64 && (NS == 64 || N <= 64), "the electrons of one spin must share a slot");
   extern __shared__ __align__(16) double smem_d[];
   int bblk = 0;
   if constexpr (BATCH) {
@@ -417,21 +413,19 @@ __global__ __launch_bounds__(256, NS > 64 ? 1 : 2) void k_sweep_half(WalkerArgs 
   // element (r, c) of the inverse at Bw[(16 tr + 4 v) NS] (wave-uniform) + lane offset
   double* Bw = a.Binv + bbase;
   const int loff = l4 * NS + l16;
-  d4w_t binv[GINV ? 1 : NT][GINV ? 1 : NT];
-  if constexpr (!GINV) {
+  d4w_t binv[NT][NT];
 #pragma unroll
-    for (int tr = 0; tr < NT; ++tr)
+  for (int tr = 0; tr < NT; ++tr)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double* rowp = Bw + (16 * tr + 4 * v) * NS;
+    for (int v = 0; v < 4; ++v) {
+      const double* rowp = Bw + (16 * tr + 4 * v) * NS;
 #pragma unroll
-        for (int tc = 0; tc < NT; ++tc) {
-          const bool ok = (16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS);
-          const double val = rowp[ok ? loff + 16 * tc : -(16 * tr + 4 * v) * NS];   // in range either way
-          binv[tr][tc][v] = ok ? val : 0.0;
-        }
+      for (int tc = 0; tc < NT; ++tc) {
+        const bool ok = (16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS);
+        const double val = rowp[ok ? loff + 16 * tc : -(16 * tr + 4 * v) * NS];   // in range either way
+        binv[tr][tc][v] = ok ? val : 0.0;
       }
-  }
+    }
 
   // positions stay in HBM: a block reads the current positions of its 16 electrons
   // (no earlier move of the half-sweep touches them) and an accepted move writes
@@ -454,7 +448,6 @@ __global__ __launch_bounds__(256, NS > 64 ? 1 : 2) void k_sweep_half(WalkerArgs 
 
   for (int b = 0; b < NB; ++b) {
     const int jmax = (NS - 16 * b) < 16 ? (NS - 16 * b) : 16;
-    const int slotb = GINV ? ((sp * NS + 16 * b) >> 6) : slot;   // lane slot of this block's electrons
     // proposal of move 16 b + l16 (lanes with equal l16 hold the same one)
     const int ip = 16 * b + l16;
     const bool pvalid = ip < NS;
@@ -511,7 +504,7 @@ __global__ __launch_bounds__(256, NS > 64 ? 1 : 2) void k_sweep_half(WalkerArgs 
     // P = M' A^-1: the inverse registers are the B operand of k step 4 tr + v
 #pragma unroll
     for (int tc = 0; tc < NT; ++tc) acc[tc] = d4w_t{0.0, 0.0, 0.0, 0.0};
-#pragma unroll (GINV ? 1 : NT)
+#pragma unroll
     for (int tr = 0; tr < NT; ++tr) {
       double av[4];
 #pragma unroll
@@ -519,12 +512,7 @@ __global__ __launch_bounds__(256, NS > 64 ? 1 : 2) void k_sweep_half(WalkerArgs 
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int tc = 0; tc < NT; ++tc) {
-          if constexpr (GINV)
-            acc[tc] = mfma_w(av[v], Bw[(16 * tr + 4 * v + l4) * NS + 16 * tc + l16], acc[tc]);
-          else
-            acc[tc] = mfma_w(av[v], binv[tr][tc][v], acc[tc]);
-        }
+        for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_w(av[v], binv[tr][tc][v], acc[tc]);
       asm volatile("" ::: "memory");
     }
 #pragma unroll
@@ -554,16 +542,8 @@ __global__ __launch_bounds__(256, NS > 64 ? 1 : 2) void k_sweep_half(WalkerArgs 
       for (int m = 0; m < 3; ++m) {
         sn[m] = readlane<Real>(sv, j + 16 * m);
         cn[m] = readlane<Real>(cv, j + 16 * m);
-        if constexpr (GINV) {
-          Real s0 = ts[0][m], c0 = tc_[0][m];
-#pragma unroll
-          for (int tt = 1; tt < EPL; ++tt) { s0 = (tt == slotb) ? ts[tt][m] : s0; c0 = (tt == slotb) ? tc_[tt][m] : c0; }
-          so[m] = readlane<Real>(s0, owner);
-          co[m] = readlane<Real>(c0, owner);
-        } else {
-          so[m] = readlane<Real>(slot == 0 ? ts[0][m] : ts[EPL - 1][m], owner);
-          co[m] = readlane<Real>(slot == 0 ? tc_[0][m] : tc_[EPL - 1][m], owner);
-        }
+        so[m] = readlane<Real>(slot == 0 ? ts[0][m] : ts[EPL - 1][m], owner);
+        co[m] = readlane<Real>(slot == 0 ? tc_[0][m] : tc_[EPL - 1][m], owner);
       }
       Real du = Real(0);
 #pragma unroll
@@ -594,7 +574,7 @@ __global__ __launch_bounds__(256, NS > 64 ? 1 : 2) void k_sweep_half(WalkerArgs 
         if (lane == owner) {
 #pragma unroll
           for (int tt = 0; tt < EPL; ++tt)
-            if (tt == slotb)
+            if (tt == slot)
               for (int m = 0; m < 3; ++m) { ts[tt][m] = sn[m]; tc_[tt][m] = cn[m]; }
         }
         ++nacc;
@@ -638,13 +618,7 @@ __global__ __launch_bounds__(256, NS > 64 ? 1 : 2) void k_sweep_half(WalkerArgs 
     }
     // G = the inverse's columns of this block (column tile b) into the M' buffer
     wave_lds_sync();
-    if constexpr (GINV) {
-#pragma unroll 1
-      for (int tr = 0; tr < NT; ++tr)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          MB[(16 * tr + 4 * v + l4) * LDG + l16] = Bw[(16 * tr + 4 * v + l4) * NS + 16 * b + l16];
-    } else {
+    {
       auto snap = [&](auto tcc) {
         constexpr int TC = decltype(tcc)::value;
 #pragma unroll
@@ -661,38 +635,22 @@ __global__ __launch_bounds__(256, NS > 64 ? 1 : 2) void k_sweep_half(WalkerArgs 
     }
     wave_lds_sync();
     // A^-1 -= G Z
-    if constexpr (GINV) {
-      for (int tr = 0; tr < NT; ++tr) {
-        double ga[4];
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) ga[kk] = -MB[(16 * tr + l16) * LDG + 4 * kk + l4];
-#pragma unroll 2
-        for (int tc = 0; tc < NT; ++tc) {
-          double* tp = Bw + (16 * tr + l4) * NS + 16 * tc + l16;
-          d4w_t tile = {tp[0], tp[4 * NS], tp[8 * NS], tp[12 * NS]};
+    for (int kk = 0; kk < 4; ++kk) {
+      double zb[NT], ga[NT];
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) tile = mfma_w(ga[kk], PB[(4 * kk + l4) * LDM + 16 * tc + l16], tile);
-          tp[0] = tile[0]; tp[4 * NS] = tile[1]; tp[8 * NS] = tile[2]; tp[12 * NS] = tile[3];
-        }
-      }
-    } else {
+      for (int tc = 0; tc < NT; ++tc) zb[tc] = PB[(4 * kk + l4) * LDM + 16 * tc + l16];
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        double zb[NT], ga[NT];
+      for (int tr = 0; tr < NT; ++tr) ga[tr] = -MB[(16 * tr + l16) * LDG + 4 * kk + l4];
 #pragma unroll
-        for (int tc = 0; tc < NT; ++tc) zb[tc] = PB[(4 * kk + l4) * LDM + 16 * tc + l16];
+      for (int tr = 0; tr < NT; ++tr)
 #pragma unroll
-        for (int tr = 0; tr < NT; ++tr) ga[tr] = -MB[(16 * tr + l16) * LDG + 4 * kk + l4];
-#pragma unroll
-        for (int tr = 0; tr < NT; ++tr)
-#pragma unroll
-          for (int tc = 0; tc < NT; ++tc) binv[tr][tc] = mfma_w(ga[tr], zb[tc], binv[tr][tc]);
-        asm volatile("" ::: "memory");
-      }
+        for (int tc = 0; tc < NT; ++tc) binv[tr][tc] = mfma_w(ga[tr], zb[tc], binv[tr][tc]);
+      asm volatile("" ::: "memory");
     }
     wave_lds_sync();
   }
-  if constexpr (!GINV) {
+  {
     // the block's walker again from the block index (the lookup is redone rather than kept live)
     const int blk_end = BATCH ? (int)blockIdx.x - bt.off[batch_job(bt, blockIdx.x)] : (int)blockIdx.x;
     Bw = a.Binv + ((size_t)(blk_end * 4 + wv) * 2 + sp) * NS * NS;
@@ -705,6 +663,267 @@ __global__ __launch_bounds__(256, NS > 64 ? 1 : 2) void k_sweep_half(WalkerArgs 
         for (int tc = 0; tc < NT; ++tc)
           if ((16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS)) rowp[loff + 16 * tc] = binv[tr][tc][v];
       }
+  }
+  if (lane == 0) a.nacc[w] += nacc;
+}
+
+// The half-sweep for N_sigma = 128, whose inverse (128 KB) stays in HBM: the same
+// delayed-update algorithm with the inverse streamed in the register tile layout (each
+// lane reads and writes only the elements it would hold as accumulators, so no other
+// lane's accesses are involved), 128 recursion columns two per lane, and the electrons of
+// a spin spread over two lane slots.  One LDS block of 16 rows per wave (P, then the z
+// rows, then the next block's MO rows), so two work-groups share a CU:
+//   * the MO rows M' of a block also go to the walker's scratch in HBM, from where the
+//     accepted ones are copied to A;
+//   * after the back-substitution Z moves to registers (the B operand layout of the
+//     update), the next block's proposals and M' are formed, and the update
+//     A^-1 -= G Z streams the inverse once, tile by tile, feeding each updated tile into
+//     the next block's P = M' A^-1 (G, the inverse's columns of the block, is read from
+//     HBM; row tile tr of G is read before the update writes row tile tr).
+struct SweepBigLds {
+  static constexpr int NS = 128, LDM = NS + 1, WAVE = 16 * LDM;
+  static constexpr size_t bytes = ((size_t)4 * WAVE + 4 * 2 * NS) * sizeof(double);
+};
+
+template <class Real, int NIMG, bool BATCH>
+__global__ __launch_bounds__(256, 2) void k_sweep_big(WalkerArgs a, SweepArgs s, Batch bt) {
+  constexpr int NS = 128, N = 2 * NS, NT = NS / 16, NB = NS / 16, KC = N / 4, EPL = N / 64, CPL = NS / 64;
+  constexpr int LDM = SweepBigLds::LDM;
+  extern __shared__ __align__(16) double smem_b[];
+  int bblk = 0;
+  if constexpr (BATCH) {
+    const int j = batch_job(bt, blockIdx.x);
+    const int spin = s.spin;
+    a = bt.jobs[j].a;
+    s = bt.jobs[j].s;
+    s.spin = spin;
+    bblk = (int)blockIdx.x - bt.off[j];
+  }
+  double* Rs = smem_b + 4 * SweepBigLds::WAVE;     // centres x, y, z, zeta
+  for (int t = threadIdx.x; t < N; t += blockDim.x) {
+    Rs[4 * t] = a.R[3 * t]; Rs[4 * t + 1] = a.R[3 * t + 1]; Rs[4 * t + 2] = a.R[3 * t + 2];
+    Rs[4 * t + 3] = a.zeta[t];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int w = (BATCH ? bblk : (int)blockIdx.x) * 4 + wv;
+  if (w >= a.W) return;
+  double* PB = smem_b + (size_t)wv * SweepBigLds::WAVE;   // 16 x LDM
+  const int sp = s.spin;
+  const double L = a.L, invL = a.invL;
+  const Real LoverPi = (Real)(L / VMC_PI);
+  double* Bw = a.Binv + ((size_t)w * 2 + sp) * NS * NS;
+  double* Am = a.Amat + ((size_t)w * 2 + sp) * NS * NS;
+  double* Ms = a.rscr + (size_t)w * a.rscr_stride;        // MO rows of the block, 16 x NS
+  Real ts[EPL][3], tc_[EPL][3];
+  double* pw = a.pos + (size_t)w * N * 3;
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) {
+    const int e = lane + 64 * t;
+    dev_sincospi<Real>((Real)(pw[3 * e] * invL), &ts[t][0], &tc_[t][0]);
+    dev_sincospi<Real>((Real)(pw[3 * e + 1] * invL), &ts[t][1], &tc_[t][1]);
+    dev_sincospi<Real>((Real)(pw[3 * e + 2] * invL), &ts[t][2], &tc_[t][2]);
+  }
+  const Real a_same = (Real)a.a_par, a_anti = (Real)a.a_anti, bj = (Real)a.b;
+  const double delta = s.delta;
+  int nacc = 0;
+
+  // proposal of move 16 b + l16 of the next block (lanes with equal l16 hold the same one)
+  double xn, yn, zn, ru3;
+  Real sv, cv;
+  auto propose = [&](int b) {
+    const int ip = 16 * b + l16;
+    const double* po = pw + 3 * (sp * NS + ip);
+    const uint32_t ctr2 = (uint32_t)(s.sweep * N + sp * NS + ip);
+    const u32x4 o0 = philox(s.step, (uint32_t)w, ctr2, 0u, s.seed, s.traj);
+    const u32x4 o1 = philox(s.step, (uint32_t)w, ctr2, 1u, s.seed, s.traj);
+    xn = wrap_box(po[0] + delta * (u01(o0.x, o0.y) - 0.5), L, invL);
+    yn = wrap_box(po[1] + delta * (u01(o0.z, o0.w) - 0.5), L, invL);
+    zn = wrap_box(po[2] + delta * (u01(o1.x, o1.y) - 0.5), L, invL);
+    ru3 = u01(o1.z, o1.w);
+    sv = Real(0); cv = Real(1);
+    const double comp = (l4 == 0) ? xn : ((l4 == 1) ? yn : zn);
+    dev_sincospi<Real>((Real)(comp * invL), &sv, &cv);
+  };
+  // M' = Phi' C on the matrix cores -> PB (left operand layout rows) and the HBM scratch
+  auto mo_rows = [&]() {
+    d4w_t acc[NT];
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc) acc[tc] = d4w_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int k = 0; k < KC; ++k) {
+      const int c = 4 * k + l4;
+      double bvs[NT];
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc) bvs[tc] = a.C[c * NS + 16 * tc + l16];
+      const double* Rc = Rs + 4 * c;
+      const double ph = (double)phi_value<Real, NIMG>(xn, yn, zn, Rc, (Real)Rc[3], L, invL);
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_w(ph, bvs[tc], acc[tc]);
+    }
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        PB[(4 * v + l4) * LDM + 16 * tc + l16] = acc[tc][v];
+        Ms[(4 * v + l4) * NS + 16 * tc + l16] = acc[tc][v];
+      }
+    wave_lds_sync();
+  };
+  // P = M' A^-1 with the inverse read from HBM, M' from PB -> PB
+  auto p_rows = [&]() {
+    d4w_t acc[NT];
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc) acc[tc] = d4w_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int tr = 0; tr < NT; ++tr) {
+      double av[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) av[v] = PB[l16 * LDM + 16 * tr + 4 * v + l4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc)
+          acc[tc] = mfma_w(av[v], Bw[(16 * tr + 4 * v + l4) * NS + 16 * tc + l16], acc[tc]);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) PB[(4 * v + l4) * LDM + 16 * tc + l16] = acc[tc][v];
+    wave_lds_sync();
+  };
+
+  propose(0);
+  mo_rows();
+  p_rows();
+  for (int b = 0; b < NB; ++b) {
+    const int slotb = (sp * NS + 16 * b) >> 6;   // lane slot of this block's electrons
+    // the moves of the block, in order; column c of the recursion vectors is element
+    // c / 64 of lane c % 64
+    uint32_t amask = 0;
+    for (int j = 0; j < 16; ++j) {
+      const int i = 16 * b + j, e = sp * NS + i, owner = e & 63;
+      double t[CPL];
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) t[u] = PB[j * LDM + lane + 64 * u];
+      for (uint32_t mm = amask; mm; mm &= mm - 1) {
+        const int jp = __builtin_ctz(mm);
+        const double cf = colread(t, 16 * b + jp);
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) t[u] = fma(-cf, PB[jp * LDM + lane + 64 * u], t[u]);
+      }
+      const double q = colread(t, i);
+      Real sn[3], cn[3], so[3], co[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        sn[m] = readlane<Real>(sv, j + 16 * m);
+        cn[m] = readlane<Real>(cv, j + 16 * m);
+        Real s0 = ts[0][m], c0 = tc_[0][m];
+#pragma unroll
+        for (int tt = 1; tt < EPL; ++tt) { s0 = (tt == slotb) ? ts[tt][m] : s0; c0 = (tt == slotb) ? tc_[tt][m] : c0; }
+        so[m] = readlane<Real>(s0, owner);
+        co[m] = readlane<Real>(c0, owner);
+      }
+      Real du = Real(0);
+#pragma unroll
+      for (int tt = 0; tt < EPL; ++tt) {
+        const int jj = lane + 64 * tt;
+        if (jj != e) {
+          const Real aa = ((jj / NS) == sp) ? a_same : a_anti;
+          du += pade_u<Real>(sn, cn, ts[tt], tc_[tt], LoverPi, aa, bj) -
+                pade_u<Real>(so, co, ts[tt], tc_[tt], LoverPi, aa, bj);
+        }
+      }
+      const double dU = wave_allsum((double)du);
+      const double pacc = q * q * (double)dev_exp<Real>((Real)(2.0 * dU));
+      double zrow[CPL] = {0.0, 0.0};
+      if (readlane_d(ru3, j) < pacc) {
+        const double iq = 1.0 / q;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) zrow[u] = (t[u] - (lane + 64 * u == i ? 1.0 : 0.0)) * iq;
+        amask |= 1u << j;
+        if (l16 == j && l4 < 3) pw[3 * e + l4] = (l4 == 0) ? xn : ((l4 == 1) ? yn : zn);
+        if (lane == owner) {
+#pragma unroll
+          for (int tt = 0; tt < EPL; ++tt)
+            if (tt == slotb)
+              for (int m = 0; m < 3; ++m) { ts[tt][m] = sn[m]; tc_[tt][m] = cn[m]; }
+        }
+        ++nacc;
+      }
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) PB[j * LDM + lane + 64 * u] = zrow[u];
+    }
+    const bool more = b + 1 < NB;
+    if (amask == 0) {                         // nothing to update: the next block's P from the same inverse
+      wave_lds_sync();
+      if (more) { propose(b + 1); mo_rows(); p_rows(); }
+      continue;
+    }
+    // accepted MO rows into A (from the scratch copy)
+    for (uint32_t mm = amask; mm; mm &= mm - 1) {
+      const int j = __builtin_ctz(mm);
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) Am[(size_t)(16 * b + j) * NS + lane + 64 * u] = Ms[j * NS + lane + 64 * u];
+    }
+    // Z = (I + Y)^-1 [z rows]: back-substitution from the last accepted move
+#pragma unroll 1
+    for (int j = 15; j >= 0; --j) {
+      if (!((amask >> j) & 1u)) continue;
+      double zo[CPL], z[CPL];
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) { zo[u] = PB[j * LDM + lane + 64 * u]; z[u] = zo[u]; }
+      for (uint32_t mm = amask & ~((2u << j) - 1u); mm; mm &= mm - 1) {
+        const int jp = __builtin_ctz(mm);
+        const double cf = colread(zo, 16 * b + jp);
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) z[u] = fma(-cf, PB[jp * LDM + lane + 64 * u], z[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) PB[j * LDM + lane + 64 * u] = z[u];
+    }
+    wave_lds_sync();
+    // Z into registers in the update's B operand layout, which frees PB
+    double zr[NT][4];
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) zr[tc][kk] = PB[(4 * kk + l4) * LDM + 16 * tc + l16];
+    wave_lds_sync();
+    // the next block's proposals and MO rows (into PB and the scratch)
+    if (more) { propose(b + 1); mo_rows(); }
+    // A^-1 -= G Z tile by tile; each updated tile also feeds the next block's P = M' A^-1
+    d4w_t pacc_t[NT];
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc) pacc_t[tc] = d4w_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int tr = 0; tr < NT; ++tr) {
+      double ga[4], av[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) ga[kk] = -Bw[(16 * tr + l16) * NS + 16 * b + 4 * kk + l4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) av[v] = more ? PB[l16 * LDM + 16 * tr + 4 * v + l4] : 0.0;
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc) {
+        double* tp = Bw + (16 * tr + l4) * NS + 16 * tc + l16;
+        d4w_t tile = {tp[0], tp[4 * NS], tp[8 * NS], tp[12 * NS]};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) tile = mfma_w(ga[kk], zr[tc][kk], tile);
+        tp[0] = tile[0]; tp[4 * NS] = tile[1]; tp[8 * NS] = tile[2]; tp[12 * NS] = tile[3];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pacc_t[tc] = mfma_w(av[v], tile[v], pacc_t[tc]);
+      }
+    }
+    wave_lds_sync();
+    if (more) {
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) PB[(4 * v + l4) * LDM + 16 * tc + l16] = pacc_t[tc][v];
+      wave_lds_sync();
+    }
   }
   if (lane == 0) a.nacc[w] += nacc;
 }
@@ -951,17 +1170,30 @@ size_t sweep_smem() {
 template <int NS, class Real>
 hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t st, const Batch* bt, int nblk) {
   dim3 grid(bt ? nblk : (a.W + 3) / 4);
-  size_t sm = sweep_smem<NS, Real>();
   const bool img = a.nimg || sizeof(Real) == 8;
-  if (bt && img)
-    hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, true>), grid, dim3(256), sm, st, a, s, *bt);
-  else if (bt)
-    hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, true>), grid, dim3(256), sm, st, a, s, *bt);
-  else if (img)
-    hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, false>), grid, dim3(256), sm, st, a, s, batch_or_none(bt));
-  else
-    hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, false>), grid, dim3(256), sm, st, a, s, batch_or_none(bt));
-  return hipGetLastError();
+  if constexpr (NS == 128) {
+    const size_t smb = SweepBigLds::bytes;
+    if (bt && img)
+      hipLaunchKernelGGL((k_sweep_big<Real, 1, true>), grid, dim3(256), smb, st, a, s, *bt);
+    else if (bt)
+      hipLaunchKernelGGL((k_sweep_big<Real, 0, true>), grid, dim3(256), smb, st, a, s, *bt);
+    else if (img)
+      hipLaunchKernelGGL((k_sweep_big<Real, 1, false>), grid, dim3(256), smb, st, a, s, batch_or_none(bt));
+    else
+      hipLaunchKernelGGL((k_sweep_big<Real, 0, false>), grid, dim3(256), smb, st, a, s, batch_or_none(bt));
+    return hipGetLastError();
+  } else {
+    size_t sm = sweep_smem<NS, Real>();
+    if (bt && img)
+      hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, true>), grid, dim3(256), sm, st, a, s, *bt);
+    else if (bt)
+      hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, true>), grid, dim3(256), sm, st, a, s, *bt);
+    else if (img)
+      hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, false>), grid, dim3(256), sm, st, a, s, batch_or_none(bt));
+    else
+      hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, false>), grid, dim3(256), sm, st, a, s, batch_or_none(bt));
+    return hipGetLastError();
+  }
 }
 
 #define VMC_DISPATCH_NS(ns, CALL) \
