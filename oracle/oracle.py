@@ -33,7 +33,7 @@ class OSys(C.Structure):
                 ("kappa", C.c_double), ("nmax", C.c_int), ("jastrow_on", C.c_int),
                 ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
                 ("R", C.POINTER(C.c_double)), ("zeta", C.POINTER(C.c_double)),
-                ("C", C.POINTER(C.c_double))]
+                ("C", C.POINTER(C.c_double)), ("b1", C.c_double)]
 
 
 _lib = None
@@ -80,7 +80,8 @@ class System:
     """Holds the arrays an OSys points to (keeps them alive)."""
 
     def __init__(self, R, zeta, C_mo, L=0.0, n_up=None, n_dn=None, basis=OB_PERIODIC_GAUSS,
-                 pot=OP_EWALD, kappa=None, nmax=9, jastrow=True, a_par=0.25, a_anti=0.5, b=1.0):
+                 pot=OP_EWALD, kappa=None, nmax=9, jastrow=True, a_par=0.25, a_anti=0.5, b=1.0,
+                 b1=0.0):
         self.R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1, 3)
         n_p = self.R.shape[0]
         self.zeta = np.ascontiguousarray(zeta, dtype=np.float64).reshape(n_p)
@@ -93,7 +94,8 @@ class System:
         if kappa is None:
             kappa = 8.0 / L if L > 0 else 0.0
         self.s = OSys(n_p, n_up, n_dn, self.C.shape[1], float(L), basis, pot, float(kappa), int(nmax),
-                      int(bool(jastrow)), a_par, a_anti, b, _dp(self.R), _dp(self.zeta), _dp(self.C))
+                      int(bool(jastrow)), a_par, a_anti, b, _dp(self.R), _dp(self.zeta), _dp(self.C),
+                      float(b1))
 
     @property
     def n_p(self):

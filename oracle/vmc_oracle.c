@@ -18,7 +18,9 @@
  *    Jastrow: two-body Pade term on the sin-periodised distance (SI, Jastrow
  *    section, periodisation substitution and the U_2 paragraph).  The e-e cusp
  *    sign is taken as u = +a rho/(1+b rho) with J = e^{+U}, a = 1/2 (anti-parallel)
- *    and 1/4 (parallel), b = 1.
+ *    and 1/4 (parallel), b = 1.  Optionally the one-body term U_1 of the same
+ *    section (Eq. e:j1) for protons (Z = 1), its homogeneous part only (the f
+ *    coefficients are optimised parameters), on the same periodised distance.
  *  - Ewald parameters, Metropolis details and the Hueckel orbitals are not in
  *    the paper; they are recorded readings shared with the GPU library only
  *    through their definitions.
@@ -244,13 +246,94 @@ static void jas_pair(const osys* s, const double d[3], int same, double* u, doub
   *laprho = (c2 - kf * rho * rho) / rho - g2 / rho;
 }
 
-/* U = sum_{i<j} u(rho_ij); gradU (Ne x 3) and lapU (Ne) are w.r.t. each electron. */
+/* One-body term of the SI (Eq. e:j1), homogeneous part, for a nucleus of charge
+ * Z = 1: f(rho) = -(2Z)^{3/4} u_1((2Z)^{1/4} rho), u_1(x) = (1 - e^{-b_1 x})/(2 b_1),
+ * on the distance rho between electron and nucleus.  Its slope at rho = 0 is -Z,
+ * the electron-nucleus cusp.  F[k] = d^k f / d rho^k, k = 0..3. */
+static void j1_radial(double b1, double rho, double F[4]) {
+  const double Z = 1.0, c = pow(2.0 * Z, 0.75), sc = pow(2.0 * Z, 0.25);
+  double e = exp(-b1 * sc * rho);
+  double u0 = (1.0 - e) / (2.0 * b1), u1 = e / 2.0, u2 = -b1 * e / 2.0, u3 = b1 * b1 * e / 2.0;
+  F[0] = -c * u0;
+  F[1] = -c * sc * u1;
+  F[2] = -c * sc * sc * u2;
+  F[3] = -c * sc * sc * sc * u3;
+}
+
+/* rho = |rt|, rt_m = (L/pi) sin(pi d_m / L) in the periodic kind, |d| otherwise. */
+static double periodised_rho(const osys* s, const double d[3]) {
+  double r2 = 0.0;
+  for (int m = 0; m < 3; ++m) {
+    double r = (s->basis_kind == OB_PERIODIC_GAUSS) ? s->L / PI * sin(PI * d[m] / s->L) : d[m];
+    r2 += r * r;
+  }
+  return sqrt(r2);
+}
+
+/* A radial function f(rho(d)) of the offset d, with rho = |rt| on the periodised
+ * components rt_m = (L/pi) sin(pi d_m / L) (d itself in the open kinds), given
+ * F[k] = d^k f/d rho^k.  Chain rule with c_m = d rt_m / d d_m = cos(pi d_m / L),
+ * d c_m / d d_m = -(pi/L)^2 rt_m, g_m = d rho / d d_m = rt_m c_m / rho and
+ * p_m = c_m^2 - (pi/L)^2 rt_m^2:
+ *   d g_m / d d_n = (delta_mn p_m - g_m g_n) / rho,
+ *   grad f = F' g,  hess f = F'' g g^T + F' (diag(p) - g g^T) / rho,
+ *   lap f = F'' G + F' (P - G) / rho  with G = |g|^2, P = sum_m p_m,
+ * and the gradient of the Laplacian with d G / d d_n = 2 g_n (p_n - G) / rho and
+ * d P / d d_n = -4 (pi/L)^2 rho g_n.  hess: xx yy zz xy xz yz. */
+static void radial_field(const osys* s, const double d[3], const double F[4], double grad[3], double hess[6],
+                         double* lap, double glap[3]) {
+  double rt[3], c[3], kf;
+  if (s->basis_kind == OB_PERIODIC_GAUSS) {
+    for (int m = 0; m < 3; ++m) {
+      rt[m] = s->L / PI * sin(PI * d[m] / s->L);
+      c[m] = cos(PI * d[m] / s->L);
+    }
+    kf = (PI / s->L) * (PI / s->L);
+  } else {
+    for (int m = 0; m < 3; ++m) { rt[m] = d[m]; c[m] = 1.0; }
+    kf = 0.0;
+  }
+  double rho = sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+  double g[3], p[3], G = 0.0, P = 0.0;
+  for (int m = 0; m < 3; ++m) {
+    g[m] = rt[m] * c[m] / rho;
+    p[m] = c[m] * c[m] - kf * rt[m] * rt[m];
+    G += g[m] * g[m];
+    P += p[m];
+  }
+  for (int m = 0; m < 3; ++m) grad[m] = F[1] * g[m];
+  int hp[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+  for (int h = 0; h < 6; ++h) {
+    int m = hp[h][0], n = hp[h][1];
+    hess[h] = F[2] * g[m] * g[n] + F[1] * ((m == n ? p[m] : 0.0) - g[m] * g[n]) / rho;
+  }
+  *lap = F[2] * G + F[1] * (P - G) / rho;
+  for (int n = 0; n < 3; ++n) {
+    double dG = 2.0 * g[n] * (p[n] - G) / rho, dP = -4.0 * kf * rho * g[n];
+    glap[n] = F[3] * g[n] * G + F[2] * dG + F[2] * g[n] * (P - G) / rho +
+              F[1] * ((dP - dG) / rho - (P - G) * g[n] / (rho * rho));
+  }
+}
+
+/* U = sum_{i<j} u(rho_ij) + U_1; gradU (Ne x 3) and lapU (Ne) are w.r.t. each electron. */
 void o_jastrow(const osys* s, const double* x, double* U, double* gradU, double* lapU) {
   int ne = s->n_up + s->n_dn;
   double Ut = 0.0;
   if (gradU) memset(gradU, 0, sizeof(double) * 3 * ne);
   if (lapU) memset(lapU, 0, sizeof(double) * ne);
-  if (!s->jastrow_on) { *U = 0.0; return; }
+  if (s->b1 > 0.0)
+    for (int i = 0; i < ne; ++i)
+      for (int a = 0; a < s->n_p; ++a) {
+        double d[3] = {x[3 * i] - s->R[3 * a], x[3 * i + 1] - s->R[3 * a + 1], x[3 * i + 2] - s->R[3 * a + 2]};
+        double F[4], g[3], h[6], lp, gl[3];
+        j1_radial(s->b1, periodised_rho(s, d), F);
+        radial_field(s, d, F, g, h, &lp, gl);
+        Ut += F[0];
+        if (gradU)
+          for (int m = 0; m < 3; ++m) gradU[3 * i + m] += g[m];
+        if (lapU) lapU[i] += lp;
+      }
+  if (!s->jastrow_on) { *U = Ut; return; }
   for (int i = 0; i < ne; ++i)
     for (int j = i + 1; j < ne; ++j) {
       double d[3] = {x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1], x[3 * i + 2] - x[3 * j + 2]};
@@ -370,6 +453,7 @@ int o_local(const osys* s, const double* x, double* lnpsi, double* sign, double*
   int want = (dlnpsi_dR != NULL) || (dEL_dR != NULL);
   double* dln = (double*)calloc(n3, sizeof(double));
   double* dT = (double*)calloc(n3, sizeof(double));
+  double* gDe = (double*)calloc(3 * ne, sizeof(double));   /* grad_i ln|D| per electron */
   int rc = 0;
   for (int sp = 0; sp < 2 && rc == 0; ++sp) {
     int n = sp ? s->n_dn : s->n_up, e0 = sp ? s->n_up : 0;
@@ -400,6 +484,7 @@ int o_local(const osys* s, const double* x, double* lnpsi, double* sign, double*
       }
       const double* gu = gU + 3 * (e0 + i);
       T += -0.5 * (lapD + 2.0 * (gD[0] * gu[0] + gD[1] * gu[1] + gD[2] * gu[2]));
+      for (int m = 0; m < 3; ++m) gDe[3 * (e0 + i) + m] = gD[m];
     }
     if (want) {
       double *dA = malloc(8 * n * n), *dG = malloc(8 * 3 * n * n), *dL = malloc(8 * n * n);
@@ -440,6 +525,27 @@ int o_local(const osys* s, const double* x, double* lnpsi, double* sign, double*
     }
     free(bf); free(A); free(G); free(Lp); free(Ai);
   }
+  /* The one-body term depends on R_a through r_i - R_a, so d/dR_a = -grad_i on it:
+   * d ln psi / dR_a gets -grad_i f_ia, and the kinetic part
+   * -1/2 sum_i (lap_i U + |grad_i U|^2 + 2 grad_i ln|D| . grad_i U) + (the determinant
+   * terms, already differentiated above with the full grad U) gets
+   * sum_i [ 1/2 grad_i lap_i f_ia + hess_i f_ia (grad_i U + grad_i ln|D|) ]. */
+  if (rc == 0 && want && s->b1 > 0.0)
+    for (int a = 0; a < np; ++a)
+      for (int i = 0; i < ne; ++i) {
+        double d[3] = {x[3 * i] - s->R[3 * a], x[3 * i + 1] - s->R[3 * a + 1], x[3 * i + 2] - s->R[3 * a + 2]};
+        double F[4], g[3], h[6], lp, gl[3];
+        j1_radial(s->b1, periodised_rho(s, d), F);
+        radial_field(s, d, F, g, h, &lp, gl);
+        double v[3];
+        for (int m = 0; m < 3; ++m) v[m] = gU[3 * i + m] + gDe[3 * i + m];
+        for (int mu = 0; mu < 3; ++mu) {
+          dln[3 * a + mu] -= g[mu];
+          double hv = 0.0;
+          for (int nu = 0; nu < 3; ++nu) hv += h[hidx(mu, nu) - 5] * v[nu];
+          dT[3 * a + mu] += 0.5 * gl[mu] + hv;
+        }
+      }
   if (rc == 0) {
     if (lnpsi) *lnpsi = lnp;
     if (sign) *sign = sg;
@@ -448,7 +554,7 @@ int o_local(const osys* s, const double* x, double* lnpsi, double* sign, double*
     if (dEL_dR)
       for (int t = 0; t < n3; ++t) dEL_dR[t] = dT[t] + dVdR[t];
   }
-  free(gU); free(lU); free(dVdR); free(dln); free(dT);
+  free(gU); free(lU); free(dVdR); free(dln); free(dT); free(gDe);
   return rc;
 }
 
@@ -544,7 +650,7 @@ static void mo_row(const osys* s, const double r[3], double* m) {
  * Sweep: electrons e = 0..Ne-1 in order; move r' = r_e + delta (u - 1/2) (wrapped
  * into the box); accept iff u_acc < |psi'/psi|^2, strictly.  The determinant
  * ratio is det A'/det A from two fresh LU factorisations; the Jastrow change is
- * the sum of the pair changes.  Random numbers: Philox key (seed, traj),
+ * the sum of the pair changes (and of the moved electron's one-body terms).  Random numbers: Philox key (seed, traj),
  * counter (step, walker, sweep*Ne + e, 0|1).  After each measured sweep the
  * local quantities of o_local are added to sums[w] = [sum E_L, sum E_L^2,
  * sum dE_L/dR (3N), sum dln|psi|/dR (3N), sum E_L dln|psi|/dR (3N)]. */
@@ -610,6 +716,14 @@ int o_vmc_run(const osys* s, int W, double* x, int n_equil, int n_meas, double d
             jas_pair(s, dn, same, &u1, &t1, &t2, g, &lr);
             jas_pair(s, dold, same, &u0, &t1, &t2, g, &lr);
             dU += u1 - u0;
+          }
+        if (s->b1 > 0.0)
+          for (int a = 0; a < s->n_p; ++a) {
+            double dn[3], dold[3], F1[4], F0[4];
+            for (int mm = 0; mm < 3; ++mm) { dn[mm] = rn[mm] - s->R[3 * a + mm]; dold[mm] = xw[3 * e + mm] - s->R[3 * a + mm]; }
+            j1_radial(s->b1, periodised_rho(s, dn), F1);
+            j1_radial(s->b1, periodised_rho(s, dold), F0);
+            dU += F1[0] - F0[0];
           }
         double p = q * q * exp(2.0 * dU);
         if (uacc < p) {

@@ -31,6 +31,9 @@ typedef struct {
   const double* R;     /* n_p x 3 */
   const double* zeta;  /* n_p */
   const double* C;     /* n_p x n_orb, row-major */
+  double b1;           /* one-body (electron-nucleus) Jastrow U_1 of the SI, Eq. e:j1, with
+                          Z_a = 1 and no orbital part: b_1 of u_1(x) = (1 - e^{-b_1 x})/(2 b_1);
+                          0 = no one-body term */
 } osys;
 
 /* Philox4x32-10 counter-based generator (Salmon et al., SC'11). */

@@ -179,6 +179,51 @@ def test_hydrogenic_orbital_local_energy(oracle, alpha):
         assert s.local(r.reshape(1, 3))["EL"] == pytest.approx(-alpha ** 2 / 2 + (alpha - 1) / rr, rel=1e-12, abs=1e-13)
 
 
+@pytest.mark.parametrize("zeta,b1", [(0.7, 1.3), (1.1, 0.4)])
+def test_one_body_jastrow_hydrogen_atom_closed_form(oracle, zeta, b1):
+    """One electron, one proton, open boundaries, psi = e^{-zeta r^2} e^{U_1} with the SI's
+    one-body term U_1 = -(2Z)^{3/4} u_1((2Z)^{1/4} r), u_1(x) = (1 - e^{-b_1 x}) / (2 b_1), Z = 1.
+    With g(r) = ln psi and g1, g2, g3 its radial derivatives, E_L = -(g2 + 2 g1/r + g1^2)/2 - 1/r,
+    dE_L/dR = -E_L'(r) r_hat and d ln psi/dR = -g1 r_hat, where
+    g1 = -2 zeta r - e^{-beta r}, g2 = -2 zeta + beta e^{-beta r}, g3 = -beta^2 e^{-beta r} and
+    beta = b_1 2^{1/4} (the product (2Z)^{3/4} (2Z)^{1/4} / 2 = 1 is the cusp slope)."""
+    R0 = np.array([0.1, 0.2, 0.3])
+    s = oracle.System(R=[R0], zeta=[zeta], C_mo=[[1.0]], n_up=1, n_dn=0, basis=oracle.OB_OPEN_GAUSS,
+                      pot=oracle.OP_COULOMB_OPEN, jastrow=False, b1=b1)
+    be = b1 * 2 ** 0.25
+    for x in np.random.default_rng(6).normal(size=(8, 3)):
+        d = x - R0
+        r = np.linalg.norm(d)
+        e = math.exp(-be * r)
+        g1, g2, g3 = -2 * zeta * r - e, -2 * zeta + be * e, -be * be * e
+        EL = -0.5 * (g2 + 2 * g1 / r + g1 ** 2) - 1 / r
+        dEL = -0.5 * (g3 + 2 * g2 / r - 2 * g1 / r ** 2 + 2 * g1 * g2) + 1 / r ** 2
+        res = s.local(x.reshape(1, 3))
+        assert res["EL"] == pytest.approx(EL, rel=1e-12, abs=1e-13)
+        assert np.allclose(res["dEL"], -dEL * d / r, rtol=1e-11, atol=1e-12)
+        assert np.allclose(res["dlnpsi"], -g1 * d / r, rtol=1e-12, atol=1e-13)
+
+
+def test_one_body_jastrow_removes_the_nuclear_divergence(oracle):
+    """Gaussian orbitals have no slope at a nucleus, so E_L carries the -1/r of the
+    electron-proton attraction as an electron meets a proton; the one-body term's slope -Z
+    at r = 0 (Kato's cusp) cancels it: E_L then tends to a finite limit, to O(r)."""
+    wl = small_system(6, 1.3, seed=4)
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, 3)
+    u = np.array([1.0, -2.0, 2.0]) / 3.0
+    for b1, bounded in [(0.0, False), (1.0, True), (2.5, True)]:
+        s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1)
+        x = wl.electrons(W=1)[0]
+        els = []
+        for eps in (1e-4, 1e-6):
+            x[2] = wl.R[4] + eps * u
+            els.append(s.local(x, False)["EL"])
+        if bounded:
+            assert abs(els[1] - els[0]) < 1e-3, (b1, els)
+        else:
+            assert els[1] - els[0] == pytest.approx(-(1e6 - 1e4), rel=1e-3)
+
+
 def _leibniz_det(M):
     n = M.shape[0]
     tot = 0.0
@@ -213,13 +258,13 @@ def test_slater_determinant_brute_force(oracle, n):
     assert res["sign"] == np.sign(dets[0] * dets[1])
 
 
-@pytest.mark.parametrize("name", ["h16", "h6"])
-def test_kinetic_energy_against_fd_laplacian(oracle, name):
+@pytest.mark.parametrize("name,b1", [("h16", 0.0), ("h6", 0.0), ("h6", 1.0), ("h16", 1.7)])
+def test_kinetic_energy_against_fd_laplacian(oracle, name, b1):
     """E_L - V = -1/2 sum_i (lap_i ln|psi| + |grad_i ln|psi||^2), the Laplacian taken by
-    second differences of ln|psi| in every electron coordinate."""
+    second differences of ln|psi| in every electron coordinate (b1 > 0: with the one-body term)."""
     wl = workload("h16") if name == "h16" else small_system(6, 1.3, seed=4)
     Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
-    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1)
     x = wl.electrons(W=1)[0]
     res = s.local(x, derivs=False)
     V, _, _ = s.potential(x)
@@ -235,20 +280,21 @@ def test_kinetic_energy_against_fd_laplacian(oracle, name):
     assert res["EL"] - V == pytest.approx(T, rel=1e-6, abs=1e-6)
 
 
-@pytest.mark.parametrize("name", ["h16", "h6"])
-def test_proton_derivatives_by_finite_differences(oracle, name):
-    """d ln|psi|/dR and dE_L/dR at fixed C, zeta, Jastrow and electron positions."""
+@pytest.mark.parametrize("name,b1", [("h16", 0.0), ("h6", 0.0), ("h6", 1.0), ("h16", 1.7)])
+def test_proton_derivatives_by_finite_differences(oracle, name, b1):
+    """d ln|psi|/dR and dE_L/dR at fixed C, zeta, Jastrow and electron positions (b1 > 0: the
+    one-body term moves with the protons)."""
     wl = workload("h16") if name == "h16" else small_system(6, 1.3, seed=4)
     Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
-    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1)
     x = wl.electrons(W=1)[0]
     res = s.local(x)
     h = 1e-5
     for t in range(0, 3 * wl.n, 1 if wl.n <= 6 else 5):
         Rp = wl.R.reshape(-1).copy(); Rm = Rp.copy()
         Rp[t] += h; Rm[t] -= h
-        a = oracle.System(Rp.reshape(-1, 3), wl.zeta, Cm, L=wl.L).local(x, False)
-        b = oracle.System(Rm.reshape(-1, 3), wl.zeta, Cm, L=wl.L).local(x, False)
+        a = oracle.System(Rp.reshape(-1, 3), wl.zeta, Cm, L=wl.L, b1=b1).local(x, False)
+        b = oracle.System(Rm.reshape(-1, 3), wl.zeta, Cm, L=wl.L, b1=b1).local(x, False)
         assert res["dlnpsi"][t] == pytest.approx((a["lnpsi"] - b["lnpsi"]) / (2 * h), rel=1e-7, abs=1e-8)
         assert res["dEL"][t] == pytest.approx((a["EL"] - b["EL"]) / (2 * h), rel=1e-6, abs=1e-7)
 

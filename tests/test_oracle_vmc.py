@@ -8,6 +8,7 @@
   has the exact derivative <dE_L/dR> + 2 (<E_L dln|psi|/dR> - E <dln|psi|/dR>)
   at R' = R; central differences of E(R +- h) must give -f to O(h^2).
 """
+import ctypes
 import math
 
 import numpy as np
@@ -72,11 +73,43 @@ def test_chain_is_deterministic(oracle):
     assert 0.2 < acc < 0.9
 
 
-@pytest.mark.parametrize("name", ["h6", "h16"])
-def test_force_estimator_equals_correlated_sampling_derivative(oracle, name):
+def test_sweep_decisions_follow_psi_ratios_with_one_body_term(oracle):
+    """Each Metropolis decision of a sweep equals u < |psi(x')/psi(x)|^2 with ln|psi| taken
+    from the local-energy routine (one-body term included) on the move drawn from the same
+    Philox counters: the sweep's own Jastrow differences agree with ln|psi|."""
+    wl = small_system(6, 1.3, seed=4)
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, 3)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=1.2)
+    W, seed, traj, step = 4, 21, 2, 3
+    x0 = wl.electrons(W=W)
+    xs = x0.copy()
+    _, nacc = s.vmc_run(xs, 1, 0, wl.delta, seed, traj=traj, step=step)
+    lib = oracle.lib()
+    for w in range(W):
+        x = x0[w].copy()
+        n = 0
+        for e in range(wl.n):
+            u = []
+            for half in (0, 1):
+                out = (ctypes.c_uint32 * 4)()
+                ctr = (ctypes.c_uint32 * 4)(step, w, e, half)
+                key = (ctypes.c_uint32 * 2)(seed, traj)
+                lib.o_philox(ctr, key, out)
+                u += [lib.o_u01(out[0], out[1]), lib.o_u01(out[2], out[3])]
+            xn = x.copy()
+            xn[e] = np.mod(x[e] + wl.delta * (np.array(u[:3]) - 0.5), wl.L)
+            p = math.exp(2 * (s.local(xn, False)["lnpsi"] - s.local(x, False)["lnpsi"]))
+            if u[3] < p:
+                x, n = xn, n + 1
+        assert n == nacc[w]
+        assert np.allclose(x, xs[w], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("name,b1", [("h6", 0.0), ("h16", 0.0), ("h6", 1.0)])
+def test_force_estimator_equals_correlated_sampling_derivative(oracle, name, b1):
     wl = small_system(6, 1.3, seed=4) if name == "h6" else workload("h16")
     Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
-    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1)
     xs = _samples(s, wl.electrons(W=4), 6, wl.delta, seed=5).reshape(-1, wl.n, 3)
     n3 = 3 * wl.n
     sums = np.zeros((1, 2 + 3 * n3))
@@ -92,7 +125,7 @@ def test_force_estimator_equals_correlated_sampling_derivative(oracle, name):
     base = np.array(base)
 
     def E_of(Rflat):
-        sp = oracle.System(Rflat.reshape(-1, 3), wl.zeta, Cm, L=wl.L)
+        sp = oracle.System(Rflat.reshape(-1, 3), wl.zeta, Cm, L=wl.L, b1=b1)
         res = [sp.local(x, False) for x in xs]
         lw = 2 * (np.array([q["lnpsi"] for q in res]) - base)
         w = np.exp(lw - lw.max())
