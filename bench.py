@@ -25,11 +25,11 @@ METRIC = "VMC walker-sweeps/s with forces at N=128 H; Langevin steps/s, p99 late
 PEAK = {"mfma_f64": 78.6, "mfma_f32": 157.3, "valu": 78.6}
 
 
-def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool) -> dict:
+def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, one_body: bool = False) -> dict:
     """Algorithmic arithmetic of one walker's share of a launch, split by the unit that
     executes it: {unit: flops} (FMA = 2 flops; exp, erfc, sqrt, rcp, sincos count 1).
     img = Gaussian images evaluated per axis (3, or 1 when the dropped ones are below
-    FP32 resolution)."""
+    FP32 resolution); one_body: the electron-proton Jastrow term is on."""
     NS = N // 2
     img = 3 if nimg else 1
     if cls == "slater_sample":
@@ -37,12 +37,18 @@ def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool) ->
         pair1 = 3 * (3 + 9 * img) + 29 + 8 + 32                  # Gaussian with 3 derivatives, products, X, sums
         pair2 = 3 * (3 + 5 * img) + 12                           # Gaussian gradient, W term
         valu = N * N * (pair1 + pair2) + N * (N - 1) * 45        # both spins' (electron, centre) pairs; Jastrow
+        if one_body:
+            # per (electron, proton) pair: its Jastrow gradient and Laplacian (30), grad ln|D| from
+            # the Gaussian gradient (3 (3 + 5 img) + 8) and the d/dR terms (80)
+            valu += N * N * (30 + 3 * (3 + 5 * img) + 8 + 80)
         if mixed:
             return {"mfma_f64": 2 * gemm, "mfma_f32": 4 * gemm, "valu": valu}
         return {"mfma_f64": 6 * gemm, "valu": valu}
     if cls == "sweep_half":
         mfma = 2 * NS * N * NS + 2 * NS ** 3 + 2 * NS ** 3       # M' = Phi' C, P = M' A^-1, rank-16 updates
         per_move = N * (3 * (3 + 2 * img) + 2) + 2 * (N - 1) * 16 + 2 * 0.58 * 7.5 * 2 * NS
+        if one_body:
+            per_move += 2 * N * 15                               # old and new distance to every proton, exp
         return {"mfma_f64": mfma, "valu": NS * per_move}
     if cls == "ewald_sample":
         recip = nk * N * 8 + nslot * N * 6
@@ -87,9 +93,9 @@ def measured_traffic(kernel: str):
     return k["bytes_per_launch"]
 
 
-def run_cpu_baseline(wl, Cm, walkers: int, sweeps: int, threads: int):
+def run_cpu_baseline(wl, Cm, walkers: int, sweeps: int, threads: int, b1: float = 0.0):
     from oracle import oracle as O
-    s = O.System(wl.R, wl.zeta, Cm, L=wl.L)
+    s = O.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1)
     x = wl.electrons(W=walkers, seed_offset=99)
     t0 = time.perf_counter()
     s.vmc_run(x, 1, sweeps, wl.delta, seed=3, traj=0, step=0, threads=threads)
@@ -282,6 +288,8 @@ def main():
     ap.add_argument("--sweeps", type=int, default=100)
     ap.add_argument("--rs", type=float, default=None, help="default: the workload's r_s")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--j1", type=float, default=0.0, metavar="B1",
+                    help="add the one-body electron-proton Jastrow term with this b_1 (0: none)")
     ap.add_argument("--cpu-walkers", type=int, default=None, help="default: 192 (h128), 16 (h256)")
     ap.add_argument("--cpu-sweeps", type=int, default=None, help="default: 6 (h128), 2 (h256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -335,7 +343,7 @@ def main():
     N, W, M = wl.n, args.walkers or wl.walkers, args.sweeps
     prec = vmc.VMC_MIXED if args.precision == "mixed" else vmc.VMC_FP64
     ctx = vmc.Context(0)
-    sysd = vmc.make_system(N, wl.L, precision=prec)
+    sysd = vmc.make_system(N, wl.L, precision=prec, b1=args.j1)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     traj = vmc.Trajectory(ctx, sysd, W, seed=wl.seed, traj_id=0)
     traj.set_walkers(dev(wl.electrons(W=W)))
@@ -391,7 +399,7 @@ def main():
     nimg = int(not (prec == vmc.VMC_MIXED and float(np.min(wl.zeta)) * (wl.L / 2) ** 2 >= 23.0))
     dom = max(times.items(), key=lambda kv: kv[1][0])
     dom_name, (dom_ms, dom_n) = dom[0], dom[1]
-    parts = work_model(dom_name, N, nk, nslot, nimg, prec == vmc.VMC_MIXED)
+    parts = work_model(dom_name, N, nk, nslot, nimg, prec == vmc.VMC_MIXED, args.j1 > 0)
     avg_s = dom_ms / max(dom_n, 1) / 1e3
     flops, achieved, peak = roofline_numbers(parts, W, avg_s)
     roofline = {"bound": "alu", "kernel": dom_name, "achieved": round(achieved, 3), "peak": round(peak, 2),
@@ -410,7 +418,7 @@ def main():
         threads = min(os.cpu_count() or 1, 16)
         cw = args.cpu_walkers or (192 if N <= 128 else 16)
         cs = args.cpu_sweeps or (6 if N <= 128 else 2)
-        v, dt = run_cpu_baseline(wl, Cm0, cw, cs, threads)
+        v, dt = run_cpu_baseline(wl, Cm0, cw, cs, threads, args.j1)
         cpu = {"value": round(v, 3), "unit": "walker-sweeps/s", "cores": threads, "kind": "oracle",
                "sample": f"{cw} walkers x (1 unmeasured + {cs} measured) sweeps of the "
                          f"same N={N} box in FP64, {dt:.1f} s"}
@@ -422,8 +430,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32/f64" if prec == vmc.VMC_MIXED else "f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {N} H + {N} e-, r_s={rs}, T={wl.T_kelvin:g} K, {W} walkers x {M} "
-                               f"measured (+5 re-equilibration) sweeps per Langevin step, {args.precision} precision",
-                   "N": N, "walkers": W, "sweeps": M, "precision": args.precision},
+                               f"measured (+5 re-equilibration) sweeps per Langevin step, {args.precision} precision"
+                               + (f", one-body Jastrow b_1={args.j1:g}" if args.j1 > 0 else ""),
+                   "N": N, "walkers": W, "sweeps": M, "precision": args.precision, "one_body_b1": args.j1},
         "langevin_steps_per_s": round(args.steps / elapsed, 4),
         "step_latency_ms": {"p50": round(p(0.5), 1), "p99": round(p(0.99), 1)},
         "E_Ha": float(out_h[0]), "sigma_E_Ha": float(out_h[1]), "acceptance": float(out_h[2]),

@@ -71,6 +71,11 @@ typedef struct {
                          every matrix with max|I - A X| > refine_tol (or not finite).
                          0 = default (1e-7); < 0 = elimination for every matrix.
                          At N = 256 the step uses the walker's measurement scratch for I - A X */
+  double j1_b1;       /* one-body electron-proton Jastrow term U_1 of the SI (Eq. e:j1), its
+                         homogeneous part for Z = 1 on the sin-periodised distance rho:
+                         -(2Z)^{3/4} u_1((2Z)^{1/4} rho), u_1(x) = (1 - e^{-b_1 x}) / (2 b_1), summed
+                         over every electron-proton pair; it gives psi the electron-nucleus cusp.
+                         j1_b1 = b_1 > 0 enables it; 0 = no one-body term; < 0 or NaN: VMC_EINVAL */
 } vmc_system;
 
 /* ---------------------------------------------------------------- context -- */

@@ -201,6 +201,34 @@ template <class Real> __device__ __forceinline__ void dev_sincospi(Real x, Real*
 template <> __device__ __forceinline__ void dev_sincospi<double>(double x, double* s, double* c) { sincospi(x, s, c); }
 template <> __device__ __forceinline__ void dev_sincospi<float>(float x, float* s, float* c) { sincospif(x, s, c); }
 
+// sin(pi x) and cos(pi x) for |x| <= 1/2 (a minimum-image offset over the box side).  FP32:
+// the Taylor series of sin t and cos t, t = pi x, through t^13 and t^14 in Horner form; the
+// truncation is below 1e-9 at |t| = pi/2, so FP32 rounding sets the error (about 1.6e-7
+// relative for sin, small offsets included).  FP64 keeps the library's sincospi.
+template <class Real> __device__ __forceinline__ void sincospi_half(Real x, Real* s, Real* c);
+template <> __device__ __forceinline__ void sincospi_half<double>(double x, double* s, double* c) {
+  sincospi(x, s, c);
+}
+template <> __device__ __forceinline__ void sincospi_half<float>(float x, float* s, float* c) {
+  const float t = 3.14159265358979f * x, t2 = t * t;
+  float ps = 1.0f / 6227020800.0f;
+  ps = fmaf(ps, t2, -1.0f / 39916800.0f);
+  ps = fmaf(ps, t2, 1.0f / 362880.0f);
+  ps = fmaf(ps, t2, -1.0f / 5040.0f);
+  ps = fmaf(ps, t2, 1.0f / 120.0f);
+  ps = fmaf(ps, t2, -1.0f / 6.0f);
+  ps = fmaf(ps, t2, 1.0f);
+  float pc = -1.0f / 87178291200.0f;
+  pc = fmaf(pc, t2, 1.0f / 479001600.0f);
+  pc = fmaf(pc, t2, -1.0f / 3628800.0f);
+  pc = fmaf(pc, t2, 1.0f / 40320.0f);
+  pc = fmaf(pc, t2, -1.0f / 720.0f);
+  pc = fmaf(pc, t2, 1.0f / 24.0f);
+  pc = fmaf(pc, t2, -0.5f);
+  *s = ps * t;
+  *c = fmaf(pc, t2, 1.0f);
+}
+
 // Pade pair value u(rho) = a rho / (1 + b rho) of the Jastrow, for the
 // sin-periodised offset built from the trig caches of the two electrons:
 // sin(pi (x_i - x_j)/L) = s_i c_j - c_i s_j.
@@ -215,6 +243,21 @@ __device__ __forceinline__ Real pade_u(const Real si[3], const Real ci[3], const
   }
   Real rho = dev_sqrt<Real>(r2);
   return a * rho * dev_rcp<Real>(Real(1) + b * rho);
+}
+
+// e^{-beta rho} on the sin-periodised distance of an electron (si, ci) and a proton
+// (sj, cj).  The one-body Jastrow term of the pair is -(1 - e^{-beta rho}) / beta, so a
+// move changes it by the difference of these exponentials divided by beta.
+template <class Real>
+__device__ __forceinline__ Real one_body_exp(const Real si[3], const Real ci[3], const Real sj[3], const Real cj[3],
+                                             Real LoverPi, Real beta) {
+  Real r2 = Real(0);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    Real rt = LoverPi * (si[m] * cj[m] - ci[m] * sj[m]);
+    r2 += rt * rt;
+  }
+  return dev_exp<Real>(-beta * dev_sqrt<Real>(r2));
 }
 
 }  // namespace vmc

@@ -316,7 +316,9 @@ struct SlaterLds {
   static constexpr size_t mreg = (size_t)NSP * LDI * sizeof(Real);
   // staging of one 16-row tile of a left operand: 16 x (K + pad) elements, K <= 2 NSP
   static constexpr size_t stage = (size_t)16 * (2 * NSP + 2) * sizeof(double);
-  static constexpr size_t bytes = GSCR ? pad(head) + pad(small) + stage : pad(head) + pad(bs) + xm;
+  // grad ln|D| per electron (3 x N, Real) for the one-body Jastrow term's d/dR, after the rest
+  static constexpr size_t gdoff = GSCR ? pad(head) + pad(small) + pad(stage) : pad(head) + pad(bs) + pad(xm);
+  static constexpr size_t bytes = gdoff + pad((size_t)3 * N * sizeof(Real));
   static constexpr size_t scr_bytes = GSCR ? pad(bs) + pad(bs > xm0 ? bs : xm0) + pad(mreg) : 0;
 };
 
@@ -394,6 +396,11 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
   double* stg_d = reinterpret_cast<double*>(lds2 + Lay::pad(Lay::small));   // GSCR operand staging
   Real* stg_r = reinterpret_cast<Real*>(stg_d);
   Real* Ws = GSCR ? Xr : Bs;
+  Real* gD = reinterpret_cast<Real*>(smem + Lay::gdoff);   // N x 3: grad ln|D| (one-body term only)
+  // one-body term: proton positions (3 x N), needed by the Jastrow pass only, in LDS that B
+  // (or the GEMM staging) takes later
+  double* Rp = GSCR ? stg_d : reinterpret_cast<double*>(lds2);
+  const bool one_body = m.j1_beta > 0.0;
   const int lane = t & 63, wave = t >> 6, l16 = lane & 15, l4 = lane >> 4;
   const double L = m.L, invL = m.invL;
   for (int u = t; u < 3 * N; u += 256) pos[u] = m.pos[(size_t)walker() * 3 * N + u];
@@ -405,6 +412,8 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
       trig[6 * i + ax] = s;
       trig[6 * i + 3 + ax] = c;
     }
+  if (one_body)
+    for (int u = t; u < 3 * N; u += 256) Rp[u] = m.R[u];
   __syncthreads();
   // Jastrow gradient and Laplacian per electron; HJ threads share an electron's pairs
   constexpr int HJ = (256 / N) > 0 ? (256 / N) : 1;
@@ -440,8 +449,42 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         lp += upp * gg + up * lr;
         if (j > i) ui += a * rho * iden;
       }
+      double f1sum = 0.0;
+      if (one_body) {
+        // one-body term f(rho) = -(1 - e^{-beta rho}) / beta of electron i and the protons of
+        // this thread's share: f' = -e^{-beta rho}, f'' = beta e^{-beta rho}.  The sum of f is
+        // taken as (sum e^{-beta rho} - count) / beta: the exponentials are small and varied,
+        // while summing the near-constant -1/beta of the distant protons in the Jastrow
+        // precision would drift by a rounding error per term
+        const Real beta = (Real)m.j1_beta;
+        Real sx = Real(0);
+#pragma unroll 1
+        for (int c = j0; c < j1; ++c) {
+          // sin and cos of pi d / L from the minimum-image offset itself, so that rho keeps its
+          // relative accuracy for close pairs (the cusp terms go as 1 / rho)
+          Real rt[3], cc[3];
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) {
+            Real sc, cs;
+            sincospi_half<Real>((Real)(min_image(pos[3 * i + ax] - Rp[3 * c + ax], L, invL) * invL), &sc, &cs);
+            rt[ax] = LoP * sc;
+            cc[ax] = cs;
+          }
+          const Real r2 = rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2];
+          const Real irho = dev_rsqrt<Real>(r2);
+          const Real rho = r2 * irho;
+          const Real ex = dev_exp<Real>(-beta * rho);
+          const Real gr0 = rt[0] * cc[0] * irho, gr1 = rt[1] * cc[1] * irho, gr2 = rt[2] * cc[2] * irho;
+          const Real gg = gr0 * gr0 + gr1 * gr1 + gr2 * gr2;
+          const Real lr = (cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2] - kf * r2) * irho - gg * irho;
+          g0 -= ex * gr0; g1 -= ex * gr1; g2 -= ex * gr2;
+          lp += beta * ex * gg - ex * lr;
+          sx += ex;
+        }
+        f1sum = ((double)sx - (double)(j1 - j0)) / m.j1_beta;
+      }
       double* q = jp + ((size_t)hj * N + i) * 5;
-      q[0] = (double)g0; q[1] = (double)g1; q[2] = (double)g2; q[3] = (double)lp; q[4] = (double)ui;
+      q[0] = (double)g0; q[1] = (double)g1; q[2] = (double)g2; q[3] = (double)lp; q[4] = (double)ui + f1sum;
     }
     __syncthreads();
     for (int i = t; i < N; i += 256) {
@@ -462,6 +505,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
   double dln0 = 0, dln1 = 0, dln2 = 0, dT0 = 0, dT1 = 0, dT2 = 0, tsl = 0;
   const double Ra0 = m.R[3 * a], Ra1 = m.R[3 * a + 1], Ra2 = m.R[3 * a + 2];
   const Real za = (Real)m.zeta[a];
+  const Real LoP1 = (Real)(L / VMC_PI), kf1 = (Real)((VMC_PI * invL) * (VMC_PI * invL)), beta1 = (Real)m.j1_beta;
   for (int sp = 0; sp < 2; ++sp) {
     // A^-1 of this spin into XM (NSP x LDI, zero padded)
     const double* Bi = m.Binv + ((size_t)walker() * 2 + sp) * NS * NS;
@@ -534,6 +578,38 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
     }
     }
     __syncthreads();
+    if (one_body) {
+      // grad_i ln|D| = sum_a grad phi_a(r_i) B_ai for the electrons of this spin, in HG
+      // shares of the centres, combined in a fixed order
+      constexpr int HG = 256 / NS;
+      double* gp = SM;                                  // HG x NS x 3 partial sums
+      for (int u = t; u < HG * NS; u += 256) {
+        const int i = u % NS, hg = u / NS, e = sp * NS + i;
+        const int c0 = hg * N / HG, c1 = (hg + 1) * N / HG;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 1
+        for (int c = c0; c < c1; ++c) {
+          const Real zc = (Real)m.zeta[c];
+          Real g[3][4];
+          gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e] - m.R[3 * c], L, invL), zc, (Real)L, g[0]);
+          gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e + 1] - m.R[3 * c + 1], L, invL), zc, (Real)L, g[1]);
+          gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e + 2] - m.R[3 * c + 2], L, invL), zc, (Real)L, g[2]);
+          const double b = (double)Bs[c * LDB + i];
+          s0 += b * (double)(g[0][1] * g[1][0] * g[2][0]);
+          s1 += b * (double)(g[0][0] * g[1][1] * g[2][0]);
+          s2 += b * (double)(g[0][0] * g[1][0] * g[2][1]);
+        }
+        gp[3 * u] = s0; gp[3 * u + 1] = s1; gp[3 * u + 2] = s2;
+      }
+      __syncthreads();
+      for (int u = t; u < 3 * NS; u += 256) {
+        const int i = u / 3, c = u % 3;
+        double s = 0.0;
+        for (int hg = 0; hg < HG; ++hg) s += gp[3 * (hg * NS + i) + c];
+        gD[3 * (sp * NS + i) + c] = (Real)s;
+      }
+      __syncthreads();
+    }
     // pass 1: basis derivatives -> X, and the terms that need only B
     if (act) {
 #pragma unroll 2
@@ -564,6 +640,56 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         dT0 += (double)(Real(0.5) * (glx + Real(2) * (hxx * u0 + hxy * u1 + hxz * u2))) * b;
         dT1 += (double)(Real(0.5) * (gly + Real(2) * (hxy * u0 + hyy * u1 + hyz * u2))) * b;
         dT2 += (double)(Real(0.5) * (glz + Real(2) * (hxz * u0 + hyz * u1 + hzz * u2))) * b;
+      }
+    }
+    if (one_body && act) {
+#pragma unroll 1
+      for (int s = 0; s < IPT; ++s) {
+        const int i = h + H * s;
+        if (i >= NS) continue;
+        const int e = sp * NS + i;
+        // the one-body term of centre a at electron e moves with R_a (d/dR_a = -grad_e):
+        // d ln psi/dR_a -= f' g and dT/dR_a += grad(lap f)/2 + hess f (grad U + grad ln|D|),
+        // with g = grad rho, p_m = c_m^2 - (pi/L)^2 rt_m^2, G = |g|^2, P = sum p_m,
+        // hess f = (f'' - f'/rho) g g^T + (f'/rho) diag(p),
+        // grad lap f = f''' G g + f'' (dG + (P - G) g / rho) + f' ((dP - dG) / rho - (P - G) g / rho^2),
+        // dG = 2 g (p - G) / rho, dP = -4 (pi/L)^2 rho g, f' = -x, f'' = beta x, f''' = -beta^2 x,
+        // x = e^{-beta rho}
+        // (sin and cos of pi d / L from the minimum-image offset, as in the Jastrow pass)
+        const double Ra[3] = {Ra0, Ra1, Ra2};
+        Real rt[3], cc[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          Real sc, cs;
+          sincospi_half<Real>((Real)(min_image(pos[3 * e + ax] - Ra[ax], L, invL) * invL), &sc, &cs);
+          rt[ax] = LoP1 * sc;
+          cc[ax] = cs;
+        }
+        const Real r2 = rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2];
+        const Real irho = dev_rsqrt<Real>(r2);
+        const Real rho = r2 * irho;
+        const Real x = dev_exp<Real>(-beta1 * rho);
+        const Real F1 = -x, F2 = beta1 * x, F3 = -beta1 * beta1 * x;
+        Real g_[3], p_[3], v_[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          g_[ax] = rt[ax] * cc[ax] * irho;
+          p_[ax] = cc[ax] * cc[ax] - kf1 * rt[ax] * rt[ax];
+          v_[ax] = (Real)gU[3 * e + ax] + gD[3 * e + ax];
+        }
+        const Real G = g_[0] * g_[0] + g_[1] * g_[1] + g_[2] * g_[2];
+        const Real P = p_[0] + p_[1] + p_[2];
+        const Real gv = g_[0] * v_[0] + g_[1] * v_[1] + g_[2] * v_[2];
+        const Real ha = (F2 - F1 * irho) * gv, hb = F1 * irho, PG = (P - G) * irho;
+        Real o[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const Real dG = Real(2) * g_[ax] * (p_[ax] - G) * irho, dP = Real(-4) * kf1 * rho * g_[ax];
+          const Real glap = F3 * G * g_[ax] + F2 * (dG + PG * g_[ax]) + F1 * ((dP - dG) - PG * g_[ax]) * irho;
+          o[ax] = Real(0.5) * glap + ha * g_[ax] + hb * p_[ax] * v_[ax];
+        }
+        dln0 -= (double)(F1 * g_[0]); dln1 -= (double)(F1 * g_[1]); dln2 -= (double)(F1 * g_[2]);
+        dT0 += (double)o[0]; dT1 += (double)o[1]; dT2 += (double)o[2];
       }
     }
     __syncthreads();

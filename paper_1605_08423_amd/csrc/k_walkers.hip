@@ -356,6 +356,54 @@ struct SweepLds {
   static constexpr int WAVE = MB + 16 * LDM;
   static constexpr size_t bytes(int N) { return ((size_t)4 * WAVE + 4 * (size_t)N) * sizeof(double); }
 };
+// With the one-body Jastrow term the sweeps keep sin and cos of pi R / L of every proton
+// (6 x N values of the Jastrow precision) after the centre table, then per wave the
+// one-body changes of the block's 16 proposals (FP64).
+template <class Real>
+constexpr size_t one_body_table_bytes(int N, int per_wave) {
+  return (size_t)6 * N * sizeof(Real) + (size_t)4 * per_wave * sizeof(double);
+}
+
+// The Metropolis move of electron e of walker w in sweep s.sweep: r' = r + delta (u - 1/2)
+// wrapped into the box, with the acceptance uniform; Philox key (seed, traj), counter
+// (step, w, sweep N + e, 0 | 1).
+__device__ __forceinline__ void draw_move(const SweepArgs& s, int w, int N, int e, const double* po, double delta,
+                                          double L, double invL, double& xn, double& yn, double& zn, double& ru3) {
+  const uint32_t ctr2 = (uint32_t)(s.sweep * N + e);
+  const u32x4 o0 = philox(s.step, (uint32_t)w, ctr2, 0u, s.seed, s.traj);
+  const u32x4 o1 = philox(s.step, (uint32_t)w, ctr2, 1u, s.seed, s.traj);
+  xn = wrap_box(po[0] + delta * (u01(o0.x, o0.y) - 0.5), L, invL);
+  yn = wrap_box(po[1] + delta * (u01(o0.z, o0.w) - 0.5), L, invL);
+  zn = wrap_box(po[2] + delta * (u01(o1.x, o1.y) - 0.5), L, invL);
+  ru3 = u01(o1.z, o1.w);
+}
+
+// Change of the one-body Jastrow term, sum over protons c of
+// [-(1 - e^{-beta rho_new}) + (1 - e^{-beta rho_old})] / beta, for the proposal held by the
+// lanes with this l16: quarter l4 takes the protons c = l4 mod 4 and the quarters are
+// combined by lane exchanges, so the four lanes of a proposal hold the same total.
+template <class Real, int N>
+__device__ __forceinline__ double one_body_change(const Real* Rt, double xo, double yo, double zo, double xn,
+                                                  double yn, double zn, double invL, Real LoverPi, Real beta,
+                                                  int l4) {
+  Real so[3], co[3], sn[3], cn[3];
+  dev_sincospi<Real>((Real)(xo * invL), &so[0], &co[0]);
+  dev_sincospi<Real>((Real)(yo * invL), &so[1], &co[1]);
+  dev_sincospi<Real>((Real)(zo * invL), &so[2], &co[2]);
+  dev_sincospi<Real>((Real)(xn * invL), &sn[0], &cn[0]);
+  dev_sincospi<Real>((Real)(yn * invL), &sn[1], &cn[1]);
+  dev_sincospi<Real>((Real)(zn * invL), &sn[2], &cn[2]);
+  Real acc = Real(0);
+#pragma unroll 2
+  for (int c = l4; c < N; c += 4) {
+    const Real sr[3] = {Rt[c], Rt[N + c], Rt[2 * N + c]};
+    const Real cr[3] = {Rt[3 * N + c], Rt[4 * N + c], Rt[5 * N + c]};
+    acc += one_body_exp<Real>(sn, cn, sr, cr, LoverPi, beta) - one_body_exp<Real>(so, co, sr, cr, LoverPi, beta);
+  }
+  acc += xor_lane<16>(acc);
+  acc += xor_lane<32>(acc);
+  return (double)(acc * dev_rcp<Real>(beta));
+}
 
 // Moves the NS electrons of spin `sp` of every walker once, in order, with
 // delayed updates of the inverse in blocks of 16 moves.  A proposal depends only
@@ -396,9 +444,15 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
     Rs[4 * t] = a.R[3 * t]; Rs[4 * t + 1] = a.R[3 * t + 1]; Rs[4 * t + 2] = a.R[3 * t + 2];
     Rs[4 * t + 3] = a.zeta[t];
   }
+  Real* Rt = reinterpret_cast<Real*>(Rs + 4 * N);   // one-body term: sin (3 x N), then cos (3 x N)
+  const bool one_body = a.j1_beta > 0.0;
+  if (one_body)
+    for (int t = threadIdx.x; t < 3 * N; t += blockDim.x)
+      dev_sincospi<Real>((Real)(a.R[3 * (t % N) + t / N] * a.invL), &Rt[t], &Rt[3 * N + t]);
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, l4 = lane >> 4;
+  double* D1 = reinterpret_cast<double*>(Rt + 6 * N) + NSP * wv;   // one-body change of each move
   // (the block index is read at its uses: a long-lived copy costs registers here)
   const int w = (BATCH ? bblk : (int)blockIdx.x) * 4 + wv;
   if (w >= a.W) return;
@@ -409,6 +463,23 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
   const double L = a.L, invL = a.invL;
   const Real LoverPi = (Real)(L / VMC_PI);
   const size_t bbase = ((size_t)w * 2 + sp) * NS * NS;
+  if (one_body) {
+    // a move's one-body change depends on its electron's position at the start of the
+    // half-sweep and on the protons only: all of them now, while the registers that will
+    // hold the inverse are free
+    const double* pw0 = a.pos + (size_t)w * N * 3;
+    for (int b = 0; b < NB; ++b) {
+      const int ip = 16 * b + l16;
+      if (ip < NS) {
+        const double* po = pw0 + 3 * (sp * NS + ip);
+        double xn, yn, zn, ru;
+        draw_move(s, w, N, sp * NS + ip, po, s.delta, L, invL, xn, yn, zn, ru);
+        const double d1 = one_body_change<Real, N>(Rt, po[0], po[1], po[2], xn, yn, zn, invL, LoverPi,
+                                                   (Real)a.j1_beta, l4);
+        if (l4 == 0) D1[ip] = d1;   // read after the synchronisation that follows the first M'
+      }
+    }
+  }
 
   // element (r, c) of the inverse at Bw[(16 tr + 4 v) NS] (wave-uniform) + lane offset
   double* Bw = a.Binv + bbase;
@@ -457,13 +528,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
     // the move's four uniforms: displacement x, y, z and the acceptance test
     double xn, yn, zn, ru3;
     {
-      const uint32_t ctr2 = (uint32_t)(s.sweep * N + sp * NS + ipc);
-      const u32x4 o0 = philox(s.step, (uint32_t)w, ctr2, 0u, s.seed, s.traj);
-      const u32x4 o1 = philox(s.step, (uint32_t)w, ctr2, 1u, s.seed, s.traj);
-      xn = wrap_box(xo_p + delta * (u01(o0.x, o0.y) - 0.5), L, invL);
-      yn = wrap_box(yo_p + delta * (u01(o0.z, o0.w) - 0.5), L, invL);
-      zn = wrap_box(zo_p + delta * (u01(o1.x, o1.y) - 0.5), L, invL);
-      ru3 = u01(o1.z, o1.w);
+      const double pov[3] = {xo_p, yo_p, zo_p};
+      draw_move(s, w, N, sp * NS + ipc, pov, delta, L, invL, xn, yn, zn, ru3);
     }
     // trig cache of proposal l16 along axis l4 (l4 < 3)
     Real sv = Real(0), cv = Real(1);
@@ -558,7 +624,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
       // xor-butterfly sum kept in vector registers: every lane adds the same two
       // partial sums at every step, so all lanes hold the identical total and the
       // acceptance test below takes the same branch in every lane
-      const double dU = wave_allsum((double)du);
+      double dU = wave_allsum((double)du);
+      if (one_body) dU += D1[i];
       // the Jastrow factor in the working precision of the Jastrow terms
       const double pacc = q * q * (double)dev_exp<Real>((Real)(2.0 * dU));
       double zrow[CPL];
@@ -704,9 +771,15 @@ __global__ __launch_bounds__(256, 2) void k_sweep_big(WalkerArgs a, SweepArgs s,
     Rs[4 * t] = a.R[3 * t]; Rs[4 * t + 1] = a.R[3 * t + 1]; Rs[4 * t + 2] = a.R[3 * t + 2];
     Rs[4 * t + 3] = a.zeta[t];
   }
+  Real* Rt = reinterpret_cast<Real*>(Rs + 4 * N);   // one-body term: sin (3 x N), then cos (3 x N)
+  const bool one_body = a.j1_beta > 0.0;
+  if (one_body)
+    for (int t = threadIdx.x; t < 3 * N; t += blockDim.x)
+      dev_sincospi<Real>((Real)(a.R[3 * (t % N) + t / N] * a.invL), &Rt[t], &Rt[3 * N + t]);
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, l4 = lane >> 4;
+  double* D1 = reinterpret_cast<double*>(Rt + 6 * N) + 16 * wv;   // one-body change of each proposal
   const int w = (BATCH ? bblk : (int)blockIdx.x) * 4 + wv;
   if (w >= a.W) return;
   double* PB = smem_b + (size_t)wv * SweepBigLds::WAVE;   // 16 x LDM
@@ -735,16 +808,14 @@ __global__ __launch_bounds__(256, 2) void k_sweep_big(WalkerArgs a, SweepArgs s,
   auto propose = [&](int b) {
     const int ip = 16 * b + l16;
     const double* po = pw + 3 * (sp * NS + ip);
-    const uint32_t ctr2 = (uint32_t)(s.sweep * N + sp * NS + ip);
-    const u32x4 o0 = philox(s.step, (uint32_t)w, ctr2, 0u, s.seed, s.traj);
-    const u32x4 o1 = philox(s.step, (uint32_t)w, ctr2, 1u, s.seed, s.traj);
-    xn = wrap_box(po[0] + delta * (u01(o0.x, o0.y) - 0.5), L, invL);
-    yn = wrap_box(po[1] + delta * (u01(o0.z, o0.w) - 0.5), L, invL);
-    zn = wrap_box(po[2] + delta * (u01(o1.x, o1.y) - 0.5), L, invL);
-    ru3 = u01(o1.z, o1.w);
+    draw_move(s, w, N, sp * NS + ip, po, delta, L, invL, xn, yn, zn, ru3);
     sv = Real(0); cv = Real(1);
     const double comp = (l4 == 0) ? xn : ((l4 == 1) ? yn : zn);
     dev_sincospi<Real>((Real)(comp * invL), &sv, &cv);
+    if (one_body) {
+      const double d1 = one_body_change<Real, N>(Rt, po[0], po[1], po[2], xn, yn, zn, invL, LoverPi, (Real)a.j1_beta, l4);
+      if (l4 == 0) D1[l16] = d1;   // read after the synchronisation that follows M'
+    }
   };
   // M' = Phi' C on the matrix cores -> PB (left operand layout rows) and the HBM scratch
   auto mo_rows = [&]() {
@@ -836,7 +907,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep_big(WalkerArgs a, SweepArgs s,
                 pade_u<Real>(so, co, ts[tt], tc_[tt], LoverPi, aa, bj);
         }
       }
-      const double dU = wave_allsum((double)du);
+      double dU = wave_allsum((double)du);
+      if (one_body) dU += D1[j];
       const double pacc = q * q * (double)dev_exp<Real>((Real)(2.0 * dU));
       double zrow[CPL] = {0.0, 0.0};
       if (readlane_d(ru3, j) < pacc) {
@@ -1171,8 +1243,9 @@ template <int NS, class Real>
 hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t st, const Batch* bt, int nblk) {
   dim3 grid(bt ? nblk : (a.W + 3) / 4);
   const bool img = a.nimg || sizeof(Real) == 8;
+  const size_t tab = a.j1_beta > 0.0 ? one_body_table_bytes<Real>(2 * NS, NS == 128 ? 16 : SweepLds<NS>::NSP) : 0;
   if constexpr (NS == 128) {
-    const size_t smb = SweepBigLds::bytes;
+    const size_t smb = SweepBigLds::bytes + tab;
     if (bt && img)
       hipLaunchKernelGGL((k_sweep_big<Real, 1, true>), grid, dim3(256), smb, st, a, s, *bt);
     else if (bt)
@@ -1183,7 +1256,7 @@ hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t s
       hipLaunchKernelGGL((k_sweep_big<Real, 0, false>), grid, dim3(256), smb, st, a, s, batch_or_none(bt));
     return hipGetLastError();
   } else {
-    size_t sm = sweep_smem<NS, Real>();
+    size_t sm = sweep_smem<NS, Real>() + tab;
     if (bt && img)
       hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, true>), grid, dim3(256), sm, st, a, s, *bt);
     else if (bt)

@@ -13,6 +13,7 @@ struct WalkerArgs {
   const double* zeta;  // N Gaussian exponents
   const double* C;     // N x NS MO coefficients
   double a_par, a_anti, b;
+  double j1_beta;      // one-body Jastrow f(rho) = -(1 - e^{-beta rho}) / beta per electron-proton pair; 0 = none
   double* pos;         // W x N x 3
   double* Amat;        // W x 2 x NS x NS
   double* Binv;        // W x 2 x NS x NS
@@ -56,6 +57,7 @@ struct MeasureArgs {
   const double* zeta;
   const double* C;
   double a_par, a_anti, b;
+  double j1_beta;       // as in WalkerArgs
   const double* pos;    // W x N x 3
   const double* Binv;   // W x 2 x NS x NS
   double* Vs;           // W  per-sample potential energy

@@ -144,6 +144,7 @@ int check_sys(const vmc_system* s) {
   if (!(s->box_L > 0.0) || !(s->ewald_kappa > 0.0) || s->ewald_nmax < 1 || s->ewald_nmax > 12) return VMC_EINVAL;
   if (s->precision != VMC_FP64 && s->precision != VMC_MIXED) return VMC_EINVAL;
   if (s->refine_tol != s->refine_tol) return VMC_EINVAL;
+  if (!(s->j1_b1 >= 0.0) || !std::isfinite(s->j1_b1)) return VMC_EINVAL;
   return VMC_OK;
 }
 
@@ -211,12 +212,17 @@ int image_count(vmc_traj* t, const double* zeta_dev, int* nimg) {
   return VMC_OK;
 }
 
+// The one-body term -(2Z)^{3/4} u_1((2Z)^{1/4} rho) with Z = 1 equals
+// -(1 - e^{-beta rho}) / beta for beta = b_1 (2Z)^{1/4}; the kernels take beta.
+double j1_beta(const vmc_system& s) { return s.j1_b1 > 0.0 ? s.j1_b1 * std::pow(2.0, 0.25) : 0.0; }
+
 WalkerArgs walker_args(vmc_traj* t, const double* R, const double* C, const double* zeta, int nimg) {
   WalkerArgs a{};
   a.W = t->W; a.N = t->N; a.NS = t->NS; a.nimg = nimg;
   a.L = t->sys.box_L; a.invL = 1.0 / t->sys.box_L;
   a.R = R; a.zeta = zeta; a.C = C;
   a.a_par = t->sys.a_par; a.a_anti = t->sys.a_anti; a.b = t->sys.b;
+  a.j1_beta = j1_beta(t->sys);
   a.pos = t->pos; a.Amat = t->Amat; a.Binv = t->Binv; a.ldet = t->ldet; a.sgn = t->sgn;
   a.status = t->ctx->d_status; a.nacc = t->nacc; a.rflag = t->rflag;
   // N_sigma > 64: the refinement's R uses the first N_sigma^2 doubles of the walker's
@@ -232,6 +238,7 @@ MeasureArgs measure_args(vmc_traj* t, const double* R, const double* C, const do
   m.L = t->sys.box_L; m.invL = 1.0 / t->sys.box_L;
   m.R = R; m.zeta = zeta; m.C = C;
   m.a_par = t->sys.a_par; m.a_anti = t->sys.a_anti; m.b = t->sys.b;
+  m.j1_beta = j1_beta(t->sys);
   m.pos = t->pos; m.Binv = t->Binv; m.Vs = t->Vs; m.dVs = t->dVs; m.Uj = t->Uj;
   m.acc = t->acc; m.rho_acc = t->rho_acc; m.scr = t->scr;
   return m;
@@ -743,9 +750,9 @@ struct Served {
 };
 
 struct BucketKey {
-  int n, prec, nimg, nmax;
+  int n, prec, nimg, nmax, j1;   // j1: the one-body term is on (the sweep's LDS holds a proton table)
   bool operator<(const BucketKey& o) const {
-    return std::tie(n, prec, nimg, nmax) < std::tie(o.n, o.prec, o.nimg, o.nmax);
+    return std::tie(n, prec, nimg, nmax, j1) < std::tie(o.n, o.prec, o.nimg, o.nmax, o.j1);
   }
 };
 
@@ -1198,7 +1205,8 @@ int vmc_server_tick(vmc_server* s, int* n_active, int* n_queued) {
   std::map<BucketKey, std::vector<Served*>> buckets;
   for (Served* q : s->active)
     if (q->phase == PH_SWEEP)
-      buckets[BucketKey{q->req.sys.n_protons, q->req.sys.precision, q->nimg, q->req.sys.ewald_nmax}].push_back(q);
+      buckets[BucketKey{q->req.sys.n_protons, q->req.sys.precision, q->nimg, q->req.sys.ewald_nmax,
+                         q->req.sys.j1_b1 > 0.0 ? 1 : 0}].push_back(q);
   double cmax = 0.0;
   std::map<BucketKey, double> cost;
   for (auto& kv : buckets) {

@@ -36,7 +36,7 @@ class VMCError(RuntimeError):
 class vmc_system(C.Structure):
     _fields_ = [("n_protons", C.c_int), ("box_L", C.c_double), ("ewald_kappa", C.c_double),
                 ("ewald_nmax", C.c_int), ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
-                ("precision", C.c_int), ("refine_tol", C.c_double)]
+                ("precision", C.c_int), ("refine_tol", C.c_double), ("j1_b1", C.c_double)]
 
 
 class vmc_request(C.Structure):
@@ -116,9 +116,11 @@ def _dev(t, n=None):
     return C.c_void_p(t.data_ptr())
 
 
-def make_system(n, L, kappa=None, nmax=9, a_par=0.25, a_anti=0.5, b=1.0, precision=VMC_FP64, refine_tol=0.0):
+def make_system(n, L, kappa=None, nmax=9, a_par=0.25, a_anti=0.5, b=1.0, precision=VMC_FP64, refine_tol=0.0,
+                b1=0.0):
+    """b1 > 0 adds the one-body electron-proton Jastrow term with that b_1 (0: none)."""
     return vmc_system(int(n), float(L), float(8.0 / L if kappa is None else kappa), int(nmax), a_par, a_anti, b,
-                      int(precision), float(refine_tol))
+                      int(precision), float(refine_tol), float(b1))
 
 
 class Context:

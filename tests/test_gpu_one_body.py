@@ -1,0 +1,168 @@
+"""The one-body electron-proton Jastrow term (SI, Jastrow section, Eq. e:j1, homogeneous part,
+Z = 1) on the GPU against the CPU oracle, through the C ABI: per-configuration ln|psi|, E_L and
+their proton derivatives (FP64 1e-10, mixed per-quantity bars), Metropolis chains on the
+oracle's Philox stream (the sweep's acceptance test includes the term), the request loop, and
+the variance reduction the electron-nucleus cusp brings."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1605_08423_amd.inputs import workload
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-10
+TOLMIX = {"lnpsi": 1e-6, "EL": 5e-5, "dlnpsi": 2e-5, "dEL": 2e-5}
+B1 = 2.5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    from paper_1605_08423_amd import vmc
+    return torch, vmc, vmc.Context(0)
+
+
+def T(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("name,K,precision", [("h16", 8, 0), ("h54", 4, 0), ("h128", 2, 0), ("h256", 1, 0),
+                                              ("h16", 8, 1), ("h54", 4, 1), ("h128", 2, 1), ("h256", 1, 1)])
+def test_eval_configs_one_body(oracle, dev, name, K, precision):
+    torch, vmc, ctx = dev
+    wl = workload(name)
+    say(f"[one-body eval_configs] {name} K={K} precision={precision}")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
+    pos = wl.electrons(W=K, seed_offset=5)
+    args = (T(torch, wl.R.reshape(-1)), T(torch, Cm), T(torch, wl.zeta), T(torch, pos))
+    g = vmc.vmc_eval_configs(ctx, vmc.make_system(wl.n, wl.L, precision=precision, b1=B1), *args).cpu().numpy()
+    g0 = vmc.vmc_eval_configs(ctx, vmc.make_system(wl.n, wl.L, precision=precision), *args).cpu().numpy()
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=B1)
+    n3 = 3 * wl.n
+    worst = dict.fromkeys(TOLMIX, 0.0)
+    for k in range(K):
+        r = s.local(pos[k])
+        worst["lnpsi"] = max(worst["lnpsi"], rel(g[k, 0], r["lnpsi"]))
+        worst["EL"] = max(worst["EL"], rel(g[k, 1], r["EL"]))
+        worst["dlnpsi"] = max(worst["dlnpsi"], rel(g[k, 2:2 + n3], r["dlnpsi"]))
+        worst["dEL"] = max(worst["dEL"], rel(g[k, 2 + n3:], r["dEL"]))
+        # the term is on: ln|psi| moves by U_1, which is of order -N / beta
+        assert g0[k, 0] - g[k, 0] > 0.1 * wl.n / (B1 * 2 ** 0.25)
+    say("  worst relative errors", {k: f"{v:.2e}" for k, v in worst.items()})
+    for q, v in worst.items():
+        assert v < (TOL64 if precision == 0 else TOLMIX[q]), (q, v)
+
+
+@pytest.mark.parametrize("name,W,ne,ns,precision", [("h16", 24, 2, 3, 0), ("h54", 6, 1, 2, 0), ("h128", 2, 1, 1, 0),
+                                                    ("h256", 2, 1, 1, 0), ("h54", 6, 1, 2, 1), ("h128", 2, 1, 1, 1)])
+def test_chain_one_body(oracle, dev, name, W, ne, ns, precision):
+    """Sweeps and measurements on the oracle's Philox stream.  FP64: no decision flips and
+    1e-10 on every per-walker mean; mixed: when no decision flips, the chain-level bars."""
+    torch, vmc, ctx = dev
+    wl = workload(name)
+    say(f"[one-body chain] {name} W={W} sweeps={ne}+{ns} precision={precision}")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
+    x0 = wl.electrons(W=W, seed_offset=9)
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=precision, b1=B1), W, seed=12, traj_id=5)
+    tr.set_walkers(T(torch, x0))
+    out = tr.energy_forces(T(torch, wl.R.reshape(-1)), T(torch, Cm), T(torch, wl.zeta), ne, ns, wl.delta, 2)
+    out = out.cpu().numpy()
+    acc = tr.accepts().cpu().numpy()
+    means = tr.walker_means().cpu().numpy()
+    posg = tr.get_walkers().cpu().numpy()
+    tr.close()
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=B1)
+    xo = x0.copy()
+    sums, nacc = s.vmc_run(xo, ne, ns, wl.delta, seed=12, traj=5, step=2)
+    red = oracle.reduce(sums, ns)
+    flips = int(np.sum(acc != nacc))
+    say(f"  accepted gpu/oracle {acc.sum()}/{nacc.sum()}  walkers with a flipped decision: {flips}")
+    n3 = 3 * wl.n
+    mo = red["means"]
+    errs = {}
+    for q, sl in [("e_w", slice(0, 1)), ("d_w", slice(1, 1 + n3)), ("g_w", slice(1 + n3, 1 + 2 * n3)),
+                  ("h_w", slice(1 + 2 * n3, 1 + 3 * n3))]:
+        errs[q] = max(rel(means[w, sl], mo[w, sl]) for w in range(W))
+    errs["E"] = rel(out[0], red["E"])
+    errs["f"] = rel(out[3:], red["f"])
+    say("  worst relative errors", {k: f"{v:.2e}" for k, v in errs.items()})
+    if precision == 0:
+        assert flips == 0
+        assert rel(posg, xo) < 1e-12
+        for q, v in errs.items():
+            assert v < TOL64, (q, v)
+    elif flips == 0:
+        assert errs["E"] < 1e-6 and errs["f"] < 1e-5
+        assert errs["e_w"] < TOLMIX["EL"] and errs["g_w"] < TOLMIX["dlnpsi"] and errs["d_w"] < TOLMIX["dEL"]
+
+
+def _request(vmc, wl, W, precision, b1, traj, steps=2, M=3):
+    alpha = 0.122 * W * M
+    return vmc.make_request(vmc.make_system(wl.n, wl.L, precision=precision, b1=b1), W, wl.R, wl.zeta,
+                            wl.electrons(W=W, seed_offset=traj), n_steps=steps, n_sweeps=M, T=wl.T_hartree,
+                            Delta=1.0 / alpha, alpha=alpha, n_equil_first=2, n_equil=1, step_delta=wl.delta,
+                            seed=4, traj_id=traj)
+
+
+def _serve(vmc, ctx, reqs):
+    srv = vmc.Server(ctx, 64 << 30)
+    ids = [srv.submit(r) for r in reqs]
+    srv.run_until_idle()
+    out = [(srv.status(i), srv.result(i)) for i in ids]
+    srv.close()
+    return out
+
+
+def test_served_one_body_alone_equals_in_mix(dev):
+    """Trajectories with and without the one-body term in one request loop (they run in
+    separate launches) give the results they give when served alone."""
+    torch, vmc, ctx = dev
+    wl = workload("h54")
+    reqs = [_request(vmc, wl, 176, 1, B1, 40), _request(vmc, wl, 176, 1, 0.0, 41), _request(vmc, wl, 200, 1, B1, 42)]
+    say("[one-body served] h54 mixed, two trajectories with the term and one without")
+    alone = [_serve(vmc, ctx, [r])[0] for r in reqs]
+    mixed = _serve(vmc, ctx, reqs)
+    for (sa, ra), (sm, rm) in zip(alone, mixed):
+        assert sa[0] == sm[0] == vmc.VMC_REQ_DONE
+        assert np.array_equal(ra["R"], rm["R"]) and np.array_equal(ra["E"], rm["E"])
+    assert not np.array_equal(mixed[0][1]["E"], mixed[1][1]["E"])
+
+
+def test_cusp_cuts_energy_and_force_variance(dev):
+    """With the cusp the local energy no longer carries the -1/r of each electron-proton
+    encounter: at N = 54 (mixed, 1024 walkers x 10 sweeps) sigma_E and the trace of the
+    force covariance S both drop."""
+    torch, vmc, ctx = dev
+    wl = workload("h54")
+    Cm = vmc.vmc_huckel_params(wl.R, wl.zeta, wl.L)
+    res = {}
+    for b1 in (0.0, B1):
+        tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=1, b1=b1), 1024, seed=3, traj_id=1)
+        tr.set_walkers(T(torch, wl.electrons(W=1024, seed_offset=2)))
+        out = tr.energy_forces(T(torch, wl.R.reshape(-1)), T(torch, Cm), T(torch, wl.zeta), 20, 10, wl.delta, 0)
+        S = tr.build_S().cpu().numpy()
+        out = out.cpu().numpy()
+        tr.close()
+        res[b1] = (float(out[0]), float(out[1]), float(np.trace(S)))
+        say(f"  b1={b1}: E={out[0]:.4f} sigma_E={out[1]:.4f} tr S={np.trace(S):.4e}")
+    assert res[B1][1] < 0.85 * res[0.0][1]
+    assert res[B1][2] < 0.6 * res[0.0][2]
+
+
+def test_one_body_parameter_checked(dev):
+    torch, vmc, ctx = dev
+    wl = workload("h16")
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(vmc.VMCError):
+            vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, b1=bad), 8, seed=1, traj_id=0)
