@@ -33,7 +33,7 @@ class OSys(C.Structure):
                 ("kappa", C.c_double), ("nmax", C.c_int), ("jastrow_on", C.c_int),
                 ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
                 ("R", C.POINTER(C.c_double)), ("zeta", C.POINTER(C.c_double)),
-                ("C", C.POINTER(C.c_double)), ("b1", C.c_double)]
+                ("C", C.POINTER(C.c_double)), ("b1", C.c_double), ("twist", C.c_int)]
 
 
 _lib = None
@@ -66,6 +66,7 @@ def _setup(l):
     l.o_potential.restype = d
     l.o_local.argtypes = [P(OSys), P(d), P(d), P(d), P(d), P(d), P(d)]
     l.o_huckel.argtypes = [i, d, P(d), P(d), i, P(d), P(d)]
+    l.o_huckel_twist.argtypes = [i, d, P(d), P(d), i, i, P(d), P(d)]
     l.o_vmc_run.argtypes = [P(OSys), i, P(d), i, i, d, u32, u32, u32, P(d), P(C.c_int64), i]
     l.o_reduce.argtypes = [i, i, i, P(d), P(d), P(d), P(d), P(d), P(d)]
     l.o_build_S.argtypes = [i, i, P(d), P(d), P(d)]
@@ -81,7 +82,7 @@ class System:
 
     def __init__(self, R, zeta, C_mo, L=0.0, n_up=None, n_dn=None, basis=OB_PERIODIC_GAUSS,
                  pot=OP_EWALD, kappa=None, nmax=9, jastrow=True, a_par=0.25, a_anti=0.5, b=1.0,
-                 b1=0.0):
+                 b1=0.0, twist=0):
         self.R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1, 3)
         n_p = self.R.shape[0]
         self.zeta = np.ascontiguousarray(zeta, dtype=np.float64).reshape(n_p)
@@ -95,7 +96,7 @@ class System:
             kappa = 8.0 / L if L > 0 else 0.0
         self.s = OSys(n_p, n_up, n_dn, self.C.shape[1], float(L), basis, pot, float(kappa), int(nmax),
                       int(bool(jastrow)), a_par, a_anti, b, _dp(self.R), _dp(self.zeta), _dp(self.C),
-                      float(b1))
+                      float(b1), int(twist))
 
     @property
     def n_p(self):
@@ -169,13 +170,13 @@ def normals(seed, traj, step, n):
     return xi
 
 
-def huckel(R, zeta, L, n_orb):
+def huckel(R, zeta, L, n_orb, twist=0):
     R = np.ascontiguousarray(R, dtype=np.float64)
     zeta = np.ascontiguousarray(zeta, dtype=np.float64)
     n_p = R.shape[0]
     Cm = np.zeros((n_p, n_orb))
     ev = np.zeros(n_p)
-    rc = lib().o_huckel(n_p, L, _dp(R), _dp(zeta), n_orb, _dp(Cm), _dp(ev))
+    rc = lib().o_huckel_twist(n_p, L, _dp(R), _dp(zeta), n_orb, int(twist), _dp(Cm), _dp(ev))
     if rc:
         raise RuntimeError("o_huckel failed")
     return Cm, ev

@@ -148,13 +148,17 @@ static double min_image(double d, double L) { return d - L * floor(d / L + 0.5);
 
 /* One Cartesian factor of a Gaussian and its first three derivatives.  In the
  * periodic case x is the minimum-image offset and the n = -1, 0, +1 images are
- * summed (the neglected images are below e^{-zeta (1.5 L)^2}). */
-static void gauss_1d(double x, double zeta, double L, int periodic, double g[4]) {
+ * summed (the neglected images are below e^{-zeta (1.5 L)^2}), image n weighted by
+ * tau^n: tau = 1 periodic, tau = -1 for the twist angle pi (SI, twisted boundary
+ * conditions, phi(r + n L) = e^{i theta n} phi(r)).  With tau = -1 the truncated sum
+ * jumps by 2 e^{-zeta (1.5 L)^2} where the minimum image changes (below 1e-26 for
+ * every box of the workloads). */
+static void gauss_1d(double x, double zeta, double L, int periodic, double tau, double g[4]) {
   g[0] = g[1] = g[2] = g[3] = 0.0;
   int nlo = periodic ? -1 : 0, nhi = periodic ? 1 : 0;
   for (int n = nlo; n <= nhi; ++n) {
     double t = x + n * L;
-    double e = exp(-zeta * t * t);
+    double e = (n == 0 ? 1.0 : tau) * exp(-zeta * t * t);
     g[0] += e;
     g[1] += -2.0 * zeta * t * e;
     g[2] += (4.0 * zeta * zeta * t * t - 2.0 * zeta) * e;
@@ -187,9 +191,15 @@ void o_basis(const osys* s, int a, const double r[3], double out[14]) {
   int periodic = (s->basis_kind == OB_PERIODIC_GAUSS);
   double g[3][4];
   for (int m = 0; m < 3; ++m) {
-    double d = r[m] - Ra[m];
-    if (periodic) d = min_image(d, s->L);
-    gauss_1d(d, z, s->L, periodic, g[m]);
+    double d = r[m] - Ra[m], tau = ((s->twist >> m) & 1) ? -1.0 : 1.0, sg = 1.0;
+    if (periodic) {
+      /* d = d_min + k L: the image sum at d is tau^k times the one at d_min */
+      double k = floor(d / s->L + 0.5);
+      d -= s->L * k;
+      if (fmod(fabs(k), 2.0) == 1.0) sg = tau;
+    }
+    gauss_1d(d, z, s->L, periodic, tau, g[m]);
+    for (int q = 0; q < 4; ++q) g[m][q] *= sg;
   }
   out[0] = g[0][0] * g[1][0] * g[2][0];
   out[1] = g[0][1] * g[1][0] * g[2][0];
@@ -603,6 +613,14 @@ static void jacobi_eigen(int n, double* A, double* V) {
  * normalised S~_ab = S_ab / sqrt(S_aa S_bb), H = -S~, the n_orb lowest
  * eigenvectors v, and C_ak = v_ak / sqrt(S_aa). */
 int o_huckel(int n_p, double L, const double* R, const double* zeta, int n_orb, double* C, double* evals) {
+  return o_huckel_twist(n_p, L, R, zeta, n_orb, 0, C, evals);
+}
+
+/* Hueckel orbitals of the twisted basis (real twists, bit m of twist = angle pi along m).
+ * The cell overlap of two image sums is one image sum of the plane-space overlaps,
+ * S_ab = sum_n tau^n (pi/(za+zb))^{3/2} e^{-mu |R_a - R_b + n L|^2}, tau^n = prod_m tau_m^{n_m}. */
+int o_huckel_twist(int n_p, double L, const double* R, const double* zeta, int n_orb, int twist, double* C,
+                   double* evals) {
   if (n_orb > n_p || n_orb < 0) return O_EINVAL;
   double* S = malloc(8 * n_p * n_p);
   for (int a = 0; a < n_p; ++a)
@@ -610,8 +628,9 @@ int o_huckel(int n_p, double L, const double* R, const double* zeta, int n_orb, 
       double za = zeta[a], zb = zeta[b], mu = za * zb / (za + zb);
       double v = pow(PI / (za + zb), 1.5);
       for (int m = 0; m < 3; ++m) {
-        double d = min_image(R[3 * a + m] - R[3 * b + m], L), acc = 0.0;
-        for (int n = -3; n <= 3; ++n) acc += exp(-mu * (d + n * L) * (d + n * L));
+        double tau = ((twist >> m) & 1) ? -1.0 : 1.0;
+        double d = R[3 * a + m] - R[3 * b + m], acc = 0.0;
+        for (int n = -4; n <= 4; ++n) acc += ((n & 1) ? tau : 1.0) * exp(-mu * (d + n * L) * (d + n * L));
         v *= acc;
       }
       S[a * n_p + b] = v;

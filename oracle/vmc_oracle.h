@@ -34,6 +34,9 @@ typedef struct {
   double b1;           /* one-body (electron-nucleus) Jastrow U_1 of the SI, Eq. e:j1, with
                           Z_a = 1 and no orbital part: b_1 of u_1(x) = (1 - e^{-b_1 x})/(2 b_1);
                           0 = no one-body term */
+  int twist;           /* twisted boundary conditions with real twists: bit m set means
+                          phi(r + L e_m) = -phi(r) (twist angle pi along axis m), clear means
+                          periodic (angle 0); the Jastrow stays periodic */
 } osys;
 
 /* Philox4x32-10 counter-based generator (Salmon et al., SC'11). */
@@ -47,6 +50,8 @@ int o_local(const osys* s, const double* x, double* lnpsi, double* sign, double*
             double* dlnpsi_dR, double* dEL_dR);
 int o_huckel(int n_p, double L, const double* R, const double* zeta, int n_orb,
              double* C, double* evals);
+int o_huckel_twist(int n_p, double L, const double* R, const double* zeta, int n_orb, int twist,
+                   double* C, double* evals);
 int o_vmc_run(const osys* s, int W, double* x, int n_equil, int n_meas, double delta,
               uint32_t seed, uint32_t traj, uint32_t step, double* sums, int64_t* n_acc,
               int n_threads);

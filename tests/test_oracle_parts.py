@@ -73,10 +73,41 @@ def test_box_muller_normals(oracle):
 
 
 # ---------------------------------------------------------------- basis ------
-def _sys1(oracle, L, zeta, basis=None):
+def _sys1(oracle, L, zeta, basis=None, twist=0):
     basis = oracle.OB_PERIODIC_GAUSS if basis is None else basis
     return oracle.System(R=[[0.3, -0.2, 0.1]], zeta=[zeta], C_mo=[[1.0]], L=L, n_up=1, n_dn=0,
-                         basis=basis, pot=oracle.OP_NONE, jastrow=False)
+                         basis=basis, pot=oracle.OP_NONE, jastrow=False, twist=twist)
+
+
+@pytest.mark.parametrize("L,zeta", [(5.8492, 1.0), (8.04, 0.8)])
+def test_twisted_gaussian_poisson_summation(oracle, L, zeta):
+    """Twist angle pi along x: sum_n (-1)^n e^{-z (x+nL)^2} = (2/L) sqrt(pi/z) sum_{k>=0}
+    e^{-q_k^2/(4z)} cos(q_k x), q_k = (2k+1) pi / L (Poisson summation with the frequencies
+    shifted by half a period); y and z stay periodic."""
+    s = _sys1(oracle, L, zeta, twist=1)
+    Ra = s.R[0]
+    m = np.arange(-80, 81)
+    g0 = math.sqrt(math.pi / zeta) / L * np.sum(np.exp(-math.pi ** 2 * m ** 2 / (zeta * L * L)))
+    q = (2 * np.arange(0, 60) + 1) * math.pi / L
+    for x in np.linspace(-0.7 * L, 1.6 * L, 17):
+        phi = s.basis(0, Ra + np.array([x, 0.0, 0.0]))[0]
+        gx = 2.0 / L * math.sqrt(math.pi / zeta) * np.sum(np.exp(-q ** 2 / (4 * zeta)) * np.cos(q * x))
+        assert phi == pytest.approx(gx * g0 * g0, rel=1e-12, abs=1e-15)
+
+
+@pytest.mark.parametrize("twist", range(8))
+def test_twisted_basis_boundary_condition(oracle, twist):
+    """phi(r + L e_m) = tau_m phi(r) for the value and every derivative, tau_m = -1 where bit m
+    of the twist is set (angle pi) and +1 otherwise."""
+    L = 6.1
+    s = _sys1(oracle, L, 1.1, twist=twist)
+    for r in (np.array([1.0, 2.0, -0.5]), np.array([3.2, -2.9, 2.95])):
+        b = s.basis(0, r)
+        for m in range(3):
+            e = np.zeros(3); e[m] = L
+            tau = -1.0 if (twist >> m) & 1 else 1.0
+            np.testing.assert_allclose(s.basis(0, r + e), tau * b, rtol=1e-12, atol=1e-15)
+            np.testing.assert_allclose(s.basis(0, r - 2 * e), b, rtol=1e-12, atol=1e-15)
 
 
 @pytest.mark.parametrize("L,zeta", [(5.8492, 1.0), (5.8492, 0.8), (8.04, 1.2)])
@@ -93,9 +124,9 @@ def test_periodic_gaussian_poisson_summation(oracle, L, zeta):
         assert phi == pytest.approx(gx * g0 * g0, rel=1e-13)
 
 
-@pytest.mark.parametrize("basis", [0, 1, 2])
-def test_basis_derivatives_by_finite_differences(oracle, basis):
-    s = _sys1(oracle, 5.8492, 0.9, basis)
+@pytest.mark.parametrize("basis,twist", [(0, 0), (1, 0), (2, 0), (0, 5), (0, 7)])
+def test_basis_derivatives_by_finite_differences(oracle, basis, twist):
+    s = _sys1(oracle, 5.8492, 0.9, basis, twist)
     rng = np.random.default_rng(basis)
     H = {(0, 0): 5, (1, 1): 6, (2, 2): 7, (0, 1): 8, (0, 2): 9, (1, 2): 10}
     for _ in range(5):
@@ -258,13 +289,15 @@ def test_slater_determinant_brute_force(oracle, n):
     assert res["sign"] == np.sign(dets[0] * dets[1])
 
 
-@pytest.mark.parametrize("name,b1", [("h16", 0.0), ("h6", 0.0), ("h6", 1.0), ("h16", 1.7)])
-def test_kinetic_energy_against_fd_laplacian(oracle, name, b1):
+@pytest.mark.parametrize("name,b1,twist", [("h16", 0.0, 0), ("h6", 0.0, 0), ("h6", 1.0, 0), ("h16", 1.7, 0),
+                                           ("h16", 0.0, 3), ("h16", 0.0, 7)])
+def test_kinetic_energy_against_fd_laplacian(oracle, name, b1, twist):
     """E_L - V = -1/2 sum_i (lap_i ln|psi| + |grad_i ln|psi||^2), the Laplacian taken by
-    second differences of ln|psi| in every electron coordinate (b1 > 0: with the one-body term)."""
+    second differences of ln|psi| in every electron coordinate (b1 > 0: with the one-body term;
+    twist: real twisted boundary conditions, Hueckel orbitals of that twist)."""
     wl = workload("h16") if name == "h16" else small_system(6, 1.3, seed=4)
-    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
-    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1)
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2, twist=twist)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1, twist=twist)
     x = wl.electrons(W=1)[0]
     res = s.local(x, derivs=False)
     V, _, _ = s.potential(x)
@@ -280,21 +313,22 @@ def test_kinetic_energy_against_fd_laplacian(oracle, name, b1):
     assert res["EL"] - V == pytest.approx(T, rel=1e-6, abs=1e-6)
 
 
-@pytest.mark.parametrize("name,b1", [("h16", 0.0), ("h6", 0.0), ("h6", 1.0), ("h16", 1.7)])
-def test_proton_derivatives_by_finite_differences(oracle, name, b1):
+@pytest.mark.parametrize("name,b1,twist", [("h16", 0.0, 0), ("h6", 0.0, 0), ("h6", 1.0, 0), ("h16", 1.7, 0),
+                                           ("h16", 0.0, 6), ("h16", 1.7, 7)])
+def test_proton_derivatives_by_finite_differences(oracle, name, b1, twist):
     """d ln|psi|/dR and dE_L/dR at fixed C, zeta, Jastrow and electron positions (b1 > 0: the
-    one-body term moves with the protons)."""
+    one-body term moves with the protons; twist: real twisted boundary conditions)."""
     wl = workload("h16") if name == "h16" else small_system(6, 1.3, seed=4)
-    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
-    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1)
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2, twist=twist)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1, twist=twist)
     x = wl.electrons(W=1)[0]
     res = s.local(x)
     h = 1e-5
     for t in range(0, 3 * wl.n, 1 if wl.n <= 6 else 5):
         Rp = wl.R.reshape(-1).copy(); Rm = Rp.copy()
         Rp[t] += h; Rm[t] -= h
-        a = oracle.System(Rp.reshape(-1, 3), wl.zeta, Cm, L=wl.L, b1=b1).local(x, False)
-        b = oracle.System(Rm.reshape(-1, 3), wl.zeta, Cm, L=wl.L, b1=b1).local(x, False)
+        a = oracle.System(Rp.reshape(-1, 3), wl.zeta, Cm, L=wl.L, b1=b1, twist=twist).local(x, False)
+        b = oracle.System(Rm.reshape(-1, 3), wl.zeta, Cm, L=wl.L, b1=b1, twist=twist).local(x, False)
         assert res["dlnpsi"][t] == pytest.approx((a["lnpsi"] - b["lnpsi"]) / (2 * h), rel=1e-7, abs=1e-8)
         assert res["dEL"][t] == pytest.approx((a["EL"] - b["EL"]) / (2 * h), rel=1e-6, abs=1e-7)
 
@@ -350,26 +384,28 @@ def test_open_coulomb_pair(oracle):
 
 
 # -------------------------------------------------------------- Hueckel ------
-def _overlap_quadrature(R, zeta, L, n=4000):
-    """Periodic overlap by the trapezoid rule over one cell, dimension by dimension."""
+def _overlap_quadrature(R, zeta, L, n=4000, twist=0):
+    """Periodic (or twisted: image k weighted by tau^k) overlap by the trapezoid rule over one
+    cell, dimension by dimension, from the image sums at the raw offsets."""
     xs = np.linspace(0.0, L, n, endpoint=False)
     npnt = len(zeta)
     g = np.zeros((npnt, 3, n))
     for a in range(npnt):
         for m in range(3):
+            tau = -1.0 if (twist >> m) & 1 else 1.0
             d = xs - R[a, m]
-            d = d - L * np.floor(d / L + 0.5)
-            g[a, m] = sum(np.exp(-zeta[a] * (d + k * L) ** 2) for k in range(-3, 4))
+            g[a, m] = sum(tau ** abs(k) * np.exp(-zeta[a] * (d + k * L) ** 2) for k in range(-5, 6))
     S = np.ones((npnt, npnt))
     for m in range(3):
         S *= (g[:, m, :] @ g[:, m, :].T) * (L / n)
     return S
 
 
-def test_huckel_orbitals(oracle):
+@pytest.mark.parametrize("twist", [0, 1, 7])
+def test_huckel_orbitals(oracle, twist):
     wl = small_system(10, 1.35, seed=8)
-    Cm, ev = oracle.huckel(wl.R, wl.zeta, wl.L, 5)
-    S = _overlap_quadrature(wl.R, wl.zeta, wl.L)
+    Cm, ev = oracle.huckel(wl.R, wl.zeta, wl.L, 5, twist=twist)
+    S = _overlap_quadrature(wl.R, wl.zeta, wl.L, twist=twist)
     # standard eigenproblem of -S~: the MOs are S-orthogonal with norms equal to the
     # eigenvalues of S~ (= -evals)
     np.testing.assert_allclose(Cm.T @ S @ Cm, np.diag(-ev[:5]), atol=1e-10)

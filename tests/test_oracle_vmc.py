@@ -105,11 +105,11 @@ def test_sweep_decisions_follow_psi_ratios_with_one_body_term(oracle):
         assert np.allclose(x, xs[w], rtol=0, atol=1e-12)
 
 
-@pytest.mark.parametrize("name,b1", [("h6", 0.0), ("h16", 0.0), ("h6", 1.0)])
-def test_force_estimator_equals_correlated_sampling_derivative(oracle, name, b1):
+@pytest.mark.parametrize("name,b1,twist", [("h6", 0.0, 0), ("h16", 0.0, 0), ("h6", 1.0, 0), ("h16", 0.0, 5)])
+def test_force_estimator_equals_correlated_sampling_derivative(oracle, name, b1, twist):
     wl = small_system(6, 1.3, seed=4) if name == "h6" else workload("h16")
-    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
-    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1)
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2, twist=twist)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1, twist=twist)
     xs = _samples(s, wl.electrons(W=4), 6, wl.delta, seed=5).reshape(-1, wl.n, 3)
     n3 = 3 * wl.n
     sums = np.zeros((1, 2 + 3 * n3))
@@ -125,7 +125,7 @@ def test_force_estimator_equals_correlated_sampling_derivative(oracle, name, b1)
     base = np.array(base)
 
     def E_of(Rflat):
-        sp = oracle.System(Rflat.reshape(-1, 3), wl.zeta, Cm, L=wl.L, b1=b1)
+        sp = oracle.System(Rflat.reshape(-1, 3), wl.zeta, Cm, L=wl.L, b1=b1, twist=twist)
         res = [sp.local(x, False) for x in xs]
         lw = 2 * (np.array([q["lnpsi"] for q in res]) - base)
         w = np.exp(lw - lw.max())
