@@ -276,6 +276,97 @@ def run_serve(args):
     print(json.dumps(line))
 
 
+def run_twists(args):
+    """Twist-averaged Langevin steps: one trajectory per real twist (twist angle 0 or pi per
+    axis, bitmasks 0..n-1), the walkers split evenly, each with the Hueckel orbitals of its
+    twist; the step takes the twist average of the forces and of their covariance."""
+    import torch
+    from paper_1605_08423_amd import vmc
+    from paper_1605_08423_amd.inputs import workload
+    wl = workload(args.workload, rs=args.rs)
+    N, M, n_tw = wl.n, args.sweeps, args.twists
+    Wtot = args.walkers or wl.walkers
+    W = Wtot // n_tw
+    prec = vmc.VMC_MIXED if args.precision == "mixed" else vmc.VMC_FP64
+    ctx = vmc.Context(0)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    trajs = []
+    for tw in range(n_tw):
+        tr = vmc.Trajectory(ctx, vmc.make_system(N, wl.L, precision=prec, b1=args.j1, twist=tw), W, seed=wl.seed,
+                            traj_id=tw)
+        tr.set_walkers(dev(wl.electrons(W=W, seed_offset=tw)))
+        trajs.append(tr)
+    R = dev(wl.R.reshape(-1))
+    R_prev = R.clone()
+    zeta = dev(wl.zeta)
+    n3 = 3 * N
+    S_prev = torch.empty((n3, n3), dtype=torch.float64, device="cuda")
+    f_stack = torch.empty((n_tw, n3), dtype=torch.float64, device="cuda")
+    S_stack = torch.empty((n_tw, n3, n3), dtype=torch.float64, device="cuda")
+    alpha = 0.122 * W * n_tw * M
+    Delta = 1.0 / alpha
+    state = {"first": True}
+    Es = []
+
+    def one_step(k, n_equil):
+        Rh = R.cpu().numpy()
+        E = 0.0
+        for tw, tr in enumerate(trajs):
+            Cm = vmc.vmc_huckel_params(Rh, wl.zeta, wl.L, twist=tw)
+            out = tr.energy_forces(R, dev(Cm), zeta, n_equil, M, wl.delta, step=k)
+            f_stack[tw].copy_(out[3:])
+            tr.build_S(S_stack[tw])
+            E += float(out[0]) / n_tw
+        f, S = vmc.vmc_twist_average(ctx, f_stack, S_stack)
+        if state["first"]:
+            S_prev.copy_(S)
+            R_prev.copy_(R)
+            state["first"] = False
+        rc = vmc.vmc_langevin_step(ctx, R, R_prev, S_prev, f, S, wl.T_hartree, Delta, alpha, 0, wl.seed, 0, k, wl.L)
+        if rc != 0:
+            raise RuntimeError(f"langevin step failed: {vmc._lib().vmc_strerror(rc).decode()}")
+        Es.append(E)
+
+    for k in range(args.warmup):
+        one_step(k, 20 if k == 0 else 5)
+    torch.cuda.synchronize()
+    ctx.reset_kernel_times()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        one_step(k, 20 if k == 0 else 5)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    times = ctx.kernel_times()
+    ctx.set_profiling(False)
+    value = W * n_tw * M * args.steps / elapsed
+    nm = 9
+    kset = [(nx, ny, nz) for nx in range(0, nm + 1) for ny in range(-nm, nm + 1) for nz in range(-nm, nm + 1)
+            if 0 < nx * nx + ny * ny + nz * nz <= nm * nm and (nx > 0 or (nx == 0 and (ny > 0 or (ny == 0 and nz > 0))))]
+    nk, nslot = len(kset), len({(ny, nz) for _, ny, nz in kset})
+    nimg = int(not (prec == vmc.VMC_MIXED and float(np.min(wl.zeta)) * (wl.L / 2) ** 2 >= 23.0))
+    dom_name, (dom_ms, dom_n) = max(times.items(), key=lambda kv: kv[1][0])
+    avg_s = dom_ms / max(dom_n, 1) / 1e3
+    flops, achieved, peak = roofline_numbers(work_model(dom_name, N, nk, nslot, nimg, prec == vmc.VMC_MIXED,
+                                                        args.j1 > 0), W, avg_s)
+    for tr in trajs:
+        tr.close()
+    print(json.dumps({
+        "metric": "twist-averaged VMC walker-sweeps/s with forces", "value": round(value, 1),
+        "unit": "walker-sweeps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32/f64" if prec == vmc.VMC_MIXED else "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {N} H, r_s={wl.rs}, {n_tw} real twists x {W} walkers x {M} "
+                               f"measured sweeps per Langevin step, {args.precision} precision",
+                   "N": N, "twists": n_tw, "walkers_per_twist": W, "sweeps": M, "precision": args.precision},
+        "langevin_steps_per_s": round(args.steps / elapsed, 4), "E_Ha_twist_average": Es[-1],
+        "roofline": {"bound": "alu", "kernel": dom_name, "achieved": round(achieved, 3), "peak": round(peak, 2),
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4) if peak else None, "traffic": None,
+                     "avg_launch_ms": round(avg_s * 1e3, 4)},
+        "kernel_ms": {k: round(v[0], 2) for k, v in times.items()},
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,6 +395,8 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=3)
     ap.add_argument("--serve-sweeps", type=int, default=20)
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
+    ap.add_argument("--twists", type=int, default=1, metavar="N",
+                    help="twist-averaged steps over the first N of the 8 real twists (2..8), walkers split evenly")
     ap.add_argument("--toy", action="store_true", help="the toy-model figure as a GPU workload instead")
     ap.add_argument("--toy-traj", type=int, default=65536)
     ap.add_argument("--toy-steps", type=int, default=2000)
@@ -313,6 +406,12 @@ def main():
             print("bench.py runs on one GPU only.", file=sys.stderr)
             sys.exit(2)
         run_toy(args)
+        return
+    if args.twists > 1:
+        if args.gpus != 1 or args.twists > 8:
+            print("bench.py runs on one GPU only, with at most the 8 real twists.", file=sys.stderr)
+            sys.exit(2)
+        run_twists(args)
         return
     if args.serve or args.serve_mix == "large":
         if args.gpus != 1:

@@ -76,6 +76,11 @@ typedef struct {
                          -(2Z)^{3/4} u_1((2Z)^{1/4} rho), u_1(x) = (1 - e^{-b_1 x}) / (2 b_1), summed
                          over every electron-proton pair; it gives psi the electron-nucleus cusp.
                          j1_b1 = b_1 > 0 enables it; 0 = no one-body term; < 0 or NaN: VMC_EINVAL */
+  int twist;          /* twisted boundary conditions of the orbitals (SI, basis section:
+                         phi(r + n L) = e^{i theta.n} phi(r)) for the real twists: bit m set means
+                         theta_m = pi (the orbitals change sign across the cell along axis m),
+                         clear means theta_m = 0.  0..7; the Jastrow factor stays periodic.  C must
+                         be the orbitals of the same twist (vmc_huckel_params_twist) */
 } vmc_system;
 
 /* ---------------------------------------------------------------- context -- */
@@ -196,6 +201,19 @@ int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R_dev, c
  * lowest eigenvectors v (symmetric QR iteration), C_ak = v_ak / sqrt(S_aa).
  * R, zeta: host (3N, N); C_out: host N x N/2. */
 int vmc_huckel_params(int n_protons, double box_L, const double* R, const double* zeta, double* C_out);
+/* The same for the twisted basis (twist as in vmc_system): image n of the overlap sum carries
+ * prod_m (+-1)^{n_m}.  twist = 0 is vmc_huckel_params; outside 0..7: VMC_EINVAL. */
+int vmc_huckel_params_twist(int n_protons, double box_L, int twist, const double* R, const double* zeta,
+                            double* C_out);
+
+/* Twist averaging (SI: the paper averages its estimates over a mesh of twists): n_tw
+ * independent runs of one box, one per twist (each its own trajectory, orbitals and
+ * walkers), give the force of the average f = (1/n_tw) sum_t f_t and, since the runs share no
+ * samples, the covariance of that mean S = (1/n_tw^2) sum_t S_t.  f_stack_dev n_tw x n3 and
+ * S_stack_dev n_tw x n3 x n3 (row-major) hold the runs' vmc_energy_forces forces and vmc_build_S
+ * matrices; writes f_dev (n3) and S_dev (n3 x n3).  All device memory; n_tw >= 1. */
+int vmc_twist_average(vmc_ctx* ctx, int n_tw, int n3, const double* f_stack_dev, const double* S_stack_dev,
+                      double* f_dev, double* S_dev);
 
 /* ---------------------------------------------------------------- serving --
  * Many independent trajectories (different N, r_s, T, walker counts) on one context,
@@ -205,7 +223,7 @@ int vmc_huckel_params(int n_protons, double box_L, const double* R, const double
  * Gaussian images, Ewald cut-off) sharing one launch per kernel.  A trajectory's
  * step is the same sequence as vmc_energy_forces (n_equil then n_sweeps sweeps),
  * vmc_build_S and vmc_langevin_step (S_prev = S and R_prev = R at its first step),
- * with C from vmc_huckel_params at its current R, so its results do not depend on
+ * with C from vmc_huckel_params_twist (its system's twist) at its current R, so its results do not depend on
  * what else is being served.  Host pointers in a request are read during
  * vmc_server_submit only.  A server drives its context's stream; do not use the
  * context for anything else between ticks. */

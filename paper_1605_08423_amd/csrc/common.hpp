@@ -156,6 +156,46 @@ __device__ __forceinline__ void gauss1d_n(Real x, Real zeta, Real L, Real g[4]) 
     if (NDER >= 3) g[3] += (Real(-8) * zeta * zeta * zeta * t * t * t + Real(12) * zeta * zeta * t) * e;
   }
 }
+// The same with image n weighted by tau^n (tau = -1: twist angle pi); the two images are
+// summed apart and enter once.
+template <class Real, int NDER, int NIMG>
+__device__ __forceinline__ void gauss1d_n(Real x, Real zeta, Real L, Real g[4], Real tau) {
+  Real h[4] = {Real(0), Real(0), Real(0), Real(0)};
+  g[0] = g[1] = g[2] = g[3] = Real(0);
+#pragma unroll
+  for (int n = -NIMG; n <= NIMG; ++n) {
+    Real t = x + Real(n) * L;
+    Real e = dev_exp<Real>(-zeta * t * t);
+    Real* o = (n == 0) ? g : h;
+    o[0] += e;
+    if (NDER >= 1) o[1] += Real(-2) * zeta * t * e;
+    if (NDER >= 2) o[2] += (Real(4) * zeta * zeta * t * t - Real(2) * zeta) * e;
+    if (NDER >= 3) o[3] += (Real(-8) * zeta * zeta * zeta * t * t * t + Real(12) * zeta * zeta * t) * e;
+  }
+  if (NIMG) {
+#pragma unroll
+    for (int q = 0; q <= NDER; ++q) g[q] += tau * h[q];
+  }
+}
+
+// The basis factor along one axis at the offset d = r - R_a (any real value): the
+// image sum at the minimum image d - k L, k = round(d / L), by gauss1d_n.  TW (a launch
+// with some twist): with the twist angle pi along the axis (tw = 1: phi(r + L e) = -phi(r))
+// the images carry (-1)^n and the factor at d is (-1)^k times the one at the minimum image.
+// Untwisted launches use TW = false, which is the plain periodic factor.
+template <class Real, int NDER, int NIMG, bool TW>
+__device__ __forceinline__ void basis_axis(double d, Real zeta, double L, double invL, int tw, Real g[4]) {
+  const double k = floor(d * invL + 0.5);
+  if constexpr (TW) {
+    gauss1d_n<Real, NDER, NIMG>((Real)(d - L * k), zeta, (Real)L, g, tw ? Real(-1) : Real(1));
+    if (tw & (int)k) {
+#pragma unroll
+      for (int q = 0; q <= NDER; ++q) g[q] = -g[q];
+    }
+  } else {
+    gauss1d_n<Real, NDER, NIMG>((Real)(d - L * k), zeta, (Real)L, g);
+  }
+}
 
 // Orders this wave's LDS writes before its later LDS reads (the wave's LDS
 // operations complete in order; the clobber keeps the compiler from moving them).

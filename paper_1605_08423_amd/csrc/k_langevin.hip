@@ -402,6 +402,32 @@ hipError_t launch_toy(double lambda, double k, double a, double mu, int s_kind, 
   return hipGetLastError();
 }
 
+// Twist averaging: element u of f (u < n3) and of S (n3 <= u < n3 + n3^2), each summed over
+// the runs in run order.
+__global__ __launch_bounds__(256) void k_twist_average(int n_tw, int n3, const double* f_stack,
+                                                       const double* S_stack, double* f, double* S) {
+  const size_t nS = (size_t)n3 * n3, total = n3 + nS;
+  for (size_t u = (size_t)blockIdx.x * 256 + threadIdx.x; u < total; u += (size_t)gridDim.x * 256) {
+    double s = 0.0;
+    if (u < (size_t)n3) {
+      for (int r = 0; r < n_tw; ++r) s += f_stack[(size_t)r * n3 + u];
+      f[u] = s / n_tw;
+    } else {
+      const size_t v = u - n3;
+      for (int r = 0; r < n_tw; ++r) s += S_stack[(size_t)r * nS + v];
+      S[v] = s / ((double)n_tw * n_tw);
+    }
+  }
+}
+
+hipError_t launch_twist_average(int n_tw, int n3, const double* f_stack, const double* S_stack, double* f, double* S,
+                                hipStream_t st) {
+  const size_t total = (size_t)n3 + (size_t)n3 * n3;
+  const int blocks = (int)((total + 255) / 256 < 2048 ? (total + 255) / 256 : 2048);
+  hipLaunchKernelGGL(k_twist_average, dim3(blocks), dim3(256), 0, st, n_tw, n3, f_stack, S_stack, f, S);
+  return hipGetLastError();
+}
+
 // Packs per-configuration results: [ln|psi|, E_L, dln|psi|/dR, dE_L/dR].
 __global__ void k_pack_eval(int K, int N, const double* means, const double* ldet, const double* Uj, double* out) {
   const int k = blockIdx.x;

@@ -361,7 +361,7 @@ __device__ __forceinline__ void gemm_stage_a(const Op* A, int lda, const Op* B, 
   __syncthreads();
 }
 
-template <int NS, class Real, int NIMG, bool BATCH>
+template <int NS, class Real, int NIMG, bool BATCH, bool TW>
 __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sample(MeasureArgs m, Batch bt) {
   using Lay = SlaterLds<NS, Real>;
   constexpr int N = 2 * NS;
@@ -591,9 +591,9 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         for (int c = c0; c < c1; ++c) {
           const Real zc = (Real)m.zeta[c];
           Real g[3][4];
-          gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e] - m.R[3 * c], L, invL), zc, (Real)L, g[0]);
-          gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e + 1] - m.R[3 * c + 1], L, invL), zc, (Real)L, g[1]);
-          gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e + 2] - m.R[3 * c + 2], L, invL), zc, (Real)L, g[2]);
+          basis_axis<Real, 1, NIMG, TW>(pos[3 * e] - m.R[3 * c], zc, L, invL, m.twist & 1, g[0]);
+          basis_axis<Real, 1, NIMG, TW>(pos[3 * e + 1] - m.R[3 * c + 1], zc, L, invL, (m.twist >> 1) & 1, g[1]);
+          basis_axis<Real, 1, NIMG, TW>(pos[3 * e + 2] - m.R[3 * c + 2], zc, L, invL, (m.twist >> 2) & 1, g[2]);
           const double b = (double)Bs[c * LDB + i];
           s0 += b * (double)(g[0][1] * g[1][0] * g[2][0]);
           s1 += b * (double)(g[0][0] * g[1][1] * g[2][0]);
@@ -618,9 +618,9 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         if (i >= NS) continue;
         const int e = sp * NS + i;
         Real g[3][4];
-        gauss1d_n<Real, 3, NIMG>((Real)min_image(pos[3 * e] - Ra0, L, invL), za, (Real)L, g[0]);
-        gauss1d_n<Real, 3, NIMG>((Real)min_image(pos[3 * e + 1] - Ra1, L, invL), za, (Real)L, g[1]);
-        gauss1d_n<Real, 3, NIMG>((Real)min_image(pos[3 * e + 2] - Ra2, L, invL), za, (Real)L, g[2]);
+        basis_axis<Real, 3, NIMG, TW>(pos[3 * e] - Ra0, za, L, invL, m.twist & 1, g[0]);
+        basis_axis<Real, 3, NIMG, TW>(pos[3 * e + 1] - Ra1, za, L, invL, (m.twist >> 1) & 1, g[1]);
+        basis_axis<Real, 3, NIMG, TW>(pos[3 * e + 2] - Ra2, za, L, invL, (m.twist >> 2) & 1, g[2]);
         const Real p00 = g[1][0] * g[2][0], p01 = g[0][0] * g[2][0], p02 = g[0][0] * g[1][0];
         // per-pair brackets in Real (FP32 in mixed mode, from FP32 basis values), sums in FP64
         const Real gx = g[0][1] * p00, gy = g[1][1] * p01, gz = g[2][1] * p02;
@@ -783,9 +783,9 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         const double Wv = (double)Ws[a * LDB + i];
         const int e = sp * NS + i;
         Real g[3][4];
-        gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e] - Ra0, L, invL), za, (Real)L, g[0]);
-        gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e + 1] - Ra1, L, invL), za, (Real)L, g[1]);
-        gauss1d_n<Real, 1, NIMG>((Real)min_image(pos[3 * e + 2] - Ra2, L, invL), za, (Real)L, g[2]);
+        basis_axis<Real, 1, NIMG, TW>(pos[3 * e] - Ra0, za, L, invL, m.twist & 1, g[0]);
+        basis_axis<Real, 1, NIMG, TW>(pos[3 * e + 1] - Ra1, za, L, invL, (m.twist >> 1) & 1, g[1]);
+        basis_axis<Real, 1, NIMG, TW>(pos[3 * e + 2] - Ra2, za, L, invL, (m.twist >> 2) & 1, g[2]);
         dT0 += (double)(g[0][1] * g[1][0] * g[2][0]) * Wv;
         dT1 += (double)(g[0][0] * g[1][1] * g[2][0]) * Wv;
         dT2 += (double)(g[0][0] * g[1][0] * g[2][1]) * Wv;
@@ -932,20 +932,25 @@ hipError_t launch_ewald_t(const MeasureArgs& m, const EwaldArgs& e, hipStream_t 
     hipLaunchKernelGGL((k_ewald_sample<N, Real, NMAXC, false>), grid, dim3(256), sm, st, m, e, b);
   return hipGetLastError();
 }
-template <int NS, class Real>
-hipError_t launch_slater_t(const MeasureArgs& m, hipStream_t st, const Batch* bt, int nblk) {
+template <int NS, class Real, bool TW>
+hipError_t launch_slater_tw(const MeasureArgs& m, hipStream_t st, const Batch* bt, int nblk) {
   size_t sm = SlaterLds<NS, Real>::bytes;
   const Batch b = bt ? *bt : Batch{nullptr, nullptr, 0};
   dim3 grid(bt ? nblk : m.W);
   if (m.nimg && bt)
-    hipLaunchKernelGGL((k_slater_sample<NS, Real, 1, true>), grid, dim3(256), sm, st, m, b);
+    hipLaunchKernelGGL((k_slater_sample<NS, Real, 1, true, TW>), grid, dim3(256), sm, st, m, b);
   else if (m.nimg)
-    hipLaunchKernelGGL((k_slater_sample<NS, Real, 1, false>), grid, dim3(256), sm, st, m, b);
+    hipLaunchKernelGGL((k_slater_sample<NS, Real, 1, false, TW>), grid, dim3(256), sm, st, m, b);
   else if (bt)
-    hipLaunchKernelGGL((k_slater_sample<NS, Real, 0, true>), grid, dim3(256), sm, st, m, b);
+    hipLaunchKernelGGL((k_slater_sample<NS, Real, 0, true, TW>), grid, dim3(256), sm, st, m, b);
   else
-    hipLaunchKernelGGL((k_slater_sample<NS, Real, 0, false>), grid, dim3(256), sm, st, m, b);
+    hipLaunchKernelGGL((k_slater_sample<NS, Real, 0, false, TW>), grid, dim3(256), sm, st, m, b);
   return hipGetLastError();
+}
+// (a batch holds only twisted or only untwisted trajectories: the request loop buckets them apart)
+template <int NS, class Real>
+hipError_t launch_slater_t(const MeasureArgs& m, hipStream_t st, const Batch* bt, int nblk) {
+  return m.twist ? launch_slater_tw<NS, Real, true>(m, st, bt, nblk) : launch_slater_tw<NS, Real, false>(m, st, bt, nblk);
 }
 
 #define VMC_DISPATCH_NS2(ns, CALL) \
@@ -970,15 +975,19 @@ hipError_t launch_ewald_sample(const MeasureArgs& m, const EwaldArgs& e, int mix
   if (mixed) { VMC_DISPATCH_NS2(m.NS, return (launch_ewald_t<2 * NSV, float>(m, e, st, bt, nblk))) }
   VMC_DISPATCH_NS2(m.NS, return (launch_ewald_t<2 * NSV, double>(m, e, st, bt, nblk)))
 }
-template <int NS>
-hipError_t launch_slater_fp64(const MeasureArgs& m, hipStream_t st, const Batch* bt, int nblk) {
+template <int NS, bool TW>
+hipError_t launch_slater_fp64_tw(const MeasureArgs& m, hipStream_t st, const Batch* bt, int nblk) {
   const Batch b = bt ? *bt : Batch{nullptr, nullptr, 0};
   dim3 grid(bt ? nblk : m.W);
   if (bt)
-    hipLaunchKernelGGL((k_slater_sample<NS, double, 1, true>), grid, dim3(256), (SlaterLds<NS, double>::bytes), st, m, b);
+    hipLaunchKernelGGL((k_slater_sample<NS, double, 1, true, TW>), grid, dim3(256), (SlaterLds<NS, double>::bytes), st, m, b);
   else
-    hipLaunchKernelGGL((k_slater_sample<NS, double, 1, false>), grid, dim3(256), (SlaterLds<NS, double>::bytes), st, m, b);
+    hipLaunchKernelGGL((k_slater_sample<NS, double, 1, false, TW>), grid, dim3(256), (SlaterLds<NS, double>::bytes), st, m, b);
   return hipGetLastError();
+}
+template <int NS>
+hipError_t launch_slater_fp64(const MeasureArgs& m, hipStream_t st, const Batch* bt, int nblk) {
+  return m.twist ? launch_slater_fp64_tw<NS, true>(m, st, bt, nblk) : launch_slater_fp64_tw<NS, false>(m, st, bt, nblk);
 }
 hipError_t launch_slater_sample(const MeasureArgs& m, int mixed, hipStream_t st, const Batch* bt, int nblk) {
   if (mixed) { VMC_DISPATCH_NS2(m.NS, return (launch_slater_t<NSV, float>(m, st, bt, nblk))) }

@@ -17,19 +17,20 @@
 
 namespace vmc {
 
-template <class Real, int NIMG>
+// phi_a(r); tw: bit m set = twist angle pi along axis m (real twisted boundary conditions)
+template <class Real, int NIMG, bool TW>
 __device__ __forceinline__ Real phi_value(double rx, double ry, double rz, const double* Ra, Real zeta,
-                                          double L, double invL) {
+                                          double L, double invL, int tw) {
   Real g[3][4];
-  gauss1d_n<Real, 0, NIMG>((Real)min_image(rx - Ra[0], L, invL), zeta, (Real)L, g[0]);
-  gauss1d_n<Real, 0, NIMG>((Real)min_image(ry - Ra[1], L, invL), zeta, (Real)L, g[1]);
-  gauss1d_n<Real, 0, NIMG>((Real)min_image(rz - Ra[2], L, invL), zeta, (Real)L, g[2]);
+  basis_axis<Real, 0, NIMG, TW>(rx - Ra[0], zeta, L, invL, tw & 1, g[0]);
+  basis_axis<Real, 0, NIMG, TW>(ry - Ra[1], zeta, L, invL, (tw >> 1) & 1, g[1]);
+  basis_axis<Real, 0, NIMG, TW>(rz - Ra[2], zeta, L, invL, (tw >> 2) & 1, g[2]);
   return g[0][0] * g[1][0] * g[2][0];
 }
 
 // --------------------------------------------------------------- build A ---
 // One wave per walker; electrons in order, lanes over centres then orbitals.
-template <int NS, class Real, int NIMG>
+template <int NS, class Real, int NIMG, bool TW>
 __global__ __launch_bounds__(256) void k_build_A(WalkerArgs a) {
   constexpr int N = 2 * NS;
   constexpr int WPB = 4;
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(256) void k_build_A(WalkerArgs a) {
   for (int e = 0; e < N; ++e) {
     double rx = p[3 * e], ry = p[3 * e + 1], rz = p[3 * e + 2];
     for (int c = lane; c < N; c += 64)
-      phi_s[wv][c] = phi_value<Real, NIMG>(rx, ry, rz, a.R + 3 * c, (Real)a.zeta[c], a.L, a.invL);
+      phi_s[wv][c] = phi_value<Real, NIMG, TW>(rx, ry, rz, a.R + 3 * c, (Real)a.zeta[c], a.L, a.invL, a.twist);
     wave_lds_sync();
     for (int k = lane; k < NS; k += 64) {
       double m = 0.0;
@@ -420,7 +421,7 @@ __device__ __forceinline__ double one_body_change(const Real* Rt, double xo, dou
 // Every LDS row access of the recursion is lane-private (lane = column).
 // One wave per walker; the inverse lives in matrix-core accumulator layout
 // (tile (tr, tc), element v of lane l = A^-1[16 tr + 4 v + l/16][16 tc + l%16]).
-template <int NS, class Real, int NIMG, bool BATCH>
+template <int NS, class Real, int NIMG, bool BATCH, bool TW>
 __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s, Batch bt) {
   constexpr int N = 2 * NS;
   using LY = SweepLds<NS>;
@@ -557,7 +558,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
       double ph = 0.0;
       if (cv_ok && pvalid) {
         const double* Rc = Rs + 4 * cc;
-        ph = (double)phi_value<Real, NIMG>(xn, yn, zn, Rc, (Real)Rc[3], L, invL);
+        ph = (double)phi_value<Real, NIMG, TW>(xn, yn, zn, Rc, (Real)Rc[3], L, invL, a.twist);
       }
 #pragma unroll
       for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_w(ph, bvs[tc], acc[tc]);
@@ -752,7 +753,7 @@ struct SweepBigLds {
   static constexpr size_t bytes = ((size_t)4 * WAVE + 4 * 2 * NS) * sizeof(double);
 };
 
-template <class Real, int NIMG, bool BATCH>
+template <class Real, int NIMG, bool BATCH, bool TW>
 __global__ __launch_bounds__(256, 2) void k_sweep_big(WalkerArgs a, SweepArgs s, Batch bt) {
   constexpr int NS = 128, N = 2 * NS, NT = NS / 16, NB = NS / 16, KC = N / 4, EPL = N / 64, CPL = NS / 64;
   constexpr int LDM = SweepBigLds::LDM;
@@ -829,7 +830,7 @@ __global__ __launch_bounds__(256, 2) void k_sweep_big(WalkerArgs a, SweepArgs s,
 #pragma unroll
       for (int tc = 0; tc < NT; ++tc) bvs[tc] = a.C[c * NS + 16 * tc + l16];
       const double* Rc = Rs + 4 * c;
-      const double ph = (double)phi_value<Real, NIMG>(xn, yn, zn, Rc, (Real)Rc[3], L, invL);
+      const double ph = (double)phi_value<Real, NIMG, TW>(xn, yn, zn, Rc, (Real)Rc[3], L, invL, a.twist);
 #pragma unroll
       for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_w(ph, bvs[tc], acc[tc]);
     }
@@ -1185,14 +1186,18 @@ __global__ __launch_bounds__(512, 1) void k_refine_big(WalkerArgs a, int sp, dou
 }
 
 // ----------------------------------------------------------- launchers ---
-template <int NS, class Real>
-hipError_t launch_build_A_t(const WalkerArgs& a, hipStream_t st) {
+template <int NS, class Real, bool TW>
+hipError_t launch_build_A_tw(const WalkerArgs& a, hipStream_t st) {
   dim3 grid((a.W + 3) / 4);
   if (a.nimg || sizeof(Real) == 8)
-    hipLaunchKernelGGL((k_build_A<NS, Real, 1>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_build_A<NS, Real, 1, TW>), grid, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((k_build_A<NS, Real, 0>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_build_A<NS, Real, 0, TW>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
+}
+template <int NS, class Real>
+hipError_t launch_build_A_t(const WalkerArgs& a, hipStream_t st) {
+  return a.twist ? launch_build_A_tw<NS, Real, true>(a, st) : launch_build_A_tw<NS, Real, false>(a, st);
 }
 inline Batch batch_or_none(const Batch* bt) { return bt ? *bt : Batch{nullptr, nullptr, 0}; }
 
@@ -1239,34 +1244,40 @@ template <int NS, class Real>
 size_t sweep_smem() {
   return SweepLds<NS>::bytes(2 * NS);
 }
-template <int NS, class Real>
-hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t st, const Batch* bt, int nblk) {
+// (a batch holds only twisted or only untwisted trajectories: the request loop buckets them apart)
+template <int NS, class Real, bool TW>
+hipError_t launch_sweep_tw(const WalkerArgs& a, const SweepArgs& s, hipStream_t st, const Batch* bt, int nblk) {
   dim3 grid(bt ? nblk : (a.W + 3) / 4);
   const bool img = a.nimg || sizeof(Real) == 8;
   const size_t tab = a.j1_beta > 0.0 ? one_body_table_bytes<Real>(2 * NS, NS == 128 ? 16 : SweepLds<NS>::NSP) : 0;
   if constexpr (NS == 128) {
     const size_t smb = SweepBigLds::bytes + tab;
     if (bt && img)
-      hipLaunchKernelGGL((k_sweep_big<Real, 1, true>), grid, dim3(256), smb, st, a, s, *bt);
+      hipLaunchKernelGGL((k_sweep_big<Real, 1, true, TW>), grid, dim3(256), smb, st, a, s, *bt);
     else if (bt)
-      hipLaunchKernelGGL((k_sweep_big<Real, 0, true>), grid, dim3(256), smb, st, a, s, *bt);
+      hipLaunchKernelGGL((k_sweep_big<Real, 0, true, TW>), grid, dim3(256), smb, st, a, s, *bt);
     else if (img)
-      hipLaunchKernelGGL((k_sweep_big<Real, 1, false>), grid, dim3(256), smb, st, a, s, batch_or_none(bt));
+      hipLaunchKernelGGL((k_sweep_big<Real, 1, false, TW>), grid, dim3(256), smb, st, a, s, batch_or_none(bt));
     else
-      hipLaunchKernelGGL((k_sweep_big<Real, 0, false>), grid, dim3(256), smb, st, a, s, batch_or_none(bt));
+      hipLaunchKernelGGL((k_sweep_big<Real, 0, false, TW>), grid, dim3(256), smb, st, a, s, batch_or_none(bt));
     return hipGetLastError();
   } else {
     size_t sm = sweep_smem<NS, Real>() + tab;
     if (bt && img)
-      hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, true>), grid, dim3(256), sm, st, a, s, *bt);
+      hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, true, TW>), grid, dim3(256), sm, st, a, s, *bt);
     else if (bt)
-      hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, true>), grid, dim3(256), sm, st, a, s, *bt);
+      hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, true, TW>), grid, dim3(256), sm, st, a, s, *bt);
     else if (img)
-      hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, false>), grid, dim3(256), sm, st, a, s, batch_or_none(bt));
+      hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, false, TW>), grid, dim3(256), sm, st, a, s, batch_or_none(bt));
     else
-      hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, false>), grid, dim3(256), sm, st, a, s, batch_or_none(bt));
+      hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, false, TW>), grid, dim3(256), sm, st, a, s, batch_or_none(bt));
     return hipGetLastError();
   }
+}
+
+template <int NS, class Real>
+hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t st, const Batch* bt, int nblk) {
+  return a.twist ? launch_sweep_tw<NS, Real, true>(a, s, st, bt, nblk) : launch_sweep_tw<NS, Real, false>(a, s, st, bt, nblk);
 }
 
 #define VMC_DISPATCH_NS(ns, CALL) \

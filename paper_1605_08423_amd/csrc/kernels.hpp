@@ -14,6 +14,7 @@ struct WalkerArgs {
   const double* C;     // N x NS MO coefficients
   double a_par, a_anti, b;
   double j1_beta;      // one-body Jastrow f(rho) = -(1 - e^{-beta rho}) / beta per electron-proton pair; 0 = none
+  int twist;           // bit m: twist angle pi along axis m (the orbitals change sign across the cell)
   double* pos;         // W x N x 3
   double* Amat;        // W x 2 x NS x NS
   double* Binv;        // W x 2 x NS x NS
@@ -58,6 +59,7 @@ struct MeasureArgs {
   const double* C;
   double a_par, a_anti, b;
   double j1_beta;       // as in WalkerArgs
+  int twist;            // as in WalkerArgs
   const double* pos;    // W x N x 3
   const double* Binv;   // W x 2 x NS x NS
   double* Vs;           // W  per-sample potential energy
@@ -126,6 +128,9 @@ size_t reduce_partial_doubles(int W, int n3);
 hipError_t launch_toy(double lambda, double k, double a, double mu, int s_kind, double T, double Delta,
                       double alpha, int scheme, uint32_t seed, int n_traj, int n_steps, const double* R0,
                       double* Rout, double* Umean, int* status, hipStream_t st);
+// f = mean of the n_tw rows of f_stack, S = sum of the n_tw matrices of S_stack / n_tw^2.
+hipError_t launch_twist_average(int n_tw, int n3, const double* f_stack, const double* S_stack, double* f, double* S,
+                                hipStream_t st);
 hipError_t launch_pack_eval(int K, int N, const double* means, const double* ldet, const double* Uj, double* out,
                             hipStream_t st);
 

@@ -145,6 +145,7 @@ int check_sys(const vmc_system* s) {
   if (s->precision != VMC_FP64 && s->precision != VMC_MIXED) return VMC_EINVAL;
   if (s->refine_tol != s->refine_tol) return VMC_EINVAL;
   if (!(s->j1_b1 >= 0.0) || !std::isfinite(s->j1_b1)) return VMC_EINVAL;
+  if (s->twist < 0 || s->twist > 7) return VMC_EINVAL;
   return VMC_OK;
 }
 
@@ -223,6 +224,7 @@ WalkerArgs walker_args(vmc_traj* t, const double* R, const double* C, const doub
   a.R = R; a.zeta = zeta; a.C = C;
   a.a_par = t->sys.a_par; a.a_anti = t->sys.a_anti; a.b = t->sys.b;
   a.j1_beta = j1_beta(t->sys);
+  a.twist = t->sys.twist;
   a.pos = t->pos; a.Amat = t->Amat; a.Binv = t->Binv; a.ldet = t->ldet; a.sgn = t->sgn;
   a.status = t->ctx->d_status; a.nacc = t->nacc; a.rflag = t->rflag;
   // N_sigma > 64: the refinement's R uses the first N_sigma^2 doubles of the walker's
@@ -239,6 +241,7 @@ MeasureArgs measure_args(vmc_traj* t, const double* R, const double* C, const do
   m.R = R; m.zeta = zeta; m.C = C;
   m.a_par = t->sys.a_par; m.a_anti = t->sys.a_anti; m.b = t->sys.b;
   m.j1_beta = j1_beta(t->sys);
+  m.twist = t->sys.twist;
   m.pos = t->pos; m.Binv = t->Binv; m.Vs = t->Vs; m.dVs = t->dVs; m.Uj = t->Uj;
   m.acc = t->acc; m.rho_acc = t->rho_acc; m.scr = t->scr;
   return m;
@@ -488,6 +491,14 @@ int vmc_traj_accepts(vmc_traj* t, int64_t* n_acc_dev) {
   return VMC_OK;
 }
 
+int vmc_twist_average(vmc_ctx* ctx, int n_tw, int n3, const double* f_stack, const double* S_stack, double* f,
+                      double* S) {
+  if (!ctx || n_tw < 1 || n3 < 1 || !f_stack || !S_stack || !f || !S) return VMC_EINVAL;
+  HIPCHK(hipSetDevice(ctx->device));
+  RUN(K_REDUCE, launch_twist_average(n_tw, n3, f_stack, S_stack, f, S, ctx->stream));
+  return VMC_OK;
+}
+
 int vmc_build_S_raw(vmc_ctx* ctx, int W, int n3, const double* f_w, const double* f, double* S) {
   if (!ctx || W < 2 || n3 < 1 || !f_w || !f || !S) return VMC_EINVAL;
   HIPCHK(hipSetDevice(ctx->device));
@@ -675,17 +686,26 @@ static int tridiag_qr(int n, std::vector<double>& T, std::vector<double>& Q) {
 }
 
 int vmc_huckel_params(int n, double L, const double* R, const double* zeta, double* C_out) {
-  if (n < 2 || (n & 1) || !(L > 0.0) || !R || !zeta || !C_out) return VMC_EINVAL;
+  return vmc_huckel_params_twist(n, L, 0, R, zeta, C_out);
+}
+
+int vmc_huckel_params_twist(int n, double L, int twist, const double* R, const double* zeta, double* C_out) {
+  if (n < 2 || (n & 1) || !(L > 0.0) || !R || !zeta || !C_out || twist < 0 || twist > 7) return VMC_EINVAL;
   std::vector<double> S((size_t)n * n), H((size_t)n * n), Q;
   for (int a = 0; a < n; ++a)
     for (int b = 0; b < n; ++b) {
       const double za = zeta[a], zb = zeta[b], mu = za * zb / (za + zb);
       double v = std::pow(M_PI / (za + zb), 1.5);
       for (int ax = 0; ax < 3; ++ax) {
+        // minimum image dd - m L; with the twist angle pi image k weighs (-1)^k and the
+        // sum at the raw offset is (-1)^m times the one at the minimum image
+        const double tau = ((twist >> ax) & 1) ? -1.0 : 1.0;
         double dd = R[3 * a + ax] - R[3 * b + ax];
-        dd -= L * std::floor(dd / L + 0.5);
+        const double m = std::floor(dd / L + 0.5);
+        dd -= L * m;
         double s = 0.0;
-        for (int k = -3; k <= 3; ++k) s += std::exp(-mu * (dd + k * L) * (dd + k * L));
+        for (int k = -3; k <= 3; ++k) s += ((k & 1) ? tau : 1.0) * std::exp(-mu * (dd + k * L) * (dd + k * L));
+        if (((long long)m) & 1) s *= tau;
         v *= s;
       }
       S[(size_t)a * n + b] = v;
@@ -751,8 +771,9 @@ struct Served {
 
 struct BucketKey {
   int n, prec, nimg, nmax, j1;   // j1: the one-body term is on (the sweep's LDS holds a proton table)
+  int tw;                        // some twist: the kernels' twisted instantiation
   bool operator<(const BucketKey& o) const {
-    return std::tie(n, prec, nimg, nmax, j1) < std::tie(o.n, o.prec, o.nimg, o.nmax, o.j1);
+    return std::tie(n, prec, nimg, nmax, j1, tw) < std::tie(o.n, o.prec, o.nimg, o.nmax, o.j1, o.tw);
   }
 };
 
@@ -886,7 +907,7 @@ int setup_step(vmc_server* s, Served* q) {
   const int N = r.sys.n_protons, NS = N / 2;
   hipStream_t st = ctx->stream;
   std::vector<double> Cv((size_t)N * NS);
-  int rc = vmc_huckel_params(N, r.sys.box_L, q->Rh.data(), q->zeta.data(), Cv.data());
+  int rc = vmc_huckel_params_twist(N, r.sys.box_L, r.sys.twist, q->Rh.data(), q->zeta.data(), Cv.data());
   if (rc) return rc;
   std::memcpy(q->hC, Cv.data(), Cv.size() * sizeof(double));   // the previous copy from hC has completed
   HIPCHK(hipMemcpyAsync(q->C, q->hC, Cv.size() * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1206,7 +1227,7 @@ int vmc_server_tick(vmc_server* s, int* n_active, int* n_queued) {
   for (Served* q : s->active)
     if (q->phase == PH_SWEEP)
       buckets[BucketKey{q->req.sys.n_protons, q->req.sys.precision, q->nimg, q->req.sys.ewald_nmax,
-                         q->req.sys.j1_b1 > 0.0 ? 1 : 0}].push_back(q);
+                         q->req.sys.j1_b1 > 0.0 ? 1 : 0, q->req.sys.twist != 0 ? 1 : 0}].push_back(q);
   double cmax = 0.0;
   std::map<BucketKey, double> cost;
   for (auto& kv : buckets) {

@@ -23,7 +23,8 @@ EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_
             "vmc_build_S_raw", "vmc_langevin_step", "vmc_eval_configs", "vmc_huckel_params",
             "vmc_request_bytes", "vmc_server_admit_count", "vmc_server_create", "vmc_server_destroy",
             "vmc_server_submit", "vmc_server_cancel", "vmc_server_tick", "vmc_server_status",
-            "vmc_server_result", "vmc_server_info", "vmc_toy_run"]
+            "vmc_server_result", "vmc_server_info", "vmc_toy_run", "vmc_huckel_params_twist",
+            "vmc_twist_average"]
 VMC_REQ_QUEUED, VMC_REQ_RUNNING, VMC_REQ_DONE, VMC_REQ_FAILED, VMC_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
@@ -36,7 +37,7 @@ class VMCError(RuntimeError):
 class vmc_system(C.Structure):
     _fields_ = [("n_protons", C.c_int), ("box_L", C.c_double), ("ewald_kappa", C.c_double),
                 ("ewald_nmax", C.c_int), ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
-                ("precision", C.c_int), ("refine_tol", C.c_double), ("j1_b1", C.c_double)]
+                ("precision", C.c_int), ("refine_tol", C.c_double), ("j1_b1", C.c_double), ("twist", C.c_int)]
 
 
 class vmc_request(C.Structure):
@@ -87,6 +88,8 @@ def _declare(l):
     l.vmc_eval_configs.argtypes = [vp, P(vmc_system), vp, vp, vp, i, vp, vp]
     l.vmc_toy_run.argtypes = [vp, P(vmc_toy_params), i, i, u32, vp, vp, vp, vp]
     l.vmc_huckel_params.argtypes = [i, d, P(d), P(d), P(d)]
+    l.vmc_huckel_params_twist.argtypes = [i, d, i, P(d), P(d), P(d)]
+    l.vmc_twist_average.argtypes = [vp, i, i, vp, vp, vp, vp]
     sz = C.c_size_t
     l.vmc_request_bytes.restype = sz
     l.vmc_request_bytes.argtypes = [P(vmc_request)]
@@ -117,10 +120,11 @@ def _dev(t, n=None):
 
 
 def make_system(n, L, kappa=None, nmax=9, a_par=0.25, a_anti=0.5, b=1.0, precision=VMC_FP64, refine_tol=0.0,
-                b1=0.0):
-    """b1 > 0 adds the one-body electron-proton Jastrow term with that b_1 (0: none)."""
+                b1=0.0, twist=0):
+    """b1 > 0 adds the one-body electron-proton Jastrow term with that b_1 (0: none); twist:
+    bit m = twist angle pi along axis m."""
     return vmc_system(int(n), float(L), float(8.0 / L if kappa is None else kappa), int(nmax), a_par, a_anti, b,
-                      int(precision), float(refine_tol), float(b1))
+                      int(precision), float(refine_tol), float(b1), int(twist))
 
 
 class Context:
@@ -287,17 +291,34 @@ def vmc_eval_configs(ctx: Context, system: vmc_system, R, Cmo, zeta, pos, out=No
     return out
 
 
-def vmc_huckel_params(R, zeta, L):
-    """Host helper (numpy in, numpy out)."""
+def vmc_huckel_params(R, zeta, L, twist=0):
+    """Host helper (numpy in, numpy out); twist: bit m = twist angle pi along axis m."""
     import numpy as np
     R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
     zeta = np.ascontiguousarray(zeta, dtype=np.float64)
     n = zeta.size
     Cm = np.zeros((n, n // 2))
     P = C.POINTER(C.c_double)
-    _check(_lib().vmc_huckel_params(n, float(L), R.ctypes.data_as(P), zeta.ctypes.data_as(P), Cm.ctypes.data_as(P)),
-           "vmc_huckel_params")
+    if twist == 0:
+        _check(_lib().vmc_huckel_params(n, float(L), R.ctypes.data_as(P), zeta.ctypes.data_as(P),
+                                        Cm.ctypes.data_as(P)), "vmc_huckel_params")
+    else:
+        _check(_lib().vmc_huckel_params_twist(n, float(L), int(twist), R.ctypes.data_as(P), zeta.ctypes.data_as(P),
+                                              Cm.ctypes.data_as(P)), "vmc_huckel_params_twist")
     return Cm
+
+
+def vmc_twist_average(ctx: Context, f_stack, S_stack, f=None, S=None):
+    """Force and covariance of the twist average: f_stack (n_tw x n3), S_stack (n_tw x n3 x n3)."""
+    import torch
+    n_tw, n3 = f_stack.shape
+    if f is None:
+        f = torch.empty(n3, dtype=torch.float64, device="cuda")
+    if S is None:
+        S = torch.empty((n3, n3), dtype=torch.float64, device="cuda")
+    _check(_lib().vmc_twist_average(ctx.h, n_tw, n3, _dev(f_stack, n_tw * n3), _dev(S_stack, n_tw * n3 * n3),
+                                    _dev(f, n3), _dev(S, n3 * n3)), "vmc_twist_average")
+    return f, S
 
 
 def supported_n(n):

@@ -33,12 +33,13 @@ def test_error_strings_and_supported_sizes():
     assert not vmc.supported_n(17) and not vmc.supported_n(100)
 
 
-@pytest.mark.parametrize("name", ["h16", "h54", "h128"])
-def test_host_huckel_spans_oracle_occupied_space(oracle, name):
+@pytest.mark.parametrize("name,twist", [("h16", 0), ("h54", 0), ("h128", 0), ("h16", 5), ("h54", 3), ("h128", 7)])
+def test_host_huckel_spans_oracle_occupied_space(oracle, name, twist):
+    """The library's host Hueckel helper (also with real twists) spans the oracle's occupied space."""
     from paper_1605_08423_amd import vmc
     from paper_1605_08423_amd.inputs import workload
     wl = workload(name)
-    Cg = vmc.vmc_huckel_params(wl.R, wl.zeta, wl.L)
-    Co, ev = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
+    Cg = vmc.vmc_huckel_params(wl.R, wl.zeta, wl.L, twist=twist)
+    Co, ev = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2, twist=twist)
     assert ev[wl.n // 2] - ev[wl.n // 2 - 1] > 1e-3      # non-degenerate HOMO-LUMO gap
     np.testing.assert_allclose(Cg @ Cg.T, Co @ Co.T, atol=1e-12)
