@@ -430,7 +430,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the walker-sharded multi-GPU path is a design "
-              f"(see DESIGN.md), so --gpus {args.gpus} is not supported.", file=sys.stderr)
+              f"that is not built, so --gpus {args.gpus} is not supported.", file=sys.stderr)
         sys.exit(2)
 
     import torch
