@@ -308,12 +308,15 @@ def run_twists(args):
     state = {"first": True}
     Es = []
 
+    from concurrent.futures import ThreadPoolExecutor
+    pool = ThreadPoolExecutor(max_workers=n_tw)   # the host Hueckel solves of the twists run side by side
+
     def one_step(k, n_equil):
         Rh = R.cpu().numpy()
+        Cs = list(pool.map(lambda tw: vmc.vmc_huckel_params(Rh, wl.zeta, wl.L, twist=tw), range(n_tw)))
         E = 0.0
         for tw, tr in enumerate(trajs):
-            Cm = vmc.vmc_huckel_params(Rh, wl.zeta, wl.L, twist=tw)
-            out = tr.energy_forces(R, dev(Cm), zeta, n_equil, M, wl.delta, step=k)
+            out = tr.energy_forces(R, dev(Cs[tw]), zeta, n_equil, M, wl.delta, step=k)
             f_stack[tw].copy_(out[3:])
             tr.build_S(S_stack[tw])
             E += float(out[0]) / n_tw

@@ -100,6 +100,48 @@ def test_chain_twisted_fp64(oracle, dev, name, W, ne, ns, twist):
     assert rel(out[0], red["E"]) < TOL64 and rel(out[3:], red["f"]) < TOL64
 
 
+@pytest.mark.parametrize("name,precision,twist", [("h54", 0, 6), ("h128", 1, 3)])
+def test_twist_with_one_body_term(oracle, dev, name, precision, twist):
+    """A twist and the one-body Jastrow term together (the term stays periodic): per-configuration
+    quantities and, in FP64, a two-sweep chain against the oracle.  The mixed-precision bars hold
+    for Slater matrices of ordinary condition (these configurations: below 2e4); near a node
+    (condition number kappa) the FP32 products lose about kappa * 6e-8 relative accuracy, so the
+    configurations are fixed by seed."""
+    torch, vmc, ctx = dev
+    wl = workload(name)
+    b1 = 2.5
+    say(f"[twist + one-body] {name} precision={precision} twist={twist}")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2, twist=twist)
+    sysd = vmc.make_system(wl.n, wl.L, precision=precision, twist=twist, b1=b1)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, twist=twist, b1=b1)
+    pos = wl.electrons(W=2, seed_offset=6)
+    g = vmc.vmc_eval_configs(ctx, sysd, T(torch, wl.R.reshape(-1)), T(torch, Cm), T(torch, wl.zeta),
+                             T(torch, pos)).cpu().numpy()
+    n3 = 3 * wl.n
+    tol = TOL64 if precision == 0 else None
+    for k in range(2):
+        r = s.local(pos[k])
+        errs = {"lnpsi": rel(g[k, 0], r["lnpsi"]), "EL": rel(g[k, 1], r["EL"]),
+                "dlnpsi": rel(g[k, 2:2 + n3], r["dlnpsi"]), "dEL": rel(g[k, 2 + n3:], r["dEL"])}
+        say("  config", k, {q: f"{v:.2e}" for q, v in errs.items()})
+        for q, v in errs.items():
+            assert v < (tol if tol else TOLMIX[q]), (q, v)
+    if precision == 0:
+        W = 4
+        x0 = wl.electrons(W=W, seed_offset=14)
+        tr = vmc.Trajectory(ctx, sysd, W, seed=15, traj_id=2)
+        tr.set_walkers(T(torch, x0))
+        out = tr.energy_forces(T(torch, wl.R.reshape(-1)), T(torch, Cm), T(torch, wl.zeta), 1, 1, wl.delta, 0)
+        out = out.cpu().numpy()
+        acc = tr.accepts().cpu().numpy()
+        tr.close()
+        xo = x0.copy()
+        sums, nacc = s.vmc_run(xo, 1, 1, wl.delta, seed=15, traj=2, step=0)
+        red = oracle.reduce(sums, 1)
+        assert np.array_equal(acc, nacc)
+        assert rel(out[0], red["E"]) < TOL64 and rel(out[3:], red["f"]) < TOL64
+
+
 def test_twist_average(dev):
     torch, vmc, ctx = dev
     rng = np.random.default_rng(4)
