@@ -139,6 +139,21 @@ def test_served_one_body_alone_equals_in_mix(dev):
     assert not np.array_equal(mixed[0][1]["E"], mixed[1][1]["E"])
 
 
+@pytest.mark.parametrize("name,W,precision", [("h128", 400, 1), ("h16", 64, 0)])
+def test_served_one_body_equals_alone_batched(dev, name, W, precision):
+    """The batched launches of the request loop with the one-body term (N = 128 mixed, N = 16
+    FP64): two trajectories served together equal each served alone, bit for bit."""
+    torch, vmc, ctx = dev
+    wl = workload(name)
+    reqs = [_request(vmc, wl, W, precision, B1, 50, steps=1, M=2), _request(vmc, wl, W + 8, precision, B1, 51, steps=1, M=2)]
+    say(f"[one-body served, batched] {name} W={W} precision={precision}")
+    alone = [_serve(vmc, ctx, [r])[0] for r in reqs]
+    both = _serve(vmc, ctx, reqs)
+    for (sa, ra), (sm, rm) in zip(alone, both):
+        assert sa[0] == sm[0] == vmc.VMC_REQ_DONE
+        assert np.array_equal(ra["R"], rm["R"]) and np.array_equal(ra["E"], rm["E"])
+
+
 def test_cusp_cuts_energy_and_force_variance(dev):
     """With the cusp the local energy no longer carries the -1/r of each electron-proton
     encounter: at N = 54 (mixed, 1024 walkers x 10 sweeps) sigma_E and the trace of the

@@ -191,6 +191,36 @@ def test_served_twisted_equals_single_trajectory_calls(dev):
     assert np.array_equal(res["E"], np.array(Es))
 
 
+def test_served_twists_alone_equal_mixed_batch(dev):
+    """Mixed precision, N = 54: trajectories with different twists and one untwisted one in one
+    request loop (the twisted ones share launches) equal each served alone, bit for bit."""
+    torch, vmc, ctx = dev
+    wl = workload("h54")
+    W, M = 176, 3
+    alpha = 0.122 * W * M
+    reqs = []
+    for traj, tw in [(60, 3), (61, 0), (62, 5)]:
+        sysd = vmc.make_system(wl.n, wl.L, precision=1, twist=tw)
+        reqs.append(vmc.make_request(sysd, W, wl.R, wl.zeta, wl.electrons(W=W, seed_offset=traj), n_steps=2,
+                                     n_sweeps=M, T=wl.T_hartree, Delta=1.0 / alpha, alpha=alpha, n_equil_first=2,
+                                     n_equil=1, step_delta=wl.delta, seed=3, traj_id=traj))
+
+    def serve(rs):
+        srv = vmc.Server(ctx, 16 << 30)
+        ids = [srv.submit(r) for r in rs]
+        srv.run_until_idle()
+        out = [(srv.status(i), srv.result(i)) for i in ids]
+        srv.close()
+        return out
+
+    say("[twists served] h54 mixed, twists 3, 0, 5")
+    alone = [serve([r])[0] for r in reqs]
+    together = serve(reqs)
+    for (sa, ra), (sm, rm) in zip(alone, together):
+        assert sa[0] == sm[0] == vmc.VMC_REQ_DONE
+        assert np.array_equal(ra["R"], rm["R"]) and np.array_equal(ra["E"], rm["E"])
+
+
 def test_twist_parameter_checked(dev):
     torch, vmc, ctx = dev
     wl = workload("h16")
