@@ -17,6 +17,10 @@
 //   d ln|psi|/dR_b = -sum_i B_bi grad phi_b(r_i),
 //   dT_L/dR_b = sum_i [1/2 (grad lap phi_b + 2 Hess phi_b . grad_i U) B_bi + grad phi_b(r_i) W_bi],
 //   M = X B (NS x NS), W = B M, from d A^-1 = -A^-1 dA A^-1 with dA/dR_b = -grad phi_b c_b^T.
+// With the one-body Jastrow term U also holds sum_{i,b} f(rho_ib), which moves with R_b:
+//   d ln|psi|/dR_b gets -sum_i grad f_ib, and dT_L/dR_b gets
+//   sum_i [1/2 grad lap f_ib + hess f_ib (grad_i U + grad_i ln|D|)].
+// Twisted boundary conditions change only the basis (its image signs).
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -282,8 +286,8 @@ template <> struct MM16<float> {
   static __device__ __forceinline__ int row(int l4, int v) { return 4 * l4 + v; }
 };
 
-// Per walker (one 256-thread block): Jastrow gradient/Laplacian per electron;
-// per spin the three contractions B = C A^-1 (FP64 matrix cores), M = X B and
+// Per walker (one 256-thread block): Jastrow gradient/Laplacian per electron
+// (one-body terms included); per spin the three contractions B = C A^-1 (FP64 matrix cores), M = X B and
 // W = B M (matrix cores in Real: their operands are stored as Real), dimensions
 // padded to multiples of 16 with zeros, and the elementwise basis passes that
 // build X and the d/dR terms.

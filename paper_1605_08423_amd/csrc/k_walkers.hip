@@ -358,8 +358,9 @@ struct SweepLds {
   static constexpr size_t bytes(int N) { return ((size_t)4 * WAVE + 4 * (size_t)N) * sizeof(double); }
 };
 // With the one-body Jastrow term the sweeps keep sin and cos of pi R / L of every proton
-// (6 x N values of the Jastrow precision) after the centre table, then per wave the
-// one-body changes of the block's 16 proposals (FP64).
+// (6 x N values of the Jastrow precision) after the centre table, then per wave the moves'
+// one-body changes in FP64 (k_sweep_half: all N_sigma of the half-sweep; k_sweep_big: the
+// 16 of the current block).
 template <class Real>
 constexpr size_t one_body_table_bytes(int N, int per_wave) {
   return (size_t)6 * N * sizeof(Real) + (size_t)4 * per_wave * sizeof(double);
