@@ -64,7 +64,8 @@ def test_eval_configs_twisted(oracle, dev, name, K, precision, twist):
     assert differs     # the twist changes the local energy (the test is not the periodic case)
 
 
-@pytest.mark.parametrize("name,W,ne,ns,twist", [("h16", 24, 2, 3, 7), ("h54", 6, 1, 2, 3), ("h128", 2, 1, 1, 5)])
+@pytest.mark.parametrize("name,W,ne,ns,twist", [("h16", 24, 2, 3, 7), ("h54", 6, 1, 2, 3), ("h128", 2, 1, 1, 5),
+                                                ("h256", 2, 1, 1, 6)])
 def test_chain_twisted_fp64(oracle, dev, name, W, ne, ns, twist):
     """Sweeps and measurements on the oracle's Philox stream: identical acceptances and
     per-walker means at 1e-10.  Moves that cross the cell boundary flip the sign of the moved
