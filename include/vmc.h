@@ -143,6 +143,22 @@ int vmc_traj_walker_forces(vmc_traj* traj, double* f_w_dev);
 /* Accepted moves per walker in the last call (int64, W). */
 int vmc_traj_accepts(vmc_traj* traj, int64_t* n_acc_dev);
 
+/* Checkpoint / resume of the state a trajectory owns between calls: its system and walker
+ * count (checked on load), the RNG key (seed, traj_id), the walker positions, and the per-walker
+ * means, forces and accepted-move counts of the last vmc_energy_forces call.  The Slater rows,
+ * inverses and Ewald tables are rebuilt by every vmc_energy_forces call and are not saved; the
+ * Langevin state (R, R_prev, S_prev) and the step counter are the caller's arrays and values.
+ * A trajectory loaded from a checkpoint and driven with the same R, C, zeta and step numbers
+ * continues the saved run bit for bit.
+ * vmc_traj_save: buf == NULL sets *len to the bytes needed; otherwise writes the checkpoint to
+ * host memory buf of *len bytes (VMC_EINVAL, with *len set to the need, if it is too small);
+ * waits for the trajectory's work on the context stream.
+ * vmc_traj_load: reads a checkpoint of len bytes from host memory into a trajectory created with
+ * the same system (N, box, precision, Ewald settings, one-body term, twist) and walker count;
+ * anything else, or a damaged buffer, returns VMC_EINVAL and leaves the trajectory unchanged. */
+int vmc_traj_save(vmc_traj* traj, void* buf, size_t* len);
+int vmc_traj_load(vmc_traj* traj, const void* buf, size_t len);
+
 /* a8 (main text, Eq. for Cov(f); SI, alpha paragraph): the acceleration matrix
  * S = Cov of the mean force = sum_w (f_w - f)(f_w - f)^T / (W (W - 1)) from the
  * trajectory's last vmc_energy_forces call.  S_dev: 3N x 3N. */

@@ -416,6 +416,77 @@ int vmc_traj_set_walkers(vmc_traj* t, const double* pos_dev) {
   return VMC_OK;
 }
 
+// Checkpoint layout: CkptHeader, then pos (W x N x 3), means (W x (1 + 9N)), f_w (W x 3N) as
+// doubles and nacc (W) as int64, all in host byte order.
+struct CkptHeader {
+  char magic[8];
+  uint32_t version, seed, traj_id;
+  int32_t n, w, precision, nmax, twist, have_means;
+  double box_L, kappa, a_par, a_anti, b, j1_b1;
+};
+static constexpr char kCkptMagic[8] = {'V', 'M', 'C', 'T', 'R', 'A', 'J', '1'};
+
+static size_t ckpt_bytes(const vmc_traj* t) {
+  const size_t W = t->W, N = t->N;
+  return sizeof(CkptHeader) + sizeof(double) * (W * N * 3 + W * (1 + 9 * N) + W * 3 * N) + sizeof(int64_t) * W;
+}
+
+int vmc_traj_save(vmc_traj* t, void* buf, size_t* len) {
+  if (!t || !len) return VMC_EINVAL;
+  const size_t need = ckpt_bytes(t);
+  if (!buf) { *len = need; return VMC_OK; }
+  if (*len < need) { *len = need; return VMC_EINVAL; }
+  HIPCHK(hipSetDevice(t->ctx->device));
+  HIPCHK(hipStreamSynchronize(t->ctx->stream));
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = 1; h.seed = t->seed; h.traj_id = t->traj_id;
+  h.n = t->N; h.w = t->W; h.precision = t->sys.precision; h.nmax = t->sys.ewald_nmax; h.twist = t->sys.twist;
+  h.have_means = t->have_means ? 1 : 0;
+  h.box_L = t->sys.box_L; h.kappa = t->sys.ewald_kappa; h.a_par = t->sys.a_par; h.a_anti = t->sys.a_anti;
+  h.b = t->sys.b; h.j1_b1 = t->sys.j1_b1;
+  unsigned char* p = static_cast<unsigned char*>(buf);
+  std::memcpy(p, &h, sizeof h);
+  p += sizeof h;
+  const size_t W = t->W, N = t->N;
+  const size_t nb[3] = {W * N * 3 * sizeof(double), W * (1 + 9 * N) * sizeof(double), W * 3 * N * sizeof(double)};
+  const void* src[3] = {t->pos, t->means, t->f_w};
+  for (int k = 0; k < 3; ++k) {
+    HIPCHK(hipMemcpy(p, src[k], nb[k], hipMemcpyDeviceToHost));
+    p += nb[k];
+  }
+  HIPCHK(hipMemcpy(p, t->nacc, W * sizeof(int64_t), hipMemcpyDeviceToHost));
+  *len = need;
+  return VMC_OK;
+}
+
+int vmc_traj_load(vmc_traj* t, const void* buf, size_t len) {
+  if (!t || !buf || len < sizeof(CkptHeader)) return VMC_EINVAL;
+  CkptHeader h;
+  std::memcpy(&h, buf, sizeof h);
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1 || len < ckpt_bytes(t)) return VMC_EINVAL;
+  const vmc_system& s = t->sys;
+  if (h.n != t->N || h.w != t->W || h.precision != s.precision || h.nmax != s.ewald_nmax || h.twist != s.twist ||
+      h.box_L != s.box_L || h.kappa != s.ewald_kappa || h.a_par != s.a_par || h.a_anti != s.a_anti || h.b != s.b ||
+      h.j1_b1 != s.j1_b1)
+    return VMC_EINVAL;
+  HIPCHK(hipSetDevice(t->ctx->device));
+  HIPCHK(hipStreamSynchronize(t->ctx->stream));
+  const unsigned char* p = static_cast<const unsigned char*>(buf) + sizeof h;
+  const size_t W = t->W, N = t->N;
+  const size_t nb[3] = {W * N * 3 * sizeof(double), W * (1 + 9 * N) * sizeof(double), W * 3 * N * sizeof(double)};
+  void* dst[3] = {t->pos, t->means, t->f_w};
+  for (int k = 0; k < 3; ++k) {
+    HIPCHK(hipMemcpy(dst[k], p, nb[k], hipMemcpyHostToDevice));
+    p += nb[k];
+  }
+  HIPCHK(hipMemcpy(t->nacc, p, W * sizeof(int64_t), hipMemcpyHostToDevice));
+  t->seed = h.seed;
+  t->traj_id = h.traj_id;
+  t->have_means = h.have_means != 0;
+  return VMC_OK;
+}
+
 int vmc_traj_get_walkers(vmc_traj* t, double* pos_dev) {
   if (!t || !pos_dev) return VMC_EINVAL;
   HIPCHK(hipMemcpyAsync(pos_dev, t->pos, (size_t)t->W * t->N * 3 * sizeof(double), hipMemcpyDeviceToDevice,

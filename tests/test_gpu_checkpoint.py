@@ -1,0 +1,107 @@
+"""Checkpoint / resume of a trajectory through the C ABI: a trajectory saved after one Langevin
+step and loaded into a fresh trajectory continues the run bit for bit; mismatched or damaged
+checkpoints are refused and leave the target unchanged."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1605_08423_amd.inputs import workload
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    from paper_1605_08423_amd import vmc
+    return torch, vmc, vmc.Context(0)
+
+
+def T(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _steps(torch, vmc, ctx, tr, wl, R, Rp, Sp, k0, k1, first, twist=0):
+    """Langevin steps k0..k1-1 of trajectory tr (R, R_prev, S_prev updated in place)."""
+    zeta = T(torch, wl.zeta)
+    alpha = 0.122 * tr.W * 3
+    outs = []
+    for k in range(k0, k1):
+        Cm = vmc.vmc_huckel_params(R.cpu().numpy(), wl.zeta, wl.L, twist=twist)
+        out = tr.energy_forces(R, T(torch, Cm), zeta, 2 if k == 0 else 1, 3, wl.delta, k)
+        S = tr.build_S()
+        if first and k == k0:
+            Sp.copy_(S)
+            Rp.copy_(R)
+        assert vmc.vmc_langevin_step(ctx, R, Rp, Sp, out[3:], S, wl.T_hartree, 1.0 / alpha, alpha, 0, 4, 9, k,
+                                     wl.L) == 0
+        outs.append(out.cpu().numpy())
+    return outs
+
+
+@pytest.mark.parametrize("name,W,precision,b1,twist", [("h16", 64, 0, 0.0, 0), ("h54", 176, 1, 2.5, 3)])
+def test_resume_continues_bit_for_bit(dev, name, W, precision, b1, twist):
+    torch, vmc, ctx = dev
+    wl = workload(name)
+    say(f"[checkpoint] {name} W={W} precision={precision} b1={b1} twist={twist}")
+    sysd = vmc.make_system(wl.n, wl.L, precision=precision, b1=b1, twist=twist)
+    n3 = 3 * wl.n
+
+    def fresh(seed):
+        tr = vmc.Trajectory(ctx, sysd, W, seed=seed, traj_id=9)
+        tr.set_walkers(T(torch, wl.electrons(W=W, seed_offset=3)))
+        R = T(torch, wl.R.reshape(-1))
+        return tr, R, R.clone(), torch.empty((n3, n3), dtype=torch.float64, device="cuda")
+
+    # uninterrupted: three steps
+    tr, R, Rp, Sp = fresh(21)
+    ref = _steps(torch, vmc, ctx, tr, wl, R, Rp, Sp, 0, 3, True, twist)
+    ref_pos = tr.get_walkers().cpu().numpy()
+    ref_R = R.cpu().numpy()
+    tr.close()
+    # one step, checkpoint (with the caller's R, R_prev, S_prev), then resume in a new trajectory
+    tr, R, Rp, Sp = fresh(21)
+    first = _steps(torch, vmc, ctx, tr, wl, R, Rp, Sp, 0, 1, True, twist)
+    blob = tr.save()
+    saved = (R.cpu().numpy(), Rp.cpu().numpy(), Sp.cpu().numpy())
+    tr.close()
+    tr2, R2, Rp2, Sp2 = fresh(777)            # a different seed: the checkpoint's key replaces it
+    tr2.set_walkers(T(torch, wl.electrons(W=W, seed_offset=8)))
+    tr2.load(blob)
+    R2.copy_(T(torch, saved[0])); Rp2.copy_(T(torch, saved[1])); Sp2.copy_(T(torch, saved[2]))
+    rest = _steps(torch, vmc, ctx, tr2, wl, R2, Rp2, Sp2, 1, 3, False, twist)
+    pos2 = tr2.get_walkers().cpu().numpy()
+    tr2.close()
+    for a, b in zip(ref, first + rest):
+        assert np.array_equal(a, b)
+    assert np.array_equal(ref_pos, pos2)
+    assert np.array_equal(ref_R, R2.cpu().numpy())
+
+
+def test_mismatched_or_damaged_checkpoint_refused(dev):
+    torch, vmc, ctx = dev
+    wl = workload("h16")
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L), 32, seed=1, traj_id=0)
+    tr.set_walkers(T(torch, wl.electrons(W=32)))
+    blob = tr.save()
+    x_before = tr.get_walkers().cpu().numpy()
+    for bad in (vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L), 40, seed=1, traj_id=0),
+                vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=1), 32, seed=1, traj_id=0),
+                vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, twist=1), 32, seed=1, traj_id=0)):
+        with pytest.raises(vmc.VMCError):
+            bad.load(blob)
+        bad.close()
+    with pytest.raises(vmc.VMCError):
+        tr.load(blob[:-8])
+    damaged = bytearray(blob)
+    damaged[0] ^= 0xFF
+    with pytest.raises(vmc.VMCError):
+        tr.load(bytes(damaged))
+    assert np.array_equal(tr.get_walkers().cpu().numpy(), x_before)
+    tr.close()
