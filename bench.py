@@ -521,9 +521,14 @@ def main():
         cw = args.cpu_walkers or (192 if N <= 128 else 16)
         cs = args.cpu_sweeps or (6 if N <= 128 else 2)
         v, dt = run_cpu_baseline(wl, Cm0, cw, cs, threads, args.j1)
+        # one thread on a smaller sample, for the per-core rate
+        w1 = 8 if N <= 128 else 2
+        v1, dt1 = run_cpu_baseline(wl, Cm0, w1, 2 if N <= 128 else 1, 1, args.j1)
         cpu = {"value": round(v, 3), "unit": "walker-sweeps/s", "cores": threads, "kind": "oracle",
+               "value_one_core": round(v1, 3),
                "sample": f"{cw} walkers x (1 unmeasured + {cs} measured) sweeps of the "
-                         f"same N={N} box in FP64, {dt:.1f} s"}
+                         f"same N={N} box in FP64, {dt:.1f} s; one core: {w1} walkers x "
+                         f"(1 + {2 if N <= 128 else 1}) sweeps, {dt1:.1f} s"}
     lat_ms = sorted(1e3 * x for x in lat)
     p = lambda q: lat_ms[min(len(lat_ms) - 1, int(math.ceil(q * len(lat_ms))) - 1)]
     line = {
