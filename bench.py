@@ -107,10 +107,13 @@ def run_cpu_baseline(wl, Cm, walkers: int, sweeps: int, threads: int, b1: float 
 # count 1): metric and force 30, 2 x 2 Cholesky and solves 20, Box-Muller 8, S-difference
 # term and update 22, U 6; Philox's integer rounds are not counted.
 TOY_FLOP_PER_STEP = 86
-# the series of the toy figure: (label, s_kind, scheme, alpha)
-TOY_SERIES = [("S=I, Eq. finaldyn", 2, 0, 0.0), ("S=G, Eq. finaldyn", 0, 0, 0.0),
-              ("S=G, explicit Gamma", 0, 2, 0.0), ("S=G, Eq. finaldyn_new a=0.2", 0, 0, 0.2),
-              ("S=H+mu G, Eq. finaldyn_new a=0.2", 1, 0, 0.2), ("S=G, Eq. norogna", 0, 1, 0.0)]
+# the series of the toy figure, and the main text's shifted Hessian: (label, s_kind, scheme, alpha, mu)
+# (mu = None: the figure's mu; H + mu I takes mu = 1, which keeps it positive definite where
+# the trajectories go)
+TOY_SERIES = [("S=I, Eq. finaldyn", 2, 0, 0.0, None), ("S=G, Eq. finaldyn", 0, 0, 0.0, None),
+              ("S=G, explicit Gamma", 0, 2, 0.0, None), ("S=G, Eq. finaldyn_new a=0.2", 0, 0, 0.2, None),
+              ("S=H+mu G, Eq. finaldyn_new a=0.2", 1, 0, 0.2, None), ("S=G, Eq. norogna", 0, 1, 0.0, None),
+              ("S=H+I, Eq. finaldyn_new a=0.2", 3, 0, 0.2, 1.0)]
 TOY_DELTAS = [0.05, 0.1, 0.2, 0.4, 0.7, 1.0]
 
 
@@ -128,8 +131,9 @@ def run_toy(args):
     R0 = torch.tensor(np.stack([tm["a"] * np.cos(th), tm["a"] * np.sin(th)], axis=1), dtype=torch.float64,
                       device="cuda")
     half_T = tm["T"] / 2
-    run = lambda sk, sc, D, al, seed: vmc.vmc_toy_run(ctx, R0, steps, tm["lambda_used"], tm["k"], tm["a"],
-                                                       tm["mu"], sk, tm["T"], D, al, sc, seed)
+    run = lambda sk, sc, D, al, seed, mu=None: vmc.vmc_toy_run(ctx, R0, steps, tm["lambda_used"], tm["k"], tm["a"],
+                                                                tm["mu"] if mu is None else mu, sk, tm["T"], D, al, sc,
+                                                                seed)
     run(0, 0, 0.1, 0.2, 1)                     # warm-up
     torch.cuda.synchronize()
     ctx.reset_kernel_times()
@@ -137,9 +141,9 @@ def run_toy(args):
     figure, unstable = {}, {}
     t0 = time.perf_counter()
     outs = []
-    for label, sk, sc, al in TOY_SERIES:
+    for label, sk, sc, al, mu in TOY_SERIES:
         for D in TOY_DELTAS:
-            outs.append((label, D, run(sk, sc, D, al, 1000 + len(outs))))
+            outs.append((label, D, run(sk, sc, D, al, 1000 + len(outs), mu)))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     times = ctx.kernel_times()

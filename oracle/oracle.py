@@ -75,6 +75,8 @@ def _setup(l):
     l.o_langevin.argtypes = [i, d, P(d), P(d), P(d), P(d), P(d), d, d, d, C.c_uint, u32, u32, u32]
     l.o_langevin_harmonic_run.argtypes = [i, P(d), P(d), d, d, d, C.c_uint, u32, i, P(d), P(d), i]
     l.o_toy_run.argtypes = [d, d, d, d, i, d, d, d, i, u32, u32, i, P(d), P(d), P(d)]
+    l.o_toy_S.argtypes = [d, d, d, d, i, P(d), P(d)]
+    l.o_toy_S.restype = None
 
 
 class System:
@@ -250,3 +252,11 @@ def toy_run(lam, k, a, mu, s_kind, T, Delta, alpha, scheme, seed, n_steps, R0=(1
         raise RuntimeError(f"toy run failed rc={rc}")
     out = (Um[0], Us) if keep else Um[0]
     return (out, R) if final else out
+
+
+def toy_S(lam, k, a, mu, s_kind, x):
+    """The toy model's acceleration matrix at the point x (2 x 2)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    S = np.zeros(4)
+    lib().o_toy_S(lam, k, a, mu, int(s_kind), _dp(x), _dp(S))
+    return S.reshape(2, 2)

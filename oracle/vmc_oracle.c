@@ -947,8 +947,9 @@ int o_langevin_harmonic_run(int n3, const double* K, const double* S, double T, 
 /* ------------------------------------------------------- rotating spring -- */
 /* SI "A simple toy model": U = k (|x| - a)^2 / 2 in the plane and the metric
  * G_lambda = n n^T / lambda + t t^T (radial eigenvalue 1/lambda, tangential 1).
- * s_kind 0: S = G_lambda; s_kind 1: S = H + mu G_lambda, H the Hessian of U. */
-static void toy_S(double lambda, double k, double a, double mu, int s_kind, const double x[2], double S[4]) {
+ * s_kind 0: S = G_lambda; s_kind 1: S = H + mu G_lambda, H the Hessian of U; s_kind 2: S = I;
+ * s_kind 3: S = H + mu I (the main text's proposal of an empirical Hessian shifted by mu > 0). */
+void o_toy_S(double lambda, double k, double a, double mu, int s_kind, const double x[2], double S[4]) {
   if (s_kind == 2) {   /* S = I: the conventional first-order dynamics (black points of Fig. toy) */
     S[0] = S[3] = 1.0;
     S[1] = S[2] = 0.0;
@@ -958,11 +959,11 @@ static void toy_S(double lambda, double k, double a, double mu, int s_kind, cons
   double n[2] = {x[0] / r, x[1] / r}, t[2] = {-n[1], n[0]};
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) S[2 * i + j] = n[i] * n[j] / lambda + t[i] * t[j];
-  if (s_kind == 1) {
+  if (s_kind == 1 || s_kind == 3) {
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 2; ++j) {
         double H = k * n[i] * n[j] + k * (r - a) / r * ((i == j) - n[i] * n[j]);
-        S[2 * i + j] = H + mu * S[2 * i + j];
+        S[2 * i + j] = H + mu * (s_kind == 1 ? S[2 * i + j] : (double)(i == j));
       }
   }
 }
@@ -980,13 +981,13 @@ int o_toy_run(double lambda, double k, double a, double mu, int s_kind, double T
               double alpha, int scheme, uint32_t seed, uint32_t traj, int n_steps, double* R, double* U_mean,
               double* U_samples) {
   double Rp[2] = {R[0], R[1]}, S[4], Sp[4];
-  toy_S(lambda, k, a, mu, s_kind, R, Sp);
+  o_toy_S(lambda, k, a, mu, s_kind, R, Sp);
   double acc = 0.0;
   int cnt = 0, burn = n_steps / 10;
   for (int t = 0; t < n_steps; ++t) {
     double r = sqrt(R[0] * R[0] + R[1] * R[1]);
     double f[2] = {-k * (r - a) * R[0] / r, -k * (r - a) * R[1] / r};
-    toy_S(lambda, k, a, mu, s_kind, R, S);
+    o_toy_S(lambda, k, a, mu, s_kind, R, S);
     int rc;
     if (scheme == 0 || scheme == 1) {
       rc = o_langevin(2, 0.0, R, Rp, Sp, f, S, T, Delta, scheme == 0 ? alpha : 0.0,
@@ -998,8 +999,8 @@ int o_toy_run(double lambda, double k, double a, double mu, int s_kind, double T
       for (int i = 0; i < 2; ++i) {
         double xp[2] = {R[0], R[1]}, xm[2] = {R[0], R[1]}, Spp[4], Smm[4], Sip[4], Sim[4];
         xp[i] += h; xm[i] -= h;
-        toy_S(lambda, k, a, mu, s_kind, xp, Spp);
-        toy_S(lambda, k, a, mu, s_kind, xm, Smm);
+        o_toy_S(lambda, k, a, mu, s_kind, xp, Spp);
+        o_toy_S(lambda, k, a, mu, s_kind, xm, Smm);
         inv2(Spp, Sip); inv2(Smm, Sim);
         for (int j = 0; j < 2; ++j) Gam[j] += (Sip[2 * j + i] - Sim[2 * j + i]) / (2 * h);
       }

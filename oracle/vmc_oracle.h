@@ -69,6 +69,7 @@ int o_toy_run(double lambda, double k, double a, double mu, int s_kind, double T
               double alpha, int scheme, uint32_t seed, uint32_t traj, int n_steps, double* R, double* U_mean,
               double* U_samples);
 void o_normals(uint32_t seed, uint32_t traj, uint32_t step, int n, double* xi);
+void o_toy_S(double lambda, double k, double a, double mu, int s_kind, const double x[2], double S[4]);
 
 #define O_STEP_CFOLD 1u
 #define O_STEP_NOISE_CORR 2u

@@ -300,6 +300,14 @@ struct ToyArgs {
 
 __device__ __forceinline__ void toy_metric(const ToyArgs& p, double x, double y, double S[3]) {
   if (p.s_kind == 2) { S[0] = 1.0; S[1] = 0.0; S[2] = 1.0; return; }
+  if (p.s_kind == 3) {
+    // S = H + mu I
+    const double r = sqrt(x * x + y * y), nx = x / r, ny = y / r, c = p.k * (r - p.a) / r;
+    S[0] = p.k * nx * nx + c * (1.0 - nx * nx) + p.mu;
+    S[1] = p.k * nx * ny - c * nx * ny;
+    S[2] = p.k * ny * ny + c * (1.0 - ny * ny) + p.mu;
+    return;
+  }
   const double r = sqrt(x * x + y * y), nx = x / r, ny = y / r;
   const double il = 1.0 / p.lambda;
   // n n^T / lambda + t t^T with t = (-ny, nx)

@@ -275,7 +275,7 @@ class vmc_toy_params(C.Structure):
                 ("scheme", C.c_int)]
 
 
-TOY_S_G, TOY_S_HESSIAN, TOY_S_IDENTITY = 0, 1, 2
+TOY_S_G, TOY_S_HESSIAN, TOY_S_IDENTITY, TOY_S_HESSIAN_SHIFT = 0, 1, 2, 3
 TOY_FINALDYN_NEW, TOY_NOROGNA, TOY_EXPLICIT_GAMMA = 0, 1, 2
 
 

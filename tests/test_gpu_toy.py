@@ -33,10 +33,10 @@ def ring_starts(n, seed):
     return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
 
 
-def gpu_run(torch, vmc, ctx, R0, n_steps, s_kind, scheme, D, alpha, seed, lam=None):
+def gpu_run(torch, vmc, ctx, R0, n_steps, s_kind, scheme, D, alpha, seed, lam=None, mu=None):
     R0d = torch.tensor(np.ascontiguousarray(R0), dtype=torch.float64, device="cuda")
     R, U, st = vmc.vmc_toy_run(ctx, R0d, n_steps, TM["lambda_used"] if lam is None else lam, TM["k"], TM["a"],
-                               TM["mu"], s_kind, TM["T"], D, alpha, scheme, seed)
+                               TM["mu"] if mu is None else mu, s_kind, TM["T"], D, alpha, scheme, seed)
     torch.cuda.synchronize()
     return R.cpu().numpy(), U.cpu().numpy(), st.cpu().numpy()
 
@@ -49,6 +49,8 @@ CASES = [  # (s_kind, scheme, Delta, alpha)
     (0, 1, 0.05, 0.0),  # Eq. norogna
     (0, 2, 0.05, 0.0),  # explicit Gamma
     (1, 2, 0.05, 0.0),
+    (3, 0, 0.2, 0.2),   # H + mu I (mu = 1), Eq. finaldyn_new
+    (3, 2, 0.05, 0.0),  # H + mu I, explicit Gamma
 ]
 
 
@@ -58,10 +60,11 @@ def test_toy_trajectories_match_oracle(oracle, dev, s_kind, scheme, D, alpha):
     n, steps, seed = 6, 400, 17
     say(f"[toy parity] s_kind={s_kind} scheme={scheme} D={D} alpha={alpha}")
     R0 = ring_starts(n, 3)
-    Rg, Ug, st = gpu_run(torch, vmc, ctx, R0, steps, s_kind, scheme, D, alpha, seed)
+    mu = 1.0 if s_kind == 3 else TM["mu"]
+    Rg, Ug, st = gpu_run(torch, vmc, ctx, R0, steps, s_kind, scheme, D, alpha, seed, mu=mu)
     assert np.all(st == 0)
     for i in range(n):
-        (uo, Ro) = oracle.toy_run(TM["lambda_used"], TM["k"], TM["a"], TM["mu"], s_kind, TM["T"], D, alpha, scheme,
+        (uo, Ro) = oracle.toy_run(TM["lambda_used"], TM["k"], TM["a"], mu, s_kind, TM["T"], D, alpha, scheme,
                                   seed, steps, R0=R0[i], traj=i, final=True)
         # 1e-10 relative on the path; the explicit-Gamma scheme divides rounding by 2h (h = 1e-6)
         tol = 1e-9 if scheme == 2 else 1e-10
@@ -105,7 +108,7 @@ def test_toy_figure_claims_from_gpu_ensembles(dev):
 def test_toy_rejects_bad_parameters(dev):
     torch, vmc, ctx = dev
     R0 = torch.zeros((4, 2), dtype=torch.float64, device="cuda") + 1.4
-    for kw in ({"D": 0.0}, {"s_kind": 3}, {"scheme": 5}, {"lam": -1.0}):
+    for kw in ({"D": 0.0}, {"s_kind": 4}, {"scheme": 5}, {"lam": -1.0}):
         args = dict(s_kind=0, scheme=0, D=0.1, lam=0.1)
         args.update(kw)
         with pytest.raises(vmc.VMCError):

@@ -256,3 +256,45 @@ def test_toy_noise_stream_follows_the_trajectory_id(oracle):
     (_, r0b) = oracle.toy_run(*args, traj=0, final=True)
     (_, r1) = oracle.toy_run(*args, traj=1, final=True)
     assert np.array_equal(r0, r0b) and not np.allclose(r0, r1)
+
+
+@pytest.mark.parametrize("s_kind", [0, 1, 2, 3])
+def test_toy_acceleration_matrices(oracle, s_kind):
+    """The toy model's S at points of the plane against its definitions: G_lambda has radial
+    eigenvalue 1/lambda and tangential eigenvalue 1; H is the Hessian of U = k (|x| - a)^2 / 2,
+    taken here by central differences of U; S = H + mu G_lambda, I, or H + mu I (the main
+    text's shifted Hessian)."""
+    tm = PAPER["toy_model"]
+    lam, k, a, mu = tm["lambda_used"], tm["k"], tm["a"], tm["mu"]
+    U = lambda x: 0.5 * k * (np.hypot(x[0], x[1]) - a) ** 2
+    rng = np.random.default_rng(s_kind)
+    for _ in range(6):
+        x = rng.uniform(-2.0, 2.0, 2)
+        if np.hypot(*x) < 0.3:
+            continue
+        n = x / np.hypot(*x)
+        tv = np.array([-n[1], n[0]])
+        G = np.outer(n, n) / lam + np.outer(tv, tv)
+        h = 1e-4
+        H = np.zeros((2, 2))
+        for i in range(2):
+            for j in range(2):
+                ei, ej = np.eye(2)[i] * h, np.eye(2)[j] * h
+                H[i, j] = (U(x + ei + ej) - U(x + ei - ej) - U(x - ei + ej) + U(x - ei - ej)) / (4 * h * h)
+        want = {0: G, 1: H + mu * G, 2: np.eye(2), 3: H + mu * np.eye(2)}[s_kind]
+        np.testing.assert_allclose(oracle.toy_S(lam, k, a, mu, s_kind, x), want, rtol=1e-6, atol=1e-6)
+    if s_kind == 0:
+        w = np.linalg.eigvalsh(oracle.toy_S(lam, k, a, mu, 0, np.array([0.3, 1.1])))
+        np.testing.assert_allclose(sorted(w), sorted([1.0 / lam, 1.0]), rtol=1e-12)
+
+
+def test_toy_model_shifted_hessian_equilibrium(oracle):
+    """S = H + mu I is positive definite only where r > a k / (k + mu); with mu = 1 (the main
+    text leaves mu to be chosen; the figure's 1/2 belongs to H + mu G_lambda) that region is seven
+    thermal widths inside the ring, and the adopted scheme samples the canonical <U> = T/2 at a
+    small step."""
+    tm = PAPER["toy_model"]
+    T = tm["T"]
+    u = np.mean([oracle.toy_run(tm["lambda_used"], tm["k"], tm["a"], 1.0, 3, T, 0.05, tm["alpha"], 0, 20 + s, 60000)
+                 for s in range(4)])
+    assert abs(u / (T / 2) - 1.0) < 0.04, u
