@@ -113,7 +113,7 @@ TOY_FLOP_PER_STEP = 86
 TOY_SERIES = [("S=I, Eq. finaldyn", 2, 0, 0.0, None), ("S=G, Eq. finaldyn", 0, 0, 0.0, None),
               ("S=G, explicit Gamma", 0, 2, 0.0, None), ("S=G, Eq. finaldyn_new a=0.2", 0, 0, 0.2, None),
               ("S=H+mu G, Eq. finaldyn_new a=0.2", 1, 0, 0.2, None), ("S=G, Eq. norogna", 0, 1, 0.0, None),
-              ("S=H+I, Eq. finaldyn_new a=0.2", 3, 0, 0.2, 1.0)]
+              ("S=H+I, Eq. finaldyn_new a=0.2", 3, 0, 0.2, 1.0), ("S=G, two-S (Eq. smartMarkov)", 0, 3, 0.0, None)]
 TOY_DELTAS = [0.05, 0.1, 0.2, 0.4, 0.7, 1.0]
 
 

@@ -186,14 +186,17 @@ int vmc_langevin_step(vmc_ctx* ctx, int n3, double box_L, double* R_dev, double*
 /* The rotating-spring toy model (SI, "A simple toy model"; main text, figure of the toy
  * model): U = k (|x| - a)^2 / 2 in the plane; S = G_lambda (radial eigenvalue 1/lambda,
  * tangential 1; s_kind 0), S = H + mu G_lambda with H the Hessian of U (s_kind 1), S = I
- * (s_kind 2) or S = H + mu I (s_kind 3; the main text's shifted Hessian).  scheme 0: Eq. finaldyn_new (alpha = 0 is Eq. finaldyn); 1: Eq. norogna (no
- * S-difference term); 2: Eq. standard with gamma = 0 and the drift-diffusion term of
- * Eq. e:cumber, Gamma_j = sum_i d_i (S^-1)_ji, by central differences (h = 1e-6). */
+ * (s_kind 2) or S = H + mu I (s_kind 3; the main text's shifted Hessian).
+ * scheme 0: Eq. finaldyn_new (alpha = 0 is Eq. finaldyn); 1: Eq. norogna (no S-difference
+ * term); 2: Eq. standard with gamma = 0 and the drift-diffusion term of Eq. e:cumber,
+ * Gamma_j = sum_i d_i (S^-1)_ji, by central differences (h = 1e-6); 3: the SI's first
+ * simplified scheme (Eq. smartMarkov), a noise step to y and the drift with the half
+ * S-difference between y and R, S evaluated at both. */
 typedef struct {
   double lambda, k, a, mu; /* G_lambda parameter, spring constant, ring radius, regulariser of H */
   int s_kind;              /* 0 G_lambda, 1 H + mu G_lambda, 2 identity, 3 H + mu I */
   double T, Delta, alpha;  /* temperature, time step, alpha of Eq. finaldyn_new (scheme 0) */
-  int scheme;              /* 0 finaldyn_new, 1 norogna, 2 explicit Gamma */
+  int scheme;              /* 0 finaldyn_new, 1 norogna, 2 explicit Gamma, 3 smartMarkov (two S) */
 } vmc_toy_params;
 
 /* n_traj independent trajectories of n_steps steps, one GPU thread each.  R0_dev (n_traj x 2,

@@ -975,8 +975,11 @@ static void inv2(const double S[4], double Si[4]) {
 
 /* scheme 0: Eq. finaldyn_new (alpha; alpha = 0 is Eq. finaldyn); scheme 1: Eq.
  * norogna (no S-difference term); scheme 2: Eq. standard with gamma = 0 and the
- * term Gamma_j = sum_i d_i S^-1_ji by central differences.  Returns the mean of
- * U over the last 90% of n_steps; U_samples (optional) gets U after every step. */
+ * term Gamma_j = sum_i d_i S^-1_ji by central differences; scheme 3: the first
+ * simplified scheme of the SI (Eq. smartMarkov), y = R + sqrt(2 T D) z and
+ * R' = y + D S^-1(R) f(R) - 1/2 S^-1(R) [S(y) - S(R)] (y - R), S taken at R and y.
+ * Returns the mean of U over the last 90% of n_steps; U_samples (optional) gets U
+ * after every step. */
 int o_toy_run(double lambda, double k, double a, double mu, int s_kind, double T, double Delta,
               double alpha, int scheme, uint32_t seed, uint32_t traj, int n_steps, double* R, double* U_mean,
               double* U_samples) {
@@ -993,6 +996,23 @@ int o_toy_run(double lambda, double k, double a, double mu, int s_kind, double T
       rc = o_langevin(2, 0.0, R, Rp, Sp, f, S, T, Delta, scheme == 0 ? alpha : 0.0,
                       scheme == 1 ? O_STEP_NO_SCORR : 0u, seed, traj, (uint32_t)t);
       if (rc) return rc;
+    } else if (scheme == 3) {
+      double Lc[4], xi[2], z[2], Si[4], Sy[4], y[2], amp = sqrt(2.0 * T * Delta);
+      if (o_cholesky(2, S, Lc)) return O_ENOTSPD;
+      o_normals(seed, traj, (uint32_t)t, 2, xi);
+      z[1] = xi[1] / Lc[3];
+      z[0] = (xi[0] - Lc[2] * z[1]) / Lc[0];
+      for (int j = 0; j < 2; ++j) y[j] = R[j] + amp * z[j];
+      o_toy_S(lambda, k, a, mu, s_kind, y, Sy);
+      inv2(S, Si);
+      double dS[4], v[2];
+      for (int q = 0; q < 4; ++q) dS[q] = Sy[q] - S[q];
+      for (int j = 0; j < 2; ++j) v[j] = Delta * f[j] - 0.5 * (dS[2 * j] * (y[0] - R[0]) + dS[2 * j + 1] * (y[1] - R[1]));
+      for (int j = 0; j < 2; ++j) {
+        Rp[j] = R[j];
+        R[j] = y[j] + Si[2 * j] * v[0] + Si[2 * j + 1] * v[1];
+      }
+      memcpy(Sp, S, sizeof(S));
     } else {
       double Si[4], Gam[2] = {0, 0}, h = 1e-6;
       inv2(S, Si);

@@ -361,7 +361,20 @@ __global__ __launch_bounds__(256) void k_toy(ToyArgs p, const double* R0, double
     // L^T z = xi: <z z^T> = S^-1
     const double z1 = rad * sn / l11, z0 = (rad * cs - l10 * z1) / l00;
     double dx, dy;
-    if (p.scheme == 2) {
+    if (p.scheme == 3) {
+      // first simplified scheme: noise step to y, then the drift with S at R and the
+      // half S-difference between y and R
+      const double amp = sqrt(2.0 * p.T * p.Delta);
+      const double yx = x + amp * z0, yy = y + amp * z1;
+      double Sy[3], Si[3];
+      toy_metric(p, yx, yy, Sy);
+      toy_inv(S, Si);
+      const double ex = yx - x, ey = yy - y;
+      const double vx = p.Delta * fx - 0.5 * ((Sy[0] - S[0]) * ex + (Sy[1] - S[1]) * ey);
+      const double vy = p.Delta * fy - 0.5 * ((Sy[1] - S[1]) * ex + (Sy[2] - S[2]) * ey);
+      dx = amp * z0 + Si[0] * vx + Si[1] * vy;
+      dy = amp * z1 + Si[1] * vx + Si[2] * vy;
+    } else if (p.scheme == 2) {
       double Si[3];
       toy_inv(S, Si);
       // Gamma_j = sum_i d/dx_i (S^-1)_ji, central differences of step h

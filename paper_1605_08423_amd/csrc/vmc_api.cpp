@@ -619,7 +619,7 @@ int vmc_toy_run(vmc_ctx* ctx, const vmc_toy_params* p, int n_traj, int n_steps, 
                 double* R, double* U_mean, int* status) {
   if (!ctx || !p || n_traj < 1 || n_steps < 1 || !R0 || !R || !U_mean || !status) return VMC_EINVAL;
   if (!(p->lambda > 0.0) || !(p->k >= 0.0) || !(p->mu >= 0.0) || !(p->T >= 0.0) || !(p->Delta > 0.0) ||
-      !(p->alpha >= 0.0) || p->s_kind < 0 || p->s_kind > 3 || p->scheme < 0 || p->scheme > 2)
+      !(p->alpha >= 0.0) || p->s_kind < 0 || p->s_kind > 3 || p->scheme < 0 || p->scheme > 3)
     return VMC_EINVAL;
   HIPCHK(hipSetDevice(ctx->device));
   RUN(K_TOY, launch_toy(p->lambda, p->k, p->a, p->mu, p->s_kind, p->T, p->Delta, p->alpha, p->scheme, seed, n_traj,

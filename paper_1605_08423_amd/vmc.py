@@ -276,7 +276,7 @@ class vmc_toy_params(C.Structure):
 
 
 TOY_S_G, TOY_S_HESSIAN, TOY_S_IDENTITY, TOY_S_HESSIAN_SHIFT = 0, 1, 2, 3
-TOY_FINALDYN_NEW, TOY_NOROGNA, TOY_EXPLICIT_GAMMA = 0, 1, 2
+TOY_FINALDYN_NEW, TOY_NOROGNA, TOY_EXPLICIT_GAMMA, TOY_TWO_S = 0, 1, 2, 3
 
 
 def vmc_toy_run(ctx: Context, R0, n_steps, lam, k, a, mu, s_kind, T, Delta, alpha, scheme, seed=0):

@@ -51,6 +51,8 @@ CASES = [  # (s_kind, scheme, Delta, alpha)
     (1, 2, 0.05, 0.0),
     (3, 0, 0.2, 0.2),   # H + mu I (mu = 1), Eq. finaldyn_new
     (3, 2, 0.05, 0.0),  # H + mu I, explicit Gamma
+    (0, 3, 0.2, 0.0),   # G_lambda, the two-S scheme (Eq. smartMarkov)
+    (3, 3, 0.05, 0.0),  # H + mu I, the two-S scheme
 ]
 
 
@@ -108,7 +110,7 @@ def test_toy_figure_claims_from_gpu_ensembles(dev):
 def test_toy_rejects_bad_parameters(dev):
     torch, vmc, ctx = dev
     R0 = torch.zeros((4, 2), dtype=torch.float64, device="cuda") + 1.4
-    for kw in ({"D": 0.0}, {"s_kind": 4}, {"scheme": 5}, {"lam": -1.0}):
+    for kw in ({"D": 0.0}, {"s_kind": 4}, {"scheme": 4}, {"lam": -1.0}):
         args = dict(s_kind=0, scheme=0, D=0.1, lam=0.1)
         args.update(kw)
         with pytest.raises(vmc.VMCError):

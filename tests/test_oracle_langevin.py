@@ -298,3 +298,16 @@ def test_toy_model_shifted_hessian_equilibrium(oracle):
     u = np.mean([oracle.toy_run(tm["lambda_used"], tm["k"], tm["a"], 1.0, 3, T, 0.05, tm["alpha"], 0, 20 + s, 60000)
                  for s in range(4)])
     assert abs(u / (T / 2) - 1.0) < 0.04, u
+
+
+def test_toy_model_two_S_scheme_samples_canonical(oracle):
+    """The SI's first simplified scheme (Eq. smartMarkov: a noise step to y, then the drift with
+    the half S-difference between y and R) implies the right Fokker-Planck equation without the
+    Gamma term: with S = G_lambda it samples <U> = T/2 at D = 0.2, where Eq. norogna (no
+    S-difference at all) is 20-40% off."""
+    tm = PAPER["toy_model"]
+    T = tm["T"]
+    u = np.mean([_toy(oracle, 3, 0.2, seed=40 + s) for s in range(6)])
+    assert abs(u / (T / 2) - 1.0) < 0.04, u
+    un = np.mean([_toy(oracle, 1, 0.2, seed=40 + s) for s in range(2)])
+    assert un / (T / 2) - 1.0 > 0.15
