@@ -142,6 +142,11 @@ int vmc_traj_walker_means(vmc_traj* traj, double* means_dev);
 int vmc_traj_walker_forces(vmc_traj* traj, double* f_w_dev);
 /* Accepted moves per walker in the last call (int64, W). */
 int vmc_traj_accepts(vmc_traj* traj, int64_t* n_acc_dev);
+/* Walker quarantine: at the start of every vmc_energy_forces call a walker with a non-finite
+ * coordinate is replaced by a copy of the next walker (cyclically) whose coordinates are all
+ * finite; if no walker is finite the call returns VMC_EINVAL and changes nothing.  *n_reset:
+ * the number of walkers so replaced at the start of the last call. */
+int vmc_traj_walkers_reset(vmc_traj* traj, int* n_reset);
 
 /* Checkpoint / resume of the state a trajectory owns between calls: its system and walker
  * count (checked on load), the RNG key (seed, traj_id), the walker positions, and the per-walker

@@ -1186,6 +1186,40 @@ __global__ __launch_bounds__(512, 1) void k_refine_big(WalkerArgs a, int sp, dou
   }
 }
 
+// ------------------------------------------------------ walker quarantine ---
+// A walker with a non-finite coordinate (flag 1) takes a copy of the next walker, cyclically,
+// whose coordinates are all finite; count[0] counts the copies, count[1] the bad walkers left
+// without a source (every walker bad).  Finite walkers are not written.
+__global__ __launch_bounds__(256) void k_walker_flags(int n3, const double* pos, int* flags) {
+  const int w = blockIdx.x;
+  int bad = 0;
+  for (int u = threadIdx.x; u < n3; u += 256) bad |= !isfinite(pos[(size_t)w * n3 + u]);
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) flags[w] = bad;
+}
+__global__ __launch_bounds__(256) void k_walker_repair(int W, int n3, double* pos, const int* flags, int* count) {
+  const int w = blockIdx.x;
+  if (!flags[w]) return;
+  int src = -1;
+  for (int d = 1; d < W && src < 0; ++d) {
+    const int c = (w + d) % W;
+    if (!flags[c]) src = c;
+  }
+  if (src < 0) {
+    if (threadIdx.x == 0) atomicAdd(count + 1, 1);
+    return;
+  }
+  for (int u = threadIdx.x; u < n3; u += 256) pos[(size_t)w * n3 + u] = pos[(size_t)src * n3 + u];
+  if (threadIdx.x == 0) atomicAdd(count, 1);
+}
+hipError_t launch_walker_quarantine(int W, int N, double* pos, int* flags, int* count, hipStream_t st) {
+  hipLaunchKernelGGL(k_walker_flags, dim3(W), dim3(256), 0, st, 3 * N, pos, flags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_walker_repair, dim3(W), dim3(256), 0, st, W, 3 * N, pos, flags, count);
+  return hipGetLastError();
+}
+
 // ----------------------------------------------------------- launchers ---
 template <int NS, class Real, bool TW>
 hipError_t launch_build_A_tw(const WalkerArgs& a, hipStream_t st) {

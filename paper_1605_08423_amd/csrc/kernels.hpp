@@ -97,6 +97,9 @@ __device__ __forceinline__ int batch_job(const Batch& b, int blk) {
 }
 
 hipError_t launch_build_A(const WalkerArgs& a, int mixed, hipStream_t st);
+// Walkers with non-finite coordinates take a copy of the next finite walker (flags: W ints;
+// count: 2 ints, copies made and bad walkers without a source, both added to).
+hipError_t launch_walker_quarantine(int W, int N, double* pos, int* flags, int* count, hipStream_t st);
 hipError_t launch_invert(const WalkerArgs& a, int spin_lo, int spin_hi, int only_flagged, hipStream_t st,
                          const Batch* bt = nullptr, int nblk = 0);
 hipError_t launch_refine(const WalkerArgs& a, int spin, double tol, hipStream_t st, const Batch* bt = nullptr,

@@ -54,6 +54,8 @@ struct vmc_traj {
   double *means = nullptr, *f_w = nullptr, *partial = nullptr, *outv = nullptr;
   int64_t* nacc = nullptr;
   int* rflag = nullptr;
+  int* qflag = nullptr;           // W + 2: per-walker non-finite flags, then the quarantine counts
+  int n_reset = 0;                // walkers re-initialised at the start of the last vmc_energy_forces
   unsigned char* scr = nullptr;   // per-walker scratch of the measurement kernel (N_sigma > 64)
   // Ewald tables
   int nk = 0, nslot = 0;
@@ -283,7 +285,7 @@ void free_traj(vmc_traj* t) {
   if (!t) return;
   void* ptrs[] = {t->pos, t->Amat, t->Binv, t->ldet, t->sgn, t->acc, t->rho_acc, t->Vs, t->dVs, t->Uj,
                   t->means, t->f_w, t->partial, t->outv, t->nacc, t->kvec, t->rho_p, t->Ptab, t->Fconst,
-                  t->Vpp, t->slot, t->slot_nx0, t->rflag, t->scr};
+                  t->Vpp, t->slot, t->slot_nx0, t->rflag, t->qflag, t->scr};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete t;
@@ -390,7 +392,8 @@ int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int W, uint32_t seed, u
             !dalloc(&t->dVs, (size_t)W * n3) && !dalloc(&t->Uj, (size_t)W) &&
             !dalloc(&t->means, (size_t)W * (1 + 3 * n3)) && !dalloc(&t->f_w, (size_t)W * n3) &&
             !dalloc(&t->partial, reduce_partial_doubles(W, (int)n3)) && !dalloc(&t->outv, 3 + n3) &&
-            !dalloc(&t->nacc, (size_t)W) && !dalloc(&t->rflag, (size_t)W * 2) && !dalloc(&t->kvec, kv.size()) && !dalloc(&t->rho_p, 2 * t->nk) &&
+            !dalloc(&t->nacc, (size_t)W) && !dalloc(&t->rflag, (size_t)W * 2) && !dalloc(&t->qflag, (size_t)W + 2) &&
+            !dalloc(&t->kvec, kv.size()) && !dalloc(&t->rho_p, 2 * t->nk) &&
             !dalloc(&t->Ptab, (size_t)t->nk * N * 2) && !dalloc(&t->Fconst, n3) && !dalloc(&t->Vpp, 1) &&
             !dalloc(&t->slot, slots.size()) && !dalloc(&t->slot_nx0, nx0.size());
   const size_t scr = slater_scratch_bytes(t->NS, sys->precision == VMC_MIXED);
@@ -487,6 +490,12 @@ int vmc_traj_load(vmc_traj* t, const void* buf, size_t len) {
   return VMC_OK;
 }
 
+int vmc_traj_walkers_reset(vmc_traj* t, int* n_reset) {
+  if (!t || !n_reset) return VMC_EINVAL;
+  *n_reset = t->n_reset;
+  return VMC_OK;
+}
+
 int vmc_traj_get_walkers(vmc_traj* t, double* pos_dev) {
   if (!t || !pos_dev) return VMC_EINVAL;
   HIPCHK(hipMemcpyAsync(pos_dev, t->pos, (size_t)t->W * t->N * 3 * sizeof(double), hipMemcpyDeviceToDevice,
@@ -502,6 +511,15 @@ int vmc_energy_forces(vmc_traj* t, const double* R, const double* C, const doubl
   hipStream_t st = ctx->stream;
   const int mixed = t->sys.precision == VMC_MIXED;
   const size_t N = t->N, n3 = 3 * N, W = t->W;
+  // quarantine: a walker whose coordinates are not all finite restarts from a copy of the
+  // next finite walker; every walker bad is an argument error (nothing is changed)
+  HIPCHK(hipMemsetAsync(t->qflag + W, 0, 2 * sizeof(int), st));
+  RUN(K_SETUP, launch_walker_quarantine((int)W, (int)N, t->pos, t->qflag, t->qflag + W, st));
+  int qc[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(qc, t->qflag + W, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (qc[1] > 0) return VMC_EINVAL;
+  t->n_reset = qc[0];
   int rc = proton_setup(t, R);
   if (rc) return rc;
   int nimg = 1;
@@ -860,7 +878,7 @@ size_t request_bytes(const vmc_system& s, int W) {
              Wz * (1 + 3 * n3) + Wz * n3 + reduce_partial_doubles(W, (int)n3) + 3 + n3 + kv.size() + 2 * nk +
              nk * N * 2 + n3 + 1;
   d += 2 * n3 + 2 * n3 * n3 + N * NS + N;                     // R, R_prev, S, S_prev, C, zeta
-  size_t b = d * sizeof(double) + Wz * sizeof(int64_t) + Wz * 2 * sizeof(int) +
+  size_t b = d * sizeof(double) + Wz * sizeof(int64_t) + Wz * 2 * sizeof(int) + (Wz + 2) * sizeof(int) +
              (slots.size() + nx0.size() + 1) * sizeof(int) +
              Wz * slater_scratch_bytes((int)NS, s.precision == VMC_MIXED);
   return b;

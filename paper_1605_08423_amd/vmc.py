@@ -24,7 +24,7 @@ EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_
             "vmc_request_bytes", "vmc_server_admit_count", "vmc_server_create", "vmc_server_destroy",
             "vmc_server_submit", "vmc_server_cancel", "vmc_server_tick", "vmc_server_status",
             "vmc_server_result", "vmc_server_info", "vmc_toy_run", "vmc_huckel_params_twist",
-            "vmc_twist_average", "vmc_traj_save", "vmc_traj_load"]
+            "vmc_twist_average", "vmc_traj_save", "vmc_traj_load", "vmc_traj_walkers_reset"]
 VMC_REQ_QUEUED, VMC_REQ_RUNNING, VMC_REQ_DONE, VMC_REQ_FAILED, VMC_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
@@ -91,6 +91,7 @@ def _declare(l):
     l.vmc_huckel_params_twist.argtypes = [i, d, i, P(d), P(d), P(d)]
     l.vmc_twist_average.argtypes = [vp, i, i, vp, vp, vp, vp]
     l.vmc_traj_save.argtypes = [vp, vp, P(C.c_size_t)]
+    l.vmc_traj_walkers_reset.argtypes = [vp, P(i)]
     l.vmc_traj_load.argtypes = [vp, vp, C.c_size_t]
     sz = C.c_size_t
     l.vmc_request_bytes.restype = sz
@@ -205,6 +206,12 @@ class Trajectory:
 
     def build_S(self, S=None):
         return vmc_build_S(self, S)
+
+    def walkers_reset(self) -> int:
+        """Walkers re-initialised (non-finite coordinates) at the start of the last call."""
+        n = C.c_int(0)
+        _check(_lib().vmc_traj_walkers_reset(self.h, C.byref(n)), "vmc_traj_walkers_reset")
+        return n.value
 
     def save(self) -> bytes:
         """Checkpoint of the trajectory's own state (see vmc_traj_save)."""

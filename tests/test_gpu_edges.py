@@ -153,3 +153,39 @@ def test_runs_are_deterministic(dev, precision):
         tr.close()
     for a, b in zip(res[0], res[1]):
         assert np.array_equal(a, b)
+
+
+def test_walker_quarantine(dev):
+    """A walker with a non-finite coordinate restarts from a copy of the next finite walker at
+    the start of vmc_energy_forces and is counted; the call then equals one started from those
+    copies.  With every walker non-finite the call is refused and changes nothing."""
+    import torch
+    from paper_1605_08423_amd import vmc
+    from paper_1605_08423_amd.inputs import workload
+    _, _, ctx = dev
+    wl = workload("h16")
+    Cm = vmc.vmc_huckel_params(wl.R, wl.zeta, wl.L)
+    T_ = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    x = wl.electrons(W=16, seed_offset=2)
+    bad = x.copy()
+    bad[5, 3, 1] = np.nan
+    bad[9, 0, 2] = np.inf
+    fixed = x.copy()
+    fixed[5], fixed[9] = x[6], x[10]
+    outs = []
+    for start, expect in ((bad, 2), (fixed, 0)):
+        tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L), 16, seed=3, traj_id=0)
+        tr.set_walkers(T_(start))
+        out = tr.energy_forces(T_(wl.R.reshape(-1)), T_(Cm), T_(wl.zeta), 1, 2, wl.delta, 0).cpu().numpy()
+        assert tr.walkers_reset() == expect
+        assert np.all(np.isfinite(out))
+        outs.append(out)
+        tr.close()
+    assert np.array_equal(outs[0], outs[1])
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L), 4, seed=3, traj_id=0)
+    allbad = np.full((4, wl.n, 3), np.nan)
+    tr.set_walkers(T_(allbad))
+    with pytest.raises(vmc.VMCError):
+        tr.energy_forces(T_(wl.R.reshape(-1)), T_(Cm), T_(wl.zeta), 1, 1, wl.delta, 0)
+    assert np.all(np.isnan(tr.get_walkers().cpu().numpy()))
+    tr.close()
