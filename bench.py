@@ -386,6 +386,8 @@ def main():
     ap.add_argument("--sweeps", type=int, default=100)
     ap.add_argument("--rs", type=float, default=None, help="default: the workload's r_s")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--log", default=None, metavar="PATH",
+                    help="write one JSON line per timed Langevin step: E, sigma_E, |f|, acceptance, cond(S), time")
     ap.add_argument("--j1", type=float, default=0.0, metavar="B1",
                     help="add the one-body electron-proton Jastrow term with this b_1 (0: none)")
     ap.add_argument("--cpu-walkers", type=int, default=None, help="default: 192 (h128), 16 (h256)")
@@ -463,6 +465,7 @@ def main():
     Delta = 1.0 / alpha               # alpha Delta = 1
     kb = []
     state = {"first": True}
+    log = open(args.log, "w") if args.log else None
 
     def one_step(k: int, n_equil: int):
         Rh = R.cpu().numpy()
@@ -473,6 +476,10 @@ def main():
             S_prev.copy_(S)
             R_prev.copy_(R)
             state["first"] = False
+        if log is not None:
+            # copy S before the step (the step keeps it as S_prev): its condition number is the
+            # preconditioner's stiffness ratio
+            state["S_host"] = S.cpu().numpy()
         rc = vmc.vmc_langevin_step(ctx, R, R_prev, S_prev, out[3:], S, T_ha, Delta, alpha, 0, wl.seed, 0, k, wl.L)
         if rc != 0:
             raise RuntimeError(f"langevin step failed: {vmc._lib().vmc_strerror(rc).decode()}")
@@ -491,6 +498,12 @@ def main():
         out = one_step(k, 20 if k == 0 else 5)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
+        if log is not None:
+            oh = out.cpu().numpy()
+            log.write(json.dumps({"step": k, "E_Ha": float(oh[0]), "sigma_E_Ha": float(oh[1]), "acceptance": float(oh[2]),
+                                  "force_norm": float(np.linalg.norm(oh[3:])),
+                                  "cond_S": float(np.linalg.cond(state["S_host"])), "ms": round(1e3 * lat[-1], 2)}) + "\n")
+            log.flush()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     times = ctx.kernel_times()
