@@ -1008,6 +1008,10 @@ int setup_step(vmc_server* s, Served* q) {
   HIPCHK(hipMemsetAsync(t->nacc, 0, W * sizeof(int64_t), st));
   HIPCHK(hipMemsetAsync(t->rflag, 0, W * 2 * sizeof(int), st));
   HIPCHK(hipMemsetAsync(q->status, 0, 2 * sizeof(int), st));
+  // walker quarantine as in vmc_energy_forces (asynchronous here: with no finite walker left
+  // the trajectory's S is not finite and the step fails, for this request only)
+  HIPCHK(hipMemsetAsync(t->qflag + W, 0, 2 * sizeof(int), st));
+  RUN(K_SETUP, launch_walker_quarantine((int)W, N, t->pos, t->qflag, t->qflag + W, st));
   WalkerArgs a = walker_args(t, q->R, q->C, q->zeta_d, q->nimg);
   a.status = q->status;
   RUN(K_BUILD_A, launch_build_A(a, r.sys.precision == VMC_MIXED, st));

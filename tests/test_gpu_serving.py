@@ -183,3 +183,28 @@ def test_refusals_cancel_and_failure_isolation(dev):
     # the surviving request equals its run alone
     (sa, ra), = serve(vmc, ctx, [s_ok])[0]
     assert np.array_equal(ra["R"], survivor["R"]) and np.array_equal(ra["E"], survivor["E"])
+
+
+def test_served_walker_quarantine(dev):
+    """A served trajectory that starts with a NaN walker runs to the end, and equals the same
+    request started with that walker replaced by its finite neighbour (the quarantine copy)."""
+    torch, vmc, ctx = dev
+    s = spec("h16", 64, 0, traj=23)
+    wl = s["wl"]
+    x = wl.electrons(W=s["W"], seed_offset=s["traj"])
+    bad, fixed = x.copy(), x.copy()
+    bad[7, 2, 0] = np.nan
+    fixed[7] = x[8]
+    res = []
+    for pos0 in (bad, fixed):
+        req = vmc.make_request(vmc.make_system(wl.n, wl.L), s["W"], wl.R, wl.zeta, pos0, n_steps=s["steps"],
+                               n_sweeps=s["M"], T=s["T"], Delta=1.0 / s["alpha"], alpha=s["alpha"],
+                               n_equil_first=s["ne1"], n_equil=s["ne"], step_delta=wl.delta, seed=s["seed"],
+                               traj_id=s["traj"])
+        srv = vmc.Server(ctx, 8 << 30)
+        rid = srv.submit(req)
+        srv.run_until_idle()
+        res.append((srv.status(rid), srv.result(rid)))
+        srv.close()
+    assert res[0][0][0] == res[1][0][0] == vmc.VMC_REQ_DONE
+    assert np.array_equal(res[0][1]["R"], res[1][1]["R"]) and np.array_equal(res[0][1]["E"], res[1][1]["E"])
