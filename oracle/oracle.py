@@ -68,6 +68,7 @@ def _setup(l):
     l.o_huckel.argtypes = [i, d, P(d), P(d), i, P(d), P(d)]
     l.o_huckel_twist.argtypes = [i, d, P(d), P(d), i, i, P(d), P(d)]
     l.o_vmc_run.argtypes = [P(OSys), i, P(d), i, i, d, u32, u32, u32, P(d), P(C.c_int64), i]
+    l.o_vmc_run_from.argtypes = [P(OSys), i, u32, P(d), i, i, d, u32, u32, u32, P(d), P(C.c_int64), i]
     l.o_reduce.argtypes = [i, i, i, P(d), P(d), P(d), P(d), P(d), P(d)]
     l.o_build_S.argtypes = [i, i, P(d), P(d), P(d)]
     l.o_build_S.restype = None
@@ -140,15 +141,16 @@ class System:
             raise RuntimeError(f"o_local failed rc={rc}")
         return dict(lnpsi=lnpsi[0], sign=sign[0], EL=EL[0], dlnpsi=dl, dEL=de)
 
-    def vmc_run(self, x, n_equil, n_meas, delta, seed, traj=0, step=0, threads=0):
-        """Runs the Metropolis chains in place on x (W, Ne, 3); returns (sums, n_acc)."""
+    def vmc_run(self, x, n_equil, n_meas, delta, seed, traj=0, step=0, threads=0, walker0=0):
+        """Runs the Metropolis chains in place on x (W, Ne, 3); returns (sums, n_acc).
+        x holds walkers walker0 .. walker0+W-1 of a larger set (their random streams)."""
         assert x.dtype == np.float64 and x.flags.c_contiguous
         W = x.shape[0]
         n3 = 3 * self.n_p
         sums = np.zeros((W, 2 + 3 * n3))
         nacc = np.zeros(W, dtype=np.int64)
-        rc = lib().o_vmc_run(C.byref(self.s), W, _dp(x), n_equil, n_meas, delta, seed, traj, step,
-                             _dp(sums), nacc.ctypes.data_as(C.POINTER(C.c_int64)), threads)
+        rc = lib().o_vmc_run_from(C.byref(self.s), W, walker0, _dp(x), n_equil, n_meas, delta, seed, traj, step,
+                                  _dp(sums), nacc.ctypes.data_as(C.POINTER(C.c_int64)), threads)
         if rc:
             raise RuntimeError(f"o_vmc_run failed rc={rc}")
         return sums, nacc

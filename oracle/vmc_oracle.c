@@ -672,9 +672,16 @@ static void mo_row(const osys* s, const double r[3], double* m) {
  * the sum of the pair changes (and of the moved electron's one-body terms).  Random numbers: Philox key (seed, traj),
  * counter (step, walker, sweep*Ne + e, 0|1).  After each measured sweep the
  * local quantities of o_local are added to sums[w] = [sum E_L, sum E_L^2,
- * sum dE_L/dR (3N), sum dln|psi|/dR (3N), sum E_L dln|psi|/dR (3N)]. */
+ * sum dE_L/dR (3N), sum dln|psi|/dR (3N), sum E_L dln|psi|/dR (3N)].
+ * o_vmc_run_from runs walkers w0 .. w0+W-1 of a larger set: x, sums and n_acc hold
+ * only those W walkers, and walker w draws from the counter of walker w0 + w. */
 int o_vmc_run(const osys* s, int W, double* x, int n_equil, int n_meas, double delta,
               uint32_t seed, uint32_t traj, uint32_t step, double* sums, int64_t* n_acc, int n_threads) {
+  return o_vmc_run_from(s, W, 0u, x, n_equil, n_meas, delta, seed, traj, step, sums, n_acc, n_threads);
+}
+
+int o_vmc_run_from(const osys* s, int W, uint32_t w0, double* x, int n_equil, int n_meas, double delta,
+                   uint32_t seed, uint32_t traj, uint32_t step, double* sums, int64_t* n_acc, int n_threads) {
   int ne = s->n_up + s->n_dn, n3 = 3 * s->n_p, nsum = 2 + 3 * n3;
   int periodic = (s->basis_kind == OB_PERIODIC_GAUSS);
   int err = 0;
@@ -707,8 +714,8 @@ int o_vmc_run(const osys* s, int W, double* x, int n_equil, int n_meas, double d
     uint32_t key[2] = {seed, traj};
     for (int sw_i = 0; sw_i < n_equil + n_meas; ++sw_i) {
       for (int e = 0; e < ne; ++e) {
-        uint32_t c0[4] = {step, (uint32_t)w, (uint32_t)(sw_i * ne + e), 0u}, o0[4], o1[4];
-        uint32_t c1[4] = {step, (uint32_t)w, (uint32_t)(sw_i * ne + e), 1u};
+        uint32_t c0[4] = {step, w0 + (uint32_t)w, (uint32_t)(sw_i * ne + e), 0u}, o0[4], o1[4];
+        uint32_t c1[4] = {step, w0 + (uint32_t)w, (uint32_t)(sw_i * ne + e), 1u};
         o_philox(c0, key, o0);
         o_philox(c1, key, o1);
         double u[3] = {o_u01(o0[0], o0[1]), o_u01(o0[2], o0[3]), o_u01(o1[0], o1[1])};

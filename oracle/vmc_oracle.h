@@ -55,6 +55,9 @@ int o_huckel_twist(int n_p, double L, const double* R, const double* zeta, int n
 int o_vmc_run(const osys* s, int W, double* x, int n_equil, int n_meas, double delta,
               uint32_t seed, uint32_t traj, uint32_t step, double* sums, int64_t* n_acc,
               int n_threads);
+int o_vmc_run_from(const osys* s, int W, uint32_t w0, double* x, int n_equil, int n_meas,
+                   double delta, uint32_t seed, uint32_t traj, uint32_t step, double* sums,
+                   int64_t* n_acc, int n_threads);
 int o_reduce(int W, int n3, int M, const double* sums, double* E, double* sigma_E,
              double* f, double* f_w, double* means);
 void o_build_S(int W, int n3, const double* f_w, const double* f, double* S);

@@ -33,6 +33,7 @@ int main(void) {
   double sums[W * (2 + 9 * NP)];
   int64_t nacc[W];
   if (o_vmc_run(&s, W, x, 1, 2, 1.0, 7u, 1u, 0u, sums, nacc, 1)) return 3;
+  if (o_vmc_run_from(&s, 1, 2u, x, 1, 1, 1.0, 7u, 1u, 0u, sums, nacc, 1)) return 3;
   double E, sig, f[3 * NP], fw[W * 3 * NP], means[W * (1 + 9 * NP)], S[9 * NP * NP];
   if (o_reduce(W, 3 * NP, 2, sums, &E, &sig, f, fw, means)) return 4;
   o_build_S(W, 3 * NP, fw, f, S);

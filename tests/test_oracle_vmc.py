@@ -73,6 +73,24 @@ def test_chain_is_deterministic(oracle):
     assert 0.2 < acc < 0.9
 
 
+def test_walker_slice_runs_the_walkers_own_streams(oracle):
+    """Walkers w0 .. w0+k-1 run alone with walker0 = w0 give exactly rows w0 .. w0+k-1 of the run
+    over the whole set (each walker's chain depends only on its own start and counter), and a
+    slice run at the wrong offset gives other chains."""
+    wl = workload("h16")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, 8)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L)
+    x = wl.electrons(W=7)
+    full = x.copy()
+    a, na = s.vmc_run(full, 1, 2, wl.delta, seed=5, traj=2, step=3)
+    part = np.ascontiguousarray(x[4:7])
+    b, nb = s.vmc_run(part, 1, 2, wl.delta, seed=5, traj=2, step=3, walker0=4)
+    assert np.array_equal(b, a[4:7]) and np.array_equal(nb, na[4:7]) and np.array_equal(part, full[4:7])
+    wrong = np.ascontiguousarray(x[4:7])
+    c, _ = s.vmc_run(wrong, 1, 2, wl.delta, seed=5, traj=2, step=3, walker0=3)
+    assert not np.array_equal(c, a[4:7])
+
+
 def test_sweep_decisions_follow_psi_ratios_with_one_body_term(oracle):
     """Each Metropolis decision of a sweep equals u < |psi(x')/psi(x)|^2 with ln|psi| taken
     from the local-energy routine (one-body term included) on the move drawn from the same
