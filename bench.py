@@ -80,15 +80,26 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def traffic_workload_key(workload: str, precision: str, walkers: int, j1: float = 0.0, rs=None) -> str:
+    """Names the run a traffic measurement belongs to, as profiles/traffic.json records it."""
+    key = f"{workload} {precision}, W={walkers}"
+    if j1 > 0:
+        key += f", b1={j1}"
+    if rs is not None:
+        key += f", r_s={rs}"
+    return key
+
+
+def measured_traffic(kernel: str, workload_key: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy), if taken on these sources."""
+    (FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy), if taken on these sources and on
+    this workload (size, precision and wavefunction change every kernel's traffic)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     k = d.get("kernels", {}).get(kernel)
-    if not k or d.get("source_hash") != kernel_source_hash():
+    if not k or d.get("source_hash") != kernel_source_hash() or d.get("workload") != workload_key:
         return None
     return k["bytes_per_launch"]
 
@@ -516,6 +527,8 @@ def main():
             if 0 < nx * nx + ny * ny + nz * nz <= nm * nm and (nx > 0 or (nx == 0 and (ny > 0 or (ny == 0 and nz > 0))))]
     nk, nslot = len(kset), len({(ny, nz) for _, ny, nz in kset})
     nimg = int(not (prec == vmc.VMC_MIXED and float(np.min(wl.zeta)) * (wl.L / 2) ** 2 >= 23.0))
+    tkey = traffic_workload_key(args.workload, args.precision, W, args.j1, args.rs)
+
     def kernel_roofline(name):
         ms, n = times[name]
         parts = work_model(name, N, nk, nslot, nimg, prec == vmc.VMC_MIXED, args.j1 > 0)
@@ -523,7 +536,7 @@ def main():
         flops, achieved, peak = roofline_numbers(parts, W, avg_s)
         return {"bound": "alu", "kernel": name, "achieved": round(achieved, 3), "peak": round(peak, 2),
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4) if peak else None,
-                "traffic": measured_traffic(name), "avg_launch_ms": round(avg_s * 1e3, 4),
+                "traffic": measured_traffic(name, tkey), "avg_launch_ms": round(avg_s * 1e3, 4),
                 "algorithmic_flop_per_launch": flops,
                 "flop_per_walker_by_unit": {u: round(f) for u, f in parts.items()}}
 

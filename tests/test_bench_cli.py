@@ -27,3 +27,20 @@ def test_work_model_and_effective_peak():
     assert bench.PEAK["valu"] < pk < bench.PEAK["mfma_f32"]
     # the sweep's matrix-core work: M' = Phi' C, P = M' A^-1 and the rank-16 updates, 4 N NS^2
     assert bench.work_model("sweep_half", 128, 1527, 253, 0, True)["mfma_f64"] == 4 * 128 * 64 * 64
+
+
+def test_traffic_is_reported_only_for_the_profiled_workload():
+    """The committed counter summary applies to one workload: another size, precision, r_s or the
+    one-body term changes every kernel's traffic, so the lookup returns None for them."""
+    import json
+    sys.path.insert(0, ROOT)
+    import bench
+    d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    key = bench.traffic_workload_key("h128", "mixed", 16384)
+    assert d["workload"] == key
+    expect = d["kernels"]["sweep_half"]["bytes_per_launch"] if d["source_hash"] == bench.kernel_source_hash() else None
+    assert bench.measured_traffic("sweep_half", key) == expect
+    for other in (bench.traffic_workload_key("h128", "fp64", 16384), bench.traffic_workload_key("h256", "mixed", 32768),
+                  bench.traffic_workload_key("h128", "mixed", 8192), bench.traffic_workload_key("h128", "mixed", 16384, 2.5),
+                  bench.traffic_workload_key("h128", "mixed", 16384, 0.0, 1.28)):
+        assert bench.measured_traffic("sweep_half", other) is None
