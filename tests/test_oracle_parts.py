@@ -416,3 +416,62 @@ def test_huckel_orbitals(oracle, twist):
     P_or = (Cm * dS[:, None]) @ (Cm * dS[:, None]).T
     P_np = V[:, :5] @ V[:, :5].T
     np.testing.assert_allclose(P_or, P_np, atol=1e-9)                      # same occupied space
+
+
+# ------------------------------------------------------ symmetries of psi ------
+def _same(r, r0, perm=None):
+    """ln|psi|, E_L and the proton derivatives agree to rounding (perm: the proton relabelling)."""
+    d0, e0 = r0["dlnpsi"].reshape(-1, 3), r0["dEL"].reshape(-1, 3)
+    if perm is not None:
+        d0, e0 = d0[perm], e0[perm]
+    assert r["lnpsi"] == pytest.approx(r0["lnpsi"], rel=1e-10, abs=1e-10)
+    assert r["EL"] == pytest.approx(r0["EL"], rel=1e-10, abs=1e-10)
+    np.testing.assert_allclose(r["dlnpsi"].reshape(-1, 3), d0, rtol=1e-8, atol=1e-9 * np.abs(d0).max())
+    np.testing.assert_allclose(r["dEL"].reshape(-1, 3), e0, rtol=1e-8, atol=1e-9 * np.abs(e0).max())
+
+
+@pytest.mark.parametrize("b1,twist", [(0.0, 0), (1.7, 0), (0.0, 5), (1.7, 3)])
+def test_translation_invariance_with_rewrapping(oracle, b1, twist):
+    """Moving every proton and electron by one vector and wrapping them all back into the box
+    changes no physical quantity: ln|psi|, E_L, dln|psi|/dR and dE_L/dR stay (the Hueckel orbitals
+    recomputed for the moved protons).  Under a twist, a particle wrapped across a twisted face
+    flips the signs of its basis values; the orbitals absorb the protons' flips and an electron's
+    flip changes only sign(psi)."""
+    wl = workload("h16")
+    rng = np.random.default_rng(11)
+    x = wl.electrons(W=1)[0]
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, 8, twist=twist)
+    r0 = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1, twist=twist).local(x)
+    for _ in range(3):
+        c = rng.uniform(-wl.L, wl.L, size=3)
+        R2, x2 = np.mod(wl.R + c, wl.L), np.mod(x + c, wl.L)
+        C2, _ = oracle.huckel(R2, wl.zeta, wl.L, 8, twist=twist)
+        _same(oracle.System(R2, wl.zeta, C2, L=wl.L, b1=b1, twist=twist).local(x2), r0)
+
+
+@pytest.mark.parametrize("b1,twist", [(0.0, 0), (1.7, 6)])
+def test_exchange_and_relabelling_symmetries(oracle, b1, twist):
+    """Exchanging two electrons of one spin flips sign(psi) and changes nothing else; exchanging
+    the whole up and down sets (equal counts, one set of orbitals for both spins) changes nothing;
+    relabelling the protons together with their exponents and orbital rows permutes dln|psi|/dR
+    and dE_L/dR in the same way and leaves ln|psi|, sign(psi) and E_L unchanged."""
+    wl = workload("h16")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, 8, twist=twist)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1, twist=twist)
+    x = wl.electrons(W=1, seed_offset=3)[0]
+    r0 = s.local(x)
+    for i, j in [(0, 5), (9, 14)]:
+        x2 = x.copy()
+        x2[[i, j]] = x2[[j, i]]
+        r = s.local(x2)
+        assert r["sign"] == -r0["sign"]
+        _same(r, r0)
+    r = s.local(np.ascontiguousarray(np.concatenate([x[8:], x[:8]])))
+    assert r["sign"] == r0["sign"]
+    _same(r, r0)
+    perm = np.random.default_rng(5).permutation(16)
+    s2 = oracle.System(np.ascontiguousarray(wl.R[perm]), np.ascontiguousarray(wl.zeta[perm]),
+                       np.ascontiguousarray(Cm[perm]), L=wl.L, b1=b1, twist=twist)
+    r = s2.local(x)
+    assert r["sign"] == r0["sign"]
+    _same(r, r0, perm)
