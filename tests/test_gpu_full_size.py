@@ -126,3 +126,69 @@ def test_full_size_step(oracle, dev, name, W, precision, ne, ns, sampled):
         say(f"  Langevin step 3N={n3}: R against the oracle {dR:.2e}")
         assert dR < 1e-12
         assert np.array_equal(Rpg.cpu().numpy(), Rpo) and np.array_equal(Spg.cpu().numpy(), Spo)
+
+
+@pytest.mark.parametrize("precision,twist", [(0, 0), (1, 0), (0, 5)])
+def test_full_size_symmetries(oracle, dev, precision, twist):
+    """Symmetries of psi on the GPU over 16,384 N = 128 configurations in one launch: a
+    translation of every particle with re-wrapping into the box (orbital rows carried along), an exchange
+    of two same-spin electrons in every configuration, and a relabelling of the protons (with their
+    exponents and orbital rows) leave ln|psi| and E_L unchanged and permute the proton derivatives.
+    Per configuration: the 99th percentile within 1e-10 in FP64 (median below 1e-12) and within the
+    mixed-precision bars in mixed.  The maximum is held to 1e-7 (FP64) and 5e-3 (mixed): on the few
+    unequilibrated configurations with ill-conditioned Slater matrices, FP64 rounding fixes E_L only
+    to about 1e-9 (the oracle's own translation discrepancy there is the same size), and the
+    proton derivatives to about 1e-8."""
+    torch, vmc, ctx = dev
+    wl = workload("h128")
+    K, N = 16384, wl.n
+    say(f"[full size symmetries] h128 K={K} precision={precision} twist={twist}")
+    sysd = vmc.make_system(N, wl.L, precision=precision, twist=twist)
+    pos = wl.electrons(W=K, seed_offset=23)
+
+    def run(R, zeta, p, C=None):
+        if C is None:
+            C, _ = oracle.huckel(R, zeta, wl.L, N // 2, twist=twist)
+        g = vmc.vmc_eval_configs(ctx, sysd, T(torch, R.reshape(-1)), T(torch, C), T(torch, zeta), T(torch, p))
+        return g.cpu().numpy(), C
+
+    g0, C0 = run(wl.R, wl.zeta, pos)
+    tol = ({"lnpsi": 1e-10, "EL": 1e-10, "dlnpsi": 1e-10, "dEL": 1e-10} if precision == 0 else
+           {"lnpsi": 1e-6, "EL": 5e-5, "dlnpsi": 2e-5, "dEL": 2e-5})
+    tail = 1e-7 if precision == 0 else 5e-3      # worst measured: 1.2e-8 (FP64), 4.1e-4 (mixed)
+
+    def per_config(a, b):
+        a, b = a.reshape(K, -1), b.reshape(K, -1)
+        return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+    def check(g, label, perm=None):
+        d0 = g0[:, 2:].reshape(K, 2, N, 3)
+        if perm is not None:
+            d0 = d0[:, :, perm, :]
+        d = g[:, 2:].reshape(K, 2, N, 3)
+        errs = {"lnpsi": per_config(g[:, 0], g0[:, 0]), "EL": per_config(g[:, 1], g0[:, 1]),
+                "dlnpsi": per_config(d[:, 0], d0[:, 0]), "dEL": per_config(d[:, 1], d0[:, 1])}
+        say(f"  {label}: per-configuration relative error median / 99th percentile / max",
+            {q: f"{np.median(v):.1e} / {np.quantile(v, 0.99):.1e} / {v.max():.1e}" for q, v in errs.items()})
+        for q, v in errs.items():
+            assert np.quantile(v, 0.99) < tol[q], (label, q)
+            assert v.max() < tail, (label, q)
+            if precision == 0:
+                assert np.median(v) < 1e-12, (label, q)
+
+    # the moved protons' orbitals exactly: wrapping proton a by k_am box lengths along axis m
+    # multiplies its basis function by prod_m tau_m^k_am (tau_m = -1 on a twisted axis), which its
+    # row of C takes over (a fresh Hueckel solve would add the eigensolver's rounding)
+    c = np.array([0.37, -0.81, 0.55]) * wl.L
+    k = np.floor((wl.R + c) / wl.L).astype(np.int64)
+    R2, pos2 = wl.R + c - wl.L * k, np.mod(pos + c, wl.L)
+    tw_bits = np.array([(twist >> m) & 1 for m in range(3)])
+    D = (-1.0) ** ((k * tw_bits).sum(axis=1) % 2)
+    check(run(R2, wl.zeta, pos2, np.ascontiguousarray(D[:, None] * C0))[0], "translation")
+    px = pos.copy()
+    px[:, [3, 40]] = px[:, [40, 3]]
+    px[:, [70, 127]] = px[:, [127, 70]]
+    check(run(wl.R, wl.zeta, px, C0)[0], "same-spin exchanges")
+    perm = np.random.default_rng(8).permutation(N)
+    check(run(np.ascontiguousarray(wl.R[perm]), np.ascontiguousarray(wl.zeta[perm]), pos,
+              np.ascontiguousarray(C0[perm]))[0], "proton relabelling", perm)
