@@ -128,21 +128,24 @@ def test_full_size_step(oracle, dev, name, W, precision, ne, ns, sampled):
         assert np.array_equal(Rpg.cpu().numpy(), Rpo) and np.array_equal(Spg.cpu().numpy(), Spo)
 
 
-@pytest.mark.parametrize("precision,twist", [(0, 0), (1, 0), (0, 5)])
-def test_full_size_symmetries(oracle, dev, precision, twist):
-    """Symmetries of psi on the GPU over 16,384 N = 128 configurations in one launch: a
+@pytest.mark.parametrize("name,K,precision,twist", [("h128", 16384, 0, 0), ("h128", 16384, 1, 0), ("h128", 16384, 0, 5),
+                                                     ("h256", 32768, 1, 0), ("h256", 32768, 0, 3)])
+def test_full_size_symmetries(oracle, dev, name, K, precision, twist):
+    """Symmetries of psi on the GPU over all configurations of a full-size batch (16,384 at N = 128,
+    32,768 at N = 256) in one launch: a
     translation of every particle with re-wrapping into the box (orbital rows carried along), an exchange
     of two same-spin electrons in every configuration, and a relabelling of the protons (with their
     exponents and orbital rows) leave ln|psi| and E_L unchanged and permute the proton derivatives.
     Per configuration: the 99th percentile within 1e-10 in FP64 (median below 1e-12) and within the
-    mixed-precision bars in mixed.  The maximum is held to 1e-7 (FP64) and 5e-3 (mixed): on the few
-    unequilibrated configurations with ill-conditioned Slater matrices, FP64 rounding fixes E_L only
-    to about 1e-9 (the oracle's own translation discrepancy there is the same size), and the
-    proton derivatives to about 1e-8."""
+    mixed-precision bars in mixed.  The maximum is held to 1e-7 (FP64) and 5e-2 (mixed).  The tail
+    comes from a few unequilibrated configurations.  Some have ill-conditioned Slater matrices, where
+    FP64 rounding fixes E_L only to about 1e-9 (the oracle's own translation discrepancy there is the
+    same size) and the proton derivatives to about 1e-8.  Others have E_L near zero against
+    |V| ~ 400 Ha, where FP32 rounding of V is a large relative error in E_L."""
     torch, vmc, ctx = dev
-    wl = workload("h128")
-    K, N = 16384, wl.n
-    say(f"[full size symmetries] h128 K={K} precision={precision} twist={twist}")
+    wl = workload(name)
+    N = wl.n
+    say(f"[full size symmetries] {name} K={K} precision={precision} twist={twist}")
     sysd = vmc.make_system(N, wl.L, precision=precision, twist=twist)
     pos = wl.electrons(W=K, seed_offset=23)
 
@@ -155,7 +158,7 @@ def test_full_size_symmetries(oracle, dev, precision, twist):
     g0, C0 = run(wl.R, wl.zeta, pos)
     tol = ({"lnpsi": 1e-10, "EL": 1e-10, "dlnpsi": 1e-10, "dEL": 1e-10} if precision == 0 else
            {"lnpsi": 1e-6, "EL": 5e-5, "dlnpsi": 2e-5, "dEL": 2e-5})
-    tail = 1e-7 if precision == 0 else 5e-3      # worst measured: 1.2e-8 (FP64), 4.1e-4 (mixed)
+    tail = 1e-7 if precision == 0 else 5e-2      # worst measured: 1.2e-8 (FP64), 1.1e-2 (mixed, N = 256)
 
     def per_config(a, b):
         a, b = a.reshape(K, -1), b.reshape(K, -1)
@@ -186,8 +189,8 @@ def test_full_size_symmetries(oracle, dev, precision, twist):
     D = (-1.0) ** ((k * tw_bits).sum(axis=1) % 2)
     check(run(R2, wl.zeta, pos2, np.ascontiguousarray(D[:, None] * C0))[0], "translation")
     px = pos.copy()
-    px[:, [3, 40]] = px[:, [40, 3]]
-    px[:, [70, 127]] = px[:, [127, 70]]
+    for i, j in ((3, N // 2 - 24), (N // 2 + 6, N - 1)):      # one pair of each spin
+        px[:, [i, j]] = px[:, [j, i]]
     check(run(wl.R, wl.zeta, px, C0)[0], "same-spin exchanges")
     perm = np.random.default_rng(8).permutation(N)
     check(run(np.ascontiguousarray(wl.R[perm]), np.ascontiguousarray(wl.zeta[perm]), pos,
