@@ -163,6 +163,18 @@ int vmc_traj_walkers_reset(vmc_traj* traj, int* n_reset);
  * anything else, or a damaged buffer, returns VMC_EINVAL and leaves the trajectory unchanged. */
 int vmc_traj_save(vmc_traj* traj, void* buf, size_t* len);
 int vmc_traj_load(vmc_traj* traj, const void* buf, size_t len);
+/* Restart at another density (SI, systematic setup: configurations made at r_s* serve at any
+ * r_s after scaling by s = r_s / r_s*).  vmc_traj_load_rescaled reads a checkpoint taken in a
+ * box of side L* into a trajectory whose system differs from the checkpoint's at most in box_L
+ * and ewald_kappa (N, walker count, precision, n_max, Jastrow, one-body term and twist must
+ * match; VMC_EINVAL otherwise, or for a damaged buffer, with the trajectory unchanged).  Every
+ * walker coordinate is multiplied by s = L / L* (L = this trajectory's box_L; at fixed N,
+ * L is proportional to r_s), so walkers in [0, L*) land in [0, L).  The RNG key is the
+ * checkpoint's.  The means, forces and acceptance counts belong to the old density and are
+ * cleared: vmc_build_S and vmc_traj_walker_* return VMC_EINVAL until the next
+ * vmc_energy_forces call.  The caller scales the proton positions (R, R_prev) by the same s
+ * and starts the Langevin update afresh (S_prev from the first step at the new density). */
+int vmc_traj_load_rescaled(vmc_traj* traj, const void* buf, size_t len);
 
 /* a8 (main text, Eq. for Cov(f); SI, alpha paragraph): the acceleration matrix
  * S = Cov of the mean force = sum_w (f_w - f)(f_w - f)^T / (W (W - 1)) from the

@@ -463,32 +463,51 @@ int vmc_traj_save(vmc_traj* t, void* buf, size_t* len) {
   return VMC_OK;
 }
 
-int vmc_traj_load(vmc_traj* t, const void* buf, size_t len) {
+// Shared by vmc_traj_load and vmc_traj_load_rescaled.  rescale: the checkpoint's box side may
+// differ from the trajectory's (its Ewald kappa then follows the box); walker coordinates are
+// multiplied by L / L*, and the accumulators of the old density are cleared.
+static int traj_load(vmc_traj* t, const void* buf, size_t len, bool rescale) {
   if (!t || !buf || len < sizeof(CkptHeader)) return VMC_EINVAL;
   CkptHeader h;
   std::memcpy(&h, buf, sizeof h);
   if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1 || len < ckpt_bytes(t)) return VMC_EINVAL;
   const vmc_system& s = t->sys;
   if (h.n != t->N || h.w != t->W || h.precision != s.precision || h.nmax != s.ewald_nmax || h.twist != s.twist ||
-      h.box_L != s.box_L || h.kappa != s.ewald_kappa || h.a_par != s.a_par || h.a_anti != s.a_anti || h.b != s.b ||
-      h.j1_b1 != s.j1_b1)
+      h.a_par != s.a_par || h.a_anti != s.a_anti || h.b != s.b || h.j1_b1 != s.j1_b1)
     return VMC_EINVAL;
+  if (!rescale && (h.box_L != s.box_L || h.kappa != s.ewald_kappa)) return VMC_EINVAL;
+  if (rescale && !(h.box_L > 0.0 && std::isfinite(h.box_L))) return VMC_EINVAL;
   HIPCHK(hipSetDevice(t->ctx->device));
   HIPCHK(hipStreamSynchronize(t->ctx->stream));
   const unsigned char* p = static_cast<const unsigned char*>(buf) + sizeof h;
   const size_t W = t->W, N = t->N;
   const size_t nb[3] = {W * N * 3 * sizeof(double), W * (1 + 9 * N) * sizeof(double), W * 3 * N * sizeof(double)};
-  void* dst[3] = {t->pos, t->means, t->f_w};
-  for (int k = 0; k < 3; ++k) {
-    HIPCHK(hipMemcpy(dst[k], p, nb[k], hipMemcpyHostToDevice));
-    p += nb[k];
+  if (rescale) {
+    // x -> (L / L*) x keeps every coordinate in [0, L) and every walker's shape
+    const double sc = s.box_L / h.box_L;
+    std::vector<double> x(W * N * 3);
+    std::memcpy(x.data(), p, nb[0]);
+    for (double& v : x) v *= sc;
+    HIPCHK(hipMemcpy(t->pos, x.data(), nb[0], hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(t->nacc, 0, W * sizeof(int64_t)));
+    t->have_means = false;
+  } else {
+    void* dst[3] = {t->pos, t->means, t->f_w};
+    for (int k = 0; k < 3; ++k) {
+      HIPCHK(hipMemcpy(dst[k], p, nb[k], hipMemcpyHostToDevice));
+      p += nb[k];
+    }
+    HIPCHK(hipMemcpy(t->nacc, p, W * sizeof(int64_t), hipMemcpyHostToDevice));
+    t->have_means = h.have_means != 0;
   }
-  HIPCHK(hipMemcpy(t->nacc, p, W * sizeof(int64_t), hipMemcpyHostToDevice));
   t->seed = h.seed;
   t->traj_id = h.traj_id;
-  t->have_means = h.have_means != 0;
   return VMC_OK;
 }
+
+int vmc_traj_load(vmc_traj* t, const void* buf, size_t len) { return traj_load(t, buf, len, false); }
+
+int vmc_traj_load_rescaled(vmc_traj* t, const void* buf, size_t len) { return traj_load(t, buf, len, true); }
 
 int vmc_traj_walkers_reset(vmc_traj* t, int* n_reset) {
   if (!t || !n_reset) return VMC_EINVAL;

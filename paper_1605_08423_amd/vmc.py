@@ -24,7 +24,7 @@ EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_
             "vmc_request_bytes", "vmc_server_admit_count", "vmc_server_create", "vmc_server_destroy",
             "vmc_server_submit", "vmc_server_cancel", "vmc_server_tick", "vmc_server_status",
             "vmc_server_result", "vmc_server_info", "vmc_toy_run", "vmc_huckel_params_twist",
-            "vmc_twist_average", "vmc_traj_save", "vmc_traj_load", "vmc_traj_walkers_reset"]
+            "vmc_twist_average", "vmc_traj_save", "vmc_traj_load", "vmc_traj_load_rescaled", "vmc_traj_walkers_reset"]
 VMC_REQ_QUEUED, VMC_REQ_RUNNING, VMC_REQ_DONE, VMC_REQ_FAILED, VMC_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
@@ -93,6 +93,7 @@ def _declare(l):
     l.vmc_traj_save.argtypes = [vp, vp, P(C.c_size_t)]
     l.vmc_traj_walkers_reset.argtypes = [vp, P(i)]
     l.vmc_traj_load.argtypes = [vp, vp, C.c_size_t]
+    l.vmc_traj_load_rescaled.argtypes = [vp, vp, C.c_size_t]
     sz = C.c_size_t
     l.vmc_request_bytes.restype = sz
     l.vmc_request_bytes.argtypes = [P(vmc_request)]
@@ -224,6 +225,12 @@ class Trajectory:
     def load(self, data: bytes):
         buf = C.create_string_buffer(data, len(data))
         _check(_lib().vmc_traj_load(self.h, buf, len(data)), "vmc_traj_load")
+
+    def load_rescaled(self, data: bytes):
+        """Restart from a checkpoint taken in another box: walkers scaled by L / L*
+        (see vmc_traj_load_rescaled); the caller scales R by the same factor."""
+        buf = C.create_string_buffer(data, len(data))
+        _check(_lib().vmc_traj_load_rescaled(self.h, buf, len(data)), "vmc_traj_load_rescaled")
 
     def close(self):
         if self.h:

@@ -1,6 +1,7 @@
 """Checkpoint / resume of a trajectory through the C ABI: a trajectory saved after one Langevin
 step and loaded into a fresh trajectory continues the run bit for bit; mismatched or damaged
-checkpoints are refused and leave the target unchanged."""
+checkpoints are refused and leave the target unchanged; a checkpoint restarts a trajectory at
+another density with its walkers scaled by the ratio of the box sides."""
 import sys
 
 import numpy as np
@@ -105,3 +106,53 @@ def test_mismatched_or_damaged_checkpoint_refused(dev):
         tr.load(bytes(damaged))
     assert np.array_equal(tr.get_walkers().cpu().numpy(), x_before)
     tr.close()
+
+
+@pytest.mark.parametrize("precision,twist", [(0, 0), (1, 5)])
+def test_restart_at_another_density(dev, precision, twist):
+    """A checkpoint taken at r_s* = 1.32 restarts a trajectory at r_s = 1.40 (SI, systematic setup:
+    configurations scaled by s = r_s / r_s*): the walkers arrive multiplied by s = L / L*, bit for
+    bit; the old density's means are gone until the next call; the next step equals that of a
+    fresh trajectory at the new density started from the scaled walkers with the checkpoint's key.
+    A plain load into the new box and a rescaled load of another size are refused."""
+    torch, vmc, ctx = dev
+    wl = workload("h54")
+    W = 64
+    L1 = wl.L * (1.40 / 1.32)
+    say(f"[rescaled restart] h54 W={W} precision={precision} twist={twist} L {wl.L:.4f} -> {L1:.4f}")
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=precision, twist=twist), W, seed=31, traj_id=6)
+    tr.set_walkers(T(torch, wl.electrons(W=W, seed_offset=12)))
+    Cm = vmc.vmc_huckel_params(wl.R, wl.zeta, wl.L, twist=twist)
+    tr.energy_forces(T(torch, wl.R.reshape(-1)), T(torch, Cm), T(torch, wl.zeta), 2, 2, wl.delta, 0)
+    blob = tr.save()
+    x_saved = tr.get_walkers().cpu().numpy()
+    tr.close()
+
+    sys1 = vmc.make_system(wl.n, L1, precision=precision, twist=twist)
+    s = L1 / wl.L
+    R1 = wl.R * s
+    C1 = vmc.vmc_huckel_params(R1, wl.zeta, L1, twist=twist)
+    a = vmc.Trajectory(ctx, sys1, W, seed=5, traj_id=0)
+    with pytest.raises(vmc.VMCError):
+        a.load(blob)                                  # the box differs: only the rescaled load takes it
+    a.load_rescaled(blob)
+    assert np.array_equal(a.get_walkers().cpu().numpy(), x_saved * s)
+    assert x_saved.max() * s < L1
+    with pytest.raises(vmc.VMCError):
+        a.walker_means()
+    with pytest.raises(vmc.VMCError):
+        a.build_S()
+    out_a = a.energy_forces(T(torch, R1.reshape(-1)), T(torch, C1), T(torch, wl.zeta), 1, 2, wl.delta, 1).cpu().numpy()
+    m_a = a.walker_means().cpu().numpy()
+    a.close()
+    b = vmc.Trajectory(ctx, sys1, W, seed=31, traj_id=6)
+    b.set_walkers(T(torch, x_saved * s))
+    out_b = b.energy_forces(T(torch, R1.reshape(-1)), T(torch, C1), T(torch, wl.zeta), 1, 2, wl.delta, 1).cpu().numpy()
+    m_b = b.walker_means().cpu().numpy()
+    b.close()
+    assert np.array_equal(out_a, out_b) and np.array_equal(m_a, m_b)
+    for bad in (vmc.Trajectory(ctx, sys1, W + 4, seed=5, traj_id=0),
+                vmc.Trajectory(ctx, vmc.make_system(wl.n, L1, precision=1 - precision, twist=twist), W, seed=5, traj_id=0)):
+        with pytest.raises(vmc.VMCError):
+            bad.load_rescaled(blob)
+        bad.close()
