@@ -1109,6 +1109,110 @@ __global__ __launch_bounds__(256, 1) void k_refine(WalkerArgs a, int sp, double 
   if (lane == 0 && !(rmax <= tol)) a.rflag[(size_t)w * 2 + sp] = 1;
 }
 
+// The same step with two waves per matrix, for matrices of an even number (>= 2) of column
+// tiles: wave h of a pair owns column tiles [h NT/2, (h+1) NT/2) of R and of the new X, so it
+// holds half the fragments of k_refine and two work-groups (two matrices each) fit per CU,
+// letting one matrix's loads overlap another's matrix-core work.  X's LDS copy, the left
+// operand of X R, is shared by the pair and taken before either wave writes X back.  Every
+// output tile accumulates the same products in the same order as in k_refine, so the results
+// are identical.
+template <int NS>
+struct RefinePairLds {
+  static constexpr size_t bytes = (size_t)2 * RefineLds<NS>::NSP * RefineLds<NS>::LDX * sizeof(double);
+};
+
+template <int NS>
+__global__ __launch_bounds__(256, 2) void k_refine_pair(WalkerArgs a, int sp, double tol) {
+  constexpr int NSP = RefineLds<NS>::NSP, NT = NSP / 16, LDX = RefineLds<NS>::LDX, NH = NT / 2;
+  static_assert(NT >= 2 && NT % 2 == 0, "the two waves split the column tiles evenly");
+  extern __shared__ __align__(16) double smem_r[];
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int w = (int)blockIdx.x * 2 + (wv >> 1), h = wv & 1;
+  const bool active = w < a.W;
+  double* xs = smem_r + (size_t)(wv >> 1) * NSP * LDX;
+  const size_t base = ((size_t)(active ? w : 0) * 2 + sp) * NS * NS;
+  const double* Ag = a.Amat + base;
+  double* Xg = a.Binv + base;
+  const int loff = l4 * NS + l16;
+  d4w_t xr[NT][NH];                 // X[:, tiles h NH .. h NH + NH - 1] in accumulator layout
+  if (active) {
+#pragma unroll
+    for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double* rowp = Xg + (16 * tr + 4 * v) * NS;
+#pragma unroll
+        for (int j = 0; j < NH; ++j) {
+          const int tc = h * NH + j;
+          const bool ok = (16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS);
+          const double val = rowp[ok ? loff + 16 * tc : -(16 * tr + 4 * v) * NS];
+          xr[tr][j][v] = ok ? val : 0.0;
+          xs[(16 * tr + 4 * v + l4) * LDX + 16 * tc + l16] = ok ? val : 0.0;
+        }
+      }
+  }
+  __syncthreads();                  // the pair's halves of X are in LDS (the only barrier)
+  if (!active) return;
+  // R[:, own tiles] = I - A X[:, own tiles]
+  d4w_t rr[NT][NH];
+  double rmax = 0.0;
+#pragma unroll
+  for (int tr = 0; tr < NT; ++tr) {
+    d4w_t acc[NH];
+#pragma unroll
+    for (int j = 0; j < NH; ++j) acc[j] = d4w_t{0.0, 0.0, 0.0, 0.0};
+    const int arow = 16 * tr + l16;
+#pragma unroll
+    for (int ks = 0; ks < NSP / 4; ++ks) {
+      const int acol = 4 * ks + l4;
+      const bool ok = arow < NS && acol < NS;
+      const double val = Ag[ok ? arow * NS + acol : 0];
+      const double av = ok ? val : 0.0;
+#pragma unroll
+      for (int j = 0; j < NH; ++j) acc[j] = mfma_w(av, xr[ks / 4][j][ks % 4], acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NH; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * tr + 4 * v + l4, col = 16 * (h * NH + j) + l16;
+        const double r = (row < NS && col < NS) ? ((row == col ? 1.0 : 0.0) - acc[j][v]) : 0.0;
+        rr[tr][j][v] = r;
+        rmax = fmax(rmax, fabs(r)) + (r - r);     // NaN propagates
+      }
+  }
+  // X[:, own tiles] + X R[:, own tiles], written back in place (the other wave reads X from LDS)
+#pragma unroll
+  for (int tr = 0; tr < NT; ++tr) {
+    d4w_t acc[NH];
+#pragma unroll
+    for (int j = 0; j < NH; ++j) acc[j] = xr[tr][j];
+#pragma unroll
+    for (int ks = 0; ks < NSP / 4; ++ks) {
+      const double av = xs[(16 * tr + l16) * LDX + 4 * ks + l4];
+#pragma unroll
+      for (int j = 0; j < NH; ++j) acc[j] = mfma_w(av, rr[ks / 4][j][ks % 4], acc[j]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double* rowp = Xg + (16 * tr + 4 * v) * NS;
+#pragma unroll
+      for (int j = 0; j < NH; ++j) {
+        const int tc = h * NH + j;
+        if ((16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS)) rowp[loff + 16 * tc] = acc[j][v];
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double o = __shfl_xor(rmax, off, 64);
+    rmax = (o > rmax || o != o) ? o : rmax;
+  }
+  // either wave of the pair may flag the matrix (both store the same value)
+  if (lane == 0 && !(rmax <= tol)) a.rflag[(size_t)w * 2 + sp] = 1;
+}
+
 // The refinement step for NS = 128, where X and A do not fit in registers: one 512-thread
 // work-group per matrix.  Both products take the right operand's column tile w of wave w in
 // registers (read once) and stage the left operand 16 rows at a time in LDS, row tiles in
@@ -1267,6 +1371,16 @@ hipError_t launch_refine_t(const WalkerArgs& a, int spin, double tol, hipStream_
       hipLaunchKernelGGL((k_refine_big<NS, false>), g, dim3(512), 0, st, a, spin, tol, batch_or_none(bt));
     return hipGetLastError();
   } else {
+    constexpr int NT = RefineLds<NS>::NSP / 16;
+    if constexpr (NT >= 2 && NT % 2 == 0) {
+      // one trajectory: two waves per matrix (the request loop's batched launches keep k_refine,
+      // whose results are identical)
+      if (!bt) {
+        hipLaunchKernelGGL((k_refine_pair<NS>), dim3((a.W + 1) / 2), dim3(256), RefinePairLds<NS>::bytes, st, a,
+                           spin, tol);
+        return hipGetLastError();
+      }
+    }
     dim3 grid(bt ? nblk : (a.W + 3) / 4);
     if (bt)
       hipLaunchKernelGGL((k_refine<NS, true>), grid, dim3(256), RefineLds<NS>::bytes, st, a, spin, tol, *bt);
