@@ -1121,14 +1121,22 @@ struct RefinePairLds {
   static constexpr size_t bytes = (size_t)2 * RefineLds<NS>::NSP * RefineLds<NS>::LDX * sizeof(double);
 };
 
-template <int NS>
-__global__ __launch_bounds__(256, 2) void k_refine_pair(WalkerArgs a, int sp, double tol) {
+template <int NS, bool BATCH>
+__global__ __launch_bounds__(256, 2) void k_refine_pair(WalkerArgs a, int sp, double tol, Batch bt) {
   constexpr int NSP = RefineLds<NS>::NSP, NT = NSP / 16, LDX = RefineLds<NS>::LDX, NH = NT / 2;
   static_assert(NT >= 2 && NT % 2 == 0, "the two waves split the column tiles evenly");
   extern __shared__ __align__(16) double smem_r[];
+  int bblk = 0;
+  if constexpr (BATCH) {
+    const int j = batch_job(bt, blockIdx.x);
+    a = bt.jobs[j].a;
+    tol = bt.jobs[j].tol;
+    bblk = (int)blockIdx.x - bt.off[j];
+  }
+  const int blk = BATCH ? bblk : (int)blockIdx.x;
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l16 = lane & 15, l4 = lane >> 4;
-  const int w = (int)blockIdx.x * 2 + (wv >> 1), h = wv & 1;
+  const int w = blk * 2 + (wv >> 1), h = wv & 1;
   const bool active = w < a.W;
   double* xs = smem_r + (size_t)(wv >> 1) * NSP * LDX;
   const size_t base = ((size_t)(active ? w : 0) * 2 + sp) * NS * NS;
@@ -1371,15 +1379,14 @@ hipError_t launch_refine_t(const WalkerArgs& a, int spin, double tol, hipStream_
       hipLaunchKernelGGL((k_refine_big<NS, false>), g, dim3(512), 0, st, a, spin, tol, batch_or_none(bt));
     return hipGetLastError();
   } else {
-    constexpr int NT = RefineLds<NS>::NSP / 16;
-    if constexpr (NT >= 2 && NT % 2 == 0) {
-      // one trajectory: two waves per matrix (the request loop's batched launches keep k_refine,
-      // whose results are identical)
-      if (!bt) {
-        hipLaunchKernelGGL((k_refine_pair<NS>), dim3((a.W + 1) / 2), dim3(256), RefinePairLds<NS>::bytes, st, a,
-                           spin, tol);
-        return hipGetLastError();
-      }
+    if constexpr (refine_pairs(NS)) {             // two waves per matrix, two matrices per block
+      if (bt)
+        hipLaunchKernelGGL((k_refine_pair<NS, true>), dim3(nblk), dim3(256), RefinePairLds<NS>::bytes, st, a, spin,
+                           tol, *bt);
+      else
+        hipLaunchKernelGGL((k_refine_pair<NS, false>), dim3((a.W + 1) / 2), dim3(256), RefinePairLds<NS>::bytes, st,
+                           a, spin, tol, batch_or_none(bt));
+      return hipGetLastError();
     }
     dim3 grid(bt ? nblk : (a.W + 3) / 4);
     if (bt)

@@ -104,6 +104,11 @@ hipError_t launch_invert(const WalkerArgs& a, int spin_lo, int spin_hi, int only
                          const Batch* bt = nullptr, int nblk = 0);
 hipError_t launch_refine(const WalkerArgs& a, int spin, double tol, hipStream_t st, const Batch* bt = nullptr,
                          int nblk = 0);
+// Blocks of the refresh launch: two waves per matrix and two matrices per block where a matrix has
+// an even number (>= 2) of 16-wide column tiles, four one-wave matrices per block otherwise, one
+// block per matrix for N_sigma > 64.
+constexpr bool refine_pairs(int NS) { return NS <= 64 && (NS + 15) / 16 >= 2 && ((NS + 15) / 16) % 2 == 0; }
+constexpr int refine_blocks(int NS, int W) { return NS > 64 ? W : refine_pairs(NS) ? (W + 1) / 2 : (W + 3) / 4; }
 hipError_t launch_sweep(const WalkerArgs& a, const SweepArgs& s, int mixed, hipStream_t st, const Batch* bt = nullptr,
                         int nblk = 0);
 

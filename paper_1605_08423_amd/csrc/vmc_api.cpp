@@ -1088,18 +1088,24 @@ int bucket_sweep(vmc_server* s, const std::vector<Served*>& qs) {
   const int nq = (int)qs.size();
   // host tables: [jobs sweep | jobs refresh | jobs measure] then offsets
   std::vector<TrajJob> js, jr, jm;
-  std::vector<int> os{0}, orf{0}, om{0};
+  std::vector<int> os{0}, orf{0}, orp{0}, om{0};
   for (Served* q : qs) {
     const TrajJob j = make_job(q, q->sweep);
     js.push_back(j);
     os.push_back(os.back() + (q->t->W + 3) / 4);
-    // refresh blocks: four walkers each, or one matrix each for N_sigma > 64
-    if (q->sweep >= 1) { jr.push_back(j); orf.push_back(orf.back() + (q->t->NS > 64 ? q->t->W : (q->t->W + 3) / 4)); }
+    // fallback elimination blocks: four walkers each, or one matrix each for N_sigma > 64; the
+    // refresh's own blocks (refine_blocks) may pack matrices differently
+    if (q->sweep >= 1) {
+      jr.push_back(j);
+      orf.push_back(orf.back() + (q->t->NS > 64 ? q->t->W : (q->t->W + 3) / 4));
+      orp.push_back(orp.back() + refine_blocks(q->t->NS, q->t->W));
+    }
     if (q->sweep >= q->n_equil_cur) { jm.push_back(j); om.push_back(om.back() + q->t->W); }
   }
   const size_t nj = js.size() + jr.size() + jm.size();
   const size_t bytes_jobs = nj * sizeof(TrajJob);
-  const size_t bytes = bytes_jobs + (os.size() + orf.size() + om.size()) * sizeof(int) + 64;
+  // every piece is padded to 16 bytes: at most 15 more bytes for each of the seven
+  const size_t bytes = bytes_jobs + (os.size() + orf.size() + orp.size() + om.size()) * sizeof(int) + 7 * 16;
   const int k = s->ring;
   s->ring = (s->ring + 1) % vmc_server::RING;
   if (s->tab_used[k]) HIPCHK(hipEventSynchronize(s->tab_ev[k]));      // its previous upload has been consumed
@@ -1133,18 +1139,20 @@ int bucket_sweep(vmc_server* s, const std::vector<Served*>& qs) {
   const size_t o_jm = put(jm.data(), jm.size() * sizeof(TrajJob));
   const size_t o_os = put(os.data(), os.size() * sizeof(int));
   const size_t o_or = put(orf.data(), orf.size() * sizeof(int));
+  const size_t o_op = put(orp.data(), orp.size() * sizeof(int));
   const size_t o_om = put(om.data(), om.size() * sizeof(int));
   HIPCHK(hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, st));
   HIPCHK(hipEventRecord(s->tab_ev[k], st));
   s->tab_used[k] = true;
   const Batch bsw{(const TrajJob*)(d + o_js), (const int*)(d + o_os), (int)js.size()};
   const Batch brf{(const TrajJob*)(d + o_jr), (const int*)(d + o_or), (int)jr.size()};
+  const Batch brp{(const TrajJob*)(d + o_jr), (const int*)(d + o_op), (int)jr.size()};
   const Batch bms{(const TrajJob*)(d + o_jm), (const int*)(d + o_om), (int)jm.size()};
   const int mixed = qs[0]->req.sys.precision == VMC_MIXED;
   const TrajJob& j0 = js[0];
   for (int sp = 0; sp < 2; ++sp) {
     if (!jr.empty()) {
-      RUN(K_REFINE, launch_refine(j0.a, sp, j0.tol, st, &brf, orf.back()));
+      RUN(K_REFINE, launch_refine(j0.a, sp, j0.tol, st, &brp, orp.back()));
       RUN(K_INVERT, launch_invert(j0.a, sp, sp + 1, 1, st, &brf, orf.back()));
     }
     SweepArgs sa = j0.s;
