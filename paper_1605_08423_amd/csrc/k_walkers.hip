@@ -1225,9 +1225,11 @@ __global__ __launch_bounds__(256, 2) void k_refine_pair(WalkerArgs a, int sp, do
 // work-group per matrix.  Both products take the right operand's column tile w of wave w in
 // registers (read once) and stage the left operand 16 rows at a time in LDS, row tiles in
 // the outer loop so X can be updated in place (row tile rt of X + X R needs only row tile rt
-// of X).  R = I - A X goes to the walker's scratch between the two products.
+// of X).  R = I - A X goes to the walker's scratch between the two products.  Built for four
+// waves per SIMD (128 registers, a few spilled) so that two work-groups share a CU and one's
+// row-tile loads and barriers overlap the other's matrix-core work.
 template <int NS, bool BATCH>
-__global__ __launch_bounds__(512, 1) void k_refine_big(WalkerArgs a, int sp, double tol, Batch bt) {
+__global__ __launch_bounds__(512, 4) void k_refine_big(WalkerArgs a, int sp, double tol, Batch bt) {
   static_assert(NS == 128, "eight column tiles, one per wave");
   constexpr int KK = NS / 4, NRT = NS / 16, LDS_S = NS + 1, NTH = 512;
   __shared__ double stage[16 * LDS_S];
