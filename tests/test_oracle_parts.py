@@ -37,6 +37,16 @@ def _philox_inverse(out, key):
     return [n0, n1, n2, n3]
 
 
+def test_philox_known_answers(oracle):
+    """The published Philox4x32-10 known-answer vectors (Salmon et al., SC'11): pins the
+    multipliers, the Weyl key increments, the round count and the output word order."""
+    kat = json.load(open(os.path.join(GOLD, "philox4x32_10_kat.json")))["vectors"]
+    for v in kat:
+        ctr = [int(h, 16) for h in v["ctr"]]
+        key = [int(h, 16) for h in v["key"]]
+        assert oracle.philox(ctr, key) == [int(h, 16) for h in v["out"]], v
+
+
 def test_philox_is_keyed_bijection(oracle):
     rng = np.random.default_rng(7)
     for _ in range(50):
