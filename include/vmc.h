@@ -42,8 +42,13 @@ enum {
   VMC_ENOTSPD = -3,    /* Cholesky of S failed: S not positive definite */
   VMC_ESINGULAR = -4,  /* a Slater matrix had a zero pivot at an inverse refresh */
   VMC_EDEVICE = -5,    /* a HIP runtime error */
-  VMC_ENOTBUILT = -6   /* no device code for this GPU */
+  VMC_ENOTBUILT = -6,  /* no device code for this GPU */
+  VMC_ECANCELLED = -7, /* stopped by vmc_cancel or vmc_server_cancel; the state is as before the call */
+  VMC_ENOCONV = -8     /* the host eigen-solver of the Hueckel orbitals did not converge */
 };
+
+/* `step` of vmc_energy_forces: use the trajectory's own Langevin step counter. */
+#define VMC_STEP_TRAJ 0xFFFFFFFFu
 
 enum { VMC_FP64 = 0, VMC_MIXED = 1 };
 
@@ -87,6 +92,17 @@ typedef struct {
 /* Creates a context on HIP device `device`.  Allocates small device scratch. */
 int vmc_create(vmc_ctx** out, int device);
 void vmc_destroy(vmc_ctx* ctx);
+/* HBM budget of the context's trajectories (bytes; 0 = no limit, the default): vmc_traj_create
+ * returns VMC_ENOMEM when the device bytes of the context's live trajectories (vmc_traj_bytes)
+ * would exceed it.  vmc_hbm_in_use: the bytes they hold now. */
+int vmc_set_hbm_budget(vmc_ctx* ctx, size_t bytes);
+int vmc_hbm_in_use(vmc_ctx* ctx, size_t* in_use);
+/* Device bytes a trajectory of this system and walker count holds (0 if invalid). */
+size_t vmc_traj_bytes(const vmc_system* sys, int n_walkers);
+/* Asks the vmc_energy_forces call running on this context (or, if none runs, the next one)
+ * to stop: it returns VMC_ECANCELLED within a few sweeps, with the trajectory as it was
+ * before the call.  The only call that may be made from another thread. */
+int vmc_cancel(vmc_ctx* ctx);
 /* hip_stream: a hipStream_t (NULL = null stream).  Not owned. */
 int vmc_set_stream(vmc_ctx* ctx, void* hip_stream);
 const char* vmc_strerror(int code);
@@ -104,7 +120,9 @@ int vmc_reset_kernel_times(vmc_ctx* ctx);
 /* ------------------------------------------------------------- trajectory -- */
 /* Device-resident state of one trajectory: W walkers (electron positions,
  * cached Slater matrices and inverses, accumulators), the per-walker force
- * means of the last vmc_energy_forces call and the RNG key (seed, traj_id).
+ * means of the last vmc_energy_forces call, the RNG key (seed, traj_id) and the
+ * Langevin state: proton positions R, the previous step's R and S (Eq. finaldyn_new
+ * needs R(t - Delta) and S(R(t - Delta))), the last S and the step counter.
  * Allocates device memory (about W * (16 N^2 + 120 N) bytes + Ewald tables; at N = 256
  * also a per-walker region for the measurement's matrix products, 323 KiB in
  * mixed precision and 645 KiB in FP64). */
@@ -115,6 +133,13 @@ void vmc_traj_destroy(vmc_traj* traj);
  * the box on input). */
 int vmc_traj_set_walkers(vmc_traj* traj, const double* pos_dev);
 int vmc_traj_get_walkers(vmc_traj* traj, double* pos_dev);
+/* Proton positions R (3N, device) held by the trajectory.  vmc_traj_set_R starts a new
+ * Langevin history (the next vmc_traj_langevin_step is a first step: R_prev = R, S_prev = S);
+ * the step counter keeps counting.  vmc_traj_get_R: VMC_EINVAL before R was set. */
+int vmc_traj_set_R(vmc_traj* traj, const double* R_dev);
+int vmc_traj_get_R(vmc_traj* traj, double* R_dev);
+/* Completed vmc_traj_langevin_step calls (the noise counter of the next step). */
+int vmc_traj_step_count(vmc_traj* traj, uint32_t* steps);
 
 /* a1-a7 (main text, Eq. for V(R) and f = -dV/dR; SI, alpha paragraph): VMC
  * estimate of the Born-Oppenheimer energy and ionic forces at proton positions
@@ -133,7 +158,12 @@ int vmc_traj_get_walkers(vmc_traj* traj, double* pos_dev);
  * E = mean_w e_w, sigma_E = sd_w(e_w)/sqrt(W), f = mean_w f_w,
  * f_w = -(<dE_L/dR>_w + 2(<E_L dln|psi|/dR>_w - E <dln|psi|/dR>_w)).
  * Per-walker means stay on the device for vmc_build_S / vmc_traj_walker_*.
- * Returns VMC_ESINGULAR if an inverse refresh hit an exactly zero pivot. */
+ * R_dev == NULL uses the trajectory's R (vmc_traj_set_R); step == VMC_STEP_TRAJ uses its
+ * Langevin step counter.
+ * Returns VMC_ESINGULAR if an inverse refresh hit an exactly zero pivot (e.g. two same-spin
+ * electrons at one point), VMC_ECANCELLED after vmc_cancel, VMC_EINVAL if no walker has finite
+ * coordinates; on every failure the walkers, accepted-move counts and the last call's means
+ * are left as they were before the call and out_dev is not written. */
 int vmc_energy_forces(vmc_traj* traj, const double* R_dev, const double* C_dev, const double* zeta_dev,
                       int n_equil, int n_sweeps, double step_delta, uint32_t step, double* out_dev);
 /* Per-walker means of the last call: means_dev W x (1 + 9N) = [e_w, d_w(3N), g_w(3N), h_w(3N)]
@@ -151,16 +181,19 @@ int vmc_traj_walkers_reset(vmc_traj* traj, int* n_reset);
 /* Checkpoint / resume of the state a trajectory owns between calls: its system and walker
  * count (checked on load), the RNG key (seed, traj_id), the walker positions, and the per-walker
  * means, forces and accepted-move counts of the last vmc_energy_forces call.  The Slater rows,
- * inverses and Ewald tables are rebuilt by every vmc_energy_forces call and are not saved; the
- * Langevin state (R, R_prev, S_prev) and the step counter are the caller's arrays and values.
- * A trajectory loaded from a checkpoint and driven with the same R, C, zeta and step numbers
- * continues the saved run bit for bit.
+ * inverses and Ewald tables are rebuilt by every vmc_energy_forces call and are not saved.  The
+ * trajectory's Langevin state (R, R_prev, S, S_prev, the last estimate [E, sigma_E,
+ * acceptance, f] and the step counter) is saved with it.  A trajectory loaded from a checkpoint
+ * continues the saved run bit for bit (vmc_energy_forces with R_dev = NULL and step =
+ * VMC_STEP_TRAJ, vmc_build_S, vmc_traj_langevin_step) with no state held by the caller but C
+ * and zeta.  The checkpoint carries an FNV-1a checksum of its bytes.
  * vmc_traj_save: buf == NULL sets *len to the bytes needed; otherwise writes the checkpoint to
  * host memory buf of *len bytes (VMC_EINVAL, with *len set to the need, if it is too small);
  * waits for the trajectory's work on the context stream.
  * vmc_traj_load: reads a checkpoint of len bytes from host memory into a trajectory created with
  * the same system (N, box, precision, Ewald settings, one-body term, twist) and walker count;
- * anything else, or a damaged buffer, returns VMC_EINVAL and leaves the trajectory unchanged. */
+ * anything else, or a damaged buffer (checksum, size, version), returns VMC_EINVAL and leaves the
+ * trajectory unchanged. */
 int vmc_traj_save(vmc_traj* traj, void* buf, size_t* len);
 int vmc_traj_load(vmc_traj* traj, const void* buf, size_t len);
 /* Restart at another density (SI, systematic setup: configurations made at r_s* serve at any
@@ -172,13 +205,14 @@ int vmc_traj_load(vmc_traj* traj, const void* buf, size_t len);
  * L is proportional to r_s), so walkers in [0, L*) land in [0, L).  The RNG key is the
  * checkpoint's.  The means, forces and acceptance counts belong to the old density and are
  * cleared: vmc_build_S and vmc_traj_walker_* return VMC_EINVAL until the next
- * vmc_energy_forces call.  The caller scales the proton positions (R, R_prev) by the same s
- * and starts the Langevin update afresh (S_prev from the first step at the new density). */
+ * vmc_energy_forces call.  The Langevin state is cleared too: the caller sets the proton
+ * positions scaled by the same s (vmc_traj_set_R), and the next step is a first step. */
 int vmc_traj_load_rescaled(vmc_traj* traj, const void* buf, size_t len);
 
 /* a8 (main text, Eq. for Cov(f); SI, alpha paragraph): the acceleration matrix
  * S = Cov of the mean force = sum_w (f_w - f)(f_w - f)^T / (W (W - 1)) from the
- * trajectory's last vmc_energy_forces call.  S_dev: 3N x 3N. */
+ * trajectory's last vmc_energy_forces call, kept by the trajectory for
+ * vmc_traj_langevin_step.  S_dev: 3N x 3N, or NULL (kept on the device only). */
 int vmc_build_S(vmc_traj* traj, double* S_dev);
 /* The same for caller-provided per-walker forces f_w_dev (W x n3) and their mean f_dev (n3). */
 int vmc_build_S_raw(vmc_ctx* ctx, int W, int n3, const double* f_w_dev, const double* f_dev, double* S_dev);
@@ -193,12 +227,20 @@ int vmc_build_S_raw(vmc_ctx* ctx, int W, int n3, const double* f_w_dev, const do
  * (n3) and S_prev_dev (n3 x n3) are updated in place ((R_prev, S_prev) <- (R, S));
  * on the first step pass R_prev = R and S_prev = S.  Units: T and Delta in
  * Hartree (S in Ha^2/bohr^2 makes alpha 1/Ha).  Returns VMC_ENOTSPD (state
- * unchanged) if S is not positive definite; VMC_EINVAL if Delta <= 0,
- * alpha < 0, T < 0 or the noise-corrected T is negative. */
+ * unchanged) if S is not positive definite; VMC_EINVAL (state unchanged) if Delta <= 0,
+ * alpha < 0, T < 0, the noise-corrected T is negative, or a position, the force, the
+ * S-difference term or the noise is not finite. */
 int vmc_langevin_step(vmc_ctx* ctx, int n3, double box_L, double* R_dev, double* R_prev_dev,
                       double* S_prev_dev, const double* f_dev, const double* S_dev, double T,
                       double Delta, double alpha, unsigned flags, uint32_t seed, uint32_t traj_id,
                       uint32_t step);
+/* a9-a10 on the trajectory's own state: the same step with R, R_prev, S_prev, f (the last
+ * vmc_energy_forces), S (the last vmc_build_S; not needed with VMC_STEP_CFOLD), box_L, the RNG
+ * key (seed, traj_id) and the step counter held by the trajectory; on its first step (after
+ * vmc_traj_set_R) R_prev = R and S_prev = S.  On success R moves, (R_prev, S_prev) <- (R, S) and
+ * the counter advances; on failure (VMC_ENOTSPD, VMC_EINVAL) nothing changes.  VMC_EINVAL too if
+ * R, the estimate or S is missing. */
+int vmc_traj_langevin_step(vmc_traj* traj, double T, double Delta, double alpha, unsigned flags);
 
 /* The rotating-spring toy model (SI, "A simple toy model"; main text, figure of the toy
  * model): U = k (|x| - a)^2 / 2 in the plane; S = G_lambda (radial eigenvalue 1/lambda,
@@ -235,7 +277,8 @@ int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R_dev, c
 /* a1 (host helper): Hueckel MO coefficients on the periodic s-Gaussians.
  * Overlap S_ab of the periodic Gaussians, H = -S_ab / sqrt(S_aa S_bb), its N/2
  * lowest eigenvectors v (symmetric QR iteration), C_ak = v_ak / sqrt(S_aa).
- * R, zeta: host (3N, N); C_out: host N x N/2. */
+ * R, zeta: host (3N, N); C_out: host N x N/2.  VMC_EINVAL for a non-finite R or zeta <= 0,
+ * VMC_ENOCONV if the QR iteration does not converge. */
 int vmc_huckel_params(int n_protons, double box_L, const double* R, const double* zeta, double* C_out);
 /* The same for the twisted basis (twist as in vmc_system): image n of the overlap sum carries
  * prod_m (+-1)^{n_m}.  twist = 0 is vmc_huckel_params; outside 0..7: VMC_EINVAL. */
@@ -296,7 +339,7 @@ void vmc_server_destroy(vmc_server* srv);
  * can never fit the budget.  *id_out identifies it in the calls below. */
 int vmc_server_submit(vmc_server* srv, const vmc_request* req, int* id_out);
 /* Removes a queued request, or stops a running one and frees its memory (waits for
- * the stream). */
+ * the stream); its state becomes VMC_REQ_CANCELLED with error VMC_ECANCELLED. */
 int vmc_server_cancel(vmc_server* srv, int id);
 /* Collects finished steps, admits, sets up the trajectories that start a step and
  * queues sweeps of every resident trajectory (returns without waiting for them):
@@ -304,7 +347,8 @@ int vmc_server_cancel(vmc_server* srv, int id);
  * for lighter buckets, in proportion. */
 int vmc_server_tick(vmc_server* srv, int* n_active, int* n_queued);
 /* state: VMC_REQ_*; error: the VMC_E* code of a failed request (singular matrix,
- * S not positive definite, ...); a failure affects that request only. */
+ * S not positive definite, a non-finite R at the start of a step, the host eigen-solver, ...);
+ * a failure affects that request only: vmc_server_tick returns an error only for HIP errors. */
 int vmc_server_status(vmc_server* srv, int id, int* state, int* steps_done, int* error);
 /* Host outputs (any may be NULL): R after the completed steps (3N), E and sigma_E
  * of every completed step, each step's latency in ms (from the step becoming

@@ -885,17 +885,17 @@ int o_langevin(int n3, double L, double* R, double* R_prev, double* S_prev,
     v[i] = f[i] - c / (2.0 * Db);
   }
   double* Lc = malloc(8 * n3 * n3);
+  double* y = malloc(8 * n3);
+  double* xi = malloc(8 * (n3 + 1));
+  double* z = malloc(8 * n3);
   int rc = o_cholesky(n3, Se, Lc);
+  double Teff = T;
   if (rc == 0) {
-    double Teff = T;
     if (flags & O_STEP_NOISE_CORR) Teff = T - Dt * Dt / (2.0 * Db);
     if (Teff < 0.0) rc = O_EINVAL;
   }
   if (rc == 0) {
     /* y = S^-1 v: L w = v, then L^T y = w. */
-    double* y = malloc(8 * n3);
-    double* xi = malloc(8 * (n3 + 1));
-    double* z = malloc(8 * n3);
     for (int i = 0; i < n3; ++i) {
       double t = v[i];
       for (int k = 0; k < i; ++k) t -= Lc[i * n3 + k] * y[k];
@@ -912,7 +912,11 @@ int o_langevin(int n3, double L, double* R, double* R_prev, double* S_prev,
       for (int k = i + 1; k < n3; ++k) t -= Lc[k * n3 + i] * z[k];
       z[i] = t / Lc[i * n3 + i];
     }
-    double Teff = (flags & O_STEP_NOISE_CORR) ? T - Dt * Dt / (2.0 * Db) : T;
+    /* a non-finite position, force or noise (NaN input) is an argument error: no change */
+    for (int i = 0; i < n3; ++i)
+      if (!isfinite(y[i]) || !isfinite(z[i]) || !isfinite(R[i]) || !isfinite(R_prev[i])) rc = O_EINVAL;
+  }
+  if (rc == 0) {
     double amp = sqrt(2.0 * Teff * Db);
     for (int i = 0; i < n3; ++i) {
       double rn = R[i] + Dt * y[i] + amp * z[i];
@@ -921,8 +925,8 @@ int o_langevin(int n3, double L, double* R, double* R_prev, double* S_prev,
       R[i] = rn;
     }
     memcpy(S_prev, S, 8 * n3 * n3);
-    free(y); free(xi); free(z);
   }
+  free(y); free(xi); free(z);
   free(Se); free(Sp); free(v); free(dR); free(Lc);
   return rc;
 }

@@ -1,0 +1,268 @@
+// Host-only parts of the library (see host.hpp): reciprocal vectors, the admission rule,
+// the Hueckel eigen-solver and the checkpoint format.
+#include "host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace vmc_host {
+
+// Half-space reciprocal vectors grouped by (ny, nz), nx innermost.
+// Half-space k = 2 pi n / L, 0 < |n|^2 <= nmax^2, grouped in (ny, nz) slots with nx
+// innermost; the slot list is sorted by nx range (longest first, stable) so that
+// the reciprocal-space lanes of a wave get slots of about equal length.
+void build_kvectors(const vmc_system& s, std::vector<double>& kv, std::vector<int>& slots_out,
+                    std::vector<int>& nx0_out) {
+  const int nm = s.ewald_nmax;
+  const double L = s.box_L, V = L * L * L, kap = s.ewald_kappa, tp = 2.0 * M_PI / L;
+  std::vector<int> slots, nx0;
+  int k = 0;
+  for (int ny = -nm; ny <= nm; ++ny)
+    for (int nz = -nm; nz <= nm; ++nz) {
+      const int r2 = ny * ny + nz * nz;
+      if (r2 > nm * nm) continue;
+      int nxmax = 0;
+      while ((nxmax + 1) * (nxmax + 1) + r2 <= nm * nm) ++nxmax;
+      const bool pos_half = (ny > 0) || (ny == 0 && nz > 0);
+      const int nxmin = pos_half ? 0 : 1;
+      if (nxmin > nxmax) continue;
+      slots.push_back(ny);
+      slots.push_back(nz);
+      slots.push_back(k);
+      slots.push_back(nxmax - nxmin + 1);
+      nx0.push_back(nxmin);
+      for (int nx = nxmin; nx <= nxmax; ++nx, ++k) {
+        const double kx = tp * nx, ky = tp * ny, kz = tp * nz, k2 = kx * kx + ky * ky + kz * kz;
+        kv.push_back(kx);
+        kv.push_back(ky);
+        kv.push_back(kz);
+        kv.push_back(4.0 * M_PI / V * std::exp(-k2 / (4.0 * kap * kap)) / k2);
+      }
+    }
+  std::vector<int> order(nx0.size());
+  for (size_t q = 0; q < order.size(); ++q) order[q] = (int)q;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return nx0[x] + slots[4 * x + 3] > nx0[y] + slots[4 * y + 3];
+  });
+  slots_out.clear();
+  nx0_out.clear();
+  for (int q : order) {
+    for (int c = 0; c < 4; ++c) slots_out.push_back(slots[4 * q + c]);
+    nx0_out.push_back(nx0[q]);
+  }
+}
+
+int admit_count(size_t budget, size_t resident, int n, const size_t* bytes) {
+  int k = 0;
+  for (; k < n; ++k) {
+    if (bytes[k] > budget || resident > budget - bytes[k]) break;
+    resident += bytes[k];
+  }
+  return k;
+}
+
+// ------------------------------------------------------------ checkpoint --
+static constexpr char kCkptMagic[8] = {'V', 'M', 'C', 'T', 'R', 'A', 'J', '2'};
+
+size_t ckpt_payload_bytes(int n, int w) {
+  const size_t W = (size_t)w, N = (size_t)n, n3 = 3 * N;
+  return sizeof(double) * (W * N * 3 + W * (1 + 9 * N) + W * n3 + (3 + n3) + 2 * n3 + 2 * n3 * n3) +
+         sizeof(int64_t) * W;
+}
+
+void ckpt_init_header(CkptHeader* h, int n, int w) {
+  std::memset(h, 0, sizeof *h);
+  std::memcpy(h->magic, kCkptMagic, 8);
+  h->version = kCkptVersion;
+  h->n = n;
+  h->w = w;
+  h->payload_bytes = ckpt_payload_bytes(n, w);
+}
+
+// FNV-1a, 64 bit (Fowler, Noll, Vo): h = (h xor byte) * 1099511628211 from the offset basis.
+static uint64_t fnv1a(uint64_t h, const unsigned char* p, size_t n) {
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+static uint64_t ckpt_checksum(const unsigned char* buf, size_t payload) {
+  CkptHeader h;
+  std::memcpy(&h, buf, sizeof h);
+  h.checksum = 0;
+  uint64_t c = fnv1a(14695981039346656037ull, reinterpret_cast<const unsigned char*>(&h), sizeof h);
+  return fnv1a(c, buf + sizeof h, payload);
+}
+
+void ckpt_seal(void* buf) {
+  unsigned char* p = static_cast<unsigned char*>(buf);
+  CkptHeader h;
+  std::memcpy(&h, p, sizeof h);
+  h.checksum = ckpt_checksum(p, h.payload_bytes);
+  std::memcpy(p, &h, sizeof h);
+}
+
+int ckpt_validate(const void* buf, size_t len, CkptHeader* out) {
+  if (!buf || len < sizeof(CkptHeader)) return VMC_EINVAL;
+  const unsigned char* p = static_cast<const unsigned char*>(buf);
+  CkptHeader h;
+  std::memcpy(&h, p, sizeof h);
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != kCkptVersion) return VMC_EINVAL;
+  if (h.n < 2 || h.n > 4096 || h.w < 1) return VMC_EINVAL;
+  if (h.payload_bytes != ckpt_payload_bytes(h.n, h.w) || len - sizeof h < h.payload_bytes) return VMC_EINVAL;
+  if (ckpt_checksum(p, h.payload_bytes) != h.checksum) return VMC_EINVAL;
+  if (out) *out = h;
+  return VMC_OK;
+}
+
+}  // namespace vmc_host
+
+using namespace vmc_host;
+
+// ---------------------------------------------------------------- Hueckel --
+// Symmetric eigen-decomposition A = Q T Q^T: Householder reflections reduce A
+// to tridiagonal T, then implicit QR steps with a Wilkinson shift (Givens
+// rotations chasing the bulge, deflation of negligible sub-diagonals) drive T
+// to diagonal.  Q accumulates every transformation; its columns are eigenvectors.
+static void householder_tridiag(int n, std::vector<double>& A, std::vector<double>& Q) {
+  Q.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  std::vector<double> v(n), p(n), w(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1, o = k + 1;
+    const double x0 = A[(size_t)o * n + k];
+    double sigma = 0.0;
+    for (int i = 1; i < m; ++i) sigma += A[(size_t)(o + i) * n + k] * A[(size_t)(o + i) * n + k];
+    if (sigma == 0.0) continue;
+    const double mu = std::sqrt(x0 * x0 + sigma);
+    const double v0 = (x0 <= 0.0) ? x0 - mu : -sigma / (x0 + mu);
+    const double beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
+    v[0] = 1.0;
+    for (int i = 1; i < m; ++i) v[i] = A[(size_t)(o + i) * n + k] / v0;
+    double pv = 0.0;
+    for (int i = 0; i < m; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += A[(size_t)(o + i) * n + o + j] * v[j];
+      p[i] = beta * acc;
+      pv += p[i] * v[i];
+    }
+    for (int i = 0; i < m; ++i) w[i] = p[i] - 0.5 * beta * pv * v[i];
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) A[(size_t)(o + i) * n + o + j] -= v[i] * w[j] + w[i] * v[j];
+    A[(size_t)o * n + k] = A[(size_t)k * n + o] = mu;
+    for (int i = 1; i < m; ++i) A[(size_t)(o + i) * n + k] = A[(size_t)k * n + o + i] = 0.0;
+    for (int r = 0; r < n; ++r) {
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += Q[(size_t)r * n + o + j] * v[j];
+      for (int j = 0; j < m; ++j) Q[(size_t)r * n + o + j] -= beta * acc * v[j];
+    }
+  }
+}
+
+static int tridiag_qr(int n, std::vector<double>& T, std::vector<double>& Q) {
+  const double eps = 2.220446049250313e-16;
+  auto small = [&](int i) {   // sub-diagonal entry (i, i-1) negligible?
+    return std::fabs(T[(size_t)i * n + i - 1]) <=
+           eps * (std::fabs(T[(size_t)i * n + i]) + std::fabs(T[(size_t)(i - 1) * n + i - 1]));
+  };
+  auto rot = [&](int k, int lo, int hi, double c, double s) {
+    const int j0 = std::max(lo, k - 1), j1 = std::min(hi, k + 2);
+    for (int j = j0; j <= j1; ++j) {
+      const double t1 = T[(size_t)k * n + j], t2 = T[(size_t)(k + 1) * n + j];
+      T[(size_t)k * n + j] = c * t1 + s * t2;
+      T[(size_t)(k + 1) * n + j] = -s * t1 + c * t2;
+    }
+    for (int i = j0; i <= j1; ++i) {
+      const double t1 = T[(size_t)i * n + k], t2 = T[(size_t)i * n + k + 1];
+      T[(size_t)i * n + k] = c * t1 + s * t2;
+      T[(size_t)i * n + k + 1] = -s * t1 + c * t2;
+    }
+    for (int i = 0; i < n; ++i) {
+      const double t1 = Q[(size_t)i * n + k], t2 = Q[(size_t)i * n + k + 1];
+      Q[(size_t)i * n + k] = c * t1 + s * t2;
+      Q[(size_t)i * n + k + 1] = -s * t1 + c * t2;
+    }
+  };
+  int hi = n - 1, iter = 0;
+  while (hi > 0) {
+    if (++iter > 60 * n) return VMC_ENOCONV;
+    if (small(hi)) {
+      T[(size_t)hi * n + hi - 1] = T[(size_t)(hi - 1) * n + hi] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && !small(lo)) --lo;
+    if (lo > 0) T[(size_t)lo * n + lo - 1] = T[(size_t)(lo - 1) * n + lo] = 0.0;
+    const double a = T[(size_t)(hi - 1) * n + hi - 1], b = T[(size_t)hi * n + hi - 1], c = T[(size_t)hi * n + hi];
+    const double dd = 0.5 * (a - c);
+    const double mu = c - b * b / (dd + (dd >= 0.0 ? 1.0 : -1.0) * std::hypot(dd, b));
+    double x = T[(size_t)lo * n + lo] - mu, z = T[(size_t)(lo + 1) * n + lo];
+    for (int k = lo; k < hi; ++k) {
+      if (k > lo) {
+        x = T[(size_t)k * n + k - 1];
+        z = T[(size_t)(k + 1) * n + k - 1];
+      }
+      const double r = std::hypot(x, z);
+      const double cs = r == 0.0 ? 1.0 : x / r, sn = r == 0.0 ? 0.0 : z / r;
+      rot(k, lo, hi, cs, sn);
+      if (k > lo) T[(size_t)(k + 1) * n + k - 1] = T[(size_t)(k - 1) * n + k + 1] = 0.0;
+    }
+  }
+  return VMC_OK;
+}
+
+extern "C" int vmc_huckel_params(int n, double L, const double* R, const double* zeta, double* C_out) {
+  return vmc_huckel_params_twist(n, L, 0, R, zeta, C_out);
+}
+
+extern "C" int vmc_huckel_params_twist(int n, double L, int twist, const double* R, const double* zeta, double* C_out) {
+  if (n < 2 || (n & 1) || !(L > 0.0) || !R || !zeta || !C_out || twist < 0 || twist > 7) return VMC_EINVAL;
+  for (int i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(R[i])) return VMC_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!(zeta[i] > 0.0) || !std::isfinite(zeta[i])) return VMC_EINVAL;
+  std::vector<double> S((size_t)n * n), H((size_t)n * n), Q;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const double za = zeta[a], zb = zeta[b], mu = za * zb / (za + zb);
+      double v = std::pow(M_PI / (za + zb), 1.5);
+      for (int ax = 0; ax < 3; ++ax) {
+        // minimum image dd - m L; with the twist angle pi image k weighs (-1)^k and the
+        // sum at the raw offset is (-1)^m times the one at the minimum image
+        const double tau = ((twist >> ax) & 1) ? -1.0 : 1.0;
+        double dd = R[3 * a + ax] - R[3 * b + ax];
+        const double m = std::floor(dd / L + 0.5);
+        dd -= L * m;
+        double s = 0.0;
+        for (int k = -3; k <= 3; ++k) s += ((k & 1) ? tau : 1.0) * std::exp(-mu * (dd + k * L) * (dd + k * L));
+        if (((long long)m) & 1) s *= tau;
+        v *= s;
+      }
+      S[(size_t)a * n + b] = v;
+    }
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b)
+      H[(size_t)a * n + b] = -S[(size_t)a * n + b] / std::sqrt(S[(size_t)a * n + a] * S[(size_t)b * n + b]);
+  householder_tridiag(n, H, Q);
+  int rc = tridiag_qr(n, H, Q);
+  if (rc) return rc;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return H[(size_t)x * n + x] < H[(size_t)y * n + y]; });
+  const int no = n / 2;
+  for (int k = 0; k < no; ++k)
+    for (int a = 0; a < n; ++a)
+      C_out[(size_t)a * no + k] = Q[(size_t)a * n + order[k]] / std::sqrt(S[(size_t)a * n + a]);
+  return VMC_OK;
+}
+
+
+extern "C" int vmc_server_admit_count(size_t budget, size_t resident, int n_queued, const size_t* bytes) {
+  if (n_queued < 0 || (n_queued > 0 && !bytes)) return -1;
+  return admit_count(budget, resident, n_queued, bytes);
+}

@@ -262,6 +262,14 @@ __global__ __launch_bounds__(1024) void k_langevin(int n3, double L, double* R, 
     for (int i = t; i < k; i += nt) z[i] -= Lw[(size_t)k * n3 + i] * zk;
     __syncthreads();
   }
+  // a non-finite position, force, S-difference term or noise is an argument error: the state stays
+  for (int i = t; i < n3; i += nt)
+    if (!isfinite(y[i]) || !isfinite(z[i]) || !isfinite(R[i]) || !isfinite(R_prev[i])) fail = 1;
+  __syncthreads();
+  if (fail) {
+    if (t == 0) *status = 1;
+    return;
+  }
   const double amp = sqrt(2.0 * Teff * Db);
   for (int i = t; i < n3; i += nt) {
     double rn = R[i] + Dt * y[i] + amp * z[i];

@@ -118,11 +118,13 @@ __global__ __launch_bounds__(256) void k_invert(WalkerArgs a, int spin_lo, int s
       if (pv == 0.0) { singular = true; break; }
       logdet += log(fabs(pv));
       if (pv < 0.0) sgn = -sgn;
-      const double pinv = 1.0 / pv;
       const bool me = lane == piv;
       if (me) { used = true; myk = p; }
       if (lane == p) mypi = piv;
-      const double g = (me ? (pv - 1.0) : rp) * pinv;
+      // multiplier by division, not by the reciprocal: a row equal to the pivot row gets g = 1
+      // exactly and becomes exactly zero, so an exactly singular matrix (two same-spin electrons
+      // at one point) meets an exactly zero pivot
+      const double g = (me ? (pv - 1.0) : rp) / pv;
       const double diag = (me ? 1.0 : 0.0) - g;
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -262,7 +264,7 @@ __global__ __launch_bounds__(256, 2) void k_invert_big(WalkerArgs a, int spin_lo
       if (me) { used = true; myk = p; }
       if (h == 0 && r == p) { pi_s[p] = piv; pv_s[p] = pv; }
       if (h == ph) {
-        gcol[r] = (me ? (pv - 1.0) : rp) * (1.0 / pv);
+        gcol[r] = (me ? (pv - 1.0) : rp) / pv;        // by division: equal rows cancel exactly
         const double dv = me ? 1.0 : 0.0;
 #pragma unroll
         for (int j = 0; j < BC; ++j) x[lb][j] = (j == q) ? dv : x[lb][j];

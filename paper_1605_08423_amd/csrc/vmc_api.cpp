@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -14,9 +15,12 @@
 #include <vector>
 
 #include "../../include/vmc.h"
+#include "host.hpp"
 #include "kernels.hpp"
 
 using namespace vmc;
+using vmc_host::admit_count;
+using vmc_host::build_kvectors;
 
 namespace {
 
@@ -26,6 +30,9 @@ const char* kClassName[K_NCLASS] = {"proton_setup", "build_A", "invert", "refine
                                     "slater_sample", "finalize", "reduce", "syrk", "langevin", "toy"};
 
 struct Pending { int cls; hipEvent_t a, b; };
+// vmc_energy_forces keeps at most this many sweeps queued ahead of the device, so that
+// a cancellation takes effect within that many sweeps.
+constexpr int kWindow = 8;
 
 }  // namespace
 
@@ -42,6 +49,9 @@ struct vmc_ctx {
   size_t lang_work_n = 0;
   double* syrk_work = nullptr;
   size_t syrk_work_n = 0;
+  size_t budget = 0, in_use = 0;   // HBM budget of the trajectories (0 = none), bytes they hold
+  std::atomic<int> cancel{0};     // set by vmc_cancel (any thread), consumed by vmc_energy_forces
+  hipEvent_t window[kWindow] = {nullptr};   // sweeps in flight, see vmc_energy_forces
 };
 
 struct vmc_traj {
@@ -57,6 +67,13 @@ struct vmc_traj {
   int* qflag = nullptr;           // W + 2: per-walker non-finite flags, then the quarantine counts
   int n_reset = 0;                // walkers re-initialised at the start of the last vmc_energy_forces
   unsigned char* scr = nullptr;   // per-walker scratch of the measurement kernel (N_sigma > 64)
+  double* pos_bak = nullptr;      // walker positions at the start of the running call (restored on failure)
+  int64_t* nacc_bak = nullptr;    // accepted-move counts of the previous call (restored on failure)
+  // Langevin state owned by the trajectory (vmc_traj_set_R, vmc_traj_langevin_step)
+  double *Rd = nullptr, *Rprev = nullptr, *Sd = nullptr, *Sprev = nullptr;
+  size_t bytes = 0;               // device bytes (traj_bytes), counted against the context's budget
+  uint32_t lang_step = 0;         // completed vmc_traj_langevin_step calls (the noise counter)
+  bool have_R = false, have_prev = false, have_S = false;
   // Ewald tables
   int nk = 0, nslot = 0;
   double *kvec = nullptr, *rho_p = nullptr, *Ptab = nullptr, *Fconst = nullptr, *Vpp = nullptr;
@@ -151,51 +168,6 @@ int check_sys(const vmc_system* s) {
   return VMC_OK;
 }
 
-// Half-space reciprocal vectors grouped by (ny, nz), nx innermost.
-// Half-space k = 2 pi n / L, 0 < |n|^2 <= nmax^2, grouped in (ny, nz) slots with nx
-// innermost; the slot list is sorted by nx range (longest first, stable) so that
-// the reciprocal-space lanes of a wave get slots of about equal length.
-void build_kvectors(const vmc_system& s, std::vector<double>& kv, std::vector<int>& slots_out,
-                    std::vector<int>& nx0_out) {
-  const int nm = s.ewald_nmax;
-  const double L = s.box_L, V = L * L * L, kap = s.ewald_kappa, tp = 2.0 * M_PI / L;
-  std::vector<int> slots, nx0;
-  int k = 0;
-  for (int ny = -nm; ny <= nm; ++ny)
-    for (int nz = -nm; nz <= nm; ++nz) {
-      const int r2 = ny * ny + nz * nz;
-      if (r2 > nm * nm) continue;
-      int nxmax = 0;
-      while ((nxmax + 1) * (nxmax + 1) + r2 <= nm * nm) ++nxmax;
-      const bool pos_half = (ny > 0) || (ny == 0 && nz > 0);
-      const int nxmin = pos_half ? 0 : 1;
-      if (nxmin > nxmax) continue;
-      slots.push_back(ny);
-      slots.push_back(nz);
-      slots.push_back(k);
-      slots.push_back(nxmax - nxmin + 1);
-      nx0.push_back(nxmin);
-      for (int nx = nxmin; nx <= nxmax; ++nx, ++k) {
-        const double kx = tp * nx, ky = tp * ny, kz = tp * nz, k2 = kx * kx + ky * ky + kz * kz;
-        kv.push_back(kx);
-        kv.push_back(ky);
-        kv.push_back(kz);
-        kv.push_back(4.0 * M_PI / V * std::exp(-k2 / (4.0 * kap * kap)) / k2);
-      }
-    }
-  std::vector<int> order(nx0.size());
-  for (size_t q = 0; q < order.size(); ++q) order[q] = (int)q;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return nx0[x] + slots[4 * x + 3] > nx0[y] + slots[4 * y + 3];
-  });
-  slots_out.clear();
-  nx0_out.clear();
-  for (int q : order) {
-    for (int c = 0; c < 4; ++c) slots_out.push_back(slots[4 * q + c]);
-    nx0_out.push_back(nx0[q]);
-  }
-}
-
 // Gaussian images kept per axis: all three (n = -1, 0, 1) unless the mode is mixed and
 // every dropped image is below e^{-zeta_min (L/2)^2} <= e^{-23} (under FP32 resolution).
 int image_rule(const vmc_system& s, const double* zeta_host) {
@@ -281,11 +253,26 @@ int measure(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e) {
   return VMC_OK;
 }
 
+// Device bytes vmc_traj_create allocates for this system and walker count.
+size_t traj_bytes(const vmc_system& s, int W) {
+  std::vector<double> kv;
+  std::vector<int> slots, nx0;
+  build_kvectors(s, kv, slots, nx0);
+  const size_t N = s.n_protons, NS = N / 2, n3 = 3 * N, nk = kv.size() / 4, Wz = W;
+  const size_t d = 2 * Wz * N * 3 + 2 * Wz * 2 * NS * NS + 2 * Wz * 2 + Wz * (2 + 9 * N) + Wz * nk * 2 + Wz +
+                   Wz * n3 + Wz + Wz * (1 + 3 * n3) + Wz * n3 + reduce_partial_doubles(W, (int)n3) + 3 + n3 +
+                   kv.size() + 2 * nk + nk * N * 2 + n3 + 1 + 2 * n3 + 2 * n3 * n3;
+  return d * sizeof(double) + 2 * Wz * sizeof(int64_t) + (3 * Wz + 2 + slots.size() + nx0.size()) * sizeof(int) +
+         Wz * slater_scratch_bytes((int)NS, s.precision == VMC_MIXED);
+}
+
 void free_traj(vmc_traj* t) {
   if (!t) return;
+  if (t->ctx) t->ctx->in_use -= t->bytes;
   void* ptrs[] = {t->pos, t->Amat, t->Binv, t->ldet, t->sgn, t->acc, t->rho_acc, t->Vs, t->dVs, t->Uj,
                   t->means, t->f_w, t->partial, t->outv, t->nacc, t->kvec, t->rho_p, t->Ptab, t->Fconst,
-                  t->Vpp, t->slot, t->slot_nx0, t->rflag, t->qflag, t->scr};
+                  t->Vpp, t->slot, t->slot_nx0, t->rflag, t->qflag, t->scr, t->pos_bak, t->nacc_bak,
+                  t->Rd, t->Rprev, t->Sd, t->Sprev};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete t;
@@ -304,6 +291,8 @@ const char* vmc_strerror(int code) {
     case VMC_ESINGULAR: return "singular Slater matrix at an inverse refresh";
     case VMC_EDEVICE: return "HIP runtime error";
     case VMC_ENOTBUILT: return "no device code for this GPU";
+    case VMC_ECANCELLED: return "cancelled";
+    case VMC_ENOCONV: return "host eigen-solver did not converge";
     default: return "unknown error";
   }
 }
@@ -333,7 +322,32 @@ void vmc_destroy(vmc_ctx* c) {
   if (c->d_status) (void)hipFree(c->d_status);
   if (c->lang_work) (void)hipFree(c->lang_work);
   if (c->syrk_work) (void)hipFree(c->syrk_work);
+  for (hipEvent_t e : c->window)
+    if (e) (void)hipEventDestroy(e);
   delete c;
+}
+
+int vmc_cancel(vmc_ctx* c) {
+  if (!c) return VMC_EINVAL;
+  c->cancel.store(1);
+  return VMC_OK;
+}
+
+int vmc_set_hbm_budget(vmc_ctx* c, size_t bytes) {
+  if (!c) return VMC_EINVAL;
+  c->budget = bytes;
+  return VMC_OK;
+}
+
+int vmc_hbm_in_use(vmc_ctx* c, size_t* in_use) {
+  if (!c || !in_use) return VMC_EINVAL;
+  *in_use = c->in_use;
+  return VMC_OK;
+}
+
+size_t vmc_traj_bytes(const vmc_system* sys, int W) {
+  if (check_sys(sys) || W < 1) return 0;
+  return traj_bytes(*sys, W);
 }
 
 int vmc_set_stream(vmc_ctx* c, void* s) {
@@ -374,9 +388,13 @@ int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int W, uint32_t seed, u
   int rc = check_sys(sys);
   if (rc) return rc;
   HIPCHK(hipSetDevice(ctx->device));
+  const size_t bytes = traj_bytes(*sys, W);
+  if (ctx->budget && ctx->in_use + bytes > ctx->budget) return VMC_ENOMEM;
   vmc_traj* t = new (std::nothrow) vmc_traj();
   if (!t) return VMC_ENOMEM;
   t->ctx = ctx; t->sys = *sys; t->W = W; t->N = sys->n_protons; t->NS = t->N / 2;
+  t->bytes = bytes;
+  ctx->in_use += bytes;
   t->seed = seed; t->traj_id = traj_id;
   std::vector<double> kv;
   std::vector<int> slots, nx0;
@@ -395,14 +413,21 @@ int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int W, uint32_t seed, u
             !dalloc(&t->nacc, (size_t)W) && !dalloc(&t->rflag, (size_t)W * 2) && !dalloc(&t->qflag, (size_t)W + 2) &&
             !dalloc(&t->kvec, kv.size()) && !dalloc(&t->rho_p, 2 * t->nk) &&
             !dalloc(&t->Ptab, (size_t)t->nk * N * 2) && !dalloc(&t->Fconst, n3) && !dalloc(&t->Vpp, 1) &&
-            !dalloc(&t->slot, slots.size()) && !dalloc(&t->slot_nx0, nx0.size());
+            !dalloc(&t->slot, slots.size()) && !dalloc(&t->slot_nx0, nx0.size()) &&
+            !dalloc(&t->pos_bak, W * N * 3) && !dalloc(&t->nacc_bak, (size_t)W) && !dalloc(&t->Rd, n3) &&
+            !dalloc(&t->Rprev, n3) && !dalloc(&t->Sd, n3 * n3) && !dalloc(&t->Sprev, n3 * n3);
   const size_t scr = slater_scratch_bytes(t->NS, sys->precision == VMC_MIXED);
   if (ok && scr) ok = !dalloc(&t->scr, (size_t)W * scr);
   if (!ok) { free_traj(t); return VMC_ENOMEM; }
   if (hipMemcpy(t->kvec, kv.data(), kv.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(t->slot, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(t->slot_nx0, nx0.data(), nx0.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(t->nacc, 0, W * sizeof(int64_t)) != hipSuccess) {
+      hipMemset(t->nacc, 0, W * sizeof(int64_t)) != hipSuccess ||
+      hipMemset(t->Rd, 0, n3 * sizeof(double)) != hipSuccess ||
+      hipMemset(t->Rprev, 0, n3 * sizeof(double)) != hipSuccess ||
+      hipMemset(t->Sd, 0, n3 * n3 * sizeof(double)) != hipSuccess ||
+      hipMemset(t->Sprev, 0, n3 * n3 * sizeof(double)) != hipSuccess ||
+      hipMemset(t->outv, 0, (3 + n3) * sizeof(double)) != hipSuccess) {
     free_traj(t);
     return VMC_EDEVICE;
   }
@@ -419,19 +444,22 @@ int vmc_traj_set_walkers(vmc_traj* t, const double* pos_dev) {
   return VMC_OK;
 }
 
-// Checkpoint layout: CkptHeader, then pos (W x N x 3), means (W x (1 + 9N)), f_w (W x 3N) as
-// doubles and nacc (W) as int64, all in host byte order.
-struct CkptHeader {
-  char magic[8];
-  uint32_t version, seed, traj_id;
-  int32_t n, w, precision, nmax, twist, have_means;
-  double box_L, kappa, a_par, a_anti, b, j1_b1;
-};
-static constexpr char kCkptMagic[8] = {'V', 'M', 'C', 'T', 'R', 'A', 'J', '1'};
-
+// Checkpoint format: vmc_host::CkptHeader and its payload (host.hpp), sealed by a checksum.
 static size_t ckpt_bytes(const vmc_traj* t) {
-  const size_t W = t->W, N = t->N;
-  return sizeof(CkptHeader) + sizeof(double) * (W * N * 3 + W * (1 + 9 * N) + W * 3 * N) + sizeof(int64_t) * W;
+  return sizeof(vmc_host::CkptHeader) + vmc_host::ckpt_payload_bytes(t->N, t->W);
+}
+
+// The device arrays of the payload in their order, with their sizes in bytes (the
+// accepted-move counts come last).
+static int ckpt_parts(vmc_traj* t, double* ptr[7], size_t nb[7]) {
+  const size_t W = t->W, N = t->N, n3 = 3 * N;
+  double* p[7] = {t->pos, t->means, t->f_w, t->outv, t->Rd, t->Rprev, t->Sd};
+  const size_t b[7] = {W * N * 3, W * (1 + 9 * N), W * n3, 3 + n3, n3, n3, n3 * n3};
+  for (int k = 0; k < 7; ++k) {
+    ptr[k] = p[k];
+    nb[k] = b[k] * sizeof(double);
+  }
+  return 7;
 }
 
 int vmc_traj_save(vmc_traj* t, void* buf, size_t* len) {
@@ -441,36 +469,41 @@ int vmc_traj_save(vmc_traj* t, void* buf, size_t* len) {
   if (*len < need) { *len = need; return VMC_EINVAL; }
   HIPCHK(hipSetDevice(t->ctx->device));
   HIPCHK(hipStreamSynchronize(t->ctx->stream));
-  CkptHeader h{};
-  std::memcpy(h.magic, kCkptMagic, 8);
-  h.version = 1; h.seed = t->seed; h.traj_id = t->traj_id;
-  h.n = t->N; h.w = t->W; h.precision = t->sys.precision; h.nmax = t->sys.ewald_nmax; h.twist = t->sys.twist;
-  h.have_means = t->have_means ? 1 : 0;
+  vmc_host::CkptHeader h;
+  vmc_host::ckpt_init_header(&h, t->N, t->W);
+  h.seed = t->seed; h.traj_id = t->traj_id; h.lang_step = t->lang_step;
+  h.precision = t->sys.precision; h.nmax = t->sys.ewald_nmax; h.twist = t->sys.twist;
+  h.have_means = t->have_means; h.have_R = t->have_R; h.have_prev = t->have_prev; h.have_S = t->have_S;
   h.box_L = t->sys.box_L; h.kappa = t->sys.ewald_kappa; h.a_par = t->sys.a_par; h.a_anti = t->sys.a_anti;
   h.b = t->sys.b; h.j1_b1 = t->sys.j1_b1;
   unsigned char* p = static_cast<unsigned char*>(buf);
   std::memcpy(p, &h, sizeof h);
   p += sizeof h;
-  const size_t W = t->W, N = t->N;
-  const size_t nb[3] = {W * N * 3 * sizeof(double), W * (1 + 9 * N) * sizeof(double), W * 3 * N * sizeof(double)};
-  const void* src[3] = {t->pos, t->means, t->f_w};
-  for (int k = 0; k < 3; ++k) {
+  double* src[7];
+  size_t nb[7];
+  const int np = ckpt_parts(t, src, nb);
+  for (int k = 0; k < np; ++k) {
     HIPCHK(hipMemcpy(p, src[k], nb[k], hipMemcpyDeviceToHost));
     p += nb[k];
   }
-  HIPCHK(hipMemcpy(p, t->nacc, W * sizeof(int64_t), hipMemcpyDeviceToHost));
+  // S_prev sits between S and the counts in the payload
+  const size_t n3 = 3 * (size_t)t->N;
+  HIPCHK(hipMemcpy(p, t->Sprev, n3 * n3 * sizeof(double), hipMemcpyDeviceToHost));
+  p += n3 * n3 * sizeof(double);
+  HIPCHK(hipMemcpy(p, t->nacc, (size_t)t->W * sizeof(int64_t), hipMemcpyDeviceToHost));
+  vmc_host::ckpt_seal(buf);
   *len = need;
   return VMC_OK;
 }
 
 // Shared by vmc_traj_load and vmc_traj_load_rescaled.  rescale: the checkpoint's box side may
 // differ from the trajectory's (its Ewald kappa then follows the box); walker coordinates are
-// multiplied by L / L*, and the accumulators of the old density are cleared.
+// multiplied by L / L*, the accumulators of the old density are cleared and so is the
+// Langevin state (the caller sets the scaled R).
 static int traj_load(vmc_traj* t, const void* buf, size_t len, bool rescale) {
-  if (!t || !buf || len < sizeof(CkptHeader)) return VMC_EINVAL;
-  CkptHeader h;
-  std::memcpy(&h, buf, sizeof h);
-  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1 || len < ckpt_bytes(t)) return VMC_EINVAL;
+  if (!t || !buf) return VMC_EINVAL;
+  vmc_host::CkptHeader h;
+  if (vmc_host::ckpt_validate(buf, len, &h) != VMC_OK) return VMC_EINVAL;
   const vmc_system& s = t->sys;
   if (h.n != t->N || h.w != t->W || h.precision != s.precision || h.nmax != s.ewald_nmax || h.twist != s.twist ||
       h.a_par != s.a_par || h.a_anti != s.a_anti || h.b != s.b || h.j1_b1 != s.j1_b1)
@@ -480,28 +513,35 @@ static int traj_load(vmc_traj* t, const void* buf, size_t len, bool rescale) {
   HIPCHK(hipSetDevice(t->ctx->device));
   HIPCHK(hipStreamSynchronize(t->ctx->stream));
   const unsigned char* p = static_cast<const unsigned char*>(buf) + sizeof h;
-  const size_t W = t->W, N = t->N;
-  const size_t nb[3] = {W * N * 3 * sizeof(double), W * (1 + 9 * N) * sizeof(double), W * 3 * N * sizeof(double)};
+  double* dst[7];
+  size_t nb[7];
+  const int np = ckpt_parts(t, dst, nb);
+  const size_t W = t->W, n3 = 3 * (size_t)t->N;
   if (rescale) {
     // x -> (L / L*) x keeps every coordinate in [0, L) and every walker's shape
     const double sc = s.box_L / h.box_L;
-    std::vector<double> x(W * N * 3);
+    std::vector<double> x(nb[0] / sizeof(double));
     std::memcpy(x.data(), p, nb[0]);
     for (double& v : x) v *= sc;
     HIPCHK(hipMemcpy(t->pos, x.data(), nb[0], hipMemcpyHostToDevice));
     HIPCHK(hipMemset(t->nacc, 0, W * sizeof(int64_t)));
-    t->have_means = false;
+    t->have_means = t->have_R = t->have_prev = t->have_S = false;
   } else {
-    void* dst[3] = {t->pos, t->means, t->f_w};
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < np; ++k) {
       HIPCHK(hipMemcpy(dst[k], p, nb[k], hipMemcpyHostToDevice));
       p += nb[k];
     }
+    HIPCHK(hipMemcpy(t->Sprev, p, n3 * n3 * sizeof(double), hipMemcpyHostToDevice));
+    p += n3 * n3 * sizeof(double);
     HIPCHK(hipMemcpy(t->nacc, p, W * sizeof(int64_t), hipMemcpyHostToDevice));
     t->have_means = h.have_means != 0;
+    t->have_R = h.have_R != 0;
+    t->have_prev = h.have_prev != 0;
+    t->have_S = h.have_S != 0;
   }
   t->seed = h.seed;
   t->traj_id = h.traj_id;
+  t->lang_step = h.lang_step;
   return VMC_OK;
 }
 
@@ -522,14 +562,37 @@ int vmc_traj_get_walkers(vmc_traj* t, double* pos_dev) {
   return VMC_OK;
 }
 
-int vmc_energy_forces(vmc_traj* t, const double* R, const double* C, const double* zeta, int n_equil,
+// Puts the walkers and accepted-move counts back to what they were when the call started
+// (the call's failure leaves the trajectory as it found it).
+static int restore_walkers(vmc_traj* t) {
+  hipStream_t st = t->ctx->stream;
+  HIPCHK(hipMemcpyAsync(t->pos, t->pos_bak, (size_t)t->W * t->N * 3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(t->nacc, t->nacc_bak, (size_t)t->W * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return VMC_OK;
+}
+
+static int fail_restore(vmc_traj* t, int code) {
+  const int rc = restore_walkers(t);
+  return rc ? rc : code;
+}
+
+int vmc_energy_forces(vmc_traj* t, const double* R_in, const double* C, const double* zeta, int n_equil,
                       int n_sweeps, double step_delta, uint32_t step, double* out_dev) {
-  if (!t || !R || !C || !zeta || !out_dev || n_equil < 0 || n_sweeps < 1 || !(step_delta > 0.0)) return VMC_EINVAL;
+  if (!t || !C || !zeta || !out_dev || n_equil < 0 || n_sweeps < 1 || !(step_delta > 0.0)) return VMC_EINVAL;
+  if (!R_in && !t->have_R) return VMC_EINVAL;
+  const double* R = R_in ? R_in : t->Rd;
+  if (step == VMC_STEP_TRAJ) step = t->lang_step;
   vmc_ctx* ctx = t->ctx;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   const int mixed = t->sys.precision == VMC_MIXED;
   const size_t N = t->N, n3 = 3 * N, W = t->W;
+  for (hipEvent_t& e : ctx->window)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  // the state a failure restores
+  HIPCHK(hipMemcpyAsync(t->pos_bak, t->pos, W * N * 3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(t->nacc_bak, t->nacc, W * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
   // quarantine: a walker whose coordinates are not all finite restarts from a copy of the
   // next finite walker; every walker bad is an argument error (nothing is changed)
   HIPCHK(hipMemsetAsync(t->qflag + W, 0, 2 * sizeof(int), st));
@@ -537,13 +600,12 @@ int vmc_energy_forces(vmc_traj* t, const double* R, const double* C, const doubl
   int qc[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(qc, t->qflag + W, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (qc[1] > 0) return VMC_EINVAL;
-  t->n_reset = qc[0];
+  if (qc[1] > 0) return VMC_EINVAL;     // no walker was touched: the quarantine had no source
   int rc = proton_setup(t, R);
-  if (rc) return rc;
+  if (rc) return fail_restore(t, rc);
   int nimg = 1;
   rc = image_count(t, zeta, &nimg);
-  if (rc) return rc;
+  if (rc) return fail_restore(t, rc);
   HIPCHK(hipMemsetAsync(t->acc, 0, W * (2 + 9 * N) * sizeof(double), st));
   HIPCHK(hipMemsetAsync(t->rho_acc, 0, W * t->nk * 2 * sizeof(double), st));
   HIPCHK(hipMemsetAsync(t->nacc, 0, W * sizeof(int64_t), st));
@@ -556,10 +618,24 @@ int vmc_energy_forces(vmc_traj* t, const double* R, const double* C, const doubl
   const double rtol = t->sys.refine_tol == 0.0 ? 1e-7 : t->sys.refine_tol;
   const int total = n_equil + n_sweeps;
   for (int s = 0; s < total; ++s) {
+    // keep at most kWindow sweeps queued; a pending cancellation stops the call here
+    if (s >= kWindow) HIPCHK(hipEventSynchronize(ctx->window[s % kWindow]));
+    if (ctx->cancel.exchange(0)) {
+      HIPCHK(hipStreamSynchronize(st));
+      return fail_restore(t, VMC_ECANCELLED);
+    }
+    if (s == 0) {
+      // elimination for both spins (a half-sweep over one spin leaves the other spin's matrix
+      // as it is); a singular start, e.g. two same-spin electrons at one point, fails here,
+      // before any move
+      RUN(K_INVERT, launch_invert(a, 0, 2, 0, st));
+      rc = check_singular(ctx);
+      if (rc) return fail_restore(t, rc);
+    }
     for (int sp = 0; sp < 2; ++sp) {
-      if (s == 0 || rtol < 0.0) {
+      if (s > 0 && rtol < 0.0) {
         RUN(K_INVERT, launch_invert(a, sp, sp + 1, 0, st));
-      } else {
+      } else if (s > 0) {
         RUN(K_REFINE, launch_refine(a, sp, rtol, st));
         RUN(K_INVERT, launch_invert(a, sp, sp + 1, 1, st));
       }
@@ -570,12 +646,17 @@ int vmc_energy_forces(vmc_traj* t, const double* R, const double* C, const doubl
       rc = measure(t, m, e);
       if (rc) return rc;
     }
+    HIPCHK(hipEventRecord(ctx->window[s % kWindow], st));
   }
+  // a zero pivot at a later refresh: nothing of this call is kept
+  rc = check_singular(ctx);
+  if (rc) return fail_restore(t, rc);
   RUN(K_FINALIZE, launch_finalize(m, e, n_sweeps, t->means, st));
   RUN(K_REDUCE, launch_reduce((int)W, (int)n3, t->means, t->nacc, (double)N * total, t->f_w, t->partial, t->outv, st));
   HIPCHK(hipMemcpyAsync(out_dev, t->outv, (3 + n3) * sizeof(double), hipMemcpyDeviceToDevice, st));
   t->have_means = true;
-  return check_singular(ctx);
+  t->have_S = false;
+  return VMC_OK;
 }
 
 int vmc_traj_walker_means(vmc_traj* t, double* means_dev) {
@@ -623,8 +704,36 @@ int vmc_build_S_raw(vmc_ctx* ctx, int W, int n3, const double* f_w, const double
 }
 
 int vmc_build_S(vmc_traj* t, double* S) {
-  if (!t || !S || !t->have_means) return VMC_EINVAL;
-  return vmc_build_S_raw(t->ctx, t->W, 3 * t->N, t->f_w, t->outv + 3, S);
+  if (!t || !t->have_means) return VMC_EINVAL;
+  const int n3 = 3 * t->N;
+  int rc = vmc_build_S_raw(t->ctx, t->W, n3, t->f_w, t->outv + 3, t->Sd);
+  if (rc) return rc;
+  t->have_S = true;
+  if (S)
+    HIPCHK(hipMemcpyAsync(S, t->Sd, (size_t)n3 * n3 * sizeof(double), hipMemcpyDeviceToDevice, t->ctx->stream));
+  return VMC_OK;
+}
+
+int vmc_traj_set_R(vmc_traj* t, const double* R_dev) {
+  if (!t || !R_dev) return VMC_EINVAL;
+  HIPCHK(hipSetDevice(t->ctx->device));
+  HIPCHK(hipMemcpyAsync(t->Rd, R_dev, 3 * (size_t)t->N * sizeof(double), hipMemcpyDeviceToDevice, t->ctx->stream));
+  t->have_R = true;
+  t->have_prev = false;
+  return VMC_OK;
+}
+
+int vmc_traj_get_R(vmc_traj* t, double* R_dev) {
+  if (!t || !R_dev || !t->have_R) return VMC_EINVAL;
+  HIPCHK(hipSetDevice(t->ctx->device));
+  HIPCHK(hipMemcpyAsync(R_dev, t->Rd, 3 * (size_t)t->N * sizeof(double), hipMemcpyDeviceToDevice, t->ctx->stream));
+  return VMC_OK;
+}
+
+int vmc_traj_step_count(vmc_traj* t, uint32_t* steps) {
+  if (!t || !steps) return VMC_EINVAL;
+  *steps = t->lang_step;
+  return VMC_OK;
 }
 
 int vmc_langevin_step(vmc_ctx* ctx, int n3, double L, double* R, double* R_prev, double* S_prev, const double* f,
@@ -649,6 +758,29 @@ int vmc_langevin_step(vmc_ctx* ctx, int n3, double L, double* R, double* R_prev,
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (st == 3) return VMC_ENOTSPD;
   if (st == 1) return VMC_EINVAL;
+  return VMC_OK;
+}
+
+int vmc_traj_langevin_step(vmc_traj* t, double T, double Delta, double alpha, unsigned flags) {
+  if (!t || !t->have_R || !t->have_means || (!t->have_S && !(flags & VMC_STEP_CFOLD))) return VMC_EINVAL;
+  vmc_ctx* ctx = t->ctx;
+  const int n3 = 3 * t->N;
+  HIPCHK(hipSetDevice(ctx->device));
+  if (!t->have_S) {
+    // S = I replaces S (VMC_STEP_CFOLD); keep the stored matrix finite for S_prev
+    HIPCHK(hipMemsetAsync(t->Sd, 0, (size_t)n3 * n3 * sizeof(double), ctx->stream));
+  }
+  if (!t->have_prev) {
+    // first step of the trajectory: R_prev = R, S_prev = S
+    HIPCHK(hipMemcpyAsync(t->Rprev, t->Rd, n3 * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(t->Sprev, t->Sd, (size_t)n3 * n3 * sizeof(double), hipMemcpyDeviceToDevice,
+                          ctx->stream));
+  }
+  const int rc = vmc_langevin_step(ctx, n3, t->sys.box_L, t->Rd, t->Rprev, t->Sprev, t->outv + 3, t->Sd, T, Delta,
+                                   alpha, flags, t->seed, t->traj_id, t->lang_step);
+  if (rc) return rc;
+  t->have_prev = true;
+  t->lang_step += 1;
   return VMC_OK;
 }
 
@@ -698,141 +830,6 @@ int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R, const
   (void)hipStreamSynchronize(st);
   vmc_traj_destroy(t);
   return rc;
-}
-
-// ---------------------------------------------------------------- Hueckel --
-// Symmetric eigen-decomposition A = Q T Q^T: Householder reflections reduce A
-// to tridiagonal T, then implicit QR steps with a Wilkinson shift (Givens
-// rotations chasing the bulge, deflation of negligible sub-diagonals) drive T
-// to diagonal.  Q accumulates every transformation; its columns are eigenvectors.
-static void householder_tridiag(int n, std::vector<double>& A, std::vector<double>& Q) {
-  Q.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
-  std::vector<double> v(n), p(n), w(n);
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1, o = k + 1;
-    const double x0 = A[(size_t)o * n + k];
-    double sigma = 0.0;
-    for (int i = 1; i < m; ++i) sigma += A[(size_t)(o + i) * n + k] * A[(size_t)(o + i) * n + k];
-    if (sigma == 0.0) continue;
-    const double mu = std::sqrt(x0 * x0 + sigma);
-    const double v0 = (x0 <= 0.0) ? x0 - mu : -sigma / (x0 + mu);
-    const double beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
-    v[0] = 1.0;
-    for (int i = 1; i < m; ++i) v[i] = A[(size_t)(o + i) * n + k] / v0;
-    double pv = 0.0;
-    for (int i = 0; i < m; ++i) {
-      double acc = 0.0;
-      for (int j = 0; j < m; ++j) acc += A[(size_t)(o + i) * n + o + j] * v[j];
-      p[i] = beta * acc;
-      pv += p[i] * v[i];
-    }
-    for (int i = 0; i < m; ++i) w[i] = p[i] - 0.5 * beta * pv * v[i];
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) A[(size_t)(o + i) * n + o + j] -= v[i] * w[j] + w[i] * v[j];
-    A[(size_t)o * n + k] = A[(size_t)k * n + o] = mu;
-    for (int i = 1; i < m; ++i) A[(size_t)(o + i) * n + k] = A[(size_t)k * n + o + i] = 0.0;
-    for (int r = 0; r < n; ++r) {
-      double acc = 0.0;
-      for (int j = 0; j < m; ++j) acc += Q[(size_t)r * n + o + j] * v[j];
-      for (int j = 0; j < m; ++j) Q[(size_t)r * n + o + j] -= beta * acc * v[j];
-    }
-  }
-}
-
-static int tridiag_qr(int n, std::vector<double>& T, std::vector<double>& Q) {
-  const double eps = 2.220446049250313e-16;
-  auto small = [&](int i) {   // sub-diagonal entry (i, i-1) negligible?
-    return std::fabs(T[(size_t)i * n + i - 1]) <=
-           eps * (std::fabs(T[(size_t)i * n + i]) + std::fabs(T[(size_t)(i - 1) * n + i - 1]));
-  };
-  auto rot = [&](int k, int lo, int hi, double c, double s) {
-    const int j0 = std::max(lo, k - 1), j1 = std::min(hi, k + 2);
-    for (int j = j0; j <= j1; ++j) {
-      const double t1 = T[(size_t)k * n + j], t2 = T[(size_t)(k + 1) * n + j];
-      T[(size_t)k * n + j] = c * t1 + s * t2;
-      T[(size_t)(k + 1) * n + j] = -s * t1 + c * t2;
-    }
-    for (int i = j0; i <= j1; ++i) {
-      const double t1 = T[(size_t)i * n + k], t2 = T[(size_t)i * n + k + 1];
-      T[(size_t)i * n + k] = c * t1 + s * t2;
-      T[(size_t)i * n + k + 1] = -s * t1 + c * t2;
-    }
-    for (int i = 0; i < n; ++i) {
-      const double t1 = Q[(size_t)i * n + k], t2 = Q[(size_t)i * n + k + 1];
-      Q[(size_t)i * n + k] = c * t1 + s * t2;
-      Q[(size_t)i * n + k + 1] = -s * t1 + c * t2;
-    }
-  };
-  int hi = n - 1, iter = 0;
-  while (hi > 0) {
-    if (++iter > 60 * n) return VMC_EDEVICE;
-    if (small(hi)) {
-      T[(size_t)hi * n + hi - 1] = T[(size_t)(hi - 1) * n + hi] = 0.0;
-      --hi;
-      continue;
-    }
-    int lo = hi - 1;
-    while (lo > 0 && !small(lo)) --lo;
-    if (lo > 0) T[(size_t)lo * n + lo - 1] = T[(size_t)(lo - 1) * n + lo] = 0.0;
-    const double a = T[(size_t)(hi - 1) * n + hi - 1], b = T[(size_t)hi * n + hi - 1], c = T[(size_t)hi * n + hi];
-    const double dd = 0.5 * (a - c);
-    const double mu = c - b * b / (dd + (dd >= 0.0 ? 1.0 : -1.0) * std::hypot(dd, b));
-    double x = T[(size_t)lo * n + lo] - mu, z = T[(size_t)(lo + 1) * n + lo];
-    for (int k = lo; k < hi; ++k) {
-      if (k > lo) {
-        x = T[(size_t)k * n + k - 1];
-        z = T[(size_t)(k + 1) * n + k - 1];
-      }
-      const double r = std::hypot(x, z);
-      const double cs = r == 0.0 ? 1.0 : x / r, sn = r == 0.0 ? 0.0 : z / r;
-      rot(k, lo, hi, cs, sn);
-      if (k > lo) T[(size_t)(k + 1) * n + k - 1] = T[(size_t)(k - 1) * n + k + 1] = 0.0;
-    }
-  }
-  return VMC_OK;
-}
-
-int vmc_huckel_params(int n, double L, const double* R, const double* zeta, double* C_out) {
-  return vmc_huckel_params_twist(n, L, 0, R, zeta, C_out);
-}
-
-int vmc_huckel_params_twist(int n, double L, int twist, const double* R, const double* zeta, double* C_out) {
-  if (n < 2 || (n & 1) || !(L > 0.0) || !R || !zeta || !C_out || twist < 0 || twist > 7) return VMC_EINVAL;
-  std::vector<double> S((size_t)n * n), H((size_t)n * n), Q;
-  for (int a = 0; a < n; ++a)
-    for (int b = 0; b < n; ++b) {
-      const double za = zeta[a], zb = zeta[b], mu = za * zb / (za + zb);
-      double v = std::pow(M_PI / (za + zb), 1.5);
-      for (int ax = 0; ax < 3; ++ax) {
-        // minimum image dd - m L; with the twist angle pi image k weighs (-1)^k and the
-        // sum at the raw offset is (-1)^m times the one at the minimum image
-        const double tau = ((twist >> ax) & 1) ? -1.0 : 1.0;
-        double dd = R[3 * a + ax] - R[3 * b + ax];
-        const double m = std::floor(dd / L + 0.5);
-        dd -= L * m;
-        double s = 0.0;
-        for (int k = -3; k <= 3; ++k) s += ((k & 1) ? tau : 1.0) * std::exp(-mu * (dd + k * L) * (dd + k * L));
-        if (((long long)m) & 1) s *= tau;
-        v *= s;
-      }
-      S[(size_t)a * n + b] = v;
-    }
-  for (int a = 0; a < n; ++a)
-    for (int b = 0; b < n; ++b)
-      H[(size_t)a * n + b] = -S[(size_t)a * n + b] / std::sqrt(S[(size_t)a * n + a] * S[(size_t)b * n + b]);
-  householder_tridiag(n, H, Q);
-  int rc = tridiag_qr(n, H, Q);
-  if (rc) return rc;
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return H[(size_t)x * n + x] < H[(size_t)y * n + y]; });
-  const int no = n / 2;
-  for (int k = 0; k < no; ++k)
-    for (int a = 0; a < n; ++a)
-      C_out[(size_t)a * no + k] = Q[(size_t)a * n + order[k]] / std::sqrt(S[(size_t)a * n + a]);
-  return VMC_OK;
 }
 
 }  // extern "C"
@@ -885,32 +882,11 @@ struct BucketKey {
   }
 };
 
-// Device bytes a request holds while resident: the trajectory's walker state and
-// Ewald tables (as vmc_traj_create allocates them) plus the server's R, R_prev, S,
-// S_prev, C, zeta and status.
+// Device bytes a request holds while resident: its trajectory (vmc_traj_bytes) plus the
+// server's C, zeta and status.
 size_t request_bytes(const vmc_system& s, int W) {
-  std::vector<double> kv;
-  std::vector<int> slots, nx0;
-  build_kvectors(s, kv, slots, nx0);
-  const size_t N = s.n_protons, NS = N / 2, n3 = 3 * N, nk = kv.size() / 4, Wz = W;
-  size_t d = Wz * N * 3 + 2 * Wz * 2 * NS * NS + 2 * Wz * 2 + Wz * (2 + 9 * N) + Wz * nk * 2 + Wz + Wz * n3 + Wz +
-             Wz * (1 + 3 * n3) + Wz * n3 + reduce_partial_doubles(W, (int)n3) + 3 + n3 + kv.size() + 2 * nk +
-             nk * N * 2 + n3 + 1;
-  d += 2 * n3 + 2 * n3 * n3 + N * NS + N;                     // R, R_prev, S, S_prev, C, zeta
-  size_t b = d * sizeof(double) + Wz * sizeof(int64_t) + Wz * 2 * sizeof(int) + (Wz + 2) * sizeof(int) +
-             (slots.size() + nx0.size() + 1) * sizeof(int) +
-             Wz * slater_scratch_bytes((int)NS, s.precision == VMC_MIXED);
-  return b;
-}
-
-// Number of queue-head requests admitted: FIFO while the running total fits.
-int admit_count(size_t budget, size_t resident, int n, const size_t* bytes) {
-  int k = 0;
-  for (; k < n; ++k) {
-    if (resident + bytes[k] > budget) break;
-    resident += bytes[k];
-  }
-  return k;
+  const size_t N = s.n_protons;
+  return traj_bytes(s, W) + (N * (N / 2) + N) * sizeof(double) + 2 * sizeof(int);
 }
 
 }  // namespace
@@ -941,7 +917,8 @@ void release(vmc_server* s, Served* q) {
     q->t = nullptr;
     s->resident -= q->bytes;
   }
-  double** ds[] = {&q->R, &q->R_prev, &q->S, &q->S_prev, &q->C, &q->zeta_d};
+  q->R = q->R_prev = q->S = q->S_prev = nullptr;     // the trajectory's own arrays
+  double** ds[] = {&q->C, &q->zeta_d};
   for (double** p : ds)
     if (*p) { (void)hipFree(*p); *p = nullptr; }
   if (q->status) { (void)hipFree(q->status); q->status = nullptr; }
@@ -982,10 +959,12 @@ int admit(vmc_server* s, Served* q) {
   if (rc) return rc;
   s->resident += q->bytes;
   s->peak = std::max(s->peak, s->resident);
-  if (dalloc(&q->R, n3) || dalloc(&q->R_prev, n3) || dalloc(&q->S, (size_t)n3 * n3) ||
-      dalloc(&q->S_prev, (size_t)n3 * n3) || dalloc(&q->C, (size_t)N * NS) || dalloc(&q->zeta_d, N) ||
-      dalloc(&q->status, 2))
-    return VMC_ENOMEM;
+  // R, R_prev, S and S_prev are the trajectory's Langevin state
+  q->R = q->t->Rd;
+  q->R_prev = q->t->Rprev;
+  q->S = q->t->Sd;
+  q->S_prev = q->t->Sprev;
+  if (dalloc(&q->C, (size_t)N * NS) || dalloc(&q->zeta_d, N) || dalloc(&q->status, 2)) return VMC_ENOMEM;
   if (hipHostMalloc((void**)&q->hbuf, (n3 + 3) * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void**)&q->hC, (size_t)N * NS * sizeof(double)) != hipSuccess)
     return VMC_ENOMEM;
@@ -1014,6 +993,8 @@ int setup_step(vmc_server* s, Served* q) {
   const vmc_request& r = q->req;
   const int N = r.sys.n_protons, NS = N / 2;
   hipStream_t st = ctx->stream;
+  for (double x : q->Rh)
+    if (!std::isfinite(x)) return VMC_EINVAL;
   std::vector<double> Cv((size_t)N * NS);
   int rc = vmc_huckel_params_twist(N, r.sys.box_L, r.sys.twist, q->Rh.data(), q->zeta.data(), Cv.data());
   if (rc) return rc;
@@ -1188,11 +1169,6 @@ size_t vmc_request_bytes(const vmc_request* r) {
   return request_bytes(r->sys, r->n_walkers);
 }
 
-int vmc_server_admit_count(size_t budget, size_t resident, int n_queued, const size_t* bytes) {
-  if (n_queued < 0 || (n_queued > 0 && !bytes)) return -1;
-  return admit_count(budget, resident, n_queued, bytes);
-}
-
 int vmc_server_create(vmc_ctx* ctx, size_t hbm_budget_bytes, vmc_server** out) {
   if (!ctx || !out || hbm_budget_bytes == 0) return VMC_EINVAL;
   vmc_server* s = new (std::nothrow) vmc_server();
@@ -1262,11 +1238,13 @@ int vmc_server_cancel(vmc_server* s, int id) {
   if (q->state == SV_QUEUED) {
     s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), q), s->queue.end());
     q->state = SV_CANCELLED;
+    q->err = VMC_ECANCELLED;
   } else if (q->state == SV_RUNNING) {
     HIPCHK(hipStreamSynchronize(s->ctx->stream));   // its queued work finishes before its memory goes
     s->active.erase(std::remove(s->active.begin(), s->active.end(), q), s->active.end());
     release(s, q);
     q->state = SV_CANCELLED;
+    q->err = VMC_ECANCELLED;
   }
   return VMC_OK;
 }
@@ -1333,12 +1311,24 @@ int vmc_server_tick(vmc_server* s, int* n_active, int* n_queued) {
       s->active.push_back(q);
     }
   }
-  // 3. set-up of trajectories starting a step
-  for (Served* q : s->active)
+  // 3. set-up of trajectories starting a step.  A host-side or argument failure of one
+  // request (a non-finite R, the eigen-solver) fails that request only; HIP errors end the tick.
+  for (size_t i = 0; i < s->active.size();) {
+    Served* q = s->active[i];
     if (q->phase == PH_SETUP) {
       const int rc = setup_step(s, q);
-      if (rc) return rc;
+      if (rc == VMC_EDEVICE || rc == VMC_ENOTBUILT) return rc;
+      if (rc) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));   // none of its work may still be queued
+        q->state = SV_FAILED;
+        q->err = rc;
+        release(s, q);
+        s->active.erase(s->active.begin() + i);
+        continue;
+      }
     }
+    ++i;
+  }
   // 4. batched sweeps per bucket, then the steps that end here.  A bucket runs
   // k = clamp(c_max / c, 1, 32) sweeps per tick, c = sum of W N^2 over its
   // trajectories (their work per sweep), so a tick advances every bucket by about

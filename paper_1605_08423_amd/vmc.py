@@ -13,6 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvmc.so")
 
 VMC_OK, VMC_EINVAL, VMC_ENOMEM, VMC_ENOTSPD, VMC_ESINGULAR, VMC_EDEVICE, VMC_ENOTBUILT = 0, -1, -2, -3, -4, -5, -6
+VMC_ECANCELLED, VMC_ENOCONV = -7, -8
+VMC_STEP_TRAJ = 0xFFFFFFFF
 VMC_FP64, VMC_MIXED = 0, 1
 VMC_STEP_CFOLD, VMC_STEP_NOISE_CORR, VMC_STEP_NO_SCORR = 1, 2, 4
 
@@ -24,7 +26,9 @@ EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_
             "vmc_request_bytes", "vmc_server_admit_count", "vmc_server_create", "vmc_server_destroy",
             "vmc_server_submit", "vmc_server_cancel", "vmc_server_tick", "vmc_server_status",
             "vmc_server_result", "vmc_server_info", "vmc_toy_run", "vmc_huckel_params_twist",
-            "vmc_twist_average", "vmc_traj_save", "vmc_traj_load", "vmc_traj_load_rescaled", "vmc_traj_walkers_reset"]
+            "vmc_twist_average", "vmc_traj_save", "vmc_traj_load", "vmc_traj_load_rescaled", "vmc_traj_walkers_reset",
+            "vmc_set_hbm_budget", "vmc_hbm_in_use", "vmc_traj_bytes", "vmc_cancel", "vmc_traj_set_R", "vmc_traj_get_R",
+            "vmc_traj_step_count", "vmc_traj_langevin_step"]
 VMC_REQ_QUEUED, VMC_REQ_RUNNING, VMC_REQ_DONE, VMC_REQ_FAILED, VMC_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
@@ -107,6 +111,15 @@ def _declare(l):
     l.vmc_server_status.argtypes = [vp, i, P(i), P(i), P(i)]
     l.vmc_server_result.argtypes = [vp, i, P(d), P(d), P(d), P(d), P(d)]
     l.vmc_server_info.argtypes = [vp, P(sz), P(sz), P(i), P(i), P(C.c_longlong)]
+    l.vmc_set_hbm_budget.argtypes = [vp, sz]
+    l.vmc_hbm_in_use.argtypes = [vp, P(sz)]
+    l.vmc_traj_bytes.restype = sz
+    l.vmc_traj_bytes.argtypes = [P(vmc_system), i]
+    l.vmc_cancel.argtypes = [vp]
+    l.vmc_traj_set_R.argtypes = [vp, vp]
+    l.vmc_traj_get_R.argtypes = [vp, vp]
+    l.vmc_traj_step_count.argtypes = [vp, P(u32)]
+    l.vmc_traj_langevin_step.argtypes = [vp, d, d, d, C.c_uint]
 
 
 def _check(rc, where):
@@ -155,6 +168,18 @@ class Context:
 
     def reset_kernel_times(self):
         _check(_lib().vmc_reset_kernel_times(self.h), "vmc_reset_kernel_times")
+
+    def set_hbm_budget(self, nbytes):
+        _check(_lib().vmc_set_hbm_budget(self.h, int(nbytes)), "vmc_set_hbm_budget")
+
+    def hbm_in_use(self):
+        n = C.c_size_t(0)
+        _check(_lib().vmc_hbm_in_use(self.h, C.byref(n)), "vmc_hbm_in_use")
+        return n.value
+
+    def cancel(self):
+        """Asks the running (or the next) vmc_energy_forces call to stop (any thread)."""
+        _check(_lib().vmc_cancel(self.h), "vmc_cancel")
 
     def close(self):
         if self.h:
@@ -205,8 +230,30 @@ class Trajectory:
         _check(_lib().vmc_traj_accepts(self.h, C.c_void_p(out.data_ptr())), "vmc_traj_accepts")
         return out
 
-    def build_S(self, S=None):
+    def build_S(self, S=None, keep_only=False):
+        """S of the last estimate; keep_only: leave it on the device in the trajectory only."""
+        if keep_only:
+            _check(_lib().vmc_build_S(self.h, None), "vmc_build_S")
+            return None
         return vmc_build_S(self, S)
+
+    def set_R(self, R):
+        _check(_lib().vmc_traj_set_R(self.h, _dev(R, 3 * self.N)), "vmc_traj_set_R")
+
+    def get_R(self):
+        import torch
+        out = torch.empty(3 * self.N, dtype=torch.float64, device="cuda")
+        _check(_lib().vmc_traj_get_R(self.h, _dev(out)), "vmc_traj_get_R")
+        return out
+
+    def step_count(self):
+        n = C.c_uint32(0)
+        _check(_lib().vmc_traj_step_count(self.h, C.byref(n)), "vmc_traj_step_count")
+        return n.value
+
+    def langevin_step(self, T, Delta, alpha, flags=0):
+        """vmc_traj_langevin_step on the trajectory's own state; returns the status code."""
+        return _lib().vmc_traj_langevin_step(self.h, float(T), float(Delta), float(alpha), int(flags))
 
     def walkers_reset(self) -> int:
         """Walkers re-initialised (non-finite coordinates) at the start of the last call."""
@@ -245,12 +292,14 @@ class Trajectory:
 
 
 def vmc_energy_forces(traj: Trajectory, R, Cmo, zeta, n_equil, n_sweeps, delta, step=0, out=None):
+    """R None: the trajectory's R; step None: its Langevin step counter (VMC_STEP_TRAJ)."""
     import torch
     N = traj.N
     if out is None:
         out = torch.empty(3 + 3 * N, dtype=torch.float64, device="cuda")
-    _check(_lib().vmc_energy_forces(traj.h, _dev(R, 3 * N), _dev(Cmo, N * (N // 2)), _dev(zeta, N), int(n_equil),
-                                    int(n_sweeps), float(delta), int(step), _dev(out, 3 + 3 * N)),
+    _check(_lib().vmc_energy_forces(traj.h, None if R is None else _dev(R, 3 * N), _dev(Cmo, N * (N // 2)),
+                                    _dev(zeta, N), int(n_equil), int(n_sweeps), float(delta),
+                                    VMC_STEP_TRAJ if step is None else int(step), _dev(out, 3 + 3 * N)),
            "vmc_energy_forces")
     return out
 
@@ -347,6 +396,10 @@ def vmc_twist_average(ctx: Context, f_stack, S_stack, f=None, S=None):
     _check(_lib().vmc_twist_average(ctx.h, n_tw, n3, _dev(f_stack, n_tw * n3), _dev(S_stack, n_tw * n3 * n3),
                                     _dev(f, n3), _dev(S, n3 * n3)), "vmc_twist_average")
     return f, S
+
+
+def traj_bytes(system: vmc_system, n_walkers: int) -> int:
+    return int(_lib().vmc_traj_bytes(C.byref(system), int(n_walkers)))
 
 
 def supported_n(n):

@@ -156,3 +156,99 @@ def test_restart_at_another_density(dev, precision, twist):
         with pytest.raises(vmc.VMCError):
             bad.load_rescaled(blob)
         bad.close()
+
+
+def _owned_steps(torch, vmc, tr, wl, n, twist=0, save_before_last_update=False):
+    """n Langevin steps on the trajectory's own state (R, R_prev, S, S_prev and the step
+    counter held by the trajectory; the caller computes only C at the trajectory's R).  With
+    save_before_last_update the last step stops after vmc_build_S and returns a checkpoint."""
+    zeta = T(torch, wl.zeta)
+    alpha = 0.122 * tr.W * 3
+    outs = []
+    for j in range(n):
+        Cm = vmc.vmc_huckel_params(tr.get_R().cpu().numpy(), wl.zeta, wl.L, twist=twist)
+        out = tr.energy_forces(None, T(torch, Cm), zeta, 2 if tr.step_count() == 0 else 1, 3, wl.delta, step=None)
+        tr.build_S(keep_only=True)
+        outs.append(out.cpu().numpy())
+        if save_before_last_update and j == n - 1:
+            return outs, tr.save()
+        assert tr.langevin_step(wl.T_hartree, 1.0 / alpha, alpha) == 0
+    return outs, None
+
+
+@pytest.mark.parametrize("name,W,precision,twist,mid", [("h16", 64, 0, 0, False), ("h54", 176, 1, 3, False),
+                                                         ("h16", 64, 1, 0, True)])
+def test_resume_with_trajectory_owned_langevin_state(dev, name, W, precision, twist, mid):
+    """The trajectory owns R, R_prev, S, S_prev and the step counter (Eq. finaldyn_new needs
+    R(t - Delta) and S(R(t - Delta))): a checkpoint taken after the first step (or, with mid,
+    between vmc_build_S and the update of the second step) and loaded into a fresh trajectory
+    with another seed, other walkers and another R continues R, E and the walkers bit for bit
+    with no state held by the caller."""
+    torch, vmc, ctx = dev
+    wl = workload(name)
+    say(f"[owned Langevin state] {name} W={W} precision={precision} twist={twist} mid={mid}")
+    sysd = vmc.make_system(wl.n, wl.L, precision=precision, twist=twist)
+
+    def fresh(seed, off):
+        tr = vmc.Trajectory(ctx, sysd, W, seed=seed, traj_id=9)
+        tr.set_walkers(T(torch, wl.electrons(W=W, seed_offset=off)))
+        tr.set_R(T(torch, (wl.R if off == 3 else wl.R[::-1]).reshape(-1)))
+        return tr
+
+    tr = fresh(21, 3)
+    ref, _ = _owned_steps(torch, vmc, tr, wl, 3, twist)
+    ref_R, ref_pos, ref_k = tr.get_R().cpu().numpy(), tr.get_walkers().cpu().numpy(), tr.step_count()
+    tr.close()
+    assert ref_k == 3
+    tr = fresh(21, 3)
+    if mid:
+        first, blob = _owned_steps(torch, vmc, tr, wl, 2, twist, save_before_last_update=True)
+    else:
+        first, _ = _owned_steps(torch, vmc, tr, wl, 1, twist)
+        blob = tr.save()
+    tr.close()
+    tr2 = fresh(777, 8)
+    tr2.load(blob)
+    alpha = 0.122 * W * 3
+    if mid:
+        assert tr2.langevin_step(wl.T_hartree, 1.0 / alpha, alpha) == 0
+    rest, _ = _owned_steps(torch, vmc, tr2, wl, 1 if mid else 2, twist)
+    assert tr2.step_count() == 3
+    assert all(np.array_equal(a, b) for a, b in zip(ref, first + rest))
+    assert np.array_equal(tr2.get_R().cpu().numpy(), ref_R)
+    assert np.array_equal(tr2.get_walkers().cpu().numpy(), ref_pos)
+    tr2.close()
+
+
+def test_damaged_payload_refused(dev):
+    """A checkpoint with one flipped bit inside the walker block, the means block or the
+    Langevin state is refused (checksum) and leaves the target as it was."""
+    torch, vmc, ctx = dev
+    wl = workload("h16")
+    W = 32
+    sysd = vmc.make_system(wl.n, wl.L)
+    tr = vmc.Trajectory(ctx, sysd, W, seed=1, traj_id=0)
+    tr.set_walkers(T(torch, wl.electrons(W=W)))
+    tr.set_R(T(torch, wl.R.reshape(-1)))
+    Cm = vmc.vmc_huckel_params(wl.R, wl.zeta, wl.L)
+    tr.energy_forces(None, T(torch, Cm), T(torch, wl.zeta), 1, 2, wl.delta, step=None)
+    blob = tr.save()
+    tgt = vmc.Trajectory(ctx, sysd, W, seed=2, traj_id=0)
+    tgt.set_walkers(T(torch, wl.electrons(W=W, seed_offset=5)))
+    x_before = tgt.get_walkers().cpu().numpy()
+    n3 = 3 * wl.n
+    payload = 8 * (W * wl.n * 3 + W * (1 + 9 * wl.n) + W * n3 + 3 + n3 + 2 * n3 + 2 * n3 * n3) + 8 * W
+    hdr = len(blob) - payload
+    for off in (hdr + 100, hdr + 8 * W * wl.n * 3 + 100, len(blob) - 8 * W - 1000):
+        damaged = bytearray(blob)
+        damaged[off] ^= 0x10
+        with pytest.raises(vmc.VMCError) as e:
+            tgt.load(bytes(damaged))
+        assert e.value.code == vmc.VMC_EINVAL
+    assert np.array_equal(tgt.get_walkers().cpu().numpy(), x_before)
+    with pytest.raises(vmc.VMCError):
+        tgt.get_R()                       # never set: the refused loads left no R behind
+    tgt.load(blob)
+    assert np.array_equal(tgt.get_R().cpu().numpy(), wl.R.reshape(-1))
+    tgt.close()
+    tr.close()

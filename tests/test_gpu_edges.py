@@ -189,3 +189,120 @@ def test_walker_quarantine(dev):
         tr.energy_forces(T_(wl.R.reshape(-1)), T_(Cm), T_(wl.zeta), 1, 1, wl.delta, 0)
     assert np.all(np.isnan(tr.get_walkers().cpu().numpy()))
     tr.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_singular_slater_matrix_changes_nothing(oracle, dev, precision):
+    """Two same-spin electrons at one point make that spin's Slater matrix exactly singular: the
+    oracle's LU and the GPU's elimination both meet an exactly zero pivot (VMC_ESINGULAR), and
+    the failing call leaves the walkers, the accepted-move counts, the last call's means and the
+    output as they were."""
+    torch, vmc, ctx = dev
+    wl = workload("h16")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, 8)
+    W = 4
+    x = wl.electrons(W=W, seed_offset=44)
+    x[2, 1] = x[2, 0]                         # electrons 0 and 1 are both spin up
+    say(f"[singular] h16 precision={precision}")
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L)
+    with pytest.raises(RuntimeError, match="rc=-4"):
+        s.local(x[2])
+    with pytest.raises(RuntimeError, match="rc=-4"):
+        s.vmc_run(x.copy(), 1, 1, wl.delta, seed=3)
+    R, C, z = T(torch, wl.R.reshape(-1)), T(torch, Cm), T(torch, wl.zeta)
+    sysd = vmc.make_system(wl.n, wl.L, precision=precision)
+    with pytest.raises(vmc.VMCError) as e:
+        vmc.vmc_eval_configs(ctx, sysd, R, C, z, T(torch, x))
+    assert e.value.code == vmc.VMC_ESINGULAR
+    tr = vmc.Trajectory(ctx, sysd, W, seed=3, traj_id=0)
+    tr.set_walkers(T(torch, wl.electrons(W=W, seed_offset=45)))
+    tr.energy_forces(R, C, z, 1, 2, wl.delta, 0)
+    means0, acc0, S0 = tr.walker_means().cpu().numpy(), tr.accepts().cpu().numpy(), tr.build_S().cpu().numpy()
+    tr.set_walkers(T(torch, x))
+    out = torch.full((3 + 3 * wl.n,), 123.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(vmc.VMCError) as e:
+        tr.energy_forces(R, C, z, 1, 2, wl.delta, 1, out=out)
+    assert e.value.code == vmc.VMC_ESINGULAR
+    assert np.array_equal(tr.get_walkers().cpu().numpy(), x)
+    assert np.array_equal(tr.walker_means().cpu().numpy(), means0)
+    assert np.array_equal(tr.accepts().cpu().numpy(), acc0)
+    assert np.array_equal(tr.build_S().cpu().numpy(), S0)
+    assert bool((out == 123.0).all())
+    tr.close()
+
+
+def test_cancel_leaves_trajectory_unchanged(dev):
+    """vmc_cancel: the call returns VMC_ECANCELLED with the walkers, counts and means of the
+    previous call; the cancellation is consumed, so the next call runs and equals the same call
+    on a trajectory that was never cancelled."""
+    torch, vmc, ctx = dev
+    wl = workload("h16")
+    Cm = vmc.vmc_huckel_params(wl.R, wl.zeta, wl.L)
+    R, C, z = T(torch, wl.R.reshape(-1)), T(torch, Cm), T(torch, wl.zeta)
+    sysd = vmc.make_system(wl.n, wl.L)
+    say("[cancel]")
+    runs = []
+    for cancel in (True, False):
+        tr = vmc.Trajectory(ctx, sysd, 32, seed=8, traj_id=2)
+        tr.set_walkers(T(torch, wl.electrons(W=32, seed_offset=2)))
+        tr.energy_forces(R, C, z, 1, 2, wl.delta, 0)
+        x1, m1 = tr.get_walkers().cpu().numpy(), tr.walker_means().cpu().numpy()
+        if cancel:
+            ctx.cancel()
+            with pytest.raises(vmc.VMCError) as e:
+                tr.energy_forces(R, C, z, 1, 20, wl.delta, 1)
+            assert e.value.code == vmc.VMC_ECANCELLED
+            assert np.array_equal(tr.get_walkers().cpu().numpy(), x1)
+            assert np.array_equal(tr.walker_means().cpu().numpy(), m1)
+        out = tr.energy_forces(R, C, z, 1, 2, wl.delta, 1).cpu().numpy()
+        runs.append((out, tr.get_walkers().cpu().numpy()))
+        tr.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("what", ["f", "R"])
+def test_langevin_nonfinite_input_refused(oracle, dev, what):
+    """A NaN force or position is an argument error on both sides; the state is unchanged."""
+    torch, vmc, ctx = dev
+    rng = np.random.default_rng(3)
+    n3 = 12
+    A = rng.standard_normal((n3, n3))
+    S = A @ A.T + n3 * np.eye(n3)
+    f = rng.standard_normal(n3)
+    R = rng.uniform(0, 5.0, n3)
+    if what == "f":
+        f[4] = np.nan
+    else:
+        R[7] = np.nan
+    Ro, Rpo, Spo = R.copy(), R.copy(), S.copy()
+    assert oracle.langevin(Ro, Rpo, Spo, f, S, 0.01, 0.5, 0.0, L=6.0) == -1
+    assert np.array_equal(Ro, R, equal_nan=True) and np.array_equal(Spo, S)
+    Rg, Rpg, Spg = T(torch, R), T(torch, R), T(torch, S)
+    rc = vmc.vmc_langevin_step(ctx, Rg, Rpg, Spg, T(torch, f), T(torch, S), 0.01, 0.5, 0.0, 0, 1, 0, 0, 6.0)
+    assert rc == vmc.VMC_EINVAL
+    assert np.array_equal(Rg.cpu().numpy(), R, equal_nan=True) and np.array_equal(Spg.cpu().numpy(), S)
+
+
+def test_hbm_budget_of_context(dev):
+    """vmc_set_hbm_budget: trajectories beyond the budget are refused with VMC_ENOMEM; the bytes
+    in use follow creation and destruction."""
+    torch, vmc, _ = dev
+    ctx = vmc.Context(0)
+    wl = workload("h16")
+    sysd = vmc.make_system(wl.n, wl.L)
+    b = vmc.traj_bytes(sysd, 64)
+    assert b > 64 * wl.n * 3 * 8
+    ctx.set_hbm_budget(2 * b + b // 2)
+    t1 = vmc.Trajectory(ctx, sysd, 64)
+    t2 = vmc.Trajectory(ctx, sysd, 64)
+    assert ctx.hbm_in_use() == 2 * b
+    with pytest.raises(vmc.VMCError) as e:
+        vmc.Trajectory(ctx, sysd, 64)
+    assert e.value.code == vmc.VMC_ENOMEM
+    t1.close()
+    assert ctx.hbm_in_use() == b
+    t3 = vmc.Trajectory(ctx, sysd, 64)
+    t2.close()
+    t3.close()
+    assert ctx.hbm_in_use() == 0
+    ctx.close()

@@ -24,6 +24,13 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def elem(a, b):
+    """Largest element-wise error relative to the element plus an absolute floor of the largest
+    element, max_i |a_i - b_i| / (|b_i| + max_j |b_j|): bounds every component, small ones too."""
+    a, b = np.atleast_1d(np.asarray(a, dtype=np.float64)), np.atleast_1d(np.asarray(b, dtype=np.float64))
+    return float(np.max(np.abs(a - b) / (np.abs(b) + np.max(np.abs(b)) + 1e-300)))
+
+
 @pytest.fixture(scope="module")
 def dev():
     import torch
@@ -55,13 +62,15 @@ def test_eval_configs_fp64(oracle, dev, name, K):
     g = _eval_gpu(torch, vmc, ctx, wl, Cm, pos, vmc.VMC_FP64)
     s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L)
     n3 = 3 * wl.n
-    worst = {"lnpsi": 0.0, "EL": 0.0, "dlnpsi": 0.0, "dEL": 0.0}
+    worst = {"lnpsi": 0.0, "EL": 0.0, "dlnpsi": 0.0, "dEL": 0.0, "dlnpsi_elem": 0.0, "dEL_elem": 0.0}
     for k in range(K):
         r = s.local(pos[k])
         worst["lnpsi"] = max(worst["lnpsi"], rel(g[k, 0], r["lnpsi"]))
         worst["EL"] = max(worst["EL"], rel(g[k, 1], r["EL"]))
         worst["dlnpsi"] = max(worst["dlnpsi"], rel(g[k, 2:2 + n3], r["dlnpsi"]))
         worst["dEL"] = max(worst["dEL"], rel(g[k, 2 + n3:], r["dEL"]))
+        worst["dlnpsi_elem"] = max(worst["dlnpsi_elem"], elem(g[k, 2:2 + n3], r["dlnpsi"]))
+        worst["dEL_elem"] = max(worst["dEL_elem"], elem(g[k, 2 + n3:], r["dEL"]))
     say("  worst relative errors", worst)
     for q, v in worst.items():
         assert v < TOL64, (q, v)
@@ -104,11 +113,12 @@ def test_chain_fp64(oracle, dev, name, W, ne, ns):
     for q, sl in [("e_w", slice(0, 1)), ("d_w", slice(1, 1 + n3)), ("g_w", slice(1 + n3, 1 + 2 * n3)),
                   ("h_w", slice(1 + 2 * n3, 1 + 3 * n3))]:
         e = max(rel(g["means"][w, sl], mo[w, sl]) for w in range(W))
-        say(f"  {q} worst walker rel err {e:.3e}")
-        assert e < TOL64, q
+        ee = max(elem(g["means"][w, sl], mo[w, sl]) for w in range(W))
+        say(f"  {q} worst walker rel err {e:.3e} (element-wise {ee:.3e})")
+        assert e < TOL64 and ee < TOL64, q
     assert rel(g["out"][0], o["red"]["E"]) < TOL64
     assert rel(g["out"][1], o["red"]["sigma_E"]) < 1e-8
-    assert rel(g["out"][3:], o["red"]["f"]) < TOL64
+    assert rel(g["out"][3:], o["red"]["f"]) < TOL64 and elem(g["out"][3:], o["red"]["f"]) < TOL64
     assert rel(g["fw"], o["red"]["f_w"]) < TOL64
     assert rel(g["S"], o["S"]) < 1e-9
     acc_rate = o["nacc"].sum() / (W * wl.n * (ne + ns))
@@ -149,6 +159,10 @@ def test_langevin_step(oracle, dev, n3, L, alpha, flags):
     rcg = vmc.vmc_langevin_step(ctx, Rg, Rpg, Spg, td(f), td(S), T, D, alpha, flags, 5, 2, 9, L)
     assert rco == 0 and rcg == 0
     assert rel(Rg.cpu().numpy(), Ro) < 1e-12
+    dg, do = Rg.cpu().numpy() - R, Ro - R           # the step itself, element by element
+    if L > 0:
+        dg, do = dg - L * np.round(dg / L), do - L * np.round(do / L)
+    assert elem(dg, do) < 1e-11
     assert np.array_equal(Rpg.cpu().numpy(), Rpo) and np.array_equal(Spg.cpu().numpy(), Spo)
 
 

@@ -79,7 +79,9 @@ def single_path(torch, vmc, ctx, s):
     return R.cpu().numpy(), np.array(Es)
 
 
-@pytest.mark.parametrize("name,W,precision", [("h16", 64, 0), ("h54", 176, 1), ("h256", 800, 1)])
+# h128 mixed runs the batched two-wave refresh (two matrices of N_sigma = 64 per block, each over
+# two waves); W = 400 > 3N = 384 keeps S full rank
+@pytest.mark.parametrize("name,W,precision", [("h16", 64, 0), ("h54", 176, 1), ("h128", 400, 1), ("h256", 800, 1)])
 def test_served_equals_single_trajectory_calls(dev, name, W, precision):
     torch, vmc, ctx = dev
     s = spec(name, W, precision)
@@ -94,18 +96,20 @@ def test_served_equals_single_trajectory_calls(dev, name, W, precision):
 def test_alone_equals_in_mix(dev):
     torch, vmc, ctx = dev
     # W > 3N for each (S must be positive definite)
-    target = [spec("h16", 64, 0, traj=3), spec("h54", 176, 1, traj=4, steps=3)]
+    target = [spec("h16", 64, 0, traj=3), spec("h54", 176, 1, traj=4, steps=3),
+              spec("h128", 400, 1, traj=5, steps=2, M=2, ne1=1)]
     others = [spec("h32", 100, 0, traj=11), spec("h16", 80, 1, traj=12, M=6), spec("h54", 200, 1, traj=13, steps=1),
               spec("h64", 200, 1, traj=14), spec("h16", 52, 0, traj=15, steps=3)]
-    say("[alone vs mix] 2 targets in a mix of 7 trajectories")
+    say("[alone vs mix] 3 targets (N = 16, 54, 128) in a mix of 8 trajectories")
     alone = [serve(vmc, ctx, [t])[0][0] for t in target]
-    mixed, info = serve(vmc, ctx, others[:3] + [target[0]] + others[3:] + [target[1]])
-    mix_t = [mixed[3], mixed[6]]
+    order = others[:3] + [target[0]] + others[3:] + [target[1], target[2]]
+    mixed, info = serve(vmc, ctx, order)
+    mix_t = [mixed[3], mixed[6], mixed[7]]
     for (sa, ra), (sm, rm) in zip(alone, mix_t):
         assert sa[0] == sm[0] == vmc.VMC_REQ_DONE
         assert np.array_equal(ra["R"], rm["R"]) and np.array_equal(ra["E"], rm["E"])
     assert all(st[0] == vmc.VMC_REQ_DONE for st, _ in mixed)
-    assert all(len(r["latency_ms"]) == s["steps"] for (st, r), s in zip(mixed, others[:3] + [target[0]] + others[3:] + [target[1]]))
+    assert all(len(r["latency_ms"]) == s["steps"] for (st, r), s in zip(mixed, order))
     say(f"  ticks {info['ticks']}, peak resident {info['peak_resident'] / 1e6:.1f} MB")
 
 
@@ -178,6 +182,7 @@ def test_refusals_cancel_and_failure_isolation(dev):
     assert st[0][0] == vmc.VMC_REQ_DONE
     assert st[1][0] == vmc.VMC_REQ_FAILED and st[1][2] == vmc.VMC_EINVAL
     assert st[2][0] == vmc.VMC_REQ_CANCELLED and st[3][0] == vmc.VMC_REQ_CANCELLED
+    assert st[2][2] == st[3][2] == vmc.VMC_ECANCELLED
     assert srv.info()["resident"] == 0
     srv.close()
     # the surviving request equals its run alone
@@ -208,3 +213,33 @@ def test_served_walker_quarantine(dev):
         srv.close()
     assert res[0][0][0] == res[1][0][0] == vmc.VMC_REQ_DONE
     assert np.array_equal(res[0][1]["R"], res[1][1]["R"]) and np.array_equal(res[0][1]["E"], res[1][1]["E"])
+
+
+def test_request_failing_at_step_setup_fails_alone(dev):
+    """A failure of one request's host-side step set-up (here a proton position that is not
+    finite, refused before the Hueckel solve) fails that request with VMC_EINVAL; the tick goes
+    on, and the other requests, submitted before and after it, complete and equal their runs
+    alone."""
+    torch, vmc, ctx = dev
+    good = [spec("h16", 64, 0, traj=40), spec("h54", 176, 1, traj=41)]
+    s_bad = spec("h16", 64, 0, traj=42)
+    wl = s_bad["wl"]
+    R_bad = wl.R.copy()
+    R_bad[3, 1] = np.nan
+    bad = vmc.make_request(vmc.make_system(wl.n, wl.L), s_bad["W"], R_bad, wl.zeta,
+                           wl.electrons(W=s_bad["W"], seed_offset=42), n_steps=2, n_sweeps=s_bad["M"], T=s_bad["T"],
+                           Delta=1.0 / s_bad["alpha"], alpha=s_bad["alpha"], n_equil_first=2, n_equil=1,
+                           step_delta=wl.delta, seed=5, traj_id=42)
+    say("[failure at set-up] one request with a NaN proton position among two good ones")
+    srv = vmc.Server(ctx, 16 << 30)
+    ids = [srv.submit(make_req(vmc, good[0])), srv.submit(bad), srv.submit(make_req(vmc, good[1]))]
+    srv.run_until_idle()
+    st = [srv.status(i) for i in ids]
+    res = [srv.result(i) for i in ids]
+    assert st[1][0] == vmc.VMC_REQ_FAILED and st[1][2] == vmc.VMC_EINVAL and st[1][1] == 0
+    assert st[0][0] == st[2][0] == vmc.VMC_REQ_DONE
+    assert srv.info()["resident"] == 0
+    srv.close()
+    for g, r in zip(good, (res[0], res[2])):
+        (sa, ra), = serve(vmc, ctx, [g])[0]
+        assert np.array_equal(ra["R"], r["R"]) and np.array_equal(ra["E"], r["E"])
