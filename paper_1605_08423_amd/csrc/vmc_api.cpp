@@ -601,6 +601,7 @@ int vmc_energy_forces(vmc_traj* t, const double* R_in, const double* C, const do
   HIPCHK(hipMemcpyAsync(qc, t->qflag + W, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (qc[1] > 0) return VMC_EINVAL;     // no walker was touched: the quarantine had no source
+  t->n_reset = qc[0];
   int rc = proton_setup(t, R);
   if (rc) return fail_restore(t, rc);
   int nimg = 1;
