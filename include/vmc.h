@@ -241,6 +241,17 @@ int vmc_langevin_step(vmc_ctx* ctx, int n3, double box_L, double* R_dev, double*
  * the counter advances; on failure (VMC_ENOTSPD, VMC_EINVAL) nothing changes.  VMC_EINVAL too if
  * R, the estimate or S is missing. */
 int vmc_traj_langevin_step(vmc_traj* traj, double T, double Delta, double alpha, unsigned flags);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): vmc_langevin_step with the same arguments, results
+ * and status codes, but no allocation of any kind.  Its Cholesky work and status word live in a
+ * static device array of the library (one per device, about 4.8 MB, held until the process
+ * ends; its address is taken at vmc_create), so n3 <= 768 (the 256-proton box); a larger n3
+ * returns VMC_EINVAL.  Every call on a device shares that device's array: calls that overlap on
+ * one device (other threads, other contexts' streams) race and must not be issued. */
+int vmc_langevin_step_noalloc(vmc_ctx* ctx, int n3, double box_L, double* R_dev, double* R_prev_dev,
+                              double* S_prev_dev, const double* f_dev, const double* S_dev, double T,
+                              double Delta, double alpha, unsigned flags, uint32_t seed, uint32_t traj_id,
+                              uint32_t step);
 
 /* The rotating-spring toy model (SI, "A simple toy model"; main text, figure of the toy
  * model): U = k (|x| - a)^2 / 2 in the plane; S = G_lambda (radial eigenvalue 1/lambda,

@@ -281,6 +281,20 @@ __global__ __launch_bounds__(1024) void k_langevin(int n3, double L, double* R, 
   if (t == 0) *status = 0;
 }
 
+// Device scratch of vmc_langevin_step_noalloc: the work of one Langevin step (langevin_work_doubles)
+// for 3N <= LANG_NOALLOC_MAX, then its status word.  One array per device, shared by every call on
+// that device (each device holds it until the process ends).  Host code never names the array in
+// a kernel argument or copy: it takes the device address from langevin_scratch_address.
+constexpr int LANG_NOALLOC_MAX = 768;
+static __device__ __align__(256) double scratch[(size_t)LANG_NOALLOC_MAX * LANG_NOALLOC_MAX +
+                                                 16 * LANG_NOALLOC_MAX + 32];
+
+size_t langevin_work_doubles(int n3) { return (size_t)n3 * n3 + 16 * (size_t)n3; }
+int langevin_noalloc_max() { return LANG_NOALLOC_MAX; }
+// With the device current: the address of that device's copy of the array.
+hipError_t langevin_scratch_address(double** ptr) { return hipGetSymbolAddress((void**)ptr, HIP_SYMBOL(scratch)); }
+size_t langevin_scratch_status_offset() { return langevin_work_doubles(LANG_NOALLOC_MAX); }
+
 hipError_t launch_langevin(int n3, double L, double* R, double* R_prev, double* S_prev, const double* f,
                            const double* S, double* Lwork, double* vwork, double T, double Delta, double alpha,
                            unsigned flags, uint32_t seed, uint32_t traj, uint32_t step, int* status,

@@ -130,6 +130,13 @@ hipError_t launch_langevin(int n3, double L, double* R, double* R_prev, double* 
                            const double* S, double* Lwork, double* vwork, double T, double Delta, double alpha,
                            unsigned flags, uint32_t seed, uint32_t traj, uint32_t step, int* status,
                            hipStream_t st);
+// Work of one Langevin step: Lwork needs langevin_work_doubles(n3) doubles.
+size_t langevin_work_doubles(int n3);
+// The per-device static scratch of the allocation-free Langevin step: largest 3N, its address on
+// the current device (hipGetSymbolAddress) and the offset (doubles) of its status word.
+int langevin_noalloc_max();
+hipError_t langevin_scratch_address(double** ptr);
+size_t langevin_scratch_status_offset();
 size_t syrk_partial_doubles(int W, int n3);
 size_t reduce_partial_doubles(int W, int n3);
 // Independent toy-model trajectories (the rotating spring of the SI), one thread each.

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -52,6 +53,7 @@ struct vmc_ctx {
   size_t budget = 0, in_use = 0;   // HBM budget of the trajectories (0 = none), bytes they hold
   std::atomic<int> cancel{0};     // set by vmc_cancel (any thread), consumed by vmc_energy_forces
   hipEvent_t window[kWindow] = {nullptr};   // sweeps in flight, see vmc_energy_forces
+  double* noalloc_scratch = nullptr;         // the device's static scratch of vmc_langevin_step_noalloc
 };
 
 struct vmc_traj {
@@ -299,16 +301,28 @@ const char* vmc_strerror(int code) {
 
 int vmc_supported_n(int n) { return (n > 0 && !(n & 1) && supported_ns(n / 2)) ? 1 : 0; }
 
+// Device address of each device's copy of the allocation-free step's static scratch, taken once
+// per device (with that device current) by the first vmc_create on it.
+static std::mutex g_scratch_mu;
+static double* g_scratch[256] = {nullptr};
+
 int vmc_create(vmc_ctx** out, int device) {
   if (!out) return VMC_EINVAL;
   *out = nullptr;
   int ndev = 0;
   HIPCHK(hipGetDeviceCount(&ndev));
-  if (device < 0 || device >= ndev) return VMC_EINVAL;
+  if (device < 0 || device >= ndev || device >= 256) return VMC_EINVAL;
   HIPCHK(hipSetDevice(device));
+  double* scratch_dev = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) HIPCHK(langevin_scratch_address(&g_scratch[device]));
+    scratch_dev = g_scratch[device];
+  }
   vmc_ctx* c = new (std::nothrow) vmc_ctx();
   if (!c) return VMC_ENOMEM;
   c->device = device;
+  c->noalloc_scratch = scratch_dev;
   if (dalloc(&c->d_status, 1)) { delete c; return VMC_ENOMEM; }
   *out = c;
   return VMC_OK;
@@ -743,7 +757,7 @@ int vmc_langevin_step(vmc_ctx* ctx, int n3, double L, double* R, double* R_prev,
   if (!ctx || n3 < 1 || n3 > 1536 || !R || !R_prev || !S_prev || !f || !S) return VMC_EINVAL;
   if (!(Delta > 0.0) || alpha < 0.0 || T < 0.0 || !(L >= 0.0) || (flags & ~7u)) return VMC_EINVAL;
   HIPCHK(hipSetDevice(ctx->device));
-  const size_t need = (size_t)n3 * n3;
+  const size_t need = langevin_work_doubles(n3);
   if (ctx->lang_work_n < need) {
     if (ctx->lang_work) (void)hipFree(ctx->lang_work);
     ctx->lang_work = nullptr;
@@ -756,6 +770,27 @@ int vmc_langevin_step(vmc_ctx* ctx, int n3, double L, double* R, double* R_prev,
                                   seed, traj_id, step, ctx->d_status, ctx->stream));
   int st = 0;
   HIPCHK(hipMemcpyAsync(&st, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (st == 3) return VMC_ENOTSPD;
+  if (st == 1) return VMC_EINVAL;
+  return VMC_OK;
+}
+
+int vmc_langevin_step_noalloc(vmc_ctx* ctx, int n3, double L, double* R, double* R_prev, double* S_prev,
+                              const double* f, const double* S, double T, double Delta, double alpha,
+                              unsigned flags, uint32_t seed, uint32_t traj_id, uint32_t step) {
+  if (!ctx || n3 < 1 || n3 > langevin_noalloc_max() || !R || !R_prev || !S_prev || !f || !S) return VMC_EINVAL;
+  if (!(Delta > 0.0) || alpha < 0.0 || T < 0.0 || !(L >= 0.0) || (flags & ~7u)) return VMC_EINVAL;
+  if (!ctx->noalloc_scratch) return VMC_EDEVICE;
+  HIPCHK(hipSetDevice(ctx->device));
+  // the device's static scratch (its address from hipGetSymbolAddress at vmc_create): the step's
+  // work, then the status word, which the kernel writes on every path (nothing to clear)
+  double* work = ctx->noalloc_scratch;
+  int* status = reinterpret_cast<int*>(work + langevin_scratch_status_offset());
+  RUN(K_LANGEVIN, launch_langevin(n3, L, R, R_prev, S_prev, f, S, work, nullptr, T, Delta, alpha, flags, seed,
+                                  traj_id, step, status, ctx->stream));
+  int st = 0;
+  HIPCHK(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (st == 3) return VMC_ENOTSPD;
   if (st == 1) return VMC_EINVAL;
@@ -931,7 +966,7 @@ void release(vmc_server* s, Served* q) {
 
 int ensure_workspaces(vmc_ctx* ctx, int W, int n3) {
   const size_t need_s = syrk_partial_doubles(W, n3);
-  if (ctx->syrk_work_n < need_s || ctx->lang_work_n < (size_t)n3 * n3)
+  if (ctx->syrk_work_n < need_s || ctx->lang_work_n < langevin_work_doubles(n3))
     HIPCHK(hipStreamSynchronize(ctx->stream));       // queued kernels may still use the old buffers
   if (ctx->syrk_work_n < need_s) {
     if (ctx->syrk_work) (void)hipFree(ctx->syrk_work);
@@ -940,7 +975,7 @@ int ensure_workspaces(vmc_ctx* ctx, int W, int n3) {
     if (dalloc(&ctx->syrk_work, need_s)) return VMC_ENOMEM;
     ctx->syrk_work_n = need_s;
   }
-  const size_t need_l = (size_t)n3 * n3;
+  const size_t need_l = langevin_work_doubles(n3);
   if (ctx->lang_work_n < need_l) {
     if (ctx->lang_work) (void)hipFree(ctx->lang_work);
     ctx->lang_work = nullptr;

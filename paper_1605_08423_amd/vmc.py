@@ -28,7 +28,7 @@ EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_
             "vmc_server_result", "vmc_server_info", "vmc_toy_run", "vmc_huckel_params_twist",
             "vmc_twist_average", "vmc_traj_save", "vmc_traj_load", "vmc_traj_load_rescaled", "vmc_traj_walkers_reset",
             "vmc_set_hbm_budget", "vmc_hbm_in_use", "vmc_traj_bytes", "vmc_cancel", "vmc_traj_set_R", "vmc_traj_get_R",
-            "vmc_traj_step_count", "vmc_traj_langevin_step"]
+            "vmc_traj_step_count", "vmc_traj_langevin_step", "vmc_langevin_step_noalloc"]
 VMC_REQ_QUEUED, VMC_REQ_RUNNING, VMC_REQ_DONE, VMC_REQ_FAILED, VMC_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
@@ -89,6 +89,7 @@ def _declare(l):
     l.vmc_build_S.argtypes = [vp, vp]
     l.vmc_build_S_raw.argtypes = [vp, i, i, vp, vp, vp]
     l.vmc_langevin_step.argtypes = [vp, i, d, vp, vp, vp, vp, vp, d, d, d, C.c_uint, u32, u32, u32]
+    l.vmc_langevin_step_noalloc.argtypes = [vp, i, d, vp, vp, vp, vp, vp, d, d, d, C.c_uint, u32, u32, u32]
     l.vmc_eval_configs.argtypes = [vp, P(vmc_system), vp, vp, vp, i, vp, vp]
     l.vmc_toy_run.argtypes = [vp, P(vmc_toy_params), i, i, u32, vp, vp, vp, vp]
     l.vmc_huckel_params.argtypes = [i, d, P(d), P(d), P(d)]
@@ -330,6 +331,17 @@ def vmc_langevin_step(ctx: Context, R, R_prev, S_prev, f, S, T, Delta, alpha, fl
     return _lib().vmc_langevin_step(ctx.h, n3, float(box_L), _dev(R), _dev(R_prev, n3), _dev(S_prev, n3 * n3),
                                     _dev(f, n3), _dev(S, n3 * n3), float(T), float(Delta), float(alpha), int(flags),
                                     int(seed), int(traj_id), int(step))
+
+
+def vmc_langevin_step_noalloc(ctx: Context, R, R_prev, S_prev, f, S, T, Delta, alpha, flags=0, seed=0, traj_id=0,
+                              step=0, box_L=0.0):
+    """vmc_langevin_step without any allocation (the library's static device scratch, 3N <= 768);
+    returns the status code."""
+    n3 = R.numel()
+    return _lib().vmc_langevin_step_noalloc(ctx.h, n3, float(box_L), _dev(R), _dev(R_prev, n3),
+                                            _dev(S_prev, n3 * n3), _dev(f, n3), _dev(S, n3 * n3), float(T),
+                                            float(Delta), float(alpha), int(flags), int(seed), int(traj_id),
+                                            int(step))
 
 
 class vmc_toy_params(C.Structure):
