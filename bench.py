@@ -20,18 +20,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "VMC walker-sweeps/s with forces at N=128 H; Langevin steps/s, p99 latency"
-# MI355X peaks per execution unit, TFLOP/s.  Packed FP32 is not used, so FP32 vector
-# arithmetic issues at the FP64 vector rate.
-PEAK = {"mfma_f64": 78.6, "mfma_f32": 157.3, "valu": 78.6}
+# MI355X published peaks per execution unit, TFLOP/s: FP64 (vector and matrix cores alike), FP32
+# matrix cores, FP32 vector.  The kernels issue FP32 vector arithmetic unpacked (one FMA per lane
+# per cycle, 78.6 TFLOP/s), so FP32 vector work can reach at most half of its published peak.
+PEAK = {"f64": 78.6, "f32_mfma": 157.3, "f32": 157.3}
 
 
-def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, one_body: bool = False) -> dict:
-    """Algorithmic arithmetic of one walker's share of a launch, split by the unit that
-    executes it: {unit: flops} (FMA = 2 flops; exp, erfc, sqrt, rcp, sincos count 1).
-    img = Gaussian images evaluated per axis (3, or 1 when the dropped ones are below
-    FP32 resolution); one_body: the electron-proton Jastrow term is on."""
+def _add(d: dict, unit: str, flops: float) -> dict:
+    d[unit] = d.get(unit, 0.0) + flops
+    return d
+
+
+def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, one_body: bool = False,
+               acc: float = 0.57) -> dict:
+    """Algorithmic work of the method in one walker's share of a launch, by the unit it runs on:
+    {unit: flops} (FMA = 2 flops; exp, erfc, sqrt, rcp, sincos count 1).  img: Gaussian images
+    evaluated per axis (3, or 1 when the dropped ones are below FP32 resolution); acc: the
+    acceptance rate (a rejected move costs no inverse update); one_body: the electron-proton
+    Jastrow term.  In mixed precision the basis, Jastrow and Ewald real-space terms are FP32."""
     NS = N // 2
     img = 3 if nimg else 1
+    lo = "f32" if mixed else "f64"
     if cls == "slater_sample":
         gemm = 2 * N * NS * NS                                   # one of B = C A^-1, M = X B, W = B M, one spin
         pair1 = 3 * (3 + 9 * img) + 29 + 8 + 32                  # Gaussian with 3 derivatives, products, X, sums
@@ -41,41 +50,61 @@ def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, on
             # per (electron, proton) pair: its Jastrow gradient and Laplacian (30), grad ln|D| from
             # the Gaussian gradient (3 (3 + 5 img) + 8) and the d/dR terms (80)
             valu += N * N * (30 + 3 * (3 + 5 * img) + 8 + 80)
-        if mixed:
-            return {"mfma_f64": 2 * gemm, "mfma_f32": 4 * gemm, "valu": valu}
-        return {"mfma_f64": 6 * gemm, "valu": valu}
+        w = {"f64": 2 * gemm}                                    # B = C A^-1 for both spins
+        _add(w, "f32_mfma" if mixed else "f64", 4 * gemm)        # M = X B, W = B M
+        return _add(w, lo, valu)
     if cls == "sweep_half":
-        mfma = 2 * NS * N * NS + 2 * NS ** 3 + 2 * NS ** 3       # M' = Phi' C, P = M' A^-1, rank-16 updates
-        per_move = N * (3 * (3 + 2 * img) + 2) + 2 * (N - 1) * 16 + 2 * 0.58 * 7.5 * 2 * NS
-        if one_body:
-            per_move += 2 * N * 15                               # old and new distance to every proton, exp
-        return {"mfma_f64": mfma, "valu": NS * per_move}
+        # one move: the proposal's basis values (per centre and axis an offset, its square and an
+        # exp per image; the product), its Jastrow change (old and new pair terms, 15 flops each),
+        # the MO row m = phi C (2 N NS), the ratio q = m . (A^-1 column) (2 NS) and, if accepted,
+        # the Sherman-Morrison update (m^T A^-1 and the rank-1 update, 4 NS^2)
+        basis = N * (3 * (3 + 2 * img) + 2)
+        jas = 30 * (N - 1) + (30 * N if one_body else 0)
+        w = {"f64": NS * (2 * N * NS + 2 * NS + acc * 4 * NS * NS)}
+        return _add(w, lo, NS * (basis + jas))
     if cls == "ewald_sample":
         recip = nk * N * 8 + nslot * N * 6
         real = (N * (N - 1) // 2) * 30 + N * N * 40
-        return {"valu": recip + real}
+        return _add({"f64": recip}, lo, real)
     if cls == "refine":
-        return {"mfma_f64": 4 * NS ** 3}
+        return {"f64": 4 * NS ** 3}
     return {}
 
 
+def executed_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, one_body: bool = False,
+                   acc: float = 0.57) -> dict:
+    """The arithmetic a launch executes, where it differs from the method's count: the sweep applies
+    its Sherman-Morrison updates in blocks of 16 moves on the matrix cores, forming the full rows
+    P = M' A^-1 of every proposal and a rank-16 update whatever the acceptance (2 NS N NS + 4 NS^3
+    on the FP64 matrix cores per half-sweep; the SQ_INSTS_VALU_MFMA_MOPS_F64 counter gives it)."""
+    if cls != "sweep_half":
+        return work_model(cls, N, nk, nslot, nimg, mixed, one_body, acc)
+    NS = N // 2
+    img = 3 if nimg else 1
+    lo = "f32" if mixed else "f64"
+    per_move = N * (3 * (3 + 2 * img) + 2) + 30 * (N - 1) + (30 * N if one_body else 0)
+    w = {"f64": 2 * NS * N * NS + 4 * NS ** 3 + NS * 16 * NS}    # matrix cores; the recursion t -= t[i] z
+    return _add(w, lo, NS * per_move)
+
+
 def roofline_numbers(parts: dict, walkers: int, avg_s: float):
-    """Achieved TFLOP/s of a launch and the peak it is measured against: the
-    time-weighted combination of the unit peaks, sum(f) / sum(f_u / peak_u)."""
+    """Achieved TFLOP/s of a launch and the peak it is measured against: the time-weighted
+    combination of the unit peaks, sum(f) / sum(f_u / peak_u)."""
     total = sum(parts.values()) * walkers
     t_peak = sum(f * walkers / (PEAK[u] * 1e12) for u, f in parts.items())
     achieved = total / avg_s / 1e12 if avg_s > 0 else 0.0
-    peak = total / t_peak / 1e12 if t_peak > 0 else PEAK["valu"]
+    peak = total / t_peak / 1e12 if t_peak > 0 else PEAK["f64"]
     return total, achieved, peak
 
 
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources; a committed traffic measurement applies only to this hash."""
+    """Hash of the kernel sources (HIP kernels, their launchers and headers); a committed traffic
+    measurement applies only to this hash."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1605_08423_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".cpp")):
+        if f.endswith(".hip") or f in ("common.hpp", "kernels.hpp"):
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -189,8 +218,8 @@ def run_toy(args):
                                f"trajectories x {steps} steps per point, T={tm['T']}, k={tm['k']}, a={tm['a']}, "
                                f"lambda={tm['lambda_used']}, mu={tm['mu']}"},
         "wall_s": round(wall, 3),
-        "roofline": {"bound": "alu", "kernel": "toy", "achieved": round(achieved, 3), "peak": PEAK["valu"],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["valu"], 4), "traffic": None,
+        "roofline": {"bound": "alu", "kernel": "toy", "achieved": round(achieved, 3), "peak": PEAK["f64"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64"], 4), "traffic": None,
                      "avg_launch_ms": round(avg_s * 1e3, 3), "flop_per_trajectory_step": TOY_FLOP_PER_STEP},
         "cpu_baseline": cpu,
         "figure_U_over_half_T_minus_1": figure, "unstable_trajectories": unstable,
@@ -201,21 +230,21 @@ def run_toy(args):
 SERVE_WALKERS = {16: 1024, 32: 2048, 54: 4096, 128: 16384}
 
 
-def run_serve(args):
+def serve_stream(n_req: int, steps: int, sweeps: int, rate: float, budget_gb: float, large: bool = False) -> dict:
     """Served stream: independent trajectories with N in {16, 32, 54, 128}, r_s ~ U[1.25, 1.50],
-    T ~ U[600, 3000] K and walker counts scaling with N, arriving as a Poisson stream;
-    continuous batching on one GPU (vmc_server_*).  Prints one JSON line."""
+    T ~ U[600, 3000] K and walker counts scaling with N, all in mixed precision, arriving as a
+    Poisson stream; continuous batching on one GPU (vmc_server_*).  large: one N = 256 box
+    (r_s 1.36, 900 K, 32768 walkers) with eight N = 54 boxes instead."""
     import torch
     from paper_1605_08423_amd import vmc
     from paper_1605_08423_amd.inputs import KB_HA_PER_K, small_system, workload
     rng = np.random.default_rng(20240605)
-    large = args.serve_mix == "large"
-    n_req = 9 if large else args.serve
+    if large:
+        n_req = 9
     ctx = vmc.Context(0)
     reqs, meta = [], []
     for i in range(n_req):
         if large:
-            # one 256-proton box (r_s 1.36, 900 K, 32768 walkers) and eight 54-proton boxes
             n = 256 if i == 0 else 54
             rs = 1.36 if i == 0 else float(rng.uniform(1.25, 1.50))
             T_k = 900.0 if i == 0 else float(rng.uniform(600.0, 3000.0))
@@ -226,16 +255,14 @@ def run_serve(args):
             T_k = float(rng.uniform(600.0, 3000.0))
             W = SERVE_WALKERS[n]
         wl = workload("h256") if (large and i == 0) else small_system(n, rs, seed=1000 + i)
-        prec = vmc.VMC_MIXED if (n >= 128 or large) else vmc.VMC_FP64
-        sysd = vmc.make_system(n, wl.L, precision=prec)
-        alpha = 0.122 * W * args.serve_sweeps
-        reqs.append(vmc.make_request(sysd, W, wl.R, wl.zeta, wl.electrons(W=W, seed_offset=i), n_steps=args.serve_steps,
-                                     n_sweeps=args.serve_sweeps, T=T_k * KB_HA_PER_K, Delta=1.0 / alpha, alpha=alpha,
+        sysd = vmc.make_system(n, wl.L, precision=vmc.VMC_MIXED)
+        alpha = 0.122 * W * sweeps
+        reqs.append(vmc.make_request(sysd, W, wl.R, wl.zeta, wl.electrons(W=W, seed_offset=i), n_steps=steps,
+                                     n_sweeps=sweeps, T=T_k * KB_HA_PER_K, Delta=1.0 / alpha, alpha=alpha,
                                      n_equil_first=5, n_equil=5, step_delta=rs, seed=77, traj_id=i))
-        meta.append((n, W, prec))
-    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, size=n_req))
-    budget = int(args.serve_budget_gb * 1e9)
-    srv = vmc.Server(ctx, budget)
+        meta.append((n, W))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    srv = vmc.Server(ctx, int(budget_gb * 1e9))
     ids = [None] * n_req
     nxt = 0
     torch.cuda.synchronize()
@@ -252,7 +279,7 @@ def run_serve(args):
             time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    lat, waits, steps, wsweeps, failed = [], [], 0, 0, 0
+    lat, waits, nsteps, wsweeps, failed = [], [], 0, 0, 0
     by_n = {}
     for i, rid in enumerate(ids):
         st, k, err = srv.status(rid)
@@ -261,33 +288,39 @@ def run_serve(args):
             failed += 1
         lat.extend(r["latency_ms"].tolist())
         waits.append(r["wait_ms"])
-        steps += k
-        n, W, _ = meta[i]
-        wsweeps += k * W * (args.serve_sweeps + 5)
+        nsteps += k
+        n, W = meta[i]
+        wsweeps += k * W * (sweeps + 5)
         by_n.setdefault(n, []).extend(r["latency_ms"].tolist())
     info = srv.info()
     srv.close()
-    pct = lambda v, q: float(np.percentile(np.asarray(v), q)) if len(v) else None
-    line = {
-        "metric": "served stream: Langevin steps/s and step latency p50/p99",
-        "value": round(steps / wall, 3), "unit": "Langevin steps/s", "n_gpus": 1, "higher_is_better": True,
-        "data": "synthetic",
-        "dtype": "f32+f64 mixed" if large else "f64 (N<128) / f32+f64 mixed (N=128)",
-        "config": {"workload": (f"one N=256 box (r_s 1.36, 900 K, 32768 walkers) with eight N=54 boxes (r_s~U[1.25,1.50], "
-                                f"T~U[600,3000] K, 4096 walkers), all mixed precision, " if large else
-                                f"{n_req} trajectories, N in {{16,32,54,128}}, r_s~U[1.25,1.50], T~U[600,3000] K, "
-                                f"W = 1024/2048/4096/16384 by N, ") +
-                               f"{args.serve_steps} Langevin steps x (5 + {args.serve_sweeps}) sweeps each, "
-                               f"Poisson arrivals at {args.serve_rate}/s",
-                   "hbm_budget_GB": args.serve_budget_gb},
-        "wall_s": round(wall, 3), "steps": steps, "failed": failed,
+    ctx.close()
+    pct = lambda v, q: round(float(np.percentile(np.asarray(v), q)), 1) if len(v) else None
+    return {
+        "workload": (f"one N=256 box (r_s 1.36, 900 K, 32768 walkers) with eight N=54 boxes (r_s~U[1.25,1.50], "
+                     f"T~U[600,3000] K, 4096 walkers), " if large else
+                     f"{n_req} trajectories, N in {{16,32,54,128}}, r_s~U[1.25,1.50], T~U[600,3000] K, "
+                     f"W = 1024/2048/4096/16384 by N, ") +
+                    f"all mixed precision, {steps} Langevin steps x (5 + {sweeps}) sweeps each, Poisson arrivals at "
+                    f"{rate}/s, HBM budget {budget_gb} GB",
+        "langevin_steps_per_s": round(nsteps / wall, 3), "wall_s": round(wall, 3), "steps": nsteps, "failed": failed,
         "walker_sweeps_per_s": round(wsweeps / wall, 1),
-        "step_latency_ms": {"p50": round(pct(lat, 50), 1), "p99": round(pct(lat, 99), 1)},
-        "step_latency_ms_by_N": {str(n): {"p50": round(pct(v, 50), 1), "p99": round(pct(v, 99), 1), "steps": len(v)}
+        "step_latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "step_latency_ms_by_N": {str(n): {"p50": pct(v, 50), "p99": pct(v, 99), "steps": len(v)}
                                  for n, v in sorted(by_n.items())},
-        "queue_wait_ms": {"p50": round(pct(waits, 50), 1), "p99": round(pct(waits, 99), 1)},
+        "queue_wait_ms": {"p50": pct(waits, 50), "p99": pct(waits, 99)},
         "peak_resident_GB": round(info["peak_resident"] / 1e9, 2), "ticks": info["ticks"],
     }
+
+
+def run_serve(args):
+    """The served stream as its own benchmark line."""
+    r = serve_stream(args.serve, args.serve_steps, args.serve_sweeps, args.serve_rate, args.serve_budget_gb,
+                     large=args.serve_mix == "large")
+    line = {"metric": "served stream: Langevin steps/s and step latency p50/p99", "value": r["langevin_steps_per_s"],
+            "unit": "Langevin steps/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "dtype": "f32/f64", "config": {"workload": r["workload"]}}
+    line.update({k: v for k, v in r.items() if k not in ("workload", "langevin_steps_per_s")})
     print(json.dumps(line))
 
 
@@ -385,6 +418,90 @@ def run_twists(args):
     }))
 
 
+def cpu_host_info() -> dict:
+    """The host the CPU baseline runs on: logical CPUs, those this process may use, the model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable": usable, "model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def kernel_space(sysd, wl, prec_mixed: bool):
+    """Reciprocal vectors, their (ny, nz) slots and the Gaussian image rule of a workload."""
+    nm = sysd.ewald_nmax
+    kset = [(nx, ny, nz) for nx in range(0, nm + 1) for ny in range(-nm, nm + 1) for nz in range(-nm, nm + 1)
+            if 0 < nx * nx + ny * ny + nz * nz <= nm * nm and (nx > 0 or (nx == 0 and (ny > 0 or (ny == 0 and nz > 0))))]
+    nk, nslot = len(kset), len({(ny, nz) for _, ny, nz in kset})
+    nimg = int(not (prec_mixed and float(np.min(wl.zeta)) * (wl.L / 2) ** 2 >= 23.0))
+    return nk, nslot, nimg
+
+
+def run_leg(wl, W: int, M: int, prec: int, b1: float, steps: int, warmup: int, log=None) -> dict:
+    """Langevin steps of one trajectory, each one full pass of the hot path: Hueckel orbitals and
+    proton tables at R, the energy/force estimate (20 equilibration sweeps at the first step, 5
+    after), S and the update on the trajectory's own state.  Times `steps` steps after `warmup`."""
+    import torch
+    from paper_1605_08423_amd import vmc
+    ctx = vmc.Context(0)
+    sysd = vmc.make_system(wl.n, wl.L, precision=prec, b1=b1)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    traj = vmc.Trajectory(ctx, sysd, W, seed=wl.seed, traj_id=0)
+    traj.set_walkers(dev(wl.electrons(W=W)))
+    traj.set_R(dev(wl.R.reshape(-1)))
+    zeta = dev(wl.zeta)
+    alpha = 0.122 * W * M             # N_c = W M samples per step
+    Delta = 1.0 / alpha               # alpha Delta = 1
+
+    def one_step(k):
+        Cm = vmc.vmc_huckel_params(traj.get_R().cpu().numpy(), wl.zeta, wl.L)
+        out = traj.energy_forces(None, dev(Cm), zeta, 20 if k == 0 else 5, M, wl.delta, step=None)
+        S = traj.build_S() if log is not None else traj.build_S(keep_only=True)
+        rc = traj.langevin_step(wl.T_hartree, Delta, alpha)
+        if rc != 0:
+            raise RuntimeError(f"langevin step failed: {vmc._lib().vmc_strerror(rc).decode()}")
+        return out, S
+
+    for k in range(warmup):
+        one_step(k)
+    torch.cuda.synchronize()
+    ctx.reset_kernel_times()
+    ctx.set_profiling(True)
+    lat = []
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        ts = time.perf_counter()
+        out, S = one_step(k)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        if log is not None:
+            oh = out.cpu().numpy()
+            log.write(json.dumps({"step": k, "E_Ha": float(oh[0]), "sigma_E_Ha": float(oh[1]), "acceptance": float(oh[2]),
+                                  "force_norm": float(np.linalg.norm(oh[3:])),
+                                  "cond_S": float(np.linalg.cond(S.cpu().numpy())), "ms": round(1e3 * lat[-1], 2)}) + "\n")
+            log.flush()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    times = ctx.kernel_times()
+    ctx.set_profiling(False)
+    out_h = out.cpu().numpy()
+    traj.close()
+    ctx.close()
+    lat_ms = sorted(1e3 * x for x in lat)
+    p = lambda q: lat_ms[min(len(lat_ms) - 1, int(math.ceil(q * len(lat_ms))) - 1)]
+    return {"value": W * M * steps / elapsed, "elapsed": elapsed, "steps": steps, "times": times, "out": out_h,
+            "p50": p(0.5), "p99": p(0.99), "sysd": sysd}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -401,8 +518,14 @@ def main():
                     help="write one JSON line per timed Langevin step: E, sigma_E, |f|, acceptance, cond(S), time")
     ap.add_argument("--j1", type=float, default=0.0, metavar="B1",
                     help="add the one-body electron-proton Jastrow term with this b_1 (0: none)")
+    ap.add_argument("--fp64-steps", type=int, default=2,
+                    help="timed steps of the plain FP64 leg beside a mixed-precision headline (0: skip)")
+    ap.add_argument("--serve-leg", type=int, default=12, metavar="K",
+                    help="trajectories of the short served-stream leg of the default line (0: skip)")
     ap.add_argument("--cpu-walkers", type=int, default=None, help="default: 192 (h128), 16 (h256)")
     ap.add_argument("--cpu-sweeps", type=int, default=None, help="default: 6 (h128), 2 (h256)")
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="oracle threads: the CPU share of one GPU on the GPU host (capped at the usable CPUs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", action="store_true", help="print per-kernel times to stderr")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -421,22 +544,20 @@ def main():
     ap.add_argument("--toy-traj", type=int, default=65536)
     ap.add_argument("--toy-steps", type=int, default=2000)
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the walker-sharded multi-GPU path is a design "
+              f"that is not built, so --gpus {args.gpus} is not supported.", file=sys.stderr)
+        sys.exit(2)
     if args.toy:
-        if args.gpus != 1:
-            print("bench.py runs on one GPU only.", file=sys.stderr)
-            sys.exit(2)
         run_toy(args)
         return
     if args.twists > 1:
-        if args.gpus != 1 or args.twists > 8:
-            print("bench.py runs on one GPU only, with at most the 8 real twists.", file=sys.stderr)
+        if args.twists > 8:
+            print("bench.py takes at most the 8 real twists.", file=sys.stderr)
             sys.exit(2)
         run_twists(args)
         return
     if args.serve or args.serve_mix == "large":
-        if args.gpus != 1:
-            print("bench.py runs on one GPU only.", file=sys.stderr)
-            sys.exit(2)
         run_serve(args)
         return
     if args.copy_probe:
@@ -448,101 +569,37 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 3}))
         return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: the walker-sharded multi-GPU path is a design "
-              f"that is not built, so --gpus {args.gpus} is not supported.", file=sys.stderr)
-        sys.exit(2)
 
-    import torch
     from paper_1605_08423_amd import vmc
     from paper_1605_08423_amd.inputs import workload
 
     wl = workload(args.workload, rs=args.rs)
-    rs = wl.rs
     N, W, M = wl.n, args.walkers or wl.walkers, args.sweeps
-    prec = vmc.VMC_MIXED if args.precision == "mixed" else vmc.VMC_FP64
-    ctx = vmc.Context(0)
-    sysd = vmc.make_system(N, wl.L, precision=prec, b1=args.j1)
-    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
-    traj = vmc.Trajectory(ctx, sysd, W, seed=wl.seed, traj_id=0)
-    traj.set_walkers(dev(wl.electrons(W=W)))
-    R = dev(wl.R.reshape(-1))
-    R_prev = R.clone()
-    zeta = dev(wl.zeta)
-    n3 = 3 * N
-    S_prev = torch.empty((n3, n3), dtype=torch.float64, device="cuda")
-    T_ha = wl.T_hartree
-    alpha = 0.122 * W * M             # N_c = W M samples per step
-    Delta = 1.0 / alpha               # alpha Delta = 1
-    kb = []
-    state = {"first": True}
+    mixed = args.precision == "mixed"
+    prec = vmc.VMC_MIXED if mixed else vmc.VMC_FP64
     log = open(args.log, "w") if args.log else None
-
-    def one_step(k: int, n_equil: int):
-        Rh = R.cpu().numpy()
-        Cm = vmc.vmc_huckel_params(Rh, wl.zeta, wl.L)
-        out = traj.energy_forces(R, dev(Cm), zeta, n_equil, M, wl.delta, step=k)
-        S = traj.build_S()
-        if state["first"]:
-            S_prev.copy_(S)
-            R_prev.copy_(R)
-            state["first"] = False
-        if log is not None:
-            # copy S before the step (the step keeps it as S_prev): its condition number is the
-            # preconditioner's stiffness ratio
-            state["S_host"] = S.cpu().numpy()
-        rc = vmc.vmc_langevin_step(ctx, R, R_prev, S_prev, out[3:], S, T_ha, Delta, alpha, 0, wl.seed, 0, k, wl.L)
-        if rc != 0:
-            raise RuntimeError(f"langevin step failed: {vmc._lib().vmc_strerror(rc).decode()}")
-        return out
-
-    for k in range(args.warmup):
-        one_step(k, 20 if k == 0 else 5)
-    torch.cuda.synchronize()
-    ctx.reset_kernel_times()
-    ctx.set_profiling(True)
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.warmup, args.warmup + args.steps):
-        ts = time.perf_counter()
-        out = one_step(k, 20 if k == 0 else 5)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - ts)
-        if log is not None:
-            oh = out.cpu().numpy()
-            log.write(json.dumps({"step": k, "E_Ha": float(oh[0]), "sigma_E_Ha": float(oh[1]), "acceptance": float(oh[2]),
-                                  "force_norm": float(np.linalg.norm(oh[3:])),
-                                  "cond_S": float(np.linalg.cond(state["S_host"])), "ms": round(1e3 * lat[-1], 2)}) + "\n")
-            log.flush()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    times = ctx.kernel_times()
-    ctx.set_profiling(False)
-    out_h = out.cpu().numpy()
-
-    value = W * M * args.steps / elapsed
-    nm = sysd.ewald_nmax
-    kset = [(nx, ny, nz) for nx in range(0, nm + 1) for ny in range(-nm, nm + 1) for nz in range(-nm, nm + 1)
-            if 0 < nx * nx + ny * ny + nz * nz <= nm * nm and (nx > 0 or (nx == 0 and (ny > 0 or (ny == 0 and nz > 0))))]
-    nk, nslot = len(kset), len({(ny, nz) for _, ny, nz in kset})
-    nimg = int(not (prec == vmc.VMC_MIXED and float(np.min(wl.zeta)) * (wl.L / 2) ** 2 >= 23.0))
+    lead = run_leg(wl, W, M, prec, args.j1, args.steps, args.warmup, log)
+    times, out_h, sysd = lead["times"], lead["out"], lead["sysd"]
+    nk, nslot, nimg = kernel_space(sysd, wl, mixed)
+    acc = float(out_h[2])
     tkey = traffic_workload_key(args.workload, args.precision, W, args.j1, args.rs)
 
     def kernel_roofline(name):
         ms, n = times[name]
-        parts = work_model(name, N, nk, nslot, nimg, prec == vmc.VMC_MIXED, args.j1 > 0)
+        parts = work_model(name, N, nk, nslot, nimg, mixed, args.j1 > 0, acc)
+        executed = executed_model(name, N, nk, nslot, nimg, mixed, args.j1 > 0, acc)
         avg_s = ms / max(n, 1) / 1e3
         flops, achieved, peak = roofline_numbers(parts, W, avg_s)
         return {"bound": "alu", "kernel": name, "achieved": round(achieved, 3), "peak": round(peak, 2),
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4) if peak else None,
                 "traffic": measured_traffic(name, tkey), "avg_launch_ms": round(avg_s * 1e3, 4),
-                "algorithmic_flop_per_launch": flops,
-                "flop_per_walker_by_unit": {u: round(f) for u, f in parts.items()}}
+                "algorithmic_flop_per_launch": round(flops), "algorithmic_flop_per_walker_by_unit":
+                    {u: round(f) for u, f in parts.items()},
+                "executed_flop_per_launch": round(sum(executed.values()) * W),
+                "executed_tflops": round(sum(executed.values()) * W / avg_s / 1e12, 3), "acceptance": round(acc, 4)}
 
     # the dominant kernel by total time in the timed region; the sweep and the measurement take
-    # nearly the same total time at h128 (105 launches of 1.35 ms against 100 of 2.8 ms), so the
-    # runner-up is reported beside it with its share of the dominant kernel's time
+    # nearly the same total time at 128 protons, so the runner-up is reported beside it
     ranked = sorted(times.items(), key=lambda kv: -kv[1][0])
     roofline = kernel_roofline(ranked[0][0])
     if len(ranked) > 1 and ranked[1][1][0] > 0:
@@ -554,11 +611,25 @@ def main():
         for kname, (ms, n) in sorted(times.items(), key=lambda kv: -kv[1][0]):
             print(f"{kname:16s} {ms:10.2f} ms  {n:6d} launches  {ms / max(n, 1):9.4f} ms/launch", file=sys.stderr)
 
+    fp64 = None
+    if mixed and args.fp64_steps > 0:
+        # the plain FP64 GPU path on the same workload, a few steps
+        r = run_leg(wl, W, M, vmc.VMC_FP64, args.j1, args.fp64_steps, 1)
+        fp64 = {"value": round(r["value"], 1), "unit": "walker-sweeps/s", "steps": r["steps"], "warmup": 1,
+                "ms_per_step": round(1e3 * r["elapsed"] / r["steps"], 2),
+                "langevin_steps_per_s": round(r["steps"] / r["elapsed"], 4),
+                "mixed_over_fp64": round(lead["value"] / r["value"], 3), "E_Ha": float(r["out"][0])}
+
+    served = None
+    if args.serve_leg > 0 and args.workload == "h128":
+        served = serve_stream(args.serve_leg, 2, 10, args.serve_rate, args.serve_budget_gb)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
+        host = cpu_host_info()
         Cm0, _ = O.huckel(wl.R, wl.zeta, wl.L, N // 2)
-        threads = min(os.cpu_count() or 1, 16)
+        threads = max(1, min(args.cpu_threads, host["usable"] or 1))
         cw = args.cpu_walkers or (192 if N <= 128 else 16)
         cs = args.cpu_sweeps or (6 if N <= 128 else 2)
         v, dt = run_cpu_baseline(wl, Cm0, cw, cs, threads, args.j1)
@@ -566,25 +637,24 @@ def main():
         w1 = 8 if N <= 128 else 2
         v1, dt1 = run_cpu_baseline(wl, Cm0, w1, 2 if N <= 128 else 1, 1, args.j1)
         cpu = {"value": round(v, 3), "unit": "walker-sweeps/s", "cores": threads, "kind": "oracle",
-               "value_one_core": round(v1, 3),
+               "value_one_core": round(v1, 3), "host": host,
                "sample": f"{cw} walkers x (1 unmeasured + {cs} measured) sweeps of the "
-                         f"same N={N} box in FP64, {dt:.1f} s; one core: {w1} walkers x "
-                         f"(1 + {2 if N <= 128 else 1}) sweeps, {dt1:.1f} s"}
-    lat_ms = sorted(1e3 * x for x in lat)
-    p = lambda q: lat_ms[min(len(lat_ms) - 1, int(math.ceil(q * len(lat_ms))) - 1)]
+                         f"same N={N} box in FP64 on {threads} threads ({dt:.1f} s; the CPU share of one GPU on "
+                         f"this host is 16 threads); one core: {w1} walkers x (1 + {2 if N <= 128 else 1}) "
+                         f"sweeps, {dt1:.1f} s"}
     line = {
-        "metric": METRIC, "value": round(value, 1), "unit": "walker-sweeps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "metric": METRIC, "value": round(lead["value"], 1), "unit": "walker-sweeps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * lead["elapsed"] / args.steps, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32/f64" if prec == vmc.VMC_MIXED else "f64", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {N} H + {N} e-, r_s={rs}, T={wl.T_kelvin:g} K, {W} walkers x {M} "
+        "dtype": "f32/f64" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {N} H + {N} e-, r_s={wl.rs}, T={wl.T_kelvin:g} K, {W} walkers x {M} "
                                f"measured (+5 re-equilibration) sweeps per Langevin step, {args.precision} precision"
                                + (f", one-body Jastrow b_1={args.j1:g}" if args.j1 > 0 else ""),
                    "N": N, "walkers": W, "sweeps": M, "precision": args.precision, "one_body_b1": args.j1},
-        "langevin_steps_per_s": round(args.steps / elapsed, 4),
-        "step_latency_ms": {"p50": round(p(0.5), 1), "p99": round(p(0.99), 1)},
-        "E_Ha": float(out_h[0]), "sigma_E_Ha": float(out_h[1]), "acceptance": float(out_h[2]),
-        "roofline": roofline, "cpu_baseline": cpu,
+        "langevin_steps_per_s": round(args.steps / lead["elapsed"], 4),
+        "step_latency_ms": {"p50": round(lead["p50"], 1), "p99": round(lead["p99"], 1)},
+        "E_Ha": float(out_h[0]), "sigma_E_Ha": float(out_h[1]), "acceptance": acc,
+        "roofline": roofline, "fp64_gpu": fp64, "served": served, "cpu_baseline": cpu,
         "kernel_ms": {k: round(v[0], 2) for k, v in times.items()},
     }
     print(json.dumps(line))

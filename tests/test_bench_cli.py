@@ -15,18 +15,27 @@ def test_multi_gpu_request_exits_with_message():
 def test_work_model_and_effective_peak():
     sys.path.insert(0, ROOT)
     import bench
-    mixed = bench.work_model("slater_sample", 128, 1527, 253, 0, True)
-    fp64 = bench.work_model("slater_sample", 128, 1527, 253, 1, False)
-    gemm = 2 * 128 * 64 * 64
-    # the three contractions of both spins: 6 x (2 N NS^2) flops per walker and sample
-    assert mixed["mfma_f64"] + mixed["mfma_f32"] == 6 * gemm == fp64["mfma_f64"]
-    assert fp64["valu"] > mixed["valu"]          # three Gaussian images per axis instead of one
+    N, NS = 128, 64
+    mixed = bench.work_model("slater_sample", N, 1527, 253, 0, True)
+    fp64 = bench.work_model("slater_sample", N, 1527, 253, 1, False)
+    gemm = 2 * N * NS * NS
+    # the three contractions of both spins, 6 x (2 N NS^2) flops per walker and sample: B = C A^-1
+    # in FP64, M = X B and W = B M on the FP32 matrix cores in mixed precision
+    assert mixed["f64"] == 2 * gemm and mixed["f32_mfma"] == 4 * gemm
+    assert set(fp64) == {"f64"} and fp64["f64"] > 6 * gemm
+    assert fp64["f64"] - 6 * gemm > mixed["f32"]       # three Gaussian images per axis instead of one
     tot1, _, pk = bench.roofline_numbers(mixed, 1, 1e-3)
     tot2, ach, pk2 = bench.roofline_numbers(mixed, 16384, 1e-3)
     assert tot2 == 16384 * tot1 and pk == pk2
-    assert bench.PEAK["valu"] < pk < bench.PEAK["mfma_f32"]
-    # the sweep's matrix-core work: M' = Phi' C, P = M' A^-1 and the rank-16 updates, 4 N NS^2
-    assert bench.work_model("sweep_half", 128, 1527, 253, 0, True)["mfma_f64"] == 4 * 128 * 64 * 64
+    assert bench.PEAK["f64"] < pk < bench.PEAK["f32"]
+    # the sweep: the method's count per move (MO row, ratio, acceptance-weighted Sherman-Morrison
+    # update in FP64; basis values and Jastrow change in FP32), and the padded work it executes
+    sw = bench.work_model("sweep_half", N, 1527, 253, 0, True, acc=0.5)
+    assert sw["f64"] == NS * (2 * N * NS + 2 * NS + 0.5 * 4 * NS * NS)
+    assert sw["f32"] == NS * (N * (3 * 5 + 2) + 30 * (N - 1))
+    ex = bench.executed_model("sweep_half", N, 1527, 253, 0, True, acc=0.5)
+    assert ex["f64"] == 2 * NS * N * NS + 4 * NS ** 3 + 16 * NS * NS
+    assert sum(ex.values()) > sum(sw.values())
 
 
 def test_traffic_is_reported_only_for_the_profiled_workload():

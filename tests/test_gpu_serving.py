@@ -130,6 +130,24 @@ def test_large_box_alone_equals_in_mix(dev):
     say(f"  ticks {info['ticks']}, peak resident {info['peak_resident'] / 1e9:.2f} GB")
 
 
+def test_large_box_full_size_alone_equals_in_mix(dev):
+    """The large mixed form at its full size: the 256-proton box with 32,768 walkers served in
+    one request loop with eight 54-proton boxes of 4,096 walkers (all mixed precision, one
+    Langevin step of a few sweeps each) equals itself served alone, bit for bit, and so does
+    one of the small boxes."""
+    torch, vmc, ctx = dev
+    big = spec("h256", 32768, 1, traj=50, steps=1, M=1, ne1=1)
+    small = [spec("h54", 4096, 1, traj=51 + i, steps=1, M=2, ne1=1) for i in range(8)]
+    say("[large box full size alone vs mix] N=256 W=32768 with eight N=54 W=4096")
+    alone = [serve(vmc, ctx, [s])[0][0] for s in (big, small[3])]
+    mixed, info = serve(vmc, ctx, small[:3] + [big] + small[3:])
+    assert all(st[0] == vmc.VMC_REQ_DONE for st, _ in mixed)
+    for (sa, ra), (sm, rm) in zip(alone, [mixed[3], mixed[4]]):
+        assert sa[0] == sm[0] == vmc.VMC_REQ_DONE
+        assert np.array_equal(ra["R"], rm["R"]) and np.array_equal(ra["E"], rm["E"])
+    say(f"  ticks {info['ticks']}, peak resident {info['peak_resident'] / 1e9:.2f} GB")
+
+
 def test_budget_bounds_residency(dev):
     torch, vmc, ctx = dev
     specs = [spec("h16", 256, 0, traj=20 + i, steps=1) for i in range(5)]
