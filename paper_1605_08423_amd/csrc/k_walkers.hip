@@ -625,10 +625,10 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
                 pade_u<Real>(so, co, ts[tt], tc_[tt], LoverPi, aa, bj);
         }
       }
-      // xor-butterfly sum kept in vector registers: every lane adds the same two
-      // partial sums at every step, so all lanes hold the identical total and the
-      // acceptance test below takes the same branch in every lane
-      double dU = wave_allsum((double)du);
+      // xor-butterfly sum kept in vector registers, in the precision of the pair terms: every
+      // lane adds the same two partial sums at every step, so all lanes hold the identical
+      // total and the acceptance test below takes the same branch in every lane
+      double dU = (double)wave_allsum(du);
       if (one_body) dU += D1[i];
       // the Jastrow factor in the working precision of the Jastrow terms
       const double pacc = q * q * (double)dev_exp<Real>((Real)(2.0 * dU));
