@@ -22,7 +22,7 @@ STEP_CFOLD, STEP_NOISE_CORR, STEP_NO_SCORR = 1, 2, 4
 def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc -O2 (no fast-math) and OpenMP over walkers."""
     cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-o", LIB_PATH,
-           os.path.join(HERE, "vmc_oracle.c"), "-lm"]
+           os.path.join(HERE, "vmc_oracle.c"), os.path.join(HERE, "vmc_oracle_complex.c"), "-lm"]
     subprocess.run(cmd, check=True, capture_output=not verbose)
     return LIB_PATH
 
@@ -78,6 +78,15 @@ def _setup(l):
     l.o_toy_run.argtypes = [d, d, d, d, i, d, d, d, i, u32, u32, i, P(d), P(d), P(d)]
     l.o_toy_S.argtypes = [d, d, d, d, i, P(d), P(d)]
     l.o_toy_S.restype = None
+    l.o_cbasis.argtypes = [P(OSys), P(d), i, P(d), P(d)]
+    l.o_cbasis.restype = None
+    l.o_cbasis_values.argtypes = [P(OSys), P(d), i, P(d), P(d)]
+    l.o_cbasis_values.restype = None
+    l.o_coverlap.argtypes = [i, d, P(d), P(d), P(d), P(d)]
+    l.o_coverlap.restype = None
+    l.o_chuckel.argtypes = [i, d, P(d), P(d), P(d), i, P(d), P(d)]
+    l.o_clocal.argtypes = [P(OSys), P(d), P(d), P(d), P(d), P(d), P(d), P(d), P(d)]
+    l.o_cvmc_run_from.argtypes = [P(OSys), P(d), P(d), i, u32, P(d), i, i, d, u32, u32, u32, P(d), P(C.c_int64), i]
 
 
 class System:
@@ -154,6 +163,83 @@ class System:
         if rc:
             raise RuntimeError(f"o_vmc_run failed rc={rc}")
         return sums, nacc
+
+
+class CSystem(System):
+    """A System with a general twist theta (radians, per axis) and complex orbitals Cc
+    (n_p x n_orb complex): the Bloch-summed Gaussian basis of vmc_oracle_complex.c."""
+
+    def __init__(self, R, zeta, Cc, theta, L, **kw):
+        Cc = np.ascontiguousarray(Cc, dtype=np.complex128).reshape(len(zeta), -1)
+        super().__init__(R, zeta, np.zeros(Cc.shape), L=L, **kw)
+        self.theta = np.ascontiguousarray(theta, dtype=np.float64).reshape(3)
+        self.Cc = Cc
+        self.Cpairs = np.ascontiguousarray(Cc.view(np.float64))
+
+    def cbasis(self, a, r):
+        out = np.zeros(28)
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        lib().o_cbasis(C.byref(self.s), _dp(self.theta), a, _dp(r), _dp(out))
+        return out.view(np.complex128)
+
+    def cbasis_values(self, pts):
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        out = np.zeros((pts.shape[0], self.n_p, 2))
+        lib().o_cbasis_values(C.byref(self.s), _dp(self.theta), pts.shape[0], _dp(pts), _dp(out))
+        return out.view(np.complex128)[..., 0]
+
+    def local(self, x, derivs=True):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        lnpsi, phase, EL = np.zeros(1), np.zeros(1), np.zeros(1)
+        dl = np.zeros(3 * self.n_p)
+        de = np.zeros(3 * self.n_p)
+        rc = lib().o_clocal(C.byref(self.s), _dp(self.theta), _dp(self.Cpairs), _dp(x), _dp(lnpsi), _dp(phase),
+                            _dp(EL), _dp(dl) if derivs else None, _dp(de) if derivs else None)
+        if rc:
+            raise RuntimeError(f"o_clocal failed rc={rc}")
+        return dict(lnpsi=lnpsi[0], phase=phase[0], EL=EL[0], dlnpsi=dl, dEL=de)
+
+    def vmc_run(self, x, n_equil, n_meas, delta, seed, traj=0, step=0, threads=0, walker0=0):
+        assert x.dtype == np.float64 and x.flags.c_contiguous
+        W = x.shape[0]
+        n3 = 3 * self.n_p
+        sums = np.zeros((W, 2 + 3 * n3))
+        nacc = np.zeros(W, dtype=np.int64)
+        rc = lib().o_cvmc_run_from(C.byref(self.s), _dp(self.theta), _dp(self.Cpairs), W, walker0, _dp(x), n_equil,
+                                   n_meas, delta, seed, traj, step, _dp(sums),
+                                   nacc.ctypes.data_as(C.POINTER(C.c_int64)), threads)
+        if rc:
+            raise RuntimeError(f"o_cvmc_run failed rc={rc}")
+        return sums, nacc
+
+
+def coverlap(R, zeta, L, theta):
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    zeta = np.ascontiguousarray(zeta, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    n = zeta.size
+    S = np.zeros((n, n, 2))
+    lib().o_coverlap(n, L, _dp(theta), _dp(R), _dp(zeta), _dp(S))
+    return S.view(np.complex128)[..., 0]
+
+
+def chuckel(R, zeta, L, n_orb, theta):
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    zeta = np.ascontiguousarray(zeta, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    n = zeta.size
+    Cm = np.zeros((n, n_orb, 2))
+    ev = np.zeros(n)
+    rc = lib().o_chuckel(n, L, _dp(theta), _dp(R), _dp(zeta), n_orb, _dp(Cm), _dp(ev))
+    if rc:
+        raise RuntimeError("o_chuckel failed")
+    return Cm.view(np.complex128)[..., 0], ev
+
+
+def monkhorst_pack(q=4):
+    """Twists of the q x q x q Monkhorst-Pack mesh: theta_m = 2 pi (2 n - q - 1) / (2 q), n = 1..q."""
+    t = [2.0 * np.pi * (2 * n - q - 1) / (2 * q) for n in range(1, q + 1)]
+    return np.array([(a, b, c) for a in t for b in t for c in t])
 
 
 def philox(ctr, key):

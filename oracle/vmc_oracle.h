@@ -74,6 +74,19 @@ int o_toy_run(double lambda, double k, double a, double mu, int s_kind, double T
 void o_normals(uint32_t seed, uint32_t traj, uint32_t step, int n, double* xi);
 void o_toy_S(double lambda, double k, double a, double mu, int s_kind, const double x[2], double S[4]);
 
+/* General (complex) twisted boundary conditions, vmc_oracle_complex.c: theta[3] the twist
+ * angles, complex arrays as (real, imaginary) pairs. */
+void o_cbasis(const osys* s, const double theta[3], int a, const double r[3], double out[28]);
+void o_cbasis_values(const osys* s, const double theta[3], int npt, const double* pts, double* out);
+void o_coverlap(int n_p, double L, const double theta[3], const double* R, const double* zeta, double* S_out);
+int o_chuckel(int n_p, double L, const double theta[3], const double* R, const double* zeta, int n_orb, double* C,
+              double* evals);
+int o_clocal(const osys* s, const double theta[3], const double* Cd, const double* x, double* lnpsi, double* phase,
+             double* EL, double* dlnpsi_dR, double* dEL_dR);
+int o_cvmc_run_from(const osys* s, const double theta[3], const double* Cd, int W, uint32_t w0, double* x,
+                    int n_equil, int n_meas, double delta, uint32_t seed, uint32_t traj, uint32_t step, double* sums,
+                    int64_t* n_acc, int n_threads);
+
 #define O_STEP_CFOLD 1u
 #define O_STEP_NOISE_CORR 2u
 #define O_STEP_NO_SCORR 4u
