@@ -86,6 +86,18 @@ typedef struct {
                          theta_m = pi (the orbitals change sign across the cell along axis m),
                          clear means theta_m = 0.  0..7; the Jastrow factor stays periodic.  C must
                          be the orbitals of the same twist (vmc_huckel_params_twist) */
+  int general_twist;  /* 1: twisted boundary conditions with the angles theta below (SI, basis section;
+                         the paper averages over a 4 x 4 x 4 Monkhorst-Pack mesh of them): each
+                         Gaussian is the Bloch sum phi_a(r) = sum_n e^{-i theta.n} g_a(r - R_a + n L),
+                         so phi(r + n L) = e^{i theta.n} phi(r); orbitals, Slater matrices and
+                         determinants are complex, sampling follows |psi|^2 and the estimators take
+                         the real part of E_L and of its proton derivative.  Requires precision
+                         VMC_FP64, twist = 0, j1_b1 = 0 and N_sigma <= 64 (else VMC_EINVAL).  The
+                         orbital coefficients C are then complex, N x N/2 (re, im) pairs of doubles
+                         (vmc_huckel_params_theta); Binv holds complex inverses (twice the bytes).
+                         Both spins use the same twist.  Not for the server (VMC_EINVAL).
+                         0: real orbitals, twist as above */
+  double theta[3];    /* twist angles per axis, radians (general_twist = 1 only; finite) */
 } vmc_system;
 
 /* ---------------------------------------------------------------- context -- */
@@ -154,6 +166,11 @@ int vmc_traj_step_count(vmc_traj* traj, uint32_t* steps);
  * refine_tol) and carried through the N/2 moves of a half-sweep by Sherman-
  * Morrison updates applied in blocks of 16 moves (delayed, same ratios).
  * After each measured sweep: E_L, dE_L/dR and dln|psi|/dR.
+ * With a general twist (vmc_system.general_twist) C_dev is complex; each half-sweep forms the
+ * spin's Slater matrix afresh and inverts it (complex Gauss-Jordan elimination with partial
+ * pivoting) before the first sweep and every 4th one, and otherwise carries the inverse of the
+ * previous half-sweep; the moves update it by plain Sherman-Morrison steps, the acceptance is
+ * u_acc < |psi'/psi|^2 with complex ratios, and E_L, dE_L/dR in the outputs are the real parts.
  * Output out_dev (3 + 3N doubles): [E, sigma_E, acceptance, f(3N)] with
  * E = mean_w e_w, sigma_E = sd_w(e_w)/sqrt(W), f = mean_w f_w,
  * f_w = -(<dE_L/dR>_w + 2(<E_L dln|psi|/dR>_w - E <dln|psi|/dR>_w)).
@@ -294,6 +311,17 @@ int vmc_huckel_params(int n_protons, double box_L, const double* R, const double
 /* The same for the twisted basis (twist as in vmc_system): image n of the overlap sum carries
  * prod_m (+-1)^{n_m}.  twist = 0 is vmc_huckel_params; outside 0..7: VMC_EINVAL. */
 int vmc_huckel_params_twist(int n_protons, double box_L, int twist, const double* R, const double* zeta,
+                            double* C_out);
+
+/* The same for a general twist (vmc_system.general_twist): image n of the overlap sum carries
+ * e^{-i theta.n}, S and H are Hermitian, and C_out receives N x N/2 complex coefficients as
+ * (re, im) pairs of doubles (2 N * N/2 doubles).  The lowest N/2 eigenvectors of H are those of
+ * the real symmetric 2N x 2N matrix [[Re H, -Im H], [Im H, Re H]] (each eigenvalue of H appears
+ * twice there); the N/2 orthonormal complex vectors are taken from the lowest N of those by
+ * Gram-Schmidt with column pivoting.  Any unitary mix of the occupied orbitals gives the same
+ * |psi|, so C is defined up to one.  VMC_EINVAL for a non-finite R, theta or zeta <= 0,
+ * VMC_ENOCONV if the QR iteration does not converge. */
+int vmc_huckel_params_theta(int n_protons, double box_L, const double* theta, const double* R, const double* zeta,
                             double* C_out);
 
 /* Twist averaging (SI: the paper averages its estimates over a mesh of twists): n_tw

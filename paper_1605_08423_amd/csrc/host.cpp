@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 
 namespace vmc_host {
@@ -261,6 +262,86 @@ extern "C" int vmc_huckel_params_twist(int n, double L, int twist, const double*
   return VMC_OK;
 }
 
+
+extern "C" int vmc_huckel_params_theta(int n, double L, const double* theta, const double* R, const double* zeta,
+                                       double* C_out) {
+  if (n < 2 || (n & 1) || !(L > 0.0) || !theta || !R || !zeta || !C_out) return VMC_EINVAL;
+  for (int m = 0; m < 3; ++m)
+    if (!std::isfinite(theta[m])) return VMC_EINVAL;
+  for (int i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(R[i])) return VMC_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!(zeta[i] > 0.0) || !std::isfinite(zeta[i])) return VMC_EINVAL;
+  using cplx = std::complex<double>;
+  // S_ab = (pi/(za+zb))^{3/2} prod_m sum_k e^{-i theta_m k} e^{-mu (d_m + k L)^2}, d = R_a - R_b taken at
+  // its minimum image d - j L, which multiplies the sum by e^{i theta_m j}
+  std::vector<cplx> S((size_t)n * n);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const double za = zeta[a], zb = zeta[b], mu = za * zb / (za + zb);
+      cplx v = std::pow(M_PI / (za + zb), 1.5);
+      for (int ax = 0; ax < 3; ++ax) {
+        double dd = R[3 * a + ax] - R[3 * b + ax];
+        const double j = std::floor(dd / L + 0.5);
+        dd -= L * j;
+        cplx sum = 0.0;
+        for (int k = -3; k <= 3; ++k) sum += std::polar(std::exp(-mu * (dd + k * L) * (dd + k * L)), -theta[ax] * k);
+        v *= sum * std::polar(1.0, theta[ax] * j);
+      }
+      S[(size_t)a * n + b] = v;
+    }
+  // H = -S_ab / sqrt(S_aa S_bb) (Hermitian) through its real symmetric embedding of order 2n
+  const int n2 = 2 * n;
+  std::vector<double> M((size_t)n2 * n2), Q;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const cplx h = -S[(size_t)a * n + b] / std::sqrt(S[(size_t)a * n + a].real() * S[(size_t)b * n + b].real());
+      M[(size_t)a * n2 + b] = h.real();
+      M[(size_t)(a + n) * n2 + b + n] = h.real();
+      M[(size_t)a * n2 + b + n] = -h.imag();
+      M[(size_t)(a + n) * n2 + b] = h.imag();
+    }
+  householder_tridiag(n2, M, Q);
+  int rc = tridiag_qr(n2, M, Q);
+  if (rc) return rc;
+  std::vector<int> order(n2);
+  for (int i = 0; i < n2; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return M[(size_t)x * n2 + x] < M[(size_t)y * n2 + y]; });
+  // the lowest n embedded eigenvectors (x, y) give n complex vectors x + i y spanning the n/2
+  // lowest eigenvectors of H; Gram-Schmidt, each time on the candidate of largest residual
+  const int no = n / 2;
+  std::vector<std::vector<cplx>> z(n, std::vector<cplx>(n));
+  for (int c = 0; c < n; ++c)
+    for (int a = 0; a < n; ++a) z[c][a] = cplx(Q[(size_t)a * n2 + order[c]], Q[(size_t)(a + n) * n2 + order[c]]);
+  std::vector<bool> used(n, false);
+  for (int k = 0; k < no; ++k) {
+    int best = -1;
+    double bn = -1.0;
+    for (int c = 0; c < n; ++c) {
+      if (used[c]) continue;
+      double nn = 0.0;
+      for (int a = 0; a < n; ++a) nn += std::norm(z[c][a]);
+      if (nn > bn) { bn = nn; best = c; }
+    }
+    if (best < 0 || !(bn > 0.0)) return VMC_ENOCONV;
+    used[best] = true;
+    const double inv = 1.0 / std::sqrt(bn);
+    for (int a = 0; a < n; ++a) z[best][a] *= inv;
+    for (int c = 0; c < n; ++c) {
+      if (used[c]) continue;
+      cplx p = 0.0;
+      for (int a = 0; a < n; ++a) p += std::conj(z[best][a]) * z[c][a];
+      for (int a = 0; a < n; ++a) z[c][a] -= p * z[best][a];
+    }
+    for (int a = 0; a < n; ++a) {
+      const cplx ca = z[best][a] / std::sqrt(S[(size_t)a * n + a].real());
+      C_out[2 * ((size_t)a * no + k)] = ca.real();
+      C_out[2 * ((size_t)a * no + k) + 1] = ca.imag();
+    }
+  }
+  return VMC_OK;
+}
 
 extern "C" int vmc_server_admit_count(size_t budget, size_t resident, int n_queued, const size_t* bytes) {
   if (n_queued < 0 || (n_queued > 0 && !bytes)) return -1;

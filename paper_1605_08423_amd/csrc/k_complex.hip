@@ -1,0 +1,629 @@
+// General twisted boundary conditions (SI, basis section): with twist angles theta the basis
+// obeys phi(r + n L) = e^{i theta.n} phi(r), so orbitals, Slater matrices and determinants are
+// complex, |psi|^2 = |D_up|^2 |D_dn|^2 e^{2U} and the local energy is complex; its real part is
+// the estimator.  FP64 throughout.
+//
+//   phi_a(r) = prod_m g_m(r_m - R_am),  g_m(d) = sum_n e^{-i theta_m n} e^{-zeta_a (d + n L)^2},
+// evaluated at the minimum image x = d - k L over the images n = -1, 0, 1, times e^{i theta_m k}.
+//
+// Layout in HBM (a complex number is a (re, im) pair of doubles):
+//   C    [N][NS]           orbital coefficients
+//   Binv [W][2][NS][NS]    (A^-1)[k][i] of A[i][k] = sum_a phi_a(r_i) C[a][k]
+//   ldet [W][2], sgn[W][2] ln|det A| and arg det A (the moves keep them current)
+// Kernels:
+//   k_csweep          one work-group per walker and spin.  With `refresh` it forms A on the
+//                     matrix cores and inverts it by Gauss-Jordan elimination in LDS, else it reads
+//                     the inverse; then it moves the spin's electrons in order with
+//                     Sherman-Morrison updates of the inverse held in LDS.  All proposals of the
+//                     spin are drawn up front and their orbital rows formed together on the matrix
+//                     cores: a proposal depends only on its own electron, which no earlier move
+//                     of the spin displaces.
+//   k_cslater_sample  Re E_L, d ln|psi|/dR and d Re E_L/dR by the contractions of the real
+//                     measurement in complex arithmetic (B = C A^-1, M = X B, W = B M).
+#include "common.hpp"
+#include "kernels.hpp"
+#include "moves.hpp"
+
+namespace vmc {
+
+namespace {
+
+struct cd {
+  double r, i;
+};
+__device__ __forceinline__ cd cmul(cd a, cd b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return {a.r - b.r, a.i - b.i}; }
+// real part of a b
+__device__ __forceinline__ double remul(cd a, cd b) { return a.r * b.r - a.i * b.i; }
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+// One complex 16x16x4 step on the FP64 matrix cores, (Dr + i Di) += (A_r + i A_i)(B_r + i B_i):
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; element v of the result is
+// D[l / 16 + 4 v][l % 16].
+__device__ __forceinline__ void cmfma(cd av, cd bv, v4d& dr, v4d& di) {
+  dr = __builtin_amdgcn_mfma_f64_16x16x4f64(av.r, bv.r, dr, 0, 0, 0);
+  dr = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.i, bv.i, dr, 0, 0, 0);
+  di = __builtin_amdgcn_mfma_f64_16x16x4f64(av.r, bv.i, di, 0, 0, 0);
+  di = __builtin_amdgcn_mfma_f64_16x16x4f64(av.i, bv.r, di, 0, 0, 0);
+}
+
+// One Cartesian factor of the Bloch-summed Gaussian and its first NDER derivatives at the raw
+// offset d along axis m.
+template <int NDER>
+__device__ __forceinline__ void cbasis_axis(double d, double zeta, double L, double invL, const TwistArgs& tw, int m,
+                                            cd g[4]) {
+  const double k = floor(d * invL + 0.5);
+  const double x = d - L * k;
+  double h[3][4];
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    const double t = x + (double)(n - 1) * L;
+    const double e = exp(-zeta * t * t);
+    h[n][0] = e;
+    if (NDER >= 1) h[n][1] = -2.0 * zeta * t * e;
+    if (NDER >= 2) h[n][2] = (4.0 * zeta * zeta * t * t - 2.0 * zeta) * e;
+    if (NDER >= 3) h[n][3] = (-8.0 * zeta * zeta * zeta * t * t * t + 12.0 * zeta * zeta * t) * e;
+  }
+  // image n weighs e^{-i theta n}: n = -1 -> c + i s, n = 0 -> 1, n = 1 -> c - i s
+  const double c = tw.c[m], s = tw.s[m];
+#pragma unroll
+  for (int q = 0; q <= NDER; ++q) g[q] = {h[1][q] + c * (h[0][q] + h[2][q]), s * (h[0][q] - h[2][q])};
+  if (k != 0.0) {
+    double pc, ps;
+    if (k == 1.0) { pc = c; ps = s; }
+    else if (k == -1.0) { pc = c; ps = -s; }
+    else sincos(tw.th[m] * k, &ps, &pc);
+#pragma unroll
+    for (int q = 0; q <= NDER; ++q) g[q] = cmul(g[q], cd{pc, ps});
+  }
+}
+
+__device__ __forceinline__ cd cphi(double rx, double ry, double rz, const double* Ra, double zeta, double L,
+                                   double invL, const TwistArgs& tw) {
+  cd g[3][4];
+  cbasis_axis<0>(rx - Ra[0], zeta, L, invL, tw, 0, g[0]);
+  cbasis_axis<0>(ry - Ra[1], zeta, L, invL, tw, 1, g[1]);
+  cbasis_axis<0>(rz - Ra[2], zeta, L, invL, tw, 2, g[2]);
+  return cmul(cmul(g[0][0], g[1][0]), g[2][0]);
+}
+
+__device__ __forceinline__ cd ld_c(const double* p, size_t idx) {
+  const double2 v = *reinterpret_cast<const double2*>(p + 2 * idx);
+  return {v.x, v.y};
+}
+__device__ __forceinline__ void st_c(double* p, size_t idx, cd v) {
+  *reinterpret_cast<double2*>(p + 2 * idx) = make_double2(v.r, v.i);
+}
+
+// Deterministic sum over a 256-thread block (waves combined in a fixed order); every thread
+// gets the result.
+__device__ __forceinline__ double csum256(double v, double* red4) {
+  v = wave_allsum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return ((red4[0] + red4[1]) + red4[2]) + red4[3];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- half sweep ---
+template <int NS>
+struct CSweepLds {
+  static constexpr int N = 2 * NS, NSP = (NS + 15) / 16 * 16, LDA = NSP + 1;
+  static constexpr int P = (256 / NS) < NS ? (256 / NS) : NS;   // partial sums of a row product
+  static constexpr int CH = (NS + P - 1) / P;                    // their k range
+  static constexpr int RPT = 256 / NS;                           // rows per pass of an NS-wide update
+  // offsets in doubles; the proposals' orbital rows come last (absent in a refresh-only launch)
+  static constexpr size_t ainv = 0, pos = ainv + 2 * (size_t)NSP * LDA, trig = pos + 3 * N, prop = trig + 6 * N,
+                          ptrig = prop + 4 * NSP, vpart = ptrig + 6 * NSP, colI = vpart + 2 * (size_t)P * NSP,
+                          prow = colI + 2 * NSP, fcol = prow + 2 * NSP, red = fcol + 2 * NSP, misc = red + 8,
+                          mp = misc + NSP + 8;
+  static constexpr size_t bytes(bool moves) { return sizeof(double) * (moves ? mp + 2 * (size_t)NSP * NSP : mp); }
+};
+
+template <int NS, bool MOVES>
+__global__ __launch_bounds__(256, 1) void k_csweep(WalkerArgs a, SweepArgs s, TwistArgs tw, int refresh) {
+  using LY = CSweepLds<NS>;
+  constexpr int N = 2 * NS, NSP = LY::NSP, LDA = LY::LDA, P = LY::P, CH = LY::CH, RPT = LY::RPT;
+  constexpr int TR = NSP / 16, TC = NSP / 16, KS = (N + 3) / 4;
+  extern __shared__ __align__(16) double smem[];
+  double* Ai = smem + LY::ainv;      // NSP x LDA complex: A, then A^-1
+  double* pos = smem + LY::pos;      // N x 3
+  double* trig = smem + LY::trig;    // N x 6: sin(pi x/L) x3, cos x3
+  double* prop = smem + LY::prop;    // NSP x 4: proposal x, y, z and the acceptance uniform
+  double* ptrig = smem + LY::ptrig;  // NSP x 6
+  double* vpart = smem + LY::vpart;  // P x NSP complex
+  double* colI = smem + LY::colI;    // NSP complex
+  double* prow = smem + LY::prow;    // NSP complex
+  double* fcol = smem + LY::fcol;    // NSP complex
+  double* red = smem + LY::red;      // 8
+  int* perm = reinterpret_cast<int*>(smem + LY::misc);   // NSP pivot rows, then flags
+  int* flag = perm + NSP;
+  double* Mp = smem + LY::mp;        // NSP x NSP complex: orbital rows of the proposals
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int w = blockIdx.x, sp = s.spin;
+  const double L = a.L, invL = a.invL;
+  for (int u = t; u < 3 * N; u += 256) pos[u] = a.pos[(size_t)w * 3 * N + u];
+  __syncthreads();
+  for (int e = t; e < N; e += 256)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) sincospi(pos[3 * e + ax] * invL, &trig[6 * e + ax], &trig[6 * e + 3 + ax]);
+  if (MOVES)
+    for (int i = t; i < NS; i += 256) {
+      double xn, yn, zn, ru;
+      draw_move(s, w, N, sp * NS + i, pos + 3 * (sp * NS + i), s.delta, L, invL, xn, yn, zn, ru);
+      prop[4 * i] = xn; prop[4 * i + 1] = yn; prop[4 * i + 2] = zn; prop[4 * i + 3] = ru;
+      sincospi(xn * invL, &ptrig[6 * i], &ptrig[6 * i + 3]);
+      sincospi(yn * invL, &ptrig[6 * i + 1], &ptrig[6 * i + 4]);
+      sincospi(zn * invL, &ptrig[6 * i + 2], &ptrig[6 * i + 5]);
+    }
+  if (t == 0) flag[0] = 0;
+  const double* Bg = a.Binv + 2 * ((size_t)w * 2 + sp) * NS * NS;
+  if (!refresh)
+    for (int u = t; u < NS * NS; u += 256) st_c(Ai, (u / NS) * LDA + u % NS, ld_c(Bg, u));
+  __syncthreads();
+  // row tiles [0, TR): the spin's electrons (A, refresh only); [TR, 2 TR): the proposals
+  {
+    const int t0 = refresh ? 0 : TR, t1 = MOVES ? 2 * TR : TR;
+    for (int tt = t0 + wave; tt < t1; tt += 4) {
+      const bool isp = tt >= TR;
+      const int rt = isp ? tt - TR : tt;
+      const int row = rt * 16 + (lane & 15);
+      const bool rok = row < NS;
+      const int rr = rok ? row : 0;
+      const double* rp = isp ? prop + 4 * rr : pos + 3 * (sp * NS + rr);
+      const double rx = rp[0], ry = rp[1], rz = rp[2];
+      v4d dr[TC], di[TC];
+#pragma unroll
+      for (int tc = 0; tc < TC; ++tc) { dr[tc] = v4d{0, 0, 0, 0}; di[tc] = v4d{0, 0, 0, 0}; }
+      for (int kk = 0; kk < KS; ++kk) {
+        const int c = kk * 4 + (lane >> 4);
+        cd ph = {0.0, 0.0};
+        if (rok && c < N) ph = cphi(rx, ry, rz, a.R + 3 * c, a.zeta[c], L, invL, tw);
+#pragma unroll
+        for (int tc = 0; tc < TC; ++tc) {
+          const int col = tc * 16 + (lane & 15);
+          const cd cv = (c < N && col < NS) ? ld_c(a.C, (size_t)c * NS + col) : cd{0.0, 0.0};
+          cmfma(ph, cv, dr[tc], di[tc]);
+        }
+      }
+      double* D = isp ? Mp : Ai;
+      const int ldd = isp ? NSP : LDA;
+#pragma unroll
+      for (int tc = 0; tc < TC; ++tc)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          st_c(D, (size_t)(rt * 16 + (lane >> 4) + 4 * v) * ldd + tc * 16 + (lane & 15), cd{dr[tc][v], di[tc][v]});
+    }
+  }
+  __syncthreads();
+  double ldv = 0.0, phv = 0.0;   // meaningful in thread 0
+  if (refresh) {
+    // Gauss-Jordan elimination with partial pivoting, in place; row swaps are undone on the
+    // columns at the end.  A pivot below N_sigma eps max|A_ij| counts as zero: with complex
+    // multipliers even two equal rows leave a rounding-sized pivot, not an exact zero.
+    {
+      double am = 0.0;
+      for (int u = t; u < NS * NS; u += 256) {
+        const cd v = ld_c(Ai, (size_t)(u / NS) * LDA + u % NS);
+        am = fmax(am, v.r * v.r + v.i * v.i);
+      }
+      int dummy = 0;
+      wave_argmax(am, dummy);
+      if (lane == 0) red[wave] = am;
+      __syncthreads();
+    }
+    const double tol2 = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * (NS * 2.220446049250313e-16) *
+                        (NS * 2.220446049250313e-16);
+    for (int p = 0; p < NS; ++p) {
+      if (wave == 0) {
+        double mag = -1.0;
+        int idx = lane;
+        if (lane >= p && lane < NS) {
+          const cd v = ld_c(Ai, (size_t)lane * LDA + p);
+          mag = v.r * v.r + v.i * v.i;
+        }
+        wave_argmax(mag, idx);
+        if (lane == 0) {
+          perm[p] = idx;
+          if (!(mag > tol2) || !isfinite(mag)) flag[0] = 1;
+          // the pivot value, read by every thread before the row swap below moves it
+          const cd v = ld_c(Ai, (size_t)idx * LDA + p);
+          red[4] = v.r;
+          red[5] = v.i;
+        }
+      }
+      __syncthreads();
+      if (flag[0]) break;
+      const int r = perm[p];
+      const cd pv = {red[4], red[5]};
+      const double m2 = pv.r * pv.r + pv.i * pv.i;
+      const cd ip = {pv.r / m2, -pv.i / m2};
+      for (int j = t; j < NS; j += 256) {
+        const cd x = ld_c(Ai, (size_t)p * LDA + j), y = ld_c(Ai, (size_t)r * LDA + j);
+        st_c(Ai, (size_t)p * LDA + j, y);
+        st_c(Ai, (size_t)r * LDA + j, x);
+        st_c(prow, j, cmul(j == p ? cd{1.0, 0.0} : y, ip));
+        if (j == p) { st_c(fcol, r, x); st_c(fcol, p, y); }
+      }
+      for (int i = t; i < NS; i += 256)
+        if (i != p && i != r) st_c(fcol, i, ld_c(Ai, (size_t)i * LDA + p));
+      __syncthreads();
+      if (t < RPT * NS) {
+        const int j = t % NS;
+        const cd pj = ld_c(prow, j);
+        for (int i = t / NS; i < NS; i += RPT) {
+          cd v;
+          if (i == p) {
+            v = pj;
+          } else {
+            const cd x = (j == p) ? cd{0.0, 0.0} : ld_c(Ai, (size_t)i * LDA + j);
+            v = csub(x, cmul(ld_c(fcol, i), pj));
+          }
+          st_c(Ai, (size_t)i * LDA + j, v);
+        }
+      }
+      if (t == 0) {
+        ldv += 0.5 * log(m2);
+        phv += atan2(pv.i, pv.r) + (r != p ? VMC_PI : 0.0);
+      }
+      __syncthreads();
+    }
+    if (flag[0]) {
+      if (t == 0) atomicExch(a.status, 1);
+      return;
+    }
+    for (int i = t; i < NS; i += 256)
+      for (int p = NS - 1; p >= 0; --p) {
+        const int r = perm[p];
+        if (r != p) {
+          const cd x = ld_c(Ai, (size_t)i * LDA + p), y = ld_c(Ai, (size_t)i * LDA + r);
+          st_c(Ai, (size_t)i * LDA + p, y);
+          st_c(Ai, (size_t)i * LDA + r, x);
+        }
+      }
+    __syncthreads();
+  } else if (t == 0) {
+    ldv = a.ldet[(size_t)w * 2 + sp];
+    phv = a.sgn[(size_t)w * 2 + sp];
+  }
+  int64_t nadd = 0;
+  if (MOVES) {
+    const double LoP = L / VMC_PI, bj = a.b;
+    for (int i = 0; i < NS; ++i) {
+      const int e = sp * NS + i;
+      // row product v = m' A^-1 in P partial sums; the Jastrow change; column i of A^-1
+      if (t < P * NS) {
+        const int j = t % NS, pp = t / NS;
+        const int k0 = pp * CH, k1 = (k0 + CH < NS) ? k0 + CH : NS;
+        cd acc = {0.0, 0.0};
+        for (int k = k0; k < k1; ++k) acc = cadd(acc, cmul(ld_c(Mp, (size_t)i * NSP + k), ld_c(Ai, (size_t)k * LDA + j)));
+        st_c(vpart, (size_t)pp * NSP + j, acc);
+      }
+      double du = 0.0;
+      if (t < N && t != e) {
+        const double* tj = trig + 6 * t;
+        const double sj[3] = {tj[0], tj[1], tj[2]}, cj[3] = {tj[3], tj[4], tj[5]};
+        const double* to = trig + 6 * e;
+        const double so[3] = {to[0], to[1], to[2]}, co[3] = {to[3], to[4], to[5]};
+        const double* tn = ptrig + 6 * i;
+        const double sn[3] = {tn[0], tn[1], tn[2]}, cn[3] = {tn[3], tn[4], tn[5]};
+        const double aa = (t / NS == sp) ? a.a_par : a.a_anti;
+        du = pade_u<double>(sn, cn, sj, cj, LoP, aa, bj) - pade_u<double>(so, co, sj, cj, LoP, aa, bj);
+      }
+      du = wave_allsum(du);
+      if (lane == 0) red[wave] = du;
+      if (t < NS) st_c(colI, t, ld_c(Ai, (size_t)t * LDA + i));
+      __syncthreads();
+      cd q = {0.0, 0.0};
+      for (int pp = 0; pp < P; ++pp) q = cadd(q, ld_c(vpart, (size_t)pp * NSP + i));
+      const double dU = ((red[0] + red[1]) + red[2]) + red[3];
+      const double q2 = q.r * q.r + q.i * q.i;
+      const double pacc = q2 * exp(2.0 * dU);
+      if (prop[4 * i + 3] < pacc) {
+        const cd iq = {q.r / q2, -q.i / q2};
+        if (t < RPT * NS) {
+          const int j = t % NS;
+          cd vj = {0.0, 0.0};
+          for (int pp = 0; pp < P; ++pp) vj = cadd(vj, ld_c(vpart, (size_t)pp * NSP + j));
+          if (j == i) vj.r -= 1.0;
+          const cd z = cmul(vj, iq);
+          for (int k = t / NS; k < NS; k += RPT)
+            st_c(Ai, (size_t)k * LDA + j, csub(ld_c(Ai, (size_t)k * LDA + j), cmul(ld_c(colI, k), z)));
+        }
+        if (t == 0) {
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) pos[3 * e + ax] = prop[4 * i + ax];
+#pragma unroll
+          for (int u = 0; u < 6; ++u) trig[6 * e + u] = ptrig[6 * i + u];
+          ++nadd;
+          ldv += 0.5 * log(q2);
+          phv += atan2(q.i, q.r);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  double* Bo = a.Binv + 2 * ((size_t)w * 2 + sp) * NS * NS;
+  for (int u = t; u < NS * NS; u += 256) st_c(Bo, u, ld_c(Ai, (size_t)(u / NS) * LDA + u % NS));
+  if (MOVES)
+    for (int u = t; u < 3 * NS; u += 256) a.pos[(size_t)w * 3 * N + 3 * sp * NS + u] = pos[3 * sp * NS + u];
+  if (t == 0) {
+    a.ldet[(size_t)w * 2 + sp] = ldv;
+    a.sgn[(size_t)w * 2 + sp] = remainder(phv, 2.0 * VMC_PI);
+    if (MOVES) a.nacc[w] += nadd;
+  }
+}
+
+// ------------------------------------------------------------ measurement ---
+template <int NS>
+struct CSlaterLay {
+  static constexpr int N = 2 * NS, NSP = (NS + 15) / 16 * 16, NP = (N + 15) / 16 * 16;
+  // per-walker scratch (complex elements): B = C A^-1 (NP x NSP), X (NSP x NP), M = X B (NSP x NSP),
+  // W = B M (NP x NSP)
+  static constexpr size_t b = 0, x = b + (size_t)NP * NSP, mm = x + (size_t)NSP * NP, wm = mm + (size_t)NSP * NSP,
+                          scr_elems = wm + (size_t)NP * NSP;
+  static constexpr int H = 256 / N;          // threads per centre in the pair passes
+  static constexpr int HJ = H > 0 ? H : 1;   // threads per electron in the Jastrow pass
+  // LDS (doubles)
+  static constexpr size_t pos = 0, gU = pos + 3 * N, lU = gU + 3 * N, trig = lU + N, part = trig + 6 * N,
+                          partn = (size_t)(HJ * N * 5 > 256 * 6 ? HJ * N * 5 : 256 * 6), red = part + partn,
+                          bytes = sizeof(double) * (red + 8);
+};
+
+// D (TRr*16 x TCc*16) = A (x K) B (K x), complex, row-major with leading dimensions in complex
+// elements; A outside rows [0, MA) or columns [0, KA), and B outside rows [0, KA) or columns
+// [0, NB), read as zero.  Wave w computes the output tiles w, w + 4, ...; all 64 lanes of a
+// wave run every matrix-core step.
+template <int TRr, int TCc, int KA>
+__device__ __forceinline__ void cgemm(const double* A, int lda, int MA, const double* B, int ldb, int NB, double* D,
+                                      int ldd, int wave, int lane) {
+  constexpr int K4 = (KA + 3) / 4;
+  for (int tt = wave; tt < TRr * TCc; tt += 4) {
+    const int tr = tt / TCc, tc = tt % TCc;
+    const int arow = tr * 16 + (lane & 15), bcol = tc * 16 + (lane & 15);
+    v4d dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+    for (int kk = 0; kk < K4; ++kk) {
+      const int k = kk * 4 + (lane >> 4);
+      const cd av = (arow < MA && k < KA) ? ld_c(A, (size_t)arow * lda + k) : cd{0.0, 0.0};
+      const cd bv = (k < KA && bcol < NB) ? ld_c(B, (size_t)k * ldb + bcol) : cd{0.0, 0.0};
+      cmfma(av, bv, dr, di);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) st_c(D, (size_t)(tr * 16 + (lane >> 4) + 4 * v) * ldd + bcol, cd{dr[v], di[v]});
+  }
+}
+
+// Per walker (one 256-thread block): the Jastrow gradient and Laplacian per electron, then per
+// spin B = C A^-1, the basis pass that forms X and the terms needing only B, M = X B, W = B M and
+// the pass that adds grad phi W; the four products on the FP64 matrix cores through the
+// walker's scratch.
+//   Re T_L = Re sum X_ia B_ai - 1/2 sum_i (lap_i U + |grad_i U|^2),  X_ia = -1/2 [lap phi_a + 2 grad phi_a . grad_i U]
+//   d ln|psi|/dR_b = -Re sum_i B_bi grad phi_b(r_i)
+//   d Re T_L/dR_b = Re sum_i [1/2 (grad lap phi_b + 2 Hess phi_b . grad_i U) B_bi + grad phi_b(r_i) W_bi]
+template <int NS>
+__global__ __launch_bounds__(256, 1) void k_cslater_sample(MeasureArgs m, TwistArgs tw) {
+  using LY = CSlaterLay<NS>;
+  constexpr int N = 2 * NS, NSP = LY::NSP, NP = LY::NP, H = LY::H, HJ = LY::HJ;
+  constexpr int NT = H * N, IPT = (NS + H - 1) / H;
+  extern __shared__ __align__(16) double smem[];
+  double* pos = smem + LY::pos;
+  double* gU = smem + LY::gU;
+  double* lU = smem + LY::lU;
+  double* trig = smem + LY::trig;
+  double* part = smem + LY::part;
+  double* red = smem + LY::red;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int w = blockIdx.x;
+  const double L = m.L, invL = m.invL;
+  double* scr = reinterpret_cast<double*>(m.scr + (size_t)w * 16 * LY::scr_elems);
+  double* Bs = scr + 2 * LY::b;
+  double* Xs = scr + 2 * LY::x;
+  double* Ms = scr + 2 * LY::mm;
+  double* Ws = scr + 2 * LY::wm;
+  for (int u = t; u < 3 * N; u += 256) pos[u] = m.pos[(size_t)w * 3 * N + u];
+  __syncthreads();
+  for (int e = t; e < N; e += 256)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) sincospi(pos[3 * e + ax] * invL, &trig[6 * e + ax], &trig[6 * e + 3 + ax]);
+  __syncthreads();
+  // Jastrow: HJ threads share an electron's pairs, combined in a fixed order
+  double tj = 0.0, usum = 0.0;
+  {
+    const double LoP = L / VMC_PI, kf = (VMC_PI * invL) * (VMC_PI * invL);
+    for (int u = t; u < HJ * N; u += 256) {
+      const int i = u % N, hj = u / N;
+      const int j0 = hj * N / HJ, j1 = (hj + 1) * N / HJ;
+      double g0 = 0, g1 = 0, g2 = 0, lp = 0, ui = 0;
+      const double* ti = trig + 6 * i;
+      for (int j = j0; j < j1; ++j) {
+        if (j == i) continue;
+        const double* tq = trig + 6 * j;
+        double rt[3], cc[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          rt[ax] = LoP * (ti[ax] * tq[3 + ax] - ti[3 + ax] * tq[ax]);
+          cc[ax] = ti[3 + ax] * tq[3 + ax] + ti[ax] * tq[ax];
+        }
+        const double r2 = rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2];
+        const double rho = sqrt(r2), irho = 1.0 / rho;
+        const double aj = ((i / NS) == (j / NS)) ? m.a_par : m.a_anti;
+        const double iden = 1.0 / (1.0 + m.b * rho);
+        const double up = aj * iden * iden, upp = -2.0 * aj * m.b * iden * iden * iden;
+        const double gr0 = rt[0] * cc[0] * irho, gr1 = rt[1] * cc[1] * irho, gr2 = rt[2] * cc[2] * irho;
+        const double gg = gr0 * gr0 + gr1 * gr1 + gr2 * gr2;
+        const double lr = (cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2] - kf * r2) * irho - gg * irho;
+        g0 += up * gr0; g1 += up * gr1; g2 += up * gr2;
+        lp += upp * gg + up * lr;
+        if (j > i) ui += aj * rho * iden;
+      }
+      double* q = part + ((size_t)hj * N + i) * 5;
+      q[0] = g0; q[1] = g1; q[2] = g2; q[3] = lp; q[4] = ui;
+    }
+    __syncthreads();
+    for (int i = t; i < N; i += 256) {
+      double g0 = 0, g1 = 0, g2 = 0, lp = 0, ui = 0;
+      for (int hj = 0; hj < HJ; ++hj) {
+        const double* q = part + ((size_t)hj * N + i) * 5;
+        g0 += q[0]; g1 += q[1]; g2 += q[2]; lp += q[3]; ui += q[4];
+      }
+      gU[3 * i] = g0; gU[3 * i + 1] = g1; gU[3 * i + 2] = g2;
+      lU[i] = lp;
+      tj += -0.5 * (lp + g0 * g0 + g1 * g1 + g2 * g2);
+      usum += ui;
+    }
+  }
+  __syncthreads();
+  const int ca = t % N, h = t / N;
+  const bool act = t < NT;
+  double dln0 = 0, dln1 = 0, dln2 = 0, dT0 = 0, dT1 = 0, dT2 = 0, tsl = 0;
+  const double Ra0 = m.R[3 * ca], Ra1 = m.R[3 * ca + 1], Ra2 = m.R[3 * ca + 2];
+  const double za = m.zeta[ca];
+  for (int sp = 0; sp < 2; ++sp) {
+    const double* Bi = m.Binv + 2 * ((size_t)w * 2 + sp) * NS * NS;
+    // B = C A^-1 (NP x NSP; K = orbitals)
+    cgemm<NP / 16, NSP / 16, NS>(m.C, NS, N, Bi, NS, NS, Bs, NSP, wave, lane);
+    // the padding of X stays zero
+    for (int u = t; u < NSP * NP; u += 256) {
+      const int i = u / NP, c = u % NP;
+      if (i >= NS || c >= N) st_c(Xs, u, cd{0.0, 0.0});
+    }
+    __syncthreads();
+    // pass 1: basis derivatives -> X, and the terms that need only B
+    if (act) {
+      for (int s = 0; s < IPT; ++s) {
+        const int i = h + H * s;
+        if (i >= NS) continue;
+        const int e = sp * NS + i;
+        cd g[3][4];
+        cbasis_axis<3>(pos[3 * e] - Ra0, za, L, invL, tw, 0, g[0]);
+        cbasis_axis<3>(pos[3 * e + 1] - Ra1, za, L, invL, tw, 1, g[1]);
+        cbasis_axis<3>(pos[3 * e + 2] - Ra2, za, L, invL, tw, 2, g[2]);
+        const cd p00 = cmul(g[1][0], g[2][0]), p01 = cmul(g[0][0], g[2][0]), p02 = cmul(g[0][0], g[1][0]);
+        const cd gx = cmul(g[0][1], p00), gy = cmul(g[1][1], p01), gz = cmul(g[2][1], p02);
+        const cd hxx = cmul(g[0][2], p00), hyy = cmul(g[1][2], p01), hzz = cmul(g[2][2], p02);
+        const cd hxy = cmul(cmul(g[0][1], g[1][1]), g[2][0]), hxz = cmul(cmul(g[0][1], g[1][0]), g[2][1]);
+        const cd hyz = cmul(cmul(g[0][0], g[1][1]), g[2][1]);
+        const cd lap = cadd(cadd(hxx, hyy), hzz);
+        const cd glx = cadd(cmul(g[0][3], p00), cmul(g[0][1], cadd(cmul(g[1][2], g[2][0]), cmul(g[1][0], g[2][2]))));
+        const cd gly = cadd(cmul(g[1][3], p01), cmul(g[1][1], cadd(cmul(g[0][2], g[2][0]), cmul(g[0][0], g[2][2]))));
+        const cd glz = cadd(cmul(g[2][3], p02), cmul(g[2][1], cadd(cmul(g[0][2], g[1][0]), cmul(g[0][0], g[1][2]))));
+        const double u0 = gU[3 * e], u1 = gU[3 * e + 1], u2 = gU[3 * e + 2];
+        const cd X = {-0.5 * (lap.r + 2.0 * (gx.r * u0 + gy.r * u1 + gz.r * u2)),
+                      -0.5 * (lap.i + 2.0 * (gx.i * u0 + gy.i * u1 + gz.i * u2))};
+        st_c(Xs, (size_t)i * NP + ca, X);
+        const cd b = ld_c(Bs, (size_t)ca * NSP + i);
+        tsl += remul(X, b);
+        dln0 -= remul(b, gx); dln1 -= remul(b, gy); dln2 -= remul(b, gz);
+        const cd q0 = {0.5 * glx.r + hxx.r * u0 + hxy.r * u1 + hxz.r * u2, 0.5 * glx.i + hxx.i * u0 + hxy.i * u1 + hxz.i * u2};
+        const cd q1 = {0.5 * gly.r + hxy.r * u0 + hyy.r * u1 + hyz.r * u2, 0.5 * gly.i + hxy.i * u0 + hyy.i * u1 + hyz.i * u2};
+        const cd q2 = {0.5 * glz.r + hxz.r * u0 + hyz.r * u1 + hzz.r * u2, 0.5 * glz.i + hxz.i * u0 + hyz.i * u1 + hzz.i * u2};
+        dT0 += remul(q0, b); dT1 += remul(q1, b); dT2 += remul(q2, b);
+      }
+    }
+    __syncthreads();
+    // M = X B (NSP x NSP; K = centres), then W = B M (NP x NSP; K = orbitals)
+    cgemm<NSP / 16, NSP / 16, NP>(Xs, NP, NSP, Bs, NSP, NSP, Ms, NSP, wave, lane);
+    __syncthreads();
+    cgemm<NP / 16, NSP / 16, NSP>(Bs, NSP, NP, Ms, NSP, NSP, Ws, NSP, wave, lane);
+    __syncthreads();
+    // pass 2: d Re T/dR_a += Re grad phi_a(r_i) W_ai
+    if (act) {
+      for (int s = 0; s < IPT; ++s) {
+        const int i = h + H * s;
+        if (i >= NS) continue;
+        const int e = sp * NS + i;
+        cd g[3][4];
+        cbasis_axis<1>(pos[3 * e] - Ra0, za, L, invL, tw, 0, g[0]);
+        cbasis_axis<1>(pos[3 * e + 1] - Ra1, za, L, invL, tw, 1, g[1]);
+        cbasis_axis<1>(pos[3 * e + 2] - Ra2, za, L, invL, tw, 2, g[2]);
+        const cd Wv = ld_c(Ws, (size_t)ca * NSP + i);
+        dT0 += remul(cmul(cmul(g[0][1], g[1][0]), g[2][0]), Wv);
+        dT1 += remul(cmul(cmul(g[0][0], g[1][1]), g[2][0]), Wv);
+        dT2 += remul(cmul(cmul(g[0][0], g[1][0]), g[2][1]), Wv);
+      }
+    }
+    __syncthreads();
+  }
+  // combine the H threads of each centre in a fixed order
+  double* rr = part;
+  if (act) {
+    double* q = rr + ((size_t)h * N + ca) * 6;
+    q[0] = dln0; q[1] = dln1; q[2] = dln2; q[3] = dT0; q[4] = dT1; q[5] = dT2;
+  }
+  const double Tsl = csum256(tsl, red);
+  const double Tj = csum256(tj, red);
+  const double Us = csum256(usum, red);
+  const double EL = Tsl + Tj + m.Vs[w];
+  double* acc = m.acc + (size_t)w * (2 + 9 * N);
+  if (t < N) {
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int hh = 0; hh < H; ++hh)
+      for (int c = 0; c < 6; ++c) v[c] += rr[((size_t)hh * N + t) * 6 + c];
+    const double* dv = m.dVs + (size_t)w * 3 * N + 3 * t;
+    for (int c = 0; c < 3; ++c) {
+      const double d = v[3 + c] + dv[c], gq = v[c];
+      acc[2 + 3 * t + c] += d;
+      acc[2 + 3 * N + 3 * t + c] += gq;
+      acc[2 + 6 * N + 3 * t + c] += EL * gq;
+    }
+  }
+  if (t == 0) {
+    acc[0] += EL;
+    acc[1] += EL * EL;
+    m.Uj[w] = Us;
+  }
+}
+
+// ---------------------------------------------------------------- launchers ---
+size_t cslater_scratch_bytes(int NS) {
+  switch (NS) {
+    case 8: return 16 * CSlaterLay<8>::scr_elems;
+    case 16: return 16 * CSlaterLay<16>::scr_elems;
+    case 27: return 16 * CSlaterLay<27>::scr_elems;
+    case 32: return 16 * CSlaterLay<32>::scr_elems;
+    case 64: return 16 * CSlaterLay<64>::scr_elems;
+    default: return 0;
+  }
+}
+
+template <int NS>
+hipError_t launch_csweep_t(const WalkerArgs& a, const SweepArgs& s, const TwistArgs& tw, int refresh, int moves,
+                           hipStream_t st) {
+  if (moves)
+    hipLaunchKernelGGL((k_csweep<NS, true>), dim3(a.W), dim3(256), CSweepLds<NS>::bytes(true), st, a, s, tw, refresh);
+  else
+    hipLaunchKernelGGL((k_csweep<NS, false>), dim3(a.W), dim3(256), CSweepLds<NS>::bytes(false), st, a, s, tw, 1);
+  return hipGetLastError();
+}
+
+template <int NS>
+hipError_t launch_cslater_t(const MeasureArgs& m, const TwistArgs& tw, hipStream_t st) {
+  hipLaunchKernelGGL((k_cslater_sample<NS>), dim3(m.W), dim3(256), CSlaterLay<NS>::bytes, st, m, tw);
+  return hipGetLastError();
+}
+
+#define VMC_CDISPATCH(ns, CALL)                  \
+  switch (ns) {                                  \
+    case 8: { constexpr int NSV = 8; CALL; }     \
+    case 16: { constexpr int NSV = 16; CALL; }   \
+    case 27: { constexpr int NSV = 27; CALL; }   \
+    case 32: { constexpr int NSV = 32; CALL; }   \
+    case 64: { constexpr int NSV = 64; CALL; }   \
+    default: return hipErrorInvalidValue;        \
+  }
+
+hipError_t launch_csweep(const WalkerArgs& a, const SweepArgs& s, const TwistArgs& tw, int refresh, int moves,
+                         hipStream_t st) {
+  if (a.W < 1 || a.N != 2 * a.NS || (s.spin != 0 && s.spin != 1) || (!moves && !refresh)) return hipErrorInvalidValue;
+  VMC_CDISPATCH(a.NS, return (launch_csweep_t<NSV>(a, s, tw, refresh, moves, st)))
+}
+
+hipError_t launch_cslater_sample(const MeasureArgs& m, const TwistArgs& tw, hipStream_t st) {
+  if (m.W < 1 || m.N != 2 * m.NS || !m.scr) return hipErrorInvalidValue;
+  VMC_CDISPATCH(m.NS, return (launch_cslater_t<NSV>(m, tw, st)))
+}
+
+}  // namespace vmc

@@ -146,6 +146,19 @@ hipError_t launch_toy(double lambda, double k, double a, double mu, int s_kind, 
 // f = mean of the n_tw rows of f_stack, S = sum of the n_tw matrices of S_stack / n_tw^2.
 hipError_t launch_twist_average(int n_tw, int n3, const double* f_stack, const double* S_stack, double* f, double* S,
                                 hipStream_t st);
+// General twist angles (radians) per axis with their cosines and sines: the complex path.
+struct TwistArgs {
+  double th[3], c[3], s[3];
+};
+// Complex path (FP64, N_sigma <= 64): one work-group per walker for spin s.spin.  refresh: form the
+// spin's Slater matrix at the current positions and invert it (else the inverse is read from
+// Binv); moves: then move the spin's electrons once.  Binv holds complex (A^-1)[k][i], ldet
+// ln|det A|, sgn arg det A.  A zero pivot sets *status and leaves the walker unchanged.
+hipError_t launch_csweep(const WalkerArgs& a, const SweepArgs& s, const TwistArgs& tw, int refresh, int moves,
+                         hipStream_t st);
+// The complex measurement (same accumulator layout as the real one) and its per-walker scratch.
+size_t cslater_scratch_bytes(int NS);
+hipError_t launch_cslater_sample(const MeasureArgs& m, const TwistArgs& tw, hipStream_t st);
 hipError_t launch_pack_eval(int K, int N, const double* means, const double* ldet, const double* Uj, double* out,
                             hipStream_t st);
 

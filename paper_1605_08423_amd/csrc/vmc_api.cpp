@@ -26,14 +26,18 @@ using vmc_host::build_kvectors;
 namespace {
 
 enum KClass { K_SETUP, K_BUILD_A, K_INVERT, K_REFINE, K_SWEEP, K_EWALD, K_SLATER, K_FINALIZE, K_REDUCE, K_SYRK,
-              K_LANGEVIN, K_TOY, K_NCLASS };
+              K_LANGEVIN, K_TOY, K_CSWEEP, K_CSLATER, K_NCLASS };
 const char* kClassName[K_NCLASS] = {"proton_setup", "build_A", "invert", "refine", "sweep_half", "ewald_sample",
-                                    "slater_sample", "finalize", "reduce", "syrk", "langevin", "toy"};
+                                    "slater_sample", "finalize", "reduce", "syrk", "langevin", "toy",
+                                    "csweep", "cslater_sample"};
 
 struct Pending { int cls; hipEvent_t a, b; };
 // vmc_energy_forces keeps at most this many sweeps queued ahead of the device, so that
 // a cancellation takes effect within that many sweeps.
 constexpr int kWindow = 8;
+// With a general twist a half-sweep forms and inverts its Slater matrix afresh at sweeps
+// 0, kCRefresh, 2 kCRefresh, ... and carries the previous half-sweep's inverse otherwise.
+constexpr int kCRefresh = 4;
 
 }  // namespace
 
@@ -167,7 +171,35 @@ int check_sys(const vmc_system* s) {
   if (s->refine_tol != s->refine_tol) return VMC_EINVAL;
   if (!(s->j1_b1 >= 0.0) || !std::isfinite(s->j1_b1)) return VMC_EINVAL;
   if (s->twist < 0 || s->twist > 7) return VMC_EINVAL;
+  if (s->general_twist != 0 && s->general_twist != 1) return VMC_EINVAL;
+  if (s->general_twist) {
+    if (s->precision != VMC_FP64 || s->twist != 0 || s->j1_b1 != 0.0 || s->n_protons / 2 > 64) return VMC_EINVAL;
+    for (int m = 0; m < 3; ++m)
+      if (!std::isfinite(s->theta[m])) return VMC_EINVAL;
+  }
   return VMC_OK;
+}
+
+bool is_complex(const vmc_system& s) { return s.general_twist == 1; }
+
+TwistArgs twist_args(const vmc_system& s) {
+  TwistArgs tw{};
+  for (int m = 0; m < 3; ++m) {
+    tw.th[m] = s.theta[m];
+    tw.c[m] = std::cos(s.theta[m]);
+    tw.s[m] = std::sin(s.theta[m]);
+  }
+  return tw;
+}
+
+// Per-walker measurement scratch and the doubles of the inverse per walker and spin.
+size_t meas_scratch_bytes(const vmc_system& s) {
+  const int NS = s.n_protons / 2;
+  return is_complex(s) ? cslater_scratch_bytes(NS) : slater_scratch_bytes(NS, s.precision == VMC_MIXED);
+}
+size_t inv_doubles(const vmc_system& s) {
+  const size_t NS = s.n_protons / 2;
+  return (is_complex(s) ? 2 : 1) * NS * NS;
 }
 
 // Gaussian images kept per axis: all three (n = -1, 0, 1) unless the mode is mixed and
@@ -254,18 +286,25 @@ int measure(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e) {
   RUN(K_SLATER, launch_slater_sample(m, mixed, ctx->stream));
   return VMC_OK;
 }
+int measure_c(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e, const TwistArgs& tw) {
+  vmc_ctx* ctx = t->ctx;
+  RUN(K_EWALD, launch_ewald_sample(m, e, 0, ctx->stream));
+  RUN(K_CSLATER, launch_cslater_sample(m, tw, ctx->stream));
+  return VMC_OK;
+}
 
 // Device bytes vmc_traj_create allocates for this system and walker count.
 size_t traj_bytes(const vmc_system& s, int W) {
   std::vector<double> kv;
   std::vector<int> slots, nx0;
   build_kvectors(s, kv, slots, nx0);
-  const size_t N = s.n_protons, NS = N / 2, n3 = 3 * N, nk = kv.size() / 4, Wz = W;
-  const size_t d = 2 * Wz * N * 3 + 2 * Wz * 2 * NS * NS + 2 * Wz * 2 + Wz * (2 + 9 * N) + Wz * nk * 2 + Wz +
+  const size_t N = s.n_protons, n3 = 3 * N, nk = kv.size() / 4, Wz = W;
+  const size_t amat = is_complex(s) ? 1 : Wz * 2 * inv_doubles(s);
+  const size_t d = 2 * Wz * N * 3 + amat + Wz * 2 * inv_doubles(s) + 2 * Wz * 2 + Wz * (2 + 9 * N) + Wz * nk * 2 + Wz +
                    Wz * n3 + Wz + Wz * (1 + 3 * n3) + Wz * n3 + reduce_partial_doubles(W, (int)n3) + 3 + n3 +
                    kv.size() + 2 * nk + nk * N * 2 + n3 + 1 + 2 * n3 + 2 * n3 * n3;
   return d * sizeof(double) + 2 * Wz * sizeof(int64_t) + (3 * Wz + 2 + slots.size() + nx0.size()) * sizeof(int) +
-         Wz * slater_scratch_bytes((int)NS, s.precision == VMC_MIXED);
+         Wz * meas_scratch_bytes(s);
 }
 
 void free_traj(vmc_traj* t) {
@@ -417,8 +456,9 @@ int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int W, uint32_t seed, u
   t->nslot = (int)nx0.size();
   t->Vself = -sys->ewald_kappa / std::sqrt(M_PI) * (2.0 * t->N);
   const size_t N = t->N, NS = t->NS, n3 = 3 * N;
-  bool ok = !dalloc(&t->pos, W * N * 3) && !dalloc(&t->Amat, (size_t)W * 2 * NS * NS) &&
-            !dalloc(&t->Binv, (size_t)W * 2 * NS * NS) && !dalloc(&t->ldet, (size_t)W * 2) &&
+  // the complex path keeps no Slater matrices between launches (one placeholder double)
+  bool ok = !dalloc(&t->pos, W * N * 3) && !dalloc(&t->Amat, is_complex(*sys) ? 1 : (size_t)W * 2 * NS * NS) &&
+            !dalloc(&t->Binv, (size_t)W * 2 * inv_doubles(*sys)) && !dalloc(&t->ldet, (size_t)W * 2) &&
             !dalloc(&t->sgn, (size_t)W * 2) && !dalloc(&t->acc, (size_t)W * (2 + 9 * N)) &&
             !dalloc(&t->rho_acc, (size_t)W * t->nk * 2) && !dalloc(&t->Vs, (size_t)W) &&
             !dalloc(&t->dVs, (size_t)W * n3) && !dalloc(&t->Uj, (size_t)W) &&
@@ -430,7 +470,7 @@ int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int W, uint32_t seed, u
             !dalloc(&t->slot, slots.size()) && !dalloc(&t->slot_nx0, nx0.size()) &&
             !dalloc(&t->pos_bak, W * N * 3) && !dalloc(&t->nacc_bak, (size_t)W) && !dalloc(&t->Rd, n3) &&
             !dalloc(&t->Rprev, n3) && !dalloc(&t->Sd, n3 * n3) && !dalloc(&t->Sprev, n3 * n3);
-  const size_t scr = slater_scratch_bytes(t->NS, sys->precision == VMC_MIXED);
+  const size_t scr = meas_scratch_bytes(*sys);
   if (ok && scr) ok = !dalloc(&t->scr, (size_t)W * scr);
   if (!ok) { free_traj(t); return VMC_ENOMEM; }
   if (hipMemcpy(t->kvec, kv.data(), kv.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -629,7 +669,9 @@ int vmc_energy_forces(vmc_traj* t, const double* R_in, const double* C, const do
   WalkerArgs a = walker_args(t, R, C, zeta, nimg);
   MeasureArgs m = measure_args(t, R, C, zeta, nimg);
   EwaldArgs e = ewald_args(t);
-  RUN(K_BUILD_A, launch_build_A(a, mixed, st));
+  const bool cplx = is_complex(t->sys);
+  const TwistArgs tw = twist_args(t->sys);
+  if (!cplx) RUN(K_BUILD_A, launch_build_A(a, mixed, st));
   const double rtol = t->sys.refine_tol == 0.0 ? 1e-7 : t->sys.refine_tol;
   const int total = n_equil + n_sweeps;
   for (int s = 0; s < total; ++s) {
@@ -638,6 +680,24 @@ int vmc_energy_forces(vmc_traj* t, const double* R_in, const double* C, const do
     if (ctx->cancel.exchange(0)) {
       HIPCHK(hipStreamSynchronize(st));
       return fail_restore(t, VMC_ECANCELLED);
+    }
+    if (cplx) {
+      // each half-sweep refreshes its own spin's inverse where due; a singular start fails after
+      // the first sweep and the walkers are restored
+      for (int sp = 0; sp < 2; ++sp) {
+        SweepArgs sa{sp, s, step, t->seed, t->traj_id, step_delta};
+        RUN(K_CSWEEP, launch_csweep(a, sa, tw, s % kCRefresh == 0, 1, st));
+      }
+      if (s == 0) {
+        rc = check_singular(ctx);
+        if (rc) return fail_restore(t, rc);
+      }
+      if (s >= n_equil) {
+        rc = measure_c(t, m, e, tw);
+        if (rc) return rc;
+      }
+      HIPCHK(hipEventRecord(ctx->window[s % kWindow], st));
+      continue;
     }
     if (s == 0) {
       // elimination for both spins (a half-sweep over one spin leaves the other spin's matrix
@@ -853,9 +913,19 @@ int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R, const
       WalkerArgs a = walker_args(t, R, C, zeta, nimg);
       MeasureArgs m = measure_args(t, R, C, zeta, nimg);
       EwaldArgs e = ewald_args(t);
-      RUN(K_BUILD_A, launch_build_A(a, mixed, st));
-      RUN(K_INVERT, launch_invert(a, 0, 2, 0, st));
-      int r2 = measure(t, m, e);
+      int r2 = 0;
+      if (is_complex(t->sys)) {
+        const TwistArgs tw = twist_args(t->sys);
+        for (int sp = 0; sp < 2; ++sp) {
+          SweepArgs sa{sp, 0, 0, 0, 0, 0.0};
+          RUN(K_CSWEEP, launch_csweep(a, sa, tw, 1, 0, st));
+        }
+        r2 = measure_c(t, m, e, tw);
+      } else {
+        RUN(K_BUILD_A, launch_build_A(a, mixed, st));
+        RUN(K_INVERT, launch_invert(a, 0, 2, 0, st));
+        r2 = measure(t, m, e);
+      }
       if (r2) return r2;
       RUN(K_FINALIZE, launch_finalize(m, e, 1, t->means, st));
       HIPCHK(launch_pack_eval(K, (int)N, t->means, t->ldet, t->Uj, out, st));
@@ -1185,7 +1255,7 @@ int bucket_sweep(vmc_server* s, const std::vector<Served*>& qs) {
 }
 
 int check_request(const vmc_request* r) {
-  if (!r || check_sys(&r->sys)) return VMC_EINVAL;
+  if (!r || check_sys(&r->sys) || r->sys.general_twist) return VMC_EINVAL;
   if (r->n_walkers < 2 || r->n_sweeps < 1 || r->n_equil < 0 || r->n_equil_first < 0 || r->n_steps < 1)
     return VMC_EINVAL;
   if (!(r->step_delta > 0.0) || !(r->Delta > 0.0) || r->alpha < 0.0 || r->T < 0.0 || (r->flags & ~7u))

@@ -28,7 +28,7 @@ EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_
             "vmc_server_result", "vmc_server_info", "vmc_toy_run", "vmc_huckel_params_twist",
             "vmc_twist_average", "vmc_traj_save", "vmc_traj_load", "vmc_traj_load_rescaled", "vmc_traj_walkers_reset",
             "vmc_set_hbm_budget", "vmc_hbm_in_use", "vmc_traj_bytes", "vmc_cancel", "vmc_traj_set_R", "vmc_traj_get_R",
-            "vmc_traj_step_count", "vmc_traj_langevin_step", "vmc_langevin_step_noalloc"]
+            "vmc_traj_step_count", "vmc_traj_langevin_step", "vmc_langevin_step_noalloc", "vmc_huckel_params_theta"]
 VMC_REQ_QUEUED, VMC_REQ_RUNNING, VMC_REQ_DONE, VMC_REQ_FAILED, VMC_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
@@ -41,7 +41,8 @@ class VMCError(RuntimeError):
 class vmc_system(C.Structure):
     _fields_ = [("n_protons", C.c_int), ("box_L", C.c_double), ("ewald_kappa", C.c_double),
                 ("ewald_nmax", C.c_int), ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
-                ("precision", C.c_int), ("refine_tol", C.c_double), ("j1_b1", C.c_double), ("twist", C.c_int)]
+                ("precision", C.c_int), ("refine_tol", C.c_double), ("j1_b1", C.c_double), ("twist", C.c_int),
+                ("general_twist", C.c_int), ("theta", C.c_double * 3)]
 
 
 class vmc_request(C.Structure):
@@ -94,6 +95,7 @@ def _declare(l):
     l.vmc_toy_run.argtypes = [vp, P(vmc_toy_params), i, i, u32, vp, vp, vp, vp]
     l.vmc_huckel_params.argtypes = [i, d, P(d), P(d), P(d)]
     l.vmc_huckel_params_twist.argtypes = [i, d, i, P(d), P(d), P(d)]
+    l.vmc_huckel_params_theta.argtypes = [i, d, P(d), P(d), P(d), P(d)]
     l.vmc_twist_average.argtypes = [vp, i, i, vp, vp, vp, vp]
     l.vmc_traj_save.argtypes = [vp, vp, P(C.c_size_t)]
     l.vmc_traj_walkers_reset.argtypes = [vp, P(i)]
@@ -138,11 +140,19 @@ def _dev(t, n=None):
 
 
 def make_system(n, L, kappa=None, nmax=9, a_par=0.25, a_anti=0.5, b=1.0, precision=VMC_FP64, refine_tol=0.0,
-                b1=0.0, twist=0):
+                b1=0.0, twist=0, theta=None):
     """b1 > 0 adds the one-body electron-proton Jastrow term with that b_1 (0: none); twist:
-    bit m = twist angle pi along axis m."""
+    bit m = twist angle pi along axis m; theta (3 angles, radians): a general twist with complex
+    orbitals (FP64 only)."""
+    th = (C.c_double * 3)(*([0.0] * 3 if theta is None else [float(v) for v in theta]))
     return vmc_system(int(n), float(L), float(8.0 / L if kappa is None else kappa), int(nmax), a_par, a_anti, b,
-                      int(precision), float(refine_tol), float(b1), int(twist))
+                      int(precision), float(refine_tol), float(b1), int(twist), int(theta is not None), th)
+
+
+def _c_doubles(system):
+    """Doubles of the orbital coefficients C for this system (complex pairs with a general twist)."""
+    n = system.n_protons
+    return n * (n // 2) * (2 if system.general_twist else 1)
 
 
 class Context:
@@ -298,7 +308,7 @@ def vmc_energy_forces(traj: Trajectory, R, Cmo, zeta, n_equil, n_sweeps, delta, 
     N = traj.N
     if out is None:
         out = torch.empty(3 + 3 * N, dtype=torch.float64, device="cuda")
-    _check(_lib().vmc_energy_forces(traj.h, None if R is None else _dev(R, 3 * N), _dev(Cmo, N * (N // 2)),
+    _check(_lib().vmc_energy_forces(traj.h, None if R is None else _dev(R, 3 * N), _dev(Cmo, _c_doubles(traj.sys)),
                                     _dev(zeta, N), int(n_equil), int(n_sweeps), float(delta),
                                     VMC_STEP_TRAJ if step is None else int(step), _dev(out, 3 + 3 * N)),
            "vmc_energy_forces")
@@ -375,7 +385,7 @@ def vmc_eval_configs(ctx: Context, system: vmc_system, R, Cmo, zeta, pos, out=No
     K = pos.shape[0]
     if out is None:
         out = torch.empty((K, 2 + 6 * N), dtype=torch.float64, device="cuda")
-    _check(_lib().vmc_eval_configs(ctx.h, C.byref(system), _dev(R, 3 * N), _dev(Cmo, N * (N // 2)), _dev(zeta, N),
+    _check(_lib().vmc_eval_configs(ctx.h, C.byref(system), _dev(R, 3 * N), _dev(Cmo, _c_doubles(system)), _dev(zeta, N),
                                    K, _dev(pos, K * N * 3), _dev(out, K * (2 + 6 * N))), "vmc_eval_configs")
     return out
 
@@ -395,6 +405,20 @@ def vmc_huckel_params(R, zeta, L, twist=0):
         _check(_lib().vmc_huckel_params_twist(n, float(L), int(twist), R.ctypes.data_as(P), zeta.ctypes.data_as(P),
                                               Cm.ctypes.data_as(P)), "vmc_huckel_params_twist")
     return Cm
+
+
+def vmc_huckel_params_theta(R, zeta, L, theta):
+    """Host helper for a general twist: complex N x N/2 orbital coefficients (numpy complex128)."""
+    import numpy as np
+    R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
+    zeta = np.ascontiguousarray(zeta, dtype=np.float64)
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(3)
+    n = zeta.size
+    Cm = np.zeros((n, n // 2, 2))
+    P = C.POINTER(C.c_double)
+    _check(_lib().vmc_huckel_params_theta(n, float(L), th.ctypes.data_as(P), R.ctypes.data_as(P),
+                                          zeta.ctypes.data_as(P), Cm.ctypes.data_as(P)), "vmc_huckel_params_theta")
+    return Cm.view(np.complex128)[..., 0]
 
 
 def vmc_twist_average(ctx: Context, f_stack, S_stack, f=None, S=None):

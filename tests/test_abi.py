@@ -43,3 +43,34 @@ def test_host_huckel_spans_oracle_occupied_space(oracle, name, twist):
     Co, ev = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2, twist=twist)
     assert ev[wl.n // 2] - ev[wl.n // 2 - 1] > 1e-3      # non-degenerate HOMO-LUMO gap
     np.testing.assert_allclose(Cg @ Cg.T, Co @ Co.T, atol=1e-12)
+
+
+@pytest.mark.parametrize("name,theta", [("h16", (0.3, -1.1, 2.0)), ("h54", (np.pi / 4, 3 * np.pi / 4, -np.pi / 4)),
+                                        ("h128", (-3 * np.pi / 4, np.pi / 4, np.pi / 4))])
+def test_host_huckel_theta_spans_oracle_occupied_space(oracle, name, theta):
+    """General twist: the library's complex Hueckel orbitals (through the real embedding of the
+    Hermitian matrix) span the oracle's occupied space (complex Jacobi), are S-orthogonal, and
+    the projected Hueckel matrix has the oracle's lowest eigenvalues."""
+    from paper_1605_08423_amd import vmc
+    from paper_1605_08423_amd.inputs import workload
+    wl = workload(name)
+    th = np.array(theta)
+    Cg = vmc.vmc_huckel_params_theta(wl.R, wl.zeta, wl.L, th)
+    Co, ev = oracle.chuckel(wl.R, wl.zeta, wl.L, wl.n // 2, th)
+    assert ev[wl.n // 2] - ev[wl.n // 2 - 1] > 1e-3
+    np.testing.assert_allclose(Cg @ Cg.conj().T, Co @ Co.conj().T, atol=1e-12)
+    S = oracle.coverlap(wl.R, wl.zeta, wl.L, th)
+    G = Cg.conj().T @ S @ Cg                    # = -(projected H): Hermitian with eigenvalues -ev
+    np.testing.assert_allclose(np.sort(-np.linalg.eigvalsh(G)), ev[:wl.n // 2], atol=1e-12)
+
+
+def test_host_huckel_theta_rejects_bad_input():
+    from paper_1605_08423_amd import vmc
+    from paper_1605_08423_amd.inputs import workload
+    wl = workload("h16")
+    with pytest.raises(vmc.VMCError):
+        vmc.vmc_huckel_params_theta(wl.R, wl.zeta, wl.L, (0.0, np.nan, 0.0))
+    z = wl.zeta.copy()
+    z[3] = 0.0
+    with pytest.raises(vmc.VMCError):
+        vmc.vmc_huckel_params_theta(wl.R, z, wl.L, (0.1, 0.2, 0.3))

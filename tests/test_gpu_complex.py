@@ -1,0 +1,219 @@
+"""General twisted boundary conditions on the GPU (complex orbitals, FP64) against the oracle's
+complex wavefunction (vmc_oracle_complex.c) on the same seeded inputs, through the C ABI.
+
+FP64 bar as for the real path: 1e-10 relative on fixed configurations and on per-walker chain
+averages (the chains share the Philox stream, so they coincide unless a decision flips, which
+is reported).  The real twists reached through the complex path must also reproduce the real
+kernels' results."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1605_08423_amd.inputs import workload, small_system
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-10
+TH_A = (0.3, -1.1, 2.0)
+TH_MP = (np.pi / 4, 3 * np.pi / 4, -np.pi / 4)    # a point of the 4 x 4 x 4 Monkhorst-Pack mesh
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def elem(a, b):
+    a, b = np.atleast_1d(np.asarray(a, dtype=np.float64)), np.atleast_1d(np.asarray(b, dtype=np.float64))
+    return float(np.max(np.abs(a - b) / (np.abs(b) + np.max(np.abs(b)) + 1e-300)))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    from paper_1605_08423_amd import vmc
+    ctx = vmc.Context(0)
+    return torch, vmc, ctx
+
+
+def _wl(name):
+    return workload(name) if name in ("h16", "h54", "h128") else small_system(int(name[1:]), 1.35, seed=21)
+
+
+def _T(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _cpairs(Cc):
+    return np.ascontiguousarray(np.asarray(Cc, dtype=np.complex128)).view(np.float64)
+
+
+@pytest.mark.parametrize("name,K,theta", [("h16", 16, TH_A), ("h32", 6, TH_MP), ("h54", 6, TH_A), ("h64", 4, TH_MP),
+                                          ("h128", 3, TH_A)])
+def test_ceval_configs(oracle, dev, name, K, theta):
+    torch, vmc, ctx = dev
+    wl = _wl(name)
+    th = np.array(theta)
+    say(f"[complex eval_configs] {name} K={K} theta={theta}")
+    Cc, _ = oracle.chuckel(wl.R, wl.zeta, wl.L, wl.n // 2, th)
+    pos = wl.electrons(W=K, seed_offset=3)
+    sysd = vmc.make_system(wl.n, wl.L, theta=th)
+    g = vmc.vmc_eval_configs(ctx, sysd, _T(torch, wl.R.reshape(-1)), _T(torch, _cpairs(Cc)), _T(torch, wl.zeta),
+                             _T(torch, pos)).cpu().numpy()
+    s = oracle.CSystem(wl.R, wl.zeta, Cc, th, wl.L)
+    n3 = 3 * wl.n
+    worst = {}
+    for k in range(K):
+        r = s.local(pos[k])
+        for q, a, b, f in [("lnpsi", g[k, 0], r["lnpsi"], rel), ("EL", g[k, 1], r["EL"], rel),
+                           ("dlnpsi", g[k, 2:2 + n3], r["dlnpsi"], elem), ("dEL", g[k, 2 + n3:], r["dEL"], elem)]:
+            worst[q] = max(worst.get(q, 0.0), f(a, b))
+    say("  worst errors", worst)
+    for q, v in worst.items():
+        assert v < TOL64, (q, v)
+
+
+def _cchain(oracle, dev, wl, theta, W, n_equil, n_sweeps, seed, step):
+    torch, vmc, ctx = dev
+    th = np.array(theta)
+    Cc, _ = oracle.chuckel(wl.R, wl.zeta, wl.L, wl.n // 2, th)
+    pos = wl.electrons(W=W, seed_offset=7)
+    sysd = vmc.make_system(wl.n, wl.L, theta=th)
+    tr = vmc.Trajectory(ctx, sysd, W, seed=seed, traj_id=3)
+    tr.set_walkers(_T(torch, pos))
+    out = tr.energy_forces(_T(torch, wl.R.reshape(-1)), _T(torch, _cpairs(Cc)), _T(torch, wl.zeta), n_equil,
+                           n_sweeps, wl.delta, step).cpu().numpy()
+    g = dict(out=out, means=tr.walker_means().cpu().numpy(), fw=tr.walker_forces().cpu().numpy(),
+             acc=tr.accepts().cpu().numpy(), pos=tr.get_walkers().cpu().numpy(), S=tr.build_S().cpu().numpy())
+    tr.close()
+    s = oracle.CSystem(wl.R, wl.zeta, Cc, th, wl.L)
+    xo = pos.copy()
+    sums, nacc = s.vmc_run(xo, n_equil, n_sweeps, wl.delta, seed=seed, traj=3, step=step)
+    red = oracle.reduce(sums, n_sweeps)
+    return g, dict(red=red, nacc=nacc, pos=xo, S=oracle.build_S(red["f_w"], red["f"]))
+
+
+# sweeps 0 and 4 form and invert the Slater matrices afresh; the others carry the inverse
+@pytest.mark.parametrize("name,theta,W,ne,ns", [("h16", TH_A, 16, 2, 5), ("h32", TH_MP, 8, 1, 5),
+                                                ("h54", TH_MP, 4, 1, 4), ("h128", TH_A, 2, 0, 2)])
+def test_cchain(oracle, dev, name, theta, W, ne, ns):
+    wl = _wl(name)
+    say(f"[complex chain] {name} theta={theta} W={W} equil={ne} sweeps={ns}")
+    g, o = _cchain(oracle, dev, wl, theta, W, ne, ns, seed=11, step=2)
+    flips = int(np.sum(g["acc"] != o["nacc"]))
+    say("  accepted moves gpu/oracle", g["acc"].sum(), o["nacc"].sum(), "walkers with a flipped decision:", flips)
+    assert flips == 0
+    assert rel(g["pos"], o["pos"]) < 1e-12
+    n3 = 3 * wl.n
+    mo = o["red"]["means"]
+    for q, sl in [("e_w", slice(0, 1)), ("d_w", slice(1, 1 + n3)), ("g_w", slice(1 + n3, 1 + 2 * n3)),
+                  ("h_w", slice(1 + 2 * n3, 1 + 3 * n3))]:
+        e = max(elem(g["means"][w, sl], mo[w, sl]) for w in range(W))
+        say(f"  {q} worst walker element-wise error {e:.3e}")
+        assert e < TOL64, q
+    assert rel(g["out"][0], o["red"]["E"]) < TOL64
+    assert elem(g["out"][3:], o["red"]["f"]) < TOL64
+    assert rel(g["fw"], o["red"]["f_w"]) < TOL64
+    assert rel(g["S"], o["S"]) < 1e-9
+    acc_rate = o["nacc"].sum() / (W * wl.n * (ne + ns))
+    assert g["out"][2] == pytest.approx(acc_rate, rel=1e-14)
+
+
+@pytest.mark.parametrize("name,twist", [("h16", 0), ("h16", 5), ("h54", 3), ("h128", 6)])
+def test_real_twists_through_the_complex_path(oracle, dev, name, twist):
+    """theta_m in {0, pi} through the complex kernels reproduces the real kernels' chain (same
+    moves, energies and forces), with the real orbitals of that twist as complex coefficients."""
+    torch, vmc, ctx = dev
+    wl = workload(name)
+    W, ne, ns = (8, 1, 5) if wl.n <= 54 else (2, 0, 2)
+    say(f"[real twist via complex path] {name} twist={twist} W={W}")
+    Cr, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2, twist=twist)
+    th = np.array([np.pi * ((twist >> m) & 1) for m in range(3)])
+    pos = wl.electrons(W=W, seed_offset=5)
+    res = []
+    for sysd, Cm in [(vmc.make_system(wl.n, wl.L, twist=twist), Cr),
+                     (vmc.make_system(wl.n, wl.L, theta=th), _cpairs(Cr.astype(np.complex128)))]:
+        tr = vmc.Trajectory(ctx, sysd, W, seed=4, traj_id=1)
+        tr.set_walkers(_T(torch, pos))
+        out = tr.energy_forces(_T(torch, wl.R.reshape(-1)), _T(torch, Cm), _T(torch, wl.zeta), ne, ns, wl.delta, 1)
+        res.append((out.cpu().numpy(), tr.accepts().cpu().numpy(), tr.get_walkers().cpu().numpy(),
+                    tr.walker_means().cpu().numpy()))
+        tr.close()
+    (o_r, a_r, p_r, m_r), (o_c, a_c, p_c, m_c) = res
+    say("  accepted real/complex", a_r.sum(), a_c.sum())
+    assert np.array_equal(a_r, a_c)
+    assert rel(p_c, p_r) < 1e-12
+    assert rel(o_c[0], o_r[0]) < TOL64 and elem(o_c[3:], o_r[3:]) < TOL64
+    assert max(elem(m_c[w], m_r[w]) for w in range(W)) < TOL64
+
+
+def test_complex_singular_start_fails_and_restores(dev):
+    """Two same-spin electrons at one point: the first refresh finds a zero pivot, the call
+    returns VMC_ESINGULAR and the walkers are as before."""
+    torch, vmc, ctx = dev
+    wl = workload("h16")
+    th = np.array(TH_A)
+    Cc = vmc.vmc_huckel_params_theta(wl.R, wl.zeta, wl.L, th)
+    pos = wl.electrons(W=4, seed_offset=1)
+    pos[2, 3] = pos[2, 5]
+    sysd = vmc.make_system(wl.n, wl.L, theta=th)
+    tr = vmc.Trajectory(ctx, sysd, 4, seed=1, traj_id=0)
+    tr.set_walkers(_T(torch, pos))
+    with pytest.raises(vmc.VMCError) as ei:
+        tr.energy_forces(_T(torch, wl.R.reshape(-1)), _T(torch, _cpairs(Cc)), _T(torch, wl.zeta), 1, 2, wl.delta, 0)
+    assert ei.value.code == vmc.VMC_ESINGULAR
+    np.testing.assert_array_equal(tr.get_walkers().cpu().numpy(), np.mod(pos, wl.L))
+    tr.close()
+
+
+def test_complex_system_validation(dev):
+    torch, vmc, ctx = dev
+    wl = workload("h16")
+    bad = [vmc.make_system(wl.n, wl.L, theta=(0.1, 0.2, 0.3), precision=vmc.VMC_MIXED),
+           vmc.make_system(wl.n, wl.L, theta=(0.1, 0.2, 0.3), b1=1.0),
+           vmc.make_system(wl.n, wl.L, theta=(0.1, 0.2, 0.3), twist=1),
+           vmc.make_system(256, 12.0, theta=(0.1, 0.2, 0.3)),
+           vmc.make_system(wl.n, wl.L, theta=(0.1, float("inf"), 0.3))]
+    for sysd in bad:
+        with pytest.raises(vmc.VMCError) as ei:
+            vmc.Trajectory(ctx, sysd, 4)
+        assert ei.value.code == vmc.VMC_EINVAL
+
+
+def test_twist_mesh_average(oracle, dev):
+    """A 2 x 2 x 2 Monkhorst-Pack mesh (theta_m = +-pi/2) of independent runs: vmc_twist_average
+    of the GPU runs equals the mean of the oracle's per-twist forces and sum of S / n^2."""
+    torch, vmc, ctx = dev
+    wl = workload("h16")
+    W, ne, ns = 24, 1, 2
+    mesh = oracle.monkhorst_pack(2)
+    n3 = 3 * wl.n
+    fs, Ss, fo, So = [], [], [], []
+    for k, th in enumerate(mesh):
+        Cc, _ = oracle.chuckel(wl.R, wl.zeta, wl.L, wl.n // 2, th)
+        pos = wl.electrons(W=W, seed_offset=11)
+        tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, theta=th), W, seed=9, traj_id=k)
+        tr.set_walkers(_T(torch, pos))
+        out = tr.energy_forces(_T(torch, wl.R.reshape(-1)), _T(torch, _cpairs(Cc)), _T(torch, wl.zeta), ne, ns,
+                               wl.delta, 0)
+        fs.append(out[3:].clone())
+        Ss.append(tr.build_S())
+        tr.close()
+        s = oracle.CSystem(wl.R, wl.zeta, Cc, th, wl.L)
+        xo = pos.copy()
+        sums, _ = s.vmc_run(xo, ne, ns, wl.delta, seed=9, traj=k, step=0)
+        red = oracle.reduce(sums, ns)
+        fo.append(red["f"])
+        So.append(oracle.build_S(red["f_w"], red["f"]))
+    f, S = vmc.vmc_twist_average(ctx, torch.stack(fs), torch.stack(Ss))
+    f_ref = np.mean(fo, axis=0)
+    S_ref = np.sum(So, axis=0) / len(mesh) ** 2
+    say("[twist mesh 2x2x2] f rel err", rel(f.cpu().numpy(), f_ref), "S rel err", rel(S.cpu().numpy(), S_ref))
+    assert elem(f.cpu().numpy(), f_ref) < TOL64
+    assert rel(S.cpu().numpy(), S_ref) < 1e-9
+    assert S.shape == (n3, n3)
