@@ -68,7 +68,24 @@ def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, on
         return _add({"f64": recip}, lo, real)
     if cls == "refine":
         return {"f64": 4 * NS ** 3}
+    if cls == "csweep":
+        # general twist, complex FP64 (a complex multiply-add is 8 flops).  One move: the proposal's
+        # Bloch-summed basis values (per centre 3 axes x 3 images of an exp and its twist phase, and
+        # the complex product, 93), the orbital row (8 N NS), the ratio (8 NS), the Jastrow change and,
+        # if accepted, the Sherman-Morrison row product and update (16 NS^2).  Every CREFRESH-th
+        # half-sweep also forms its Slater matrix (NS N 93 + 8 NS N NS) and inverts it (8 NS^3).
+        move = N * 93 + 8 * N * NS + 8 * NS + 30 * (N - 1) + acc * 16 * NS * NS
+        refresh = NS * N * 93 + 8 * NS * N * NS + 8 * NS ** 3
+        return {"f64": NS * move + refresh / CREFRESH}
+    if cls == "cslater_sample":
+        # B = C A^-1, M = X B, W = B M per spin (complex, 8 N NS^2 each); the (electron, centre) passes
+        # with the complex basis and its derivatives (295 + 110 flops); the Jastrow pass
+        return {"f64": 2 * 3 * 8 * N * NS * NS + N * N * (295 + 110) + N * (N - 1) * 45}
     return {}
+
+
+# the complex half-sweep forms and inverts its Slater matrix afresh every CREFRESH-th sweep
+CREFRESH = 4
 
 
 def executed_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, one_body: bool = False,
@@ -77,6 +94,11 @@ def executed_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool
     its Sherman-Morrison updates in blocks of 16 moves on the matrix cores, forming the full rows
     P = M' A^-1 of every proposal and a rank-16 update whatever the acceptance (2 NS N NS + 4 NS^3
     on the FP64 matrix cores per half-sweep; the SQ_INSTS_VALU_MFMA_MOPS_F64 counter gives it)."""
+    if cls == "csweep":
+        # the row product m A^-1 is formed for every proposal, accepted or not
+        NS = N // 2
+        w = work_model(cls, N, nk, nslot, nimg, mixed, one_body, acc)
+        return {"f64": w["f64"] + NS * (1 - acc) * 8 * NS * NS}
     if cls != "sweep_half":
         return work_model(cls, N, nk, nslot, nimg, mixed, one_body, acc)
     NS = N // 2
@@ -104,7 +126,7 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1605_08423_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith(".hip") or f in ("common.hpp", "kernels.hpp"):
+        if f.endswith(".hip") or f in ("common.hpp", "kernels.hpp", "moves.hpp"):
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -202,6 +224,10 @@ def run_toy(args):
     ms, nl = times["toy"]
     avg_s = ms / max(nl, 1) / 1e3
     achieved = TOY_FLOP_PER_STEP * n * steps / avg_s / 1e12
+    mesh = None
+    if args.mesh_leg > 0 and args.workload == "h128":
+        mesh = twist_mesh_leg("h128", args.mesh_leg, args.mesh_walkers, 10, 1, 1)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -418,6 +444,114 @@ def run_twists(args):
     }))
 
 
+def monkhorst_pack(q: int) -> np.ndarray:
+    """Twist angles of the q x q x q Monkhorst-Pack mesh: theta_m = 2 pi (2 n - q - 1) / (2 q), n = 1..q."""
+    t = [2.0 * math.pi * (2 * n - q - 1) / (2 * q) for n in range(1, q + 1)]
+    return np.array([(a, b, c) for a in t for b in t for c in t])
+
+
+def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int) -> dict:
+    """Twist-averaged Langevin steps over the q x q x q Monkhorst-Pack mesh of general twists (the
+    paper's production setup is q = 4): one trajectory per twist with W walkers and the complex
+    orbitals of its twist (FP64); a step solves the q^3 Hueckel problems on the host, runs every
+    twist's estimate (5 re-equilibration + M measured sweeps; 20 at the first step), forms the
+    twist averages of the forces and of their covariance and takes the Langevin step."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_1605_08423_amd import vmc
+    from paper_1605_08423_amd.inputs import workload
+    wl = workload(name)
+    N, n3 = wl.n, 3 * wl.n
+    mesh = monkhorst_pack(q)
+    n_tw = len(mesh)
+    ctx = vmc.Context(0)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    trajs = []
+    for k, th in enumerate(mesh):
+        tr = vmc.Trajectory(ctx, vmc.make_system(N, wl.L, theta=th), W, seed=wl.seed, traj_id=k)
+        tr.set_walkers(dev(wl.electrons(W=W, seed_offset=k)))
+        trajs.append(tr)
+    R = dev(wl.R.reshape(-1))
+    R_prev = R.clone()
+    zeta = dev(wl.zeta)
+    S_prev = torch.empty((n3, n3), dtype=torch.float64, device="cuda")
+    f_stack = torch.empty((n_tw, n3), dtype=torch.float64, device="cuda")
+    S_stack = torch.empty((n_tw, n3, n3), dtype=torch.float64, device="cuda")
+    alpha = 0.122 * W * n_tw * M
+    Delta = 1.0 / alpha
+    pool = ThreadPoolExecutor(max_workers=16)
+    state = {"first": True, "E": None, "acc": 0.0}
+
+    def one_step(k):
+        Rh = R.cpu().numpy()
+        Cs = list(pool.map(lambda th: vmc.vmc_huckel_params_theta(Rh, wl.zeta, wl.L, th), mesh))
+        E = acc = 0.0
+        for j, tr in enumerate(trajs):
+            out = tr.energy_forces(R, dev(np.ascontiguousarray(Cs[j]).view(np.float64)), zeta, 20 if k == 0 else 5,
+                                   M, wl.delta, step=k)
+            f_stack[j].copy_(out[3:])
+            tr.build_S(S_stack[j])
+            E += float(out[0]) / n_tw
+            acc += float(out[2]) / n_tw
+        f, S = vmc.vmc_twist_average(ctx, f_stack, S_stack)
+        if state["first"]:
+            S_prev.copy_(S)
+            R_prev.copy_(R)
+            state["first"] = False
+        rc = vmc.vmc_langevin_step(ctx, R, R_prev, S_prev, f, S, wl.T_hartree, Delta, alpha, 0, wl.seed, 0, k, wl.L)
+        if rc != 0:
+            raise RuntimeError(f"langevin step failed: {vmc._lib().vmc_strerror(rc).decode()}")
+        state["E"], state["acc"] = E, acc
+
+    for k in range(warmup):
+        one_step(k)
+    torch.cuda.synchronize()
+    ctx.reset_kernel_times()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        one_step(k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    times = ctx.kernel_times()
+    ctx.set_profiling(False)
+    for tr in trajs:
+        tr.close()
+    pool.shutdown()
+    ranked = sorted(times.items(), key=lambda kv: -kv[1][0])
+    rl = {}
+    for kname, (ms, n) in ranked[:2]:
+        avg_s = ms / max(n, 1) / 1e3
+        parts = work_model(kname, N, 0, 0, 1, False, False, state["acc"])
+        flops, achieved, peak = roofline_numbers(parts, W, avg_s)
+        ex = executed_model(kname, N, 0, 0, 1, False, False, state["acc"])
+        rl[kname] = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2), "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4) if peak else None, "avg_launch_ms": round(avg_s * 1e3, 4),
+                     "algorithmic_flop_per_launch": round(flops),
+                     "executed_tflops": round(sum(ex.values()) * W / avg_s / 1e12, 3)}
+    return {"value": round(W * n_tw * M * steps / elapsed, 1), "unit": "walker-sweeps/s",
+            "workload": f"{name}: {N} H, r_s={wl.rs}, {q}x{q}x{q} Monkhorst-Pack twists x {W} walkers x {M} measured "
+                        f"(+5 re-equilibration) sweeps per Langevin step, complex orbitals, FP64",
+            "twists": n_tw, "walkers_per_twist": W, "sweeps": M, "steps": steps, "warmup": warmup,
+            "ms_per_step": round(1e3 * elapsed / steps, 1), "langevin_steps_per_s": round(steps / elapsed, 4),
+            "E_Ha_twist_average": state["E"], "acceptance": round(state["acc"], 4),
+            "dominant_kernel": ranked[0][0], "roofline": rl,
+            "kernel_ms": {k: round(v[0], 2) for k, v in ranked if v[0] > 0}}
+
+
+def run_mesh(args):
+    r = twist_mesh_leg(args.workload if args.workload != "h256" else "h128", args.mesh, args.mesh_walkers,
+                       args.sweeps, args.steps, args.warmup)
+    dom = r["roofline"][r["dominant_kernel"]]
+    line = {"metric": "twist-averaged VMC walker-sweeps/s with forces (general twists)", "value": r["value"],
+            "unit": r["unit"], "n_gpus": 1, "steps": r["steps"], "warmup": r["warmup"],
+            "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic", "config": {"workload": r["workload"]},
+            "roofline": dict(dom, kernel=r["dominant_kernel"], traffic=None)}
+    line.update({k: v for k, v in r.items() if k not in ("value", "unit", "workload", "steps", "warmup", "ms_per_step")})
+    print(json.dumps(line))
+
+
 def cpu_host_info() -> dict:
     """The host the CPU baseline runs on: logical CPUs, those this process may use, the model."""
     model = None
@@ -540,6 +674,12 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     ap.add_argument("--twists", type=int, default=1, metavar="N",
                     help="twist-averaged steps over the first N of the 8 real twists (2..8), walkers split evenly")
+    ap.add_argument("--mesh", type=int, default=0, metavar="Q",
+                    help="twist-averaged steps over the Q x Q x Q Monkhorst-Pack mesh of general twists (complex "
+                         "orbitals, FP64) instead")
+    ap.add_argument("--mesh-walkers", type=int, default=256, help="walkers per twist of --mesh and the mesh leg")
+    ap.add_argument("--mesh-leg", type=int, default=4, metavar="Q",
+                    help="Q of the short twist-mesh leg of the default line (0: skip)")
     ap.add_argument("--toy", action="store_true", help="the toy-model figure as a GPU workload instead")
     ap.add_argument("--toy-traj", type=int, default=65536)
     ap.add_argument("--toy-steps", type=int, default=2000)
@@ -550,6 +690,9 @@ def main():
         sys.exit(2)
     if args.toy:
         run_toy(args)
+        return
+    if args.mesh:
+        run_mesh(args)
         return
     if args.twists > 1:
         if args.twists > 8:
@@ -624,6 +767,10 @@ def main():
     if args.serve_leg > 0 and args.workload == "h128":
         served = serve_stream(args.serve_leg, 2, 10, args.serve_rate, args.serve_budget_gb)
 
+    mesh = None
+    if args.mesh_leg > 0 and args.workload == "h128":
+        mesh = twist_mesh_leg("h128", args.mesh_leg, args.mesh_walkers, 10, 1, 1)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -654,7 +801,7 @@ def main():
         "langevin_steps_per_s": round(args.steps / lead["elapsed"], 4),
         "step_latency_ms": {"p50": round(lead["p50"], 1), "p99": round(lead["p99"], 1)},
         "E_Ha": float(out_h[0]), "sigma_E_Ha": float(out_h[1]), "acceptance": acc,
-        "roofline": roofline, "fp64_gpu": fp64, "served": served, "cpu_baseline": cpu,
+        "roofline": roofline, "fp64_gpu": fp64, "served": served, "twist_mesh": mesh, "cpu_baseline": cpu,
         "kernel_ms": {k: round(v[0], 2) for k, v in times.items()},
     }
     print(json.dumps(line))

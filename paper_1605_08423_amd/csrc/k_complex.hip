@@ -109,22 +109,26 @@ __device__ __forceinline__ double csum256(double v, double* red4) {
 }  // namespace
 
 // ------------------------------------------------------------- half sweep ---
+// Threads of a half-sweep work-group: eight waves, two per SIMD, so that one wave's LDS round
+// trips overlap another's arithmetic (the LDS held by one walker allows one work-group per CU).
+constexpr int CT = 512, CW = CT / 64;
+
 template <int NS>
 struct CSweepLds {
   static constexpr int N = 2 * NS, NSP = (NS + 15) / 16 * 16, LDA = NSP + 1;
-  static constexpr int P = (256 / NS) < NS ? (256 / NS) : NS;   // partial sums of a row product
+  static constexpr int P = (CT / NS) < NS ? (CT / NS) : NS;   // partial sums of a row product
   static constexpr int CH = (NS + P - 1) / P;                    // their k range
-  static constexpr int RPT = 256 / NS;                           // rows per pass of an NS-wide update
+  static constexpr int RPT = CT / NS;                           // rows per pass of an NS-wide update
   // offsets in doubles; the proposals' orbital rows come last (absent in a refresh-only launch)
   static constexpr size_t ainv = 0, pos = ainv + 2 * (size_t)NSP * LDA, trig = pos + 3 * N, prop = trig + 6 * N,
                           ptrig = prop + 4 * NSP, vpart = ptrig + 6 * NSP, colI = vpart + 2 * (size_t)P * NSP,
-                          prow = colI + 2 * NSP, fcol = prow + 2 * NSP, red = fcol + 2 * NSP, misc = red + 8,
+                          prow = colI + 2 * NSP, fcol = prow + 2 * NSP, red = fcol + 2 * NSP, misc = red + 16,
                           mp = misc + NSP + 8;
   static constexpr size_t bytes(bool moves) { return sizeof(double) * (moves ? mp + 2 * (size_t)NSP * NSP : mp); }
 };
 
 template <int NS, bool MOVES>
-__global__ __launch_bounds__(256, 1) void k_csweep(WalkerArgs a, SweepArgs s, TwistArgs tw, int refresh) {
+__global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, TwistArgs tw, int refresh) {
   using LY = CSweepLds<NS>;
   constexpr int N = 2 * NS, NSP = LY::NSP, LDA = LY::LDA, P = LY::P, CH = LY::CH, RPT = LY::RPT;
   constexpr int TR = NSP / 16, TC = NSP / 16, KS = (N + 3) / 4;
@@ -138,20 +142,20 @@ __global__ __launch_bounds__(256, 1) void k_csweep(WalkerArgs a, SweepArgs s, Tw
   double* colI = smem + LY::colI;    // NSP complex
   double* prow = smem + LY::prow;    // NSP complex
   double* fcol = smem + LY::fcol;    // NSP complex
-  double* red = smem + LY::red;      // 8
+  double* red = smem + LY::red;      // 16: per-wave partials, then the pivot
   int* perm = reinterpret_cast<int*>(smem + LY::misc);   // NSP pivot rows, then flags
   int* flag = perm + NSP;
   double* Mp = smem + LY::mp;        // NSP x NSP complex: orbital rows of the proposals
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int w = blockIdx.x, sp = s.spin;
   const double L = a.L, invL = a.invL;
-  for (int u = t; u < 3 * N; u += 256) pos[u] = a.pos[(size_t)w * 3 * N + u];
+  for (int u = t; u < 3 * N; u += CT) pos[u] = a.pos[(size_t)w * 3 * N + u];
   __syncthreads();
-  for (int e = t; e < N; e += 256)
+  for (int e = t; e < N; e += CT)
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) sincospi(pos[3 * e + ax] * invL, &trig[6 * e + ax], &trig[6 * e + 3 + ax]);
   if (MOVES)
-    for (int i = t; i < NS; i += 256) {
+    for (int i = t; i < NS; i += CT) {
       double xn, yn, zn, ru;
       draw_move(s, w, N, sp * NS + i, pos + 3 * (sp * NS + i), s.delta, L, invL, xn, yn, zn, ru);
       prop[4 * i] = xn; prop[4 * i + 1] = yn; prop[4 * i + 2] = zn; prop[4 * i + 3] = ru;
@@ -162,12 +166,12 @@ __global__ __launch_bounds__(256, 1) void k_csweep(WalkerArgs a, SweepArgs s, Tw
   if (t == 0) flag[0] = 0;
   const double* Bg = a.Binv + 2 * ((size_t)w * 2 + sp) * NS * NS;
   if (!refresh)
-    for (int u = t; u < NS * NS; u += 256) st_c(Ai, (u / NS) * LDA + u % NS, ld_c(Bg, u));
+    for (int u = t; u < NS * NS; u += CT) st_c(Ai, (u / NS) * LDA + u % NS, ld_c(Bg, u));
   __syncthreads();
   // row tiles [0, TR): the spin's electrons (A, refresh only); [TR, 2 TR): the proposals
   {
     const int t0 = refresh ? 0 : TR, t1 = MOVES ? 2 * TR : TR;
-    for (int tt = t0 + wave; tt < t1; tt += 4) {
+    for (int tt = t0 + wave; tt < t1; tt += CW) {
       const bool isp = tt >= TR;
       const int rt = isp ? tt - TR : tt;
       const int row = rt * 16 + (lane & 15);
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(256, 1) void k_csweep(WalkerArgs a, SweepArgs s, Tw
     // multipliers even two equal rows leave a rounding-sized pivot, not an exact zero.
     {
       double am = 0.0;
-      for (int u = t; u < NS * NS; u += 256) {
+      for (int u = t; u < NS * NS; u += CT) {
         const cd v = ld_c(Ai, (size_t)(u / NS) * LDA + u % NS);
         am = fmax(am, v.r * v.r + v.i * v.i);
       }
@@ -215,8 +219,9 @@ __global__ __launch_bounds__(256, 1) void k_csweep(WalkerArgs a, SweepArgs s, Tw
       if (lane == 0) red[wave] = am;
       __syncthreads();
     }
-    const double tol2 = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * (NS * 2.220446049250313e-16) *
-                        (NS * 2.220446049250313e-16);
+    double amax = red[0];
+    for (int q = 1; q < CW; ++q) amax = fmax(amax, red[q]);
+    const double tol2 = amax * (NS * 2.220446049250313e-16) * (NS * 2.220446049250313e-16);
     for (int p = 0; p < NS; ++p) {
       if (wave == 0) {
         double mag = -1.0;
@@ -231,24 +236,24 @@ __global__ __launch_bounds__(256, 1) void k_csweep(WalkerArgs a, SweepArgs s, Tw
           if (!(mag > tol2) || !isfinite(mag)) flag[0] = 1;
           // the pivot value, read by every thread before the row swap below moves it
           const cd v = ld_c(Ai, (size_t)idx * LDA + p);
-          red[4] = v.r;
-          red[5] = v.i;
+          red[8] = v.r;
+          red[9] = v.i;
         }
       }
       __syncthreads();
       if (flag[0]) break;
       const int r = perm[p];
-      const cd pv = {red[4], red[5]};
+      const cd pv = {red[8], red[9]};
       const double m2 = pv.r * pv.r + pv.i * pv.i;
       const cd ip = {pv.r / m2, -pv.i / m2};
-      for (int j = t; j < NS; j += 256) {
+      for (int j = t; j < NS; j += CT) {
         const cd x = ld_c(Ai, (size_t)p * LDA + j), y = ld_c(Ai, (size_t)r * LDA + j);
         st_c(Ai, (size_t)p * LDA + j, y);
         st_c(Ai, (size_t)r * LDA + j, x);
         st_c(prow, j, cmul(j == p ? cd{1.0, 0.0} : y, ip));
         if (j == p) { st_c(fcol, r, x); st_c(fcol, p, y); }
       }
-      for (int i = t; i < NS; i += 256)
+      for (int i = t; i < NS; i += CT)
         if (i != p && i != r) st_c(fcol, i, ld_c(Ai, (size_t)i * LDA + p));
       __syncthreads();
       if (t < RPT * NS) {
@@ -275,7 +280,7 @@ __global__ __launch_bounds__(256, 1) void k_csweep(WalkerArgs a, SweepArgs s, Tw
       if (t == 0) atomicExch(a.status, 1);
       return;
     }
-    for (int i = t; i < NS; i += 256)
+    for (int i = t; i < NS; i += CT)
       for (int p = NS - 1; p >= 0; --p) {
         const int r = perm[p];
         if (r != p) {
@@ -290,6 +295,10 @@ __global__ __launch_bounds__(256, 1) void k_csweep(WalkerArgs a, SweepArgs s, Tw
     phv = a.sgn[(size_t)w * 2 + sp];
   }
   int64_t nadd = 0;
+  // product of the accepted ratios (thread 0), kept as a complex mantissa and a power of two so
+  // that the moves need no logarithm or angle; folded into ldet and the phase at the end
+  cd qprod = {1.0, 0.0};
+  int qexp = 0;
   if (MOVES) {
     const double LoP = L / VMC_PI, bj = a.b;
     for (int i = 0; i < NS; ++i) {
@@ -319,11 +328,13 @@ __global__ __launch_bounds__(256, 1) void k_csweep(WalkerArgs a, SweepArgs s, Tw
       __syncthreads();
       cd q = {0.0, 0.0};
       for (int pp = 0; pp < P; ++pp) q = cadd(q, ld_c(vpart, (size_t)pp * NSP + i));
-      const double dU = ((red[0] + red[1]) + red[2]) + red[3];
+      double dU = red[0];
+      for (int q = 1; q < CW; ++q) dU += red[q];
       const double q2 = q.r * q.r + q.i * q.i;
       const double pacc = q2 * exp(2.0 * dU);
       if (prop[4 * i + 3] < pacc) {
-        const cd iq = {q.r / q2, -q.i / q2};
+        const double iq2 = 1.0 / q2;
+        const cd iq = {q.r * iq2, -q.i * iq2};
         if (t < RPT * NS) {
           const int j = t % NS;
           cd vj = {0.0, 0.0};
@@ -339,18 +350,25 @@ __global__ __launch_bounds__(256, 1) void k_csweep(WalkerArgs a, SweepArgs s, Tw
 #pragma unroll
           for (int u = 0; u < 6; ++u) trig[6 * e + u] = ptrig[6 * i + u];
           ++nadd;
-          ldv += 0.5 * log(q2);
-          phv += atan2(q.i, q.r);
+          qprod = cmul(qprod, q);
+          int ex;
+          (void)frexp(fmax(fabs(qprod.r), fabs(qprod.i)), &ex);
+          qprod = {ldexp(qprod.r, -ex), ldexp(qprod.i, -ex)};
+          qexp += ex;
         }
       }
       __syncthreads();
     }
   }
   double* Bo = a.Binv + 2 * ((size_t)w * 2 + sp) * NS * NS;
-  for (int u = t; u < NS * NS; u += 256) st_c(Bo, u, ld_c(Ai, (size_t)(u / NS) * LDA + u % NS));
+  for (int u = t; u < NS * NS; u += CT) st_c(Bo, u, ld_c(Ai, (size_t)(u / NS) * LDA + u % NS));
   if (MOVES)
-    for (int u = t; u < 3 * NS; u += 256) a.pos[(size_t)w * 3 * N + 3 * sp * NS + u] = pos[3 * sp * NS + u];
+    for (int u = t; u < 3 * NS; u += CT) a.pos[(size_t)w * 3 * N + 3 * sp * NS + u] = pos[3 * sp * NS + u];
   if (t == 0) {
+    if (MOVES && nadd > 0) {
+      ldv += 0.5 * log(qprod.r * qprod.r + qprod.i * qprod.i) + qexp * 0.69314718055994530942;
+      phv += atan2(qprod.i, qprod.r);
+    }
     a.ldet[(size_t)w * 2 + sp] = ldv;
     a.sgn[(size_t)w * 2 + sp] = remainder(phv, 2.0 * VMC_PI);
     if (MOVES) a.nacc[w] += nadd;
@@ -593,9 +611,9 @@ template <int NS>
 hipError_t launch_csweep_t(const WalkerArgs& a, const SweepArgs& s, const TwistArgs& tw, int refresh, int moves,
                            hipStream_t st) {
   if (moves)
-    hipLaunchKernelGGL((k_csweep<NS, true>), dim3(a.W), dim3(256), CSweepLds<NS>::bytes(true), st, a, s, tw, refresh);
+    hipLaunchKernelGGL((k_csweep<NS, true>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(true), st, a, s, tw, refresh);
   else
-    hipLaunchKernelGGL((k_csweep<NS, false>), dim3(a.W), dim3(256), CSweepLds<NS>::bytes(false), st, a, s, tw, 1);
+    hipLaunchKernelGGL((k_csweep<NS, false>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(false), st, a, s, tw, 1);
   return hipGetLastError();
 }
 

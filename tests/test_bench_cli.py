@@ -53,3 +53,22 @@ def test_traffic_is_reported_only_for_the_profiled_workload():
                   bench.traffic_workload_key("h128", "mixed", 8192), bench.traffic_workload_key("h128", "mixed", 16384, 2.5),
                   bench.traffic_workload_key("h128", "mixed", 16384, 0.0, 1.28)):
         assert bench.measured_traffic("sweep_half", other) is None
+
+
+def test_complex_work_model_and_twist_mesh(oracle):
+    """The general-twist kernels' counts (complex multiply-add = 8 flops) and the Monkhorst-Pack
+    mesh of the twist leg (the oracle's mesh, symmetric about the origin)."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    N, NS = 128, 64
+    sw = bench.work_model("csweep", N, 0, 0, 1, False, acc=0.5)
+    move = N * 93 + 8 * N * NS + 8 * NS + 30 * (N - 1) + 0.5 * 16 * NS * NS
+    assert sw == {"f64": NS * move + (NS * N * 93 + 8 * NS * N * NS + 8 * NS ** 3) / bench.CREFRESH}
+    ex = bench.executed_model("csweep", N, 0, 0, 1, False, acc=0.5)
+    assert ex["f64"] == sw["f64"] + NS * 0.5 * 8 * NS * NS
+    sl = bench.work_model("cslater_sample", N, 0, 0, 1, False)
+    assert sl["f64"] > 48 * N * NS * NS
+    mesh = bench.monkhorst_pack(4)
+    np.testing.assert_allclose(mesh, oracle.monkhorst_pack(4))
+    assert mesh.shape == (64, 3) and np.allclose(mesh.sum(0), 0.0)
