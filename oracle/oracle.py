@@ -33,7 +33,11 @@ class OSys(C.Structure):
                 ("kappa", C.c_double), ("nmax", C.c_int), ("jastrow_on", C.c_int),
                 ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
                 ("R", C.POINTER(C.c_double)), ("zeta", C.POINTER(C.c_double)),
-                ("C", C.POINTER(C.c_double)), ("b1", C.c_double), ("twist", C.c_int)]
+                ("C", C.POINTER(C.c_double)), ("b1", C.c_double), ("twist", C.c_int),
+                ("contracted", C.c_int), ("eta", C.c_double)]
+
+
+Z1, Z2 = 0.6066825, 0.3382168   # the SI's exponents of the contracted minimal basis
 
 
 _lib = None
@@ -86,6 +90,9 @@ def _setup(l):
     l.o_coverlap.restype = None
     l.o_chuckel.argtypes = [i, d, P(d), P(d), P(d), i, P(d), P(d)]
     l.o_clocal.argtypes = [P(OSys), P(d), P(d), P(d), P(d), P(d), P(d), P(d), P(d)]
+    l.o_huckel_contracted.argtypes = [i, d, P(d), d, i, P(d), P(d)]
+    l.o_overlap_contracted.argtypes = [i, d, P(d), d, P(d)]
+    l.o_overlap_contracted.restype = None
     l.o_cvmc_run_from.argtypes = [P(OSys), P(d), P(d), i, u32, P(d), i, i, d, u32, u32, u32, P(d), P(C.c_int64), i]
 
 
@@ -94,7 +101,7 @@ class System:
 
     def __init__(self, R, zeta, C_mo, L=0.0, n_up=None, n_dn=None, basis=OB_PERIODIC_GAUSS,
                  pot=OP_EWALD, kappa=None, nmax=9, jastrow=True, a_par=0.25, a_anti=0.5, b=1.0,
-                 b1=0.0, twist=0):
+                 b1=0.0, twist=0, eta=None):
         self.R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1, 3)
         n_p = self.R.shape[0]
         self.zeta = np.ascontiguousarray(zeta, dtype=np.float64).reshape(n_p)
@@ -106,9 +113,10 @@ class System:
         self.n_up, self.n_dn, self.L = n_up, n_dn, float(L)
         if kappa is None:
             kappa = 8.0 / L if L > 0 else 0.0
+        # eta given: the contracted orbital phi_1 + eta phi_2 (zeta unused)
         self.s = OSys(n_p, n_up, n_dn, self.C.shape[1], float(L), basis, pot, float(kappa), int(nmax),
                       int(bool(jastrow)), a_par, a_anti, b, _dp(self.R), _dp(self.zeta), _dp(self.C),
-                      float(b1), int(twist))
+                      float(b1), int(twist), int(eta is not None), float(eta or 0.0))
 
     @property
     def n_p(self):
@@ -270,6 +278,26 @@ def huckel(R, zeta, L, n_orb, twist=0):
     if rc:
         raise RuntimeError("o_huckel failed")
     return Cm, ev
+
+
+def huckel_contracted(R, L, n_orb, eta):
+    """Hueckel orbitals on the contracted basis phi_1 + eta phi_2 and all eigenvalues."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    n_p = R.shape[0]
+    Cm = np.zeros((n_p, n_orb))
+    ev = np.zeros(n_p)
+    rc = lib().o_huckel_contracted(n_p, float(L), _dp(R), float(eta), n_orb, _dp(Cm), _dp(ev))
+    if rc:
+        raise RuntimeError("o_huckel_contracted failed")
+    return Cm, ev
+
+
+def overlap_contracted(R, L, eta):
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    n_p = R.shape[0]
+    S = np.zeros((n_p, n_p))
+    lib().o_overlap_contracted(n_p, float(L), _dp(R), float(eta), _dp(S))
+    return S
 
 
 def reduce(sums, M):

@@ -166,6 +166,41 @@ static void gauss_1d(double x, double zeta, double L, int periodic, double tau, 
   }
 }
 
+/* One Cartesian factor of the image sum of t^2 e^{-zeta t^2} (the r^2 part of the contracted
+ * orbital's second Gaussian) and its first three derivatives, images and weights as in gauss_1d;
+ * with e = e^{-zeta t^2}: first derivative (2t - 2 zeta t^3) e, second (2 - 10 zeta t^2 +
+ * 4 zeta^2 t^4) e, third (-24 zeta t + 36 zeta^2 t^3 - 8 zeta^3 t^5) e. */
+static void gauss2_1d(double x, double zeta, double L, int periodic, double tau, double g[4]) {
+  g[0] = g[1] = g[2] = g[3] = 0.0;
+  int nlo = periodic ? -1 : 0, nhi = periodic ? 1 : 0;
+  for (int n = nlo; n <= nhi; ++n) {
+    double t = x + n * L, t2 = t * t;
+    double e = (n == 0 ? 1.0 : tau) * exp(-zeta * t2);
+    g[0] += t2 * e;
+    g[1] += (2.0 * t - 2.0 * zeta * t2 * t) * e;
+    g[2] += (2.0 - 10.0 * zeta * t2 + 4.0 * zeta * zeta * t2 * t2) * e;
+    g[3] += (-24.0 * zeta * t + 36.0 * zeta * zeta * t2 * t - 8.0 * zeta * zeta * zeta * t2 * t2 * t) * e;
+  }
+}
+
+/* w times the 14 components of the product f_x(x) f_y(y) f_z(z), added to out. */
+static void add_product(const double g[3][4], double w, double out[14]) {
+  out[0] += w * g[0][0] * g[1][0] * g[2][0];
+  out[1] += w * g[0][1] * g[1][0] * g[2][0];
+  out[2] += w * g[0][0] * g[1][1] * g[2][0];
+  out[3] += w * g[0][0] * g[1][0] * g[2][1];
+  out[4] += w * (g[0][2] * g[1][0] * g[2][0] + g[0][0] * g[1][2] * g[2][0] + g[0][0] * g[1][0] * g[2][2]);
+  out[5] += w * g[0][2] * g[1][0] * g[2][0];
+  out[6] += w * g[0][0] * g[1][2] * g[2][0];
+  out[7] += w * g[0][0] * g[1][0] * g[2][2];
+  out[8] += w * g[0][1] * g[1][1] * g[2][0];
+  out[9] += w * g[0][1] * g[1][0] * g[2][1];
+  out[10] += w * g[0][0] * g[1][1] * g[2][1];
+  out[11] += w * (g[0][3] * g[1][0] * g[2][0] + g[0][1] * g[1][2] * g[2][0] + g[0][1] * g[1][0] * g[2][2]);
+  out[12] += w * (g[0][2] * g[1][1] * g[2][0] + g[0][0] * g[1][3] * g[2][0] + g[0][0] * g[1][1] * g[2][2]);
+  out[13] += w * (g[0][2] * g[1][0] * g[2][1] + g[0][0] * g[1][2] * g[2][1] + g[0][0] * g[1][0] * g[2][3]);
+}
+
 /* Basis function a at point r: out = [phi, grad(3), lap, hess xx yy zz xy xz yz,
  * grad lap (3)]. */
 void o_basis(const osys* s, int a, const double r[3], double out[14]) {
@@ -189,6 +224,32 @@ void o_basis(const osys* s, int a, const double r[3], double out[14]) {
     return;
   }
   int periodic = (s->basis_kind == OB_PERIODIC_GAUSS);
+  if (s->contracted) {
+    /* phi_1 + eta phi_2 with r^2 = x^2 + y^2 + z^2: four separable products,
+     * g1 g1 g1 + eta (h2 g2 g2 + g2 h2 g2 + g2 g2 h2) */
+    double g1[3][4], g2[3][4], h2[3][4];
+    for (int m = 0; m < 3; ++m) {
+      double d = r[m] - Ra[m], tau = ((s->twist >> m) & 1) ? -1.0 : 1.0, sg = 1.0;
+      if (periodic) {
+        double k = floor(d / s->L + 0.5);
+        d -= s->L * k;
+        if (fmod(fabs(k), 2.0) == 1.0) sg = tau;
+      }
+      gauss_1d(d, O_Z1, s->L, periodic, tau, g1[m]);
+      gauss_1d(d, O_Z2, s->L, periodic, tau, g2[m]);
+      gauss2_1d(d, O_Z2, s->L, periodic, tau, h2[m]);
+      for (int q = 0; q < 4; ++q) { g1[m][q] *= sg; g2[m][q] *= sg; h2[m][q] *= sg; }
+    }
+    for (int q = 0; q < 14; ++q) out[q] = 0.0;
+    add_product(g1, 1.0, out);
+    for (int m = 0; m < 3; ++m) {
+      double f[3][4];
+      for (int mm = 0; mm < 3; ++mm)
+        for (int q = 0; q < 4; ++q) f[mm][q] = (mm == m) ? h2[mm][q] : g2[mm][q];
+      add_product(f, s->eta, out);
+    }
+    return;
+  }
   double g[3][4];
   for (int m = 0; m < 3; ++m) {
     double d = r[m] - Ra[m], tau = ((s->twist >> m) & 1) ? -1.0 : 1.0, sg = 1.0;
@@ -616,6 +677,8 @@ int o_huckel(int n_p, double L, const double* R, const double* zeta, int n_orb, 
   return o_huckel_twist(n_p, L, R, zeta, n_orb, 0, C, evals);
 }
 
+static int huckel_from_overlap(int n_p, const double* S, int n_orb, double* C, double* evals);
+
 /* Hueckel orbitals of the twisted basis (real twists, bit m of twist = angle pi along m).
  * The cell overlap of two image sums is one image sum of the plane-space overlaps,
  * S_ab = sum_n tau^n (pi/(za+zb))^{3/2} e^{-mu |R_a - R_b + n L|^2}, tau^n = prod_m tau_m^{n_m}. */
@@ -635,6 +698,14 @@ int o_huckel_twist(int n_p, double L, const double* R, const double* zeta, int n
       }
       S[a * n_p + b] = v;
     }
+  int rc = huckel_from_overlap(n_p, S, n_orb, C, evals);
+  free(S);
+  return rc;
+}
+
+/* The Hueckel step shared by the bases: H = -S_ab / sqrt(S_aa S_bb), its eigenvectors by
+ * Jacobi rotations, the n_orb lowest v, C_ak = v_ak / sqrt(S_aa); evals ascending. */
+static int huckel_from_overlap(int n_p, const double* S, int n_orb, double* C, double* evals) {
   double* H = malloc(8 * n_p * n_p);
   double* Vv = malloc(8 * n_p * n_p);
   for (int a = 0; a < n_p; ++a)
@@ -651,8 +722,79 @@ int o_huckel_twist(int n_p, double L, const double* R, const double* zeta, int n
     for (int a = 0; a < n_p; ++a) C[a * n_orb + k] = Vv[a * n_p + order[k]] / sqrt(S[a * n_p + a]);
   if (evals)
     for (int k = 0; k < n_p; ++k) evals[k] = H[order[k] * n_p + order[k]];
-  free(S); free(H); free(Vv); free(order);
+  free(H); free(Vv); free(order);
   return 0;
+}
+
+/* One-dimensional Gaussian moments of e^{-al x^2} e^{-be (x - d)^2} = e^{-p (x - P)^2} e^{-mu d^2}
+ * (p = al + be, P = be d / p, mu = al be / p): with x = y + P, x - d = y - Q (Q = al d / p)
+ * and the moments m0 = sqrt(pi/p), m2 = m0/(2p), m4 = 3 m0/(4 p^2) of e^{-p y^2},
+ *   out[0] = int 1             = m0
+ *   out[1] = int x^2           = m2 + P^2 m0
+ *   out[2] = int (x-d)^2       = m2 + Q^2 m0
+ *   out[3] = int x^2 (x-d)^2   = m4 + ((P - Q)^2 - 2 P Q) m2 + P^2 Q^2 m0,
+ * each times e^{-mu d^2} and summed over the images d + n L, |n| <= 4. */
+static void moments_1d(double al, double be, double d, double L, double out[4]) {
+  const double p = al + be, mu = al * be / p;
+  const double m0 = sqrt(PI / p), m2 = m0 / (2.0 * p), m4 = 3.0 * m0 / (4.0 * p * p);
+  out[0] = out[1] = out[2] = out[3] = 0.0;
+  for (int n = -4; n <= 4; ++n) {
+    const double dd = d + n * L, e = exp(-mu * dd * dd);
+    const double P = be * dd / p, Q = al * dd / p;
+    out[0] += e * m0;
+    out[1] += e * (m2 + P * P * m0);
+    out[2] += e * (m2 + Q * Q * m0);
+    out[3] += e * (m4 + ((P - Q) * (P - Q) - 2.0 * P * Q) * m2 + P * P * Q * Q * m0);
+  }
+}
+
+/* S_ab = <phi_a | phi_b> over the cell for phi = g1 + eta h2 (g1 = e^{-Z1 r^2},
+ * h2 = r^2 e^{-Z2 r^2}): one image sum of free-space overlaps, every term separable, with x the
+ * coordinate relative to R_a, d = R_b - R_a and [.]_m the moments of axis m:
+ *   <g1|g1> = prod_m [1]_m                                          (Z1, Z1)
+ *   <g1|h2> = sum_m [(x-d)^2]_m prod_{m' != m} [1]_m'                  (Z1, Z2)
+ *   <h2|g1> = sum_m [x^2]_m prod_{m' != m} [1]_m'                      (Z2, Z1)
+ *   <h2|h2> = sum_m [x^2 (x-d)^2]_m prod_{m' != m} [1]_m'
+ *           + sum_{m != m'} [x^2]_m [(x-d)^2]_m' [1]_m''               (Z2, Z2) */
+void o_overlap_contracted(int n_p, double L, const double* R, double eta, double* S) {
+  for (int a = 0; a < n_p; ++a)
+    for (int b = 0; b < n_p; ++b) {
+      double m11[3][4], m12[3][4], m21[3][4], m22[3][4];
+      for (int m = 0; m < 3; ++m) {
+        const double d = R[3 * b + m] - R[3 * a + m];
+        moments_1d(O_Z1, O_Z1, d, L, m11[m]);
+        moments_1d(O_Z1, O_Z2, d, L, m12[m]);
+        moments_1d(O_Z2, O_Z1, d, L, m21[m]);
+        moments_1d(O_Z2, O_Z2, d, L, m22[m]);
+      }
+      const double s11 = m11[0][0] * m11[1][0] * m11[2][0];
+      double s12 = 0.0, s21 = 0.0, s22 = 0.0;
+      for (int m = 0; m < 3; ++m) {
+        double p12 = m12[m][2], p21 = m21[m][1], p22 = m22[m][3];
+        for (int q = 0; q < 3; ++q)
+          if (q != m) { p12 *= m12[q][0]; p21 *= m21[q][0]; p22 *= m22[q][0]; }
+        s12 += p12;
+        s21 += p21;
+        s22 += p22;
+        for (int m2 = 0; m2 < 3; ++m2) {
+          if (m2 == m) continue;
+          double pc = m22[m][1] * m22[m2][2];
+          for (int q = 0; q < 3; ++q)
+            if (q != m && q != m2) pc *= m22[q][0];
+          s22 += pc;
+        }
+      }
+      S[a * n_p + b] = s11 + eta * (s12 + s21) + eta * eta * s22;
+    }
+}
+
+int o_huckel_contracted(int n_p, double L, const double* R, double eta, int n_orb, double* C, double* evals) {
+  if (n_orb > n_p || n_orb < 0) return O_EINVAL;
+  double* S = malloc(8 * n_p * n_p);
+  o_overlap_contracted(n_p, L, R, eta, S);
+  int rc = huckel_from_overlap(n_p, S, n_orb, C, evals);
+  free(S);
+  return rc;
 }
 
 /* ------------------------------------------------------------ Metropolis -- */

@@ -37,7 +37,15 @@ typedef struct {
   int twist;           /* twisted boundary conditions with real twists: bit m set means
                           phi(r + L e_m) = -phi(r) (twist angle pi along axis m), clear means
                           periodic (angle 0); the Jastrow stays periodic */
+  int contracted;      /* 1: the SI's contracted orbital per proton, phi_1 + eta phi_2 with
+                          phi_1 = e^{-Z1 r^2}, phi_2 = r^2 e^{-Z2 r^2} (O_Z1, O_Z2; zeta unused),
+                          with the same image sums and twists as the single Gaussian; 0: e^{-zeta r^2} */
+  double eta;          /* the contraction coefficient eta (contracted = 1) */
 } osys;
+
+/* The SI's exponents of the contracted minimal basis (section "Systematic setup"). */
+#define O_Z1 0.6066825
+#define O_Z2 0.3382168
 
 /* Philox4x32-10 counter-based generator (Salmon et al., SC'11). */
 void o_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -50,6 +58,12 @@ int o_local(const osys* s, const double* x, double* lnpsi, double* sign, double*
             double* dlnpsi_dR, double* dEL_dR);
 int o_huckel(int n_p, double L, const double* R, const double* zeta, int n_orb,
              double* C, double* evals);
+/* Hueckel orbitals on the contracted periodic basis (no twist): the overlaps of
+ * phi_1 + eta phi_2 from one image sum of the free-space overlaps of e^{-Z r^2} and
+ * r^2 e^{-Z r^2}, written out as one-dimensional Gaussian moments. */
+int o_huckel_contracted(int n_p, double L, const double* R, double eta, int n_orb, double* C, double* evals);
+/* The overlap matrix of the contracted periodic basis (n_p x n_p). */
+void o_overlap_contracted(int n_p, double L, const double* R, double eta, double* S);
 int o_huckel_twist(int n_p, double L, const double* R, const double* zeta, int n_orb, int twist,
                    double* C, double* evals);
 int o_vmc_run(const osys* s, int W, double* x, int n_equil, int n_meas, double delta,
