@@ -98,6 +98,16 @@ typedef struct {
                          Both spins use the same twist.  Not for the server (VMC_EINVAL).
                          0: real orbitals, twist as above */
   double theta[3];    /* twist angles per axis, radians (general_twist = 1 only; finite) */
+  int contracted;     /* 1: the SI's contracted minimal basis (section "Systematic setup"): one
+                         orbital per proton, phi_1 + eta phi_2 with phi_1 = e^{-Z1 r^2},
+                         phi_2 = r^2 e^{-Z2 r^2}, Z1 = 0.6066825, Z2 = 0.3382168, image-summed like the
+                         single Gaussian; zeta is then not used (but must still be a valid pointer).
+                         C must come from vmc_huckel_params_contracted.  Requires twist = 0,
+                         general_twist = 0, N_sigma <= 64 and a box with Z2 (1.5 L)^2 >= 36
+                         (L >= 6.88 bohr: the images |n| <= 1 of the diffuse phi_2 then reach
+                         FP64 resolution); not for the server.  Else VMC_EINVAL.
+                         0: one s-Gaussian e^{-zeta_a r^2} per proton */
+  double eta;         /* the contraction coefficient (contracted = 1; finite) */
 } vmc_system;
 
 /* ---------------------------------------------------------------- context -- */
@@ -312,6 +322,12 @@ int vmc_huckel_params(int n_protons, double box_L, const double* R, const double
  * prod_m (+-1)^{n_m}.  twist = 0 is vmc_huckel_params; outside 0..7: VMC_EINVAL. */
 int vmc_huckel_params_twist(int n_protons, double box_L, int twist, const double* R, const double* zeta,
                             double* C_out);
+
+/* The same for the contracted basis (vmc_system.contracted, coefficient eta): the overlaps of
+ * phi_1 + eta phi_2 are one image sum of free-space Gaussian overlaps and of their derivatives
+ * with respect to the exponents (r^2 e^{-Z r^2} = -d/dZ e^{-Z r^2}).  C_out: host N x N/2.
+ * VMC_EINVAL for a non-finite R or eta, VMC_ENOCONV if the QR iteration does not converge. */
+int vmc_huckel_params_contracted(int n_protons, double box_L, double eta, const double* R, double* C_out);
 
 /* The same for a general twist (vmc_system.general_twist): image n of the overlap sum carries
  * e^{-i theta.n}, S and H are Hermitian, and C_out receives N x N/2 complex coefficients as

@@ -197,6 +197,102 @@ __device__ __forceinline__ void basis_axis(double d, Real zeta, double L, double
   }
 }
 
+// The SI's contracted orbital per proton, phi_1 + eta phi_2 with phi_1 = e^{-Z1 r^2} and
+// phi_2 = r^2 e^{-Z2 r^2}.  Writing r^2 = x^2 + y^2 + z^2 makes it a sum of four products of
+// Cartesian factors, g1 g1 g1 + eta (h2 g2 g2 + g2 h2 g2 + g2 g2 h2), with the image sums (at the
+// minimum image, images n = -NIMG..NIMG) of g1 = e^{-Z1 t^2}, g2 = e^{-Z2 t^2} and
+// h2 = t^2 e^{-Z2 t^2} and their first NDER derivatives.
+constexpr double kZ1 = 0.6066825, kZ2 = 0.3382168;
+template <class Real, int NDER, int NIMG>
+__device__ __forceinline__ void contracted_axis(double d, double L, double invL, Real g1[4], Real g2[4], Real h2[4]) {
+  const double k = floor(d * invL + 0.5);
+  const Real x = (Real)(d - L * k), Lr = (Real)L, z1 = (Real)kZ1, z2 = (Real)kZ2;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) g1[q] = g2[q] = h2[q] = Real(0);
+#pragma unroll
+  for (int n = -NIMG; n <= NIMG; ++n) {
+    const Real t = x + Real(n) * Lr, t2 = t * t;
+    const Real e1 = dev_exp<Real>(-z1 * t2), e2 = dev_exp<Real>(-z2 * t2);
+    g1[0] += e1;
+    g2[0] += e2;
+    h2[0] += t2 * e2;
+    if (NDER >= 1) {
+      g1[1] += Real(-2) * z1 * t * e1;
+      g2[1] += Real(-2) * z2 * t * e2;
+      h2[1] += (Real(2) * t - Real(2) * z2 * t2 * t) * e2;
+    }
+    if (NDER >= 2) {
+      g1[2] += (Real(4) * z1 * z1 * t2 - Real(2) * z1) * e1;
+      g2[2] += (Real(4) * z2 * z2 * t2 - Real(2) * z2) * e2;
+      h2[2] += (Real(2) - Real(10) * z2 * t2 + Real(4) * z2 * z2 * t2 * t2) * e2;
+    }
+    if (NDER >= 3) {
+      g1[3] += (Real(-8) * z1 * z1 * z1 * t2 * t + Real(12) * z1 * z1 * t) * e1;
+      g2[3] += (Real(-8) * z2 * z2 * z2 * t2 * t + Real(12) * z2 * z2 * t) * e2;
+      h2[3] += (Real(-24) * z2 * t + Real(36) * z2 * z2 * t2 * t - Real(8) * z2 * z2 * z2 * t2 * t2 * t) * e2;
+    }
+  }
+}
+
+template <class Real, int NIMG>
+__device__ __forceinline__ Real contracted_value(double rx, double ry, double rz, const double* Ra, Real eta,
+                                                 double L, double invL) {
+  Real a1[3][4], a2[3][4], b2[3][4];
+  contracted_axis<Real, 0, NIMG>(rx - Ra[0], L, invL, a1[0], a2[0], b2[0]);
+  contracted_axis<Real, 0, NIMG>(ry - Ra[1], L, invL, a1[1], a2[1], b2[1]);
+  contracted_axis<Real, 0, NIMG>(rz - Ra[2], L, invL, a1[2], a2[2], b2[2]);
+  return a1[0][0] * a1[1][0] * a1[2][0] +
+         eta * (b2[0][0] * a2[1][0] * a2[2][0] + a2[0][0] * b2[1][0] * a2[2][0] + a2[0][0] * a2[1][0] * b2[2][0]);
+}
+
+// Derivative components of a basis function: gradient, Hessian and (FULL) gradient of the
+// Laplacian; product_terms adds w times those of a product of Cartesian factors f[axis][order].
+template <class Real>
+struct BasisD {
+  Real gx, gy, gz, hxx, hyy, hzz, hxy, hxz, hyz, glx, gly, glz;
+};
+template <class Real, bool FULL>
+__device__ __forceinline__ void product_terms(const Real (&f)[3][4], Real w, BasisD<Real>& o) {
+  const Real p00 = f[1][0] * f[2][0], p01 = f[0][0] * f[2][0], p02 = f[0][0] * f[1][0];
+  o.gx += w * f[0][1] * p00;
+  o.gy += w * f[1][1] * p01;
+  o.gz += w * f[2][1] * p02;
+  if (FULL) {
+    o.hxx += w * f[0][2] * p00;
+    o.hyy += w * f[1][2] * p01;
+    o.hzz += w * f[2][2] * p02;
+    o.hxy += w * f[0][1] * f[1][1] * f[2][0];
+    o.hxz += w * f[0][1] * f[1][0] * f[2][1];
+    o.hyz += w * f[0][0] * f[1][1] * f[2][1];
+    o.glx += w * (f[0][3] * p00 + f[0][1] * (f[1][2] * f[2][0] + f[1][0] * f[2][2]));
+    o.gly += w * (f[1][3] * p01 + f[1][1] * (f[0][2] * f[2][0] + f[0][0] * f[2][2]));
+    o.glz += w * (f[2][3] * p02 + f[2][1] * (f[0][2] * f[1][0] + f[0][0] * f[1][2]));
+  }
+}
+// The components of the contracted orbital at offset (dx, dy, dz) from its centre.
+template <class Real, int NIMG, bool FULL>
+__device__ __forceinline__ BasisD<Real> contracted_derivs(double dx, double dy, double dz, Real eta, double L,
+                                                           double invL) {
+  constexpr int ND = FULL ? 3 : 1;
+  Real a1[3][4], a2[3][4], b2[3][4];
+  contracted_axis<Real, ND, NIMG>(dx, L, invL, a1[0], a2[0], b2[0]);
+  contracted_axis<Real, ND, NIMG>(dy, L, invL, a1[1], a2[1], b2[1]);
+  contracted_axis<Real, ND, NIMG>(dz, L, invL, a1[2], a2[2], b2[2]);
+  BasisD<Real> o = {Real(0), Real(0), Real(0), Real(0), Real(0), Real(0), Real(0), Real(0), Real(0), Real(0),
+                    Real(0), Real(0)};
+  product_terms<Real, FULL>(a1, Real(1), o);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    Real f[3][4];
+#pragma unroll
+    for (int mm = 0; mm < 3; ++mm)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) f[mm][q] = (mm == m) ? b2[mm][q] : a2[mm][q];
+    product_terms<Real, FULL>(f, eta, o);
+  }
+  return o;
+}
+
 // Orders this wave's LDS writes before its later LDS reads (the wave's LDS
 // operations complete in order; the clobber keeps the compiler from moving them).
 __device__ __forceinline__ void lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }

@@ -263,6 +263,75 @@ extern "C" int vmc_huckel_params_twist(int n, double L, int twist, const double*
 }
 
 
+// Per axis of the contracted overlap: s(al, be) = sqrt(pi/p) sum_n e^{-mu dn^2} (p = al + be,
+// mu = al be / p, dn = d + n L) and its exponent derivatives; with r^2 e^{-Z r^2} = -d/dZ e^{-Z r^2}
+// the overlaps <h2|g> = -ds/dal, <g|h2> = -ds/dbe, <h2|h2> = d2s/(dal dbe) on each axis, using
+// dp/dal = 1, dmu/dal = be^2/p^2, dmu/dbe = al^2/p^2.
+static void axis_exponent_derivs(double al, double be, double d, double L, double out[4]) {
+  const double p = al + be, mu = al * be / p, c = std::sqrt(M_PI / p);
+  const double ka = be * be / (p * p), kb = al * al / (p * p);
+  out[0] = out[1] = out[2] = out[3] = 0.0;
+  for (int n = -4; n <= 4; ++n) {
+    const double dn = d + n * L, d2 = dn * dn, e = c * std::exp(-mu * d2);
+    const double fa = -0.5 / p - ka * d2, fb = -0.5 / p - kb * d2;
+    // d/dbe of (fa) = 1/(2 p^2) - 2 be d2 / p^2 + 2 be^2 d2 / p^3
+    const double fab = 0.5 / (p * p) - 2.0 * be * d2 / (p * p) + 2.0 * be * be * d2 / (p * p * p);
+    out[0] += e;
+    out[1] += e * fa;
+    out[2] += e * fb;
+    out[3] += e * (fa * fb + fab);
+  }
+}
+
+extern "C" int vmc_huckel_params_contracted(int n, double L, double eta, const double* R, double* C_out) {
+  if (n < 2 || (n & 1) || !(L > 0.0) || !R || !C_out || !std::isfinite(eta)) return VMC_EINVAL;
+  for (int i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(R[i])) return VMC_EINVAL;
+  const double z1 = 0.6066825, z2 = 0.3382168;
+  std::vector<double> S((size_t)n * n), H((size_t)n * n), Q;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      double s11[3][4], s12[3][4], s21[3][4], s22[3][4];
+      for (int m = 0; m < 3; ++m) {
+        const double d = R[3 * a + m] - R[3 * b + m];
+        axis_exponent_derivs(z1, z1, d, L, s11[m]);
+        axis_exponent_derivs(z1, z2, d, L, s12[m]);
+        axis_exponent_derivs(z2, z1, d, L, s21[m]);
+        axis_exponent_derivs(z2, z2, d, L, s22[m]);
+      }
+      // g1 g1; g1 h2 = -d/dbe; h2 g1 = -d/dal; h2 h2 = d2/(dal dbe), by the product rule over the axes
+      double v = s11[0][0] * s11[1][0] * s11[2][0];
+      double gh = 0.0, hg = 0.0, hh = 0.0;
+      for (int m = 0; m < 3; ++m) {
+        const int m1 = (m + 1) % 3, m2 = (m + 2) % 3;
+        gh -= s12[m][2] * s12[m1][0] * s12[m2][0];
+        hg -= s21[m][1] * s21[m1][0] * s21[m2][0];
+        hh += s22[m][3] * s22[m1][0] * s22[m2][0];
+        for (int q = 0; q < 3; ++q)
+          if (q != m) {
+            const int r = 3 - m - q;
+            hh += s22[m][1] * s22[q][2] * s22[r][0];
+          }
+      }
+      S[(size_t)a * n + b] = v + eta * (gh + hg) + eta * eta * hh;
+    }
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b)
+      H[(size_t)a * n + b] = -S[(size_t)a * n + b] / std::sqrt(S[(size_t)a * n + a] * S[(size_t)b * n + b]);
+  householder_tridiag(n, H, Q);
+  int rc = tridiag_qr(n, H, Q);
+  if (rc) return rc;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return H[(size_t)x * n + x] < H[(size_t)y * n + y]; });
+  const int no = n / 2;
+  for (int k = 0; k < no; ++k)
+    for (int a = 0; a < n; ++a)
+      C_out[(size_t)a * no + k] = Q[(size_t)a * n + order[k]] / std::sqrt(S[(size_t)a * n + a]);
+  return VMC_OK;
+}
+
 extern "C" int vmc_huckel_params_theta(int n, double L, const double* theta, const double* R, const double* zeta,
                                        double* C_out) {
   if (n < 2 || (n & 1) || !(L > 0.0) || !theta || !R || !zeta || !C_out) return VMC_EINVAL;

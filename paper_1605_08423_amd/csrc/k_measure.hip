@@ -365,7 +365,7 @@ __device__ __forceinline__ void gemm_stage_a(const Op* A, int lda, const Op* B, 
   __syncthreads();
 }
 
-template <int NS, class Real, int NIMG, bool BATCH, bool TW>
+template <int NS, class Real, int NIMG, bool BATCH, bool TW, bool CB = false>
 __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sample(MeasureArgs m, Batch bt) {
   using Lay = SlaterLds<NS, Real>;
   constexpr int N = 2 * NS;
@@ -593,15 +593,24 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll 1
         for (int c = c0; c < c1; ++c) {
-          const Real zc = (Real)m.zeta[c];
-          Real g[3][4];
-          basis_axis<Real, 1, NIMG, TW>(pos[3 * e] - m.R[3 * c], zc, L, invL, m.twist & 1, g[0]);
-          basis_axis<Real, 1, NIMG, TW>(pos[3 * e + 1] - m.R[3 * c + 1], zc, L, invL, (m.twist >> 1) & 1, g[1]);
-          basis_axis<Real, 1, NIMG, TW>(pos[3 * e + 2] - m.R[3 * c + 2], zc, L, invL, (m.twist >> 2) & 1, g[2]);
           const double b = (double)Bs[c * LDB + i];
-          s0 += b * (double)(g[0][1] * g[1][0] * g[2][0]);
-          s1 += b * (double)(g[0][0] * g[1][1] * g[2][0]);
-          s2 += b * (double)(g[0][0] * g[1][0] * g[2][1]);
+          if constexpr (CB) {
+            const BasisD<Real> q = contracted_derivs<Real, NIMG, false>(
+                pos[3 * e] - m.R[3 * c], pos[3 * e + 1] - m.R[3 * c + 1], pos[3 * e + 2] - m.R[3 * c + 2],
+                (Real)m.eta, L, invL);
+            s0 += b * (double)q.gx;
+            s1 += b * (double)q.gy;
+            s2 += b * (double)q.gz;
+          } else {
+            const Real zc = (Real)m.zeta[c];
+            Real g[3][4];
+            basis_axis<Real, 1, NIMG, TW>(pos[3 * e] - m.R[3 * c], zc, L, invL, m.twist & 1, g[0]);
+            basis_axis<Real, 1, NIMG, TW>(pos[3 * e + 1] - m.R[3 * c + 1], zc, L, invL, (m.twist >> 1) & 1, g[1]);
+            basis_axis<Real, 1, NIMG, TW>(pos[3 * e + 2] - m.R[3 * c + 2], zc, L, invL, (m.twist >> 2) & 1, g[2]);
+            s0 += b * (double)(g[0][1] * g[1][0] * g[2][0]);
+            s1 += b * (double)(g[0][0] * g[1][1] * g[2][0]);
+            s2 += b * (double)(g[0][0] * g[1][0] * g[2][1]);
+          }
         }
         gp[3 * u] = s0; gp[3 * u + 1] = s1; gp[3 * u + 2] = s2;
       }
@@ -621,20 +630,29 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         const int i = h + H * s;
         if (i >= NS) continue;
         const int e = sp * NS + i;
-        Real g[3][4];
-        basis_axis<Real, 3, NIMG, TW>(pos[3 * e] - Ra0, za, L, invL, m.twist & 1, g[0]);
-        basis_axis<Real, 3, NIMG, TW>(pos[3 * e + 1] - Ra1, za, L, invL, (m.twist >> 1) & 1, g[1]);
-        basis_axis<Real, 3, NIMG, TW>(pos[3 * e + 2] - Ra2, za, L, invL, (m.twist >> 2) & 1, g[2]);
-        const Real p00 = g[1][0] * g[2][0], p01 = g[0][0] * g[2][0], p02 = g[0][0] * g[1][0];
         // per-pair brackets in Real (FP32 in mixed mode, from FP32 basis values), sums in FP64
-        const Real gx = g[0][1] * p00, gy = g[1][1] * p01, gz = g[2][1] * p02;
-        const Real hxx = g[0][2] * p00, hyy = g[1][2] * p01, hzz = g[2][2] * p02;
-        const Real hxy = g[0][1] * g[1][1] * g[2][0], hxz = g[0][1] * g[1][0] * g[2][1];
-        const Real hyz = g[0][0] * g[1][1] * g[2][1];
+        Real gx, gy, gz, hxx, hyy, hzz, hxy, hxz, hyz, glx, gly, glz;
+        if constexpr (CB) {
+          const BasisD<Real> q = contracted_derivs<Real, NIMG, true>(pos[3 * e] - Ra0, pos[3 * e + 1] - Ra1,
+                                                                     pos[3 * e + 2] - Ra2, (Real)m.eta, L, invL);
+          gx = q.gx; gy = q.gy; gz = q.gz;
+          hxx = q.hxx; hyy = q.hyy; hzz = q.hzz; hxy = q.hxy; hxz = q.hxz; hyz = q.hyz;
+          glx = q.glx; gly = q.gly; glz = q.glz;
+        } else {
+          Real g[3][4];
+          basis_axis<Real, 3, NIMG, TW>(pos[3 * e] - Ra0, za, L, invL, m.twist & 1, g[0]);
+          basis_axis<Real, 3, NIMG, TW>(pos[3 * e + 1] - Ra1, za, L, invL, (m.twist >> 1) & 1, g[1]);
+          basis_axis<Real, 3, NIMG, TW>(pos[3 * e + 2] - Ra2, za, L, invL, (m.twist >> 2) & 1, g[2]);
+          const Real p00 = g[1][0] * g[2][0], p01 = g[0][0] * g[2][0], p02 = g[0][0] * g[1][0];
+          gx = g[0][1] * p00; gy = g[1][1] * p01; gz = g[2][1] * p02;
+          hxx = g[0][2] * p00; hyy = g[1][2] * p01; hzz = g[2][2] * p02;
+          hxy = g[0][1] * g[1][1] * g[2][0]; hxz = g[0][1] * g[1][0] * g[2][1];
+          hyz = g[0][0] * g[1][1] * g[2][1];
+          glx = g[0][3] * p00 + g[0][1] * (g[1][2] * g[2][0] + g[1][0] * g[2][2]);
+          gly = g[1][3] * p01 + g[1][1] * (g[0][2] * g[2][0] + g[0][0] * g[2][2]);
+          glz = g[2][3] * p02 + g[2][1] * (g[0][2] * g[1][0] + g[0][0] * g[1][2]);
+        }
         const Real lap = hxx + hyy + hzz;
-        const Real glx = g[0][3] * p00 + g[0][1] * (g[1][2] * g[2][0] + g[1][0] * g[2][2]);
-        const Real gly = g[1][3] * p01 + g[1][1] * (g[0][2] * g[2][0] + g[0][0] * g[2][2]);
-        const Real glz = g[2][3] * p02 + g[2][1] * (g[0][2] * g[1][0] + g[0][0] * g[1][2]);
         const Real u0 = (Real)gU[3 * e], u1 = (Real)gU[3 * e + 1], u2 = (Real)gU[3 * e + 2];
         const Real X = Real(-0.5) * (lap + Real(2) * (gx * u0 + gy * u1 + gz * u2));
         Xr[i * LDX + a] = X;
@@ -786,13 +804,21 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
         if (i >= NS) continue;
         const double Wv = (double)Ws[a * LDB + i];
         const int e = sp * NS + i;
-        Real g[3][4];
-        basis_axis<Real, 1, NIMG, TW>(pos[3 * e] - Ra0, za, L, invL, m.twist & 1, g[0]);
-        basis_axis<Real, 1, NIMG, TW>(pos[3 * e + 1] - Ra1, za, L, invL, (m.twist >> 1) & 1, g[1]);
-        basis_axis<Real, 1, NIMG, TW>(pos[3 * e + 2] - Ra2, za, L, invL, (m.twist >> 2) & 1, g[2]);
-        dT0 += (double)(g[0][1] * g[1][0] * g[2][0]) * Wv;
-        dT1 += (double)(g[0][0] * g[1][1] * g[2][0]) * Wv;
-        dT2 += (double)(g[0][0] * g[1][0] * g[2][1]) * Wv;
+        if constexpr (CB) {
+          const BasisD<Real> q = contracted_derivs<Real, NIMG, false>(pos[3 * e] - Ra0, pos[3 * e + 1] - Ra1,
+                                                                      pos[3 * e + 2] - Ra2, (Real)m.eta, L, invL);
+          dT0 += (double)q.gx * Wv;
+          dT1 += (double)q.gy * Wv;
+          dT2 += (double)q.gz * Wv;
+        } else {
+          Real g[3][4];
+          basis_axis<Real, 1, NIMG, TW>(pos[3 * e] - Ra0, za, L, invL, m.twist & 1, g[0]);
+          basis_axis<Real, 1, NIMG, TW>(pos[3 * e + 1] - Ra1, za, L, invL, (m.twist >> 1) & 1, g[1]);
+          basis_axis<Real, 1, NIMG, TW>(pos[3 * e + 2] - Ra2, za, L, invL, (m.twist >> 2) & 1, g[2]);
+          dT0 += (double)(g[0][1] * g[1][0] * g[2][0]) * Wv;
+          dT1 += (double)(g[0][0] * g[1][1] * g[2][0]) * Wv;
+          dT2 += (double)(g[0][0] * g[1][0] * g[2][1]) * Wv;
+        }
       }
     }
     __syncthreads();
@@ -951,9 +977,26 @@ hipError_t launch_slater_tw(const MeasureArgs& m, hipStream_t st, const Batch* b
     hipLaunchKernelGGL((k_slater_sample<NS, Real, 0, false, TW>), grid, dim3(256), sm, st, m, b);
   return hipGetLastError();
 }
+// The contracted orbital: single trajectories without twist, N_sigma <= 64.
+template <int NS, class Real>
+hipError_t launch_slater_cb(const MeasureArgs& m, hipStream_t st, const Batch* bt) {
+  if constexpr (NS > 64) {
+    return hipErrorInvalidValue;
+  } else {
+    if (bt || m.twist) return hipErrorInvalidValue;
+    const Batch b{nullptr, nullptr, 0};
+    const size_t sm = SlaterLds<NS, Real>::bytes;
+    if (m.nimg || sizeof(Real) == 8)
+      hipLaunchKernelGGL((k_slater_sample<NS, Real, 1, false, false, true>), dim3(m.W), dim3(256), sm, st, m, b);
+    else
+      hipLaunchKernelGGL((k_slater_sample<NS, Real, 0, false, false, true>), dim3(m.W), dim3(256), sm, st, m, b);
+    return hipGetLastError();
+  }
+}
 // (a batch holds only twisted or only untwisted trajectories: the request loop buckets them apart)
 template <int NS, class Real>
 hipError_t launch_slater_t(const MeasureArgs& m, hipStream_t st, const Batch* bt, int nblk) {
+  if (m.contracted) return launch_slater_cb<NS, Real>(m, st, bt);
   return m.twist ? launch_slater_tw<NS, Real, true>(m, st, bt, nblk) : launch_slater_tw<NS, Real, false>(m, st, bt, nblk);
 }
 
@@ -991,6 +1034,7 @@ hipError_t launch_slater_fp64_tw(const MeasureArgs& m, hipStream_t st, const Bat
 }
 template <int NS>
 hipError_t launch_slater_fp64(const MeasureArgs& m, hipStream_t st, const Batch* bt, int nblk) {
+  if (m.contracted) return launch_slater_cb<NS, double>(m, st, bt);
   return m.twist ? launch_slater_fp64_tw<NS, true>(m, st, bt, nblk) : launch_slater_fp64_tw<NS, false>(m, st, bt, nblk);
 }
 hipError_t launch_slater_sample(const MeasureArgs& m, int mixed, hipStream_t st, const Batch* bt, int nblk) {

@@ -31,7 +31,7 @@ __device__ __forceinline__ Real phi_value(double rx, double ry, double rz, const
 
 // --------------------------------------------------------------- build A ---
 // One wave per walker; electrons in order, lanes over centres then orbitals.
-template <int NS, class Real, int NIMG, bool TW>
+template <int NS, class Real, int NIMG, bool TW, bool CB = false>
 __global__ __launch_bounds__(256) void k_build_A(WalkerArgs a) {
   constexpr int N = 2 * NS;
   constexpr int WPB = 4;
@@ -43,7 +43,8 @@ __global__ __launch_bounds__(256) void k_build_A(WalkerArgs a) {
   for (int e = 0; e < N; ++e) {
     double rx = p[3 * e], ry = p[3 * e + 1], rz = p[3 * e + 2];
     for (int c = lane; c < N; c += 64)
-      phi_s[wv][c] = phi_value<Real, NIMG, TW>(rx, ry, rz, a.R + 3 * c, (Real)a.zeta[c], a.L, a.invL, a.twist);
+      phi_s[wv][c] = CB ? contracted_value<Real, NIMG>(rx, ry, rz, a.R + 3 * c, (Real)a.eta, a.L, a.invL)
+                        : phi_value<Real, NIMG, TW>(rx, ry, rz, a.R + 3 * c, (Real)a.zeta[c], a.L, a.invL, a.twist);
     wave_lds_sync();
     for (int k = lane; k < NS; k += 64) {
       double m = 0.0;
@@ -411,7 +412,7 @@ __device__ __forceinline__ double one_body_change(const Real* Rt, double xo, dou
 // Every LDS row access of the recursion is lane-private (lane = column).
 // One wave per walker; the inverse lives in matrix-core accumulator layout
 // (tile (tr, tc), element v of lane l = A^-1[16 tr + 4 v + l/16][16 tc + l%16]).
-template <int NS, class Real, int NIMG, bool BATCH, bool TW>
+template <int NS, class Real, int NIMG, bool BATCH, bool TW, bool CB = false>
 __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s, Batch bt) {
   constexpr int N = 2 * NS;
   using LY = SweepLds<NS>;
@@ -548,7 +549,10 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
       double ph = 0.0;
       if (cv_ok && pvalid) {
         const double* Rc = Rs + 4 * cc;
-        ph = (double)phi_value<Real, NIMG, TW>(xn, yn, zn, Rc, (Real)Rc[3], L, invL, a.twist);
+        if constexpr (CB)
+          ph = (double)contracted_value<Real, NIMG>(xn, yn, zn, Rc, (Real)a.eta, L, invL);
+        else
+          ph = (double)phi_value<Real, NIMG, TW>(xn, yn, zn, Rc, (Real)Rc[3], L, invL, a.twist);
       }
 #pragma unroll
       for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_w(ph, bvs[tc], acc[tc]);
@@ -1335,6 +1339,19 @@ hipError_t launch_build_A_tw(const WalkerArgs& a, hipStream_t st) {
 }
 template <int NS, class Real>
 hipError_t launch_build_A_t(const WalkerArgs& a, hipStream_t st) {
+  if (a.contracted) {
+    if constexpr (NS > 64) {
+      return hipErrorInvalidValue;
+    } else {
+      if (a.twist) return hipErrorInvalidValue;
+      dim3 grid((a.W + 3) / 4);
+      if (a.nimg || sizeof(Real) == 8)
+        hipLaunchKernelGGL((k_build_A<NS, Real, 1, false, true>), grid, dim3(256), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_build_A<NS, Real, 0, false, true>), grid, dim3(256), 0, st, a);
+      return hipGetLastError();
+    }
+  }
   return a.twist ? launch_build_A_tw<NS, Real, true>(a, st) : launch_build_A_tw<NS, Real, false>(a, st);
 }
 inline Batch batch_or_none(const Batch* bt) { return bt ? *bt : Batch{nullptr, nullptr, 0}; }
@@ -1424,6 +1441,24 @@ hipError_t launch_sweep_tw(const WalkerArgs& a, const SweepArgs& s, hipStream_t 
 
 template <int NS, class Real>
 hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t st, const Batch* bt, int nblk) {
+  if (a.contracted) {
+    // the contracted orbital: single trajectories without twist, N_sigma <= 64
+    if constexpr (NS > 64) {
+      return hipErrorInvalidValue;
+    } else {
+      if (bt || a.twist) return hipErrorInvalidValue;
+      const size_t tab = a.j1_beta > 0.0 ? one_body_table_bytes<Real>(2 * NS, SweepLds<NS>::NSP) : 0;
+      const size_t sm = sweep_smem<NS, Real>() + tab;
+      dim3 grid((a.W + 3) / 4);
+      if (a.nimg || sizeof(Real) == 8)
+        hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, false, false, true>), grid, dim3(256), sm, st, a, s,
+                           batch_or_none(bt));
+      else
+        hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, false, false, true>), grid, dim3(256), sm, st, a, s,
+                           batch_or_none(bt));
+      return hipGetLastError();
+    }
+  }
   return a.twist ? launch_sweep_tw<NS, Real, true>(a, s, st, bt, nblk) : launch_sweep_tw<NS, Real, false>(a, s, st, bt, nblk);
 }
 

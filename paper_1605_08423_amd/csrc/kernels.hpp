@@ -25,6 +25,8 @@ struct WalkerArgs {
   int* rflag;          // W x 2: 1 = the refinement step left a large residual, redo by elimination
   double* rscr;        // N_sigma > 64: per-walker scratch of the refinement (N_sigma^2 doubles at rscr_stride)
   size_t rscr_stride;
+  int contracted;      // 1: the contracted orbital phi_1 + eta phi_2 per proton (zeta unused)
+  double eta;
 };
 
 struct SweepArgs {
@@ -68,6 +70,8 @@ struct MeasureArgs {
   double* acc;          // W x (2 + 9N): sum E_L, sum E_L^2, sum dE_L/dR, sum dlnpsi/dR, sum E_L dlnpsi/dR
   double* rho_acc;      // W x nk x 2: sum of the electron structure factor
   unsigned char* scr;   // W x slater_scratch_bytes(NS, mixed): matrix products that do not fit in LDS
+  int contracted;       // as in WalkerArgs
+  double eta;
 };
 
 // Several trajectories of one bucket (N, precision, Gaussian images, Ewald cut-off)

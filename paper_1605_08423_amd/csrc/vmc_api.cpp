@@ -163,6 +163,8 @@ int dalloc(T** p, size_t n) {
 
 bool supported_ns(int ns) { return ns == 8 || ns == 16 || ns == 27 || ns == 32 || ns == 64 || ns == 128; }
 
+constexpr double kContractedZ2 = 0.3382168;   // the smaller exponent of the contracted orbital
+
 int check_sys(const vmc_system* s) {
   if (!s) return VMC_EINVAL;
   if (s->n_protons < 2 || (s->n_protons & 1) || !supported_ns(s->n_protons / 2)) return VMC_EINVAL;
@@ -176,6 +178,14 @@ int check_sys(const vmc_system* s) {
     if (s->precision != VMC_FP64 || s->twist != 0 || s->j1_b1 != 0.0 || s->n_protons / 2 > 64) return VMC_EINVAL;
     for (int m = 0; m < 3; ++m)
       if (!std::isfinite(s->theta[m])) return VMC_EINVAL;
+  }
+  if (s->contracted != 0 && s->contracted != 1) return VMC_EINVAL;
+  if (s->contracted) {
+    // the images |n| <= 1 of the diffuse r^2 e^{-Z2 r^2} reach FP64 resolution only if Z2 (1.5 L)^2 >= 36
+    const double h = 1.5 * s->box_L;
+    if (s->twist != 0 || s->general_twist || s->n_protons / 2 > 64 || !std::isfinite(s->eta) ||
+        kContractedZ2 * h * h < 36.0)
+      return VMC_EINVAL;
   }
   return VMC_OK;
 }
@@ -213,7 +223,8 @@ int image_rule(const vmc_system& s, const double* zeta_host) {
 }
 int image_count(vmc_traj* t, const double* zeta_dev, int* nimg) {
   *nimg = 1;
-  if (t->sys.precision != VMC_MIXED) return VMC_OK;
+  // the contracted orbital keeps all three images (its r^2 e^{-Z2 r^2} part is diffuse)
+  if (t->sys.precision != VMC_MIXED || t->sys.contracted) return VMC_OK;
   std::vector<double> z(t->N);
   HIPCHK(hipMemcpyAsync(z.data(), zeta_dev, t->N * sizeof(double), hipMemcpyDeviceToHost, t->ctx->stream));
   HIPCHK(hipStreamSynchronize(t->ctx->stream));
@@ -239,6 +250,8 @@ WalkerArgs walker_args(vmc_traj* t, const double* R, const double* C, const doub
   // measurement scratch (the measurement never runs during a refresh)
   a.rscr = reinterpret_cast<double*>(t->scr);
   a.rscr_stride = slater_scratch_bytes(t->NS, t->sys.precision == VMC_MIXED) / sizeof(double);
+  a.contracted = t->sys.contracted;
+  a.eta = t->sys.eta;
   return a;
 }
 
@@ -252,6 +265,8 @@ MeasureArgs measure_args(vmc_traj* t, const double* R, const double* C, const do
   m.twist = t->sys.twist;
   m.pos = t->pos; m.Binv = t->Binv; m.Vs = t->Vs; m.dVs = t->dVs; m.Uj = t->Uj;
   m.acc = t->acc; m.rho_acc = t->rho_acc; m.scr = t->scr;
+  m.contracted = t->sys.contracted;
+  m.eta = t->sys.eta;
   return m;
 }
 
@@ -1255,7 +1270,7 @@ int bucket_sweep(vmc_server* s, const std::vector<Served*>& qs) {
 }
 
 int check_request(const vmc_request* r) {
-  if (!r || check_sys(&r->sys) || r->sys.general_twist) return VMC_EINVAL;
+  if (!r || check_sys(&r->sys) || r->sys.general_twist || r->sys.contracted) return VMC_EINVAL;
   if (r->n_walkers < 2 || r->n_sweeps < 1 || r->n_equil < 0 || r->n_equil_first < 0 || r->n_steps < 1)
     return VMC_EINVAL;
   if (!(r->step_delta > 0.0) || !(r->Delta > 0.0) || r->alpha < 0.0 || r->T < 0.0 || (r->flags & ~7u))

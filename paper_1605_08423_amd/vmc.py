@@ -28,7 +28,8 @@ EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_
             "vmc_server_result", "vmc_server_info", "vmc_toy_run", "vmc_huckel_params_twist",
             "vmc_twist_average", "vmc_traj_save", "vmc_traj_load", "vmc_traj_load_rescaled", "vmc_traj_walkers_reset",
             "vmc_set_hbm_budget", "vmc_hbm_in_use", "vmc_traj_bytes", "vmc_cancel", "vmc_traj_set_R", "vmc_traj_get_R",
-            "vmc_traj_step_count", "vmc_traj_langevin_step", "vmc_langevin_step_noalloc", "vmc_huckel_params_theta"]
+            "vmc_traj_step_count", "vmc_traj_langevin_step", "vmc_langevin_step_noalloc", "vmc_huckel_params_theta",
+            "vmc_huckel_params_contracted"]
 VMC_REQ_QUEUED, VMC_REQ_RUNNING, VMC_REQ_DONE, VMC_REQ_FAILED, VMC_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
@@ -42,7 +43,8 @@ class vmc_system(C.Structure):
     _fields_ = [("n_protons", C.c_int), ("box_L", C.c_double), ("ewald_kappa", C.c_double),
                 ("ewald_nmax", C.c_int), ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
                 ("precision", C.c_int), ("refine_tol", C.c_double), ("j1_b1", C.c_double), ("twist", C.c_int),
-                ("general_twist", C.c_int), ("theta", C.c_double * 3)]
+                ("general_twist", C.c_int), ("theta", C.c_double * 3), ("contracted", C.c_int),
+                ("eta", C.c_double)]
 
 
 class vmc_request(C.Structure):
@@ -96,6 +98,7 @@ def _declare(l):
     l.vmc_huckel_params.argtypes = [i, d, P(d), P(d), P(d)]
     l.vmc_huckel_params_twist.argtypes = [i, d, i, P(d), P(d), P(d)]
     l.vmc_huckel_params_theta.argtypes = [i, d, P(d), P(d), P(d), P(d)]
+    l.vmc_huckel_params_contracted.argtypes = [i, d, d, P(d), P(d)]
     l.vmc_twist_average.argtypes = [vp, i, i, vp, vp, vp, vp]
     l.vmc_traj_save.argtypes = [vp, vp, P(C.c_size_t)]
     l.vmc_traj_walkers_reset.argtypes = [vp, P(i)]
@@ -140,13 +143,14 @@ def _dev(t, n=None):
 
 
 def make_system(n, L, kappa=None, nmax=9, a_par=0.25, a_anti=0.5, b=1.0, precision=VMC_FP64, refine_tol=0.0,
-                b1=0.0, twist=0, theta=None):
+                b1=0.0, twist=0, theta=None, eta=None):
     """b1 > 0 adds the one-body electron-proton Jastrow term with that b_1 (0: none); twist:
     bit m = twist angle pi along axis m; theta (3 angles, radians): a general twist with complex
-    orbitals (FP64 only)."""
+    orbitals (FP64 only); eta: the contracted orbital phi_1 + eta phi_2 per proton."""
     th = (C.c_double * 3)(*([0.0] * 3 if theta is None else [float(v) for v in theta]))
     return vmc_system(int(n), float(L), float(8.0 / L if kappa is None else kappa), int(nmax), a_par, a_anti, b,
-                      int(precision), float(refine_tol), float(b1), int(twist), int(theta is not None), th)
+                      int(precision), float(refine_tol), float(b1), int(twist), int(theta is not None), th,
+                      int(eta is not None), float(eta or 0.0))
 
 
 def _c_doubles(system):
@@ -404,6 +408,18 @@ def vmc_huckel_params(R, zeta, L, twist=0):
     else:
         _check(_lib().vmc_huckel_params_twist(n, float(L), int(twist), R.ctypes.data_as(P), zeta.ctypes.data_as(P),
                                               Cm.ctypes.data_as(P)), "vmc_huckel_params_twist")
+    return Cm
+
+
+def vmc_huckel_params_contracted(R, L, eta):
+    """Host helper: real N x N/2 orbital coefficients on the contracted basis (numpy)."""
+    import numpy as np
+    R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
+    n = R.size // 3
+    Cm = np.zeros((n, n // 2))
+    P = C.POINTER(C.c_double)
+    _check(_lib().vmc_huckel_params_contracted(n, float(L), float(eta), R.ctypes.data_as(P), Cm.ctypes.data_as(P)),
+           "vmc_huckel_params_contracted")
     return Cm
 
 

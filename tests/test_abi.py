@@ -74,3 +74,16 @@ def test_host_huckel_theta_rejects_bad_input():
     z[3] = 0.0
     with pytest.raises(vmc.VMCError):
         vmc.vmc_huckel_params_theta(wl.R, z, wl.L, (0.1, 0.2, 0.3))
+
+
+@pytest.mark.parametrize("n,rs,eta", [(16, 1.9, 0.1), (54, 1.32, -0.15), (128, 1.34, 0.35)])
+def test_host_huckel_contracted_spans_oracle_occupied_space(oracle, n, rs, eta):
+    """The library's contracted-basis Hueckel orbitals (overlaps through exponent derivatives of
+    the Gaussian overlap) span the oracle's (overlaps through one-dimensional moments)."""
+    from paper_1605_08423_amd import vmc
+    from paper_1605_08423_amd.inputs import small_system
+    wl = small_system(n, rs, seed=6)
+    Cg = vmc.vmc_huckel_params_contracted(wl.R, wl.L, eta)
+    Co, ev = oracle.huckel_contracted(wl.R, wl.L, n // 2, eta)
+    assert ev[n // 2] - ev[n // 2 - 1] > 1e-4
+    np.testing.assert_allclose(Cg @ Cg.T, Co @ Co.T, atol=1e-12)
