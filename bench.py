@@ -32,12 +32,14 @@ def _add(d: dict, unit: str, flops: float) -> dict:
 
 
 def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, one_body: bool = False,
-               acc: float = 0.57) -> dict:
+               acc: float = 0.57, contracted: bool = False) -> dict:
     """Algorithmic work of the method in one walker's share of a launch, by the unit it runs on:
     {unit: flops} (FMA = 2 flops; exp, erfc, sqrt, rcp, sincos count 1).  img: Gaussian images
     evaluated per axis (3, or 1 when the dropped ones are below FP32 resolution); acc: the
     acceptance rate (a rejected move costs no inverse update); one_body: the electron-proton
-    Jastrow term.  In mixed precision the basis, Jastrow and Ewald real-space terms are FP32."""
+    Jastrow term; contracted: the orbital phi_1 + eta phi_2 (two exps per image and axis and four
+    products of Cartesian factors instead of one).  In mixed precision the basis, Jastrow and Ewald
+    real-space terms are FP32."""
     NS = N // 2
     img = 3 if nimg else 1
     lo = "f32" if mixed else "f64"
@@ -45,6 +47,9 @@ def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, on
         gemm = 2 * N * NS * NS                                   # one of B = C A^-1, M = X B, W = B M, one spin
         pair1 = 3 * (3 + 9 * img) + 29 + 8 + 32                  # Gaussian with 3 derivatives, products, X, sums
         pair2 = 3 * (3 + 5 * img) + 12                           # Gaussian gradient, W term
+        if contracted:
+            pair1 = 3 * (3 + 27 * img) + 4 * 45 + 8 + 32         # g1, g2, h2 with 3 derivatives; four products
+            pair2 = 3 * (3 + 13 * img) + 4 * 6 + 6
         valu = N * N * (pair1 + pair2) + N * (N - 1) * 45        # both spins' (electron, centre) pairs; Jastrow
         if one_body:
             # per (electron, proton) pair: its Jastrow gradient and Laplacian (30), grad ln|D| from
@@ -58,7 +63,7 @@ def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, on
         # exp per image; the product), its Jastrow change (old and new pair terms, 15 flops each),
         # the MO row m = phi C (2 N NS), the ratio q = m . (A^-1 column) (2 NS) and, if accepted,
         # the Sherman-Morrison update (m^T A^-1 and the rank-1 update, 4 NS^2)
-        basis = N * (3 * (3 + 2 * img) + 2)
+        basis = N * (3 * (3 + 2 * img) + 2) if not contracted else N * (3 * (3 + 8 * img) + 14)
         jas = 30 * (N - 1) + (30 * N if one_body else 0)
         w = {"f64": NS * (2 * N * NS + 2 * NS + acc * 4 * NS * NS)}
         return _add(w, lo, NS * (basis + jas))
@@ -89,7 +94,7 @@ CREFRESH = 4
 
 
 def executed_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, one_body: bool = False,
-                   acc: float = 0.57) -> dict:
+                   acc: float = 0.57, contracted: bool = False) -> dict:
     """The arithmetic a launch executes, where it differs from the method's count: the sweep applies
     its Sherman-Morrison updates in blocks of 16 moves on the matrix cores, forming the full rows
     P = M' A^-1 of every proposal and a rank-16 update whatever the acceptance (2 NS N NS + 4 NS^3
@@ -100,11 +105,12 @@ def executed_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool
         w = work_model(cls, N, nk, nslot, nimg, mixed, one_body, acc)
         return {"f64": w["f64"] + NS * (1 - acc) * 8 * NS * NS}
     if cls != "sweep_half":
-        return work_model(cls, N, nk, nslot, nimg, mixed, one_body, acc)
+        return work_model(cls, N, nk, nslot, nimg, mixed, one_body, acc, contracted)
     NS = N // 2
     img = 3 if nimg else 1
     lo = "f32" if mixed else "f64"
-    per_move = N * (3 * (3 + 2 * img) + 2) + 30 * (N - 1) + (30 * N if one_body else 0)
+    basis = N * (3 * (3 + 2 * img) + 2) if not contracted else N * (3 * (3 + 8 * img) + 14)
+    per_move = basis + 30 * (N - 1) + (30 * N if one_body else 0)
     w = {"f64": 2 * NS * N * NS + 4 * NS ** 3 + NS * 16 * NS}    # matrix cores; the recursion t -= t[i] z
     return _add(w, lo, NS * per_move)
 
@@ -224,10 +230,6 @@ def run_toy(args):
     ms, nl = times["toy"]
     avg_s = ms / max(nl, 1) / 1e3
     achieved = TOY_FLOP_PER_STEP * n * steps / avg_s / 1e12
-    mesh = None
-    if args.mesh_leg > 0 and args.workload == "h128":
-        mesh = twist_mesh_leg("h128", args.mesh_leg, args.mesh_walkers, 10, 1, 1)
-
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -580,14 +582,14 @@ def kernel_space(sysd, wl, prec_mixed: bool):
     return nk, nslot, nimg
 
 
-def run_leg(wl, W: int, M: int, prec: int, b1: float, steps: int, warmup: int, log=None) -> dict:
+def run_leg(wl, W: int, M: int, prec: int, b1: float, steps: int, warmup: int, log=None, eta=None) -> dict:
     """Langevin steps of one trajectory, each one full pass of the hot path: Hueckel orbitals and
     proton tables at R, the energy/force estimate (20 equilibration sweeps at the first step, 5
     after), S and the update on the trajectory's own state.  Times `steps` steps after `warmup`."""
     import torch
     from paper_1605_08423_amd import vmc
     ctx = vmc.Context(0)
-    sysd = vmc.make_system(wl.n, wl.L, precision=prec, b1=b1)
+    sysd = vmc.make_system(wl.n, wl.L, precision=prec, b1=b1, eta=eta)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     traj = vmc.Trajectory(ctx, sysd, W, seed=wl.seed, traj_id=0)
     traj.set_walkers(dev(wl.electrons(W=W)))
@@ -597,7 +599,9 @@ def run_leg(wl, W: int, M: int, prec: int, b1: float, steps: int, warmup: int, l
     Delta = 1.0 / alpha               # alpha Delta = 1
 
     def one_step(k):
-        Cm = vmc.vmc_huckel_params(traj.get_R().cpu().numpy(), wl.zeta, wl.L)
+        Rh = traj.get_R().cpu().numpy()
+        Cm = (vmc.vmc_huckel_params(Rh, wl.zeta, wl.L) if eta is None
+              else vmc.vmc_huckel_params_contracted(Rh, wl.L, eta))
         out = traj.energy_forces(None, dev(Cm), zeta, 20 if k == 0 else 5, M, wl.delta, step=None)
         S = traj.build_S() if log is not None else traj.build_S(keep_only=True)
         rc = traj.langevin_step(wl.T_hartree, Delta, alpha)
@@ -652,6 +656,11 @@ def main():
                     help="write one JSON line per timed Langevin step: E, sigma_E, |f|, acceptance, cond(S), time")
     ap.add_argument("--j1", type=float, default=0.0, metavar="B1",
                     help="add the one-body electron-proton Jastrow term with this b_1 (0: none)")
+    ap.add_argument("--eta", type=float, default=None,
+                    help="the contracted orbital phi_1 + eta phi_2 per proton (the SI's Z1, Z2) instead of one "
+                         "s-Gaussian")
+    ap.add_argument("--contracted-leg", type=float, default=0.1, metavar="ETA",
+                    help="eta of the short contracted-basis leg of the default line (nan: skip)")
     ap.add_argument("--fp64-steps", type=int, default=2,
                     help="timed steps of the plain FP64 leg beside a mixed-precision headline (0: skip)")
     ap.add_argument("--serve-leg", type=int, default=12, metavar="K",
@@ -721,7 +730,7 @@ def main():
     mixed = args.precision == "mixed"
     prec = vmc.VMC_MIXED if mixed else vmc.VMC_FP64
     log = open(args.log, "w") if args.log else None
-    lead = run_leg(wl, W, M, prec, args.j1, args.steps, args.warmup, log)
+    lead = run_leg(wl, W, M, prec, args.j1, args.steps, args.warmup, log, args.eta)
     times, out_h, sysd = lead["times"], lead["out"], lead["sysd"]
     nk, nslot, nimg = kernel_space(sysd, wl, mixed)
     acc = float(out_h[2])
@@ -729,8 +738,8 @@ def main():
 
     def kernel_roofline(name):
         ms, n = times[name]
-        parts = work_model(name, N, nk, nslot, nimg, mixed, args.j1 > 0, acc)
-        executed = executed_model(name, N, nk, nslot, nimg, mixed, args.j1 > 0, acc)
+        parts = work_model(name, N, nk, nslot, nimg, mixed, args.j1 > 0, acc, args.eta is not None)
+        executed = executed_model(name, N, nk, nslot, nimg, mixed, args.j1 > 0, acc, args.eta is not None)
         avg_s = ms / max(n, 1) / 1e3
         flops, achieved, peak = roofline_numbers(parts, W, avg_s)
         return {"bound": "alu", "kernel": name, "achieved": round(achieved, 3), "peak": round(peak, 2),
@@ -767,6 +776,25 @@ def main():
     if args.serve_leg > 0 and args.workload == "h128":
         served = serve_stream(args.serve_leg, 2, 10, args.serve_rate, args.serve_budget_gb)
 
+    contracted = None
+    if args.eta is None and args.contracted_leg == args.contracted_leg and args.workload == "h128":
+        # the same workload on the contracted basis, a few steps
+        r = run_leg(wl, W, M, prec, args.j1, 2, 1, None, args.contracted_leg)
+        kms = {k: v for k, v in r["times"].items() if v[1]}
+        dom = max(kms.items(), key=lambda kv: kv[1][0])
+        avg_s = dom[1][0] / dom[1][1] / 1e3
+        nk_c, nslot_c, _ = kernel_space(r["sysd"], wl, mixed)
+        parts = work_model(dom[0], N, nk_c, nslot_c, 1, mixed, args.j1 > 0, float(r["out"][2]), True)
+        flops, achieved, peak = roofline_numbers(parts, W, avg_s)
+        contracted = {"eta": args.contracted_leg, "value": round(r["value"], 1), "unit": "walker-sweeps/s",
+                      "steps": r["steps"], "warmup": 1, "ms_per_step": round(1e3 * r["elapsed"] / r["steps"], 2),
+                      "over_single_gaussian": round(r["value"] / lead["value"], 3), "E_Ha": float(r["out"][0]),
+                      "acceptance": round(float(r["out"][2]), 4), "dominant_kernel": dom[0],
+                      "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
+                                   "unit": "TFLOP/s", "frac": round(achieved / peak, 4) if peak else None,
+                                   "avg_launch_ms": round(avg_s * 1e3, 4)},
+                      "kernel_ms": {k: round(v[0], 2) for k, v in kms.items()}}
+
     mesh = None
     if args.mesh_leg > 0 and args.workload == "h128":
         mesh = twist_mesh_leg("h128", args.mesh_leg, args.mesh_walkers, 10, 1, 1)
@@ -796,12 +824,14 @@ def main():
         "dtype": "f32/f64" if mixed else "f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {N} H + {N} e-, r_s={wl.rs}, T={wl.T_kelvin:g} K, {W} walkers x {M} "
                                f"measured (+5 re-equilibration) sweeps per Langevin step, {args.precision} precision"
-                               + (f", one-body Jastrow b_1={args.j1:g}" if args.j1 > 0 else ""),
+                               + (f", one-body Jastrow b_1={args.j1:g}" if args.j1 > 0 else "")
+                               + (f", contracted basis eta={args.eta:g}" if args.eta is not None else ""),
                    "N": N, "walkers": W, "sweeps": M, "precision": args.precision, "one_body_b1": args.j1},
         "langevin_steps_per_s": round(args.steps / lead["elapsed"], 4),
         "step_latency_ms": {"p50": round(lead["p50"], 1), "p99": round(lead["p99"], 1)},
         "E_Ha": float(out_h[0]), "sigma_E_Ha": float(out_h[1]), "acceptance": acc,
-        "roofline": roofline, "fp64_gpu": fp64, "served": served, "twist_mesh": mesh, "cpu_baseline": cpu,
+        "roofline": roofline, "fp64_gpu": fp64, "served": served, "twist_mesh": mesh,
+        "contracted_basis": contracted, "cpu_baseline": cpu,
         "kernel_ms": {k: round(v[0], 2) for k, v in times.items()},
     }
     print(json.dumps(line))
