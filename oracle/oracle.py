@@ -34,10 +34,11 @@ class OSys(C.Structure):
                 ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
                 ("R", C.POINTER(C.c_double)), ("zeta", C.POINTER(C.c_double)),
                 ("C", C.POINTER(C.c_double)), ("b1", C.c_double), ("twist", C.c_int),
-                ("contracted", C.c_int), ("eta", C.c_double)]
+                ("contracted", C.c_int), ("eta", C.c_double), ("j3f", C.c_double * 3)]
 
 
 Z1, Z2 = 0.6066825, 0.3382168   # the SI's exponents of the contracted minimal basis
+ZJ = 0.7933844                  # the exponent of the Jastrow orbitals
 
 
 _lib = None
@@ -90,6 +91,8 @@ def _setup(l):
     l.o_coverlap.restype = None
     l.o_chuckel.argtypes = [i, d, P(d), P(d), P(d), i, P(d), P(d)]
     l.o_clocal.argtypes = [P(OSys), P(d), P(d), P(d), P(d), P(d), P(d), P(d), P(d)]
+    l.o_j3_orbitals.argtypes = [P(OSys), i, P(d), P(d)]
+    l.o_j3_orbitals.restype = None
     l.o_huckel_contracted.argtypes = [i, d, P(d), d, i, P(d), P(d)]
     l.o_overlap_contracted.argtypes = [i, d, P(d), d, P(d)]
     l.o_overlap_contracted.restype = None
@@ -101,7 +104,7 @@ class System:
 
     def __init__(self, R, zeta, C_mo, L=0.0, n_up=None, n_dn=None, basis=OB_PERIODIC_GAUSS,
                  pot=OP_EWALD, kappa=None, nmax=9, jastrow=True, a_par=0.25, a_anti=0.5, b=1.0,
-                 b1=0.0, twist=0, eta=None):
+                 b1=0.0, twist=0, eta=None, j3=None):
         self.R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1, 3)
         n_p = self.R.shape[0]
         self.zeta = np.ascontiguousarray(zeta, dtype=np.float64).reshape(n_p)
@@ -116,7 +119,8 @@ class System:
         # eta given: the contracted orbital phi_1 + eta phi_2 (zeta unused)
         self.s = OSys(n_p, n_up, n_dn, self.C.shape[1], float(L), basis, pot, float(kappa), int(nmax),
                       int(bool(jastrow)), a_par, a_anti, b, _dp(self.R), _dp(self.zeta), _dp(self.C),
-                      float(b1), int(twist), int(eta is not None), float(eta or 0.0))
+                      float(b1), int(twist), int(eta is not None), float(eta or 0.0),
+                      (C.c_double * 3)(*(j3 if j3 is not None else (0.0, 0.0, 0.0))))
 
     @property
     def n_p(self):
@@ -131,6 +135,12 @@ class System:
         r = np.ascontiguousarray(r, dtype=np.float64)
         lib().o_basis(C.byref(self.s), a, _dp(r), _dp(out))
         return out
+
+    def j3_orbitals(self, a, r):
+        out = np.zeros(28)
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        lib().o_j3_orbitals(C.byref(self.s), a, _dp(r), _dp(out))
+        return out[:14], out[14:]
 
     def jastrow(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)

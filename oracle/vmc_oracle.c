@@ -386,7 +386,60 @@ static void radial_field(const osys* s, const double d[3], const double F[4], do
   }
 }
 
-/* U = sum_{i<j} u(rho_ij) + U_1; gradU (Ne x 3) and lapU (Ne) are w.r.t. each electron. */
+/* ------------------------------------------------------ three-body term -- */
+static int j3_on(const osys* s) { return s->j3f[0] != 0.0 || s->j3f[1] != 0.0 || s->j3f[2] != 0.0; }
+
+/* One Cartesian factor of the Jastrow orbitals at the offset d along an axis: with the periodised
+ * component rho = (L/pi) sin(pi d / L) (rho = d in the open kinds), u = rho^2 and
+ * a = e^{-ZJ u}, b = u a, the derivatives in d to third order by the chain rule:
+ *   u' = 2 rho c, u'' = 2 (c^2 - k rho^2), u''' = -8 k rho c   (c = cos(pi d / L), k = (pi/L)^2),
+ *   a' = -Z u' a, a'' = (Z^2 u'^2 - Z u'') a, a''' = (-Z^3 u'^3 + 3 Z^2 u' u'' - Z u''') a,
+ *   b' = u' a + u a', b'' = u'' a + 2 u' a' + u a'', b''' = u''' a + 3 u'' a' + 3 u' a'' + u a'''. */
+static void j3_axis(const osys* s, double d, double a[4], double b[4]) {
+  double rho, c, k;
+  if (s->basis_kind == OB_PERIODIC_GAUSS) {
+    rho = s->L / PI * sin(PI * d / s->L);
+    c = cos(PI * d / s->L);
+    k = (PI / s->L) * (PI / s->L);
+  } else {
+    rho = d; c = 1.0; k = 0.0;
+  }
+  const double Z = O_ZJ;
+  const double u = rho * rho, u1 = 2.0 * rho * c, u2 = 2.0 * (c * c - k * rho * rho), u3 = -8.0 * k * rho * c;
+  const double e = exp(-Z * u);
+  a[0] = e;
+  a[1] = -Z * u1 * e;
+  a[2] = (Z * Z * u1 * u1 - Z * u2) * e;
+  a[3] = (-Z * Z * Z * u1 * u1 * u1 + 3.0 * Z * Z * u1 * u2 - Z * u3) * e;
+  b[0] = u * a[0];
+  b[1] = u1 * a[0] + u * a[1];
+  b[2] = u2 * a[0] + 2.0 * u1 * a[1] + u * a[2];
+  b[3] = u3 * a[0] + 3.0 * u2 * a[1] + 3.0 * u1 * a[2] + u * a[3];
+}
+
+/* chi_1 = a a a and chi_2 = rho^2 e^{-Z rho^2} = b a a + a b a + a a b, each as 14 components. */
+void o_j3_orbitals(const osys* s, int atom, const double r[3], double out[28]) {
+  double A[3][4], B[3][4];
+  for (int m = 0; m < 3; ++m) j3_axis(s, r[m] - s->R[3 * atom + m], A[m], B[m]);
+  for (int q = 0; q < 28; ++q) out[q] = 0.0;
+  add_product(A, 1.0, out);
+  for (int m = 0; m < 3; ++m) {
+    double f[3][4];
+    for (int mm = 0; mm < 3; ++mm)
+      for (int q = 0; q < 4; ++q) f[mm][q] = (mm == m) ? B[mm][q] : A[mm][q];
+    add_product(f, 1.0, out + 14);
+  }
+}
+
+/* chi_a(r)^T F chi'  for 14-component orbital blocks: component q of the first pair with the
+ * value of the second (F symmetric: f11, f12, f22). */
+static double j3_form(const osys* s, const double* ci, int q, const double* cj, int qj) {
+  const double* f = s->j3f;
+  return f[0] * ci[q] * cj[qj] + f[1] * (ci[q] * cj[14 + qj] + ci[14 + q] * cj[qj]) + f[2] * ci[14 + q] * cj[14 + qj];
+}
+
+/* U = sum_{i<j} u(rho_ij) + U_1 + U_3; gradU (Ne x 3) and lapU (Ne) are w.r.t. each electron.
+ * U_3 = sum_a sum_{i<j} chi_a(r_i)^T F chi_a(r_j) (SI, Eq. e:j33, on-site), summed pair by pair. */
 void o_jastrow(const osys* s, const double* x, double* U, double* gradU, double* lapU) {
   int ne = s->n_up + s->n_dn;
   double Ut = 0.0;
@@ -404,6 +457,25 @@ void o_jastrow(const osys* s, const double* x, double* U, double* gradU, double*
           for (int m = 0; m < 3; ++m) gradU[3 * i + m] += g[m];
         if (lapU) lapU[i] += lp;
       }
+  if (j3_on(s)) {
+    const int np = s->n_p;
+    double* ch = malloc(sizeof(double) * 28 * (size_t)ne * np);
+    for (int i = 0; i < ne; ++i)
+      for (int a = 0; a < np; ++a) o_j3_orbitals(s, a, x + 3 * i, ch + 28 * ((size_t)i * np + a));
+    for (int a = 0; a < np; ++a)
+      for (int i = 0; i < ne; ++i) {
+        const double* ci = ch + 28 * ((size_t)i * np + a);
+        for (int j = 0; j < ne; ++j) {
+          if (j == i) continue;
+          const double* cj = ch + 28 * ((size_t)j * np + a);
+          if (j > i) Ut += j3_form(s, ci, 0, cj, 0);
+          if (gradU)
+            for (int m = 0; m < 3; ++m) gradU[3 * i + m] += j3_form(s, ci, 1 + m, cj, 0);
+          if (lapU) lapU[i] += j3_form(s, ci, 4, cj, 0);
+        }
+      }
+    free(ch);
+  }
   if (!s->jastrow_on) { *U = Ut; return; }
   for (int i = 0; i < ne; ++i)
     for (int j = i + 1; j < ne; ++j) {
@@ -617,6 +689,40 @@ int o_local(const osys* s, const double* x, double* lnpsi, double* sign, double*
           dT[3 * a + mu] += 0.5 * gl[mu] + hv;
         }
       }
+  /* The three-body term depends on R_a through chi_a(r_i - R_a), d/dR_a = -grad_i on it: with
+   * v_k = grad_k U + grad_k ln|D| and the sums over the other electrons j != k,
+   *   d ln psi/dR_a,mu = -sum_k sum_j (d_mu chi_ak)^T F chi_aj,
+   *   d(grad_k U)_nu/dR_a,mu = -sum_j [(d_mu d_nu chi_ak)^T F chi_aj + (d_nu chi_ak)^T F d_mu chi_aj],
+   *   d(lap_k U)/dR_a,mu = -sum_j [(d_mu lap chi_ak)^T F chi_aj + (lap chi_ak)^T F d_mu chi_aj],
+   * and the kinetic part changes by -1/2 sum_k d(lap_k U) - sum_k v_k . d(grad_k U). */
+  if (rc == 0 && want && j3_on(s)) {
+    double* ch = malloc(sizeof(double) * 28 * (size_t)ne * np);
+    for (int i = 0; i < ne; ++i)
+      for (int a = 0; a < np; ++a) o_j3_orbitals(s, a, x + 3 * i, ch + 28 * ((size_t)i * np + a));
+    for (int a = 0; a < np; ++a)
+      for (int mu = 0; mu < 3; ++mu) {
+        double dl = 0.0, dt = 0.0;
+        for (int k = 0; k < ne; ++k) {
+          const double* ck = ch + 28 * ((size_t)k * np + a);
+          double v[3];
+          for (int m = 0; m < 3; ++m) v[m] = gU[3 * k + m] + gDe[3 * k + m];
+          for (int j = 0; j < ne; ++j) {
+            if (j == k) continue;
+            const double* cj = ch + 28 * ((size_t)j * np + a);
+            dl -= j3_form(s, ck, 1 + mu, cj, 0);
+            const double dlap = -(j3_form(s, ck, 11 + mu, cj, 0) + j3_form(s, ck, 4, cj, 1 + mu));
+            dt += -0.5 * dlap;
+            for (int nu = 0; nu < 3; ++nu) {
+              const double dg = -(j3_form(s, ck, hidx(mu, nu), cj, 0) + j3_form(s, ck, 1 + nu, cj, 1 + mu));
+              dt -= v[nu] * dg;
+            }
+          }
+        }
+        dln[3 * a + mu] += dl;
+        dT[3 * a + mu] += dt;
+      }
+    free(ch);
+  }
   if (rc == 0) {
     if (lnpsi) *lnpsi = lnp;
     if (sign) *sign = sg;
@@ -892,6 +998,19 @@ int o_vmc_run_from(const osys* s, int W, uint32_t w0, double* x, int n_equil, in
             j1_radial(s->b1, periodised_rho(s, dn), F1);
             j1_radial(s->b1, periodised_rho(s, dold), F0);
             dU += F1[0] - F0[0];
+          }
+        if (j3_on(s))
+          /* the three-body change: sum over nuclei and the other electrons of
+           * (chi(r' - R_a) - chi(r_e - R_a))^T F chi(r_j - R_a) */
+          for (int a = 0; a < s->n_p; ++a) {
+            double cn[28], co[28], cj[28];
+            o_j3_orbitals(s, a, rn, cn);
+            o_j3_orbitals(s, a, xw + 3 * e, co);
+            for (int j = 0; j < ne; ++j) {
+              if (j == e) continue;
+              o_j3_orbitals(s, a, xw + 3 * j, cj);
+              dU += j3_form(s, cn, 0, cj, 0) - j3_form(s, co, 0, cj, 0);
+            }
           }
         double p = q * q * exp(2.0 * dU);
         if (uacc < p) {

@@ -41,11 +41,22 @@ typedef struct {
                           phi_1 = e^{-Z1 r^2}, phi_2 = r^2 e^{-Z2 r^2} (O_Z1, O_Z2; zeta unused),
                           with the same image sums and twists as the single Gaussian; 0: e^{-zeta r^2} */
   double eta;          /* the contraction coefficient eta (contracted = 1) */
+  double j3f[3];       /* the on-site three-body (electron-electron-nucleus) Jastrow term U_3 of the SI
+                          (Eq. e:j33): f_11, f_12 = f_21, f_22 of the 2 x 2 matrix coupling the
+                          orbitals chi_1 = e^{-ZJ rho^2}, chi_2 = rho^2 e^{-ZJ rho^2} (O_ZJ) of two
+                          electrons on the same nucleus, the same for every nucleus; all zero = no term */
 } osys;
+
+/* The exponent of the Jastrow orbitals (SI, Jastrow section). */
+#define O_ZJ 0.7933844
 
 /* The SI's exponents of the contracted minimal basis (section "Systematic setup"). */
 #define O_Z1 0.6066825
 #define O_Z2 0.3382168
+
+/* The three-body term's orbitals chi_1, chi_2 of nucleus `atom` at r: out[0..13] and out[14..27]
+ * are the 14 components [value, grad(3), lap, hess xx yy zz xy xz yz, grad lap(3)] of each. */
+void o_j3_orbitals(const osys* s, int atom, const double r[3], double out[28]);
 
 /* Philox4x32-10 counter-based generator (Salmon et al., SC'11). */
 void o_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

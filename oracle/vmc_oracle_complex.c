@@ -255,7 +255,7 @@ static void cmatmul(int n, const cplx* A, const cplx* B, cplx* C) {
  * The one-body Jastrow term is not part of this wavefunction (s->b1 must be 0). */
 int o_clocal(const osys* s, const double theta[3], const double* Cd, const double* x, double* lnpsi, double* phase,
              double* EL, double* dlnpsi_dR, double* dEL_dR) {
-  if (s->b1 > 0.0 || s->contracted || s->basis_kind != OB_PERIODIC_GAUSS) return O_EINVAL;
+  if (s->b1 > 0.0 || s->contracted || s->j3f[0] != 0.0 || s->j3f[1] != 0.0 || s->j3f[2] != 0.0 || s->basis_kind != OB_PERIODIC_GAUSS) return O_EINVAL;
   const int np = s->n_p, ne = s->n_up + s->n_dn, no = s->n_orb, n3 = 3 * np;
   double U;
   double* gU = malloc(sizeof(double) * 3 * ne);
@@ -371,7 +371,7 @@ static void cmo_row(const osys* s, const double theta[3], const double* Cd, cons
 int o_cvmc_run_from(const osys* s, const double theta[3], const double* Cd, int W, uint32_t w0, double* x,
                     int n_equil, int n_meas, double delta, uint32_t seed, uint32_t traj, uint32_t step, double* sums,
                     int64_t* n_acc, int n_threads) {
-  if (s->b1 > 0.0 || s->contracted) return O_EINVAL;
+  if (s->b1 > 0.0 || s->contracted || s->j3f[0] != 0.0 || s->j3f[1] != 0.0 || s->j3f[2] != 0.0) return O_EINVAL;
   const int ne = s->n_up + s->n_dn, n3 = 3 * s->n_p, nsum = 2 + 3 * n3;
   int err = 0;
 #ifdef _OPENMP
