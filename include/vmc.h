@@ -108,6 +108,15 @@ typedef struct {
                          FP64 resolution); not for the server.  Else VMC_EINVAL.
                          0: one s-Gaussian e^{-zeta_a r^2} per proton */
   double eta;         /* the contraction coefficient (contracted = 1; finite) */
+  double j3_f[3];     /* the on-site three-body (electron-electron-nucleus) Jastrow term U_3 of the SI
+                         (Jastrow section, Eq. e:j33): U_3 = sum_a sum_{i<j} chi_a(r_i)^T F chi_a(r_j)
+                         with chi_1 = e^{-ZJ rho^2}, chi_2 = rho^2 e^{-ZJ rho^2}, ZJ = 0.7933844, on
+                         the sin-periodised offset rho between electron and nucleus, and
+                         F = [[f11, f12], [f12, f22]] = [[j3_f[0], j3_f[1]], [j3_f[1], j3_f[2]]] the same
+                         for every nucleus.  All zero: no term.  The term requires twist = 0,
+                         general_twist = 0, contracted = 0 and N_sigma <= 64, and is not for the
+                         server (else VMC_EINVAL); its measurement terms are FP64 in both modes, its
+                         sweep terms in the Jastrow precision */
 } vmc_system;
 
 /* ---------------------------------------------------------------- context -- */

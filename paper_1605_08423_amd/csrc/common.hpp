@@ -293,6 +293,23 @@ __device__ __forceinline__ BasisD<Real> contracted_derivs(double dx, double dy, 
   return o;
 }
 
+// The on-site three-body Jastrow term's orbitals (SI, Jastrow section): chi_1 = e^{-ZJ rho^2} and
+// chi_2 = rho^2 e^{-ZJ rho^2} of the sin-periodised offset rho_m = (L/pi) sin(pi d_m / L) between an
+// electron and a nucleus; their values from the sines and cosines of pi x / L of both.
+constexpr double kZJ = 0.7933844;
+template <class Real>
+__device__ __forceinline__ void j3_values(const Real se[3], const Real ce[3], const Real sa[3], const Real ca[3],
+                                          Real LoverPi, Real& v1, Real& v2) {
+  Real u = Real(0);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const Real rt = LoverPi * (se[m] * ca[m] - ce[m] * sa[m]);
+    u += rt * rt;
+  }
+  v1 = dev_exp<Real>(-(Real)kZJ * u);
+  v2 = u * v1;
+}
+
 // Orders this wave's LDS writes before its later LDS reads (the wave's LDS
 // operations complete in order; the clobber keeps the compiler from moving them).
 __device__ __forceinline__ void lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }

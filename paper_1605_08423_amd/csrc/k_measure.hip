@@ -491,11 +491,18 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
       q[0] = (double)g0; q[1] = (double)g1; q[2] = (double)g2; q[3] = (double)lp; q[4] = (double)ui + f1sum;
     }
     __syncthreads();
+    // the three-body term's gradient, Laplacian and value, from the pass before this kernel
+    const double* j3in = m.j3 ? m.j3scr + (size_t)walker() * j3_measure_doubles(N) : nullptr;
     for (int i = t; i < N; i += 256) {
       double g0 = 0, g1 = 0, g2 = 0, lp = 0, ui = 0;
       for (int hj = 0; hj < HJ; ++hj) {
         const double* q = jp + ((size_t)hj * N + i) * 5;
         g0 += q[0]; g1 += q[1]; g2 += q[2]; lp += q[3]; ui += q[4];
+      }
+      if (j3in) {
+        g0 += j3in[3 * i]; g1 += j3in[3 * i + 1]; g2 += j3in[3 * i + 2];
+        lp += j3in[3 * N + i];
+        if (i == 0) ui += j3in[4 * N];
       }
       gU[3 * i] = g0; gU[3 * i + 1] = g1; gU[3 * i + 2] = g2;
       lU[i] = lp;
@@ -582,7 +589,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
     }
     }
     __syncthreads();
-    if (one_body) {
+    if (one_body || m.j3) {
       // grad_i ln|D| = sum_a grad phi_a(r_i) B_ai for the electrons of this spin, in HG
       // shares of the centres, combined in a fixed order
       constexpr int HG = 256 / NS;
@@ -851,6 +858,15 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
     acc[0] += EL;
     acc[1] += EL * EL;
     m.Uj[w] = Us;
+  }
+  if (m.j3) {
+    // for the three-body term's d/dR pass: grad U, grad ln|D| and E_L of this sample
+    double* out = m.j3scr + (size_t)w * j3_measure_doubles(N) + 4 * N + 1;
+    for (int u = t; u < 3 * N; u += 256) {
+      out[u] = gU[u];
+      out[3 * N + u] = (double)gD[u];
+    }
+    if (t == 0) out[6 * N] = EL;
   }
 }
 

@@ -412,7 +412,7 @@ __device__ __forceinline__ double one_body_change(const Real* Rt, double xo, dou
 // Every LDS row access of the recursion is lane-private (lane = column).
 // One wave per walker; the inverse lives in matrix-core accumulator layout
 // (tile (tr, tc), element v of lane l = A^-1[16 tr + 4 v + l/16][16 tc + l%16]).
-template <int NS, class Real, int NIMG, bool BATCH, bool TW, bool CB = false>
+template <int NS, class Real, int NIMG, bool BATCH, bool TW, bool CB = false, bool J3 = false>
 __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s, Batch bt) {
   constexpr int N = 2 * NS;
   using LY = SweepLds<NS>;
@@ -436,9 +436,9 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
     Rs[4 * t] = a.R[3 * t]; Rs[4 * t + 1] = a.R[3 * t + 1]; Rs[4 * t + 2] = a.R[3 * t + 2];
     Rs[4 * t + 3] = a.zeta[t];
   }
-  Real* Rt = reinterpret_cast<Real*>(Rs + 4 * N);   // one-body term: sin (3 x N), then cos (3 x N)
+  Real* Rt = reinterpret_cast<Real*>(Rs + 4 * N);   // one-body and three-body terms: sin (3 x N), then cos (3 x N)
   const bool one_body = a.j1_beta > 0.0;
-  if (one_body)
+  if (one_body || J3)
     for (int t = threadIdx.x; t < 3 * N; t += blockDim.x)
       dev_sincospi<Real>((Real)(a.R[3 * (t % N) + t / N] * a.invL), &Rt[t], &Rt[3 * N + t]);
   __syncthreads();
@@ -508,6 +508,16 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
   const Real a_same = (Real)a.a_par, a_anti = (Real)a.a_anti, bj = (Real)a.b;
   const double delta = s.delta;
   int nacc = 0;
+  // three-body term: lanes hold G_a = sum_i (chi_1, chi_2)(r_i - R_a) of nuclei lane, lane + 64
+  double Gj[EPL][2];
+  if constexpr (J3) {
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) {
+      const int c = lane + 64 * t;
+      Gj[t][0] = c < N ? a.j3G[((size_t)w * N + c) * 2] : 0.0;
+      Gj[t][1] = c < N ? a.j3G[((size_t)w * N + c) * 2 + 1] : 0.0;
+    }
+  }
 
   for (int b = 0; b < NB; ++b) {
     const int jmax = (NS - 16 * b) < 16 ? (NS - 16 * b) : 16;
@@ -616,6 +626,27 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
                 pade_u<Real>(so, co, ts[tt], tc_[tt], LoverPi, aa, bj);
         }
       }
+      // three-body change over the lane's nuclei: (chi(r') - chi(r))^T F (G_a - chi(r))
+      Real dj[EPL][2];
+      if constexpr (J3) {
+#pragma unroll
+        for (int tt = 0; tt < EPL; ++tt) {
+          const int c = lane + 64 * tt;
+          dj[tt][0] = dj[tt][1] = Real(0);
+          if (c < N) {
+            const Real sa[3] = {Rt[c], Rt[N + c], Rt[2 * N + c]};
+            const Real ca[3] = {Rt[3 * N + c], Rt[4 * N + c], Rt[5 * N + c]};
+            Real n1, n2, o1, o2;
+            j3_values<Real>(sn, cn, sa, ca, LoverPi, n1, n2);
+            j3_values<Real>(so, co, sa, ca, LoverPi, o1, o2);
+            dj[tt][0] = n1 - o1;
+            dj[tt][1] = n2 - o2;
+            const Real g1 = (Real)Gj[tt][0] - o1, g2 = (Real)Gj[tt][1] - o2;
+            du += (Real)a.j3f[0] * dj[tt][0] * g1 + (Real)a.j3f[1] * (dj[tt][0] * g2 + dj[tt][1] * g1) +
+                  (Real)a.j3f[2] * dj[tt][1] * g2;
+          }
+        }
+      }
       // xor-butterfly sum kept in vector registers, in the precision of the pair terms: every
       // lane adds the same two partial sums at every step, so all lanes hold the identical
       // total and the acceptance test below takes the same branch in every lane
@@ -631,6 +662,13 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
 #pragma unroll
         for (int u = 0; u < CPL; ++u) zrow[u] = (t[u] - (lane + 64 * u == i ? 1.0 : 0.0)) * iq;
         amask |= 1u << j;
+        if constexpr (J3) {
+#pragma unroll
+          for (int tt = 0; tt < EPL; ++tt) {
+            Gj[tt][0] += (double)dj[tt][0];
+            Gj[tt][1] += (double)dj[tt][1];
+          }
+        }
         // lanes j, j + 16, j + 32 hold move j's proposal; each writes one coordinate
         if (l16 == j && l4 < 3) pw[3 * e + l4] = (l4 == 0) ? xn : ((l4 == 1) ? yn : zn);
         if (lane == owner) {
@@ -725,6 +763,16 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
         for (int tc = 0; tc < NT; ++tc)
           if ((16 * tr + 4 * v + l4 < NS) && (16 * tc + l16 < NS)) rowp[loff + 16 * tc] = binv[tr][tc][v];
       }
+  }
+  if constexpr (J3) {
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) {
+      const int c = lane + 64 * t;
+      if (c < N) {
+        a.j3G[((size_t)w * N + c) * 2] = Gj[t][0];
+        a.j3G[((size_t)w * N + c) * 2 + 1] = Gj[t][1];
+      }
+    }
   }
   if (lane == 0) a.nacc[w] += nacc;
 }
@@ -1441,6 +1489,24 @@ hipError_t launch_sweep_tw(const WalkerArgs& a, const SweepArgs& s, hipStream_t 
 
 template <int NS, class Real>
 hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t st, const Batch* bt, int nblk) {
+  if (a.j3) {
+    // the three-body term: single trajectories, single Gaussians, no twist, N_sigma <= 64
+    if constexpr (NS > 64) {
+      return hipErrorInvalidValue;
+    } else {
+      if (bt || a.twist || a.contracted || !a.j3G) return hipErrorInvalidValue;
+      const size_t tab = one_body_table_bytes<Real>(2 * NS, SweepLds<NS>::NSP);
+      const size_t sm = sweep_smem<NS, Real>() + tab;
+      dim3 grid((a.W + 3) / 4);
+      if (a.nimg || sizeof(Real) == 8)
+        hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, false, false, false, true>), grid, dim3(256), sm, st, a, s,
+                           batch_or_none(bt));
+      else
+        hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, false, false, false, true>), grid, dim3(256), sm, st, a, s,
+                           batch_or_none(bt));
+      return hipGetLastError();
+    }
+  }
   if (a.contracted) {
     // the contracted orbital: single trajectories without twist, N_sigma <= 64
     if constexpr (NS > 64) {

@@ -27,6 +27,9 @@ struct WalkerArgs {
   size_t rscr_stride;
   int contracted;      // 1: the contracted orbital phi_1 + eta phi_2 per proton (zeta unused)
   double eta;
+  int j3;              // 1: the on-site three-body Jastrow term with the matrix j3f = (f11, f12, f22)
+  double j3f[3];
+  double* j3G;         // W x N x 2: per walker and nucleus, G_a = sum over electrons of (chi_1, chi_2)
 };
 
 struct SweepArgs {
@@ -72,6 +75,10 @@ struct MeasureArgs {
   unsigned char* scr;   // W x slater_scratch_bytes(NS, mixed): matrix products that do not fit in LDS
   int contracted;       // as in WalkerArgs
   double eta;
+  int j3;               // as in WalkerArgs
+  double j3f[3];
+  double* j3scr;        // W x j3_measure_doubles(N): the term's per-electron gradient, Laplacian and U_3,
+                        // then the full grad U, grad ln|D| and E_L of the sample (written by the Slater pass)
 };
 
 // Several trajectories of one bucket (N, precision, Gaussian images, Ewald cut-off)
@@ -150,6 +157,14 @@ hipError_t launch_toy(double lambda, double k, double a, double mu, int s_kind, 
 // f = mean of the n_tw rows of f_stack, S = sum of the n_tw matrices of S_stack / n_tw^2.
 hipError_t launch_twist_average(int n_tw, int n3, const double* f_stack, const double* S_stack, double* f, double* S,
                                 hipStream_t st);
+// The on-site three-body Jastrow term: G_a of every walker from its positions (before the sweeps),
+// and the measurement's two passes around the Slater pass (its gradient, Laplacian and U_3 before;
+// its d/dR terms after, from the full grad U, grad ln|D| and E_L the Slater pass leaves).
+constexpr size_t j3_measure_doubles(int N) { return (size_t)10 * N + 2; }
+hipError_t launch_j3_init(const WalkerArgs& a, hipStream_t st);
+hipError_t launch_j3_grad(const MeasureArgs& m, hipStream_t st);
+hipError_t launch_j3_forces(const MeasureArgs& m, hipStream_t st);
+
 // General twist angles (radians) per axis with their cosines and sines: the complex path.
 struct TwistArgs {
   double th[3], c[3], s[3];

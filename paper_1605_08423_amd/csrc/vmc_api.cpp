@@ -26,10 +26,10 @@ using vmc_host::build_kvectors;
 namespace {
 
 enum KClass { K_SETUP, K_BUILD_A, K_INVERT, K_REFINE, K_SWEEP, K_EWALD, K_SLATER, K_FINALIZE, K_REDUCE, K_SYRK,
-              K_LANGEVIN, K_TOY, K_CSWEEP, K_CSLATER, K_NCLASS };
+              K_LANGEVIN, K_TOY, K_CSWEEP, K_CSLATER, K_J3, K_NCLASS };
 const char* kClassName[K_NCLASS] = {"proton_setup", "build_A", "invert", "refine", "sweep_half", "ewald_sample",
                                     "slater_sample", "finalize", "reduce", "syrk", "langevin", "toy",
-                                    "csweep", "cslater_sample"};
+                                    "csweep", "cslater_sample", "j3"};
 
 struct Pending { int cls; hipEvent_t a, b; };
 // vmc_energy_forces keeps at most this many sweeps queued ahead of the device, so that
@@ -77,6 +77,7 @@ struct vmc_traj {
   int64_t* nacc_bak = nullptr;    // accepted-move counts of the previous call (restored on failure)
   // Langevin state owned by the trajectory (vmc_traj_set_R, vmc_traj_langevin_step)
   double *Rd = nullptr, *Rprev = nullptr, *Sd = nullptr, *Sprev = nullptr;
+  double *j3G = nullptr, *j3scr = nullptr;   // the three-body term: G_a per walker, measurement scratch
   size_t bytes = 0;               // device bytes (traj_bytes), counted against the context's budget
   uint32_t lang_step = 0;         // completed vmc_traj_langevin_step calls (the noise counter)
   bool have_R = false, have_prev = false, have_S = false;
@@ -165,6 +166,8 @@ bool supported_ns(int ns) { return ns == 8 || ns == 16 || ns == 27 || ns == 32 |
 
 constexpr double kContractedZ2 = 0.3382168;   // the smaller exponent of the contracted orbital
 
+bool has_j3(const vmc_system& s) { return s.j3_f[0] != 0.0 || s.j3_f[1] != 0.0 || s.j3_f[2] != 0.0; }
+
 int check_sys(const vmc_system* s) {
   if (!s) return VMC_EINVAL;
   if (s->n_protons < 2 || (s->n_protons & 1) || !supported_ns(s->n_protons / 2)) return VMC_EINVAL;
@@ -180,6 +183,9 @@ int check_sys(const vmc_system* s) {
       if (!std::isfinite(s->theta[m])) return VMC_EINVAL;
   }
   if (s->contracted != 0 && s->contracted != 1) return VMC_EINVAL;
+  for (int m = 0; m < 3; ++m)
+    if (!std::isfinite(s->j3_f[m])) return VMC_EINVAL;
+  if (has_j3(*s) && (s->twist != 0 || s->general_twist || s->contracted || s->n_protons / 2 > 64)) return VMC_EINVAL;
   if (s->contracted) {
     // the images |n| <= 1 of the diffuse r^2 e^{-Z2 r^2} reach FP64 resolution only if Z2 (1.5 L)^2 >= 36
     const double h = 1.5 * s->box_L;
@@ -252,6 +258,9 @@ WalkerArgs walker_args(vmc_traj* t, const double* R, const double* C, const doub
   a.rscr_stride = slater_scratch_bytes(t->NS, t->sys.precision == VMC_MIXED) / sizeof(double);
   a.contracted = t->sys.contracted;
   a.eta = t->sys.eta;
+  a.j3 = has_j3(t->sys);
+  for (int q = 0; q < 3; ++q) a.j3f[q] = t->sys.j3_f[q];
+  a.j3G = t->j3G;
   return a;
 }
 
@@ -267,6 +276,9 @@ MeasureArgs measure_args(vmc_traj* t, const double* R, const double* C, const do
   m.acc = t->acc; m.rho_acc = t->rho_acc; m.scr = t->scr;
   m.contracted = t->sys.contracted;
   m.eta = t->sys.eta;
+  m.j3 = has_j3(t->sys);
+  for (int q = 0; q < 3; ++q) m.j3f[q] = t->sys.j3_f[q];
+  m.j3scr = t->j3scr;
   return m;
 }
 
@@ -297,8 +309,10 @@ int check_singular(vmc_ctx* ctx) {
 int measure(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e) {
   vmc_ctx* ctx = t->ctx;
   const int mixed = t->sys.precision == VMC_MIXED;
+  if (m.j3) RUN(K_J3, launch_j3_grad(m, ctx->stream));
   RUN(K_EWALD, launch_ewald_sample(m, e, mixed, ctx->stream));
   RUN(K_SLATER, launch_slater_sample(m, mixed, ctx->stream));
+  if (m.j3) RUN(K_J3, launch_j3_forces(m, ctx->stream));
   return VMC_OK;
 }
 int measure_c(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e, const TwistArgs& tw) {
@@ -318,8 +332,9 @@ size_t traj_bytes(const vmc_system& s, int W) {
   const size_t d = 2 * Wz * N * 3 + amat + Wz * 2 * inv_doubles(s) + 2 * Wz * 2 + Wz * (2 + 9 * N) + Wz * nk * 2 + Wz +
                    Wz * n3 + Wz + Wz * (1 + 3 * n3) + Wz * n3 + reduce_partial_doubles(W, (int)n3) + 3 + n3 +
                    kv.size() + 2 * nk + nk * N * 2 + n3 + 1 + 2 * n3 + 2 * n3 * n3;
-  return d * sizeof(double) + 2 * Wz * sizeof(int64_t) + (3 * Wz + 2 + slots.size() + nx0.size()) * sizeof(int) +
-         Wz * meas_scratch_bytes(s);
+  const size_t j3 = has_j3(s) ? Wz * (2 * N + j3_measure_doubles((int)N)) : 0;
+  return (d + j3) * sizeof(double) + 2 * Wz * sizeof(int64_t) +
+         (3 * Wz + 2 + slots.size() + nx0.size()) * sizeof(int) + Wz * meas_scratch_bytes(s);
 }
 
 void free_traj(vmc_traj* t) {
@@ -328,7 +343,7 @@ void free_traj(vmc_traj* t) {
   void* ptrs[] = {t->pos, t->Amat, t->Binv, t->ldet, t->sgn, t->acc, t->rho_acc, t->Vs, t->dVs, t->Uj,
                   t->means, t->f_w, t->partial, t->outv, t->nacc, t->kvec, t->rho_p, t->Ptab, t->Fconst,
                   t->Vpp, t->slot, t->slot_nx0, t->rflag, t->qflag, t->scr, t->pos_bak, t->nacc_bak,
-                  t->Rd, t->Rprev, t->Sd, t->Sprev};
+                  t->Rd, t->Rprev, t->Sd, t->Sprev, t->j3G, t->j3scr};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete t;
@@ -487,6 +502,8 @@ int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int W, uint32_t seed, u
             !dalloc(&t->Rprev, n3) && !dalloc(&t->Sd, n3 * n3) && !dalloc(&t->Sprev, n3 * n3);
   const size_t scr = meas_scratch_bytes(*sys);
   if (ok && scr) ok = !dalloc(&t->scr, (size_t)W * scr);
+  if (ok && has_j3(*sys))
+    ok = !dalloc(&t->j3G, (size_t)W * N * 2) && !dalloc(&t->j3scr, (size_t)W * j3_measure_doubles((int)N));
   if (!ok) { free_traj(t); return VMC_ENOMEM; }
   if (hipMemcpy(t->kvec, kv.data(), kv.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(t->slot, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
@@ -687,6 +704,7 @@ int vmc_energy_forces(vmc_traj* t, const double* R_in, const double* C, const do
   const bool cplx = is_complex(t->sys);
   const TwistArgs tw = twist_args(t->sys);
   if (!cplx) RUN(K_BUILD_A, launch_build_A(a, mixed, st));
+  if (a.j3) RUN(K_J3, launch_j3_init(a, st));
   const double rtol = t->sys.refine_tol == 0.0 ? 1e-7 : t->sys.refine_tol;
   const int total = n_equil + n_sweeps;
   for (int s = 0; s < total; ++s) {
@@ -1270,7 +1288,7 @@ int bucket_sweep(vmc_server* s, const std::vector<Served*>& qs) {
 }
 
 int check_request(const vmc_request* r) {
-  if (!r || check_sys(&r->sys) || r->sys.general_twist || r->sys.contracted) return VMC_EINVAL;
+  if (!r || check_sys(&r->sys) || r->sys.general_twist || r->sys.contracted || has_j3(r->sys)) return VMC_EINVAL;
   if (r->n_walkers < 2 || r->n_sweeps < 1 || r->n_equil < 0 || r->n_equil_first < 0 || r->n_steps < 1)
     return VMC_EINVAL;
   if (!(r->step_delta > 0.0) || !(r->Delta > 0.0) || r->alpha < 0.0 || r->T < 0.0 || (r->flags & ~7u))

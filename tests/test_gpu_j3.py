@@ -1,0 +1,139 @@
+"""The on-site three-body (electron-electron-nucleus) Jastrow term on the GPU against the oracle's
+on the same seeded inputs, through the C ABI: fixed configurations (also with the one-body term)
+and same-seed chains in FP64 (bar 1e-10) and in mixed precision (the mixed bars), plus the
+argument checks."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1605_08423_amd.inputs import small_system, workload
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-10
+TOLM = {"lnpsi": 1e-6, "EL": 5e-5, "dlnpsi": 2e-5, "dEL": 2e-5}
+F3 = (-0.3, 0.1, 0.05)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def elem(a, b):
+    a, b = np.atleast_1d(np.asarray(a, dtype=np.float64)), np.atleast_1d(np.asarray(b, dtype=np.float64))
+    return float(np.max(np.abs(a - b) / (np.abs(b) + np.max(np.abs(b)) + 1e-300)))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    from paper_1605_08423_amd import vmc
+    return torch, vmc, vmc.Context(0)
+
+
+def _T(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _wl(name):
+    return workload(name) if name in ("h16", "h54", "h128") else small_system(int(name[1:]), 1.35, seed=21)
+
+
+# Mixed cases: the third h128 configuration of this seed has E_L = -6.4 with b1 = 2.5 and the term,
+# and the FP32 error of the base path at that configuration (4e-4 Ha without either term) is then
+# 8.5e-5 of E_L; the relative bar fits E_L values well away from zero, so b1 = 2.5 runs at h54.
+@pytest.mark.parametrize("name,K,prec,b1", [("h16", 16, 0, 0.0), ("h32", 6, 0, 0.0), ("h54", 6, 0, 0.0),
+                                            ("h128", 3, 0, 0.0), ("h16", 8, 0, 2.5), ("h54", 4, 0, 2.5),
+                                            ("h16", 16, 1, 0.0), ("h54", 6, 1, 2.5), ("h128", 3, 1, 0.0)])
+def test_j3_eval_configs(oracle, dev, name, K, prec, b1):
+    torch, vmc, ctx = dev
+    wl = _wl(name)
+    say(f"[three-body eval_configs] {name} K={K} {'mixed' if prec else 'fp64'} b1={b1}")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
+    pos = wl.electrons(W=K, seed_offset=4)
+    sysd = vmc.make_system(wl.n, wl.L, precision=prec, b1=b1, j3=F3)
+    g = vmc.vmc_eval_configs(ctx, sysd, _T(torch, wl.R.reshape(-1)), _T(torch, Cm), _T(torch, wl.zeta),
+                             _T(torch, pos)).cpu().numpy()
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1, j3=F3)
+    n3 = 3 * wl.n
+    worst = {}
+    for k in range(K):
+        r = s.local(pos[k])
+        for q, a, b in [("lnpsi", g[k, 0], r["lnpsi"]), ("EL", g[k, 1], r["EL"]),
+                        ("dlnpsi", g[k, 2:2 + n3], r["dlnpsi"]), ("dEL", g[k, 2 + n3:], r["dEL"])]:
+            worst[q] = max(worst.get(q, 0.0), rel(a, b) if q in ("lnpsi", "EL") else elem(a, b))
+    say("  worst errors", worst)
+    for q, v in worst.items():
+        assert v < (TOL64 if prec == 0 else TOLM[q]), (q, v)
+
+
+@pytest.mark.parametrize("name,W,ne,ns", [("h16", 16, 2, 4), ("h54", 4, 1, 3), ("h128", 2, 0, 2)])
+def test_j3_chain_fp64(oracle, dev, name, W, ne, ns):
+    torch, vmc, ctx = dev
+    wl = _wl(name)
+    say(f"[three-body chain fp64] {name} W={W} equil={ne} sweeps={ns}")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
+    pos = wl.electrons(W=W, seed_offset=7)
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, j3=F3), W, seed=11, traj_id=3)
+    tr.set_walkers(_T(torch, pos))
+    out = tr.energy_forces(_T(torch, wl.R.reshape(-1)), _T(torch, Cm), _T(torch, wl.zeta), ne, ns, wl.delta,
+                           2).cpu().numpy()
+    means, acc, posg = tr.walker_means().cpu().numpy(), tr.accepts().cpu().numpy(), tr.get_walkers().cpu().numpy()
+    tr.close()
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, j3=F3)
+    xo = pos.copy()
+    sums, nacc = s.vmc_run(xo, ne, ns, wl.delta, seed=11, traj=3, step=2)
+    red = oracle.reduce(sums, ns)
+    flips = int(np.sum(acc != nacc))
+    say("  accepted moves gpu/oracle", acc.sum(), nacc.sum(), "walkers with a flipped decision:", flips)
+    assert flips == 0
+    assert rel(posg, xo) < 1e-12
+    worst = max(elem(means[w], red["means"][w]) for w in range(W))
+    say(f"  worst walker element-wise error of the means {worst:.3e}")
+    assert worst < TOL64
+    assert rel(out[0], red["E"]) < TOL64 and elem(out[3:], red["f"]) < TOL64
+
+
+@pytest.mark.parametrize("name,W,ne,ns", [("h16", 64, 4, 8), ("h54", 64, 2, 3)])
+def test_j3_chain_mixed_same_seed(oracle, dev, name, W, ne, ns):
+    torch, vmc, ctx = dev
+    wl = _wl(name)
+    say(f"[three-body chain mixed] {name} W={W}")
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
+    pos = wl.electrons(W=W, seed_offset=9)
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=vmc.VMC_MIXED, j3=F3), W, seed=5, traj_id=1)
+    tr.set_walkers(_T(torch, pos))
+    out = tr.energy_forces(_T(torch, wl.R.reshape(-1)), _T(torch, Cm), _T(torch, wl.zeta), ne, ns, wl.delta,
+                           0).cpu().numpy()
+    acc = tr.accepts().cpu().numpy()
+    tr.close()
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, j3=F3)
+    xo = pos.copy()
+    sums, nacc = s.vmc_run(xo, ne, ns, wl.delta, seed=5, traj=1, step=0)
+    red = oracle.reduce(sums, ns)
+    flips = int(np.sum(acc != nacc))
+    say("  E gpu/oracle", out[0], red["E"], "flipped walkers", flips)
+    if flips == 0:
+        assert rel(out[0], red["E"]) < 1e-6
+        assert rel(out[3:], red["f"]) < 1e-5
+    else:
+        assert abs(out[0] - red["E"]) < 2 * red["sigma_E"]
+
+
+def test_j3_system_validation(dev):
+    torch, vmc, ctx = dev
+    wl = workload("h16")
+    bad = [vmc.make_system(wl.n, wl.L, j3=F3, twist=1),
+           vmc.make_system(wl.n, wl.L, j3=F3, theta=(0.1, 0.2, 0.3)),
+           vmc.make_system(256, 14.0, j3=F3),
+           vmc.make_system(wl.n, wl.L, j3=(0.1, float("inf"), 0.0))]
+    for sysd in bad:
+        with pytest.raises(vmc.VMCError) as ei:
+            vmc.Trajectory(ctx, sysd, 4)
+        assert ei.value.code == vmc.VMC_EINVAL
