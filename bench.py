@@ -32,14 +32,14 @@ def _add(d: dict, unit: str, flops: float) -> dict:
 
 
 def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, one_body: bool = False,
-               acc: float = 0.57, contracted: bool = False) -> dict:
+               acc: float = 0.57, contracted: bool = False, three_body: bool = False) -> dict:
     """Algorithmic work of the method in one walker's share of a launch, by the unit it runs on:
     {unit: flops} (FMA = 2 flops; exp, erfc, sqrt, rcp, sincos count 1).  img: Gaussian images
     evaluated per axis (3, or 1 when the dropped ones are below FP32 resolution); acc: the
     acceptance rate (a rejected move costs no inverse update); one_body: the electron-proton
     Jastrow term; contracted: the orbital phi_1 + eta phi_2 (two exps per image and axis and four
-    products of Cartesian factors instead of one).  In mixed precision the basis, Jastrow and Ewald
-    real-space terms are FP32."""
+    products of Cartesian factors instead of one); three_body: the on-site electron-electron-nucleus
+    Jastrow term.  In mixed precision the basis, Jastrow and Ewald real-space terms are FP32."""
     NS = N // 2
     img = 3 if nimg else 1
     lo = "f32" if mixed else "f64"
@@ -64,7 +64,7 @@ def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, on
         # the MO row m = phi C (2 N NS), the ratio q = m . (A^-1 column) (2 NS) and, if accepted,
         # the Sherman-Morrison update (m^T A^-1 and the rank-1 update, 4 NS^2)
         basis = N * (3 * (3 + 2 * img) + 2) if not contracted else N * (3 * (3 + 8 * img) + 14)
-        jas = 30 * (N - 1) + (30 * N if one_body else 0)
+        jas = 30 * (N - 1) + (30 * N if one_body else 0) + (J3_MOVE * N if three_body else 0)
         w = {"f64": NS * (2 * N * NS + 2 * NS + acc * 4 * NS * NS)}
         return _add(w, lo, NS * (basis + jas))
     if cls == "ewald_sample":
@@ -82,6 +82,19 @@ def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, on
         move = N * 93 + 8 * N * NS + 8 * NS + 30 * (N - 1) + acc * 16 * NS * NS
         refresh = NS * N * 93 + 8 * NS * N * NS + 8 * NS ** 3
         return {"f64": NS * move + refresh / CREFRESH}
+    if cls == "j3_init":
+        # G_a = sum_i chi_a(r_i) of every nucleus: per (electron, nucleus) pair the squared
+        # periodised distance (15), an exp and two sums
+        return {"f64": N * N * 19}
+    if cls == "j3_grad":
+        # G_a and sum_i chi_ai^T F chi_ai (N^2 x 26); per (electron, nucleus) pair the orbitals'
+        # value, gradient and Laplacian (J3_VGL) and four F-forms with G_a - chi (28); in the working
+        # precision of the Jastrow terms
+        return {lo: N * N * (26 + J3_VGL + 28)}
+    if cls == "j3_forces":
+        # per (electron, nucleus) pair the orbitals with their Hessian and gradient of the Laplacian
+        # (J3_FULL), then G_a, G_a,mu, the two velocity contractions per axis and the self terms (150)
+        return {lo: N * N * (J3_FULL + 150)}
     if cls == "cslater_sample":
         # B = C A^-1, M = X B, W = B M per spin (complex, 8 N NS^2 each); the (electron, centre) passes
         # with the complex basis and its derivatives (295 + 110 flops); the Jastrow pass
@@ -91,10 +104,28 @@ def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, on
 
 # the complex half-sweep forms and inverts its Slater matrix afresh every CREFRESH-th sweep
 CREFRESH = 4
+# F of the three-body leg: the lowest VMC energy of a scan at 54 protons with b_1 = 2.5
+J3_LEG_F = (-0.2, 0.0, 0.05)
+
+
+def _f3(text: str):
+    """'f11,f12,f22' -> a 3-tuple of floats; 'none' -> None."""
+    if text.strip().lower() == "none":
+        return None
+    v = tuple(float(x) for x in text.split(","))
+    if len(v) != 3:
+        raise argparse.ArgumentTypeError("three numbers f11,f12,f22")
+    return v
+# Three-body flops per (electron, nucleus) pair: a move's change (chi at the new and the old
+# position, 2 x 20, and the F-form with G_a - chi, 10); the orbitals chi_1, chi_2 with value,
+# gradient and Laplacian (per axis the sin-periodised offset and its polynomial factors, 3 x 30,
+# the exp and the products, 60) and with every component up to the gradient of the Laplacian
+# (3 x 42 and 4 products of 14 components, 250)
+J3_MOVE, J3_VGL, J3_FULL = 50, 150, 376
 
 
 def executed_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, one_body: bool = False,
-                   acc: float = 0.57, contracted: bool = False) -> dict:
+                   acc: float = 0.57, contracted: bool = False, three_body: bool = False) -> dict:
     """The arithmetic a launch executes, where it differs from the method's count: the sweep applies
     its Sherman-Morrison updates in blocks of 16 moves on the matrix cores, forming the full rows
     P = M' A^-1 of every proposal and a rank-16 update whatever the acceptance (2 NS N NS + 4 NS^3
@@ -105,12 +136,12 @@ def executed_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool
         w = work_model(cls, N, nk, nslot, nimg, mixed, one_body, acc)
         return {"f64": w["f64"] + NS * (1 - acc) * 8 * NS * NS}
     if cls != "sweep_half":
-        return work_model(cls, N, nk, nslot, nimg, mixed, one_body, acc, contracted)
+        return work_model(cls, N, nk, nslot, nimg, mixed, one_body, acc, contracted, three_body)
     NS = N // 2
     img = 3 if nimg else 1
     lo = "f32" if mixed else "f64"
     basis = N * (3 * (3 + 2 * img) + 2) if not contracted else N * (3 * (3 + 8 * img) + 14)
-    per_move = basis + 30 * (N - 1) + (30 * N if one_body else 0)
+    per_move = basis + 30 * (N - 1) + (30 * N if one_body else 0) + (J3_MOVE * N if three_body else 0)
     w = {"f64": 2 * NS * N * NS + 4 * NS ** 3 + NS * 16 * NS}    # matrix cores; the recursion t -= t[i] z
     return _add(w, lo, NS * per_move)
 
@@ -137,11 +168,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_workload_key(workload: str, precision: str, walkers: int, j1: float = 0.0, rs=None) -> str:
+def traffic_workload_key(workload: str, precision: str, walkers: int, j1: float = 0.0, rs=None, j3=None) -> str:
     """Names the run a traffic measurement belongs to, as profiles/traffic.json records it."""
     key = f"{workload} {precision}, W={walkers}"
     if j1 > 0:
         key += f", b1={j1}"
+    if j3 is not None:
+        key += f", F3={','.join(f'{x:g}' for x in j3)}"
     if rs is not None:
         key += f", r_s={rs}"
     return key
@@ -582,14 +615,14 @@ def kernel_space(sysd, wl, prec_mixed: bool):
     return nk, nslot, nimg
 
 
-def run_leg(wl, W: int, M: int, prec: int, b1: float, steps: int, warmup: int, log=None, eta=None) -> dict:
+def run_leg(wl, W: int, M: int, prec: int, b1: float, steps: int, warmup: int, log=None, eta=None, j3=None) -> dict:
     """Langevin steps of one trajectory, each one full pass of the hot path: Hueckel orbitals and
     proton tables at R, the energy/force estimate (20 equilibration sweeps at the first step, 5
     after), S and the update on the trajectory's own state.  Times `steps` steps after `warmup`."""
     import torch
     from paper_1605_08423_amd import vmc
     ctx = vmc.Context(0)
-    sysd = vmc.make_system(wl.n, wl.L, precision=prec, b1=b1, eta=eta)
+    sysd = vmc.make_system(wl.n, wl.L, precision=prec, b1=b1, eta=eta, j3=j3)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     traj = vmc.Trajectory(ctx, sysd, W, seed=wl.seed, traj_id=0)
     traj.set_walkers(dev(wl.electrons(W=W)))
@@ -661,6 +694,10 @@ def main():
                          "s-Gaussian")
     ap.add_argument("--contracted-leg", type=float, default=0.1, metavar="ETA",
                     help="eta of the short contracted-basis leg of the default line (nan: skip)")
+    ap.add_argument("--j3", type=_f3, default=None, metavar="F11,F12,F22",
+                    help="add the on-site three-body Jastrow term with this symmetric F")
+    ap.add_argument("--three-body-leg", type=_f3, default=J3_LEG_F, metavar="F11,F12,F22",
+                    help="F of the short three-body leg of the default line (run with b_1 = 2.5; 'none': skip)")
     ap.add_argument("--fp64-steps", type=int, default=2,
                     help="timed steps of the plain FP64 leg beside a mixed-precision headline (0: skip)")
     ap.add_argument("--serve-leg", type=int, default=12, metavar="K",
@@ -730,16 +767,17 @@ def main():
     mixed = args.precision == "mixed"
     prec = vmc.VMC_MIXED if mixed else vmc.VMC_FP64
     log = open(args.log, "w") if args.log else None
-    lead = run_leg(wl, W, M, prec, args.j1, args.steps, args.warmup, log, args.eta)
+    lead = run_leg(wl, W, M, prec, args.j1, args.steps, args.warmup, log, args.eta, args.j3)
     times, out_h, sysd = lead["times"], lead["out"], lead["sysd"]
     nk, nslot, nimg = kernel_space(sysd, wl, mixed)
     acc = float(out_h[2])
-    tkey = traffic_workload_key(args.workload, args.precision, W, args.j1, args.rs)
+    tkey = traffic_workload_key(args.workload, args.precision, W, args.j1, args.rs, args.j3)
+    j3on = args.j3 is not None
 
     def kernel_roofline(name):
         ms, n = times[name]
-        parts = work_model(name, N, nk, nslot, nimg, mixed, args.j1 > 0, acc, args.eta is not None)
-        executed = executed_model(name, N, nk, nslot, nimg, mixed, args.j1 > 0, acc, args.eta is not None)
+        parts = work_model(name, N, nk, nslot, nimg, mixed, args.j1 > 0, acc, args.eta is not None, j3on)
+        executed = executed_model(name, N, nk, nslot, nimg, mixed, args.j1 > 0, acc, args.eta is not None, j3on)
         avg_s = ms / max(n, 1) / 1e3
         flops, achieved, peak = roofline_numbers(parts, W, avg_s)
         return {"bound": "alu", "kernel": name, "achieved": round(achieved, 3), "peak": round(peak, 2),
@@ -795,6 +833,29 @@ def main():
                                    "avg_launch_ms": round(avg_s * 1e3, 4)},
                       "kernel_ms": {k: round(v[0], 2) for k, v in kms.items()}}
 
+    three_body = None
+    if args.j3 is None and args.three_body_leg is not None and args.eta is None and args.workload == "h128":
+        # the same workload with the one-body cusp (b_1 = 2.5) and the three-body term, a few steps
+        b1 = args.j1 if args.j1 > 0 else 2.5
+        r = run_leg(wl, W, M, prec, b1, 2, 1, None, None, args.three_body_leg)
+        acc3 = float(r["out"][2])
+        kms = {k: v for k, v in r["times"].items() if v[1]}
+        per = {}
+        for k in ("sweep_half", "slater_sample", "j3_grad", "j3_forces"):
+            if k not in kms:
+                continue
+            avg_s = kms[k][0] / kms[k][1] / 1e3
+            parts = work_model(k, N, nk, nslot, nimg, mixed, True, acc3, False, True)
+            _, achieved, peak = roofline_numbers(parts, W, avg_s)
+            per[k] = {"avg_launch_ms": round(avg_s * 1e3, 4), "achieved": round(achieved, 3), "peak": round(peak, 2),
+                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4) if peak else None}
+        three_body = {"F": list(args.three_body_leg), "b1": b1, "value": round(r["value"], 1),
+                      "unit": "walker-sweeps/s", "steps": r["steps"], "warmup": 1,
+                      "ms_per_step": round(1e3 * r["elapsed"] / r["steps"], 2),
+                      "over_headline": round(r["value"] / lead["value"], 3), "E_Ha": float(r["out"][0]),
+                      "sigma_E_Ha": float(r["out"][1]), "acceptance": round(acc3, 4), "kernels": per,
+                      "kernel_ms": {k: round(v[0], 2) for k, v in kms.items()}}
+
     mesh = None
     if args.mesh_leg > 0 and args.workload == "h128":
         mesh = twist_mesh_leg("h128", args.mesh_leg, args.mesh_walkers, 10, 1, 1)
@@ -825,13 +886,14 @@ def main():
         "config": {"workload": f"{args.workload}: {N} H + {N} e-, r_s={wl.rs}, T={wl.T_kelvin:g} K, {W} walkers x {M} "
                                f"measured (+5 re-equilibration) sweeps per Langevin step, {args.precision} precision"
                                + (f", one-body Jastrow b_1={args.j1:g}" if args.j1 > 0 else "")
-                               + (f", contracted basis eta={args.eta:g}" if args.eta is not None else ""),
+                               + (f", contracted basis eta={args.eta:g}" if args.eta is not None else "")
+                               + (f", three-body F={','.join(f'{x:g}' for x in args.j3)}" if j3on else ""),
                    "N": N, "walkers": W, "sweeps": M, "precision": args.precision, "one_body_b1": args.j1},
         "langevin_steps_per_s": round(args.steps / lead["elapsed"], 4),
         "step_latency_ms": {"p50": round(lead["p50"], 1), "p99": round(lead["p99"], 1)},
         "E_Ha": float(out_h[0]), "sigma_E_Ha": float(out_h[1]), "acceptance": acc,
         "roofline": roofline, "fp64_gpu": fp64, "served": served, "twist_mesh": mesh,
-        "contracted_basis": contracted, "cpu_baseline": cpu,
+        "contracted_basis": contracted, "three_body": three_body, "cpu_baseline": cpu,
         "kernel_ms": {k: round(v[0], 2) for k, v in times.items()},
     }
     print(json.dumps(line))

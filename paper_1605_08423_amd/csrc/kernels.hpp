@@ -162,8 +162,8 @@ hipError_t launch_twist_average(int n_tw, int n3, const double* f_stack, const d
 // its d/dR terms after, from the full grad U, grad ln|D| and E_L the Slater pass leaves).
 constexpr size_t j3_measure_doubles(int N) { return (size_t)10 * N + 2; }
 hipError_t launch_j3_init(const WalkerArgs& a, hipStream_t st);
-hipError_t launch_j3_grad(const MeasureArgs& m, hipStream_t st);
-hipError_t launch_j3_forces(const MeasureArgs& m, hipStream_t st);
+hipError_t launch_j3_grad(const MeasureArgs& m, int mixed, hipStream_t st);
+hipError_t launch_j3_forces(const MeasureArgs& m, int mixed, hipStream_t st);
 
 // General twist angles (radians) per axis with their cosines and sines: the complex path.
 struct TwistArgs {

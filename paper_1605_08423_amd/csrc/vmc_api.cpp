@@ -26,10 +26,10 @@ using vmc_host::build_kvectors;
 namespace {
 
 enum KClass { K_SETUP, K_BUILD_A, K_INVERT, K_REFINE, K_SWEEP, K_EWALD, K_SLATER, K_FINALIZE, K_REDUCE, K_SYRK,
-              K_LANGEVIN, K_TOY, K_CSWEEP, K_CSLATER, K_J3, K_NCLASS };
+              K_LANGEVIN, K_TOY, K_CSWEEP, K_CSLATER, K_J3_INIT, K_J3_GRAD, K_J3_FORCES, K_NCLASS };
 const char* kClassName[K_NCLASS] = {"proton_setup", "build_A", "invert", "refine", "sweep_half", "ewald_sample",
                                     "slater_sample", "finalize", "reduce", "syrk", "langevin", "toy",
-                                    "csweep", "cslater_sample", "j3"};
+                                    "csweep", "cslater_sample", "j3_init", "j3_grad", "j3_forces"};
 
 struct Pending { int cls; hipEvent_t a, b; };
 // vmc_energy_forces keeps at most this many sweeps queued ahead of the device, so that
@@ -309,10 +309,10 @@ int check_singular(vmc_ctx* ctx) {
 int measure(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e) {
   vmc_ctx* ctx = t->ctx;
   const int mixed = t->sys.precision == VMC_MIXED;
-  if (m.j3) RUN(K_J3, launch_j3_grad(m, ctx->stream));
+  if (m.j3) RUN(K_J3_GRAD, launch_j3_grad(m, mixed, ctx->stream));
   RUN(K_EWALD, launch_ewald_sample(m, e, mixed, ctx->stream));
   RUN(K_SLATER, launch_slater_sample(m, mixed, ctx->stream));
-  if (m.j3) RUN(K_J3, launch_j3_forces(m, ctx->stream));
+  if (m.j3) RUN(K_J3_FORCES, launch_j3_forces(m, mixed, ctx->stream));
   return VMC_OK;
 }
 int measure_c(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e, const TwistArgs& tw) {
@@ -704,7 +704,7 @@ int vmc_energy_forces(vmc_traj* t, const double* R_in, const double* C, const do
   const bool cplx = is_complex(t->sys);
   const TwistArgs tw = twist_args(t->sys);
   if (!cplx) RUN(K_BUILD_A, launch_build_A(a, mixed, st));
-  if (a.j3) RUN(K_J3, launch_j3_init(a, st));
+  if (a.j3) RUN(K_J3_INIT, launch_j3_init(a, st));
   const double rtol = t->sys.refine_tol == 0.0 ? 1e-7 : t->sys.refine_tol;
   const int total = n_equil + n_sweeps;
   for (int s = 0; s < total; ++s) {

@@ -176,7 +176,7 @@ class Context:
         _check(_lib().vmc_set_profiling(self.h, int(on)), "vmc_set_profiling")
 
     def kernel_times(self):
-        n = 16
+        n = 32
         names = (C.c_char_p * n)()
         ms = (C.c_double * n)()
         cnt = (C.c_longlong * n)()
