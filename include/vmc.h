@@ -115,8 +115,9 @@ typedef struct {
                          F = [[f11, f12], [f12, f22]] = [[j3_f[0], j3_f[1]], [j3_f[1], j3_f[2]]] the same
                          for every nucleus.  All zero: no term.  The term requires twist = 0,
                          general_twist = 0, contracted = 0 and N_sigma <= 64, and is not for the
-                         server (else VMC_EINVAL); its measurement terms are FP64 in both modes, its
-                         sweep terms in the Jastrow precision */
+                         server (else VMC_EINVAL); its orbitals are evaluated in the precision of
+                         the Jastrow terms (FP32 in VMC_MIXED), their per-nucleus sums combined and
+                         accumulated in FP64 */
 } vmc_system;
 
 /* ---------------------------------------------------------------- context -- */

@@ -72,3 +72,29 @@ def test_complex_work_model_and_twist_mesh(oracle):
     mesh = bench.monkhorst_pack(4)
     np.testing.assert_allclose(mesh, oracle.monkhorst_pack(4))
     assert mesh.shape == (64, 3) and np.allclose(mesh.sum(0), 0.0)
+
+
+def test_three_body_work_model_and_arguments():
+    """The three-body kernels' counts in the working precision of the Jastrow terms, the term's
+    share of a move in the half-sweep, and the F argument of --j3 / --three-body-leg."""
+    import argparse
+    import pytest
+    sys.path.insert(0, ROOT)
+    import bench
+    N, NS = 128, 64
+    for mixed, unit in ((True, "f32"), (False, "f64")):
+        g = bench.work_model("j3_grad", N, 0, 0, 1, mixed)
+        f = bench.work_model("j3_forces", N, 0, 0, 1, mixed)
+        assert g == {unit: N * N * (26 + bench.J3_VGL + 28)} and f == {unit: N * N * (bench.J3_FULL + 150)}
+    assert bench.work_model("j3_init", N, 0, 0, 1, True) == {"f64": N * N * 19}
+    a = bench.work_model("sweep_half", N, 0, 0, 1, True, acc=0.5)
+    b = bench.work_model("sweep_half", N, 0, 0, 1, True, acc=0.5, three_body=True)
+    assert b["f64"] == a["f64"] and b["f32"] - a["f32"] == NS * bench.J3_MOVE * N
+    ea = bench.executed_model("sweep_half", N, 0, 0, 1, True, acc=0.5)
+    eb = bench.executed_model("sweep_half", N, 0, 0, 1, True, acc=0.5, three_body=True)
+    assert eb["f32"] - ea["f32"] == NS * bench.J3_MOVE * N
+    assert bench._f3("-0.2,0,0.05") == (-0.2, 0.0, 0.05) and bench._f3("none") is None
+    with pytest.raises(argparse.ArgumentTypeError):
+        bench._f3("1,2")
+    assert bench.traffic_workload_key("h128", "mixed", 16, 2.5, None, (-0.2, 0.0, 0.05)) == \
+        "h128 mixed, W=16, b1=2.5, F3=-0.2,0,0.05"
