@@ -74,6 +74,8 @@ def _setup(l):
     l.o_huckel_twist.argtypes = [i, d, P(d), P(d), i, i, P(d), P(d)]
     l.o_vmc_run.argtypes = [P(OSys), i, P(d), i, i, d, u32, u32, u32, P(d), P(C.c_int64), i]
     l.o_vmc_run_from.argtypes = [P(OSys), i, u32, P(d), i, i, d, u32, u32, u32, P(d), P(C.c_int64), i]
+    l.o_vmc_run_opt.argtypes = [P(OSys), i, u32, P(d), i, i, d, u32, u32, u32, P(d), P(C.c_int64), P(d), i]
+    l.o_param_derivs.argtypes = [P(OSys), P(d), P(d)]
     l.o_reduce.argtypes = [i, i, i, P(d), P(d), P(d), P(d), P(d), P(d)]
     l.o_build_S.argtypes = [i, i, P(d), P(d), P(d)]
     l.o_build_S.restype = None
@@ -168,19 +170,30 @@ class System:
             raise RuntimeError(f"o_local failed rc={rc}")
         return dict(lnpsi=lnpsi[0], sign=sign[0], EL=EL[0], dlnpsi=dl, dEL=de)
 
-    def vmc_run(self, x, n_equil, n_meas, delta, seed, traj=0, step=0, threads=0, walker0=0):
-        """Runs the Metropolis chains in place on x (W, Ne, 3); returns (sums, n_acc).
-        x holds walkers walker0 .. walker0+W-1 of a larger set (their random streams)."""
+    def vmc_run(self, x, n_equil, n_meas, delta, seed, traj=0, step=0, threads=0, walker0=0, params=False):
+        """Runs the Metropolis chains in place on x (W, Ne, 3); returns (sums, n_acc), and with
+        params=True also the per-walker parameter sums (W, 36): [sum E_L, sum O (5), sum E_L O (5),
+        sum O O^T (25)] over the measured samples.  x holds walkers walker0 .. walker0+W-1 of a
+        larger set (their random streams)."""
         assert x.dtype == np.float64 and x.flags.c_contiguous
         W = x.shape[0]
         n3 = 3 * self.n_p
         sums = np.zeros((W, 2 + 3 * n3))
         nacc = np.zeros(W, dtype=np.int64)
-        rc = lib().o_vmc_run_from(C.byref(self.s), W, walker0, _dp(x), n_equil, n_meas, delta, seed, traj, step,
-                                  _dp(sums), nacc.ctypes.data_as(C.POINTER(C.c_int64)), threads)
+        popt = np.zeros((W, NOPT)) if params else None
+        rc = lib().o_vmc_run_opt(C.byref(self.s), W, walker0, _dp(x), n_equil, n_meas, delta, seed, traj, step,
+                                 _dp(sums), nacc.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 _dp(popt) if params else None, threads)
         if rc:
             raise RuntimeError(f"o_vmc_run failed rc={rc}")
-        return sums, nacc
+        return (sums, nacc, popt) if params else (sums, nacc)
+
+    def param_derivs(self, x):
+        """O_k = d ln psi / d p_k for p = (b, b_1, f_11, f_12, f_22) at the configuration x."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        O = np.zeros(5)
+        lib().o_param_derivs(C.byref(self.s), _dp(x), _dp(O))
+        return O
 
 
 class CSystem(System):
@@ -321,6 +334,36 @@ def reduce(sums, M):
     if rc:
         raise RuntimeError("o_reduce failed")
     return dict(E=E[0], sigma_E=sig[0], f=f, f_w=fw, means=means)
+
+
+# per-walker parameter sums of o_vmc_run_opt: [sum E_L, sum O (5), sum E_L O (5), sum O O^T (25)]
+NOPT = 36
+PARAM_NAMES = ("b", "b1", "f11", "f12", "f22")
+
+
+def param_stats(popt, M):
+    """Means over the W M samples of a run: [E, <O> (5), <E_L O> (5), <O O^T> (25)]."""
+    popt = np.asarray(popt, dtype=np.float64)
+    return popt.sum(axis=0) / (popt.shape[0] * M)
+
+
+def sr_step(stats, active, eps, tau):
+    """One step of stochastic reconfiguration (Sorella, PRB 64, 024512 (2001)) from the sample
+    means of param_stats: the generalised forces f_k = -dE/dp_k = -2 (<E_L O_k> - E <O_k>), the
+    covariance S_kl = <O_k O_l> - <O_k><O_l> of the logarithmic derivatives, its diagonal scaled
+    by (1 + eps), and the change dp = tau S^-1 f over the parameters whose bit is set in active
+    (the others stay).  Returns (dp, f, S)."""
+    stats = np.asarray(stats, dtype=np.float64)
+    E, O, EO, OO = stats[0], stats[1:6], stats[6:11], stats[11:36].reshape(5, 5)
+    f = -2.0 * (EO - E * O)
+    S = OO - np.outer(O, O)
+    idx = [k for k in range(5) if (active >> k) & 1]
+    dp = np.zeros(5)
+    if idx:
+        Sa = S[np.ix_(idx, idx)].copy()
+        Sa[np.diag_indices_from(Sa)] *= 1.0 + eps
+        dp[idx] = tau * np.linalg.solve(Sa, f[idx])
+    return dp, f, S
 
 
 def build_S(f_w, f):

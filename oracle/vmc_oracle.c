@@ -24,6 +24,11 @@
  *  - Ewald parameters, Metropolis details and the Hueckel orbitals are not in
  *    the paper; they are recorded readings shared with the GPU library only
  *    through their definitions.
+ *  - Wavefunction optimisation (main text: the wavefunction is re-optimised before
+ *    every ionic step; the optimiser is only cited): the logarithmic derivatives of
+ *    the Jastrow parameters (o_param_derivs) and their per-walker sums along the
+ *    chain (o_vmc_run_opt) feed stochastic reconfiguration, whose step is written
+ *    from its published definition in oracle.py (sr_step).
  * Every function below is pinned by a test in tests/test_oracle_*.py; the
  * end-to-end Monte Carlo averages themselves are "parity unpinned" beyond the
  * pins of their parts (no values exist in the paper for this wavefunction).
@@ -491,6 +496,58 @@ void o_jastrow(const osys* s, const double* x, double* U, double* gradU, double*
   *U = Ut;
 }
 
+/* ------------------------------------------------- variational parameters -- */
+/* O_k = d ln psi / d p_k for the Jastrow parameters p = (b, b_1, f_11, f_12, f_22): the
+ * logarithmic derivatives that stochastic reconfiguration (Sorella, PRB 64, 024512 (2001); the
+ * paper re-optimises the wavefunction before each ionic step) uses.  Each is the derivative of
+ * the term's own definition, summed pair by pair:
+ *   b    two-body u = a rho / (1 + b rho):        sum_{i<j} -a_ij rho_ij^2 / (1 + b rho_ij)^2
+ *   b_1  one-body -(2Z)^{3/4} u_1((2Z)^{1/4} rho), u_1(y) = (1 - e^{-b_1 y}) / (2 b_1), Z = 1:
+ *        d u_1 / d b_1 = [b_1 y e^{-b_1 y} - (1 - e^{-b_1 y})] / (2 b_1^2), summed over (i, a)
+ *   f_qr three-body (Eq. e:j33) with f_12 = f_21:  sum_a sum_{i<j} chi_q(r_ia) chi_r(r_ja)
+ *        (+ chi_r(r_ia) chi_q(r_ja) for q != r).
+ * O_b1 is 0 without the one-body term (b_1 = 0 means no term); the three-body derivatives do not
+ * depend on F and are formed for any F, zero included. */
+void o_param_derivs(const osys* s, const double* x, double O[5]) {
+  const int ne = s->n_up + s->n_dn;
+  for (int k = 0; k < 5; ++k) O[k] = 0.0;
+  if (s->jastrow_on)
+    for (int i = 0; i < ne; ++i)
+      for (int j = i + 1; j < ne; ++j) {
+        double d[3] = {x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1], x[3 * i + 2] - x[3 * j + 2]};
+        const double rho = periodised_rho(s, d), a = spin_of(s, i) == spin_of(s, j) ? s->a_par : s->a_anti;
+        const double den = 1.0 + s->b * rho;
+        O[0] += -a * rho * rho / (den * den);
+      }
+  if (s->b1 > 0.0) {
+    const double Z = 1.0, c = pow(2.0 * Z, 0.75), sc = pow(2.0 * Z, 0.25), b1 = s->b1;
+    for (int i = 0; i < ne; ++i)
+      for (int a = 0; a < s->n_p; ++a) {
+        double d[3] = {x[3 * i] - s->R[3 * a], x[3 * i + 1] - s->R[3 * a + 1], x[3 * i + 2] - s->R[3 * a + 2]};
+        const double y = sc * periodised_rho(s, d), e = exp(-b1 * y);
+        O[1] += -c * (b1 * y * e - (1.0 - e)) / (2.0 * b1 * b1);
+      }
+  }
+  double* v1 = malloc(sizeof(double) * ne);
+  double* v2 = malloc(sizeof(double) * ne);
+  for (int a = 0; a < s->n_p; ++a) {
+    for (int i = 0; i < ne; ++i) {
+      double ci[28];
+      o_j3_orbitals(s, a, x + 3 * i, ci);
+      v1[i] = ci[0];
+      v2[i] = ci[14];
+    }
+    for (int i = 0; i < ne; ++i)
+      for (int j = i + 1; j < ne; ++j) {
+        O[2] += v1[i] * v1[j];
+        O[3] += v1[i] * v2[j] + v2[i] * v1[j];
+        O[4] += v2[i] * v2[j];
+      }
+  }
+  free(v1);
+  free(v2);
+}
+
 /* -------------------------------------------------------------- potential -- */
 /* Coulomb energy of the protons (+1 at R) and electrons (-1 at x).
  * OP_EWALD: real-space erfc sum over minimum-image pairs, reciprocal sum over
@@ -925,11 +982,17 @@ static void mo_row(const osys* s, const double r[3], double* m) {
  * only those W walkers, and walker w draws from the counter of walker w0 + w. */
 int o_vmc_run(const osys* s, int W, double* x, int n_equil, int n_meas, double delta,
               uint32_t seed, uint32_t traj, uint32_t step, double* sums, int64_t* n_acc, int n_threads) {
-  return o_vmc_run_from(s, W, 0u, x, n_equil, n_meas, delta, seed, traj, step, sums, n_acc, n_threads);
+  return o_vmc_run_opt(s, W, 0u, x, n_equil, n_meas, delta, seed, traj, step, sums, n_acc, NULL, n_threads);
 }
 
 int o_vmc_run_from(const osys* s, int W, uint32_t w0, double* x, int n_equil, int n_meas, double delta,
                    uint32_t seed, uint32_t traj, uint32_t step, double* sums, int64_t* n_acc, int n_threads) {
+  return o_vmc_run_opt(s, W, w0, x, n_equil, n_meas, delta, seed, traj, step, sums, n_acc, NULL, n_threads);
+}
+
+int o_vmc_run_opt(const osys* s, int W, uint32_t w0, double* x, int n_equil, int n_meas, double delta,
+                  uint32_t seed, uint32_t traj, uint32_t step, double* sums, int64_t* n_acc, double* popt,
+                  int n_threads) {
   int ne = s->n_up + s->n_dn, n3 = 3 * s->n_p, nsum = 2 + 3 * n3;
   int periodic = (s->basis_kind == OB_PERIODIC_GAUSS);
   int err = 0;
@@ -941,6 +1004,8 @@ int o_vmc_run_from(const osys* s, int W, uint32_t w0, double* x, int n_equil, in
     double* xw = x + (size_t)w * 3 * ne;
     double* sw = sums + (size_t)w * nsum;
     memset(sw, 0, sizeof(double) * nsum);
+    double* pw = popt ? popt + (size_t)w * O_NOPT : NULL;
+    if (pw) memset(pw, 0, sizeof(double) * O_NOPT);
     int64_t acc = 0;
     double *Asp[2], ld[2] = {0, 0}, sgs[2] = {1, 1};
     int nsp[2] = {s->n_up, s->n_dn};
@@ -1030,6 +1095,16 @@ int o_vmc_run_from(const osys* s, int W, uint32_t w0, double* x, int n_equil, in
           sw[2 + t] += dE[t];
           sw[2 + n3 + t] += dg[t];
           sw[2 + 2 * n3 + t] += el * dg[t];
+        }
+        if (pw) {
+          double O[5];
+          o_param_derivs(s, xw, O);
+          pw[0] += el;
+          for (int k = 0; k < 5; ++k) {
+            pw[1 + k] += O[k];
+            pw[6 + k] += el * O[k];
+            for (int l = 0; l < 5; ++l) pw[11 + 5 * k + l] += O[k] * O[l];
+          }
         }
       }
     }
