@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvmc.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["k_walkers.hip", "k_measure.hip", "k_langevin.hip", "k_complex.hip", "k_j3.hip", "vmc_api.cpp", "host.cpp"]
+SOURCES = ["k_walkers.hip", "k_measure.hip", "k_langevin.hip", "k_complex.hip", "k_j3.hip", "k_opt.hip", "vmc_api.cpp", "host.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]

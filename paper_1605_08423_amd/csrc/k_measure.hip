@@ -858,6 +858,7 @@ __global__ __launch_bounds__(256, sizeof(Real) == 4 ? 2 : 1) void k_slater_sampl
     acc[0] += EL;
     acc[1] += EL * EL;
     m.Uj[w] = Us;
+    if (m.ELs) m.ELs[w] = EL;
   }
   if (m.j3) {
     // for the three-body term's d/dR pass: grad U, grad ln|D| and E_L of this sample

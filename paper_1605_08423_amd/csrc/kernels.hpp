@@ -79,6 +79,8 @@ struct MeasureArgs {
   double j3f[3];
   double* j3scr;        // W x j3_measure_doubles(N): the term's per-electron gradient, Laplacian and U_3,
                         // then the full grad U, grad ln|D| and E_L of the sample (written by the Slater pass)
+  double* ELs;          // W: E_L of the sample, written by the Slater pass when not null
+  double* popt;         // W x kOptStats: the walker's parameter sums (k_opt_sample)
 };
 
 // Several trajectories of one bucket (N, precision, Gaussian images, Ewald cut-off)
@@ -162,6 +164,11 @@ hipError_t launch_twist_average(int n_tw, int n3, const double* f_stack, const d
 // its d/dR terms after, from the full grad U, grad ln|D| and E_L the Slater pass leaves).
 constexpr size_t j3_measure_doubles(int N) { return (size_t)10 * N + 2; }
 hipError_t launch_j3_init(const WalkerArgs& a, hipStream_t st);
+// Wavefunction optimisation: per walker [sum E_L, sum O (5), sum E_L O (5), sum O O^T (25)] of the
+// logarithmic derivatives O of the Jastrow parameters (b, b_1, f_11, f_12, f_22), and their means.
+constexpr int kOptStats = 36;
+hipError_t launch_opt_sample(const MeasureArgs& m, hipStream_t st);
+hipError_t launch_opt_reduce(int W, int M, const double* popt, double* out, hipStream_t st);
 hipError_t launch_j3_grad(const MeasureArgs& m, int mixed, hipStream_t st);
 hipError_t launch_j3_forces(const MeasureArgs& m, int mixed, hipStream_t st);
 

@@ -26,10 +26,10 @@ using vmc_host::build_kvectors;
 namespace {
 
 enum KClass { K_SETUP, K_BUILD_A, K_INVERT, K_REFINE, K_SWEEP, K_EWALD, K_SLATER, K_FINALIZE, K_REDUCE, K_SYRK,
-              K_LANGEVIN, K_TOY, K_CSWEEP, K_CSLATER, K_J3_INIT, K_J3_GRAD, K_J3_FORCES, K_NCLASS };
+              K_LANGEVIN, K_TOY, K_CSWEEP, K_CSLATER, K_J3_INIT, K_J3_GRAD, K_J3_FORCES, K_OPT, K_NCLASS };
 const char* kClassName[K_NCLASS] = {"proton_setup", "build_A", "invert", "refine", "sweep_half", "ewald_sample",
                                     "slater_sample", "finalize", "reduce", "syrk", "langevin", "toy",
-                                    "csweep", "cslater_sample", "j3_init", "j3_grad", "j3_forces"};
+                                    "csweep", "cslater_sample", "j3_init", "j3_grad", "j3_forces", "opt_sample"};
 
 struct Pending { int cls; hipEvent_t a, b; };
 // vmc_energy_forces keeps at most this many sweeps queued ahead of the device, so that
@@ -78,6 +78,10 @@ struct vmc_traj {
   // Langevin state owned by the trajectory (vmc_traj_set_R, vmc_traj_langevin_step)
   double *Rd = nullptr, *Rprev = nullptr, *Sd = nullptr, *Sprev = nullptr;
   double *j3G = nullptr, *j3scr = nullptr;   // the three-body term: G_a per walker, measurement scratch
+  // wavefunction-optimisation statistics (vmc_traj_set_param_stats): E_L per sample, per-walker sums
+  double *ELs = nullptr, *popt = nullptr;
+  bool param_stats = false, have_popt = false;
+  int popt_M = 0;
   size_t bytes = 0;               // device bytes (traj_bytes), counted against the context's budget
   uint32_t lang_step = 0;         // completed vmc_traj_langevin_step calls (the noise counter)
   bool have_R = false, have_prev = false, have_S = false;
@@ -174,6 +178,7 @@ int check_sys(const vmc_system* s) {
   if (!(s->box_L > 0.0) || !(s->ewald_kappa > 0.0) || s->ewald_nmax < 1 || s->ewald_nmax > 12) return VMC_EINVAL;
   if (s->precision != VMC_FP64 && s->precision != VMC_MIXED) return VMC_EINVAL;
   if (s->refine_tol != s->refine_tol) return VMC_EINVAL;
+  if (!(s->b >= 0.0) || !std::isfinite(s->b)) return VMC_EINVAL;
   if (!(s->j1_b1 >= 0.0) || !std::isfinite(s->j1_b1)) return VMC_EINVAL;
   if (s->twist < 0 || s->twist > 7) return VMC_EINVAL;
   if (s->general_twist != 0 && s->general_twist != 1) return VMC_EINVAL;
@@ -279,6 +284,8 @@ MeasureArgs measure_args(vmc_traj* t, const double* R, const double* C, const do
   m.j3 = has_j3(t->sys);
   for (int q = 0; q < 3; ++q) m.j3f[q] = t->sys.j3_f[q];
   m.j3scr = t->j3scr;
+  m.ELs = t->param_stats ? t->ELs : nullptr;
+  m.popt = t->popt;
   return m;
 }
 
@@ -313,6 +320,7 @@ int measure(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e) {
   RUN(K_EWALD, launch_ewald_sample(m, e, mixed, ctx->stream));
   RUN(K_SLATER, launch_slater_sample(m, mixed, ctx->stream));
   if (m.j3) RUN(K_J3_FORCES, launch_j3_forces(m, mixed, ctx->stream));
+  if (m.ELs) RUN(K_OPT, launch_opt_sample(m, ctx->stream));
   return VMC_OK;
 }
 int measure_c(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e, const TwistArgs& tw) {
@@ -333,7 +341,8 @@ size_t traj_bytes(const vmc_system& s, int W) {
                    Wz * n3 + Wz + Wz * (1 + 3 * n3) + Wz * n3 + reduce_partial_doubles(W, (int)n3) + 3 + n3 +
                    kv.size() + 2 * nk + nk * N * 2 + n3 + 1 + 2 * n3 + 2 * n3 * n3;
   const size_t j3 = has_j3(s) ? Wz * (2 * N + j3_measure_doubles((int)N)) : 0;
-  return (d + j3) * sizeof(double) + 2 * Wz * sizeof(int64_t) +
+  const size_t opt = Wz * (1 + kOptStats);
+  return (d + j3 + opt) * sizeof(double) + 2 * Wz * sizeof(int64_t) +
          (3 * Wz + 2 + slots.size() + nx0.size()) * sizeof(int) + Wz * meas_scratch_bytes(s);
 }
 
@@ -343,7 +352,7 @@ void free_traj(vmc_traj* t) {
   void* ptrs[] = {t->pos, t->Amat, t->Binv, t->ldet, t->sgn, t->acc, t->rho_acc, t->Vs, t->dVs, t->Uj,
                   t->means, t->f_w, t->partial, t->outv, t->nacc, t->kvec, t->rho_p, t->Ptab, t->Fconst,
                   t->Vpp, t->slot, t->slot_nx0, t->rflag, t->qflag, t->scr, t->pos_bak, t->nacc_bak,
-                  t->Rd, t->Rprev, t->Sd, t->Sprev, t->j3G, t->j3scr};
+                  t->Rd, t->Rprev, t->Sd, t->Sprev, t->j3G, t->j3scr, t->ELs, t->popt};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete t;
@@ -499,7 +508,8 @@ int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int W, uint32_t seed, u
             !dalloc(&t->Ptab, (size_t)t->nk * N * 2) && !dalloc(&t->Fconst, n3) && !dalloc(&t->Vpp, 1) &&
             !dalloc(&t->slot, slots.size()) && !dalloc(&t->slot_nx0, nx0.size()) &&
             !dalloc(&t->pos_bak, W * N * 3) && !dalloc(&t->nacc_bak, (size_t)W) && !dalloc(&t->Rd, n3) &&
-            !dalloc(&t->Rprev, n3) && !dalloc(&t->Sd, n3 * n3) && !dalloc(&t->Sprev, n3 * n3);
+            !dalloc(&t->Rprev, n3) && !dalloc(&t->Sd, n3 * n3) && !dalloc(&t->Sprev, n3 * n3) &&
+            !dalloc(&t->ELs, (size_t)W) && !dalloc(&t->popt, (size_t)W * kOptStats);
   const size_t scr = meas_scratch_bytes(*sys);
   if (ok && scr) ok = !dalloc(&t->scr, (size_t)W * scr);
   if (ok && has_j3(*sys))
@@ -698,6 +708,8 @@ int vmc_energy_forces(vmc_traj* t, const double* R_in, const double* C, const do
   HIPCHK(hipMemsetAsync(t->nacc, 0, W * sizeof(int64_t), st));
   HIPCHK(hipMemsetAsync(t->rflag, 0, W * 2 * sizeof(int), st));
   HIPCHK(hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
+  t->have_popt = false;
+  if (t->param_stats) HIPCHK(hipMemsetAsync(t->popt, 0, W * kOptStats * sizeof(double), st));
   WalkerArgs a = walker_args(t, R, C, zeta, nimg);
   MeasureArgs m = measure_args(t, R, C, zeta, nimg);
   EwaldArgs e = ewald_args(t);
@@ -764,6 +776,40 @@ int vmc_energy_forces(vmc_traj* t, const double* R_in, const double* C, const do
   HIPCHK(hipMemcpyAsync(out_dev, t->outv, (3 + n3) * sizeof(double), hipMemcpyDeviceToDevice, st));
   t->have_means = true;
   t->have_S = false;
+  t->have_popt = t->param_stats;
+  t->popt_M = n_sweeps;
+  return VMC_OK;
+}
+
+int vmc_traj_set_param_stats(vmc_traj* t, int on) {
+  if (!t || (on != 0 && on != 1) || (on && is_complex(t->sys))) return VMC_EINVAL;
+  t->param_stats = on == 1;
+  t->have_popt = false;
+  return VMC_OK;
+}
+
+int vmc_traj_param_stats(vmc_traj* t, double* stats_dev) {
+  if (!t || !stats_dev || !t->have_popt) return VMC_EINVAL;
+  HIPCHK(hipSetDevice(t->ctx->device));
+  vmc_ctx* ctx = t->ctx;
+  RUN(K_REDUCE, launch_opt_reduce(t->W, t->popt_M, t->popt, stats_dev, ctx->stream));
+  return VMC_OK;
+}
+
+int vmc_traj_set_jastrow(vmc_traj* t, double b, double j1_b1, const double* j3_f) {
+  if (!t || !j3_f) return VMC_EINVAL;
+  vmc_system s = t->sys;
+  s.b = b;
+  s.j1_b1 = j1_b1;
+  for (int q = 0; q < 3; ++q) s.j3_f[q] = j3_f[q];
+  if (check_sys(&s)) return VMC_EINVAL;
+  // the one-body term stays on or off; the three-body term may change freely only where its
+  // per-walker memory exists (it was on at creation)
+  if ((j1_b1 > 0.0) != (t->sys.j1_b1 > 0.0)) return VMC_EINVAL;
+  if (has_j3(s) && !t->j3G) return VMC_EINVAL;
+  t->sys = s;
+  t->have_means = false;
+  t->have_popt = false;
   return VMC_OK;
 }
 

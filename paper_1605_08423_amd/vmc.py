@@ -29,7 +29,8 @@ EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_
             "vmc_twist_average", "vmc_traj_save", "vmc_traj_load", "vmc_traj_load_rescaled", "vmc_traj_walkers_reset",
             "vmc_set_hbm_budget", "vmc_hbm_in_use", "vmc_traj_bytes", "vmc_cancel", "vmc_traj_set_R", "vmc_traj_get_R",
             "vmc_traj_step_count", "vmc_traj_langevin_step", "vmc_langevin_step_noalloc", "vmc_huckel_params_theta",
-            "vmc_huckel_params_contracted"]
+            "vmc_huckel_params_contracted", "vmc_traj_set_param_stats", "vmc_traj_param_stats",
+            "vmc_traj_set_jastrow", "vmc_sr_update"]
 VMC_REQ_QUEUED, VMC_REQ_RUNNING, VMC_REQ_DONE, VMC_REQ_FAILED, VMC_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
@@ -99,6 +100,10 @@ def _declare(l):
     l.vmc_huckel_params_twist.argtypes = [i, d, i, P(d), P(d), P(d)]
     l.vmc_huckel_params_theta.argtypes = [i, d, P(d), P(d), P(d), P(d)]
     l.vmc_huckel_params_contracted.argtypes = [i, d, d, P(d), P(d)]
+    l.vmc_traj_set_param_stats.argtypes = [vp, i]
+    l.vmc_traj_param_stats.argtypes = [vp, vp]
+    l.vmc_traj_set_jastrow.argtypes = [vp, d, d, P(d)]
+    l.vmc_sr_update.argtypes = [P(d), i, d, d, P(d)]
     l.vmc_twist_average.argtypes = [vp, i, i, vp, vp, vp, vp]
     l.vmc_traj_save.argtypes = [vp, vp, P(C.c_size_t)]
     l.vmc_traj_walkers_reset.argtypes = [vp, P(i)]
@@ -246,6 +251,22 @@ class Trajectory:
         out = torch.empty(self.W, dtype=torch.int64, device="cuda")
         _check(_lib().vmc_traj_accepts(self.h, C.c_void_p(out.data_ptr())), "vmc_traj_accepts")
         return out
+
+    def set_param_stats(self, on=True):
+        """Accumulate the Jastrow parameters' logarithmic derivatives in later energy_forces calls."""
+        _check(_lib().vmc_traj_set_param_stats(self.h, int(bool(on))), "vmc_traj_set_param_stats")
+
+    def param_stats(self):
+        """[E, <O> (5), <E_L O> (5), <O O^T> (25)] of the last energy_forces call (device tensor)."""
+        import torch
+        out = torch.empty(36, dtype=torch.float64, device="cuda")
+        _check(_lib().vmc_traj_param_stats(self.h, C.c_void_p(out.data_ptr())), "vmc_traj_param_stats")
+        return out
+
+    def set_jastrow(self, b, b1, j3):
+        """New Jastrow parameters (Pade b, one-body b_1, three-body (f11, f12, f22)) for later calls."""
+        _check(_lib().vmc_traj_set_jastrow(self.h, float(b), float(b1), (C.c_double * 3)(*j3)),
+               "vmc_traj_set_jastrow")
 
     def build_S(self, S=None, keep_only=False):
         """S of the last estimate; keep_only: leave it on the device in the trajectory only."""
@@ -411,6 +432,18 @@ def vmc_huckel_params(R, zeta, L, twist=0):
         _check(_lib().vmc_huckel_params_twist(n, float(L), int(twist), R.ctypes.data_as(P), zeta.ctypes.data_as(P),
                                               Cm.ctypes.data_as(P)), "vmc_huckel_params_twist")
     return Cm
+
+
+def vmc_sr_update(stats, active, eps, tau):
+    """Host helper: one stochastic-reconfiguration step dp (numpy, 5) from the 36 means of
+    Trajectory.param_stats (a tensor or an array)."""
+    import numpy as np
+    st = np.ascontiguousarray(stats.cpu().numpy() if hasattr(stats, "cpu") else stats, dtype=np.float64)
+    dp = np.zeros(5)
+    P = C.POINTER(C.c_double)
+    _check(_lib().vmc_sr_update(st.ctypes.data_as(P), int(active), float(eps), float(tau), dp.ctypes.data_as(P)),
+           "vmc_sr_update")
+    return dp
 
 
 def vmc_huckel_params_contracted(R, L, eta):
