@@ -82,6 +82,12 @@ def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, on
         move = N * 93 + 8 * N * NS + 8 * NS + 30 * (N - 1) + acc * 16 * NS * NS
         refresh = NS * N * 93 + 8 * NS * N * NS + 8 * NS ** 3
         return {"f64": NS * move + refresh / CREFRESH}
+    if cls == "opt_sample":
+        # per sample: the two-body derivative over the N(N-1)/2 electron pairs (periodised
+        # distance 18, sqrt, the Pade derivative 6), the one-body derivative over the N^2
+        # electron-proton pairs (distance 18, exp, 6), the three-body sums per proton (distance 15,
+        # exp, 8) in the working precision of the Jastrow terms, and the 36 moments in FP64
+        return _add({"f64": 72}, lo, N * (N - 1) // 2 * 25 + (N * N * 25 if one_body else 0) + N * N * 24)
     if cls == "j3_init":
         # G_a = sum_i chi_a(r_i) of every nucleus: per (electron, nucleus) pair the squared
         # periodised distance (15), an exp and two sums
@@ -615,6 +621,70 @@ def kernel_space(sysd, wl, prec_mixed: bool):
     return nk, nslot, nimg
 
 
+def run_opt_leg(wl, W: int, M: int, prec: int, b1: float, F, n_opt: int, m_opt: int, steps: int, mask: int = 0b11101,
+                eps: float = 0.1, tau: float = 0.1) -> dict:
+    """Langevin steps with the wavefunction re-optimised before each (the paper's n_opt steps of
+    optimisation per ionic step): n_opt stochastic-reconfiguration iterations, each m_opt measured
+    sweeps (+5 re-equilibration) with the parameter statistics, the SR step on the parameters in
+    `mask` (bits: b, b_1, f11, f12, f22) and the new parameters, then the energy/force estimate, S
+    and the update as in run_leg.  The first step is the warm-up; `steps` are timed."""
+    import torch
+    from paper_1605_08423_amd import vmc
+    ctx = vmc.Context(0)
+    p = np.array([1.0, b1, *F], dtype=np.float64)
+    sysd = vmc.make_system(wl.n, wl.L, precision=prec, b=p[0], b1=p[1], j3=tuple(p[2:]))
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    traj = vmc.Trajectory(ctx, sysd, W, seed=wl.seed, traj_id=0)
+    traj.set_walkers(dev(wl.electrons(W=W)))
+    traj.set_R(dev(wl.R.reshape(-1)))
+    zeta = dev(wl.zeta)
+    alpha = 0.122 * W * M
+    Delta = 1.0 / alpha
+    path, energies, sr_s = [p.copy()], [], []
+
+    def one_step(k):
+        nonlocal p
+        Cm = dev(vmc.vmc_huckel_params(traj.get_R().cpu().numpy(), wl.zeta, wl.L))
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        traj.set_param_stats(True)
+        for i in range(n_opt):
+            # optimisation sweeps draw from counters of their own, apart from the trajectory's
+            traj.energy_forces(None, Cm, zeta, 20 if k == 0 and i == 0 else 5, m_opt, wl.delta,
+                               step=0x80000000 | (k << 8) | i)
+            st = traj.param_stats()
+            energies.append(float(st[0].item()))
+            dp = vmc.vmc_sr_update(st, mask, eps, tau)
+            p = p + dp
+            traj.set_jastrow(p[0], p[1], tuple(p[2:]))
+            path.append(p.copy())
+        traj.set_param_stats(False)
+        sr_s.append(time.perf_counter() - ts)
+        out = traj.energy_forces(None, Cm, zeta, 5, M, wl.delta, step=None)
+        traj.build_S(keep_only=True)
+        rc = traj.langevin_step(wl.T_hartree, Delta, alpha)
+        if rc != 0:
+            raise RuntimeError(f"langevin step failed: {vmc._lib().vmc_strerror(rc).decode()}")
+        return out
+
+    one_step(0)
+    torch.cuda.synchronize()
+    ctx.reset_kernel_times()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for k in range(1, 1 + steps):
+        out = one_step(k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    times = ctx.kernel_times()
+    ctx.set_profiling(False)
+    out_h = out.cpu().numpy()
+    traj.close()
+    ctx.close()
+    return {"elapsed": elapsed, "steps": steps, "times": times, "out": out_h, "path": path, "sr_E": energies,
+            "sweeps_per_step": n_opt * (m_opt + 5) + M + 5, "sr_s": sum(sr_s[1:]) / max(steps * n_opt, 1)}
+
+
 def run_leg(wl, W: int, M: int, prec: int, b1: float, steps: int, warmup: int, log=None, eta=None, j3=None) -> dict:
     """Langevin steps of one trajectory, each one full pass of the hot path: Hueckel orbitals and
     proton tables at R, the energy/force estimate (20 equilibration sweeps at the first step, 5
@@ -696,6 +766,9 @@ def main():
                     help="eta of the short contracted-basis leg of the default line (nan: skip)")
     ap.add_argument("--j3", type=_f3, default=None, metavar="F11,F12,F22",
                     help="add the on-site three-body Jastrow term with this symmetric F")
+    ap.add_argument("--opt-leg", type=int, default=4, metavar="N_OPT",
+                    help="SR iterations per ionic step of the short wavefunction-optimisation leg of the default "
+                         "line (10 sweeps each; b_1 = 2.5 and the three-body leg's F to start; 0: skip)")
     ap.add_argument("--three-body-leg", type=_f3, default=J3_LEG_F, metavar="F11,F12,F22",
                     help="F of the short three-body leg of the default line (run with b_1 = 2.5; 'none': skip)")
     ap.add_argument("--fp64-steps", type=int, default=2,
@@ -856,6 +929,28 @@ def main():
                       "sigma_E_Ha": float(r["out"][1]), "acceptance": round(acc3, 4), "kernels": per,
                       "kernel_ms": {k: round(v[0], 2) for k, v in kms.items()}}
 
+    optimisation = None
+    if args.opt_leg > 0 and args.j3 is None and args.eta is None and args.workload == "h128":
+        F0 = args.three_body_leg or J3_LEG_F
+        b1 = args.j1 if args.j1 > 0 else 2.5
+        r = run_opt_leg(wl, W, M, prec, b1, F0, args.opt_leg, 10, 2)
+        kms = {k: v for k, v in r["times"].items() if v[1]}
+        per = {}
+        if "opt_sample" in kms:
+            avg_s = kms["opt_sample"][0] / kms["opt_sample"][1] / 1e3
+            _, achieved, peak = roofline_numbers(work_model("opt_sample", N, nk, nslot, nimg, mixed, True), W, avg_s)
+            per = {"avg_launch_ms": round(avg_s * 1e3, 4), "achieved": round(achieved, 3), "peak": round(peak, 2),
+                   "unit": "TFLOP/s", "frac": round(achieved / peak, 4) if peak else None}
+        ms_step = 1e3 * r["elapsed"] / r["steps"]
+        optimisation = {"n_opt": args.opt_leg, "sweeps_per_sr_step": 10, "b1": b1, "F0": list(F0),
+                        "active": "b, f11, f12, f22", "eps": 0.1, "tau": 0.1, "steps": r["steps"], "warmup": 1,
+                        "ms_per_ionic_step": round(ms_step, 2),
+                        "ms_per_sr_iteration": round(1e3 * r["sr_s"], 2),
+                        "walker_sweeps_per_s": round(W * r["sweeps_per_step"] * r["steps"] / r["elapsed"], 1),
+                        "E_Ha": float(r["out"][0]), "sr_E_Ha": [round(e, 4) for e in r["sr_E"]],
+                        "params_b_b1_F": [round(float(v), 4) for v in r["path"][-1]], "opt_sample": per,
+                        "kernel_ms": {k: round(v[0], 2) for k, v in kms.items()}}
+
     mesh = None
     if args.mesh_leg > 0 and args.workload == "h128":
         mesh = twist_mesh_leg("h128", args.mesh_leg, args.mesh_walkers, 10, 1, 1)
@@ -893,7 +988,8 @@ def main():
         "step_latency_ms": {"p50": round(lead["p50"], 1), "p99": round(lead["p99"], 1)},
         "E_Ha": float(out_h[0]), "sigma_E_Ha": float(out_h[1]), "acceptance": acc,
         "roofline": roofline, "fp64_gpu": fp64, "served": served, "twist_mesh": mesh,
-        "contracted_basis": contracted, "three_body": three_body, "cpu_baseline": cpu,
+        "contracted_basis": contracted, "three_body": three_body, "optimisation": optimisation,
+        "cpu_baseline": cpu,
         "kernel_ms": {k: round(v[0], 2) for k, v in times.items()},
     }
     print(json.dumps(line))

@@ -10,7 +10,7 @@
 //        proton, O_11 = 1/2 sum_a (G_1^2 - T_11), O_12 = sum_a (G_1 G_2 - T_12),
 //        O_22 = 1/2 sum_a (G_2^2 - T_22)  (the pair sums sum_{i<j}, for any F).
 // k_opt_sample adds [E_L, O (5), E_L O (5), O O^T (25)] of every measured sample to its walker's
-// sums; k_opt_reduce forms the means over walkers and samples in a fixed order.  FP64 throughout.
+// sums; k_opt_reduce forms the means over walkers and samples in a fixed order.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -22,83 +22,92 @@ inline int opt_threads(int N) { return ((N + 63) / 64) * 64; }
 
 }  // namespace
 
-// One block per walker; thread i takes electron i (its pairs with every other electron, halved,
-// and with every proton) and proton i (the three-body sums over the electrons).
+// One block per walker.  Thread i takes electron i: its pairs with the electrons i + 1 .. i + N/2
+// (cyclically; the pair at distance N/2 only from its lower electron, so every pair is taken once
+// and the threads share the pairs evenly) and with every proton; and proton i: the three-body
+// sums over the electrons.  The terms are evaluated in the working precision of the Jastrow terms
+// (FP32 in mixed precision) and summed over the block, and accumulated, in FP64.
+template <class Real>
 __global__ __launch_bounds__(256) void k_opt_sample(MeasureArgs m) {
-  extern __shared__ __align__(16) double sm[];
+  extern __shared__ __align__(16) unsigned char smraw[];
+  Real* te = reinterpret_cast<Real*>(smraw);   // N x 6: electrons' sin x3, cos x3 of pi x / L
+  Real* ta = te + 6 * m.N;                     // N x 6: protons
   const int N = m.N, NS = m.NS, w = blockIdx.x, t = threadIdx.x, T = blockDim.x;
-  double* te = sm;            // N x 6: electrons' sin x3, cos x3 of pi x / L
-  double* ta = sm + 6 * N;    // N x 6: protons
   __shared__ double red[4][5];
   __shared__ double Ob[5];
   const double* pos = m.pos + (size_t)w * 3 * N;
   for (int u = t; u < 3 * N; u += T) {
     const int i = u / 3, c = u % 3;
-    sincospi(pos[u] * m.invL, &te[6 * i + c], &te[6 * i + 3 + c]);
-    sincospi(m.R[u] * m.invL, &ta[6 * i + c], &ta[6 * i + 3 + c]);
+    dev_sincospi<Real>((Real)(pos[u] * m.invL), &te[6 * i + c], &te[6 * i + 3 + c]);
+    dev_sincospi<Real>((Real)(m.R[u] * m.invL), &ta[6 * i + c], &ta[6 * i + 3 + c]);
   }
   __syncthreads();
-  const double LoP = m.L / VMC_PI;
-  double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const Real LoP = (Real)(m.L / VMC_PI), bb = (Real)m.b, ap = (Real)m.a_par, aa = (Real)m.a_anti;
+  Real o[5] = {Real(0), Real(0), Real(0), Real(0), Real(0)};
+  const int half = N / 2;
   for (int i = t; i < N; i += T) {
-    const double* si = te + 6 * i;
-    // two-body: every other electron, half of each pair to each of its electrons
-    for (int j = 0; j < N; ++j) {
-      if (j == i) continue;
-      const double* sj = te + 6 * j;
-      double r2 = 0.0;
+    const Real* si = te + 6 * i;
+    // two-body
+    const int dmax = i < half ? half : half - 1;
+    for (int d = 1; d <= dmax; ++d) {
+      const int j = i + d < N ? i + d : i + d - N;
+      const Real* sj = te + 6 * j;
+      Real r2 = Real(0);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double rt = LoP * (si[c] * sj[3 + c] - si[3 + c] * sj[c]);
+        const Real rt = LoP * (si[c] * sj[3 + c] - si[3 + c] * sj[c]);
         r2 += rt * rt;
       }
-      const double rho = sqrt(r2), a = ((i < NS) == (j < NS)) ? m.a_par : m.a_anti;
-      const double den = 1.0 + m.b * rho;
-      o[0] += -0.5 * a * r2 / (den * den);
+      const Real a = ((i < NS) == (j < NS)) ? ap : aa, den = Real(1) + bb * sqrt(r2);
+      o[0] -= a * r2 / (den * den);
     }
-    // one-body
+    // one-body: d/db_1 of -(1 - e^{-beta rho}) / beta with beta = 2^{1/4} b_1
     if (m.j1_beta > 0.0) {
-      const double beta = m.j1_beta, q = 1.189207115002721;   // 2^{1/4} = d beta / d b_1
+      const Real beta = (Real)m.j1_beta, ib = (Real)(1.0 / m.j1_beta), q = (Real)1.189207115002721;
+      Real s1 = Real(0);
       for (int c = 0; c < N; ++c) {
-        const double* sa = ta + 6 * c;
-        double r2 = 0.0;
+        const Real* sa = ta + 6 * c;
+        Real r2 = Real(0);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          const double rt = LoP * (si[d] * sa[3 + d] - si[3 + d] * sa[d]);
+          const Real rt = LoP * (si[d] * sa[3 + d] - si[3 + d] * sa[d]);
           r2 += rt * rt;
         }
-        const double rho = sqrt(r2), e = exp(-beta * rho);
-        o[1] += q * ((1.0 - e) / (beta * beta) - rho * e / beta);
+        const Real rho = sqrt(r2), e = dev_exp<Real>(-beta * rho);
+        s1 += ((Real(1) - e) * ib - rho * e) * ib;
       }
+      o[1] += q * s1;
     }
   }
   // three-body: per proton the sums over the electrons
+  const Real Z = (Real)kZJ;
   for (int c = t; c < N; c += T) {
-    const double* sa = ta + 6 * c;
-    double g1 = 0.0, g2 = 0.0, t11 = 0.0, t12 = 0.0, t22 = 0.0;
+    const Real* sa = ta + 6 * c;
+    Real g1 = Real(0), g2 = Real(0), t11 = Real(0), t12 = Real(0), t22 = Real(0);
     for (int i = 0; i < N; ++i) {
-      const double* si = te + 6 * i;
-      double u = 0.0;
+      const Real* si = te + 6 * i;
+      Real u = Real(0);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const double rt = LoP * (si[d] * sa[3 + d] - si[3 + d] * sa[d]);
+        const Real rt = LoP * (si[d] * sa[3 + d] - si[3 + d] * sa[d]);
         u += rt * rt;
       }
-      const double v1 = exp(-kZJ * u), v2 = u * v1;
+      const Real v1 = dev_exp<Real>(-Z * u), v2 = u * v1;
       g1 += v1;
       g2 += v2;
       t11 += v1 * v1;
       t12 += v1 * v2;
       t22 += v2 * v2;
     }
-    o[2] += 0.5 * (g1 * g1 - t11);
-    o[3] += g1 * g2 - t12;
-    o[4] += 0.5 * (g2 * g2 - t22);
+    const double G1 = (double)g1, G2 = (double)g2;
+    o[2] += (Real)(0.5 * (G1 * G1 - (double)t11));
+    o[3] += (Real)(G1 * G2 - (double)t12);
+    o[4] += (Real)(0.5 * (G2 * G2 - (double)t22));
   }
-  // fixed-order block sums
+  // fixed-order block sums in FP64
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const double v = wave_allsum(o[k]);
+    const double v = wave_allsum((double)o[k]);
     if ((t & 63) == 0) red[t >> 6][k] = v;
   }
   __syncthreads();
@@ -131,9 +140,14 @@ __global__ __launch_bounds__(256) void k_opt_reduce(int W, double inv_samples, c
   if (t == 0) out[q] = (((red[0] + red[1]) + red[2]) + red[3]) * inv_samples;
 }
 
-hipError_t launch_opt_sample(const MeasureArgs& m, hipStream_t st) {
-  if (m.W < 1 || m.N < 2 || m.N > 256 || !m.popt || !m.ELs) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_opt_sample, dim3(m.W), dim3(opt_threads(m.N)), (size_t)12 * m.N * sizeof(double), st, m);
+hipError_t launch_opt_sample(const MeasureArgs& m, int mixed, hipStream_t st) {
+  if (m.W < 1 || m.N < 2 || (m.N & 1) || m.N > 256 || !m.popt || !m.ELs) return hipErrorInvalidValue;
+  if (mixed)
+    hipLaunchKernelGGL(k_opt_sample<float>, dim3(m.W), dim3(opt_threads(m.N)), (size_t)12 * m.N * sizeof(float), st,
+                       m);
+  else
+    hipLaunchKernelGGL(k_opt_sample<double>, dim3(m.W), dim3(opt_threads(m.N)), (size_t)12 * m.N * sizeof(double),
+                       st, m);
   return hipGetLastError();
 }
 

@@ -167,7 +167,7 @@ hipError_t launch_j3_init(const WalkerArgs& a, hipStream_t st);
 // Wavefunction optimisation: per walker [sum E_L, sum O (5), sum E_L O (5), sum O O^T (25)] of the
 // logarithmic derivatives O of the Jastrow parameters (b, b_1, f_11, f_12, f_22), and their means.
 constexpr int kOptStats = 36;
-hipError_t launch_opt_sample(const MeasureArgs& m, hipStream_t st);
+hipError_t launch_opt_sample(const MeasureArgs& m, int mixed, hipStream_t st);
 hipError_t launch_opt_reduce(int W, int M, const double* popt, double* out, hipStream_t st);
 hipError_t launch_j3_grad(const MeasureArgs& m, int mixed, hipStream_t st);
 hipError_t launch_j3_forces(const MeasureArgs& m, int mixed, hipStream_t st);

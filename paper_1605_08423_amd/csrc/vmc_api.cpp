@@ -320,7 +320,7 @@ int measure(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e) {
   RUN(K_EWALD, launch_ewald_sample(m, e, mixed, ctx->stream));
   RUN(K_SLATER, launch_slater_sample(m, mixed, ctx->stream));
   if (m.j3) RUN(K_J3_FORCES, launch_j3_forces(m, mixed, ctx->stream));
-  if (m.ELs) RUN(K_OPT, launch_opt_sample(m, ctx->stream));
+  if (m.ELs) RUN(K_OPT, launch_opt_sample(m, mixed, ctx->stream));
   return VMC_OK;
 }
 int measure_c(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e, const TwistArgs& tw) {

@@ -98,3 +98,15 @@ def test_three_body_work_model_and_arguments():
         bench._f3("1,2")
     assert bench.traffic_workload_key("h128", "mixed", 16, 2.5, None, (-0.2, 0.0, 0.05)) == \
         "h128 mixed, W=16, b1=2.5, F3=-0.2,0,0.05"
+
+
+def test_optimisation_work_model():
+    """The SR statistics kernel's count: the two-body pairs once each, the one-body pairs only with
+    the term, the three-body sums always, in the working precision; the moments in FP64."""
+    sys.path.insert(0, ROOT)
+    import bench
+    N = 128
+    a = bench.work_model("opt_sample", N, 0, 0, 1, True, one_body=True)
+    b = bench.work_model("opt_sample", N, 0, 0, 1, False, one_body=False)
+    assert a == {"f64": 72, "f32": N * (N - 1) // 2 * 25 + N * N * 25 + N * N * 24}
+    assert b == {"f64": N * (N - 1) // 2 * 25 + N * N * 24 + 72}

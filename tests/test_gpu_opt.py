@@ -73,7 +73,8 @@ def test_param_stats_chain_fp64(oracle, dev, name, W, ne, ns, b1, j3):
 @pytest.mark.parametrize("name,W,ne,ns", [("h16", 64, 4, 8), ("h54", 64, 2, 3)])
 def test_param_stats_chain_mixed(oracle, dev, name, W, ne, ns):
     """Mixed precision on the same Philox stream: with no flipped decision the positions are the
-    oracle's, so the O moments agree to FP64 rounding and the E_L moments to the mixed bars."""
+    oracle's; the O terms are then FP32 (summed in FP64) and the moments agree within the mixed
+    bar of the proton derivatives (2e-5), the E_L moments within 1e-5."""
     say(f"[opt stats mixed] {name} W={W}")
     st, ref, flips = _run(oracle, dev, name, W, ne, ns, 1, 2.5, F3, seed=5, traj=1, step=0)
     o_only = [1, 2, 3, 4, 5] + list(range(11, 36))
@@ -84,7 +85,7 @@ def test_param_stats_chain_mixed(oracle, dev, name, W, ne, ns):
     # through the SR loop below
     assert flips <= W // 8
     if flips == 0:
-        assert elem(st[o_only], ref[o_only]) < 1e-10
+        assert elem(st[o_only], ref[o_only]) < 2e-5
         assert elem(st[e_part], ref[e_part]) < 1e-5
 
 
