@@ -113,9 +113,9 @@ typedef struct {
                          with chi_1 = e^{-ZJ rho^2}, chi_2 = rho^2 e^{-ZJ rho^2}, ZJ = 0.7933844, on
                          the sin-periodised offset rho between electron and nucleus, and
                          F = [[f11, f12], [f12, f22]] = [[j3_f[0], j3_f[1]], [j3_f[1], j3_f[2]]] the same
-                         for every nucleus.  All zero: no term.  The term requires twist = 0,
-                         general_twist = 0, contracted = 0 and N_sigma <= 64, and is not for the
-                         server (else VMC_EINVAL); its orbitals are evaluated in the precision of
+                         for every nucleus.  All zero: no term.  The term requires general_twist = 0
+                         and N_sigma <= 64 (it combines with the real twists, the contracted basis and
+                         the one-body term), and is not for the server (else VMC_EINVAL); its orbitals are evaluated in the precision of
                          the Jastrow terms (FP32 in VMC_MIXED), their per-nucleus sums combined and
                          accumulated in FP64 */
 } vmc_system;

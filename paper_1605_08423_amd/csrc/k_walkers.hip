@@ -1490,20 +1490,37 @@ hipError_t launch_sweep_tw(const WalkerArgs& a, const SweepArgs& s, hipStream_t 
 template <int NS, class Real>
 hipError_t launch_sweep_t(const WalkerArgs& a, const SweepArgs& s, hipStream_t st, const Batch* bt, int nblk) {
   if (a.j3) {
-    // the three-body term: single trajectories, single Gaussians, no twist, N_sigma <= 64
+    // the three-body term: single trajectories, N_sigma <= 64, with the single Gaussian (real twists
+    // allowed) or the contracted orbital (no twist)
     if constexpr (NS > 64) {
       return hipErrorInvalidValue;
     } else {
-      if (bt || a.twist || a.contracted || !a.j3G) return hipErrorInvalidValue;
+      if (bt || (a.twist && a.contracted) || !a.j3G) return hipErrorInvalidValue;
       const size_t tab = one_body_table_bytes<Real>(2 * NS, SweepLds<NS>::NSP);
       const size_t sm = sweep_smem<NS, Real>() + tab;
       dim3 grid((a.W + 3) / 4);
-      if (a.nimg || sizeof(Real) == 8)
+      const bool img = a.nimg || sizeof(Real) == 8;
+      if (a.contracted) {
+        if (img)
+          hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, false, false, true, true>), grid, dim3(256), sm, st, a, s,
+                             batch_or_none(bt));
+        else
+          hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, false, false, true, true>), grid, dim3(256), sm, st, a, s,
+                             batch_or_none(bt));
+      } else if (a.twist) {
+        if (img)
+          hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, false, true, false, true>), grid, dim3(256), sm, st, a, s,
+                             batch_or_none(bt));
+        else
+          hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, false, true, false, true>), grid, dim3(256), sm, st, a, s,
+                             batch_or_none(bt));
+      } else if (img) {
         hipLaunchKernelGGL((k_sweep_half<NS, Real, 1, false, false, false, true>), grid, dim3(256), sm, st, a, s,
                            batch_or_none(bt));
-      else
+      } else {
         hipLaunchKernelGGL((k_sweep_half<NS, Real, 0, false, false, false, true>), grid, dim3(256), sm, st, a, s,
                            batch_or_none(bt));
+      }
       return hipGetLastError();
     }
   }

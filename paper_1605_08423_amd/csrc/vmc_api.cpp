@@ -190,7 +190,7 @@ int check_sys(const vmc_system* s) {
   if (s->contracted != 0 && s->contracted != 1) return VMC_EINVAL;
   for (int m = 0; m < 3; ++m)
     if (!std::isfinite(s->j3_f[m])) return VMC_EINVAL;
-  if (has_j3(*s) && (s->twist != 0 || s->general_twist || s->contracted || s->n_protons / 2 > 64)) return VMC_EINVAL;
+  if (has_j3(*s) && (s->general_twist || s->n_protons / 2 > 64)) return VMC_EINVAL;
   if (s->contracted) {
     // the images |n| <= 1 of the diffuse r^2 e^{-Z2 r^2} reach FP64 resolution only if Z2 (1.5 L)^2 >= 36
     const double h = 1.5 * s->box_L;

@@ -129,11 +129,93 @@ def test_j3_chain_mixed_same_seed(oracle, dev, name, W, ne, ns):
 def test_j3_system_validation(dev):
     torch, vmc, ctx = dev
     wl = workload("h16")
-    bad = [vmc.make_system(wl.n, wl.L, j3=F3, twist=1),
-           vmc.make_system(wl.n, wl.L, j3=F3, theta=(0.1, 0.2, 0.3)),
+    bad = [vmc.make_system(wl.n, wl.L, j3=F3, theta=(0.1, 0.2, 0.3)),
            vmc.make_system(256, 14.0, j3=F3),
            vmc.make_system(wl.n, wl.L, j3=(0.1, float("inf"), 0.0))]
     for sysd in bad:
         with pytest.raises(vmc.VMCError) as ei:
             vmc.Trajectory(ctx, sysd, 4)
         assert ei.value.code == vmc.VMC_EINVAL
+
+
+ETA = 0.1
+
+
+def _variant(oracle, name, kind, b1):
+    """Workload, orbitals and oracle-system keywords of the three-body term combined with the
+    contracted basis (kind 'eta') or a real twist (kind 'twN')."""
+    if kind == "eta":
+        wl = workload(name) if name in ("h54", "h128") else small_system(16, 1.9, seed=21)
+        Cm, _ = oracle.huckel_contracted(wl.R, wl.L, wl.n // 2, ETA)
+        return wl, Cm, dict(eta=ETA), dict(eta=ETA)
+    tw = int(kind[2:])
+    wl = _wl(name)
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2, twist=tw)
+    return wl, Cm, dict(twist=tw), dict(twist=tw)
+
+
+@pytest.mark.parametrize("name,kind,K,prec,b1", [("h16", "eta", 8, 0, 2.5), ("h54", "eta", 4, 0, 0.0),
+                                                 ("h16", "tw5", 8, 0, 2.5), ("h54", "tw3", 4, 0, 0.0),
+                                                 ("h54", "eta", 6, 1, 2.5), ("h54", "tw6", 6, 1, 2.5)])
+def test_j3_with_contracted_basis_and_twists(oracle, dev, name, kind, K, prec, b1):
+    """FP64: the bar 1e-10.  Mixed: the FP32 error at a configuration is mostly the base path's (its
+    Slater matrix's conditioning), so the base path without b_1 and the term is evaluated on the
+    same configurations, and each quantity must stay within the mixed bar or within 1.5 times the
+    base path's own error at that configuration."""
+    torch, vmc, ctx = dev
+    wl, Cm, skw, okw = _variant(oracle, name, kind, b1)
+    say(f"[three-body + {kind}] {name} K={K} {'mixed' if prec else 'fp64'} b1={b1}")
+    pos = wl.electrons(W=K, seed_offset=4)
+    n3 = 3 * wl.n
+
+    def errors(b1_, j3_):
+        sysd = vmc.make_system(wl.n, wl.L, precision=prec, b1=b1_, j3=j3_, **skw)
+        g = vmc.vmc_eval_configs(ctx, sysd, _T(torch, wl.R.reshape(-1)), _T(torch, Cm), _T(torch, wl.zeta),
+                                 _T(torch, pos)).cpu().numpy()
+        s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1_, j3=j3_, **okw)
+        err = {}
+        for k in range(K):
+            r = s.local(pos[k])
+            for q, a, b in [("lnpsi", g[k, 0], r["lnpsi"]), ("EL", g[k, 1], r["EL"]),
+                            ("dlnpsi", g[k, 2:2 + n3], r["dlnpsi"]), ("dEL", g[k, 2 + n3:], r["dEL"])]:
+                err[q, k] = rel(a, b) if q in ("lnpsi", "EL") else elem(a, b)
+        return err
+
+    err = errors(b1, F3)
+    worst = {q: max(v for (qq, _), v in err.items() if qq == q) for q in ("lnpsi", "EL", "dlnpsi", "dEL")}
+    say("  worst errors", worst)
+    if prec == 0:
+        for q, v in worst.items():
+            assert v < TOL64, (q, v)
+        return
+    base = errors(0.0, None)
+    say("  base path's worst errors", {q: max(v for (qq, _), v in base.items() if qq == q)
+                                      for q in ("lnpsi", "EL", "dlnpsi", "dEL")})
+    for (q, k), v in err.items():
+        assert v < TOLM[q] or v < 1.5 * base[q, k], (q, k, v, base[q, k])
+
+
+@pytest.mark.parametrize("name,kind,W,ne,ns", [("h16", "eta", 16, 2, 3), ("h16", "tw6", 16, 2, 3),
+                                               ("h54", "eta", 4, 1, 2)])
+def test_j3_chain_fp64_with_contracted_basis_and_twists(oracle, dev, name, kind, W, ne, ns):
+    torch, vmc, ctx = dev
+    wl, Cm, skw, okw = _variant(oracle, name, kind, 2.5)
+    say(f"[three-body chain fp64 + {kind}] {name} W={W}")
+    pos = wl.electrons(W=W, seed_offset=7)
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, b1=2.5, j3=F3, **skw), W, seed=11, traj_id=3)
+    tr.set_walkers(_T(torch, pos))
+    out = tr.energy_forces(_T(torch, wl.R.reshape(-1)), _T(torch, Cm), _T(torch, wl.zeta), ne, ns, wl.delta,
+                           2).cpu().numpy()
+    means, acc, posg = tr.walker_means().cpu().numpy(), tr.accepts().cpu().numpy(), tr.get_walkers().cpu().numpy()
+    tr.close()
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=2.5, j3=F3, **okw)
+    xo = pos.copy()
+    sums, nacc = s.vmc_run(xo, ne, ns, wl.delta, seed=11, traj=3, step=2)
+    red = oracle.reduce(sums, ns)
+    flips = int(np.sum(acc != nacc))
+    worst = max(elem(means[w], red["means"][w]) for w in range(W))
+    say("  walkers with a flipped decision:", flips, f" worst walker element-wise error of the means {worst:.3e}")
+    assert flips == 0
+    assert rel(posg, xo) < 1e-12
+    assert worst < TOL64
+    assert rel(out[0], red["E"]) < TOL64 and elem(out[3:], red["f"]) < TOL64
