@@ -260,9 +260,11 @@ int vmc_sr_update(const double* stats, int active, double eps, double tau, doubl
  * host memory buf of *len bytes (VMC_EINVAL, with *len set to the need, if it is too small);
  * waits for the trajectory's work on the context stream.
  * vmc_traj_load: reads a checkpoint of len bytes from host memory into a trajectory created with
- * the same system (N, box, precision, Ewald settings, one-body term, twist) and walker count;
- * anything else, or a damaged buffer (checksum, size, version), returns VMC_EINVAL and leaves the
- * trajectory unchanged. */
+ * the same system (N, box, precision, Ewald settings, cusp parameters, twist or general twist and
+ * its angles, basis and eta, the one-body and three-body terms on or off) and walker count; the
+ * Jastrow parameters b, j1_b1 and j3_f are taken from the checkpoint (as vmc_traj_set_jastrow sets
+ * them, so an optimised wavefunction resumes).  Anything else, or a damaged buffer (checksum,
+ * size, version), returns VMC_EINVAL and leaves the trajectory unchanged. */
 int vmc_traj_save(vmc_traj* traj, void* buf, size_t* len);
 int vmc_traj_load(vmc_traj* traj, const void* buf, size_t len);
 /* Restart at another density (SI, systematic setup: configurations made at r_s* serve at any

@@ -572,6 +572,8 @@ int vmc_traj_save(vmc_traj* t, void* buf, size_t* len) {
   h.have_means = t->have_means; h.have_R = t->have_R; h.have_prev = t->have_prev; h.have_S = t->have_S;
   h.box_L = t->sys.box_L; h.kappa = t->sys.ewald_kappa; h.a_par = t->sys.a_par; h.a_anti = t->sys.a_anti;
   h.b = t->sys.b; h.j1_b1 = t->sys.j1_b1;
+  h.general_twist = t->sys.general_twist; h.contracted = t->sys.contracted; h.eta = t->sys.eta;
+  for (int q = 0; q < 3; ++q) { h.theta[q] = t->sys.theta[q]; h.j3_f[q] = t->sys.j3_f[q]; }
   unsigned char* p = static_cast<unsigned char*>(buf);
   std::memcpy(p, &h, sizeof h);
   p += sizeof h;
@@ -601,9 +603,20 @@ static int traj_load(vmc_traj* t, const void* buf, size_t len, bool rescale) {
   vmc_host::CkptHeader h;
   if (vmc_host::ckpt_validate(buf, len, &h) != VMC_OK) return VMC_EINVAL;
   const vmc_system& s = t->sys;
+  // the system must match; the variational Jastrow parameters (b, b_1, F) come from the
+  // checkpoint, as vmc_traj_set_jastrow would set them (an optimised wavefunction resumes)
   if (h.n != t->N || h.w != t->W || h.precision != s.precision || h.nmax != s.ewald_nmax || h.twist != s.twist ||
-      h.a_par != s.a_par || h.a_anti != s.a_anti || h.b != s.b || h.j1_b1 != s.j1_b1)
+      h.general_twist != s.general_twist || h.contracted != s.contracted || h.a_par != s.a_par ||
+      h.a_anti != s.a_anti)
     return VMC_EINVAL;
+  if (s.contracted && h.eta != s.eta) return VMC_EINVAL;
+  for (int q = 0; q < 3; ++q)
+    if (s.general_twist && h.theta[q] != s.theta[q]) return VMC_EINVAL;
+  vmc_system js = s;
+  js.b = h.b;
+  js.j1_b1 = h.j1_b1;
+  for (int q = 0; q < 3; ++q) js.j3_f[q] = h.j3_f[q];
+  if (check_sys(&js) || (js.j1_b1 > 0.0) != (s.j1_b1 > 0.0) || (has_j3(js) && !t->j3G)) return VMC_EINVAL;
   if (!rescale && (h.box_L != s.box_L || h.kappa != s.ewald_kappa)) return VMC_EINVAL;
   if (rescale && !(h.box_L > 0.0 && std::isfinite(h.box_L))) return VMC_EINVAL;
   HIPCHK(hipSetDevice(t->ctx->device));
@@ -638,6 +651,8 @@ static int traj_load(vmc_traj* t, const void* buf, size_t len, bool rescale) {
   t->seed = h.seed;
   t->traj_id = h.traj_id;
   t->lang_step = h.lang_step;
+  t->sys = js;
+  t->have_popt = false;
   return VMC_OK;
 }
 

@@ -252,3 +252,60 @@ def test_damaged_payload_refused(dev):
     assert np.array_equal(tgt.get_R().cpu().numpy(), wl.R.reshape(-1))
     tgt.close()
     tr.close()
+
+
+def test_optimised_jastrow_resumes_from_a_checkpoint(dev):
+    """A trajectory whose Jastrow parameters were changed (as an SR loop does) is saved; a fresh
+    trajectory created with the original parameters takes b, b_1 and F from the checkpoint and
+    continues the run bit for bit.  A checkpoint of another basis, eta, twist angle or without
+    the three-body memory is refused."""
+    torch, vmc, ctx = dev
+    from oracle import oracle as O
+    wl = workload("h16")
+    F3 = (-0.3, 0.1, 0.05)
+    Cm = T(torch, O.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)[0])
+    R, z = T(torch, wl.R.reshape(-1)), T(torch, wl.zeta)
+    sysd = vmc.make_system(wl.n, wl.L, b1=2.5, j3=F3)
+    new = (0.8, 2.2, (-0.2, 0.02, 0.06))
+
+    def run(tr, k):
+        return tr.energy_forces(R, Cm, z, 1, 2, wl.delta, k).cpu().numpy()
+
+    tr = vmc.Trajectory(ctx, sysd, 32, seed=5, traj_id=2)
+    tr.set_walkers(T(torch, wl.electrons(W=32)))
+    tr.set_jastrow(*new)
+    run(tr, 0)
+    blob = tr.save()
+    ref = run(tr, 1)
+    tr.close()
+    tr2 = vmc.Trajectory(ctx, sysd, 32, seed=99, traj_id=0)
+    tr2.load(blob)
+    assert np.array_equal(run(tr2, 1), ref)
+    tr2.close()
+    bad = [vmc.make_system(wl.n, wl.L, b1=2.5),                                    # no three-body memory
+           vmc.make_system(wl.n, wl.L, j3=F3),                                     # no one-body term
+           vmc.make_system(wl.n, wl.L, b1=2.5, j3=F3, theta=None, twist=2)]
+    for sd in bad:
+        t = vmc.Trajectory(ctx, sd, 32)
+        with pytest.raises(vmc.VMCError):
+            t.load(blob)
+        t.close()
+    wc = workload("h54")
+    eta_blob = None
+    for eta in (0.1, 0.2):
+        t = vmc.Trajectory(ctx, vmc.make_system(wc.n, wc.L, eta=eta), 8, seed=1)
+        if eta_blob is None:
+            eta_blob = t.save()
+        else:
+            with pytest.raises(vmc.VMCError):
+                t.load(eta_blob)
+        t.close()
+    th_blob = None
+    for th in ((0.1, 0.2, 0.3), (0.1, 0.2, 0.4)):
+        t = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, theta=th), 8, seed=1)
+        if th_blob is None:
+            th_blob = t.save()
+        else:
+            with pytest.raises(vmc.VMCError):
+                t.load(th_blob)
+        t.close()
