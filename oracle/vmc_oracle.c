@@ -632,6 +632,68 @@ double o_potential(const osys* s, const double* x, double* dV_dR, double* dV_dx)
 }
 
 /* ------------------------------------------------------------ local energy -- */
+/* The proton derivatives of the one-body and three-body Jastrow terms (each moves with its
+ * nucleus): adds their part of d ln psi / dR to dln and of dT_L / dR to dT, given per electron
+ * vv = grad_i U + grad_i ln|D| (the real part of grad_i ln D for complex orbitals). */
+void o_jastrow_dR(const osys* s, const double* x, const double* vv, double* dln, double* dT) {
+  const int ne = s->n_up + s->n_dn, np = s->n_p;
+  /* The one-body term depends on R_a through r_i - R_a, so d/dR_a = -grad_i on it:
+   * d ln psi / dR_a gets -grad_i f_ia, and the kinetic part
+   * -1/2 sum_i (lap_i U + |grad_i U|^2 + 2 grad_i ln|D| . grad_i U) + (the determinant
+   * terms, already differentiated above with the full grad U) gets
+   * sum_i [ 1/2 grad_i lap_i f_ia + hess_i f_ia (grad_i U + grad_i ln|D|) ]. */
+  if (s->b1 > 0.0)
+    for (int a = 0; a < np; ++a)
+      for (int i = 0; i < ne; ++i) {
+        double d[3] = {x[3 * i] - s->R[3 * a], x[3 * i + 1] - s->R[3 * a + 1], x[3 * i + 2] - s->R[3 * a + 2]};
+        double F[4], g[3], h[6], lp, gl[3];
+        j1_radial(s->b1, periodised_rho(s, d), F);
+        radial_field(s, d, F, g, h, &lp, gl);
+        double v[3];
+        for (int m = 0; m < 3; ++m) v[m] = vv[3 * i + m];
+        for (int mu = 0; mu < 3; ++mu) {
+          dln[3 * a + mu] -= g[mu];
+          double hv = 0.0;
+          for (int nu = 0; nu < 3; ++nu) hv += h[hidx(mu, nu) - 5] * v[nu];
+          dT[3 * a + mu] += 0.5 * gl[mu] + hv;
+        }
+      }
+  /* The three-body term depends on R_a through chi_a(r_i - R_a), d/dR_a = -grad_i on it: with
+   * v_k = grad_k U + grad_k ln|D| and the sums over the other electrons j != k,
+   *   d ln psi/dR_a,mu = -sum_k sum_j (d_mu chi_ak)^T F chi_aj,
+   *   d(grad_k U)_nu/dR_a,mu = -sum_j [(d_mu d_nu chi_ak)^T F chi_aj + (d_nu chi_ak)^T F d_mu chi_aj],
+   *   d(lap_k U)/dR_a,mu = -sum_j [(d_mu lap chi_ak)^T F chi_aj + (lap chi_ak)^T F d_mu chi_aj],
+   * and the kinetic part changes by -1/2 sum_k d(lap_k U) - sum_k v_k . d(grad_k U). */
+  if (j3_on(s)) {
+    double* ch = malloc(sizeof(double) * 28 * (size_t)ne * np);
+    for (int i = 0; i < ne; ++i)
+      for (int a = 0; a < np; ++a) o_j3_orbitals(s, a, x + 3 * i, ch + 28 * ((size_t)i * np + a));
+    for (int a = 0; a < np; ++a)
+      for (int mu = 0; mu < 3; ++mu) {
+        double dl = 0.0, dt = 0.0;
+        for (int k = 0; k < ne; ++k) {
+          const double* ck = ch + 28 * ((size_t)k * np + a);
+          double v[3];
+          for (int m = 0; m < 3; ++m) v[m] = vv[3 * k + m];
+          for (int j = 0; j < ne; ++j) {
+            if (j == k) continue;
+            const double* cj = ch + 28 * ((size_t)j * np + a);
+            dl -= j3_form(s, ck, 1 + mu, cj, 0);
+            const double dlap = -(j3_form(s, ck, 11 + mu, cj, 0) + j3_form(s, ck, 4, cj, 1 + mu));
+            dt += -0.5 * dlap;
+            for (int nu = 0; nu < 3; ++nu) {
+              const double dg = -(j3_form(s, ck, hidx(mu, nu), cj, 0) + j3_form(s, ck, 1 + nu, cj, 1 + mu));
+              dt -= v[nu] * dg;
+            }
+          }
+        }
+        dln[3 * a + mu] += dl;
+        dT[3 * a + mu] += dt;
+      }
+    free(ch);
+  }
+}
+
 /* For one electron configuration x (Ne x 3): ln|psi|, sign(psi), the local
  * energy E_L = -1/2 sum_i lap_i psi / psi + V, and the derivatives of ln|psi|
  * and E_L with respect to the proton positions at fixed C, zeta and Jastrow.
@@ -725,60 +787,11 @@ int o_local(const osys* s, const double* x, double* lnpsi, double* sign, double*
     }
     free(bf); free(A); free(G); free(Lp); free(Ai);
   }
-  /* The one-body term depends on R_a through r_i - R_a, so d/dR_a = -grad_i on it:
-   * d ln psi / dR_a gets -grad_i f_ia, and the kinetic part
-   * -1/2 sum_i (lap_i U + |grad_i U|^2 + 2 grad_i ln|D| . grad_i U) + (the determinant
-   * terms, already differentiated above with the full grad U) gets
-   * sum_i [ 1/2 grad_i lap_i f_ia + hess_i f_ia (grad_i U + grad_i ln|D|) ]. */
-  if (rc == 0 && want && s->b1 > 0.0)
-    for (int a = 0; a < np; ++a)
-      for (int i = 0; i < ne; ++i) {
-        double d[3] = {x[3 * i] - s->R[3 * a], x[3 * i + 1] - s->R[3 * a + 1], x[3 * i + 2] - s->R[3 * a + 2]};
-        double F[4], g[3], h[6], lp, gl[3];
-        j1_radial(s->b1, periodised_rho(s, d), F);
-        radial_field(s, d, F, g, h, &lp, gl);
-        double v[3];
-        for (int m = 0; m < 3; ++m) v[m] = gU[3 * i + m] + gDe[3 * i + m];
-        for (int mu = 0; mu < 3; ++mu) {
-          dln[3 * a + mu] -= g[mu];
-          double hv = 0.0;
-          for (int nu = 0; nu < 3; ++nu) hv += h[hidx(mu, nu) - 5] * v[nu];
-          dT[3 * a + mu] += 0.5 * gl[mu] + hv;
-        }
-      }
-  /* The three-body term depends on R_a through chi_a(r_i - R_a), d/dR_a = -grad_i on it: with
-   * v_k = grad_k U + grad_k ln|D| and the sums over the other electrons j != k,
-   *   d ln psi/dR_a,mu = -sum_k sum_j (d_mu chi_ak)^T F chi_aj,
-   *   d(grad_k U)_nu/dR_a,mu = -sum_j [(d_mu d_nu chi_ak)^T F chi_aj + (d_nu chi_ak)^T F d_mu chi_aj],
-   *   d(lap_k U)/dR_a,mu = -sum_j [(d_mu lap chi_ak)^T F chi_aj + (lap chi_ak)^T F d_mu chi_aj],
-   * and the kinetic part changes by -1/2 sum_k d(lap_k U) - sum_k v_k . d(grad_k U). */
-  if (rc == 0 && want && j3_on(s)) {
-    double* ch = malloc(sizeof(double) * 28 * (size_t)ne * np);
-    for (int i = 0; i < ne; ++i)
-      for (int a = 0; a < np; ++a) o_j3_orbitals(s, a, x + 3 * i, ch + 28 * ((size_t)i * np + a));
-    for (int a = 0; a < np; ++a)
-      for (int mu = 0; mu < 3; ++mu) {
-        double dl = 0.0, dt = 0.0;
-        for (int k = 0; k < ne; ++k) {
-          const double* ck = ch + 28 * ((size_t)k * np + a);
-          double v[3];
-          for (int m = 0; m < 3; ++m) v[m] = gU[3 * k + m] + gDe[3 * k + m];
-          for (int j = 0; j < ne; ++j) {
-            if (j == k) continue;
-            const double* cj = ch + 28 * ((size_t)j * np + a);
-            dl -= j3_form(s, ck, 1 + mu, cj, 0);
-            const double dlap = -(j3_form(s, ck, 11 + mu, cj, 0) + j3_form(s, ck, 4, cj, 1 + mu));
-            dt += -0.5 * dlap;
-            for (int nu = 0; nu < 3; ++nu) {
-              const double dg = -(j3_form(s, ck, hidx(mu, nu), cj, 0) + j3_form(s, ck, 1 + nu, cj, 1 + mu));
-              dt -= v[nu] * dg;
-            }
-          }
-        }
-        dln[3 * a + mu] += dl;
-        dT[3 * a + mu] += dt;
-      }
-    free(ch);
+  if (rc == 0 && want && (s->b1 > 0.0 || j3_on(s))) {
+    double* vv = malloc(sizeof(double) * 3 * ne);
+    for (int t = 0; t < 3 * ne; ++t) vv[t] = gU[t] + gDe[t];
+    o_jastrow_dR(s, x, vv, dln, dT);
+    free(vv);
   }
   if (rc == 0) {
     if (lnpsi) *lnpsi = lnp;

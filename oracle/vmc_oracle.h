@@ -65,6 +65,9 @@ double o_u01(uint32_t hi, uint32_t lo);
 void o_basis(const osys* s, int a, const double r[3], double out[14]);
 void o_jastrow(const osys* s, const double* x, double* U, double* gradU, double* lapU);
 double o_potential(const osys* s, const double* x, double* dV_dR, double* dV_dx);
+/* Adds the proton derivatives of the one-body and three-body Jastrow terms to dln (d ln psi/dR)
+ * and dT (dT_L/dR), given vv = grad_i U + grad_i ln|D| per electron (3 N). */
+void o_jastrow_dR(const osys* s, const double* x, const double* vv, double* dln, double* dT);
 int o_local(const osys* s, const double* x, double* lnpsi, double* sign, double* EL,
             double* dlnpsi_dR, double* dEL_dR);
 int o_huckel(int n_p, double L, const double* R, const double* zeta, int n_orb,

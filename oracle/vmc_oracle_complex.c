@@ -12,8 +12,10 @@
  * and |psi|^2 = |D_up|^2 |D_dn|^2 e^{2U}.  The local energy is complex; its real part is the
  * estimator (the imaginary part integrates to zero against |psi|^2), so
  *     E = <Re E_L>,  f = -<d Re E_L / dR> - 2 <(Re E_L - E) d ln|psi| / dR>.
- * Readings: the Jastrow factor and the Coulomb part are the untwisted ones (they depend on
- * distances only); both spins use the same twist and orbitals (the SI's opposite twists for
+ * Readings: the Jastrow factor (two-body, and optionally the one-body and on-site three-body
+ * terms) and the Coulomb part are the untwisted ones (they depend on distances only; the proton
+ * derivatives of the one- and three-body terms couple to the real part of grad ln D); both spins
+ * use the same twist and orbitals (the SI's opposite twists for
  * opposite spins would conjugate D_dn, which leaves |psi|^2, Re E_L and both force terms
  * unchanged).  Images |n| <= 1 per axis, as in the real oracle.
  */
@@ -252,10 +254,11 @@ static void cmatmul(int n, const cplx* A, const cplx* B, cplx* C) {
 /* Local quantities of the complex-twisted wavefunction at electron configuration x:
  * ln|psi|, arg psi, Re E_L and the proton derivatives of ln|psi| and of Re E_L (by Jacobi's
  * formula, d A^-1 = -A^-1 dA A^-1, as in the real oracle).  C: n_p x n_orb complex pairs.
- * The one-body Jastrow term is not part of this wavefunction (s->b1 must be 0). */
+ * The one-body and three-body Jastrow terms are real and enter as in the real oracle, their proton
+ * derivatives coupling to the real part of grad ln D (o_jastrow_dR).  Single Gaussians only. */
 int o_clocal(const osys* s, const double theta[3], const double* Cd, const double* x, double* lnpsi, double* phase,
              double* EL, double* dlnpsi_dR, double* dEL_dR) {
-  if (s->b1 > 0.0 || s->contracted || s->j3f[0] != 0.0 || s->j3f[1] != 0.0 || s->j3f[2] != 0.0 || s->basis_kind != OB_PERIODIC_GAUSS) return O_EINVAL;
+  if (s->contracted || s->basis_kind != OB_PERIODIC_GAUSS) return O_EINVAL;
   const int np = s->n_p, ne = s->n_up + s->n_dn, no = s->n_orb, n3 = 3 * np;
   double U;
   double* gU = malloc(sizeof(double) * 3 * ne);
@@ -269,6 +272,8 @@ int o_clocal(const osys* s, const double theta[3], const double* Cd, const doubl
   const int want = (dlnpsi_dR != NULL) || (dEL_dR != NULL);
   double* dln = calloc(n3, sizeof(double));
   double* dT = calloc(n3, sizeof(double));
+  double* vv = malloc(sizeof(double) * 3 * ne);   /* grad_i U + Re grad_i ln D */
+  memcpy(vv, gU, sizeof(double) * 3 * ne);
   int rc = 0;
   for (int sp = 0; sp < 2 && rc == 0; ++sp) {
     const int n = sp ? s->n_dn : s->n_up, e0 = sp ? s->n_up : 0;
@@ -301,6 +306,7 @@ int o_clocal(const osys* s, const double theta[3], const double* Cd, const doubl
       }
       const double* gu = gU + 3 * (e0 + i);
       T += -0.5 * creal(lapD + 2.0 * (gD[0] * gu[0] + gD[1] * gu[1] + gD[2] * gu[2]));
+      for (int m = 0; m < 3; ++m) vv[3 * (e0 + i) + m] += creal(gD[m]);
     }
     if (want) {
       cplx *dA = malloc(sizeof(cplx) * n * n), *dG = malloc(sizeof(cplx) * 3 * n * n), *dL = malloc(sizeof(cplx) * n * n);
@@ -341,6 +347,7 @@ int o_clocal(const osys* s, const double theta[3], const double* Cd, const doubl
 #undef CC
     free(bf); free(A); free(G); free(Lp); free(Ai);
   }
+  if (rc == 0 && want) o_jastrow_dR(s, x, vv, dln, dT);
   if (rc == 0) {
     if (lnpsi) *lnpsi = lnp;
     if (phase) *phase = remainder(ph, 2.0 * CPI);
@@ -349,7 +356,7 @@ int o_clocal(const osys* s, const double theta[3], const double* Cd, const doubl
     if (dEL_dR)
       for (int t = 0; t < n3; ++t) dEL_dR[t] = dT[t] + dVdR[t];
   }
-  free(gU); free(lU); free(dVdR); free(dln); free(dT);
+  free(gU); free(lU); free(dVdR); free(dln); free(dT); free(vv);
   return rc;
 }
 
@@ -371,7 +378,7 @@ static void cmo_row(const osys* s, const double theta[3], const double* Cd, cons
 int o_cvmc_run_from(const osys* s, const double theta[3], const double* Cd, int W, uint32_t w0, double* x,
                     int n_equil, int n_meas, double delta, uint32_t seed, uint32_t traj, uint32_t step, double* sums,
                     int64_t* n_acc, int n_threads) {
-  if (s->b1 > 0.0 || s->contracted || s->j3f[0] != 0.0 || s->j3f[1] != 0.0 || s->j3f[2] != 0.0) return O_EINVAL;
+  if (s->contracted) return O_EINVAL;
   const int ne = s->n_up + s->n_dn, n3 = 3 * s->n_p, nsum = 2 + 3 * n3;
   int err = 0;
 #ifdef _OPENMP

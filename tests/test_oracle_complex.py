@@ -15,6 +15,8 @@ import pytest
 from paper_1605_08423_amd.inputs import small_system, workload
 
 THETAS = [(0.3, -1.1, 2.0), (np.pi / 4, 3 * np.pi / 4, -np.pi / 4)]
+# the Jastrow factor: the two-body term alone, and with the one-body and three-body terms
+JAS = [dict(), dict(b1=1.7, j3=(-0.3, 0.1, 0.05))]
 
 
 def _sys(oracle, wl, theta, **kw):
@@ -69,16 +71,18 @@ def test_bloch_condition(oracle, theta):
                 assert np.allclose(s.cbasis(a, r2), np.exp(1j * theta[ax] * n) * s.cbasis(a, r), rtol=1e-12, atol=1e-14)
 
 
-def test_real_twists_reduce_to_the_real_oracle(oracle):
+@pytest.mark.parametrize("jas", JAS)
+def test_real_twists_reduce_to_the_real_oracle(oracle, jas):
     """At the eight real twists (theta_m in {0, pi}) the complex wavefunction is the real one:
-    the same occupied space, ln|psi|, E_L and proton derivatives (the sign of psi is its phase)."""
+    the same occupied space, ln|psi|, E_L and proton derivatives (the sign of psi is its phase),
+    also with the one-body and three-body Jastrow terms."""
     wl = workload("h16")
     x = wl.electrons(W=2, seed_offset=9)
     for tw in range(8):
         theta = np.array([np.pi * ((tw >> m) & 1) for m in range(3)])
-        s = _sys(oracle, wl, theta)
+        s = _sys(oracle, wl, theta, **jas)
         Cr, _ = oracle.huckel(wl.R, wl.zeta, wl.L, 8, twist=tw)
-        sr = oracle.System(wl.R, wl.zeta, Cr, L=wl.L, twist=tw)
+        sr = oracle.System(wl.R, wl.zeta, Cr, L=wl.L, twist=tw, **jas)
         assert np.allclose(s.Cc @ s.Cc.conj().T, Cr @ Cr.T, atol=1e-12)
         for k in range(2):
             a, b = s.local(x[k]), sr.local(x[k])
@@ -144,12 +148,13 @@ def test_determinants_equal_leibniz(oracle, n):
         assert np.exp(1j * r["phase"]) == pytest.approx(D / abs(D), abs=1e-10)
 
 
+@pytest.mark.parametrize("jas", JAS)
 @pytest.mark.parametrize("theta", THETAS)
-def test_kinetic_energy_equals_fd_laplacian(oracle, theta):
+def test_kinetic_energy_equals_fd_laplacian(oracle, theta, jas):
     """Re E_L - V = Re(-1/2 sum_i lap_i psi / psi), the Laplacian of psi = e^{ln|psi| + i arg psi}
     by central differences in every electron coordinate."""
     wl = small_system(6, 1.3, seed=4)
-    s = _sys(oracle, wl, theta)
+    s = _sys(oracle, wl, theta, **jas)
     x = wl.electrons(W=1, seed_offset=5)[0]
     r = s.local(x, False)
     V, _, _ = s.potential(x)
@@ -190,12 +195,13 @@ def test_many_body_bloch_condition_and_exchange(oracle, theta):
     assert r["EL"] == pytest.approx(r0["EL"], rel=1e-11)
 
 
+@pytest.mark.parametrize("jas", JAS)
 @pytest.mark.parametrize("theta", THETAS)
-def test_proton_derivatives_equal_fd(oracle, theta):
+def test_proton_derivatives_equal_fd(oracle, theta, jas):
     """d ln|psi| / dR and d Re E_L / dR against central differences in the proton positions
     (orbital coefficients held fixed)."""
     wl = small_system(6, 1.3, seed=4)
-    s = _sys(oracle, wl, theta)
+    s = _sys(oracle, wl, theta, **jas)
     x = wl.electrons(W=1, seed_offset=7)[0]
     r = s.local(x)
     h = 1e-5
@@ -203,18 +209,19 @@ def test_proton_derivatives_equal_fd(oracle, theta):
         Rp, Rm = wl.R.reshape(-1).copy(), wl.R.reshape(-1).copy()
         Rp[t] += h
         Rm[t] -= h
-        sp = oracle.CSystem(Rp.reshape(-1, 3), wl.zeta, s.Cc, theta, wl.L)
-        sm = oracle.CSystem(Rm.reshape(-1, 3), wl.zeta, s.Cc, theta, wl.L)
+        sp = oracle.CSystem(Rp.reshape(-1, 3), wl.zeta, s.Cc, theta, wl.L, **jas)
+        sm = oracle.CSystem(Rm.reshape(-1, 3), wl.zeta, s.Cc, theta, wl.L, **jas)
         a, b = sp.local(x, False), sm.local(x, False)
         assert r["dlnpsi"][t] == pytest.approx((a["lnpsi"] - b["lnpsi"]) / (2 * h), rel=1e-6, abs=1e-7)
         assert r["dEL"][t] == pytest.approx((a["EL"] - b["EL"]) / (2 * h), rel=1e-6, abs=1e-6)
 
 
-def test_sweep_decisions_follow_psi_ratios(oracle):
+@pytest.mark.parametrize("jas", JAS)
+def test_sweep_decisions_follow_psi_ratios(oracle, jas):
     """Each Metropolis decision of a sweep equals u < |psi(x')/psi(x)|^2 with ln|psi| from the
     local-energy routine, on the move drawn from the same Philox counters."""
     wl = small_system(6, 1.3, seed=4)
-    s = _sys(oracle, wl, np.array(THETAS[0]))
+    s = _sys(oracle, wl, np.array(THETAS[0]), **jas)
     W, seed, traj, step = 4, 21, 2, 3
     x0 = wl.electrons(W=W)
     xs = x0.copy()
@@ -238,10 +245,11 @@ def test_sweep_decisions_follow_psi_ratios(oracle):
         assert np.allclose(x, xs[w], rtol=0, atol=1e-12)
 
 
-def test_force_estimator_equals_correlated_sampling_derivative(oracle):
+@pytest.mark.parametrize("jas", JAS)
+def test_force_estimator_equals_correlated_sampling_derivative(oracle, jas):
     wl = small_system(6, 1.3, seed=4)
     theta = np.array(THETAS[1])
-    s = _sys(oracle, wl, theta)
+    s = _sys(oracle, wl, theta, **jas)
     x = wl.electrons(W=4)
     xs = []
     for k in range(6):
@@ -263,7 +271,7 @@ def test_force_estimator_equals_correlated_sampling_derivative(oracle):
     base = np.array(base)
 
     def E_of(Rflat):
-        sp = oracle.CSystem(Rflat.reshape(-1, 3), wl.zeta, s.Cc, theta, wl.L)
+        sp = oracle.CSystem(Rflat.reshape(-1, 3), wl.zeta, s.Cc, theta, wl.L, **jas)
         res = [sp.local(y, False) for y in xs]
         lw = 2 * (np.array([q["lnpsi"] for q in res]) - base)
         w = np.exp(lw - lw.max())
