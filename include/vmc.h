@@ -91,8 +91,10 @@ typedef struct {
                          Gaussian is the Bloch sum phi_a(r) = sum_n e^{-i theta.n} g_a(r - R_a + n L),
                          so phi(r + n L) = e^{i theta.n} phi(r); orbitals, Slater matrices and
                          determinants are complex, sampling follows |psi|^2 and the estimators take
-                         the real part of E_L and of its proton derivative.  Requires precision
-                         VMC_FP64, twist = 0, j1_b1 = 0 and N_sigma <= 64 (else VMC_EINVAL).  The
+                         the real part of E_L and of its proton derivative.  The one-body and
+                         three-body Jastrow terms combine with it (their proton derivatives take the
+                         real part of grad ln D).  Requires precision VMC_FP64, twist = 0, the single
+                         Gaussian basis and N_sigma <= 64 (else VMC_EINVAL).  The
                          orbital coefficients C are then complex, N x N/2 (re, im) pairs of doubles
                          (vmc_huckel_params_theta); Binv holds complex inverses (twice the bytes).
                          Both spins use the same twist.  Not for the server (VMC_EINVAL).
@@ -113,9 +115,9 @@ typedef struct {
                          with chi_1 = e^{-ZJ rho^2}, chi_2 = rho^2 e^{-ZJ rho^2}, ZJ = 0.7933844, on
                          the sin-periodised offset rho between electron and nucleus, and
                          F = [[f11, f12], [f12, f22]] = [[j3_f[0], j3_f[1]], [j3_f[1], j3_f[2]]] the same
-                         for every nucleus.  All zero: no term.  The term requires general_twist = 0
-                         and N_sigma <= 64 (it combines with the real twists, the contracted basis and
-                         the one-body term), and is not for the server (else VMC_EINVAL); its orbitals are evaluated in the precision of
+                         for every nucleus.  All zero: no term.  The term requires N_sigma <= 64 (it
+                         combines with the real and general twists, the contracted basis and the
+                         one-body term), and is not for the server (else VMC_EINVAL); its orbitals are evaluated in the precision of
                          the Jastrow terms (FP32 in VMC_MIXED), their per-nucleus sums combined and
                          accumulated in FP64 */
 } vmc_system;
@@ -226,7 +228,7 @@ int vmc_traj_walkers_reset(vmc_traj* traj, int* n_reset);
  * vmc_traj_param_stats, vmc_sr_update (host) and vmc_traj_set_jastrow. */
 /* on = 1: every later vmc_energy_forces call also accumulates, per walker and in FP64, the
  * samples' [E_L, O (5), E_L O (5), O O^T (25)] (one more kernel per measured sweep); 0: off
- * (the default).  Real orbitals only (general_twist: VMC_EINVAL). */
+ * (the default); with real or complex orbitals. */
 int vmc_traj_set_param_stats(vmc_traj* traj, int on);
 /* Means over the W walkers and M measured sweeps of the last vmc_energy_forces call made with the
  * statistics on, in a fixed summation order: stats_dev (device, 36 doubles) = [E, <O> (5),

@@ -154,6 +154,17 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
   for (int e = t; e < N; e += CT)
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) sincospi(pos[3 * e + ax] * invL, &trig[6 * e + ax], &trig[6 * e + 3 + ax]);
+  // thread c < N takes proton c in the one- and three-body terms: the sines and cosines of
+  // pi R_c / L, and G_c = sum_i chi_c(r_i) kept for the whole half-sweep
+  double sa[3] = {0.0, 0.0, 0.0}, ca[3] = {1.0, 1.0, 1.0};
+  if (t < N)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) sincospi(a.R[3 * t + ax] * invL, &sa[ax], &ca[ax]);
+  double G1 = 0.0, G2 = 0.0;
+  if (MOVES && a.j3 && t < N) {
+    G1 = a.j3G[((size_t)w * N + t) * 2];
+    G2 = a.j3G[((size_t)w * N + t) * 2 + 1];
+  }
   if (MOVES)
     for (int i = t; i < NS; i += CT) {
       double xn, yn, zn, ru;
@@ -311,16 +322,34 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
         for (int k = k0; k < k1; ++k) acc = cadd(acc, cmul(ld_c(Mp, (size_t)i * NSP + k), ld_c(Ai, (size_t)k * LDA + j)));
         st_c(vpart, (size_t)pp * NSP + j, acc);
       }
-      double du = 0.0;
-      if (t < N && t != e) {
-        const double* tj = trig + 6 * t;
-        const double sj[3] = {tj[0], tj[1], tj[2]}, cj[3] = {tj[3], tj[4], tj[5]};
+      double du = 0.0, dj1 = 0.0, dj2 = 0.0;
+      if (t < N) {
         const double* to = trig + 6 * e;
         const double so[3] = {to[0], to[1], to[2]}, co[3] = {to[3], to[4], to[5]};
         const double* tn = ptrig + 6 * i;
         const double sn[3] = {tn[0], tn[1], tn[2]}, cn[3] = {tn[3], tn[4], tn[5]};
-        const double aa = (t / NS == sp) ? a.a_par : a.a_anti;
-        du = pade_u<double>(sn, cn, sj, cj, LoP, aa, bj) - pade_u<double>(so, co, sj, cj, LoP, aa, bj);
+        // the pair term with electron t
+        if (t != e) {
+          const double* tj = trig + 6 * t;
+          const double sj[3] = {tj[0], tj[1], tj[2]}, cj[3] = {tj[3], tj[4], tj[5]};
+          const double aa = (t / NS == sp) ? a.a_par : a.a_anti;
+          du = pade_u<double>(sn, cn, sj, cj, LoP, aa, bj) - pade_u<double>(so, co, sj, cj, LoP, aa, bj);
+        }
+        // the one-body term with proton t: -(1 - e^{-beta rho}) / beta changes by the difference
+        // of the exponentials over beta
+        if (a.j1_beta > 0.0)
+          du += (one_body_exp<double>(sn, cn, sa, ca, LoP, a.j1_beta) -
+                 one_body_exp<double>(so, co, sa, ca, LoP, a.j1_beta)) / a.j1_beta;
+        // the three-body term on nucleus t: (chi(r') - chi(r))^T F (G_t - chi(r))
+        if (a.j3) {
+          double n1, n2, o1, o2;
+          j3_values<double>(sn, cn, sa, ca, LoP, n1, n2);
+          j3_values<double>(so, co, sa, ca, LoP, o1, o2);
+          dj1 = n1 - o1;
+          dj2 = n2 - o2;
+          const double g1 = G1 - o1, g2 = G2 - o2;
+          du += a.j3f[0] * dj1 * g1 + a.j3f[1] * (dj1 * g2 + dj2 * g1) + a.j3f[2] * dj2 * g2;
+        }
       }
       du = wave_allsum(du);
       if (lane == 0) red[wave] = du;
@@ -333,6 +362,8 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
       const double q2 = q.r * q.r + q.i * q.i;
       const double pacc = q2 * exp(2.0 * dU);
       if (prop[4 * i + 3] < pacc) {
+        G1 += dj1;
+        G2 += dj2;
         const double iq2 = 1.0 / q2;
         const cd iq = {q.r * iq2, -q.i * iq2};
         if (t < RPT * NS) {
@@ -364,6 +395,10 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
   for (int u = t; u < NS * NS; u += CT) st_c(Bo, u, ld_c(Ai, (size_t)(u / NS) * LDA + u % NS));
   if (MOVES)
     for (int u = t; u < 3 * NS; u += CT) a.pos[(size_t)w * 3 * N + 3 * sp * NS + u] = pos[3 * sp * NS + u];
+  if (MOVES && a.j3 && t < N) {
+    a.j3G[((size_t)w * N + t) * 2] = G1;
+    a.j3G[((size_t)w * N + t) * 2 + 1] = G2;
+  }
   if (t == 0) {
     if (MOVES && nadd > 0) {
       ldv += 0.5 * log(qprod.r * qprod.r + qprod.i * qprod.i) + qexp * 0.69314718055994530942;
@@ -388,7 +423,9 @@ struct CSlaterLay {
   // LDS (doubles)
   static constexpr size_t pos = 0, gU = pos + 3 * N, lU = gU + 3 * N, trig = lU + N, part = trig + 6 * N,
                           partn = (size_t)(HJ * N * 5 > 256 * 6 ? HJ * N * 5 : 256 * 6), red = part + partn,
-                          bytes = sizeof(double) * (red + 8);
+                          gd = red + 8, bytes = sizeof(double) * (gd + 3 * N);
+  // the partial sums of Re grad ln D (256 / NS shares x NS x 3) reuse the pair-pass region
+  static_assert((256 / NS) * NS * 3 <= (int)partn, "partial sums of grad ln D exceed their region");
 };
 
 // D (TRr*16 x TCc*16) = A (x K) B (K x), complex, row-major with leading dimensions in complex
@@ -433,9 +470,11 @@ __global__ __launch_bounds__(256, 1) void k_cslater_sample(MeasureArgs m, TwistA
   double* trig = smem + LY::trig;
   double* part = smem + LY::part;
   double* red = smem + LY::red;
+  double* gd = smem + LY::gd;        // N x 3: Re grad ln D per electron (one- and three-body terms)
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int w = blockIdx.x;
   const double L = m.L, invL = m.invL;
+  const bool one_body = m.j1_beta > 0.0;
   double* scr = reinterpret_cast<double*>(m.scr + (size_t)w * 16 * LY::scr_elems);
   double* Bs = scr + 2 * LY::b;
   double* Xs = scr + 2 * LY::x;
@@ -477,15 +516,49 @@ __global__ __launch_bounds__(256, 1) void k_cslater_sample(MeasureArgs m, TwistA
         lp += upp * gg + up * lr;
         if (j > i) ui += aj * rho * iden;
       }
+      if (one_body) {
+        // the one-body term f(rho) = -(1 - e^{-beta rho}) / beta of electron i and this thread's
+        // share of the protons: f' = -e^{-beta rho}, f'' = beta e^{-beta rho}; the sum of f as
+        // (sum e^{-beta rho} - count) / beta
+        const double beta = m.j1_beta;
+        double sx = 0.0;
+        for (int c = j0; c < j1; ++c) {
+          double rt[3], cc[3];
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) {
+            double sc, cs;
+            sincospi(min_image(pos[3 * i + ax] - m.R[3 * c + ax], L, invL) * invL, &sc, &cs);
+            rt[ax] = LoP * sc;
+            cc[ax] = cs;
+          }
+          const double r2 = rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2];
+          const double rho = sqrt(r2), irho = 1.0 / rho;
+          const double ex = exp(-beta * rho);
+          const double gr0 = rt[0] * cc[0] * irho, gr1 = rt[1] * cc[1] * irho, gr2 = rt[2] * cc[2] * irho;
+          const double gg = gr0 * gr0 + gr1 * gr1 + gr2 * gr2;
+          const double lr = (cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2] - kf * r2) * irho - gg * irho;
+          g0 -= ex * gr0; g1 -= ex * gr1; g2 -= ex * gr2;
+          lp += beta * ex * gg - ex * lr;
+          sx += ex;
+        }
+        ui += (sx - (double)(j1 - j0)) / beta;
+      }
       double* q = part + ((size_t)hj * N + i) * 5;
       q[0] = g0; q[1] = g1; q[2] = g2; q[3] = lp; q[4] = ui;
     }
     __syncthreads();
+    // the three-body term's gradient, Laplacian and value, from the pass before this kernel
+    const double* j3in = m.j3 ? m.j3scr + (size_t)w * j3_measure_doubles(N) : nullptr;
     for (int i = t; i < N; i += 256) {
       double g0 = 0, g1 = 0, g2 = 0, lp = 0, ui = 0;
       for (int hj = 0; hj < HJ; ++hj) {
         const double* q = part + ((size_t)hj * N + i) * 5;
         g0 += q[0]; g1 += q[1]; g2 += q[2]; lp += q[3]; ui += q[4];
+      }
+      if (j3in) {
+        g0 += j3in[3 * i]; g1 += j3in[3 * i + 1]; g2 += j3in[3 * i + 2];
+        lp += j3in[3 * N + i];
+        if (i == 0) ui += j3in[4 * N];
       }
       gU[3 * i] = g0; gU[3 * i + 1] = g1; gU[3 * i + 2] = g2;
       lU[i] = lp;
@@ -509,6 +582,36 @@ __global__ __launch_bounds__(256, 1) void k_cslater_sample(MeasureArgs m, TwistA
       if (i >= NS || c >= N) st_c(Xs, u, cd{0.0, 0.0});
     }
     __syncthreads();
+    if (one_body || m.j3) {
+      // Re grad_i ln D = Re sum_a grad phi_a(r_i) B_ai for the electrons of this spin, in HG
+      // shares of the centres, combined in a fixed order
+      constexpr int HG = 256 / NS;
+      double* gp = part;
+      for (int u = t; u < HG * NS; u += 256) {
+        const int i = u % NS, hg = u / NS, e = sp * NS + i;
+        const int c0 = hg * N / HG, c1 = (hg + 1) * N / HG;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int c = c0; c < c1; ++c) {
+          cd g[3][4];
+          cbasis_axis<1>(pos[3 * e] - m.R[3 * c], m.zeta[c], L, invL, tw, 0, g[0]);
+          cbasis_axis<1>(pos[3 * e + 1] - m.R[3 * c + 1], m.zeta[c], L, invL, tw, 1, g[1]);
+          cbasis_axis<1>(pos[3 * e + 2] - m.R[3 * c + 2], m.zeta[c], L, invL, tw, 2, g[2]);
+          const cd b = ld_c(Bs, (size_t)c * NSP + i);
+          s0 += remul(b, cmul(cmul(g[0][1], g[1][0]), g[2][0]));
+          s1 += remul(b, cmul(cmul(g[0][0], g[1][1]), g[2][0]));
+          s2 += remul(b, cmul(cmul(g[0][0], g[1][0]), g[2][1]));
+        }
+        gp[3 * u] = s0; gp[3 * u + 1] = s1; gp[3 * u + 2] = s2;
+      }
+      __syncthreads();
+      for (int u = t; u < 3 * NS; u += 256) {
+        const int i = u / 3, c = u % 3;
+        double sg = 0.0;
+        for (int hg = 0; hg < HG; ++hg) sg += gp[3 * (hg * NS + i) + c];
+        gd[3 * (sp * NS + i) + c] = sg;
+      }
+      __syncthreads();
+    }
     // pass 1: basis derivatives -> X, and the terms that need only B
     if (act) {
       for (int s = 0; s < IPT; ++s) {
@@ -539,6 +642,54 @@ __global__ __launch_bounds__(256, 1) void k_cslater_sample(MeasureArgs m, TwistA
         const cd q1 = {0.5 * gly.r + hxy.r * u0 + hyy.r * u1 + hyz.r * u2, 0.5 * gly.i + hxy.i * u0 + hyy.i * u1 + hyz.i * u2};
         const cd q2 = {0.5 * glz.r + hxz.r * u0 + hyz.r * u1 + hzz.r * u2, 0.5 * glz.i + hxz.i * u0 + hyz.i * u1 + hzz.i * u2};
         dT0 += remul(q0, b); dT1 += remul(q1, b); dT2 += remul(q2, b);
+      }
+    }
+    if (one_body && act) {
+      // the one-body term of proton ca at electron e moves with R_ca (d/dR = -grad_e):
+      // d ln|psi|/dR -= F1 g, dT/dR += grad(lap f)/2 + hess f (grad U + Re grad ln D), with the
+      // radial derivatives F1 = -x, F2 = beta x, F3 = -beta^2 x (x = e^{-beta rho}), g = grad rho,
+      // p_m = c_m^2 - (pi/L)^2 rt_m^2, G = |g|^2, P = sum p_m,
+      // hess f = (F2 - F1/rho) g g^T + (F1/rho) diag(p),
+      // grad lap f = F3 G g + F2 (dG + (P - G) g / rho) + F1 ((dP - dG) / rho - (P - G) g / rho^2),
+      // dG = 2 g (p - G) / rho, dP = -4 (pi/L)^2 rho g
+      const double LoP1 = L / VMC_PI, kf1 = (VMC_PI * invL) * (VMC_PI * invL), beta1 = m.j1_beta;
+      const double Ra[3] = {Ra0, Ra1, Ra2};
+      for (int s = 0; s < IPT; ++s) {
+        const int i = h + H * s;
+        if (i >= NS) continue;
+        const int e = sp * NS + i;
+        double rt[3], cc[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          double sc, cs;
+          sincospi(min_image(pos[3 * e + ax] - Ra[ax], L, invL) * invL, &sc, &cs);
+          rt[ax] = LoP1 * sc;
+          cc[ax] = cs;
+        }
+        const double r2 = rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2];
+        const double rho = sqrt(r2), irho = 1.0 / rho;
+        const double x = exp(-beta1 * rho);
+        const double F1 = -x, F2 = beta1 * x, F3 = -beta1 * beta1 * x;
+        double g_[3], p_[3], v_[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          g_[ax] = rt[ax] * cc[ax] * irho;
+          p_[ax] = cc[ax] * cc[ax] - kf1 * rt[ax] * rt[ax];
+          v_[ax] = gU[3 * e + ax] + gd[3 * e + ax];
+        }
+        const double G = g_[0] * g_[0] + g_[1] * g_[1] + g_[2] * g_[2];
+        const double P = p_[0] + p_[1] + p_[2];
+        const double gv = g_[0] * v_[0] + g_[1] * v_[1] + g_[2] * v_[2];
+        const double ha = (F2 - F1 * irho) * gv, hb = F1 * irho, PG = (P - G) * irho;
+        double o[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const double dG = 2.0 * g_[ax] * (p_[ax] - G) * irho, dP = -4.0 * kf1 * rho * g_[ax];
+          const double glap = F3 * G * g_[ax] + F2 * (dG + PG * g_[ax]) + F1 * ((dP - dG) - PG * g_[ax]) * irho;
+          o[ax] = 0.5 * glap + ha * g_[ax] + hb * p_[ax] * v_[ax];
+        }
+        dln0 -= F1 * g_[0]; dln1 -= F1 * g_[1]; dln2 -= F1 * g_[2];
+        dT0 += o[0]; dT1 += o[1]; dT2 += o[2];
       }
     }
     __syncthreads();
@@ -592,6 +743,16 @@ __global__ __launch_bounds__(256, 1) void k_cslater_sample(MeasureArgs m, TwistA
     acc[0] += EL;
     acc[1] += EL * EL;
     m.Uj[w] = Us;
+    if (m.ELs) m.ELs[w] = EL;
+  }
+  if (m.j3) {
+    // for the three-body term's d/dR pass: grad U, Re grad ln D and Re E_L of this sample
+    double* out = m.j3scr + (size_t)w * j3_measure_doubles(N) + 4 * N + 1;
+    for (int u = t; u < 3 * N; u += 256) {
+      out[u] = gU[u];
+      out[3 * N + u] = gd[u];
+    }
+    if (t == 0) out[6 * N] = EL;
   }
 }
 
@@ -610,6 +771,7 @@ size_t cslater_scratch_bytes(int NS) {
 template <int NS>
 hipError_t launch_csweep_t(const WalkerArgs& a, const SweepArgs& s, const TwistArgs& tw, int refresh, int moves,
                            hipStream_t st) {
+  static_assert(CSweepLds<NS>::bytes(true) <= 160 * 1024, "the complex half-sweep exceeds the LDS of a CU");
   if (moves)
     hipLaunchKernelGGL((k_csweep<NS, true>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(true), st, a, s, tw, refresh);
   else
@@ -619,6 +781,7 @@ hipError_t launch_csweep_t(const WalkerArgs& a, const SweepArgs& s, const TwistA
 
 template <int NS>
 hipError_t launch_cslater_t(const MeasureArgs& m, const TwistArgs& tw, hipStream_t st) {
+  static_assert(CSlaterLay<NS>::bytes <= 160 * 1024, "the complex measurement exceeds the LDS of a CU");
   hipLaunchKernelGGL((k_cslater_sample<NS>), dim3(m.W), dim3(256), CSlaterLay<NS>::bytes, st, m, tw);
   return hipGetLastError();
 }

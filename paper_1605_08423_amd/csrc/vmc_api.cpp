@@ -183,14 +183,14 @@ int check_sys(const vmc_system* s) {
   if (s->twist < 0 || s->twist > 7) return VMC_EINVAL;
   if (s->general_twist != 0 && s->general_twist != 1) return VMC_EINVAL;
   if (s->general_twist) {
-    if (s->precision != VMC_FP64 || s->twist != 0 || s->j1_b1 != 0.0 || s->n_protons / 2 > 64) return VMC_EINVAL;
+    if (s->precision != VMC_FP64 || s->twist != 0 || s->n_protons / 2 > 64) return VMC_EINVAL;
     for (int m = 0; m < 3; ++m)
       if (!std::isfinite(s->theta[m])) return VMC_EINVAL;
   }
   if (s->contracted != 0 && s->contracted != 1) return VMC_EINVAL;
   for (int m = 0; m < 3; ++m)
     if (!std::isfinite(s->j3_f[m])) return VMC_EINVAL;
-  if (has_j3(*s) && (s->general_twist || s->n_protons / 2 > 64)) return VMC_EINVAL;
+  if (has_j3(*s) && s->n_protons / 2 > 64) return VMC_EINVAL;
   if (s->contracted) {
     // the images |n| <= 1 of the diffuse r^2 e^{-Z2 r^2} reach FP64 resolution only if Z2 (1.5 L)^2 >= 36
     const double h = 1.5 * s->box_L;
@@ -325,8 +325,11 @@ int measure(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e) {
 }
 int measure_c(vmc_traj* t, const MeasureArgs& m, const EwaldArgs& e, const TwistArgs& tw) {
   vmc_ctx* ctx = t->ctx;
+  if (m.j3) RUN(K_J3_GRAD, launch_j3_grad(m, 0, ctx->stream));
   RUN(K_EWALD, launch_ewald_sample(m, e, 0, ctx->stream));
   RUN(K_CSLATER, launch_cslater_sample(m, tw, ctx->stream));
+  if (m.j3) RUN(K_J3_FORCES, launch_j3_forces(m, 0, ctx->stream));
+  if (m.ELs) RUN(K_OPT, launch_opt_sample(m, 0, ctx->stream));
   return VMC_OK;
 }
 
@@ -797,7 +800,7 @@ int vmc_energy_forces(vmc_traj* t, const double* R_in, const double* C, const do
 }
 
 int vmc_traj_set_param_stats(vmc_traj* t, int on) {
-  if (!t || (on != 0 && on != 1) || (on && is_complex(t->sys))) return VMC_EINVAL;
+  if (!t || (on != 0 && on != 1)) return VMC_EINVAL;
   t->param_stats = on == 1;
   t->have_popt = false;
   return VMC_OK;

@@ -175,7 +175,7 @@ def test_complex_system_validation(dev):
     torch, vmc, ctx = dev
     wl = workload("h16")
     bad = [vmc.make_system(wl.n, wl.L, theta=(0.1, 0.2, 0.3), precision=vmc.VMC_MIXED),
-           vmc.make_system(wl.n, wl.L, theta=(0.1, 0.2, 0.3), b1=1.0),
+           vmc.make_system(wl.n, wl.L, theta=(0.1, 0.2, 0.3), eta=0.1),
            vmc.make_system(wl.n, wl.L, theta=(0.1, 0.2, 0.3), twist=1),
            vmc.make_system(256, 12.0, theta=(0.1, 0.2, 0.3)),
            vmc.make_system(wl.n, wl.L, theta=(0.1, float("inf"), 0.3))]
@@ -217,3 +217,64 @@ def test_twist_mesh_average(oracle, dev):
     assert elem(f.cpu().numpy(), f_ref) < TOL64
     assert rel(S.cpu().numpy(), S_ref) < 1e-9
     assert S.shape == (n3, n3)
+
+
+F3 = (-0.3, 0.1, 0.05)
+
+
+@pytest.mark.parametrize("name,K,theta,b1,j3", [("h16", 12, TH_A, 2.5, F3), ("h32", 6, TH_MP, 0.0, F3),
+                                                ("h54", 6, TH_MP, 2.5, F3), ("h64", 4, TH_A, 2.5, None),
+                                                ("h128", 3, TH_A, 2.5, F3)])
+def test_ceval_configs_with_one_and_three_body_terms(oracle, dev, name, K, theta, b1, j3):
+    torch, vmc, ctx = dev
+    wl = _wl(name)
+    th = np.array(theta)
+    say(f"[complex eval_configs + J] {name} K={K} theta={theta} b1={b1} j3={j3 is not None}")
+    Cc, _ = oracle.chuckel(wl.R, wl.zeta, wl.L, wl.n // 2, th)
+    pos = wl.electrons(W=K, seed_offset=3)
+    sysd = vmc.make_system(wl.n, wl.L, theta=th, b1=b1, j3=j3)
+    g = vmc.vmc_eval_configs(ctx, sysd, _T(torch, wl.R.reshape(-1)), _T(torch, _cpairs(Cc)), _T(torch, wl.zeta),
+                             _T(torch, pos)).cpu().numpy()
+    s = oracle.CSystem(wl.R, wl.zeta, Cc, th, wl.L, b1=b1, j3=j3)
+    n3 = 3 * wl.n
+    worst = {}
+    for k in range(K):
+        r = s.local(pos[k])
+        for q, a, b, f in [("lnpsi", g[k, 0], r["lnpsi"], rel), ("EL", g[k, 1], r["EL"], rel),
+                           ("dlnpsi", g[k, 2:2 + n3], r["dlnpsi"], elem), ("dEL", g[k, 2 + n3:], r["dEL"], elem)]:
+            worst[q] = max(worst.get(q, 0.0), f(a, b))
+    say("  worst errors", worst)
+    for q, v in worst.items():
+        assert v < TOL64, (q, v)
+
+
+@pytest.mark.parametrize("name,theta,W,ne,ns", [("h16", TH_A, 16, 2, 5), ("h54", TH_MP, 4, 1, 4)])
+def test_cchain_with_one_and_three_body_terms(oracle, dev, name, theta, W, ne, ns):
+    """Same-seed chains with b_1 = 2.5 and the three-body term through the complex path: every
+    decision and the per-walker means as the oracle's; the SR statistics' mean E_L equals E."""
+    torch, vmc, ctx = dev
+    wl = _wl(name)
+    th = np.array(theta)
+    say(f"[complex chain + J] {name} theta={theta} W={W}")
+    Cc, _ = oracle.chuckel(wl.R, wl.zeta, wl.L, wl.n // 2, th)
+    pos = wl.electrons(W=W, seed_offset=7)
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, theta=th, b1=2.5, j3=F3), W, seed=11, traj_id=3)
+    tr.set_walkers(_T(torch, pos))
+    tr.set_param_stats(True)
+    out = tr.energy_forces(_T(torch, wl.R.reshape(-1)), _T(torch, _cpairs(Cc)), _T(torch, wl.zeta), ne, ns,
+                           wl.delta, 2).cpu().numpy()
+    means, acc, posg = tr.walker_means().cpu().numpy(), tr.accepts().cpu().numpy(), tr.get_walkers().cpu().numpy()
+    st = tr.param_stats().cpu().numpy()
+    tr.close()
+    s = oracle.CSystem(wl.R, wl.zeta, Cc, th, wl.L, b1=2.5, j3=F3)
+    xo = pos.copy()
+    sums, nacc = s.vmc_run(xo, ne, ns, wl.delta, seed=11, traj=3, step=2)
+    red = oracle.reduce(sums, ns)
+    flips = int(np.sum(acc != nacc))
+    worst = max(elem(means[w], red["means"][w]) for w in range(W))
+    say("  walkers with a flipped decision:", flips, f" worst walker element-wise error of the means {worst:.3e}")
+    assert flips == 0
+    assert rel(posg, xo) < 1e-12
+    assert worst < TOL64
+    assert rel(out[0], red["E"]) < TOL64 and elem(out[3:], red["f"]) < TOL64
+    assert st[0] == pytest.approx(out[0], rel=1e-12)

@@ -129,8 +129,7 @@ def test_j3_chain_mixed_same_seed(oracle, dev, name, W, ne, ns):
 def test_j3_system_validation(dev):
     torch, vmc, ctx = dev
     wl = workload("h16")
-    bad = [vmc.make_system(wl.n, wl.L, j3=F3, theta=(0.1, 0.2, 0.3)),
-           vmc.make_system(256, 14.0, j3=F3),
+    bad = [vmc.make_system(256, 14.0, j3=F3),
            vmc.make_system(wl.n, wl.L, j3=(0.1, float("inf"), 0.0))]
     for sysd in bad:
         with pytest.raises(vmc.VMCError) as ei:

@@ -126,18 +126,17 @@ def test_argument_checks(dev):
     wl = workload("h16")
     plain = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L), 4)
     full = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, b1=2.5, j3=F3), 4)
-    cplx = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, theta=(0.1, 0.2, 0.3)), 4)
     try:
         for call in (lambda: plain.param_stats(),                       # no call with statistics yet
                      lambda: plain.set_jastrow(-0.1, 0.0, (0, 0, 0)),   # negative b
                      lambda: plain.set_jastrow(1.0, 2.5, (0, 0, 0)),    # one-body term switched on
                      lambda: plain.set_jastrow(1.0, 0.0, F3),           # no three-body memory
                      lambda: full.set_jastrow(1.0, 0.0, F3),            # one-body term switched off
-                     lambda: full.set_jastrow(1.0, 2.5, (np.nan, 0, 0)),
-                     lambda: cplx.set_param_stats(True)):
+                     lambda: full.set_jastrow(1.0, 2.5, (np.nan, 0, 0))):
             with pytest.raises(vmc.VMCError) as ei:
                 call()
             assert ei.value.code == vmc.VMC_EINVAL
+        assert vmc._lib().vmc_traj_set_param_stats(full.h, 2) == vmc.VMC_EINVAL
         full.set_jastrow(1.0, 2.5, (0.0, 0.0, 0.0))      # the term off, its memory kept
         full.set_jastrow(1.0, 2.5, F3)
         st = np.zeros(36)
@@ -146,7 +145,7 @@ def test_argument_checks(dev):
             vmc.vmc_sr_update(st, 0b00001, 0.1, 0.1)
         assert ei.value.code == vmc.VMC_ENOTSPD
     finally:
-        for t in (plain, full, cplx):
+        for t in (plain, full):
             t.close()
 
 
