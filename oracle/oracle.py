@@ -92,6 +92,9 @@ def _setup(l):
     l.o_coverlap.argtypes = [i, d, P(d), P(d), P(d), P(d)]
     l.o_coverlap.restype = None
     l.o_chuckel.argtypes = [i, d, P(d), P(d), P(d), i, P(d), P(d)]
+    l.o_coverlap_contracted.argtypes = [i, d, P(d), P(d), d, P(d)]
+    l.o_coverlap_contracted.restype = None
+    l.o_chuckel_contracted.argtypes = [i, d, P(d), P(d), d, i, P(d), P(d)]
     l.o_clocal.argtypes = [P(OSys), P(d), P(d), P(d), P(d), P(d), P(d), P(d), P(d)]
     l.o_j3_orbitals.argtypes = [P(OSys), i, P(d), P(d)]
     l.o_j3_orbitals.restype = None
@@ -264,6 +267,27 @@ def chuckel(R, zeta, L, n_orb, theta):
     rc = lib().o_chuckel(n, L, _dp(theta), _dp(R), _dp(zeta), n_orb, _dp(Cm), _dp(ev))
     if rc:
         raise RuntimeError("o_chuckel failed")
+    return Cm.view(np.complex128)[..., 0], ev
+
+
+def coverlap_contracted(R, L, eta, theta):
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    n = R.size // 3
+    S = np.zeros((n, n, 2))
+    lib().o_coverlap_contracted(n, L, _dp(theta), _dp(R), float(eta), _dp(S))
+    return S.view(np.complex128)[..., 0]
+
+
+def chuckel_contracted(R, L, n_orb, eta, theta):
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    n = R.size // 3
+    Cm = np.zeros((n, n_orb, 2))
+    ev = np.zeros(n)
+    rc = lib().o_chuckel_contracted(n, L, _dp(theta), _dp(R), float(eta), n_orb, _dp(Cm), _dp(ev))
+    if rc:
+        raise RuntimeError("o_chuckel_contracted failed")
     return Cm.view(np.complex128)[..., 0], ev
 
 

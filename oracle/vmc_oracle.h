@@ -119,6 +119,10 @@ void o_cbasis_values(const osys* s, const double theta[3], int npt, const double
 void o_coverlap(int n_p, double L, const double theta[3], const double* R, const double* zeta, double* S_out);
 int o_chuckel(int n_p, double L, const double theta[3], const double* R, const double* zeta, int n_orb, double* C,
               double* evals);
+/* The contracted basis (phi_1 + eta phi_2) under the twist: its overlaps and Hueckel orbitals. */
+void o_coverlap_contracted(int n_p, double L, const double theta[3], const double* R, double eta, double* S_out);
+int o_chuckel_contracted(int n_p, double L, const double theta[3], const double* R, double eta, int n_orb, double* C,
+                         double* evals);
 int o_clocal(const osys* s, const double theta[3], const double* Cd, const double* x, double* lnpsi, double* phase,
              double* EL, double* dlnpsi_dR, double* dEL_dR);
 int o_cvmc_run_from(const osys* s, const double theta[3], const double* Cd, int W, uint32_t w0, double* x,

@@ -17,7 +17,9 @@
  * derivatives of the one- and three-body terms couple to the real part of grad ln D); both spins
  * use the same twist and orbitals (the SI's opposite twists for
  * opposite spins would conjugate D_dn, which leaves |psi|^2, Re E_L and both force terms
- * unchanged).  Images |n| <= 1 per axis, as in the real oracle.
+ * unchanged).  Images |n| <= 1 per axis, as in the real oracle.  The SI's contracted orbital
+ * phi_1 + eta phi_2 is Bloch-summed factor by factor like the single Gaussian (o_cbasis), its
+ * overlaps are the real contracted overlaps' axis moments with Bloch weights.
  */
 #include <complex.h>
 #include <math.h>
@@ -54,13 +56,76 @@ static void cgauss_1d(double d, double zeta, double L, double theta, cplx g[4]) 
   for (int q = 0; q < 4; ++q) g[q] *= ph;
 }
 
+/* The contracted orbital's factors on one axis (SI, basis section): the Bloch sums of
+ * e^{-z t^2} (g) and of t^2 e^{-z t^2} (h) with their first three derivatives at the raw offset
+ * d, images n = -1, 0, 1 at the minimum image x weighted e^{-i theta n}, times e^{i theta k}.
+ * With e = e^{-z t^2}: h' = (2 t - 2 z t^3) e, h'' = (2 - 10 z t^2 + 4 z^2 t^4) e,
+ * h''' = (-24 z t + 36 z^2 t^3 - 8 z^3 t^5) e. */
+static void cgauss2_1d(double d, double z, double L, double theta, cplx g[4], cplx h[4]) {
+  const double k = floor(d / L + 0.5);
+  const double x = d - k * L;
+  for (int q = 0; q < 4; ++q) g[q] = h[q] = 0.0;
+  for (int n = -1; n <= 1; ++n) {
+    const double t = x + n * L, t2 = t * t;
+    const cplx e = cexp(-I * theta * n) * exp(-z * t2);
+    g[0] += e;
+    g[1] += -2.0 * z * t * e;
+    g[2] += (4.0 * z * z * t2 - 2.0 * z) * e;
+    g[3] += (-8.0 * z * z * z * t2 * t + 12.0 * z * z * t) * e;
+    h[0] += t2 * e;
+    h[1] += (2.0 * t - 2.0 * z * t2 * t) * e;
+    h[2] += (2.0 - 10.0 * z * t2 + 4.0 * z * z * t2 * t2) * e;
+    h[3] += (-24.0 * z * t + 36.0 * z * z * t2 * t - 8.0 * z * z * z * t2 * t2 * t) * e;
+  }
+  const cplx ph = cexp(I * theta * k);
+  for (int q = 0; q < 4; ++q) { g[q] *= ph; h[q] *= ph; }
+}
+
+/* Adds w times the 14 components [value, grad(3), lap, hess xx yy zz xy xz yz, grad lap(3)] of
+ * the product f[0](x) f[1](y) f[2](z) of Cartesian factors (f[m][q]: q-th derivative). */
+static void cprod14(const cplx f[3][4], cplx w, cplx v[14]) {
+  v[0] += w * f[0][0] * f[1][0] * f[2][0];
+  v[1] += w * f[0][1] * f[1][0] * f[2][0];
+  v[2] += w * f[0][0] * f[1][1] * f[2][0];
+  v[3] += w * f[0][0] * f[1][0] * f[2][1];
+  v[4] += w * (f[0][2] * f[1][0] * f[2][0] + f[0][0] * f[1][2] * f[2][0] + f[0][0] * f[1][0] * f[2][2]);
+  v[5] += w * f[0][2] * f[1][0] * f[2][0];
+  v[6] += w * f[0][0] * f[1][2] * f[2][0];
+  v[7] += w * f[0][0] * f[1][0] * f[2][2];
+  v[8] += w * f[0][1] * f[1][1] * f[2][0];
+  v[9] += w * f[0][1] * f[1][0] * f[2][1];
+  v[10] += w * f[0][0] * f[1][1] * f[2][1];
+  v[11] += w * (f[0][3] * f[1][0] * f[2][0] + f[0][1] * f[1][2] * f[2][0] + f[0][1] * f[1][0] * f[2][2]);
+  v[12] += w * (f[0][2] * f[1][1] * f[2][0] + f[0][0] * f[1][3] * f[2][0] + f[0][0] * f[1][1] * f[2][2]);
+  v[13] += w * (f[0][2] * f[1][0] * f[2][1] + f[0][0] * f[1][2] * f[2][1] + f[0][0] * f[1][0] * f[2][3]);
+}
+
 /* Basis function a at r: out = [phi, grad(3), lap, hess xx yy zz xy xz yz, grad lap (3)],
  * complex, as 28 doubles (real, imaginary) in that order. */
 void o_cbasis(const osys* s, const double theta[3], int a, const double r[3], double out[28]) {
   const double* Ra = s->R + 3 * a;
+  cplx v[14];
+  if (s->contracted) {
+    /* phi_1 + eta phi_2 = g1 g1 g1 + eta (h2 g2 g2 + g2 h2 g2 + g2 g2 h2), exponents Z1 and Z2 */
+    cplx g1[3][4], g2[3][4], h2[3][4];
+    for (int m = 0; m < 3; ++m) {
+      cplx hd[4];
+      cgauss2_1d(r[m] - Ra[m], O_Z1, s->L, theta[m], g1[m], hd);
+      cgauss2_1d(r[m] - Ra[m], O_Z2, s->L, theta[m], g2[m], h2[m]);
+    }
+    for (int q = 0; q < 14; ++q) v[q] = 0.0;
+    cprod14(g1, 1.0, v);
+    for (int m = 0; m < 3; ++m) {
+      cplx f[3][4];
+      for (int mm = 0; mm < 3; ++mm)
+        for (int q = 0; q < 4; ++q) f[mm][q] = (mm == m) ? h2[mm][q] : g2[mm][q];
+      cprod14(f, s->eta, v);
+    }
+    for (int q = 0; q < 14; ++q) { out[2 * q] = creal(v[q]); out[2 * q + 1] = cimag(v[q]); }
+    return;
+  }
   cplx g[3][4];
   for (int m = 0; m < 3; ++m) cgauss_1d(r[m] - Ra[m], s->zeta[a], s->L, theta[m], g[m]);
-  cplx v[14];
   v[0] = g[0][0] * g[1][0] * g[2][0];
   v[1] = g[0][1] * g[1][0] * g[2][0];
   v[2] = g[0][0] * g[1][1] * g[2][0];
@@ -103,6 +168,62 @@ void o_coverlap(int n_p, double L, const double theta[3], const double* R, const
         for (int p = -4; p <= 4; ++p) acc += cexp(-I * theta[m] * p) * exp(-mu * (d + p * L) * (d + p * L));
         v *= acc;
       }
+      S_out[2 * (a * n_p + b)] = creal(v);
+      S_out[2 * (a * n_p + b) + 1] = cimag(v);
+    }
+}
+
+/* One axis of the contracted overlap: moments of the free-space product of e^{-al (x - A)^2} and
+ * e^{-be (x - B)^2} over the images of the second centre at d + n L (d = B - A), n = -4..4, each
+ * weighted e^{i theta n} (the Bloch sum of the second factor): out = [<1>, <(x-A)^2>, <(x-B)^2>,
+ * <(x-A)^2 (x-B)^2>] with the product centred at (al A + be B)/p, P = be dn/p, Q = al dn/p. */
+static void cmoments_1d(double al, double be, double d, double L, double theta, cplx out[4]) {
+  const double p = al + be, mu = al * be / p;
+  const double m0 = sqrt(CPI / p), m2 = m0 / (2.0 * p), m4 = 3.0 * m0 / (4.0 * p * p);
+  out[0] = out[1] = out[2] = out[3] = 0.0;
+  for (int n = -4; n <= 4; ++n) {
+    const double dd = d + n * L;
+    const cplx e = cexp(I * theta * n) * exp(-mu * dd * dd);
+    const double P = be * dd / p, Q = al * dd / p;
+    out[0] += e * m0;
+    out[1] += e * (m2 + P * P * m0);
+    out[2] += e * (m2 + Q * Q * m0);
+    out[3] += e * (m4 + ((P - Q) * (P - Q) - 2.0 * P * Q) * m2 + P * P * Q * Q * m0);
+  }
+}
+
+/* Overlaps of the contracted Bloch orbitals over the cell (Hermitian): the same term-by-term
+ * product of axis moments as the real contracted basis, each axis an image sum with Bloch
+ * weights (S_out: n_p x n_p complex as pairs). */
+void o_coverlap_contracted(int n_p, double L, const double theta[3], const double* R, double eta, double* S_out) {
+  for (int a = 0; a < n_p; ++a)
+    for (int b = 0; b < n_p; ++b) {
+      cplx m11[3][4], m12[3][4], m21[3][4], m22[3][4];
+      for (int m = 0; m < 3; ++m) {
+        const double d = R[3 * b + m] - R[3 * a + m];
+        cmoments_1d(O_Z1, O_Z1, d, L, theta[m], m11[m]);
+        cmoments_1d(O_Z1, O_Z2, d, L, theta[m], m12[m]);
+        cmoments_1d(O_Z2, O_Z1, d, L, theta[m], m21[m]);
+        cmoments_1d(O_Z2, O_Z2, d, L, theta[m], m22[m]);
+      }
+      const cplx s11 = m11[0][0] * m11[1][0] * m11[2][0];
+      cplx s12 = 0.0, s21 = 0.0, s22 = 0.0;
+      for (int m = 0; m < 3; ++m) {
+        cplx p12 = m12[m][2], p21 = m21[m][1], p22 = m22[m][3];
+        for (int q = 0; q < 3; ++q)
+          if (q != m) { p12 *= m12[q][0]; p21 *= m21[q][0]; p22 *= m22[q][0]; }
+        s12 += p12;
+        s21 += p21;
+        s22 += p22;
+        for (int m2 = 0; m2 < 3; ++m2) {
+          if (m2 == m) continue;
+          cplx pc = m22[m][1] * m22[m2][2];
+          for (int q = 0; q < 3; ++q)
+            if (q != m && q != m2) pc *= m22[q][0];
+          s22 += pc;
+        }
+      }
+      const cplx v = s11 + eta * (s12 + s21) + eta * eta * s22;
       S_out[2 * (a * n_p + b)] = creal(v);
       S_out[2 * (a * n_p + b) + 1] = cimag(v);
     }
@@ -155,11 +276,26 @@ static void cjacobi_eigen(int n, cplx* A, cplx* V) {
 
 /* Hueckel orbitals of the twisted basis: H = -S~ with S~_ab = S_ab / sqrt(S_aa S_bb), the n_orb
  * lowest eigenvectors v of the Hermitian H, C_ak = v_ak / sqrt(S_aa) (complex, as pairs). */
+static int chuckel_from_overlap(int n_p, double* Sd, int n_orb, double* C, double* evals);
 int o_chuckel(int n_p, double L, const double theta[3], const double* R, const double* zeta, int n_orb, double* C,
               double* evals) {
   if (n_orb > n_p || n_orb < 0) return O_EINVAL;
   double* Sd = malloc(sizeof(double) * 2 * n_p * n_p);
   o_coverlap(n_p, L, theta, R, zeta, Sd);
+  return chuckel_from_overlap(n_p, Sd, n_orb, C, evals);
+}
+
+/* The same on the contracted basis. */
+int o_chuckel_contracted(int n_p, double L, const double theta[3], const double* R, double eta, int n_orb, double* C,
+                         double* evals) {
+  if (n_orb > n_p || n_orb < 0) return O_EINVAL;
+  double* Sd = malloc(sizeof(double) * 2 * n_p * n_p);
+  o_coverlap_contracted(n_p, L, theta, R, eta, Sd);
+  return chuckel_from_overlap(n_p, Sd, n_orb, C, evals);
+}
+
+/* Hueckel orbitals from the overlap Sd (complex pairs; freed here). */
+static int chuckel_from_overlap(int n_p, double* Sd, int n_orb, double* C, double* evals) {
   cplx* H = malloc(sizeof(cplx) * n_p * n_p);
   cplx* V = malloc(sizeof(cplx) * n_p * n_p);
   for (int a = 0; a < n_p; ++a)
@@ -258,7 +394,7 @@ static void cmatmul(int n, const cplx* A, const cplx* B, cplx* C) {
  * derivatives coupling to the real part of grad ln D (o_jastrow_dR).  Single Gaussians only. */
 int o_clocal(const osys* s, const double theta[3], const double* Cd, const double* x, double* lnpsi, double* phase,
              double* EL, double* dlnpsi_dR, double* dEL_dR) {
-  if (s->contracted || s->basis_kind != OB_PERIODIC_GAUSS) return O_EINVAL;
+  if (s->basis_kind != OB_PERIODIC_GAUSS) return O_EINVAL;
   const int np = s->n_p, ne = s->n_up + s->n_dn, no = s->n_orb, n3 = 3 * np;
   double U;
   double* gU = malloc(sizeof(double) * 3 * ne);
@@ -378,7 +514,7 @@ static void cmo_row(const osys* s, const double theta[3], const double* Cd, cons
 int o_cvmc_run_from(const osys* s, const double theta[3], const double* Cd, int W, uint32_t w0, double* x,
                     int n_equil, int n_meas, double delta, uint32_t seed, uint32_t traj, uint32_t step, double* sums,
                     int64_t* n_acc, int n_threads) {
-  if (s->contracted) return O_EINVAL;
+
   const int ne = s->n_up + s->n_dn, n3 = 3 * s->n_p, nsum = 2 + 3 * n3;
   int err = 0;
 #ifdef _OPENMP

@@ -291,3 +291,116 @@ def test_monkhorst_pack_mesh():
     assert th.shape == (64, 3)
     assert np.allclose(np.sort(np.unique(np.round(th[:, 0], 12))), [-3 * np.pi / 4, -np.pi / 4, np.pi / 4, 3 * np.pi / 4])
     assert np.allclose(th.sum(0), 0.0)                  # symmetric about the origin
+
+
+# ---- the contracted basis (phi_1 + eta phi_2) under general twists, in a box with Z2 (1.5 L)^2 >= 36
+ETA = 0.1
+
+
+def _cbox():
+    return small_system(6, 2.5, seed=4)
+
+
+def _csys(oracle, wl, theta, **kw):
+    Cc, _ = oracle.chuckel_contracted(wl.R, wl.L, wl.n // 2, ETA, theta)
+    return oracle.CSystem(wl.R, wl.zeta, Cc, theta, wl.L, eta=ETA, **kw)
+
+
+def test_contracted_bloch_basis_reduces_to_the_real_one_at_real_twists(oracle):
+    wl = _cbox()
+    assert oracle.Z2 * (1.5 * wl.L) ** 2 >= 36.0
+    rng = np.random.default_rng(2)
+    for tw in range(8):
+        theta = np.array([np.pi * ((tw >> m) & 1) for m in range(3)])
+        sc = oracle.CSystem(wl.R, wl.zeta, np.eye(wl.n, 3, dtype=complex), theta, wl.L, eta=ETA)
+        sr = oracle.System(wl.R, wl.zeta, np.eye(wl.n, 3), L=wl.L, twist=tw, eta=ETA)
+        for _ in range(4):
+            a = int(rng.integers(wl.n))
+            r = wl.R[a] + rng.uniform(-1.5 * wl.L, 1.5 * wl.L, 3)
+            c, v = sc.cbasis(a, r), sr.basis(a, r)
+            assert np.allclose(c.real, v, rtol=1e-12, atol=1e-14 * np.max(np.abs(v)))
+            assert np.max(np.abs(c.imag)) < 1e-13 * np.max(np.abs(v))
+
+
+@pytest.mark.parametrize("theta", THETAS)
+def test_contracted_bloch_condition(oracle, theta):
+    wl = _cbox()
+    s = oracle.CSystem(wl.R, wl.zeta, np.eye(wl.n, 3, dtype=complex), np.array(theta), wl.L, eta=ETA)
+    rng = np.random.default_rng(3)
+    for _ in range(4):
+        a = int(rng.integers(wl.n))
+        r = rng.uniform(0.0, wl.L, 3)
+        f0 = s.cbasis(a, r)
+        for m in range(3):
+            r2 = r.copy()
+            r2[m] += wl.L
+            assert np.allclose(s.cbasis(a, r2), np.exp(1j * theta[m]) * f0, rtol=1e-12,
+                               atol=1e-13 * np.max(np.abs(f0)))
+
+
+@pytest.mark.parametrize("theta", THETAS)
+def test_contracted_overlap_equals_cell_quadrature(oracle, theta):
+    """The contracted overlaps (axis moments with Bloch weights) against the trapezoid rule over
+    the cell of conj(phi_a) phi_b; Hermitian; the Hueckel orbitals against numpy's eigh."""
+    wl = _cbox()
+    th = np.array(theta)
+    s = oracle.CSystem(wl.R, wl.zeta, np.eye(wl.n, 3, dtype=complex), th, wl.L, eta=ETA)
+    ng = 40
+    g = (np.arange(ng) + 0.5) * wl.L / ng
+    pts = np.array(list(itertools.product(g, g, g)))
+    phi = s.cbasis_values(pts)
+    Sq = (phi.conj().T @ phi) * (wl.L / ng) ** 3
+    S = oracle.coverlap_contracted(wl.R, wl.L, ETA, th)
+    assert np.max(np.abs(S - Sq)) < 1e-9 * np.max(np.abs(S))
+    assert np.max(np.abs(S - S.conj().T)) < 1e-15 * np.max(np.abs(S))
+    Cc, ev = oracle.chuckel_contracted(wl.R, wl.L, 3, ETA, th)
+    assert np.allclose(Cc.conj().T @ S @ Cc, np.diag(-ev[:3]), atol=1e-12)
+    d = np.sqrt(np.real(np.diag(S)))
+    w, v = np.linalg.eigh(-S / np.outer(d, d))
+    Cn = v[:, :3] / d[:, None]
+    assert np.allclose(Cc @ Cc.conj().T, Cn @ Cn.conj().T, atol=1e-12)
+
+
+@pytest.mark.parametrize("jas", JAS)
+def test_contracted_complex_wavefunction_at_zero_twist_is_the_real_one(oracle, jas):
+    wl = _cbox()
+    s = _csys(oracle, wl, np.zeros(3), **jas)
+    Cr, _ = oracle.huckel_contracted(wl.R, wl.L, 3, ETA)
+    sr = oracle.System(wl.R, wl.zeta, Cr, L=wl.L, eta=ETA, **jas)
+    assert np.allclose(s.Cc @ s.Cc.conj().T, Cr @ Cr.T, atol=1e-12)
+    for x in wl.electrons(W=2, seed_offset=9):
+        a, b = s.local(x), sr.local(x)
+        assert a["lnpsi"] == pytest.approx(b["lnpsi"], rel=1e-12, abs=1e-12)
+        assert a["EL"] == pytest.approx(b["EL"], rel=1e-12)
+        assert np.allclose(a["dlnpsi"], b["dlnpsi"], rtol=1e-10, atol=1e-11)
+        assert np.allclose(a["dEL"], b["dEL"], rtol=1e-10, atol=1e-10)
+
+
+@pytest.mark.parametrize("jas", JAS)
+def test_contracted_complex_kinetic_energy_and_proton_derivatives_by_fd(oracle, jas):
+    wl = _cbox()
+    th = np.array(THETAS[1])
+    s = _csys(oracle, wl, th, **jas)
+    x = wl.electrons(W=1, seed_offset=5)[0]
+    r = s.local(x)
+    V, _, _ = s.potential(x)
+    psi = lambda y: np.exp(s.local(y, False)["lnpsi"] + 1j * s.local(y, False)["phase"])
+    p0 = psi(x)
+    h = 1e-4
+    lap = 0j
+    for e in range(wl.n):
+        for m in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[e, m] += h
+            xm[e, m] -= h
+            lap += (psi(xp) - 2 * p0 + psi(xm)) / (h * h)
+    assert r["EL"] - V == pytest.approx(float(np.real(-0.5 * lap / p0)), rel=2e-6, abs=2e-6)
+    hr = 1e-5
+    for t in range(0, 3 * wl.n, 2):
+        Rp, Rm = wl.R.reshape(-1).copy(), wl.R.reshape(-1).copy()
+        Rp[t] += hr
+        Rm[t] -= hr
+        a = oracle.CSystem(Rp.reshape(-1, 3), wl.zeta, s.Cc, th, wl.L, eta=ETA, **jas).local(x, False)
+        b = oracle.CSystem(Rm.reshape(-1, 3), wl.zeta, s.Cc, th, wl.L, eta=ETA, **jas).local(x, False)
+        assert r["dlnpsi"][t] == pytest.approx((a["lnpsi"] - b["lnpsi"]) / (2 * hr), rel=1e-6, abs=1e-7)
+        assert r["dEL"][t] == pytest.approx((a["EL"] - b["EL"]) / (2 * hr), rel=1e-6, abs=1e-6)
