@@ -93,10 +93,12 @@ typedef struct {
                          determinants are complex, sampling follows |psi|^2 and the estimators take
                          the real part of E_L and of its proton derivative.  The one-body and
                          three-body Jastrow terms combine with it (their proton derivatives take the
-                         real part of grad ln D).  Requires precision VMC_FP64, twist = 0, the single
-                         Gaussian basis and N_sigma <= 64 (else VMC_EINVAL).  The
+                         real part of grad ln D), and so does the contracted basis (contracted = 1:
+                         its three Cartesian factors Bloch-summed alike).  Requires precision
+                         VMC_FP64, twist = 0 and N_sigma <= 64 (else VMC_EINVAL).  The
                          orbital coefficients C are then complex, N x N/2 (re, im) pairs of doubles
-                         (vmc_huckel_params_theta); Binv holds complex inverses (twice the bytes).
+                         (vmc_huckel_params_theta, or vmc_huckel_params_theta_contracted on the
+                         contracted basis); Binv holds complex inverses (twice the bytes).
                          Both spins use the same twist.  Not for the server (VMC_EINVAL).
                          0: real orbitals, twist as above */
   double theta[3];    /* twist angles per axis, radians (general_twist = 1 only; finite) */
@@ -104,8 +106,9 @@ typedef struct {
                          orbital per proton, phi_1 + eta phi_2 with phi_1 = e^{-Z1 r^2},
                          phi_2 = r^2 e^{-Z2 r^2}, Z1 = 0.6066825, Z2 = 0.3382168, image-summed like the
                          single Gaussian; zeta is then not used (but must still be a valid pointer).
-                         C must come from vmc_huckel_params_contracted.  Requires twist = 0,
-                         general_twist = 0, N_sigma <= 64 and a box with Z2 (1.5 L)^2 >= 36
+                         C must come from vmc_huckel_params_contracted (with a general twist: from
+                         vmc_huckel_params_theta_contracted).  Requires twist = 0 (the real twists
+                         through general_twist), N_sigma <= 64 and a box with Z2 (1.5 L)^2 >= 36
                          (L >= 6.88 bohr: the images |n| <= 1 of the diffuse phi_2 then reach
                          FP64 resolution); not for the server.  Else VMC_EINVAL.
                          0: one s-Gaussian e^{-zeta_a r^2} per proton */
@@ -385,6 +388,12 @@ int vmc_huckel_params_contracted(int n_protons, double box_L, double eta, const 
  * VMC_ENOCONV if the QR iteration does not converge. */
 int vmc_huckel_params_theta(int n_protons, double box_L, const double* theta, const double* R, const double* zeta,
                             double* C_out);
+/* The same on the contracted basis (phi_1 + eta phi_2 per proton, the SI's exponents Z1, Z2):
+ * the overlaps of vmc_huckel_params_contracted with each axis's image k weighted e^{-i theta k};
+ * C_out: N x N/2 complex (re, im) pairs.  VMC_EINVAL for odd or too small N, L <= 0, non-finite
+ * theta, eta or R; VMC_ENOCONV if the QR iteration does not converge. */
+int vmc_huckel_params_theta_contracted(int n_protons, double box_L, const double* theta, double eta, const double* R,
+                                       double* C_out);
 
 /* Twist averaging (SI: the paper averages its estimates over a mesh of twists): n_tw
  * independent runs of one box, one per twist (each its own trajectory, orbitals and

@@ -332,33 +332,10 @@ extern "C" int vmc_huckel_params_contracted(int n, double L, double eta, const d
   return VMC_OK;
 }
 
-extern "C" int vmc_huckel_params_theta(int n, double L, const double* theta, const double* R, const double* zeta,
-                                       double* C_out) {
-  if (n < 2 || (n & 1) || !(L > 0.0) || !theta || !R || !zeta || !C_out) return VMC_EINVAL;
-  for (int m = 0; m < 3; ++m)
-    if (!std::isfinite(theta[m])) return VMC_EINVAL;
-  for (int i = 0; i < 3 * n; ++i)
-    if (!std::isfinite(R[i])) return VMC_EINVAL;
-  for (int i = 0; i < n; ++i)
-    if (!(zeta[i] > 0.0) || !std::isfinite(zeta[i])) return VMC_EINVAL;
+// Hueckel orbitals from the Hermitian overlap S (n x n): H = -S_ab / sqrt(S_aa S_bb) through its real
+// symmetric embedding of order 2n, the n/2 lowest eigenvectors as complex (re, im) pairs in C_out.
+static int hermitian_huckel(int n, const std::vector<std::complex<double>>& S, double* C_out) {
   using cplx = std::complex<double>;
-  // S_ab = (pi/(za+zb))^{3/2} prod_m sum_k e^{-i theta_m k} e^{-mu (d_m + k L)^2}, d = R_a - R_b taken at
-  // its minimum image d - j L, which multiplies the sum by e^{i theta_m j}
-  std::vector<cplx> S((size_t)n * n);
-  for (int a = 0; a < n; ++a)
-    for (int b = 0; b < n; ++b) {
-      const double za = zeta[a], zb = zeta[b], mu = za * zb / (za + zb);
-      cplx v = std::pow(M_PI / (za + zb), 1.5);
-      for (int ax = 0; ax < 3; ++ax) {
-        double dd = R[3 * a + ax] - R[3 * b + ax];
-        const double j = std::floor(dd / L + 0.5);
-        dd -= L * j;
-        cplx sum = 0.0;
-        for (int k = -3; k <= 3; ++k) sum += std::polar(std::exp(-mu * (dd + k * L) * (dd + k * L)), -theta[ax] * k);
-        v *= sum * std::polar(1.0, theta[ax] * j);
-      }
-      S[(size_t)a * n + b] = v;
-    }
   // H = -S_ab / sqrt(S_aa S_bb) (Hermitian) through its real symmetric embedding of order 2n
   const int n2 = 2 * n;
   std::vector<double> M((size_t)n2 * n2), Q;
@@ -410,6 +387,99 @@ extern "C" int vmc_huckel_params_theta(int n, double L, const double* theta, con
     }
   }
   return VMC_OK;
+}
+
+
+extern "C" int vmc_huckel_params_theta(int n, double L, const double* theta, const double* R, const double* zeta,
+                                       double* C_out) {
+  if (n < 2 || (n & 1) || !(L > 0.0) || !theta || !R || !zeta || !C_out) return VMC_EINVAL;
+  for (int m = 0; m < 3; ++m)
+    if (!std::isfinite(theta[m])) return VMC_EINVAL;
+  for (int i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(R[i])) return VMC_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!(zeta[i] > 0.0) || !std::isfinite(zeta[i])) return VMC_EINVAL;
+  using cplx = std::complex<double>;
+  // S_ab = (pi/(za+zb))^{3/2} prod_m sum_k e^{-i theta_m k} e^{-mu (d_m + k L)^2}, d = R_a - R_b taken at
+  // its minimum image d - j L, which multiplies the sum by e^{i theta_m j}
+  std::vector<cplx> S((size_t)n * n);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const double za = zeta[a], zb = zeta[b], mu = za * zb / (za + zb);
+      cplx v = std::pow(M_PI / (za + zb), 1.5);
+      for (int ax = 0; ax < 3; ++ax) {
+        double dd = R[3 * a + ax] - R[3 * b + ax];
+        const double j = std::floor(dd / L + 0.5);
+        dd -= L * j;
+        cplx sum = 0.0;
+        for (int k = -3; k <= 3; ++k) sum += std::polar(std::exp(-mu * (dd + k * L) * (dd + k * L)), -theta[ax] * k);
+        v *= sum * std::polar(1.0, theta[ax] * j);
+      }
+      S[(size_t)a * n + b] = v;
+    }
+  return hermitian_huckel(n, S, C_out);
+}
+
+// Per axis of the contracted overlap under a twist: the terms of axis_exponent_derivs with image k of
+// d = R_a - R_b (taken at its minimum image d - j L) weighted e^{-i theta k}, times e^{i theta j}.
+static void axis_exponent_derivs_theta(double al, double be, double d, double L, double theta,
+                                       std::complex<double> out[4]) {
+  const double p = al + be, mu = al * be / p, c = std::sqrt(M_PI / p);
+  const double ka = be * be / (p * p), kb = al * al / (p * p);
+  const double j = std::floor(d / L + 0.5);
+  const double dd = d - L * j;
+  for (int q = 0; q < 4; ++q) out[q] = 0.0;
+  for (int k = -4; k <= 4; ++k) {
+    const double dn = dd + k * L, d2 = dn * dn, e = c * std::exp(-mu * d2);
+    const double fa = -0.5 / p - ka * d2, fb = -0.5 / p - kb * d2;
+    const double fab = 0.5 / (p * p) - 2.0 * be * d2 / (p * p) + 2.0 * be * be * d2 / (p * p * p);
+    const std::complex<double> w = std::polar(1.0, -theta * k);
+    out[0] += w * e;
+    out[1] += w * (e * fa);
+    out[2] += w * (e * fb);
+    out[3] += w * (e * (fa * fb + fab));
+  }
+  const std::complex<double> ph = std::polar(1.0, theta * j);
+  for (int q = 0; q < 4; ++q) out[q] *= ph;
+}
+
+extern "C" int vmc_huckel_params_theta_contracted(int n, double L, const double* theta, double eta, const double* R,
+                                                  double* C_out) {
+  if (n < 2 || (n & 1) || !(L > 0.0) || !theta || !R || !C_out || !std::isfinite(eta)) return VMC_EINVAL;
+  for (int m = 0; m < 3; ++m)
+    if (!std::isfinite(theta[m])) return VMC_EINVAL;
+  for (int i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(R[i])) return VMC_EINVAL;
+  using cplx = std::complex<double>;
+  const double z1 = 0.6066825, z2 = 0.3382168;
+  std::vector<cplx> S((size_t)n * n);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      cplx s11[3][4], s12[3][4], s21[3][4], s22[3][4];
+      for (int m = 0; m < 3; ++m) {
+        const double d = R[3 * a + m] - R[3 * b + m];
+        axis_exponent_derivs_theta(z1, z1, d, L, theta[m], s11[m]);
+        axis_exponent_derivs_theta(z1, z2, d, L, theta[m], s12[m]);
+        axis_exponent_derivs_theta(z2, z1, d, L, theta[m], s21[m]);
+        axis_exponent_derivs_theta(z2, z2, d, L, theta[m], s22[m]);
+      }
+      // as vmc_huckel_params_contracted, with complex axis factors
+      cplx v = s11[0][0] * s11[1][0] * s11[2][0];
+      cplx gh = 0.0, hg = 0.0, hh = 0.0;
+      for (int m = 0; m < 3; ++m) {
+        const int m1 = (m + 1) % 3, m2 = (m + 2) % 3;
+        gh -= s12[m][2] * s12[m1][0] * s12[m2][0];
+        hg -= s21[m][1] * s21[m1][0] * s21[m2][0];
+        hh += s22[m][3] * s22[m1][0] * s22[m2][0];
+        for (int q = 0; q < 3; ++q)
+          if (q != m) {
+            const int r = 3 - m - q;
+            hh += s22[m][1] * s22[q][2] * s22[r][0];
+          }
+      }
+      S[(size_t)a * n + b] = v + eta * (gh + hg) + eta * eta * hh;
+    }
+  return hermitian_huckel(n, S, C_out);
 }
 
 extern "C" int vmc_server_admit_count(size_t budget, size_t resident, int n_queued, const size_t* bytes) {

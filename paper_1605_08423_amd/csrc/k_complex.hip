@@ -88,6 +88,121 @@ __device__ __forceinline__ cd cphi(double rx, double ry, double rz, const double
   return cmul(cmul(g[0][0], g[1][0]), g[2][0]);
 }
 
+// The SI's contracted orbital phi_1 + eta phi_2 under the twist: per axis the Bloch factors of
+// g1 = e^{-Z1 t^2}, g2 = e^{-Z2 t^2} and h2 = t^2 e^{-Z2 t^2} with their first NDER derivatives,
+// each taken like cbasis_axis (images n = -1, 0, 1 at the minimum image weighted e^{-i theta n},
+// times e^{i theta k}); the orbital is g1 g1 g1 + eta (h2 g2 g2 + g2 h2 g2 + g2 g2 h2).
+template <int NDER>
+__device__ __forceinline__ void bloch_factor(const double h[3][4], double k, const TwistArgs& tw, int m, cd g[4]) {
+  const double c = tw.c[m], s = tw.s[m];
+#pragma unroll
+  for (int q = 0; q <= NDER; ++q) g[q] = {h[1][q] + c * (h[0][q] + h[2][q]), s * (h[0][q] - h[2][q])};
+  if (k != 0.0) {
+    double pc, ps;
+    if (k == 1.0) { pc = c; ps = s; }
+    else if (k == -1.0) { pc = c; ps = -s; }
+    else sincos(tw.th[m] * k, &ps, &pc);
+#pragma unroll
+    for (int q = 0; q <= NDER; ++q) g[q] = cmul(g[q], cd{pc, ps});
+  }
+}
+
+template <int NDER>
+__device__ __forceinline__ void ccontracted_axis(double d, double L, double invL, const TwistArgs& tw, int m, cd g1[4],
+                                                 cd g2[4], cd h2[4]) {
+  const double k = floor(d * invL + 0.5);
+  const double x = d - L * k, z1 = kZ1, z2 = kZ2;
+  double a1[3][4], a2[3][4], b2[3][4];
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    const double t = x + (double)(n - 1) * L, t2 = t * t;
+    const double e1 = exp(-z1 * t2), e2 = exp(-z2 * t2);
+    a1[n][0] = e1;
+    a2[n][0] = e2;
+    b2[n][0] = t2 * e2;
+    if (NDER >= 1) {
+      a1[n][1] = -2.0 * z1 * t * e1;
+      a2[n][1] = -2.0 * z2 * t * e2;
+      b2[n][1] = (2.0 * t - 2.0 * z2 * t2 * t) * e2;
+    }
+    if (NDER >= 2) {
+      a1[n][2] = (4.0 * z1 * z1 * t2 - 2.0 * z1) * e1;
+      a2[n][2] = (4.0 * z2 * z2 * t2 - 2.0 * z2) * e2;
+      b2[n][2] = (2.0 - 10.0 * z2 * t2 + 4.0 * z2 * z2 * t2 * t2) * e2;
+    }
+    if (NDER >= 3) {
+      a1[n][3] = (-8.0 * z1 * z1 * z1 * t2 * t + 12.0 * z1 * z1 * t) * e1;
+      a2[n][3] = (-8.0 * z2 * z2 * z2 * t2 * t + 12.0 * z2 * z2 * t) * e2;
+      b2[n][3] = (-24.0 * z2 * t + 36.0 * z2 * z2 * t2 * t - 8.0 * z2 * z2 * z2 * t2 * t2 * t) * e2;
+    }
+  }
+  bloch_factor<NDER>(a1, k, tw, m, g1);
+  bloch_factor<NDER>(a2, k, tw, m, g2);
+  bloch_factor<NDER>(b2, k, tw, m, h2);
+}
+
+// Value, gradient, Hessian and gradient of the Laplacian of a complex basis function.
+struct CBasisD {
+  cd v, gx, gy, gz, hxx, hyy, hzz, hxy, hxz, hyz, glx, gly, glz;
+};
+// Adds w times the components of the product f[0](x) f[1](y) f[2](z) (FULL: all; else value
+// and gradient).
+template <bool FULL>
+__device__ __forceinline__ void cprod_terms(const cd (&f)[3][4], double w, CBasisD& o) {
+  const cd p00 = cmul(f[1][0], f[2][0]), p01 = cmul(f[0][0], f[2][0]), p02 = cmul(f[0][0], f[1][0]);
+  auto add = [w](cd& acc, cd v) { acc = cadd(acc, cd{w * v.r, w * v.i}); };
+  add(o.v, cmul(f[0][0], p00));
+  add(o.gx, cmul(f[0][1], p00));
+  add(o.gy, cmul(f[1][1], p01));
+  add(o.gz, cmul(f[2][1], p02));
+  if (FULL) {
+    add(o.hxx, cmul(f[0][2], p00));
+    add(o.hyy, cmul(f[1][2], p01));
+    add(o.hzz, cmul(f[2][2], p02));
+    add(o.hxy, cmul(cmul(f[0][1], f[1][1]), f[2][0]));
+    add(o.hxz, cmul(cmul(f[0][1], f[1][0]), f[2][1]));
+    add(o.hyz, cmul(cmul(f[0][0], f[1][1]), f[2][1]));
+    add(o.glx, cadd(cmul(f[0][3], p00), cmul(f[0][1], cadd(cmul(f[1][2], f[2][0]), cmul(f[1][0], f[2][2])))));
+    add(o.gly, cadd(cmul(f[1][3], p01), cmul(f[1][1], cadd(cmul(f[0][2], f[2][0]), cmul(f[0][0], f[2][2])))));
+    add(o.glz, cadd(cmul(f[2][3], p02), cmul(f[2][1], cadd(cmul(f[0][2], f[1][0]), cmul(f[0][0], f[1][2])))));
+  }
+}
+
+template <bool FULL>
+__device__ __forceinline__ CBasisD ccontracted_derivs(double dx, double dy, double dz, double eta, double L,
+                                                      double invL, const TwistArgs& tw) {
+  constexpr int ND = FULL ? 3 : 1;
+  cd g1[3][4], g2[3][4], h2[3][4];
+  ccontracted_axis<ND>(dx, L, invL, tw, 0, g1[0], g2[0], h2[0]);
+  ccontracted_axis<ND>(dy, L, invL, tw, 1, g1[1], g2[1], h2[1]);
+  ccontracted_axis<ND>(dz, L, invL, tw, 2, g1[2], g2[2], h2[2]);
+  const cd z = {0.0, 0.0};
+  CBasisD o = {z, z, z, z, z, z, z, z, z, z, z, z, z};
+  cprod_terms<FULL>(g1, 1.0, o);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    cd f[3][4];
+#pragma unroll
+    for (int mm = 0; mm < 3; ++mm)
+#pragma unroll
+      for (int q = 0; q <= ND; ++q) f[mm][q] = (mm == m) ? h2[mm][q] : g2[mm][q];
+    cprod_terms<FULL>(f, eta, o);
+  }
+  return o;
+}
+
+__device__ __forceinline__ cd ccontracted_value(double rx, double ry, double rz, const double* Ra, double eta,
+                                                double L, double invL, const TwistArgs& tw) {
+  cd g1[3][4], g2[3][4], h2[3][4];
+  ccontracted_axis<0>(rx - Ra[0], L, invL, tw, 0, g1[0], g2[0], h2[0]);
+  ccontracted_axis<0>(ry - Ra[1], L, invL, tw, 1, g1[1], g2[1], h2[1]);
+  ccontracted_axis<0>(rz - Ra[2], L, invL, tw, 2, g1[2], g2[2], h2[2]);
+  const cd v1 = cmul(cmul(g1[0][0], g1[1][0]), g1[2][0]);
+  const cd v2 = cadd(cadd(cmul(cmul(h2[0][0], g2[1][0]), g2[2][0]), cmul(cmul(g2[0][0], h2[1][0]), g2[2][0])),
+                     cmul(cmul(g2[0][0], g2[1][0]), h2[2][0]));
+  return {v1.r + eta * v2.r, v1.i + eta * v2.i};
+}
+
 __device__ __forceinline__ cd ld_c(const double* p, size_t idx) {
   const double2 v = *reinterpret_cast<const double2*>(p + 2 * idx);
   return {v.x, v.y};
@@ -127,7 +242,7 @@ struct CSweepLds {
   static constexpr size_t bytes(bool moves) { return sizeof(double) * (moves ? mp + 2 * (size_t)NSP * NSP : mp); }
 };
 
-template <int NS, bool MOVES>
+template <int NS, bool MOVES, bool CB>
 __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, TwistArgs tw, int refresh) {
   using LY = CSweepLds<NS>;
   constexpr int N = 2 * NS, NSP = LY::NSP, LDA = LY::LDA, P = LY::P, CH = LY::CH, RPT = LY::RPT;
@@ -196,7 +311,10 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
       for (int kk = 0; kk < KS; ++kk) {
         const int c = kk * 4 + (lane >> 4);
         cd ph = {0.0, 0.0};
-        if (rok && c < N) ph = cphi(rx, ry, rz, a.R + 3 * c, a.zeta[c], L, invL, tw);
+        if (rok && c < N) {
+          if constexpr (CB) ph = ccontracted_value(rx, ry, rz, a.R + 3 * c, a.eta, L, invL, tw);
+          else ph = cphi(rx, ry, rz, a.R + 3 * c, a.zeta[c], L, invL, tw);
+        }
 #pragma unroll
         for (int tc = 0; tc < TC; ++tc) {
           const int col = tc * 16 + (lane & 15);
@@ -458,7 +576,7 @@ __device__ __forceinline__ void cgemm(const double* A, int lda, int MA, const do
 //   Re T_L = Re sum X_ia B_ai - 1/2 sum_i (lap_i U + |grad_i U|^2),  X_ia = -1/2 [lap phi_a + 2 grad phi_a . grad_i U]
 //   d ln|psi|/dR_b = -Re sum_i B_bi grad phi_b(r_i)
 //   d Re T_L/dR_b = Re sum_i [1/2 (grad lap phi_b + 2 Hess phi_b . grad_i U) B_bi + grad phi_b(r_i) W_bi]
-template <int NS>
+template <int NS, bool CB>
 __global__ __launch_bounds__(256, 1) void k_cslater_sample(MeasureArgs m, TwistArgs tw) {
   using LY = CSlaterLay<NS>;
   constexpr int N = 2 * NS, NSP = LY::NSP, NP = LY::NP, H = LY::H, HJ = LY::HJ;
@@ -592,14 +710,22 @@ __global__ __launch_bounds__(256, 1) void k_cslater_sample(MeasureArgs m, TwistA
         const int c0 = hg * N / HG, c1 = (hg + 1) * N / HG;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (int c = c0; c < c1; ++c) {
-          cd g[3][4];
-          cbasis_axis<1>(pos[3 * e] - m.R[3 * c], m.zeta[c], L, invL, tw, 0, g[0]);
-          cbasis_axis<1>(pos[3 * e + 1] - m.R[3 * c + 1], m.zeta[c], L, invL, tw, 1, g[1]);
-          cbasis_axis<1>(pos[3 * e + 2] - m.R[3 * c + 2], m.zeta[c], L, invL, tw, 2, g[2]);
           const cd b = ld_c(Bs, (size_t)c * NSP + i);
-          s0 += remul(b, cmul(cmul(g[0][1], g[1][0]), g[2][0]));
-          s1 += remul(b, cmul(cmul(g[0][0], g[1][1]), g[2][0]));
-          s2 += remul(b, cmul(cmul(g[0][0], g[1][0]), g[2][1]));
+          if constexpr (CB) {
+            const CBasisD q = ccontracted_derivs<false>(pos[3 * e] - m.R[3 * c], pos[3 * e + 1] - m.R[3 * c + 1],
+                                                        pos[3 * e + 2] - m.R[3 * c + 2], m.eta, L, invL, tw);
+            s0 += remul(b, q.gx);
+            s1 += remul(b, q.gy);
+            s2 += remul(b, q.gz);
+          } else {
+            cd g[3][4];
+            cbasis_axis<1>(pos[3 * e] - m.R[3 * c], m.zeta[c], L, invL, tw, 0, g[0]);
+            cbasis_axis<1>(pos[3 * e + 1] - m.R[3 * c + 1], m.zeta[c], L, invL, tw, 1, g[1]);
+            cbasis_axis<1>(pos[3 * e + 2] - m.R[3 * c + 2], m.zeta[c], L, invL, tw, 2, g[2]);
+            s0 += remul(b, cmul(cmul(g[0][1], g[1][0]), g[2][0]));
+            s1 += remul(b, cmul(cmul(g[0][0], g[1][1]), g[2][0]));
+            s2 += remul(b, cmul(cmul(g[0][0], g[1][0]), g[2][1]));
+          }
         }
         gp[3 * u] = s0; gp[3 * u + 1] = s1; gp[3 * u + 2] = s2;
       }
@@ -618,19 +744,28 @@ __global__ __launch_bounds__(256, 1) void k_cslater_sample(MeasureArgs m, TwistA
         const int i = h + H * s;
         if (i >= NS) continue;
         const int e = sp * NS + i;
-        cd g[3][4];
-        cbasis_axis<3>(pos[3 * e] - Ra0, za, L, invL, tw, 0, g[0]);
-        cbasis_axis<3>(pos[3 * e + 1] - Ra1, za, L, invL, tw, 1, g[1]);
-        cbasis_axis<3>(pos[3 * e + 2] - Ra2, za, L, invL, tw, 2, g[2]);
-        const cd p00 = cmul(g[1][0], g[2][0]), p01 = cmul(g[0][0], g[2][0]), p02 = cmul(g[0][0], g[1][0]);
-        const cd gx = cmul(g[0][1], p00), gy = cmul(g[1][1], p01), gz = cmul(g[2][1], p02);
-        const cd hxx = cmul(g[0][2], p00), hyy = cmul(g[1][2], p01), hzz = cmul(g[2][2], p02);
-        const cd hxy = cmul(cmul(g[0][1], g[1][1]), g[2][0]), hxz = cmul(cmul(g[0][1], g[1][0]), g[2][1]);
-        const cd hyz = cmul(cmul(g[0][0], g[1][1]), g[2][1]);
+        cd gx, gy, gz, hxx, hyy, hzz, hxy, hxz, hyz, glx, gly, glz;
+        if constexpr (CB) {
+          const CBasisD q = ccontracted_derivs<true>(pos[3 * e] - Ra0, pos[3 * e + 1] - Ra1, pos[3 * e + 2] - Ra2, m.eta,
+                                                     L, invL, tw);
+          gx = q.gx; gy = q.gy; gz = q.gz;
+          hxx = q.hxx; hyy = q.hyy; hzz = q.hzz; hxy = q.hxy; hxz = q.hxz; hyz = q.hyz;
+          glx = q.glx; gly = q.gly; glz = q.glz;
+        } else {
+          cd g[3][4];
+          cbasis_axis<3>(pos[3 * e] - Ra0, za, L, invL, tw, 0, g[0]);
+          cbasis_axis<3>(pos[3 * e + 1] - Ra1, za, L, invL, tw, 1, g[1]);
+          cbasis_axis<3>(pos[3 * e + 2] - Ra2, za, L, invL, tw, 2, g[2]);
+          const cd p00 = cmul(g[1][0], g[2][0]), p01 = cmul(g[0][0], g[2][0]), p02 = cmul(g[0][0], g[1][0]);
+          gx = cmul(g[0][1], p00); gy = cmul(g[1][1], p01); gz = cmul(g[2][1], p02);
+          hxx = cmul(g[0][2], p00); hyy = cmul(g[1][2], p01); hzz = cmul(g[2][2], p02);
+          hxy = cmul(cmul(g[0][1], g[1][1]), g[2][0]); hxz = cmul(cmul(g[0][1], g[1][0]), g[2][1]);
+          hyz = cmul(cmul(g[0][0], g[1][1]), g[2][1]);
+          glx = cadd(cmul(g[0][3], p00), cmul(g[0][1], cadd(cmul(g[1][2], g[2][0]), cmul(g[1][0], g[2][2]))));
+          gly = cadd(cmul(g[1][3], p01), cmul(g[1][1], cadd(cmul(g[0][2], g[2][0]), cmul(g[0][0], g[2][2]))));
+          glz = cadd(cmul(g[2][3], p02), cmul(g[2][1], cadd(cmul(g[0][2], g[1][0]), cmul(g[0][0], g[1][2]))));
+        }
         const cd lap = cadd(cadd(hxx, hyy), hzz);
-        const cd glx = cadd(cmul(g[0][3], p00), cmul(g[0][1], cadd(cmul(g[1][2], g[2][0]), cmul(g[1][0], g[2][2]))));
-        const cd gly = cadd(cmul(g[1][3], p01), cmul(g[1][1], cadd(cmul(g[0][2], g[2][0]), cmul(g[0][0], g[2][2]))));
-        const cd glz = cadd(cmul(g[2][3], p02), cmul(g[2][1], cadd(cmul(g[0][2], g[1][0]), cmul(g[0][0], g[1][2]))));
         const double u0 = gU[3 * e], u1 = gU[3 * e + 1], u2 = gU[3 * e + 2];
         const cd X = {-0.5 * (lap.r + 2.0 * (gx.r * u0 + gy.r * u1 + gz.r * u2)),
                       -0.5 * (lap.i + 2.0 * (gx.i * u0 + gy.i * u1 + gz.i * u2))};
@@ -704,14 +839,22 @@ __global__ __launch_bounds__(256, 1) void k_cslater_sample(MeasureArgs m, TwistA
         const int i = h + H * s;
         if (i >= NS) continue;
         const int e = sp * NS + i;
-        cd g[3][4];
-        cbasis_axis<1>(pos[3 * e] - Ra0, za, L, invL, tw, 0, g[0]);
-        cbasis_axis<1>(pos[3 * e + 1] - Ra1, za, L, invL, tw, 1, g[1]);
-        cbasis_axis<1>(pos[3 * e + 2] - Ra2, za, L, invL, tw, 2, g[2]);
         const cd Wv = ld_c(Ws, (size_t)ca * NSP + i);
-        dT0 += remul(cmul(cmul(g[0][1], g[1][0]), g[2][0]), Wv);
-        dT1 += remul(cmul(cmul(g[0][0], g[1][1]), g[2][0]), Wv);
-        dT2 += remul(cmul(cmul(g[0][0], g[1][0]), g[2][1]), Wv);
+        if constexpr (CB) {
+          const CBasisD q = ccontracted_derivs<false>(pos[3 * e] - Ra0, pos[3 * e + 1] - Ra1, pos[3 * e + 2] - Ra2,
+                                                      m.eta, L, invL, tw);
+          dT0 += remul(q.gx, Wv);
+          dT1 += remul(q.gy, Wv);
+          dT2 += remul(q.gz, Wv);
+        } else {
+          cd g[3][4];
+          cbasis_axis<1>(pos[3 * e] - Ra0, za, L, invL, tw, 0, g[0]);
+          cbasis_axis<1>(pos[3 * e + 1] - Ra1, za, L, invL, tw, 1, g[1]);
+          cbasis_axis<1>(pos[3 * e + 2] - Ra2, za, L, invL, tw, 2, g[2]);
+          dT0 += remul(cmul(cmul(g[0][1], g[1][0]), g[2][0]), Wv);
+          dT1 += remul(cmul(cmul(g[0][0], g[1][1]), g[2][0]), Wv);
+          dT2 += remul(cmul(cmul(g[0][0], g[1][0]), g[2][1]), Wv);
+        }
       }
     }
     __syncthreads();
@@ -772,17 +915,26 @@ template <int NS>
 hipError_t launch_csweep_t(const WalkerArgs& a, const SweepArgs& s, const TwistArgs& tw, int refresh, int moves,
                            hipStream_t st) {
   static_assert(CSweepLds<NS>::bytes(true) <= 160 * 1024, "the complex half-sweep exceeds the LDS of a CU");
-  if (moves)
-    hipLaunchKernelGGL((k_csweep<NS, true>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(true), st, a, s, tw, refresh);
+  if (moves && a.contracted)
+    hipLaunchKernelGGL((k_csweep<NS, true, true>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(true), st, a, s, tw,
+                       refresh);
+  else if (moves)
+    hipLaunchKernelGGL((k_csweep<NS, true, false>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(true), st, a, s, tw,
+                       refresh);
+  else if (a.contracted)
+    hipLaunchKernelGGL((k_csweep<NS, false, true>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(false), st, a, s, tw, 1);
   else
-    hipLaunchKernelGGL((k_csweep<NS, false>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(false), st, a, s, tw, 1);
+    hipLaunchKernelGGL((k_csweep<NS, false, false>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(false), st, a, s, tw, 1);
   return hipGetLastError();
 }
 
 template <int NS>
 hipError_t launch_cslater_t(const MeasureArgs& m, const TwistArgs& tw, hipStream_t st) {
   static_assert(CSlaterLay<NS>::bytes <= 160 * 1024, "the complex measurement exceeds the LDS of a CU");
-  hipLaunchKernelGGL((k_cslater_sample<NS>), dim3(m.W), dim3(256), CSlaterLay<NS>::bytes, st, m, tw);
+  if (m.contracted)
+    hipLaunchKernelGGL((k_cslater_sample<NS, true>), dim3(m.W), dim3(256), CSlaterLay<NS>::bytes, st, m, tw);
+  else
+    hipLaunchKernelGGL((k_cslater_sample<NS, false>), dim3(m.W), dim3(256), CSlaterLay<NS>::bytes, st, m, tw);
   return hipGetLastError();
 }
 

@@ -194,7 +194,7 @@ int check_sys(const vmc_system* s) {
   if (s->contracted) {
     // the images |n| <= 1 of the diffuse r^2 e^{-Z2 r^2} reach FP64 resolution only if Z2 (1.5 L)^2 >= 36
     const double h = 1.5 * s->box_L;
-    if (s->twist != 0 || s->general_twist || s->n_protons / 2 > 64 || !std::isfinite(s->eta) ||
+    if (s->twist != 0 || s->n_protons / 2 > 64 || !std::isfinite(s->eta) ||
         kContractedZ2 * h * h < 36.0)
       return VMC_EINVAL;
   }

@@ -30,7 +30,7 @@ EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_
             "vmc_set_hbm_budget", "vmc_hbm_in_use", "vmc_traj_bytes", "vmc_cancel", "vmc_traj_set_R", "vmc_traj_get_R",
             "vmc_traj_step_count", "vmc_traj_langevin_step", "vmc_langevin_step_noalloc", "vmc_huckel_params_theta",
             "vmc_huckel_params_contracted", "vmc_traj_set_param_stats", "vmc_traj_param_stats",
-            "vmc_traj_set_jastrow", "vmc_sr_update"]
+            "vmc_traj_set_jastrow", "vmc_sr_update", "vmc_huckel_params_theta_contracted"]
 VMC_REQ_QUEUED, VMC_REQ_RUNNING, VMC_REQ_DONE, VMC_REQ_FAILED, VMC_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
@@ -104,6 +104,7 @@ def _declare(l):
     l.vmc_traj_param_stats.argtypes = [vp, vp]
     l.vmc_traj_set_jastrow.argtypes = [vp, d, d, P(d)]
     l.vmc_sr_update.argtypes = [P(d), i, d, d, P(d)]
+    l.vmc_huckel_params_theta_contracted.argtypes = [i, d, P(d), d, P(d), P(d)]
     l.vmc_twist_average.argtypes = [vp, i, i, vp, vp, vp, vp]
     l.vmc_traj_save.argtypes = [vp, vp, P(C.c_size_t)]
     l.vmc_traj_walkers_reset.argtypes = [vp, P(i)]
@@ -469,6 +470,19 @@ def vmc_huckel_params_theta(R, zeta, L, theta):
     P = C.POINTER(C.c_double)
     _check(_lib().vmc_huckel_params_theta(n, float(L), th.ctypes.data_as(P), R.ctypes.data_as(P),
                                           zeta.ctypes.data_as(P), Cm.ctypes.data_as(P)), "vmc_huckel_params_theta")
+    return Cm.view(np.complex128)[..., 0]
+
+
+def vmc_huckel_params_theta_contracted(R, L, theta, eta):
+    """Host helper for a general twist on the contracted basis: complex N x N/2 coefficients."""
+    import numpy as np
+    R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(3)
+    n = R.size // 3
+    Cm = np.zeros((n, n // 2, 2))
+    P = C.POINTER(C.c_double)
+    _check(_lib().vmc_huckel_params_theta_contracted(n, float(L), th.ctypes.data_as(P), float(eta), R.ctypes.data_as(P),
+                                                     Cm.ctypes.data_as(P)), "vmc_huckel_params_theta_contracted")
     return Cm.view(np.complex128)[..., 0]
 
 

@@ -115,3 +115,26 @@ def test_host_sr_update_matches_the_oracle(oracle):
         with pytest.raises(vmc.VMCError) as ei:
             vmc.vmc_sr_update(*args)
         assert ei.value.code == vmc.VMC_EINVAL
+
+
+@pytest.mark.parametrize("theta", [(0.3, -1.1, 2.0), (np.pi / 4, 3 * np.pi / 4, -np.pi / 4), (0.0, 0.0, 0.0)])
+def test_host_huckel_theta_contracted_spans_oracle_occupied_space(oracle, theta):
+    """The host's contracted Hueckel orbitals under a general twist (exponent derivatives of the
+    Gaussian overlap with Bloch weights, Hermitian solve through the real embedding) span the
+    oracle's occupied space (axis moments with Bloch weights, complex Jacobi); at zero twist they
+    also span the real contracted helper's."""
+    from paper_1605_08423_amd import vmc
+    from paper_1605_08423_amd.inputs import small_system
+    wl = small_system(16, 1.9, seed=21)
+    th = np.array(theta)
+    Cg = vmc.vmc_huckel_params_theta_contracted(wl.R, wl.L, th, 0.1)
+    Co, _ = oracle.chuckel_contracted(wl.R, wl.L, 8, 0.1, th)
+    S = oracle.coverlap_contracted(wl.R, wl.L, 0.1, th)
+    # the S-orthonormal projectors onto the occupied space agree
+    def proj(Cm):
+        G = Cm.conj().T @ S @ Cm
+        return Cm @ np.linalg.solve(G, Cm.conj().T)
+    assert np.max(np.abs(proj(Cg) - proj(Co))) < 1e-11
+    if not np.any(th):
+        Cr = vmc.vmc_huckel_params_contracted(wl.R, wl.L, 0.1)
+        assert np.max(np.abs(proj(Cg) - proj(Cr.astype(complex)))) < 1e-11

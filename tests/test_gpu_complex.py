@@ -278,3 +278,82 @@ def test_cchain_with_one_and_three_body_terms(oracle, dev, name, theta, W, ne, n
     assert worst < TOL64
     assert rel(out[0], red["E"]) < TOL64 and elem(out[3:], red["f"]) < TOL64
     assert st[0] == pytest.approx(out[0], rel=1e-12)
+
+
+ETA = 0.1
+
+
+def _cbox(name):
+    """Boxes with Z2 (1.5 L)^2 >= 36 for the contracted basis."""
+    return workload(name) if name in ("h54", "h128") else small_system(16, 1.9, seed=21)
+
+
+@pytest.mark.parametrize("name,K,theta,b1,j3", [("h16", 8, TH_A, 0.0, None), ("h16", 8, TH_MP, 2.5, F3),
+                                                ("h54", 4, TH_A, 2.5, F3), ("h128", 2, TH_MP, 0.0, None)])
+def test_ceval_configs_contracted(oracle, dev, name, K, theta, b1, j3):
+    torch, vmc, ctx = dev
+    wl = _cbox(name)
+    th = np.array(theta)
+    say(f"[complex contracted eval_configs] {name} K={K} theta={theta} b1={b1} j3={j3 is not None}")
+    Cc, _ = oracle.chuckel_contracted(wl.R, wl.L, wl.n // 2, ETA, th)
+    pos = wl.electrons(W=K, seed_offset=3)
+    sysd = vmc.make_system(wl.n, wl.L, theta=th, eta=ETA, b1=b1, j3=j3)
+    g = vmc.vmc_eval_configs(ctx, sysd, _T(torch, wl.R.reshape(-1)), _T(torch, _cpairs(Cc)), _T(torch, wl.zeta),
+                             _T(torch, pos)).cpu().numpy()
+    s = oracle.CSystem(wl.R, wl.zeta, Cc, th, wl.L, eta=ETA, b1=b1, j3=j3)
+    n3 = 3 * wl.n
+    worst = {}
+    for k in range(K):
+        r = s.local(pos[k])
+        for q, a, b, f in [("lnpsi", g[k, 0], r["lnpsi"], rel), ("EL", g[k, 1], r["EL"], rel),
+                           ("dlnpsi", g[k, 2:2 + n3], r["dlnpsi"], elem), ("dEL", g[k, 2 + n3:], r["dEL"], elem)]:
+            worst[q] = max(worst.get(q, 0.0), f(a, b))
+    say("  worst errors", worst)
+    for q, v in worst.items():
+        assert v < TOL64, (q, v)
+
+
+@pytest.mark.parametrize("name,theta,W,ne,ns", [("h16", TH_A, 16, 2, 5), ("h54", TH_MP, 4, 1, 4)])
+def test_cchain_contracted(oracle, dev, name, theta, W, ne, ns):
+    """Same-seed chains on the contracted basis with b_1 and the three-body term under a general
+    twist, through the refresh and the carried sweeps."""
+    torch, vmc, ctx = dev
+    wl = _cbox(name)
+    th = np.array(theta)
+    say(f"[complex contracted chain] {name} theta={theta} W={W}")
+    Cc, _ = oracle.chuckel_contracted(wl.R, wl.L, wl.n // 2, ETA, th)
+    pos = wl.electrons(W=W, seed_offset=7)
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, theta=th, eta=ETA, b1=2.5, j3=F3), W, seed=11, traj_id=3)
+    tr.set_walkers(_T(torch, pos))
+    out = tr.energy_forces(_T(torch, wl.R.reshape(-1)), _T(torch, _cpairs(Cc)), _T(torch, wl.zeta), ne, ns,
+                           wl.delta, 2).cpu().numpy()
+    means, acc, posg = tr.walker_means().cpu().numpy(), tr.accepts().cpu().numpy(), tr.get_walkers().cpu().numpy()
+    tr.close()
+    s = oracle.CSystem(wl.R, wl.zeta, Cc, th, wl.L, eta=ETA, b1=2.5, j3=F3)
+    xo = pos.copy()
+    sums, nacc = s.vmc_run(xo, ne, ns, wl.delta, seed=11, traj=3, step=2)
+    red = oracle.reduce(sums, ns)
+    flips = int(np.sum(acc != nacc))
+    worst = max(elem(means[w], red["means"][w]) for w in range(W))
+    say("  walkers with a flipped decision:", flips, f" worst walker element-wise error of the means {worst:.3e}")
+    assert flips == 0
+    assert rel(posg, xo) < 1e-12
+    assert worst < TOL64
+    assert rel(out[0], red["E"]) < TOL64 and elem(out[3:], red["f"]) < TOL64
+
+
+def test_contracted_host_huckel_under_twist_drives_the_gpu(oracle, dev):
+    """The library's own contracted Hueckel orbitals under a twist give the oracle's local values
+    (the two orbital sets span one occupied space, so |psi| and E_L agree)."""
+    torch, vmc, ctx = dev
+    wl = _cbox("h16")
+    th = np.array(TH_MP)
+    Cg = vmc.vmc_huckel_params_theta_contracted(wl.R, wl.L, th, ETA)
+    Co, _ = oracle.chuckel_contracted(wl.R, wl.L, wl.n // 2, ETA, th)
+    pos = wl.electrons(W=4, seed_offset=5)
+    g = vmc.vmc_eval_configs(ctx, vmc.make_system(wl.n, wl.L, theta=th, eta=ETA), _T(torch, wl.R.reshape(-1)),
+                             _T(torch, _cpairs(Cg)), _T(torch, wl.zeta), _T(torch, pos)).cpu().numpy()
+    s = oracle.CSystem(wl.R, wl.zeta, Co, th, wl.L, eta=ETA)
+    for k in range(4):
+        r = s.local(pos[k])
+        assert rel(g[k, 1], r["EL"]) < 1e-9

@@ -134,7 +134,6 @@ def test_contracted_system_validation(dev):
     wl = _box("h16")
     bad = [vmc.make_system(small.n, small.L, eta=ETA),
            vmc.make_system(wl.n, wl.L, eta=ETA, twist=1),
-           vmc.make_system(wl.n, wl.L, eta=ETA, theta=(0.1, 0.2, 0.3)),
            vmc.make_system(256, 14.0, eta=ETA),
            vmc.make_system(wl.n, wl.L, eta=float("nan"))]
     for sysd in bad:
