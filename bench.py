@@ -495,12 +495,15 @@ def monkhorst_pack(q: int) -> np.ndarray:
     return np.array([(a, b, c) for a in t for b in t for c in t])
 
 
-def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int) -> dict:
+def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, wavefunction: str = "gaussian") -> dict:
     """Twist-averaged Langevin steps over the q x q x q Monkhorst-Pack mesh of general twists (the
     paper's production setup is q = 4): one trajectory per twist with W walkers and the complex
     orbitals of its twist (FP64); a step solves the q^3 Hueckel problems on the host, runs every
     twist's estimate (5 re-equilibration + M measured sweeps; 20 at the first step), forms the
-    twist averages of the forces and of their covariance and takes the Langevin step."""
+    twist averages of the forces and of their covariance and takes the Langevin step.
+    wavefunction "gaussian": one s-Gaussian per proton and the two-body Jastrow; "paper": the
+    contracted orbital phi_1 + eta phi_2 (eta = 0.1), the one-body term (b_1 = 2.5) and the
+    three-body term (F of the three-body leg)."""
     import torch
     from concurrent.futures import ThreadPoolExecutor
     from paper_1605_08423_amd import vmc
@@ -511,9 +514,11 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int) -
     n_tw = len(mesh)
     ctx = vmc.Context(0)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    paper = wavefunction == "paper"
+    wkw = dict(eta=0.1, b1=2.5, j3=J3_LEG_F) if paper else {}
     trajs = []
     for k, th in enumerate(mesh):
-        tr = vmc.Trajectory(ctx, vmc.make_system(N, wl.L, theta=th), W, seed=wl.seed, traj_id=k)
+        tr = vmc.Trajectory(ctx, vmc.make_system(N, wl.L, theta=th, **wkw), W, seed=wl.seed, traj_id=k)
         tr.set_walkers(dev(wl.electrons(W=W, seed_offset=k)))
         trajs.append(tr)
     R = dev(wl.R.reshape(-1))
@@ -529,7 +534,10 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int) -
 
     def one_step(k):
         Rh = R.cpu().numpy()
-        Cs = list(pool.map(lambda th: vmc.vmc_huckel_params_theta(Rh, wl.zeta, wl.L, th), mesh))
+        if paper:
+            Cs = list(pool.map(lambda th: vmc.vmc_huckel_params_theta_contracted(Rh, wl.L, th, 0.1), mesh))
+        else:
+            Cs = list(pool.map(lambda th: vmc.vmc_huckel_params_theta(Rh, wl.zeta, wl.L, th), mesh))
         E = acc = 0.0
         for j, tr in enumerate(trajs):
             out = tr.energy_forces(R, dev(np.ascontiguousarray(Cs[j]).view(np.float64)), zeta, 20 if k == 0 else 5,
@@ -565,7 +573,8 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int) -
     pool.shutdown()
     ranked = sorted(times.items(), key=lambda kv: -kv[1][0])
     rl = {}
-    for kname, (ms, n) in ranked[:2]:
+    # the work model counts the single-Gaussian, two-body wavefunction
+    for kname, (ms, n) in (ranked[:2] if not paper else []):
         avg_s = ms / max(n, 1) / 1e3
         parts = work_model(kname, N, 0, 0, 1, False, False, state["acc"])
         flops, achieved, peak = roofline_numbers(parts, W, avg_s)
@@ -576,18 +585,21 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int) -
                      "executed_tflops": round(sum(ex.values()) * W / avg_s / 1e12, 3)}
     return {"value": round(W * n_tw * M * steps / elapsed, 1), "unit": "walker-sweeps/s",
             "workload": f"{name}: {N} H, r_s={wl.rs}, {q}x{q}x{q} Monkhorst-Pack twists x {W} walkers x {M} measured "
-                        f"(+5 re-equilibration) sweeps per Langevin step, complex orbitals, FP64",
+                        f"(+5 re-equilibration) sweeps per Langevin step, complex orbitals, FP64"
+                        + (", contracted basis eta=0.1, one-body b_1=2.5, three-body F="
+                           + ",".join(f"{x:g}" for x in J3_LEG_F) if paper else ""),
             "twists": n_tw, "walkers_per_twist": W, "sweeps": M, "steps": steps, "warmup": warmup,
             "ms_per_step": round(1e3 * elapsed / steps, 1), "langevin_steps_per_s": round(steps / elapsed, 4),
             "E_Ha_twist_average": state["E"], "acceptance": round(state["acc"], 4),
-            "dominant_kernel": ranked[0][0], "roofline": rl,
+            "dominant_kernel": ranked[0][0], "roofline": rl or None, "wavefunction": wavefunction,
             "kernel_ms": {k: round(v[0], 2) for k, v in ranked if v[0] > 0}}
 
 
 def run_mesh(args):
     r = twist_mesh_leg(args.workload if args.workload != "h256" else "h128", args.mesh, args.mesh_walkers,
-                       args.sweeps, args.steps, args.warmup)
-    dom = r["roofline"][r["dominant_kernel"]]
+                       args.sweeps, args.steps, args.warmup, args.mesh_wavefunction)
+    dom = (r["roofline"] or {}).get(r["dominant_kernel"], {"bound": "alu", "achieved": None, "peak": PEAK["f64"],
+                                                           "unit": "TFLOP/s", "frac": None})
     line = {"metric": "twist-averaged VMC walker-sweeps/s with forces (general twists)", "value": r["value"],
             "unit": r["unit"], "n_gpus": 1, "steps": r["steps"], "warmup": r["warmup"],
             "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -801,6 +813,11 @@ def main():
                     help="twist-averaged steps over the Q x Q x Q Monkhorst-Pack mesh of general twists (complex "
                          "orbitals, FP64) instead")
     ap.add_argument("--mesh-walkers", type=int, default=256, help="walkers per twist of --mesh and the mesh leg")
+    ap.add_argument("--paper-mesh-leg", type=int, default=4, metavar="Q",
+                    help="Q of the short twist-mesh leg with the paper's wavefunction terms (0: skip)")
+    ap.add_argument("--mesh-wavefunction", choices=["gaussian", "paper"], default="gaussian",
+                    help="the wavefunction of --mesh: one s-Gaussian and the two-body Jastrow, or the paper's terms "
+                         "(contracted basis, one- and three-body Jastrow)")
     ap.add_argument("--mesh-leg", type=int, default=4, metavar="Q",
                     help="Q of the short twist-mesh leg of the default line (0: skip)")
     ap.add_argument("--toy", action="store_true", help="the toy-model figure as a GPU workload instead")
@@ -958,6 +975,9 @@ def main():
     mesh = None
     if args.mesh_leg > 0 and args.workload == "h128":
         mesh = twist_mesh_leg("h128", args.mesh_leg, args.mesh_walkers, 10, 1, 1)
+    paper_mesh = None
+    if args.paper_mesh_leg > 0 and args.workload == "h128":
+        paper_mesh = twist_mesh_leg("h128", args.paper_mesh_leg, args.mesh_walkers, 10, 1, 1, "paper")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -992,6 +1012,7 @@ def main():
         "step_latency_ms": {"p50": round(lead["p50"], 1), "p99": round(lead["p99"], 1)},
         "E_Ha": float(out_h[0]), "sigma_E_Ha": float(out_h[1]), "acceptance": acc,
         "roofline": roofline, "fp64_gpu": fp64, "served": served, "twist_mesh": mesh,
+        "twist_mesh_paper_wavefunction": paper_mesh,
         "contracted_basis": contracted, "three_body": three_body, "optimisation": optimisation,
         "cpu_baseline": cpu,
         "kernel_ms": {k: round(v[0], 2) for k, v in times.items()},
