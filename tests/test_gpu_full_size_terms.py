@@ -1,0 +1,122 @@
+"""The wavefunction terms at the full sizes the benchmark's legs time, through the C ABI: one
+trajectory of all its walkers per launch, with sampled walkers (first, middle, last) run by the
+oracle one by one on their own Philox streams (identical acceptance counts, per-walker means at
+1e-10 in FP64 and within the mixed-precision bars in mixed precision), and the reductions over
+every walker recomputed from the GPU's own per-walker means at 1e-10.
+
+* h128 mixed, 16384 walkers, b_1 = 2.5 and the three-body F of the three-body leg;
+* h128 mixed, 16384 walkers, the contracted basis (eta = 0.1) of the contracted-basis leg;
+* h128 FP64, 16384 walkers, the contracted basis with both terms;
+* one twist of the paper-wavefunction mesh leg: h128, 256 walkers, a Monkhorst-Pack twist, the
+  contracted basis and b_1 (the three-body term is left out here because the complex oracle's
+  moves re-evaluate the whole Jastrow factor, which costs N^3 per move with it; the smaller
+  complex tests cover it)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1605_08423_amd.inputs import workload
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-10
+TOLMIX = {"e_w": 5e-5, "d_w": 2e-5, "g_w": 2e-5, "h_w": 5e-5}
+F_LEG = (-0.2, 0.0, 0.05)
+ETA = 0.1
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    from paper_1605_08423_amd import vmc
+    return torch, vmc, vmc.Context(0)
+
+
+def T(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _check(oracle, s, wl, x0, out_h, means, fw, acc, pos, W, ne, ns, precision, sampled, walker_run):
+    n3 = 3 * wl.n
+    parts = {"e_w": slice(0, 1), "d_w": slice(1, 1 + n3), "g_w": slice(1 + n3, 1 + 2 * n3),
+             "h_w": slice(1 + 2 * n3, 1 + 3 * n3)}
+    for w in sampled:
+        xo = np.ascontiguousarray(x0[w:w + 1])
+        sums, nacc = walker_run(xo, w)
+        mo = oracle.reduce(sums, ns)["means"][0]
+        errs = {q: rel(means[w, sl], mo[sl]) for q, sl in parts.items()}
+        say(f"  walker {w}: accepted gpu/oracle {acc[w]}/{nacc[0]}  ", {q: f"{v:.2e}" for q, v in errs.items()})
+        assert acc[w] == nacc[0]
+        if precision == 0:
+            assert rel(pos[w], xo[0]) < 1e-12
+        for q, v in errs.items():
+            assert v < (TOL64 if precision == 0 else TOLMIX[q]), (w, q, v)
+    sums_all = np.zeros((W, 2 + 3 * n3))
+    sums_all[:, 0] = means[:, 0] * ns
+    sums_all[:, 2:] = means[:, 1:] * ns
+    red = oracle.reduce(sums_all, ns)
+    acc_rate = acc.sum() / (W * (ne + ns) * wl.n)
+    errs = {"E": rel(out_h[0], red["E"]), "sigma_E": rel(out_h[1], red["sigma_E"]),
+            "acceptance": rel(out_h[2], acc_rate), "f_w": rel(fw, red["f_w"]), "f": rel(out_h[3:], red["f"])}
+    say("  reductions over all walkers", {q: f"{v:.2e}" for q, v in errs.items()})
+    for q, v in errs.items():
+        assert v < TOL64, (q, v)
+
+
+@pytest.mark.parametrize("label,precision,b1,j3,eta,sampled", [
+    ("three-body leg", 1, 2.5, F_LEG, None, (0, 8191, 16383)),
+    ("contracted-basis leg", 1, 0.0, None, ETA, (0, 16383)),
+    ("contracted basis with both terms", 0, 2.5, F_LEG, ETA, (5, 16382))])
+def test_full_size_real_orbitals(oracle, dev, label, precision, b1, j3, eta, sampled):
+    torch, vmc, ctx = dev
+    wl = workload("h128")
+    W, ne, ns = 16384, 1, 2
+    say(f"[full size] h128 {label}: W={W} precision={precision} sweeps={ne}+{ns} sampled={sampled}")
+    if eta is None:
+        Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
+    else:
+        Cm, _ = oracle.huckel_contracted(wl.R, wl.L, wl.n // 2, eta)
+    x0 = wl.electrons(W=W, seed_offset=23)
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=precision, b1=b1, j3=j3, eta=eta), W,
+                        seed=wl.seed, traj_id=4)
+    tr.set_walkers(T(torch, x0))
+    out_h = tr.energy_forces(T(torch, wl.R.reshape(-1)), T(torch, Cm), T(torch, wl.zeta), ne, ns, wl.delta,
+                             6).cpu().numpy()
+    means, fw = tr.walker_means().cpu().numpy(), tr.walker_forces().cpu().numpy()
+    acc, pos = tr.accepts().cpu().numpy(), tr.get_walkers().cpu().numpy()
+    tr.close()
+    assert np.all(np.isfinite(out_h))
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1, j3=j3, eta=eta)
+    _check(oracle, s, wl, x0, out_h, means, fw, acc, pos, W, ne, ns, precision, sampled,
+           lambda xo, w: s.vmc_run(xo, ne, ns, wl.delta, seed=wl.seed, traj=4, step=6, walker0=w))
+
+
+def test_full_size_one_twist_of_the_paper_mesh(oracle, dev):
+    torch, vmc, ctx = dev
+    wl = workload("h128")
+    W, ne, ns = 256, 1, 2
+    th = np.array([np.pi / 4, -3 * np.pi / 4, np.pi / 4])
+    say(f"[full size] h128 paper-mesh twist {th}: W={W} sweeps={ne}+{ns}")
+    Cc, _ = oracle.chuckel_contracted(wl.R, wl.L, wl.n // 2, ETA, th)
+    x0 = wl.electrons(W=W, seed_offset=29)
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, theta=th, eta=ETA, b1=2.5), W, seed=wl.seed, traj_id=4)
+    tr.set_walkers(T(torch, x0))
+    Cpairs = np.ascontiguousarray(np.asarray(Cc, dtype=np.complex128)).view(np.float64)
+    out_h = tr.energy_forces(T(torch, wl.R.reshape(-1)), T(torch, Cpairs), T(torch, wl.zeta), ne, ns, wl.delta,
+                             6).cpu().numpy()
+    means, fw = tr.walker_means().cpu().numpy(), tr.walker_forces().cpu().numpy()
+    acc, pos = tr.accepts().cpu().numpy(), tr.get_walkers().cpu().numpy()
+    tr.close()
+    s = oracle.CSystem(wl.R, wl.zeta, Cc, th, wl.L, eta=ETA, b1=2.5)
+    _check(oracle, s, wl, x0, out_h, means, fw, acc, pos, W, ne, ns, 0, (0, 255),
+           lambda xo, w: s.vmc_run(xo, ne, ns, wl.delta, seed=wl.seed, traj=4, step=6, walker0=w))
