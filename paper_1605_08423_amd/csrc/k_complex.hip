@@ -14,10 +14,10 @@
 //   k_csweep          one work-group per walker and spin.  With `refresh` it forms A on the
 //                     matrix cores and inverts it by Gauss-Jordan elimination in LDS, else it reads
 //                     the inverse; then it moves the spin's electrons in order with
-//                     Sherman-Morrison updates of the inverse held in LDS.  All proposals of the
-//                     spin are drawn up front and their orbital rows formed together on the matrix
-//                     cores: a proposal depends only on its own electron, which no earlier move
-//                     of the spin displaces.
+//                     Sherman-Morrison updates of the inverse held in LDS, delayed over blocks of
+//                     16 moves.  All proposals of the spin are drawn up front and their orbital
+//                     rows formed together on the matrix cores: a proposal depends only on its own
+//                     electron, which no earlier move of the spin displaces.
 //   k_cslater_sample  Re E_L, d ln|psi|/dR and d Re E_L/dR by the contractions of the real
 //                     measurement in complex arithmetic (B = C A^-1, M = X B, W = B M).
 #include "common.hpp"
@@ -269,17 +269,14 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
   for (int e = t; e < N; e += CT)
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) sincospi(pos[3 * e + ax] * invL, &trig[6 * e + ax], &trig[6 * e + 3 + ax]);
-  // thread c < N takes proton c in the one- and three-body terms: the sines and cosines of
-  // pi R_c / L, and G_c = sum_i chi_c(r_i) kept for the whole half-sweep
-  double sa[3] = {0.0, 0.0, 0.0}, ca[3] = {1.0, 1.0, 1.0};
-  if (t < N)
+  // the sines and cosines of pi R_c / L of every proton (one- and three-body terms), in the
+  // region of the row-product partial sums, which the delayed moves do not use
+  double* ptab = smem + LY::vpart;   // N x 6
+  static_assert(6 * N <= 2 * P * NSP, "the proton table fits the partial-sum region");
+  if (MOVES && (a.j1_beta > 0.0 || a.j3))
+    for (int c = t; c < N; c += CT)
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) sincospi(a.R[3 * t + ax] * invL, &sa[ax], &ca[ax]);
-  double G1 = 0.0, G2 = 0.0;
-  if (MOVES && a.j3 && t < N) {
-    G1 = a.j3G[((size_t)w * N + t) * 2];
-    G2 = a.j3G[((size_t)w * N + t) * 2 + 1];
-  }
+      for (int ax = 0; ax < 3; ++ax) sincospi(a.R[3 * c + ax] * invL, &ptab[6 * c + ax], &ptab[6 * c + 3 + ax]);
   if (MOVES)
     for (int i = t; i < NS; i += CT) {
       double xn, yn, zn, ru;
@@ -294,21 +291,28 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
   if (!refresh)
     for (int u = t; u < NS * NS; u += CT) st_c(Ai, (u / NS) * LDA + u % NS, ld_c(Bg, u));
   __syncthreads();
-  // row tiles [0, TR): the spin's electrons (A, refresh only); [TR, 2 TR): the proposals
+  // row tiles [0, TR): the spin's electrons (A, refresh only); [TR, 2 TR): the proposals.  With
+  // fewer tiles than waves the centres of a tile are split over CW / (tiles) waves, whose partial
+  // products are added into the tile one after another in a fixed order.
   {
-    const int t0 = refresh ? 0 : TR, t1 = MOVES ? 2 * TR : TR;
-    for (int tt = t0 + wave; tt < t1; tt += CW) {
-      const bool isp = tt >= TR;
-      const int rt = isp ? tt - TR : tt;
+    static_assert(2 * TR <= CW, "one tile per wave");
+    const int t0 = refresh ? 0 : TR, t1 = MOVES ? 2 * TR : TR, nt = t1 - t0;
+    const int split = CW / nt, kper = (KS + split - 1) / split;
+    const int part = wave / nt, tt = t0 + wave % nt;
+    const bool active = part < split;
+    const bool isp = tt >= TR;
+    const int rt = isp ? tt - TR : tt;
+    v4d dr[TC], di[TC];
+#pragma unroll
+    for (int tc = 0; tc < TC; ++tc) { dr[tc] = v4d{0, 0, 0, 0}; di[tc] = v4d{0, 0, 0, 0}; }
+    if (active) {
       const int row = rt * 16 + (lane & 15);
       const bool rok = row < NS;
       const int rr = rok ? row : 0;
       const double* rp = isp ? prop + 4 * rr : pos + 3 * (sp * NS + rr);
       const double rx = rp[0], ry = rp[1], rz = rp[2];
-      v4d dr[TC], di[TC];
-#pragma unroll
-      for (int tc = 0; tc < TC; ++tc) { dr[tc] = v4d{0, 0, 0, 0}; di[tc] = v4d{0, 0, 0, 0}; }
-      for (int kk = 0; kk < KS; ++kk) {
+      const int k1 = (part + 1) * kper < KS ? (part + 1) * kper : KS;
+      for (int kk = part * kper; kk < k1; ++kk) {
         const int c = kk * 4 + (lane >> 4);
         cd ph = {0.0, 0.0};
         if (rok && c < N) {
@@ -322,17 +326,26 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
           cmfma(ph, cv, dr[tc], di[tc]);
         }
       }
-      double* D = isp ? Mp : Ai;
-      const int ldd = isp ? NSP : LDA;
+    }
+    double* D = isp ? Mp : Ai;
+    const int ldd = isp ? NSP : LDA;
+    for (int q = 0; q < split; ++q) {
+      if (active && part == q)
 #pragma unroll
-      for (int tc = 0; tc < TC; ++tc)
+        for (int tc = 0; tc < TC; ++tc)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          st_c(D, (size_t)(rt * 16 + (lane >> 4) + 4 * v) * ldd + tc * 16 + (lane & 15), cd{dr[tc][v], di[tc][v]});
+          for (int v = 0; v < 4; ++v) {
+            const size_t o = (size_t)(rt * 16 + (lane >> 4) + 4 * v) * ldd + tc * 16 + (lane & 15);
+            const cd x = {dr[tc][v], di[tc][v]};
+            st_c(D, o, q == 0 ? x : cadd(ld_c(D, o), x));
+          }
+      if (q + 1 < split) __syncthreads();
     }
   }
   __syncthreads();
   double ldv = 0.0, phv = 0.0;   // meaningful in thread 0
+  cd dprod = {1.0, 0.0};
+  int dexp = 0, nswap = 0;
   if (refresh) {
     // Gauss-Jordan elimination with partial pivoting, in place; row swaps are undone on the
     // columns at the end.  A pivot below N_sigma eps max|A_ij| counts as zero: with complex
@@ -400,10 +413,20 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
         }
       }
       if (t == 0) {
-        ldv += 0.5 * log(m2);
-        phv += atan2(pv.i, pv.r) + (r != p ? VMC_PI : 0.0);
+        // the pivots' product as a mantissa and a power of two (its logarithm and angle once at
+        // the end), and the row swaps, each a factor -1
+        dprod = cmul(dprod, pv);
+        int ex;
+        (void)frexp(fmax(fabs(dprod.r), fabs(dprod.i)), &ex);
+        dprod = {ldexp(dprod.r, -ex), ldexp(dprod.i, -ex)};
+        dexp += ex;
+        nswap += r != p ? 1 : 0;
       }
       __syncthreads();
+    }
+    if (t == 0) {
+      ldv = 0.5 * log(dprod.r * dprod.r + dprod.i * dprod.i) + dexp * 0.69314718055994530942;
+      phv = atan2(dprod.i, dprod.r) + (nswap & 1 ? VMC_PI : 0.0);
     }
     if (flag[0]) {
       if (t == 0) atomicExch(a.status, 1);
@@ -428,95 +451,270 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
   // that the moves need no logarithm or angle; folded into ldet and the phase at the end
   cd qprod = {1.0, 0.0};
   int qexp = 0;
-  if (MOVES) {
+  if constexpr (MOVES) {
+    // The moves in blocks of 16, as in the real half-sweep: the block's row products
+    // P = M'[block] A^-1 on the matrix cores (waves tc < TC, column tile tc), then wave 0 alone runs
+    // the 16 moves in order with no barrier: move j takes t = P_j after the accepted moves j' < j
+    // of the block by the left-looking recursion t -= t[i_j'] z_j' (z_j' = (t_j' - e_i_j') / q_j'),
+    // its ratio q_j = t[i_j] and its Jastrow change; after the block Z = (I + Y)^-1 [z
+    // rows] by back-substitution (Y[j][j''] = z_j[i_j''], j'' > j) and every wave updates its
+    // tiles of A^-1 -= A^-1[:, block] Z on the matrix cores.  P and then Z overwrite the block's
+    // orbital rows, which nothing reads again.
+    constexpr int EPL = (N + 63) / 64, NBK = NSP / 16, NTILE = TR * TC, MAXT = (NTILE + CW - 1) / CW;
+    static_assert(NSP <= 64, "one recursion column per lane");
     const double LoP = L / VMC_PI, bj = a.b;
-    for (int i = 0; i < NS; ++i) {
-      const int e = sp * NS + i;
-      // row product v = m' A^-1 in P partial sums; the Jastrow change; column i of A^-1
-      if (t < P * NS) {
-        const int j = t % NS, pp = t / NS;
-        const int k0 = pp * CH, k1 = (k0 + CH < NS) ? k0 + CH : NS;
-        cd acc = {0.0, 0.0};
-        for (int k = k0; k < k1; ++k) acc = cadd(acc, cmul(ld_c(Mp, (size_t)i * NSP + k), ld_c(Ai, (size_t)k * LDA + j)));
-        st_c(vpart, (size_t)pp * NSP + j, acc);
-      }
-      double du = 0.0, dj1 = 0.0, dj2 = 0.0;
-      if (t < N) {
-        const double* to = trig + 6 * e;
-        const double so[3] = {to[0], to[1], to[2]}, co[3] = {to[3], to[4], to[5]};
-        const double* tn = ptrig + 6 * i;
-        const double sn[3] = {tn[0], tn[1], tn[2]}, cn[3] = {tn[3], tn[4], tn[5]};
-        // the pair term with electron t
-        if (t != e) {
-          const double* tj = trig + 6 * t;
-          const double sj[3] = {tj[0], tj[1], tj[2]}, cj[3] = {tj[3], tj[4], tj[5]};
-          const double aa = (t / NS == sp) ? a.a_par : a.a_anti;
-          du = pade_u<double>(sn, cn, sj, cj, LoP, aa, bj) - pade_u<double>(so, co, sj, cj, LoP, aa, bj);
+    const bool one_body = a.j1_beta > 0.0;
+    double* D1 = fcol;   // one-body change of each move
+    // A move's one-body change depends on its own electron and the protons only, so all of them
+    // are formed first: move i by the eight threads 8 i .. 8 i + 7, each over the protons
+    // c = t mod 8 (mod 8), combined by lane exchanges in a fixed order.
+    if (one_body) {
+      for (int i0 = 0; i0 < NSP; i0 += CT / 8) {
+        const int i = i0 + (t >> 3);
+        double acc = 0.0;
+        if (i < NS) {
+          const double* to = trig + 6 * (sp * NS + i);
+          const double* tn = ptrig + 6 * i;
+          const double so[3] = {to[0], to[1], to[2]}, co[3] = {to[3], to[4], to[5]};
+          const double sn[3] = {tn[0], tn[1], tn[2]}, cn[3] = {tn[3], tn[4], tn[5]};
+          for (int c = t & 7; c < N; c += 8) {
+            const double* tp = ptab + 6 * c;
+            const double sc[3] = {tp[0], tp[1], tp[2]}, cc[3] = {tp[3], tp[4], tp[5]};
+            acc += one_body_exp<double>(sn, cn, sc, cc, LoP, a.j1_beta) -
+                   one_body_exp<double>(so, co, sc, cc, LoP, a.j1_beta);
+          }
         }
-        // the one-body term with proton t: -(1 - e^{-beta rho}) / beta changes by the difference
-        // of the exponentials over beta
-        if (a.j1_beta > 0.0)
-          du += (one_body_exp<double>(sn, cn, sa, ca, LoP, a.j1_beta) -
-                 one_body_exp<double>(so, co, sa, ca, LoP, a.j1_beta)) / a.j1_beta;
-        // the three-body term on nucleus t: (chi(r') - chi(r))^T F (G_t - chi(r))
-        if (a.j3) {
-          double n1, n2, o1, o2;
-          j3_values<double>(sn, cn, sa, ca, LoP, n1, n2);
-          j3_values<double>(so, co, sa, ca, LoP, o1, o2);
-          dj1 = n1 - o1;
-          dj2 = n2 - o2;
-          const double g1 = G1 - o1, g2 = G2 - o2;
-          du += a.j3f[0] * dj1 * g1 + a.j3f[1] * (dj1 * g2 + dj2 * g1) + a.j3f[2] * dj2 * g2;
-        }
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        acc += __shfl_xor(acc, 4, 64);
+        if ((t & 7) == 0 && i < NS) D1[i] = acc / a.j1_beta;
       }
-      du = wave_allsum(du);
-      if (lane == 0) red[wave] = du;
-      if (t < NS) st_c(colI, t, ld_c(Ai, (size_t)t * LDA + i));
+    }
+    // The pair terms of a move are staged per block by all threads: with the electrons where the
+    // block starts, base_j = sum_{jj != e_j} u(r'_j, r_jj) - u(r_j, r_jj) (move j by the 32 threads
+    // 32 j .. 32 j + 31, each over the electrons jj = t mod 32 (mod 32), combined by lane
+    // exchanges in a fixed order), and for two moves j' < j of the block the correction
+    // X[j][j'] = [u(r'_j, r'_j') - u(r_j, r'_j')] - [u(r'_j, r_j') - u(r_j, r_j')] that applies
+    // once move j' is accepted.  The electrons' sines and cosines in LDS follow the accepted moves.
+    constexpr int JB = NS < 16 ? NS : 16;
+    static_assert(6 * N + JB * JB <= 2 * P * NSP, "the proton table and the pair corrections fit");
+    double* Xc = ptab + 6 * N;   // JB x JB pair corrections
+    double* base = colI;         // 16 staged pair changes
+    // wave 0's state for the moves: lane l keeps protons l, l + 64 (their sines and cosines) and
+    // the three-body sums G of nuclei l, l + 64
+    double sa[EPL][3], ca[EPL][3], Gj[EPL][2];
+    if (wave == 0) {
+#pragma unroll
+      for (int tt = 0; tt < EPL; ++tt) {
+        const int c = lane + 64 * tt;
+        const bool ok = c < N;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          sa[tt][m] = (ok && (one_body || a.j3)) ? ptab[6 * c + m] : 0.0;
+          ca[tt][m] = (ok && (one_body || a.j3)) ? ptab[6 * c + 3 + m] : 1.0;
+        }
+        Gj[tt][0] = (ok && a.j3) ? a.j3G[((size_t)w * N + c) * 2] : 0.0;
+        Gj[tt][1] = (ok && a.j3) ? a.j3G[((size_t)w * N + c) * 2 + 1] : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int b = 0; b < NBK; ++b) {
+      const int jmax = NS - 16 * b < 16 ? NS - 16 * b : 16;
+      double* PB = Mp + 2 * (size_t)16 * b * NSP;   // 16 x NSP complex: M'[block], then P, then z / Z
+      {
+        v4d pr = {0.0, 0.0, 0.0, 0.0}, pim = {0.0, 0.0, 0.0, 0.0};
+        if (wave < TC) {
+          const int col = 16 * wave + (lane & 15);
+          for (int kk = 0; kk < NSP / 4; ++kk) {
+            const int k = 4 * kk + (lane >> 4);
+            const cd av = ld_c(PB, (size_t)(lane & 15) * NSP + k);
+            const cd bv = (k < NS && col < NS) ? ld_c(Ai, (size_t)k * LDA + col) : cd{0.0, 0.0};
+            cmfma(av, bv, pr, pim);
+          }
+        }
+        {
+          const int j = t >> 5;
+          double acc = 0.0;
+          if (j < jmax) {
+            const int e = sp * NS + 16 * b + j;
+            const double* to = trig + 6 * e;
+            const double* tn = ptrig + 6 * (16 * b + j);
+            const double so[3] = {to[0], to[1], to[2]}, co[3] = {to[3], to[4], to[5]};
+            const double sn[3] = {tn[0], tn[1], tn[2]}, cn[3] = {tn[3], tn[4], tn[5]};
+            for (int jj = t & 31; jj < N; jj += 32) {
+              if (jj == e) continue;
+              const double* tj = trig + 6 * jj;
+              const double sj[3] = {tj[0], tj[1], tj[2]}, cj[3] = {tj[3], tj[4], tj[5]};
+              const double aa = (jj / NS == sp) ? a.a_par : a.a_anti;
+              acc += pade_u<double>(sn, cn, sj, cj, LoP, aa, bj) - pade_u<double>(so, co, sj, cj, LoP, aa, bj);
+            }
+          }
+          acc += __shfl_xor(acc, 16, 64);
+          acc += __shfl_xor(acc, 8, 64);
+          acc += __shfl_xor(acc, 4, 64);
+          acc += __shfl_xor(acc, 2, 64);
+          acc += __shfl_xor(acc, 1, 64);
+          if ((t & 31) == 0 && j < jmax) base[j] = acc;
+          const int jx = t >> 4, jp = t & 15;
+          if (t < 256 && jp < jx && jx < jmax) {
+            const double* to = trig + 6 * (sp * NS + 16 * b + jx);
+            const double* tn = ptrig + 6 * (16 * b + jx);
+            const double* po = trig + 6 * (sp * NS + 16 * b + jp);
+            const double* pn = ptrig + 6 * (16 * b + jp);
+            const double so[3] = {to[0], to[1], to[2]}, co[3] = {to[3], to[4], to[5]};
+            const double sn[3] = {tn[0], tn[1], tn[2]}, cn[3] = {tn[3], tn[4], tn[5]};
+            const double qo[3] = {po[0], po[1], po[2]}, ko[3] = {po[3], po[4], po[5]};
+            const double qn[3] = {pn[0], pn[1], pn[2]}, kn[3] = {pn[3], pn[4], pn[5]};
+            const double ap = a.a_par;
+            Xc[jx * JB + jp] = (pade_u<double>(sn, cn, qn, kn, LoP, ap, bj) - pade_u<double>(so, co, qn, kn, LoP, ap, bj)) -
+                               (pade_u<double>(sn, cn, qo, ko, LoP, ap, bj) - pade_u<double>(so, co, qo, ko, LoP, ap, bj));
+          }
+        }
+        __syncthreads();
+        if (wave < TC)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            st_c(PB, (size_t)((lane >> 4) + 4 * v) * NSP + 16 * wave + (lane & 15), cd{pr[v], pim[v]});
+        __syncthreads();
+      }
+      if (wave == 0) {
+        uint32_t amask = 0;
+        for (int j = 0; j < jmax; ++j) {
+          const int i = 16 * b + j, e = sp * NS + i;
+          cd tv = lane < NSP ? ld_c(PB, (size_t)j * NSP + lane) : cd{0.0, 0.0};
+          // the Jastrow change: the staged pair change with the corrections of the block's
+          // accepted moves, the three-body term on the lane's nuclei,
+          // (chi(r') - chi(r))^T F (G - chi(r)), and the staged one-body change
+          const double* to = trig + 6 * e;
+          const double* tn = ptrig + 6 * i;
+          const double so[3] = {to[0], to[1], to[2]}, co[3] = {to[3], to[4], to[5]};
+          const double sn[3] = {tn[0], tn[1], tn[2]}, cn[3] = {tn[3], tn[4], tn[5]};
+          double du = (lane < JB && ((amask >> lane) & 1u)) ? Xc[j * JB + lane] : 0.0, dj[EPL][2];
+#pragma unroll
+          for (int tt = 0; tt < EPL; ++tt) {
+            const int jj = lane + 64 * tt;
+            dj[tt][0] = dj[tt][1] = 0.0;
+            if (a.j3 && jj < N) {
+              double n1, n2, o1, o2;
+              j3_values<double>(sn, cn, sa[tt], ca[tt], LoP, n1, n2);
+              j3_values<double>(so, co, sa[tt], ca[tt], LoP, o1, o2);
+              dj[tt][0] = n1 - o1;
+              dj[tt][1] = n2 - o2;
+              const double g1 = Gj[tt][0] - o1, g2 = Gj[tt][1] - o2;
+              du += a.j3f[0] * dj[tt][0] * g1 + a.j3f[1] * (dj[tt][0] * g2 + dj[tt][1] * g1) +
+                    a.j3f[2] * dj[tt][1] * g2;
+            }
+          }
+          double dU = base[j] + wave_allsum(du);
+          if (one_body) dU += D1[i];
+          for (uint32_t mm = amask; mm; mm &= mm - 1) {
+            const int jp = __builtin_ctz(mm);
+            const cd cf = {readlane_d(tv.r, 16 * b + jp), readlane_d(tv.i, 16 * b + jp)};
+            const cd z = lane < NSP ? ld_c(PB, (size_t)jp * NSP + lane) : cd{0.0, 0.0};
+            tv = csub(tv, cmul(cf, z));
+          }
+          const cd q = {readlane_d(tv.r, i), readlane_d(tv.i, i)};
+          const double q2 = q.r * q.r + q.i * q.i;
+          const double pacc = q2 * exp(2.0 * dU);
+          cd zrow = {0.0, 0.0};
+          if (prop[4 * i + 3] < pacc) {
+            const double iq2 = 1.0 / q2;
+            const cd iq = {q.r * iq2, -q.i * iq2};
+            cd vj = tv;
+            if (lane == i) vj.r -= 1.0;
+            zrow = cmul(vj, iq);
+            amask |= 1u << j;
+#pragma unroll
+            for (int tt = 0; tt < EPL; ++tt) {
+              Gj[tt][0] += dj[tt][0];
+              Gj[tt][1] += dj[tt][1];
+            }
+            if (lane < 3) pos[3 * e + lane] = prop[4 * i + lane];
+            if (lane < 6) trig[6 * e + lane] = tn[lane];
+            ++nadd;
+            qprod = cmul(qprod, q);
+            int ex;
+            (void)frexp(fmax(fabs(qprod.r), fabs(qprod.i)), &ex);
+            qprod = {ldexp(qprod.r, -ex), ldexp(qprod.i, -ex)};
+            qexp += ex;
+          }
+          if (lane < NSP) st_c(PB, (size_t)j * NSP + lane, zrow);
+          wave_lds_sync();
+        }
+        // Z = (I + Y)^-1 [z rows]: back-substitution from the last accepted move
+        for (int j = 15; j >= 0; --j) {
+          if (!((amask >> j) & 1u)) continue;
+          const cd zo = lane < NSP ? ld_c(PB, (size_t)j * NSP + lane) : cd{0.0, 0.0};
+          cd z = zo;
+          for (uint32_t mm = amask & ~((2u << j) - 1u); mm; mm &= mm - 1) {
+            const int jp = __builtin_ctz(mm);
+            const cd cf = {readlane_d(zo.r, 16 * b + jp), readlane_d(zo.i, 16 * b + jp)};
+            const cd zp = lane < NSP ? ld_c(PB, (size_t)jp * NSP + lane) : cd{0.0, 0.0};
+            z = csub(z, cmul(cf, zp));
+          }
+          if (lane < NSP) st_c(PB, (size_t)j * NSP + lane, z);
+          wave_lds_sync();
+        }
+        if (lane == 0) flag[1] = (int)amask;
+      }
       __syncthreads();
-      cd q = {0.0, 0.0};
-      for (int pp = 0; pp < P; ++pp) q = cadd(q, ld_c(vpart, (size_t)pp * NSP + i));
-      double dU = red[0];
-      for (int q = 1; q < CW; ++q) dU += red[q];
-      const double q2 = q.r * q.r + q.i * q.i;
-      const double pacc = q2 * exp(2.0 * dU);
-      if (prop[4 * i + 3] < pacc) {
-        G1 += dj1;
-        G2 += dj2;
-        const double iq2 = 1.0 / q2;
-        const cd iq = {q.r * iq2, -q.i * iq2};
-        if (t < RPT * NS) {
-          const int j = t % NS;
-          cd vj = {0.0, 0.0};
-          for (int pp = 0; pp < P; ++pp) vj = cadd(vj, ld_c(vpart, (size_t)pp * NSP + j));
-          if (j == i) vj.r -= 1.0;
-          const cd z = cmul(vj, iq);
-          for (int k = t / NS; k < NS; k += RPT)
-            st_c(Ai, (size_t)k * LDA + j, csub(ld_c(Ai, (size_t)k * LDA + j), cmul(ld_c(colI, k), z)));
+      if (flag[1]) {
+        // A^-1 -= A^-1[:, block] Z, tile by tile: every wave reads its tiles, the (negated) block
+        // columns and Z first, and writes only after the barrier, since the block's column tile is
+        // both read and updated
+        v4d cr[MAXT], ci[MAXT];
+        cd ga[MAXT][4], zb[MAXT][4];
+#pragma unroll
+        for (int r = 0; r < MAXT; ++r) {
+          const int id = wave + CW * r;
+          const int tr = id / TC, tc = id % TC;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * tr + (lane >> 4) + 4 * v, col = 16 * tc + (lane & 15);
+            const cd c = (id < NTILE && row < NS && col < NS) ? ld_c(Ai, (size_t)row * LDA + col) : cd{0.0, 0.0};
+            cr[r][v] = c.r;
+            ci[r][v] = c.i;
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int grow = 16 * tr + (lane & 15), gcol = 16 * b + 4 * kk + (lane >> 4);
+            const cd g = (id < NTILE && grow < NS && gcol < NS) ? ld_c(Ai, (size_t)grow * LDA + gcol) : cd{0.0, 0.0};
+            ga[r][kk] = {-g.r, -g.i};
+            zb[r][kk] = id < NTILE ? ld_c(PB, (size_t)(4 * kk + (lane >> 4)) * NSP + 16 * tc + (lane & 15))
+                                   : cd{0.0, 0.0};
+          }
         }
-        if (t == 0) {
+        __syncthreads();
 #pragma unroll
-          for (int ax = 0; ax < 3; ++ax) pos[3 * e + ax] = prop[4 * i + ax];
+        for (int r = 0; r < MAXT; ++r) {
+          const int id = wave + CW * r;
+          if (id >= NTILE) continue;
+          const int tr = id / TC, tc = id % TC;
 #pragma unroll
-          for (int u = 0; u < 6; ++u) trig[6 * e + u] = ptrig[6 * i + u];
-          ++nadd;
-          qprod = cmul(qprod, q);
-          int ex;
-          (void)frexp(fmax(fabs(qprod.r), fabs(qprod.i)), &ex);
-          qprod = {ldexp(qprod.r, -ex), ldexp(qprod.i, -ex)};
-          qexp += ex;
+          for (int kk = 0; kk < 4; ++kk) cmfma(ga[r][kk], zb[r][kk], cr[r], ci[r]);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * tr + (lane >> 4) + 4 * v, col = 16 * tc + (lane & 15);
+            if (row < NS && col < NS) st_c(Ai, (size_t)row * LDA + col, cd{cr[r][v], ci[r][v]});
+          }
         }
       }
       __syncthreads();
     }
+    if (wave == 0 && a.j3)
+#pragma unroll
+      for (int tt = 0; tt < EPL; ++tt) {
+        const int c = lane + 64 * tt;
+        if (c < N) {
+          a.j3G[((size_t)w * N + c) * 2] = Gj[tt][0];
+          a.j3G[((size_t)w * N + c) * 2 + 1] = Gj[tt][1];
+        }
+      }
   }
   double* Bo = a.Binv + 2 * ((size_t)w * 2 + sp) * NS * NS;
   for (int u = t; u < NS * NS; u += CT) st_c(Bo, u, ld_c(Ai, (size_t)(u / NS) * LDA + u % NS));
   if (MOVES)
     for (int u = t; u < 3 * NS; u += CT) a.pos[(size_t)w * 3 * N + 3 * sp * NS + u] = pos[3 * sp * NS + u];
-  if (MOVES && a.j3 && t < N) {
-    a.j3G[((size_t)w * N + t) * 2] = G1;
-    a.j3G[((size_t)w * N + t) * 2 + 1] = G2;
-  }
   if (t == 0) {
     if (MOVES && nadd > 0) {
       ldv += 0.5 * log(qprod.r * qprod.r + qprod.i * qprod.i) + qexp * 0.69314718055994530942;
