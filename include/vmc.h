@@ -192,9 +192,12 @@ int vmc_traj_step_count(vmc_traj* traj, uint32_t* steps);
  * Morrison updates applied in blocks of 16 moves (delayed, same ratios).
  * After each measured sweep: E_L, dE_L/dR and dln|psi|/dR.
  * With a general twist (vmc_system.general_twist) C_dev is complex; each half-sweep forms the
- * spin's Slater matrix afresh and inverts it (complex Gauss-Jordan elimination with partial
- * pivoting) before the first sweep and every 4th one, and otherwise carries the inverse of the
- * previous half-sweep; the moves update it by plain Sherman-Morrison steps, the acceptance is
+ * spin's Slater matrix afresh before the first sweep and every 4th one: at the first sweep it
+ * inverts it (complex Gauss-Jordan elimination with partial pivoting), at the later ones it
+ * refines the carried inverse by one Newton-Schulz step (elimination where max|I - A X| >
+ * refine_tol, or for every matrix when refine_tol < 0); otherwise it carries the inverse of the
+ * previous half-sweep; the moves update it by Sherman-Morrison steps applied in blocks of 16
+ * moves (delayed, same ratios), the acceptance is
  * u_acc < |psi'/psi|^2 with complex ratios, and E_L, dE_L/dR in the outputs are the real parts.
  * Output out_dev (3 + 3N doubles): [E, sigma_E, acceptance, f(3N)] with
  * E = mean_w e_w, sigma_E = sd_w(e_w)/sqrt(W), f = mean_w f_w,

@@ -242,8 +242,12 @@ struct CSweepLds {
   static constexpr size_t bytes(bool moves) { return sizeof(double) * (moves ? mp + 2 * (size_t)NSP * NSP : mp); }
 };
 
+// refresh: 0 carries the previous half-sweep's inverse; 1 forms A and inverts it by elimination;
+// 2 forms A and refines the carried inverse X by one Newton-Schulz step X + X (I - A X), with the
+// elimination instead where max |I - A X| exceeds rtol (or is not finite).
 template <int NS, bool MOVES, bool CB>
-__global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, TwistArgs tw, int refresh) {
+__global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, TwistArgs tw, int refresh,
+                                                  double rtol) {
   using LY = CSweepLds<NS>;
   constexpr int N = 2 * NS, NSP = LY::NSP, LDA = LY::LDA, P = LY::P, CH = LY::CH, RPT = LY::RPT;
   constexpr int TR = NSP / 16, TC = NSP / 16, KS = (N + 3) / 4;
@@ -290,13 +294,18 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
   const double* Bg = a.Binv + 2 * ((size_t)w * 2 + sp) * NS * NS;
   if (!refresh)
     for (int u = t; u < NS * NS; u += CT) st_c(Ai, (u / NS) * LDA + u % NS, ld_c(Bg, u));
+  if (refresh == 2)   // X into the proposal-row region (zero outside N_sigma x N_sigma) until the rows are formed
+    for (int u = t; u < NSP * NSP; u += CT) {
+      const int i = u / NSP, j = u % NSP;
+      st_c(Mp, u, (i < NS && j < NS) ? ld_c(Bg, (size_t)i * NS + j) : cd{0.0, 0.0});
+    }
   __syncthreads();
   // row tiles [0, TR): the spin's electrons (A, refresh only); [TR, 2 TR): the proposals.  With
   // fewer tiles than waves the centres of a tile are split over CW / (tiles) waves, whose partial
   // products are added into the tile one after another in a fixed order.
-  {
-    static_assert(2 * TR <= CW, "one tile per wave");
-    const int t0 = refresh ? 0 : TR, t1 = MOVES ? 2 * TR : TR, nt = t1 - t0;
+  static_assert(2 * TR <= CW, "one tile per wave");
+  auto form_rows = [&](const int t0, const int t1) {
+    const int nt = t1 - t0;
     const int split = CW / nt, kper = (KS + split - 1) / split;
     const int part = wave / nt, tt = t0 + wave % nt;
     const bool active = part < split;
@@ -339,14 +348,95 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
             const cd x = {dr[tc][v], di[tc][v]};
             st_c(D, o, q == 0 ? x : cadd(ld_c(D, o), x));
           }
-      if (q + 1 < split) __syncthreads();
+      __syncthreads();
     }
+  };
+  // a refinement forms A first and the proposals' rows after it, since X occupies their region
+  if (refresh == 2) form_rows(0, TR);
+  else if (refresh) form_rows(0, MOVES ? 2 * TR : TR);
+  else if (MOVES) form_rows(TR, 2 * TR);
+  bool eliminate = refresh == 1;
+  if (refresh == 2) {
+    // R = I - A X and X' = X + X R on the matrix cores, tile by tile (tiles w, w + CW of wave w),
+    // operands read from LDS before every barrier that precedes a write
+    constexpr int NT2 = TR * TR, MT = (NT2 + CW - 1) / CW;
+    v4d rr[MT], ri[MT];
+    double rmax = 0.0;
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+      const int id = wave + CW * q, tr = id / TR, tc = id % TR;
+      rr[q] = v4d{0, 0, 0, 0};
+      ri[q] = v4d{0, 0, 0, 0};
+      if (id < NT2)
+        for (int kk = 0; kk < NSP / 4; ++kk) {
+          const int k = 4 * kk + (lane >> 4);
+          cmfma(ld_c(Ai, (size_t)(16 * tr + (lane & 15)) * LDA + k), ld_c(Mp, (size_t)k * NSP + 16 * tc + (lane & 15)),
+                rr[q], ri[q]);
+        }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * tr + (lane >> 4) + 4 * v, col = 16 * tc + (lane & 15);
+        const bool ok = id < NT2 && row < NS && col < NS;
+        rr[q][v] = ok ? (row == col ? 1.0 : 0.0) - rr[q][v] : 0.0;
+        ri[q][v] = ok ? -ri[q][v] : 0.0;
+        const double m2 = rr[q][v] * rr[q][v] + ri[q][v] * ri[q][v];
+        rmax = (m2 > rmax || m2 != m2) ? m2 : rmax;   // a NaN is kept
+      }
+    }
+    if (rmax != rmax) rmax = INFINITY;
+    int dummy = 0;
+    wave_argmax(rmax, dummy);
+    if (lane == 0) red[wave] = rmax;
+    __syncthreads();
+    double rm = red[0];
+    for (int q = 1; q < CW; ++q) rm = fmax(rm, red[q]);
+    eliminate = !(rm <= rtol * rtol);
+    if (!eliminate) {
+      // R replaces A, then X' = X + X R replaces R
+#pragma unroll
+      for (int q = 0; q < MT; ++q) {
+        const int id = wave + CW * q, tr = id / TR, tc = id % TR;
+        if (id < NT2)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            st_c(Ai, (size_t)(16 * tr + (lane >> 4) + 4 * v) * LDA + 16 * tc + (lane & 15), cd{rr[q][v], ri[q][v]});
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < MT; ++q) {
+        const int id = wave + CW * q, tr = id / TR, tc = id % TR;
+        if (id < NT2) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const cd x = ld_c(Mp, (size_t)(16 * tr + (lane >> 4) + 4 * v) * NSP + 16 * tc + (lane & 15));
+            rr[q][v] = x.r;
+            ri[q][v] = x.i;
+          }
+          for (int kk = 0; kk < NSP / 4; ++kk) {
+            const int k = 4 * kk + (lane >> 4);
+            cmfma(ld_c(Mp, (size_t)(16 * tr + (lane & 15)) * NSP + k), ld_c(Ai, (size_t)k * LDA + 16 * tc + (lane & 15)),
+                  rr[q], ri[q]);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < MT; ++q) {
+        const int id = wave + CW * q, tr = id / TR, tc = id % TR;
+        if (id < NT2)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            st_c(Ai, (size_t)(16 * tr + (lane >> 4) + 4 * v) * LDA + 16 * tc + (lane & 15), cd{rr[q][v], ri[q][v]});
+      }
+      __syncthreads();
+    }
+    if (MOVES) form_rows(TR, 2 * TR);
   }
   __syncthreads();
   double ldv = 0.0, phv = 0.0;   // meaningful in thread 0
   cd dprod = {1.0, 0.0};
   int dexp = 0, nswap = 0;
-  if (refresh) {
+  if (eliminate) {
     // Gauss-Jordan elimination with partial pivoting, in place; row swaps are undone on the
     // columns at the end.  A pivot below N_sigma eps max|A_ij| counts as zero: with complex
     // multipliers even two equal rows leave a rounding-sized pivot, not an exact zero.
@@ -1111,18 +1201,18 @@ size_t cslater_scratch_bytes(int NS) {
 
 template <int NS>
 hipError_t launch_csweep_t(const WalkerArgs& a, const SweepArgs& s, const TwistArgs& tw, int refresh, int moves,
-                           hipStream_t st) {
+                           double rtol, hipStream_t st) {
   static_assert(CSweepLds<NS>::bytes(true) <= 160 * 1024, "the complex half-sweep exceeds the LDS of a CU");
   if (moves && a.contracted)
     hipLaunchKernelGGL((k_csweep<NS, true, true>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(true), st, a, s, tw,
-                       refresh);
+                       refresh, rtol);
   else if (moves)
     hipLaunchKernelGGL((k_csweep<NS, true, false>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(true), st, a, s, tw,
-                       refresh);
+                       refresh, rtol);
   else if (a.contracted)
-    hipLaunchKernelGGL((k_csweep<NS, false, true>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(false), st, a, s, tw, 1);
+    hipLaunchKernelGGL((k_csweep<NS, false, true>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(false), st, a, s, tw, 1, rtol);
   else
-    hipLaunchKernelGGL((k_csweep<NS, false, false>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(false), st, a, s, tw, 1);
+    hipLaunchKernelGGL((k_csweep<NS, false, false>), dim3(a.W), dim3(CT), CSweepLds<NS>::bytes(false), st, a, s, tw, 1, rtol);
   return hipGetLastError();
 }
 
@@ -1147,9 +1237,11 @@ hipError_t launch_cslater_t(const MeasureArgs& m, const TwistArgs& tw, hipStream
   }
 
 hipError_t launch_csweep(const WalkerArgs& a, const SweepArgs& s, const TwistArgs& tw, int refresh, int moves,
-                         hipStream_t st) {
-  if (a.W < 1 || a.N != 2 * a.NS || (s.spin != 0 && s.spin != 1) || (!moves && !refresh)) return hipErrorInvalidValue;
-  VMC_CDISPATCH(a.NS, return (launch_csweep_t<NSV>(a, s, tw, refresh, moves, st)))
+                         double rtol, hipStream_t st) {
+  if (a.W < 1 || a.N != 2 * a.NS || (s.spin != 0 && s.spin != 1) || (!moves && refresh != 1) || refresh < 0 ||
+      refresh > 2)
+    return hipErrorInvalidValue;
+  VMC_CDISPATCH(a.NS, return (launch_csweep_t<NSV>(a, s, tw, refresh, moves, rtol, st)))
 }
 
 hipError_t launch_cslater_sample(const MeasureArgs& m, const TwistArgs& tw, hipStream_t st) {

@@ -176,12 +176,14 @@ hipError_t launch_j3_forces(const MeasureArgs& m, int mixed, hipStream_t st);
 struct TwistArgs {
   double th[3], c[3], s[3];
 };
-// Complex path (FP64, N_sigma <= 64): one work-group per walker for spin s.spin.  refresh: form the
-// spin's Slater matrix at the current positions and invert it (else the inverse is read from
-// Binv); moves: then move the spin's electrons once.  Binv holds complex (A^-1)[k][i], ldet
-// ln|det A|, sgn arg det A.  A zero pivot sets *status and leaves the walker unchanged.
+// Complex path (FP64, N_sigma <= 64): one work-group per walker for spin s.spin.  refresh 1: form the
+// spin's Slater matrix at the current positions and invert it; refresh 2: form it and refine the
+// inverse read from Binv by one Newton-Schulz step, inverting afresh where max |I - A X| > rtol;
+// refresh 0: read the inverse from Binv.  moves: then move the spin's electrons once.  Binv holds
+// complex (A^-1)[k][i], ldet ln|det A|, sgn arg det A.  A zero pivot sets *status and leaves the
+// walker unchanged.
 hipError_t launch_csweep(const WalkerArgs& a, const SweepArgs& s, const TwistArgs& tw, int refresh, int moves,
-                         hipStream_t st);
+                         double rtol, hipStream_t st);
 // The complex measurement (same accumulator layout as the real one) and its per-walker scratch.
 size_t cslater_scratch_bytes(int NS);
 hipError_t launch_cslater_sample(const MeasureArgs& m, const TwistArgs& tw, hipStream_t st);

@@ -35,8 +35,9 @@ struct Pending { int cls; hipEvent_t a, b; };
 // vmc_energy_forces keeps at most this many sweeps queued ahead of the device, so that
 // a cancellation takes effect within that many sweeps.
 constexpr int kWindow = 8;
-// With a general twist a half-sweep forms and inverts its Slater matrix afresh at sweeps
-// 0, kCRefresh, 2 kCRefresh, ... and carries the previous half-sweep's inverse otherwise.
+// With a general twist a half-sweep forms its Slater matrix at sweeps 0, kCRefresh,
+// 2 kCRefresh, ... (inverting it at sweep 0, refining the carried inverse by a Newton-Schulz
+// step at the others) and carries the previous half-sweep's inverse otherwise.
 constexpr int kCRefresh = 4;
 
 }  // namespace
@@ -749,7 +750,10 @@ int vmc_energy_forces(vmc_traj* t, const double* R_in, const double* C, const do
       // the first sweep and the walkers are restored
       for (int sp = 0; sp < 2; ++sp) {
         SweepArgs sa{sp, s, step, t->seed, t->traj_id, step_delta};
-        RUN(K_CSWEEP, launch_csweep(a, sa, tw, s % kCRefresh == 0, 1, st));
+        // the first sweep inverts afresh (new R and orbitals), later refreshes refine the carried
+        // inverse unless refinement is switched off
+        const int mode = s % kCRefresh != 0 ? 0 : (s == 0 || rtol < 0.0) ? 1 : 2;
+        RUN(K_CSWEEP, launch_csweep(a, sa, tw, mode, 1, rtol, st));
       }
       if (s == 0) {
         rc = check_singular(ctx);
@@ -1015,7 +1019,7 @@ int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R, const
         const TwistArgs tw = twist_args(t->sys);
         for (int sp = 0; sp < 2; ++sp) {
           SweepArgs sa{sp, 0, 0, 0, 0, 0.0};
-          RUN(K_CSWEEP, launch_csweep(a, sa, tw, 1, 0, st));
+          RUN(K_CSWEEP, launch_csweep(a, sa, tw, 1, 0, 0.0, st));
         }
         r2 = measure_c(t, m, e, tw);
       } else {

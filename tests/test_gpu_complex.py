@@ -78,6 +78,21 @@ def test_ceval_configs(oracle, dev, name, K, theta):
         assert v < TOL64, (q, v)
 
 
+def _gchain(oracle, dev, wl, theta, W, n_equil, n_sweeps, seed, step, refine_tol=0.0):
+    torch, vmc, ctx = dev
+    th = np.array(theta)
+    Cc, _ = oracle.chuckel(wl.R, wl.zeta, wl.L, wl.n // 2, th)
+    pos = wl.electrons(W=W, seed_offset=7)
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, theta=th, refine_tol=refine_tol), W, seed=seed, traj_id=3)
+    tr.set_walkers(_T(torch, pos))
+    out = tr.energy_forces(_T(torch, wl.R.reshape(-1)), _T(torch, _cpairs(Cc)), _T(torch, wl.zeta), n_equil,
+                           n_sweeps, wl.delta, step).cpu().numpy()
+    g = dict(out=out, means=tr.walker_means().cpu().numpy(), acc=tr.accepts().cpu().numpy(),
+             pos=tr.get_walkers().cpu().numpy())
+    tr.close()
+    return g
+
+
 def _cchain(oracle, dev, wl, theta, W, n_equil, n_sweeps, seed, step):
     torch, vmc, ctx = dev
     th = np.array(theta)
@@ -98,7 +113,8 @@ def _cchain(oracle, dev, wl, theta, W, n_equil, n_sweeps, seed, step):
     return g, dict(red=red, nacc=nacc, pos=xo, S=oracle.build_S(red["f_w"], red["f"]))
 
 
-# sweeps 0 and 4 form and invert the Slater matrices afresh; the others carry the inverse
+# sweeps 0 and 4 form the Slater matrices (elimination at 0, a Newton-Schulz step from the carried
+# inverse at 4); the others carry the inverse
 @pytest.mark.parametrize("name,theta,W,ne,ns", [("h16", TH_A, 16, 2, 5), ("h32", TH_MP, 8, 1, 5),
                                                 ("h54", TH_MP, 4, 1, 4), ("h128", TH_A, 2, 0, 2)])
 def test_cchain(oracle, dev, name, theta, W, ne, ns):
@@ -122,6 +138,26 @@ def test_cchain(oracle, dev, name, theta, W, ne, ns):
     assert rel(g["S"], o["S"]) < 1e-9
     acc_rate = o["nacc"].sum() / (W * wl.n * (ne + ns))
     assert g["out"][2] == pytest.approx(acc_rate, rel=1e-14)
+
+
+# refreshes at sweeps 0, 4 and 8: elimination at the first, then a Newton-Schulz step from the
+# carried inverse (default tolerance), elimination everywhere (refine_tol < 0), or the step's
+# residual check sending every matrix to elimination (a tolerance no residual meets)
+@pytest.mark.parametrize("name,theta,W", [("h32", TH_MP, 8), ("h54", TH_A, 4)])
+def test_refined_refresh_matches_elimination(oracle, dev, name, theta, W):
+    wl = _wl(name)
+    say(f"[complex refresh] {name} theta={theta} W={W} 1 + 8 sweeps")
+    runs = {tol: _gchain(oracle, dev, wl, theta, W, 1, 8, seed=13, step=4, refine_tol=tol)
+            for tol in (0.0, -1.0, 1e-300)}
+    ref = runs[-1.0]
+    for tol in (0.0, 1e-300):
+        g = runs[tol]
+        e = elem(g["means"], ref["means"])
+        say(f"  refine_tol={tol}: accepted {g['acc'].sum()} vs {ref['acc'].sum()}, means element-wise {e:.2e}")
+        assert np.array_equal(g["acc"], ref["acc"])
+        assert rel(g["pos"], ref["pos"]) < 1e-12
+        assert e < 1e-12
+        assert rel(g["out"], ref["out"]) < 1e-12
 
 
 @pytest.mark.parametrize("name,twist", [("h16", 0), ("h16", 5), ("h54", 3), ("h128", 6)])
