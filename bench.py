@@ -495,7 +495,8 @@ def monkhorst_pack(q: int) -> np.ndarray:
     return np.array([(a, b, c) for a in t for b in t for c in t])
 
 
-def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, wavefunction: str = "gaussian") -> dict:
+def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, wavefunction: str = "gaussian",
+                   streams: int = 4) -> dict:
     """Twist-averaged Langevin steps over the q x q x q Monkhorst-Pack mesh of general twists (the
     paper's production setup is q = 4): one trajectory per twist with W walkers and the complex
     orbitals of its twist (FP64); a step solves the q^3 Hueckel problems on the host, runs every
@@ -503,7 +504,13 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, w
     twist averages of the forces and of their covariance and takes the Langevin step.
     wavefunction "gaussian": one s-Gaussian per proton and the two-body Jastrow; "paper": the
     contracted orbital phi_1 + eta phi_2 (eta = 0.1), the one-body term (b_1 = 2.5) and the
-    three-body term (F of the three-body leg)."""
+    three-body term (F of the three-body leg).
+    The twists are independent: with streams > 1 they run on that many HIP streams (one library
+    context and one host thread each, twists dealt round-robin), so that the launches of
+    different twists overlap on the GPU (a launch of one twist fills each CU with one work-group
+    of 256 walkers); the averages are taken in twist order after all streams finish.  Kernel
+    times are then summed over the streams, and a launch's duration includes the time it shares
+    the GPU with other streams' launches."""
     import torch
     from concurrent.futures import ThreadPoolExecutor
     from paper_1605_08423_amd import vmc
@@ -516,11 +523,19 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, w
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     paper = wavefunction == "paper"
     wkw = dict(eta=0.1, b1=2.5, j3=J3_LEG_F) if paper else {}
+    ns = max(1, min(streams, n_tw))
+    strs = [torch.cuda.Stream() for _ in range(ns)] if ns > 1 else [torch.cuda.current_stream()]
+    ctxs = []
+    for st in strs:
+        with torch.cuda.stream(st):
+            ctxs.append(vmc.Context(0) if ns > 1 else ctx)
     trajs = []
     for k, th in enumerate(mesh):
-        tr = vmc.Trajectory(ctx, vmc.make_system(N, wl.L, theta=th, **wkw), W, seed=wl.seed, traj_id=k)
-        tr.set_walkers(dev(wl.electrons(W=W, seed_offset=k)))
+        with torch.cuda.stream(strs[k % ns]):
+            tr = vmc.Trajectory(ctxs[k % ns], vmc.make_system(N, wl.L, theta=th, **wkw), W, seed=wl.seed, traj_id=k)
+            tr.set_walkers(dev(wl.electrons(W=W, seed_offset=k)))
         trajs.append(tr)
+    torch.cuda.synchronize()
     R = dev(wl.R.reshape(-1))
     R_prev = R.clone()
     zeta = dev(wl.zeta)
@@ -530,6 +545,7 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, w
     alpha = 0.122 * W * n_tw * M
     Delta = 1.0 / alpha
     pool = ThreadPoolExecutor(max_workers=16)
+    sgroups = ThreadPoolExecutor(max_workers=ns)
     state = {"first": True, "E": None, "acc": 0.0}
 
     def one_step(k):
@@ -538,14 +554,21 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, w
             Cs = list(pool.map(lambda th: vmc.vmc_huckel_params_theta_contracted(Rh, wl.L, th, 0.1), mesh))
         else:
             Cs = list(pool.map(lambda th: vmc.vmc_huckel_params_theta(Rh, wl.zeta, wl.L, th), mesh))
-        E = acc = 0.0
-        for j, tr in enumerate(trajs):
-            out = tr.energy_forces(R, dev(np.ascontiguousarray(Cs[j]).view(np.float64)), zeta, 20 if k == 0 else 5,
-                                   M, wl.delta, step=k)
-            f_stack[j].copy_(out[3:])
-            tr.build_S(S_stack[j])
-            E += float(out[0]) / n_tw
-            acc += float(out[2]) / n_tw
+        Ej, accj = [0.0] * n_tw, [0.0] * n_tw
+
+        def group(c):
+            with torch.cuda.stream(strs[c]):
+                for j in range(c, n_tw, ns):
+                    out = trajs[j].energy_forces(R, dev(np.ascontiguousarray(Cs[j]).view(np.float64)), zeta,
+                                                 20 if k == 0 else 5, M, wl.delta, step=k)
+                    f_stack[j].copy_(out[3:])
+                    trajs[j].build_S(S_stack[j])
+                    Ej[j], accj[j] = float(out[0]), float(out[2])
+
+        list(sgroups.map(group, range(ns)))
+        torch.cuda.synchronize()
+        E = sum(e / n_tw for e in Ej)
+        acc = sum(x / n_tw for x in accj)
         f, S = vmc.vmc_twist_average(ctx, f_stack, S_stack)
         if state["first"]:
             S_prev.copy_(S)
@@ -559,18 +582,27 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, w
     for k in range(warmup):
         one_step(k)
     torch.cuda.synchronize()
-    ctx.reset_kernel_times()
-    ctx.set_profiling(True)
+    for c in set(ctxs) | {ctx}:
+        c.reset_kernel_times()
+        c.set_profiling(True)
     t0 = time.perf_counter()
     for k in range(warmup, warmup + steps):
         one_step(k)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    times = ctx.kernel_times()
-    ctx.set_profiling(False)
+    times = {}
+    for c in set(ctxs) | {ctx}:
+        for kname, (ms, n) in c.kernel_times().items():
+            t_ms, t_n = times.get(kname, (0.0, 0))
+            times[kname] = (t_ms + ms, t_n + n)
+        c.set_profiling(False)
     for tr in trajs:
         tr.close()
+    for c in ctxs:
+        if c is not ctx:
+            c.close()
     pool.shutdown()
+    sgroups.shutdown()
     ranked = sorted(times.items(), key=lambda kv: -kv[1][0])
     rl = {}
     # the work model counts the single-Gaussian, two-body wavefunction
@@ -591,13 +623,13 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, w
             "twists": n_tw, "walkers_per_twist": W, "sweeps": M, "steps": steps, "warmup": warmup,
             "ms_per_step": round(1e3 * elapsed / steps, 1), "langevin_steps_per_s": round(steps / elapsed, 4),
             "E_Ha_twist_average": state["E"], "acceptance": round(state["acc"], 4),
-            "dominant_kernel": ranked[0][0], "roofline": rl or None, "wavefunction": wavefunction,
+            "dominant_kernel": ranked[0][0], "roofline": rl or None, "wavefunction": wavefunction, "streams": ns,
             "kernel_ms": {k: round(v[0], 2) for k, v in ranked if v[0] > 0}}
 
 
 def run_mesh(args):
     r = twist_mesh_leg(args.workload if args.workload != "h256" else "h128", args.mesh, args.mesh_walkers,
-                       args.sweeps, args.steps, args.warmup, args.mesh_wavefunction)
+                       args.sweeps, args.steps, args.warmup, args.mesh_wavefunction, args.mesh_streams)
     dom = (r["roofline"] or {}).get(r["dominant_kernel"], {"bound": "alu", "achieved": None, "peak": PEAK["f64"],
                                                            "unit": "TFLOP/s", "frac": None})
     line = {"metric": "twist-averaged VMC walker-sweeps/s with forces (general twists)", "value": r["value"],
@@ -815,6 +847,8 @@ def main():
     ap.add_argument("--mesh-walkers", type=int, default=256, help="walkers per twist of --mesh and the mesh leg")
     ap.add_argument("--paper-mesh-leg", type=int, default=4, metavar="Q",
                     help="Q of the short twist-mesh leg with the paper's wavefunction terms (0: skip)")
+    ap.add_argument("--mesh-streams", type=int, default=4,
+                    help="HIP streams the twists of --mesh and of the mesh legs run on (one library context each)")
     ap.add_argument("--mesh-wavefunction", choices=["gaussian", "paper"], default="gaussian",
                     help="the wavefunction of --mesh: one s-Gaussian and the two-body Jastrow, or the paper's terms "
                          "(contracted basis, one- and three-body Jastrow)")
@@ -974,10 +1008,11 @@ def main():
 
     mesh = None
     if args.mesh_leg > 0 and args.workload == "h128":
-        mesh = twist_mesh_leg("h128", args.mesh_leg, args.mesh_walkers, 10, 1, 1)
+        mesh = twist_mesh_leg("h128", args.mesh_leg, args.mesh_walkers, 10, 1, 1, streams=args.mesh_streams)
     paper_mesh = None
     if args.paper_mesh_leg > 0 and args.workload == "h128":
-        paper_mesh = twist_mesh_leg("h128", args.paper_mesh_leg, args.mesh_walkers, 10, 1, 1, "paper")
+        paper_mesh = twist_mesh_leg("h128", args.paper_mesh_leg, args.mesh_walkers, 10, 1, 1, "paper",
+                                    streams=args.mesh_streams)
 
     cpu = None
     if not args.no_cpu_baseline:
