@@ -505,12 +505,13 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, w
     wavefunction "gaussian": one s-Gaussian per proton and the two-body Jastrow; "paper": the
     contracted orbital phi_1 + eta phi_2 (eta = 0.1), the one-body term (b_1 = 2.5) and the
     three-body term (F of the three-body leg).
-    The twists are independent: with streams > 1 they run on that many HIP streams (one library
-    context and one host thread each, twists dealt round-robin), so that the launches of
-    different twists overlap on the GPU (a launch of one twist fills each CU with one work-group
-    of 256 walkers); the averages are taken in twist order after all streams finish.  Kernel
-    times are then summed over the streams, and a launch's duration includes the time it shares
-    the GPU with other streams' launches."""
+    The host solves the twists' Hueckel problems on a pool of threads while the GPU runs the
+    twists whose orbitals are ready.  The twists are independent: with streams > 1 they run on
+    that many HIP streams (one library context and one host thread each, twists dealt
+    round-robin), so that the launches of different twists overlap on the GPU (a launch of one
+    twist fills each CU with one work-group of 256 walkers); the averages are taken in twist
+    order after all streams finish.  Kernel times are then summed over the streams, and a
+    launch's duration includes the time it shares the GPU with other streams' launches."""
     import torch
     from concurrent.futures import ThreadPoolExecutor
     from paper_1605_08423_amd import vmc
@@ -550,17 +551,19 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, w
 
     def one_step(k):
         Rh = R.cpu().numpy()
+        # the host Hueckel solves, in twist order on the pool; a twist's estimate starts as soon as
+        # its orbitals are ready, so the GPU works while the later twists are solved
         if paper:
-            Cs = list(pool.map(lambda th: vmc.vmc_huckel_params_theta_contracted(Rh, wl.L, th, 0.1), mesh))
+            Cs = [pool.submit(vmc.vmc_huckel_params_theta_contracted, Rh, wl.L, th, 0.1) for th in mesh]
         else:
-            Cs = list(pool.map(lambda th: vmc.vmc_huckel_params_theta(Rh, wl.zeta, wl.L, th), mesh))
+            Cs = [pool.submit(vmc.vmc_huckel_params_theta, Rh, wl.zeta, wl.L, th) for th in mesh]
         Ej, accj = [0.0] * n_tw, [0.0] * n_tw
 
         def group(c):
             with torch.cuda.stream(strs[c]):
                 for j in range(c, n_tw, ns):
-                    out = trajs[j].energy_forces(R, dev(np.ascontiguousarray(Cs[j]).view(np.float64)), zeta,
-                                                 20 if k == 0 else 5, M, wl.delta, step=k)
+                    Cj = np.ascontiguousarray(Cs[j].result()).view(np.float64)
+                    out = trajs[j].energy_forces(R, dev(Cj), zeta, 20 if k == 0 else 5, M, wl.delta, step=k)
                     f_stack[j].copy_(out[3:])
                     trajs[j].build_S(S_stack[j])
                     Ej[j], accj[j] = float(out[0]), float(out[2])

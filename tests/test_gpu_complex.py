@@ -255,6 +255,49 @@ def test_twist_mesh_average(oracle, dev):
     assert S.shape == (n3, n3)
 
 
+def test_twists_on_concurrent_streams_equal_one_stream(oracle, dev):
+    """The eight twists of a 2 x 2 x 2 mesh at h32, run on four HIP streams at once (one library
+    context and one host thread per stream, twists dealt round-robin), give the same outputs,
+    per-walker means and positions, bit for bit, as the same runs one after another on one stream."""
+    from concurrent.futures import ThreadPoolExecutor
+    torch, vmc, ctx = dev
+    wl = _wl("h32")
+    W, ne, ns = 16, 1, 4
+    mesh = oracle.monkhorst_pack(2)
+    Cs = [_cpairs(oracle.chuckel(wl.R, wl.zeta, wl.L, wl.n // 2, th)[0]) for th in mesh]
+
+    def run(c, k):
+        tr = vmc.Trajectory(c, vmc.make_system(wl.n, wl.L, theta=mesh[k]), W, seed=5, traj_id=k)
+        tr.set_walkers(_T(torch, wl.electrons(W=W, seed_offset=k)))
+        out = tr.energy_forces(_T(torch, wl.R.reshape(-1)), _T(torch, Cs[k]), _T(torch, wl.zeta), ne, ns, wl.delta, 3)
+        r = (out.cpu().numpy(), tr.walker_means().cpu().numpy(), tr.get_walkers().cpu().numpy())
+        tr.close()
+        return r
+
+    one = [run(ctx, k) for k in range(len(mesh))]
+    strs = [torch.cuda.Stream() for _ in range(4)]
+    ctxs = []
+    for st in strs:
+        with torch.cuda.stream(st):
+            ctxs.append(vmc.Context(0))
+
+    def group(c):
+        with torch.cuda.stream(strs[c]):
+            return {k: run(ctxs[c], k) for k in range(c, len(mesh), 4)}
+
+    with ThreadPoolExecutor(4) as ex:
+        many = {}
+        for d in ex.map(group, range(4)):
+            many.update(d)
+    torch.cuda.synchronize()
+    for c in ctxs:
+        c.close()
+    for k in range(len(mesh)):
+        for a, b in zip(one[k], many[k]):
+            assert np.array_equal(a, b), k
+    say("[twists on four streams] eight twists equal to one stream, bit for bit")
+
+
 F3 = (-0.3, 0.1, 0.05)
 
 
