@@ -618,6 +618,9 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, w
                      "frac": round(achieved / peak, 4) if peak else None, "avg_launch_ms": round(avg_s * 1e3, 4),
                      "algorithmic_flop_per_launch": round(flops),
                      "executed_tflops": round(sum(ex.values()) * W / avg_s / 1e12, 3)}
+        if ns > 1:
+            # launches of different streams share the GPU, so these rates are lower bounds
+            rl[kname]["overlapped_streams"] = ns
     return {"value": round(W * n_tw * M * steps / elapsed, 1), "unit": "walker-sweeps/s",
             "workload": f"{name}: {N} H, r_s={wl.rs}, {q}x{q}x{q} Monkhorst-Pack twists x {W} walkers x {M} measured "
                         f"(+5 re-equilibration) sweeps per Langevin step, complex orbitals, FP64"
