@@ -124,94 +124,147 @@ int ckpt_validate(const void* buf, size_t len, CkptHeader* out) {
 using namespace vmc_host;
 
 // ---------------------------------------------------------------- Hueckel --
-// Symmetric eigen-decomposition A = Q T Q^T: Householder reflections reduce A
-// to tridiagonal T, then implicit QR steps with a Wilkinson shift (Givens
-// rotations chasing the bulge, deflation of negligible sub-diagonals) drive T
-// to diagonal.  Q accumulates every transformation; its columns are eigenvectors.
-static void householder_tridiag(int n, std::vector<double>& A, std::vector<double>& Q) {
-  Q.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
-  std::vector<double> v(n), p(n), w(n);
+// The m lowest eigenpairs of the symmetric A (n x n, overwritten): Householder reduction to the
+// tridiagonal T (the reflections kept, not accumulated), the m lowest eigenvalues of T by
+// bisection on Sturm counts, each eigenvector of T by inverse iteration (T - sigma I solved by
+// Gaussian elimination with partial pivoting, three iterations from a fixed start; the vectors of
+// eigenvalues closer than 1e-3 |T| orthogonalised by modified Gram-Schmidt, and a shift equal to
+// the previous eigenvalue moved up by 10 eps |T|), carried back through the reflections.  Only the
+// occupied half of the spectrum is needed, which the full QR iteration with accumulated rotations
+// paid n^3 for.  evals: m ascending values; vecs: n x m, column k belonging to evals[k].
+static int lowest_eigenpairs(int n, int m, std::vector<double>& A, std::vector<double>& evals,
+                             std::vector<double>& vecs) {
+  std::vector<double> V((size_t)n * n, 0.0), betas(n, 0.0), v(n), p(n), w(n);
   for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1, o = k + 1;
+    const int mm = n - k - 1, o = k + 1;
     const double x0 = A[(size_t)o * n + k];
     double sigma = 0.0;
-    for (int i = 1; i < m; ++i) sigma += A[(size_t)(o + i) * n + k] * A[(size_t)(o + i) * n + k];
+    for (int i = 1; i < mm; ++i) sigma += A[(size_t)(o + i) * n + k] * A[(size_t)(o + i) * n + k];
     if (sigma == 0.0) continue;
     const double mu = std::sqrt(x0 * x0 + sigma);
     const double v0 = (x0 <= 0.0) ? x0 - mu : -sigma / (x0 + mu);
     const double beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
     v[0] = 1.0;
-    for (int i = 1; i < m; ++i) v[i] = A[(size_t)(o + i) * n + k] / v0;
+    for (int i = 1; i < mm; ++i) v[i] = A[(size_t)(o + i) * n + k] / v0;
     double pv = 0.0;
-    for (int i = 0; i < m; ++i) {
+    for (int i = 0; i < mm; ++i) {
       double acc = 0.0;
-      for (int j = 0; j < m; ++j) acc += A[(size_t)(o + i) * n + o + j] * v[j];
+      for (int j = 0; j < mm; ++j) acc += A[(size_t)(o + i) * n + o + j] * v[j];
       p[i] = beta * acc;
       pv += p[i] * v[i];
     }
-    for (int i = 0; i < m; ++i) w[i] = p[i] - 0.5 * beta * pv * v[i];
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) A[(size_t)(o + i) * n + o + j] -= v[i] * w[j] + w[i] * v[j];
+    for (int i = 0; i < mm; ++i) w[i] = p[i] - 0.5 * beta * pv * v[i];
+    for (int i = 0; i < mm; ++i)
+      for (int j = 0; j < mm; ++j) A[(size_t)(o + i) * n + o + j] -= v[i] * w[j] + w[i] * v[j];
     A[(size_t)o * n + k] = A[(size_t)k * n + o] = mu;
-    for (int i = 1; i < m; ++i) A[(size_t)(o + i) * n + k] = A[(size_t)k * n + o + i] = 0.0;
-    for (int r = 0; r < n; ++r) {
-      double acc = 0.0;
-      for (int j = 0; j < m; ++j) acc += Q[(size_t)r * n + o + j] * v[j];
-      for (int j = 0; j < m; ++j) Q[(size_t)r * n + o + j] -= beta * acc * v[j];
-    }
+    for (int i = 1; i < mm; ++i) A[(size_t)(o + i) * n + k] = A[(size_t)k * n + o + i] = 0.0;
+    betas[k] = beta;
+    for (int i = 0; i < mm; ++i) V[(size_t)k * n + o + i] = v[i];
   }
-}
-
-static int tridiag_qr(int n, std::vector<double>& T, std::vector<double>& Q) {
-  const double eps = 2.220446049250313e-16;
-  auto small = [&](int i) {   // sub-diagonal entry (i, i-1) negligible?
-    return std::fabs(T[(size_t)i * n + i - 1]) <=
-           eps * (std::fabs(T[(size_t)i * n + i]) + std::fabs(T[(size_t)(i - 1) * n + i - 1]));
+  std::vector<double> d(n), e(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+  for (int i = 0; i + 1 < n; ++i) e[i] = A[(size_t)(i + 1) * n + i];
+  double tn = 0.0, lo = d[0], hi = d[0];
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+    tn = std::max(tn, std::fabs(d[i]) + r);
+  }
+  const double eps = 2.220446049250313e-16, tiny = eps * (tn > 0.0 ? tn : 1.0);
+  // number of eigenvalues of T below x (signs of the pivots of T - x I)
+  auto below = [&](double x) {
+    int c = 0;
+    double q = d[0] - x;
+    if (q == 0.0) q = -tiny;
+    if (q < 0.0) ++c;
+    for (int i = 1; i < n; ++i) {
+      q = d[i] - x - e[i - 1] * e[i - 1] / q;
+      if (q == 0.0) q = -tiny;
+      if (q < 0.0) ++c;
+    }
+    return c;
   };
-  auto rot = [&](int k, int lo, int hi, double c, double s) {
-    const int j0 = std::max(lo, k - 1), j1 = std::min(hi, k + 2);
-    for (int j = j0; j <= j1; ++j) {
-      const double t1 = T[(size_t)k * n + j], t2 = T[(size_t)(k + 1) * n + j];
-      T[(size_t)k * n + j] = c * t1 + s * t2;
-      T[(size_t)(k + 1) * n + j] = -s * t1 + c * t2;
+  evals.assign(m, 0.0);
+  for (int k = 0; k < m; ++k) {
+    double a = (k > 0 ? evals[k - 1] : lo) - tiny, b = hi + tiny;
+    for (int it = 0; it < 200 && b - a > 2.0 * eps * std::max(std::fabs(a), std::fabs(b)) + tiny * 1e-3; ++it) {
+      const double c = 0.5 * (a + b);
+      if (c <= a || c >= b) break;
+      if (below(c) > k) b = c; else a = c;
     }
-    for (int i = j0; i <= j1; ++i) {
-      const double t1 = T[(size_t)i * n + k], t2 = T[(size_t)i * n + k + 1];
-      T[(size_t)i * n + k] = c * t1 + s * t2;
-      T[(size_t)i * n + k + 1] = -s * t1 + c * t2;
-    }
-    for (int i = 0; i < n; ++i) {
-      const double t1 = Q[(size_t)i * n + k], t2 = Q[(size_t)i * n + k + 1];
-      Q[(size_t)i * n + k] = c * t1 + s * t2;
-      Q[(size_t)i * n + k + 1] = -s * t1 + c * t2;
-    }
-  };
-  int hi = n - 1, iter = 0;
-  while (hi > 0) {
-    if (++iter > 60 * n) return VMC_ENOCONV;
-    if (small(hi)) {
-      T[(size_t)hi * n + hi - 1] = T[(size_t)(hi - 1) * n + hi] = 0.0;
-      --hi;
-      continue;
-    }
-    int lo = hi - 1;
-    while (lo > 0 && !small(lo)) --lo;
-    if (lo > 0) T[(size_t)lo * n + lo - 1] = T[(size_t)(lo - 1) * n + lo] = 0.0;
-    const double a = T[(size_t)(hi - 1) * n + hi - 1], b = T[(size_t)hi * n + hi - 1], c = T[(size_t)hi * n + hi];
-    const double dd = 0.5 * (a - c);
-    const double mu = c - b * b / (dd + (dd >= 0.0 ? 1.0 : -1.0) * std::hypot(dd, b));
-    double x = T[(size_t)lo * n + lo] - mu, z = T[(size_t)(lo + 1) * n + lo];
-    for (int k = lo; k < hi; ++k) {
-      if (k > lo) {
-        x = T[(size_t)k * n + k - 1];
-        z = T[(size_t)(k + 1) * n + k - 1];
+    evals[k] = 0.5 * (a + b);
+  }
+  vecs.assign((size_t)n * m, 0.0);
+  std::vector<double> u0(n), u1(n), u2(n), ml(n), x(n), ev((size_t)m * n);
+  std::vector<char> sw(n);
+  const double ortol = 1e-3 * tn;
+  for (int k = 0; k < m; ++k) {
+    double sig = evals[k];
+    if (k > 0 && sig - evals[k - 1] < 10.0 * eps * tn) sig = evals[k - 1] + 10.0 * eps * tn;
+    // T - sig I = P L U, U with two super-diagonals
+    double dd = d[0] - sig, s1 = n > 1 ? e[0] : 0.0, s2 = 0.0;
+    for (int i = 0; i + 1 < n; ++i) {
+      const double sub = e[i], nd = d[i + 1] - sig, ns = i + 2 < n ? e[i + 1] : 0.0;
+      if (std::fabs(sub) > std::fabs(dd)) {
+        sw[i] = 1;
+        u0[i] = sub; u1[i] = nd; u2[i] = ns;
+        const double f = dd / sub;
+        ml[i] = f;
+        dd = s1 - f * nd;
+        s1 = s2 - f * ns;
+      } else {
+        sw[i] = 0;
+        if (dd == 0.0) dd = tiny;
+        u0[i] = dd; u1[i] = s1; u2[i] = s2;
+        const double f = sub / dd;
+        ml[i] = f;
+        dd = nd - f * s1;
+        s1 = ns - f * s2;
       }
-      const double r = std::hypot(x, z);
-      const double cs = r == 0.0 ? 1.0 : x / r, sn = r == 0.0 ? 0.0 : z / r;
-      rot(k, lo, hi, cs, sn);
-      if (k > lo) T[(size_t)(k + 1) * n + k - 1] = T[(size_t)(k - 1) * n + k + 1] = 0.0;
+      s2 = 0.0;
     }
+    if (dd == 0.0) dd = tiny;
+    u0[n - 1] = dd; u1[n - 1] = 0.0; u2[n - 1] = 0.0;
+    // a fixed start with every component present
+    uint64_t st = 0x9E3779B97F4A7C15ull * (uint64_t)(k + 1);
+    for (int i = 0; i < n; ++i) {
+      st = st * 6364136223846793005ull + 1442695040888963407ull;
+      x[i] = (double)(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    }
+    for (int it = 0; it < 3; ++it) {
+      for (int i = 0; i + 1 < n; ++i) {
+        if (sw[i]) std::swap(x[i], x[i + 1]);
+        x[i + 1] -= ml[i] * x[i];
+      }
+      for (int i = n - 1; i >= 0; --i) {
+        double s = x[i];
+        if (i + 1 < n) s -= u1[i] * x[i + 1];
+        if (i + 2 < n) s -= u2[i] * x[i + 2];
+        x[i] = s / u0[i];
+      }
+      for (int j = k - 1; j >= 0 && evals[k] - evals[j] < ortol; --j) {
+        double dp = 0.0;
+        for (int i = 0; i < n; ++i) dp += ev[(size_t)j * n + i] * x[i];
+        for (int i = 0; i < n; ++i) x[i] -= dp * ev[(size_t)j * n + i];
+      }
+      double nn = 0.0;
+      for (int i = 0; i < n; ++i) nn += x[i] * x[i];
+      if (!(nn > 0.0) || !std::isfinite(nn)) return VMC_ENOCONV;
+      const double inv = 1.0 / std::sqrt(nn);
+      for (int i = 0; i < n; ++i) x[i] *= inv;
+    }
+    for (int i = 0; i < n; ++i) ev[(size_t)k * n + i] = x[i];
+    // back through the reflections, the last one first
+    for (int r = n - 3; r >= 0; --r) {
+      if (betas[r] == 0.0) continue;
+      const double* vr = &V[(size_t)r * n];
+      double dp = 0.0;
+      for (int i = r + 1; i < n; ++i) dp += vr[i] * x[i];
+      dp *= betas[r];
+      for (int i = r + 1; i < n; ++i) x[i] -= dp * vr[i];
+    }
+    for (int i = 0; i < n; ++i) vecs[(size_t)i * m + k] = x[i];
   }
   return VMC_OK;
 }
@@ -228,7 +281,7 @@ extern "C" int vmc_huckel_params_twist(int n, double L, int twist, const double*
     if (!(zeta[i] > 0.0) || !std::isfinite(zeta[i])) return VMC_EINVAL;
   std::vector<double> S((size_t)n * n), H((size_t)n * n), Q;
   for (int a = 0; a < n; ++a)
-    for (int b = 0; b < n; ++b) {
+    for (int b = a; b < n; ++b) {   // the lower triangle by symmetry
       const double za = zeta[a], zb = zeta[b], mu = za * zb / (za + zb);
       double v = std::pow(M_PI / (za + zb), 1.5);
       for (int ax = 0; ax < 3; ++ax) {
@@ -244,21 +297,17 @@ extern "C" int vmc_huckel_params_twist(int n, double L, int twist, const double*
         v *= s;
       }
       S[(size_t)a * n + b] = v;
+      S[(size_t)b * n + a] = S[(size_t)a * n + b];
     }
   for (int a = 0; a < n; ++a)
     for (int b = 0; b < n; ++b)
       H[(size_t)a * n + b] = -S[(size_t)a * n + b] / std::sqrt(S[(size_t)a * n + a] * S[(size_t)b * n + b]);
-  householder_tridiag(n, H, Q);
-  int rc = tridiag_qr(n, H, Q);
-  if (rc) return rc;
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return H[(size_t)x * n + x] < H[(size_t)y * n + y]; });
   const int no = n / 2;
+  std::vector<double> ev;
+  const int rc = lowest_eigenpairs(n, no, H, ev, Q);
+  if (rc) return rc;
   for (int k = 0; k < no; ++k)
-    for (int a = 0; a < n; ++a)
-      C_out[(size_t)a * no + k] = Q[(size_t)a * n + order[k]] / std::sqrt(S[(size_t)a * n + a]);
+    for (int a = 0; a < n; ++a) C_out[(size_t)a * no + k] = Q[(size_t)a * no + k] / std::sqrt(S[(size_t)a * n + a]);
   return VMC_OK;
 }
 
@@ -290,7 +339,7 @@ extern "C" int vmc_huckel_params_contracted(int n, double L, double eta, const d
   const double z1 = 0.6066825, z2 = 0.3382168;
   std::vector<double> S((size_t)n * n), H((size_t)n * n), Q;
   for (int a = 0; a < n; ++a)
-    for (int b = 0; b < n; ++b) {
+    for (int b = a; b < n; ++b) {   // the lower triangle by symmetry
       double s11[3][4], s12[3][4], s21[3][4], s22[3][4];
       for (int m = 0; m < 3; ++m) {
         const double d = R[3 * a + m] - R[3 * b + m];
@@ -314,21 +363,17 @@ extern "C" int vmc_huckel_params_contracted(int n, double L, double eta, const d
           }
       }
       S[(size_t)a * n + b] = v + eta * (gh + hg) + eta * eta * hh;
+      S[(size_t)b * n + a] = S[(size_t)a * n + b];
     }
   for (int a = 0; a < n; ++a)
     for (int b = 0; b < n; ++b)
       H[(size_t)a * n + b] = -S[(size_t)a * n + b] / std::sqrt(S[(size_t)a * n + a] * S[(size_t)b * n + b]);
-  householder_tridiag(n, H, Q);
-  int rc = tridiag_qr(n, H, Q);
-  if (rc) return rc;
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return H[(size_t)x * n + x] < H[(size_t)y * n + y]; });
   const int no = n / 2;
+  std::vector<double> ev;
+  const int rc = lowest_eigenpairs(n, no, H, ev, Q);
+  if (rc) return rc;
   for (int k = 0; k < no; ++k)
-    for (int a = 0; a < n; ++a)
-      C_out[(size_t)a * no + k] = Q[(size_t)a * n + order[k]] / std::sqrt(S[(size_t)a * n + a]);
+    for (int a = 0; a < n; ++a) C_out[(size_t)a * no + k] = Q[(size_t)a * no + k] / std::sqrt(S[(size_t)a * n + a]);
   return VMC_OK;
 }
 
@@ -347,19 +392,15 @@ static int hermitian_huckel(int n, const std::vector<std::complex<double>>& S, d
       M[(size_t)a * n2 + b + n] = -h.imag();
       M[(size_t)(a + n) * n2 + b] = h.imag();
     }
-  householder_tridiag(n2, M, Q);
-  int rc = tridiag_qr(n2, M, Q);
+  std::vector<double> ev;
+  const int rc = lowest_eigenpairs(n2, n, M, ev, Q);
   if (rc) return rc;
-  std::vector<int> order(n2);
-  for (int i = 0; i < n2; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return M[(size_t)x * n2 + x] < M[(size_t)y * n2 + y]; });
   // the lowest n embedded eigenvectors (x, y) give n complex vectors x + i y spanning the n/2
   // lowest eigenvectors of H; Gram-Schmidt, each time on the candidate of largest residual
   const int no = n / 2;
   std::vector<std::vector<cplx>> z(n, std::vector<cplx>(n));
   for (int c = 0; c < n; ++c)
-    for (int a = 0; a < n; ++a) z[c][a] = cplx(Q[(size_t)a * n2 + order[c]], Q[(size_t)(a + n) * n2 + order[c]]);
+    for (int a = 0; a < n; ++a) z[c][a] = cplx(Q[(size_t)a * n + c], Q[(size_t)(a + n) * n + c]);
   std::vector<bool> used(n, false);
   for (int k = 0; k < no; ++k) {
     int best = -1;
@@ -404,7 +445,7 @@ extern "C" int vmc_huckel_params_theta(int n, double L, const double* theta, con
   // its minimum image d - j L, which multiplies the sum by e^{i theta_m j}
   std::vector<cplx> S((size_t)n * n);
   for (int a = 0; a < n; ++a)
-    for (int b = 0; b < n; ++b) {
+    for (int b = a; b < n; ++b) {   // the lower triangle by symmetry
       const double za = zeta[a], zb = zeta[b], mu = za * zb / (za + zb);
       cplx v = std::pow(M_PI / (za + zb), 1.5);
       for (int ax = 0; ax < 3; ++ax) {
@@ -416,6 +457,7 @@ extern "C" int vmc_huckel_params_theta(int n, double L, const double* theta, con
         v *= sum * std::polar(1.0, theta[ax] * j);
       }
       S[(size_t)a * n + b] = v;
+      S[(size_t)b * n + a] = std::conj(S[(size_t)a * n + b]);
     }
   return hermitian_huckel(n, S, C_out);
 }
@@ -454,7 +496,7 @@ extern "C" int vmc_huckel_params_theta_contracted(int n, double L, const double*
   const double z1 = 0.6066825, z2 = 0.3382168;
   std::vector<cplx> S((size_t)n * n);
   for (int a = 0; a < n; ++a)
-    for (int b = 0; b < n; ++b) {
+    for (int b = a; b < n; ++b) {   // the lower triangle by symmetry
       cplx s11[3][4], s12[3][4], s21[3][4], s22[3][4];
       for (int m = 0; m < 3; ++m) {
         const double d = R[3 * a + m] - R[3 * b + m];
@@ -478,6 +520,7 @@ extern "C" int vmc_huckel_params_theta_contracted(int n, double L, const double*
           }
       }
       S[(size_t)a * n + b] = v + eta * (gh + hg) + eta * eta * hh;
+      S[(size_t)b * n + a] = std::conj(S[(size_t)a * n + b]);
     }
   return hermitian_huckel(n, S, C_out);
 }
