@@ -366,9 +366,10 @@ int vmc_eval_configs(vmc_ctx* ctx, const vmc_system* sys, const double* R_dev, c
 
 /* a1 (host helper): Hueckel MO coefficients on the periodic s-Gaussians.
  * Overlap S_ab of the periodic Gaussians, H = -S_ab / sqrt(S_aa S_bb), its N/2
- * lowest eigenvectors v (symmetric QR iteration), C_ak = v_ak / sqrt(S_aa).
+ * lowest eigenvectors v (Householder reduction to tridiagonal form, the N/2 lowest eigenvalues
+ * by bisection, their eigenvectors by inverse iteration), C_ak = v_ak / sqrt(S_aa).
  * R, zeta: host (3N, N); C_out: host N x N/2.  VMC_EINVAL for a non-finite R or zeta <= 0,
- * VMC_ENOCONV if the QR iteration does not converge. */
+ * VMC_ENOCONV if an eigenvector does not come out finite. */
 int vmc_huckel_params(int n_protons, double box_L, const double* R, const double* zeta, double* C_out);
 /* The same for the twisted basis (twist as in vmc_system): image n of the overlap sum carries
  * prod_m (+-1)^{n_m}.  twist = 0 is vmc_huckel_params; outside 0..7: VMC_EINVAL. */
@@ -378,7 +379,7 @@ int vmc_huckel_params_twist(int n_protons, double box_L, int twist, const double
 /* The same for the contracted basis (vmc_system.contracted, coefficient eta): the overlaps of
  * phi_1 + eta phi_2 are one image sum of free-space Gaussian overlaps and of their derivatives
  * with respect to the exponents (r^2 e^{-Z r^2} = -d/dZ e^{-Z r^2}).  C_out: host N x N/2.
- * VMC_EINVAL for a non-finite R or eta, VMC_ENOCONV if the QR iteration does not converge. */
+ * VMC_EINVAL for a non-finite R or eta, VMC_ENOCONV if an eigenvector does not come out finite. */
 int vmc_huckel_params_contracted(int n_protons, double box_L, double eta, const double* R, double* C_out);
 
 /* The same for a general twist (vmc_system.general_twist): image n of the overlap sum carries
@@ -388,13 +389,13 @@ int vmc_huckel_params_contracted(int n_protons, double box_L, double eta, const 
  * twice there); the N/2 orthonormal complex vectors are taken from the lowest N of those by
  * Gram-Schmidt with column pivoting.  Any unitary mix of the occupied orbitals gives the same
  * |psi|, so C is defined up to one.  VMC_EINVAL for a non-finite R, theta or zeta <= 0,
- * VMC_ENOCONV if the QR iteration does not converge. */
+ * VMC_ENOCONV if an eigenvector does not come out finite. */
 int vmc_huckel_params_theta(int n_protons, double box_L, const double* theta, const double* R, const double* zeta,
                             double* C_out);
 /* The same on the contracted basis (phi_1 + eta phi_2 per proton, the SI's exponents Z1, Z2):
  * the overlaps of vmc_huckel_params_contracted with each axis's image k weighted e^{-i theta k};
  * C_out: N x N/2 complex (re, im) pairs.  VMC_EINVAL for odd or too small N, L <= 0, non-finite
- * theta, eta or R; VMC_ENOCONV if the QR iteration does not converge. */
+ * theta, eta or R; VMC_ENOCONV if an eigenvector does not come out finite. */
 int vmc_huckel_params_theta_contracted(int n_protons, double box_L, const double* theta, double eta, const double* R,
                                        double* C_out);
 
