@@ -44,7 +44,7 @@ enum {
   VMC_EDEVICE = -5,    /* a HIP runtime error */
   VMC_ENOTBUILT = -6,  /* no device code for this GPU */
   VMC_ECANCELLED = -7, /* stopped by vmc_cancel or vmc_server_cancel; the state is as before the call */
-  VMC_ENOCONV = -8     /* the host eigen-solver of the Hueckel orbitals did not converge */
+  VMC_ENOCONV = -8     /* the host eigen-solver of the Hueckel orbitals failed (no finite eigenvector) */
 };
 
 /* `step` of vmc_energy_forces: use the trajectory's own Langevin step counter. */

@@ -376,7 +376,7 @@ const char* vmc_strerror(int code) {
     case VMC_EDEVICE: return "HIP runtime error";
     case VMC_ENOTBUILT: return "no device code for this GPU";
     case VMC_ECANCELLED: return "cancelled";
-    case VMC_ENOCONV: return "host eigen-solver did not converge";
+    case VMC_ENOCONV: return "host eigen-solver failed";
     default: return "unknown error";
   }
 }
