@@ -138,3 +138,40 @@ def test_host_huckel_theta_contracted_spans_oracle_occupied_space(oracle, theta)
     if not np.any(th):
         Cr = vmc.vmc_huckel_params_contracted(wl.R, wl.L, 0.1)
         assert np.max(np.abs(proj(Cg) - proj(Cr.astype(complex)))) < 1e-11
+
+
+def _sc_lattice(m, rs):
+    """m^3 protons on a simple cubic lattice in the box of m^3 electrons at r_s (all zeta = 1):
+    every Hueckel level is a shell of the lattice's symmetry, many of them degenerate."""
+    n = m ** 3
+    L = (4.0 * np.pi * n / 3.0) ** (1.0 / 3.0) * rs
+    g = (np.arange(m) + 0.5) * (L / m)
+    R = np.array([[x, y, z] for x in g for y in g for z in g])
+    return n, L, R, np.ones(n)
+
+
+@pytest.mark.parametrize("m,theta,shells", [(4, None, True), (4, (np.pi / 2, 0.0, 0.0), True), (2, None, True),
+                                            (4, (0.3, -1.1, 2.0), False)])
+def test_host_huckel_on_degenerate_lattice_levels(oracle, m, theta, shells):
+    """On a perfect lattice the Hueckel levels come in degenerate shells, the occupied cut may fall
+    inside one, and the eigenvectors of a shell are any basis of it.  What is fixed: with
+    v = diag(S)^(1/2) C the occupied vectors are orthonormal, span an invariant subspace of
+    H = -S_ab / sqrt(S_aa S_bb) (H v = v (v^H H v)), and v^H H v has the N/2 lowest eigenvalues
+    of H (numpy's dense solver).  A general twist lifts the lattice's degeneracies (last case)."""
+    from paper_1605_08423_amd import vmc
+    n, L, R, zeta = _sc_lattice(m, 1.3)
+    th = np.zeros(3) if theta is None else np.array(theta)
+    S = np.asarray(oracle.coverlap(R, zeta, L, th))
+    dg = np.sqrt(S.diagonal().real)
+    H = -S / np.outer(dg, dg)
+    C = (np.asarray(vmc.vmc_huckel_params(R, zeta, L), dtype=complex) if theta is None
+         else np.asarray(vmc.vmc_huckel_params_theta(R, zeta, L, th)))
+    v = dg[:, None] * C
+    no = n // 2
+    ev = np.linalg.eigvalsh(H)
+    np.testing.assert_allclose(v.conj().T @ v, np.eye(no), atol=1e-12)
+    Hv = v.conj().T @ H @ v
+    np.testing.assert_allclose(H @ v, v @ Hv, atol=1e-12)
+    np.testing.assert_allclose(np.linalg.eigvalsh(Hv), ev[:no], atol=1e-12)
+    # the symmetric cases do have degenerate shells among the occupied levels
+    assert (np.min(np.diff(ev[:no])) < 1e-10) == shells
