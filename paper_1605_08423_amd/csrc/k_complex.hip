@@ -864,8 +864,10 @@ __device__ __forceinline__ void cgemm(const double* A, int lda, int MA, const do
 //   Re T_L = Re sum X_ia B_ai - 1/2 sum_i (lap_i U + |grad_i U|^2),  X_ia = -1/2 [lap phi_a + 2 grad phi_a . grad_i U]
 //   d ln|psi|/dR_b = -Re sum_i B_bi grad phi_b(r_i)
 //   d Re T_L/dR_b = Re sum_i [1/2 (grad lap phi_b + 2 Hess phi_b . grad_i U) B_bi + grad phi_b(r_i) W_bi]
+// Two work-groups per CU for the single Gaussian (a few registers spill), so that measurements of
+// twists on other streams share a CU; the contracted basis needs one CU's registers per walker.
 template <int NS, bool CB>
-__global__ __launch_bounds__(256, 1) void k_cslater_sample(MeasureArgs m, TwistArgs tw) {
+__global__ __launch_bounds__(256, CB ? 1 : 2) void k_cslater_sample(MeasureArgs m, TwistArgs tw) {
   using LY = CSlaterLay<NS>;
   constexpr int N = 2 * NS, NSP = LY::NSP, NP = LY::NP, H = LY::H, HJ = LY::HJ;
   constexpr int NT = H * N, IPT = (NS + H - 1) / H;
