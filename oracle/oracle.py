@@ -34,7 +34,8 @@ class OSys(C.Structure):
                 ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
                 ("R", C.POINTER(C.c_double)), ("zeta", C.POINTER(C.c_double)),
                 ("C", C.POINTER(C.c_double)), ("b1", C.c_double), ("twist", C.c_int),
-                ("contracted", C.c_int), ("eta", C.c_double), ("j3f", C.c_double * 3)]
+                ("contracted", C.c_int), ("eta", C.c_double), ("j3f", C.c_double * 3),
+                ("j1f", C.c_double * 2)]
 
 
 Z1, Z2 = 0.6066825, 0.3382168   # the SI's exponents of the contracted minimal basis
@@ -109,7 +110,7 @@ class System:
 
     def __init__(self, R, zeta, C_mo, L=0.0, n_up=None, n_dn=None, basis=OB_PERIODIC_GAUSS,
                  pot=OP_EWALD, kappa=None, nmax=9, jastrow=True, a_par=0.25, a_anti=0.5, b=1.0,
-                 b1=0.0, twist=0, eta=None, j3=None):
+                 b1=0.0, twist=0, eta=None, j3=None, j1f=None):
         self.R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1, 3)
         n_p = self.R.shape[0]
         self.zeta = np.ascontiguousarray(zeta, dtype=np.float64).reshape(n_p)
@@ -125,7 +126,8 @@ class System:
         self.s = OSys(n_p, n_up, n_dn, self.C.shape[1], float(L), basis, pot, float(kappa), int(nmax),
                       int(bool(jastrow)), a_par, a_anti, b, _dp(self.R), _dp(self.zeta), _dp(self.C),
                       float(b1), int(twist), int(eta is not None), float(eta or 0.0),
-                      (C.c_double * 3)(*(j3 if j3 is not None else (0.0, 0.0, 0.0))))
+                      (C.c_double * 3)(*(j3 if j3 is not None else (0.0, 0.0, 0.0))),
+                      (C.c_double * 2)(*(j1f if j1f is not None else (0.0, 0.0))))
 
     @property
     def n_p(self):

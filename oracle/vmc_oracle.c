@@ -393,6 +393,7 @@ static void radial_field(const osys* s, const double d[3], const double F[4], do
 
 /* ------------------------------------------------------ three-body term -- */
 static int j3_on(const osys* s) { return s->j3f[0] != 0.0 || s->j3f[1] != 0.0 || s->j3f[2] != 0.0; }
+static int j1f_on(const osys* s) { return s->j1f[0] != 0.0 || s->j1f[1] != 0.0; }
 
 /* One Cartesian factor of the Jastrow orbitals at the offset d along an axis: with the periodised
  * component rho = (L/pi) sin(pi d / L) (rho = d in the open kinds), u = rho^2 and
@@ -461,6 +462,17 @@ void o_jastrow(const osys* s, const double* x, double* U, double* gradU, double*
         if (gradU)
           for (int m = 0; m < 3; ++m) gradU[3 * i + m] += g[m];
         if (lapU) lapU[i] += lp;
+      }
+  /* the orbital part of U_1 (Eq. e:j1): f^T chi_a(r_i) over every electron and nucleus */
+  if (j1f_on(s))
+    for (int i = 0; i < ne; ++i)
+      for (int a = 0; a < s->n_p; ++a) {
+        double c[28];
+        o_j3_orbitals(s, a, x + 3 * i, c);
+        Ut += s->j1f[0] * c[0] + s->j1f[1] * c[14];
+        if (gradU)
+          for (int m = 0; m < 3; ++m) gradU[3 * i + m] += s->j1f[0] * c[1 + m] + s->j1f[1] * c[15 + m];
+        if (lapU) lapU[i] += s->j1f[0] * c[4] + s->j1f[1] * c[18];
       }
   if (j3_on(s)) {
     const int np = s->n_p;
@@ -658,6 +670,23 @@ void o_jastrow_dR(const osys* s, const double* x, const double* vv, double* dln,
           dT[3 * a + mu] += 0.5 * gl[mu] + hv;
         }
       }
+  /* The orbital part of U_1, f^T chi_a(r_i - R_a), the same way: d ln psi/dR_a,mu gets
+   * -f^T d_mu chi_ai and the kinetic part 1/2 f^T d_mu lap chi_ai + sum_nu v_i,nu f^T d_mu d_nu chi_ai. */
+  if (j1f_on(s))
+    for (int a = 0; a < np; ++a)
+      for (int i = 0; i < ne; ++i) {
+        double c[28];
+        o_j3_orbitals(s, a, x + 3 * i, c);
+        for (int mu = 0; mu < 3; ++mu) {
+          dln[3 * a + mu] -= s->j1f[0] * c[1 + mu] + s->j1f[1] * c[15 + mu];
+          double t = 0.5 * (s->j1f[0] * c[11 + mu] + s->j1f[1] * c[25 + mu]);
+          for (int nu = 0; nu < 3; ++nu) {
+            const int q = hidx(mu, nu);
+            t += vv[3 * i + nu] * (s->j1f[0] * c[q] + s->j1f[1] * c[14 + q]);
+          }
+          dT[3 * a + mu] += t;
+        }
+      }
   /* The three-body term depends on R_a through chi_a(r_i - R_a), d/dR_a = -grad_i on it: with
    * v_k = grad_k U + grad_k ln|D| and the sums over the other electrons j != k,
    *   d ln psi/dR_a,mu = -sum_k sum_j (d_mu chi_ak)^T F chi_aj,
@@ -787,7 +816,7 @@ int o_local(const osys* s, const double* x, double* lnpsi, double* sign, double*
     }
     free(bf); free(A); free(G); free(Lp); free(Ai);
   }
-  if (rc == 0 && want && (s->b1 > 0.0 || j3_on(s))) {
+  if (rc == 0 && want && (s->b1 > 0.0 || j3_on(s) || j1f_on(s))) {
     double* vv = malloc(sizeof(double) * 3 * ne);
     for (int t = 0; t < 3 * ne; ++t) vv[t] = gU[t] + gDe[t];
     o_jastrow_dR(s, x, vv, dln, dT);
@@ -1076,6 +1105,14 @@ int o_vmc_run_opt(const osys* s, int W, uint32_t w0, double* x, int n_equil, int
             j1_radial(s->b1, periodised_rho(s, dn), F1);
             j1_radial(s->b1, periodised_rho(s, dold), F0);
             dU += F1[0] - F0[0];
+          }
+        if (j1f_on(s))
+          /* the orbital part of U_1: f^T (chi(r' - R_a) - chi(r_e - R_a)) over the nuclei */
+          for (int a = 0; a < s->n_p; ++a) {
+            double cn[28], co[28];
+            o_j3_orbitals(s, a, rn, cn);
+            o_j3_orbitals(s, a, xw + 3 * e, co);
+            dU += s->j1f[0] * (cn[0] - co[0]) + s->j1f[1] * (cn[14] - co[14]);
           }
         if (j3_on(s))
           /* the three-body change: sum over nuclei and the other electrons of

@@ -45,6 +45,9 @@ typedef struct {
                           (Eq. e:j33): f_11, f_12 = f_21, f_22 of the 2 x 2 matrix coupling the
                           orbitals chi_1 = e^{-ZJ rho^2}, chi_2 = rho^2 e^{-ZJ rho^2} (O_ZJ) of two
                           electrons on the same nucleus, the same for every nucleus; all zero = no term */
+  double j1f[2];       /* the orbital part of the one-body Jastrow term U_1 of the SI (Eq. e:j1):
+                          sum_a sum_i (f_1 chi_1 + f_2 chi_2)(r_i - R_a) on the three-body term's
+                          orbitals, the same f for every nucleus; both zero = no such part */
 } osys;
 
 /* The exponent of the Jastrow orbitals (SI, Jastrow section). */

@@ -15,8 +15,9 @@ import pytest
 from paper_1605_08423_amd.inputs import small_system, workload
 
 THETAS = [(0.3, -1.1, 2.0), (np.pi / 4, 3 * np.pi / 4, -np.pi / 4)]
-# the Jastrow factor: the two-body term alone, and with the one-body and three-body terms
-JAS = [dict(), dict(b1=1.7, j3=(-0.3, 0.1, 0.05))]
+# the Jastrow factor: the two-body term alone, with the one-body and three-body terms, and with
+# the orbital part of the one-body term as well
+JAS = [dict(), dict(b1=1.7, j3=(-0.3, 0.1, 0.05)), dict(b1=1.7, j3=(-0.3, 0.1, 0.05), j1f=(0.35, -0.6))]
 
 
 def _sys(oracle, wl, theta, **kw):
