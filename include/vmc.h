@@ -123,6 +123,12 @@ typedef struct {
                          one-body term), and is not for the server (else VMC_EINVAL); its orbitals are evaluated in the precision of
                          the Jastrow terms (FP32 in VMC_MIXED), their per-nucleus sums combined and
                          accumulated in FP64 */
+  double j1_f[2];     /* the orbital part of the one-body Jastrow term U_1 of the SI (Jastrow section,
+                         Eq. e:j1): sum_a sum_i (f_1 chi_1 + f_2 chi_2)(r_i - R_a) on the three-body
+                         term's orbitals chi_1, chi_2, with (f_1, f_2) = (j1_f[0], j1_f[1]) the same for
+                         every nucleus (finite).  Both zero: no such part.  Independent of j1_b1 (the
+                         cusp part) and of j3_f, with the same scope as j3_f: N_sigma <= 64, not for the
+                         server (else VMC_EINVAL), evaluated and accumulated like the three-body term */
 } vmc_system;
 
 /* ---------------------------------------------------------------- context -- */

@@ -30,10 +30,10 @@ struct CkptHeader {
   char magic[8];
   uint32_t version, seed, traj_id, lang_step;
   int32_t n, w, precision, nmax, twist, have_means, have_R, have_prev, have_S, general_twist, contracted, pad_;
-  double box_L, kappa, a_par, a_anti, b, j1_b1, theta[3], eta, j3_f[3];
+  double box_L, kappa, a_par, a_anti, b, j1_b1, theta[3], eta, j3_f[3], j1_f[2];
   uint64_t payload_bytes, checksum;
 };
-constexpr uint32_t kCkptVersion = 3;
+constexpr uint32_t kCkptVersion = 4;
 size_t ckpt_payload_bytes(int n, int w);
 // Writes magic, version and payload size into h (the caller fills the rest).
 void ckpt_init_header(CkptHeader* h, int n, int w);

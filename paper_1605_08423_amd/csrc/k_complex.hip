@@ -693,6 +693,7 @@ __global__ __launch_bounds__(CT, 1) void k_csweep(WalkerArgs a, SweepArgs s, Twi
               const double g1 = Gj[tt][0] - o1, g2 = Gj[tt][1] - o2;
               du += a.j3f[0] * dj[tt][0] * g1 + a.j3f[1] * (dj[tt][0] * g2 + dj[tt][1] * g1) +
                     a.j3f[2] * dj[tt][1] * g2;
+              du += a.j1f[0] * dj[tt][0] + a.j1f[1] * dj[tt][1];   // the one-body orbital part
             }
           }
           double dU = base[j] + wave_allsum(du);

@@ -14,6 +14,9 @@
 //   d T_L/dR_a,mu = P_mu^T F G_a + Q^T F G_a,mu - sum_k (X_k,mu^T F chi_ak + Y_k^T F d_mu chi_ak),
 //   d ln psi/dR_a,mu = -G_a,mu^T F G_a + sum_k (d_mu chi_ak)^T F chi_ak,
 // which one pass over the electrons forms, evaluating each pair's orbitals once.
+// The orbital part of the one-body term (Eq. e:j1), U_1f = sum_a f^T G_a, is linear in the same
+// orbitals: grad_k and lap_k get sum_a f^T (grad, lap) chi_ak, d ln psi/dR_a,mu gets -f^T G_a,mu and
+// d T_L/dR_a,mu gets f^T P_mu; the kernels add these beside the three-body terms.
 // The sweep keeps G_a of every walker current (k_sweep_half's three-body variant); k_j3_init forms
 // G_a from the positions before the sweeps (FP64), and the measurement's kernels evaluate the
 // orbitals and their sums in the working precision of the Jastrow terms (FP32 in mixed precision,
@@ -170,6 +173,7 @@ __global__ __launch_bounds__(256) void k_j3_grad(MeasureArgs m) {
   __syncthreads();
   const Real LoP = (Real)(m.L / VMC_PI), kf = (Real)((VMC_PI * m.invL) * (VMC_PI * m.invL)), Z = (Real)kZJ;
   const Real F[3] = {(Real)m.j3f[0], (Real)m.j3f[1], (Real)m.j3f[2]};
+  const Real f1 = (Real)m.j1f[0], f2 = (Real)m.j1f[1];
   for (int c = t; c < N; c += T) {
     Real g1 = Real(0), g2 = Real(0), q = Real(0);
     for (int i = 0; i < N; ++i) {
@@ -197,22 +201,23 @@ __global__ __launch_bounds__(256) void k_j3_grad(MeasureArgs m) {
       pair_trig<Real>(te + 6 * k, ta + 6 * c, s, cc);
       j3_orbitals<Real, 5>(s, cc, LoP, kf, c1, c2);
       const Real r1 = G[2 * c] - c1[0], r2 = G[2 * c + 1] - c2[0];
-      gx += fform<Real>(F, c1[1], c2[1], r1, r2);
-      gy += fform<Real>(F, c1[2], c2[2], r1, r2);
-      gz += fform<Real>(F, c1[3], c2[3], r1, r2);
-      lp += fform<Real>(F, c1[4], c2[4], r1, r2);
+      gx += fform<Real>(F, c1[1], c2[1], r1, r2) + (f1 * c1[1] + f2 * c2[1]);
+      gy += fform<Real>(F, c1[2], c2[2], r1, r2) + (f1 * c1[2] + f2 * c2[2]);
+      gz += fform<Real>(F, c1[3], c2[3], r1, r2) + (f1 * c1[3] + f2 * c2[3]);
+      lp += fform<Real>(F, c1[4], c2[4], r1, r2) + (f1 * c1[4] + f2 * c2[4]);
     }
     out[3 * k] = (double)gx;
     out[3 * k + 1] = (double)gy;
     out[3 * k + 2] = (double)gz;
     out[3 * N + k] = (double)lp;
   }
-  // U_3 = 1/2 sum_a (G^T F G - Q_a), in a fixed order, in FP64 from the per-nucleus sums
+  // U_3 = 1/2 sum_a (G^T F G - Q_a) and U_1f = sum_a f^T G_a, in a fixed order, in FP64 from the
+  // per-nucleus sums
   const double Fd[3] = {m.j3f[0], m.j3f[1], m.j3f[2]};
   double part = 0.0;
   for (int c = t; c < N; c += T) {
     const double g1 = (double)G[2 * c], g2 = (double)G[2 * c + 1];
-    part += 0.5 * (fform<double>(Fd, g1, g2, g1, g2) - (double)Q[c]);
+    part += 0.5 * (fform<double>(Fd, g1, g2, g1, g2) - (double)Q[c]) + (m.j1f[0] * g1 + m.j1f[1] * g2);
   }
   part = wave_allsum(part);
   if ((t & 63) == 0) red[t >> 6] = part;
@@ -284,8 +289,9 @@ __global__ __launch_bounds__(256) void k_j3_forces(MeasureArgs m) {
     for (int mu = 0; mu < 3; ++mu) {
       const double gm1 = (double)Gm1[mu], gm2 = (double)Gm2[mu];
       const double dT = fform<double>(Fd, (double)P1[mu], (double)P2[mu], g1, g2) +
-                        fform<double>(Fd, q1, q2, gm1, gm2) - (double)sT[mu];
-      const double dln = (double)sL[mu] - fform<double>(Fd, gm1, gm2, g1, g2);
+                        fform<double>(Fd, q1, q2, gm1, gm2) - (double)sT[mu] +
+                        (m.j1f[0] * (double)P1[mu] + m.j1f[1] * (double)P2[mu]);
+      const double dln = (double)sL[mu] - fform<double>(Fd, gm1, gm2, g1, g2) - (m.j1f[0] * gm1 + m.j1f[1] * gm2);
       acc[2 + 3 * c + mu] += dT;
       acc[2 + 3 * N + 3 * c + mu] += dln;
       acc[2 + 6 * N + 3 * c + mu] += EL * dln;

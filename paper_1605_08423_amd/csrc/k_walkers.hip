@@ -626,7 +626,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
                 pade_u<Real>(so, co, ts[tt], tc_[tt], LoverPi, aa, bj);
         }
       }
-      // three-body change over the lane's nuclei: (chi(r') - chi(r))^T F (G_a - chi(r))
+      // three-body change over the lane's nuclei, (chi(r') - chi(r))^T F (G_a - chi(r)), and the
+      // one-body orbital part's, f^T (chi(r') - chi(r))
       Real dj[EPL][2];
       if constexpr (J3) {
 #pragma unroll
@@ -644,6 +645,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep_half(WalkerArgs a, SweepArgs s
             const Real g1 = (Real)Gj[tt][0] - o1, g2 = (Real)Gj[tt][1] - o2;
             du += (Real)a.j3f[0] * dj[tt][0] * g1 + (Real)a.j3f[1] * (dj[tt][0] * g2 + dj[tt][1] * g1) +
                   (Real)a.j3f[2] * dj[tt][1] * g2;
+            // the one-body term's orbital part: f^T (chi(r') - chi(r))
+            du += (Real)a.j1f[0] * dj[tt][0] + (Real)a.j1f[1] * dj[tt][1];
           }
         }
       }

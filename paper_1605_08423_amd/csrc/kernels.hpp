@@ -27,8 +27,10 @@ struct WalkerArgs {
   size_t rscr_stride;
   int contracted;      // 1: the contracted orbital phi_1 + eta phi_2 per proton (zeta unused)
   double eta;
-  int j3;              // 1: the on-site three-body Jastrow term with the matrix j3f = (f11, f12, f22)
+  int j3;              // 1: the Jastrow-orbital terms are on: the on-site three-body term with the
+                       // matrix j3f = (f11, f12, f22) and/or the one-body orbital part with j1f
   double j3f[3];
+  double j1f[2];       // (f_1, f_2) of the one-body term's orbital part, f^T chi_a(r_i) per pair
   double* j3G;         // W x N x 2: per walker and nucleus, G_a = sum over electrons of (chi_1, chi_2)
 };
 
@@ -77,6 +79,7 @@ struct MeasureArgs {
   double eta;
   int j3;               // as in WalkerArgs
   double j3f[3];
+  double j1f[2];
   double* j3scr;        // W x j3_measure_doubles(N): the term's per-electron gradient, Laplacian and U_3,
                         // then the full grad U, grad ln|D| and E_L of the sample (written by the Slater pass)
   double* ELs;          // W: E_L of the sample, written by the Slater pass when not null

@@ -172,6 +172,9 @@ bool supported_ns(int ns) { return ns == 8 || ns == 16 || ns == 27 || ns == 32 |
 constexpr double kContractedZ2 = 0.3382168;   // the smaller exponent of the contracted orbital
 
 bool has_j3(const vmc_system& s) { return s.j3_f[0] != 0.0 || s.j3_f[1] != 0.0 || s.j3_f[2] != 0.0; }
+// the Jastrow-orbital terms (three-body F, one-body orbital part f) share the orbitals, the per-walker
+// nucleus sums G_a and the measurement kernels
+bool has_jorb(const vmc_system& s) { return has_j3(s) || s.j1_f[0] != 0.0 || s.j1_f[1] != 0.0; }
 
 int check_sys(const vmc_system* s) {
   if (!s) return VMC_EINVAL;
@@ -191,7 +194,9 @@ int check_sys(const vmc_system* s) {
   if (s->contracted != 0 && s->contracted != 1) return VMC_EINVAL;
   for (int m = 0; m < 3; ++m)
     if (!std::isfinite(s->j3_f[m])) return VMC_EINVAL;
-  if (has_j3(*s) && s->n_protons / 2 > 64) return VMC_EINVAL;
+  for (int m = 0; m < 2; ++m)
+    if (!std::isfinite(s->j1_f[m])) return VMC_EINVAL;
+  if (has_jorb(*s) && s->n_protons / 2 > 64) return VMC_EINVAL;
   if (s->contracted) {
     // the images |n| <= 1 of the diffuse r^2 e^{-Z2 r^2} reach FP64 resolution only if Z2 (1.5 L)^2 >= 36
     const double h = 1.5 * s->box_L;
@@ -264,8 +269,9 @@ WalkerArgs walker_args(vmc_traj* t, const double* R, const double* C, const doub
   a.rscr_stride = slater_scratch_bytes(t->NS, t->sys.precision == VMC_MIXED) / sizeof(double);
   a.contracted = t->sys.contracted;
   a.eta = t->sys.eta;
-  a.j3 = has_j3(t->sys);
+  a.j3 = has_jorb(t->sys);
   for (int q = 0; q < 3; ++q) a.j3f[q] = t->sys.j3_f[q];
+  for (int q = 0; q < 2; ++q) a.j1f[q] = t->sys.j1_f[q];
   a.j3G = t->j3G;
   return a;
 }
@@ -282,8 +288,9 @@ MeasureArgs measure_args(vmc_traj* t, const double* R, const double* C, const do
   m.acc = t->acc; m.rho_acc = t->rho_acc; m.scr = t->scr;
   m.contracted = t->sys.contracted;
   m.eta = t->sys.eta;
-  m.j3 = has_j3(t->sys);
+  m.j3 = has_jorb(t->sys);
   for (int q = 0; q < 3; ++q) m.j3f[q] = t->sys.j3_f[q];
+  for (int q = 0; q < 2; ++q) m.j1f[q] = t->sys.j1_f[q];
   m.j3scr = t->j3scr;
   m.ELs = t->param_stats ? t->ELs : nullptr;
   m.popt = t->popt;
@@ -344,7 +351,7 @@ size_t traj_bytes(const vmc_system& s, int W) {
   const size_t d = 2 * Wz * N * 3 + amat + Wz * 2 * inv_doubles(s) + 2 * Wz * 2 + Wz * (2 + 9 * N) + Wz * nk * 2 + Wz +
                    Wz * n3 + Wz + Wz * (1 + 3 * n3) + Wz * n3 + reduce_partial_doubles(W, (int)n3) + 3 + n3 +
                    kv.size() + 2 * nk + nk * N * 2 + n3 + 1 + 2 * n3 + 2 * n3 * n3;
-  const size_t j3 = has_j3(s) ? Wz * (2 * N + j3_measure_doubles((int)N)) : 0;
+  const size_t j3 = has_jorb(s) ? Wz * (2 * N + j3_measure_doubles((int)N)) : 0;
   const size_t opt = Wz * (1 + kOptStats);
   return (d + j3 + opt) * sizeof(double) + 2 * Wz * sizeof(int64_t) +
          (3 * Wz + 2 + slots.size() + nx0.size()) * sizeof(int) + Wz * meas_scratch_bytes(s);
@@ -516,7 +523,7 @@ int vmc_traj_create(vmc_ctx* ctx, const vmc_system* sys, int W, uint32_t seed, u
             !dalloc(&t->ELs, (size_t)W) && !dalloc(&t->popt, (size_t)W * kOptStats);
   const size_t scr = meas_scratch_bytes(*sys);
   if (ok && scr) ok = !dalloc(&t->scr, (size_t)W * scr);
-  if (ok && has_j3(*sys))
+  if (ok && has_jorb(*sys))
     ok = !dalloc(&t->j3G, (size_t)W * N * 2) && !dalloc(&t->j3scr, (size_t)W * j3_measure_doubles((int)N));
   if (!ok) { free_traj(t); return VMC_ENOMEM; }
   if (hipMemcpy(t->kvec, kv.data(), kv.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -578,6 +585,7 @@ int vmc_traj_save(vmc_traj* t, void* buf, size_t* len) {
   h.b = t->sys.b; h.j1_b1 = t->sys.j1_b1;
   h.general_twist = t->sys.general_twist; h.contracted = t->sys.contracted; h.eta = t->sys.eta;
   for (int q = 0; q < 3; ++q) { h.theta[q] = t->sys.theta[q]; h.j3_f[q] = t->sys.j3_f[q]; }
+  for (int q = 0; q < 2; ++q) h.j1_f[q] = t->sys.j1_f[q];
   unsigned char* p = static_cast<unsigned char*>(buf);
   std::memcpy(p, &h, sizeof h);
   p += sizeof h;
@@ -620,7 +628,8 @@ static int traj_load(vmc_traj* t, const void* buf, size_t len, bool rescale) {
   js.b = h.b;
   js.j1_b1 = h.j1_b1;
   for (int q = 0; q < 3; ++q) js.j3_f[q] = h.j3_f[q];
-  if (check_sys(&js) || (js.j1_b1 > 0.0) != (s.j1_b1 > 0.0) || (has_j3(js) && !t->j3G)) return VMC_EINVAL;
+  for (int q = 0; q < 2; ++q) js.j1_f[q] = h.j1_f[q];
+  if (check_sys(&js) || (js.j1_b1 > 0.0) != (s.j1_b1 > 0.0) || (has_jorb(js) && !t->j3G)) return VMC_EINVAL;
   if (!rescale && (h.box_L != s.box_L || h.kappa != s.ewald_kappa)) return VMC_EINVAL;
   if (rescale && !(h.box_L > 0.0 && std::isfinite(h.box_L))) return VMC_EINVAL;
   HIPCHK(hipSetDevice(t->ctx->device));
@@ -828,7 +837,7 @@ int vmc_traj_set_jastrow(vmc_traj* t, double b, double j1_b1, const double* j3_f
   // the one-body term stays on or off; the three-body term may change freely only where its
   // per-walker memory exists (it was on at creation)
   if ((j1_b1 > 0.0) != (t->sys.j1_b1 > 0.0)) return VMC_EINVAL;
-  if (has_j3(s) && !t->j3G) return VMC_EINVAL;
+  if (has_jorb(s) && !t->j3G) return VMC_EINVAL;
   t->sys = s;
   t->have_means = false;
   t->have_popt = false;
@@ -1356,7 +1365,7 @@ int bucket_sweep(vmc_server* s, const std::vector<Served*>& qs) {
 }
 
 int check_request(const vmc_request* r) {
-  if (!r || check_sys(&r->sys) || r->sys.general_twist || r->sys.contracted || has_j3(r->sys)) return VMC_EINVAL;
+  if (!r || check_sys(&r->sys) || r->sys.general_twist || r->sys.contracted || has_jorb(r->sys)) return VMC_EINVAL;
   if (r->n_walkers < 2 || r->n_sweeps < 1 || r->n_equil < 0 || r->n_equil_first < 0 || r->n_steps < 1)
     return VMC_EINVAL;
   if (!(r->step_delta > 0.0) || !(r->Delta > 0.0) || r->alpha < 0.0 || r->T < 0.0 || (r->flags & ~7u))

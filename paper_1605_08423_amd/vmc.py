@@ -45,7 +45,7 @@ class vmc_system(C.Structure):
                 ("ewald_nmax", C.c_int), ("a_par", C.c_double), ("a_anti", C.c_double), ("b", C.c_double),
                 ("precision", C.c_int), ("refine_tol", C.c_double), ("j1_b1", C.c_double), ("twist", C.c_int),
                 ("general_twist", C.c_int), ("theta", C.c_double * 3), ("contracted", C.c_int),
-                ("eta", C.c_double), ("j3_f", C.c_double * 3)]
+                ("eta", C.c_double), ("j3_f", C.c_double * 3), ("j1_f", C.c_double * 2)]
 
 
 class vmc_request(C.Structure):
@@ -149,16 +149,17 @@ def _dev(t, n=None):
 
 
 def make_system(n, L, kappa=None, nmax=9, a_par=0.25, a_anti=0.5, b=1.0, precision=VMC_FP64, refine_tol=0.0,
-                b1=0.0, twist=0, theta=None, eta=None, j3=None):
+                b1=0.0, twist=0, theta=None, eta=None, j3=None, j1f=None):
     """b1 > 0 adds the one-body electron-proton Jastrow term with that b_1 (0: none); twist:
     bit m = twist angle pi along axis m; theta (3 angles, radians): a general twist with complex
     orbitals (FP64 only); eta: the contracted orbital phi_1 + eta phi_2 per proton; j3: (f11, f12, f22) of
-    the on-site three-body Jastrow term."""
+    the on-site three-body Jastrow term; j1f: (f_1, f_2) of the one-body term's orbital part."""
     th = (C.c_double * 3)(*([0.0] * 3 if theta is None else [float(v) for v in theta]))
     return vmc_system(int(n), float(L), float(8.0 / L if kappa is None else kappa), int(nmax), a_par, a_anti, b,
                       int(precision), float(refine_tol), float(b1), int(twist), int(theta is not None), th,
                       int(eta is not None), float(eta or 0.0),
-                      (C.c_double * 3)(*(j3 if j3 is not None else (0.0, 0.0, 0.0))))
+                      (C.c_double * 3)(*(j3 if j3 is not None else (0.0, 0.0, 0.0))),
+                      (C.c_double * 2)(*(j1f if j1f is not None else (0.0, 0.0))))
 
 
 def _c_doubles(system):
