@@ -232,3 +232,51 @@ def test_h128_mixed_within_2sigma_of_512_walker_oracle(oracle, dev):
     assert abs(g["out"][0] - gold["E"]) < 2 * sig
     assert 0.5 < np.mean(z * z) < 1.6
     assert np.mean(np.abs(z) > 2) < 0.12
+
+
+def _cond_up(s, x, Cm, n_up):
+    """2-norm condition number of the up-spin Slater matrix A_ik = sum_a phi_a(r_i) C_ak, from the
+    oracle's basis values."""
+    n_p = Cm.shape[0]
+    Phi = np.array([[s.basis(a, x[i])[0] for a in range(n_p)] for i in range(n_up)])
+    return float(np.linalg.cond(Phi @ Cm[:, :n_up]))
+
+
+def test_mixed_error_follows_the_slater_conditioning(oracle, dev):
+    """The conditioning tail of the mixed mode, exercised against the oracle: one up-spin electron
+    is moved onto another at distances 0.3, 0.03, 0.003 and 0.0003 bohr, which drives the Slater
+    matrix's condition number kappa from 1.3e2 to 1.9e5.  The kinetic terms of E_L are sums over
+    entries of B = C A^-1 (which grow with kappa) that cancel to O(1), and its R-derivatives contract
+    two such factors (W = B M), so the rounding of the FP32-stored products is amplified by up to
+    (kappa / kappa_0)^2 against the well-conditioned start kappa_0 (measured on this sequence: the
+    mixed E_L error grows from 2e-9 to 9e-2, dE_L/dR from 7e-8 to 0.3).  The bar is the
+    per-configuration one plus 8 (kappa / kappa_0)^2 u, with u = 2^-24 in mixed precision and
+    2^-53 (over 1e-10) in FP64."""
+    torch, vmc, ctx = dev
+    wl = workload("h16")
+    n_up = wl.n // 2
+    Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, n_up)
+    base = wl.electrons(W=1, seed_offset=12)[0]
+    u = np.array([0.6, -0.48, 0.64])
+    cfgs = []
+    for d in (0.3, 0.03, 0.003, 0.0003):
+        x = base.copy()
+        x[1] = np.mod(x[0] + d * u, wl.L)
+        cfgs.append(x)
+    pos = np.array(cfgs)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L)
+    kap = [_cond_up(s, x, Cm, n_up) for x in cfgs]
+    ref = [s.local(x) for x in cfgs]
+    n3 = 3 * wl.n
+    for prec, bar, eps in ((vmc.VMC_MIXED, TOL, 2.0 ** -24), (vmc.VMC_FP64, None, 2.0 ** -53)):
+        g = vmc.vmc_eval_configs(ctx, vmc.make_system(wl.n, wl.L, precision=prec), T(torch, wl.R.reshape(-1)),
+                                 T(torch, Cm), T(torch, wl.zeta), T(torch, pos)).cpu().numpy()
+        for k, (x, r) in enumerate(zip(cfgs, ref)):
+            eE, eD = rel(g[k, 1], r["EL"]), elem(g[k, 2 + n3:], r["dEL"])
+            amp = 8 * (kap[k] / kap[0]) ** 2 * eps
+            lim = (1e-10 if bar is None else bar["EL"]) + amp
+            limD = (1e-10 if bar is None else bar["dEL"]) + amp
+            say(f"  {'fp64' if bar is None else 'mixed'} kappa={kap[k]:.2e}: E_L rel err {eE:.2e} (bar {lim:.2e}), "
+                f"dE_L/dR {eD:.2e} (bar {limD:.2e})")
+            assert eE < lim and eD < limD
+    assert kap[-1] > 100 * kap[0]
