@@ -86,8 +86,9 @@ def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, on
         # per sample: the two-body derivative over the N(N-1)/2 electron pairs (periodised
         # distance 18, sqrt, the Pade derivative 6), the one-body derivative over the N^2
         # electron-proton pairs (distance 18, exp, 6), the three-body sums per proton (distance 15,
-        # exp, 8) in the working precision of the Jastrow terms, and the 36 moments in FP64
-        return _add({"f64": 72}, lo, N * (N - 1) // 2 * 25 + (N * N * 25 if one_body else 0) + N * N * 24)
+        # exp, 8) in the working precision of the Jastrow terms, and the 64 moments of the seven
+        # parameters in FP64
+        return _add({"f64": 128}, lo, N * (N - 1) // 2 * 25 + (N * N * 25 if one_body else 0) + N * N * 24)
     if cls == "j3_init":
         # G_a = sum_i chi_a(r_i) of every nucleus: per (electron, nucleus) pair the squared
         # periodised distance (15), an exp and two sums
@@ -680,13 +681,13 @@ def run_opt_leg(wl, W: int, M: int, prec: int, b1: float, F, n_opt: int, m_opt: 
     """Langevin steps with the wavefunction re-optimised before each (the paper's n_opt steps of
     optimisation per ionic step): n_opt stochastic-reconfiguration iterations, each m_opt measured
     sweeps (+5 re-equilibration) with the parameter statistics, the SR step on the parameters in
-    `mask` (bits: b, b_1, f11, f12, f22) and the new parameters, then the energy/force estimate, S
+    `mask` (bits: b, b_1, f11, f12, f22, f1, f2) and the new parameters, then the energy/force estimate, S
     and the update as in run_leg.  The first step is the warm-up; `steps` are timed."""
     import torch
     from paper_1605_08423_amd import vmc
     ctx = vmc.Context(0)
-    p = np.array([1.0, b1, *F], dtype=np.float64)
-    sysd = vmc.make_system(wl.n, wl.L, precision=prec, b=p[0], b1=p[1], j3=tuple(p[2:]))
+    p = np.array([1.0, b1, *F, 0.0, 0.0], dtype=np.float64)   # the leg's wavefunction has no orbital part f
+    sysd = vmc.make_system(wl.n, wl.L, precision=prec, b=p[0], b1=p[1], j3=tuple(p[2:5]))
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     traj = vmc.Trajectory(ctx, sysd, W, seed=wl.seed, traj_id=0)
     traj.set_walkers(dev(wl.electrons(W=W)))
@@ -710,7 +711,7 @@ def run_opt_leg(wl, W: int, M: int, prec: int, b1: float, F, n_opt: int, m_opt: 
             energies.append(float(st[0].item()))
             dp = vmc.vmc_sr_update(st, mask, eps, tau)
             p = p + dp
-            traj.set_jastrow(p[0], p[1], tuple(p[2:]))
+            traj.set_jastrow(p[0], p[1], tuple(p[2:5]), tuple(p[5:7]))
             path.append(p.copy())
         traj.set_param_stats(False)
         sr_s.append(time.perf_counter() - ts)
@@ -1009,7 +1010,7 @@ def main():
                         "ms_per_sr_iteration": round(1e3 * r["sr_s"], 2),
                         "walker_sweeps_per_s": round(W * r["sweeps_per_step"] * r["steps"] / r["elapsed"], 1),
                         "E_Ha": float(r["out"][0]), "sr_E_Ha": [round(e, 4) for e in r["sr_E"]],
-                        "params_b_b1_F": [round(float(v), 4) for v in r["path"][-1]], "opt_sample": per,
+                        "params_b_b1_F_f": [round(float(v), 4) for v in r["path"][-1]], "opt_sample": per,
                         "kernel_ms": {k: round(v[0], 2) for k, v in kms.items()}}
 
     mesh = None

@@ -232,33 +232,36 @@ int vmc_traj_walkers_reset(vmc_traj* traj, int* n_reset);
 /* ------------------------------------------------ wavefunction optimisation --
  * The main text re-optimises the wavefunction before every ionic step (n_opt optimisation steps
  * per step) and cites its optimiser; these calls give stochastic reconfiguration (SR; Sorella,
- * PRB 64, 024512 (2001)) on the Jastrow parameters p = (b, b_1, f_11, f_12, f_22): the Pade b of
- * the two-body term, b_1 of the one-body term (Eq. e:j1) and the three-body matrix F (Eq. e:j33).
+ * PRB 64, 024512 (2001)) on the Jastrow parameters p = (b, b_1, f_11, f_12, f_22, f_1, f_2): the
+ * Pade b of the two-body term, b_1 of the one-body term's cusp part (Eq. e:j1), the three-body
+ * matrix F (Eq. e:j33) and f of the one-body term's orbital part (Eq. e:j1).
  * O_k = d ln psi / d p_k: b: sum_{i<j} -a_ij rho^2 / (1 + b rho)^2; b_1: the derivative of the
- * one-body term (0 without it); f_qr: sum_a sum_{i<j} chi_q(r_ia) chi_r(r_ja) (+ the transposed
- * product for q != r), formed for any F.  A loop of SR steps alternates vmc_energy_forces,
+ * one-body cusp part (0 without it); f_qr: sum_a sum_{i<j} chi_q(r_ia) chi_r(r_ja) (+ the
+ * transposed product for q != r), formed for any F; f_q: sum_a sum_i chi_q(r_ia), for any f.  A loop of SR steps alternates vmc_energy_forces,
  * vmc_traj_param_stats, vmc_sr_update (host) and vmc_traj_set_jastrow. */
 /* on = 1: every later vmc_energy_forces call also accumulates, per walker and in FP64, the
- * samples' [E_L, O (5), E_L O (5), O O^T (25)] (one more kernel per measured sweep); 0: off
+ * samples' [E_L, O (7), E_L O (7), O O^T (49)] (one more kernel per measured sweep); 0: off
  * (the default); with real or complex orbitals. */
 int vmc_traj_set_param_stats(vmc_traj* traj, int on);
 /* Means over the W walkers and M measured sweeps of the last vmc_energy_forces call made with the
- * statistics on, in a fixed summation order: stats_dev (device, 36 doubles) = [E, <O> (5),
- * <E_L O> (5), <O O^T> (5 x 5 row-major)].  VMC_EINVAL if there is no such call since the
+ * statistics on, in a fixed summation order: stats_dev (device, 64 doubles) = [E, <O> (7),
+ * <E_L O> (7), <O O^T> (7 x 7 row-major)].  VMC_EINVAL if there is no such call since the
  * statistics were switched on or the parameters changed. */
 int vmc_traj_param_stats(vmc_traj* traj, double* stats_dev);
 /* Sets the trajectory's Jastrow parameters for later calls (host values): the Pade b (>= 0), the
- * one-body b_1 (> 0 if the trajectory was created with the one-body term, 0 if not) and the
- * three-body F (j3_f[3], finite; non-zero only if the trajectory was created with a non-zero F,
- * whose per-walker memory it needs).  The walkers are kept; VMC_EINVAL on any violation, and then
+ * one-body b_1 (> 0 if the trajectory was created with the one-body cusp part, 0 if not), the
+ * three-body F (j3_f[3]) and the one-body orbital part's f (j1_f[2]; NULL keeps the current f),
+ * finite; F and f non-zero only if the trajectory was created with a non-zero F or f, whose
+ * per-walker memory they need.  The walkers are kept; VMC_EINVAL on any violation, and then
  * nothing changes. */
-int vmc_traj_set_jastrow(vmc_traj* traj, double b, double j1_b1, const double* j3_f);
-/* Host helper: one SR step from the 36 means of vmc_traj_param_stats (host copy).  With
+int vmc_traj_set_jastrow(vmc_traj* traj, double b, double j1_b1, const double* j3_f, const double* j1_f);
+/* Host helper: one SR step from the 64 means of vmc_traj_param_stats (host copy).  With
  * f_k = -2 (<E_L O_k> - E <O_k>) (minus the energy gradient) and S_kl = <O_k O_l> - <O_k><O_l>
- * over the parameters whose bit k is set in `active` (bit 0: b, 1: b_1, 2..4: f_11, f_12, f_22),
- * S_kk scaled by (1 + eps): dp = tau S^-1 f on those parameters, 0 on the others (dp: host,
- * 5 doubles).  VMC_ENOTSPD if the regularised S is not positive definite (e.g. a parameter whose
- * O is zero on every sample); VMC_EINVAL on non-finite input, eps < 0 or bits above 4. */
+ * over the parameters whose bit k is set in `active` (bit 0: b, 1: b_1, 2..4: f_11, f_12, f_22,
+ * 5..6: f_1, f_2), S_kk scaled by (1 + eps): dp = tau S^-1 f on those parameters, 0 on the others
+ * (dp: host, 7 doubles).  VMC_ENOTSPD if the regularised S is not positive definite (e.g. a
+ * parameter whose O is zero on every sample); VMC_EINVAL on non-finite input, eps < 0 or bits
+ * above 6. */
 int vmc_sr_update(const double* stats, int active, double eps, double tau, double* dp);
 
 /* Checkpoint / resume of the state a trajectory owns between calls: its system and walker
@@ -276,7 +279,7 @@ int vmc_sr_update(const double* stats, int active, double eps, double tau, doubl
  * vmc_traj_load: reads a checkpoint of len bytes from host memory into a trajectory created with
  * the same system (N, box, precision, Ewald settings, cusp parameters, twist or general twist and
  * its angles, basis and eta, the one-body and three-body terms on or off) and walker count; the
- * Jastrow parameters b, j1_b1 and j3_f are taken from the checkpoint (as vmc_traj_set_jastrow sets
+ * Jastrow parameters b, j1_b1, j3_f and j1_f are taken from the checkpoint (as vmc_traj_set_jastrow sets
  * them, so an optimised wavefunction resumes).  Anything else, or a damaged buffer (checksum,
  * size, version), returns VMC_EINVAL and leaves the trajectory unchanged. */
 int vmc_traj_save(vmc_traj* traj, void* buf, size_t* len);

@@ -177,8 +177,8 @@ class System:
 
     def vmc_run(self, x, n_equil, n_meas, delta, seed, traj=0, step=0, threads=0, walker0=0, params=False):
         """Runs the Metropolis chains in place on x (W, Ne, 3); returns (sums, n_acc), and with
-        params=True also the per-walker parameter sums (W, 36): [sum E_L, sum O (5), sum E_L O (5),
-        sum O O^T (25)] over the measured samples.  x holds walkers walker0 .. walker0+W-1 of a
+        params=True also the per-walker parameter sums (W, NOPT): [sum E_L, sum O (NPAR),
+        sum E_L O (NPAR), sum O O^T (NPAR^2)] over the measured samples.  x holds walkers walker0 .. walker0+W-1 of a
         larger set (their random streams)."""
         assert x.dtype == np.float64 and x.flags.c_contiguous
         W = x.shape[0]
@@ -194,9 +194,9 @@ class System:
         return (sums, nacc, popt) if params else (sums, nacc)
 
     def param_derivs(self, x):
-        """O_k = d ln psi / d p_k for p = (b, b_1, f_11, f_12, f_22) at the configuration x."""
+        """O_k = d ln psi / d p_k for p = (b, b_1, f_11, f_12, f_22, f_1, f_2) at the configuration x."""
         x = np.ascontiguousarray(x, dtype=np.float64)
-        O = np.zeros(5)
+        O = np.zeros(NPAR)
         lib().o_param_derivs(C.byref(self.s), _dp(x), _dp(O))
         return O
 
@@ -362,13 +362,15 @@ def reduce(sums, M):
     return dict(E=E[0], sigma_E=sig[0], f=f, f_w=fw, means=means)
 
 
-# per-walker parameter sums of o_vmc_run_opt: [sum E_L, sum O (5), sum E_L O (5), sum O O^T (25)]
-NOPT = 36
-PARAM_NAMES = ("b", "b1", "f11", "f12", "f22")
+# the Jastrow parameters (two-body b, one-body cusp b_1, three-body F, one-body orbital part f) and
+# the per-walker parameter sums of o_vmc_run_opt: [sum E_L, sum O (7), sum E_L O (7), sum O O^T (49)]
+PARAM_NAMES = ("b", "b1", "f11", "f12", "f22", "f1", "f2")
+NPAR = len(PARAM_NAMES)
+NOPT = 1 + 2 * NPAR + NPAR * NPAR
 
 
 def param_stats(popt, M):
-    """Means over the W M samples of a run: [E, <O> (5), <E_L O> (5), <O O^T> (25)]."""
+    """Means over the W M samples of a run: [E, <O> (NPAR), <E_L O> (NPAR), <O O^T> (NPAR^2)]."""
     popt = np.asarray(popt, dtype=np.float64)
     return popt.sum(axis=0) / (popt.shape[0] * M)
 
@@ -380,11 +382,12 @@ def sr_step(stats, active, eps, tau):
     by (1 + eps), and the change dp = tau S^-1 f over the parameters whose bit is set in active
     (the others stay).  Returns (dp, f, S)."""
     stats = np.asarray(stats, dtype=np.float64)
-    E, O, EO, OO = stats[0], stats[1:6], stats[6:11], stats[11:36].reshape(5, 5)
+    n = NPAR
+    E, O, EO, OO = stats[0], stats[1:1 + n], stats[1 + n:1 + 2 * n], stats[1 + 2 * n:NOPT].reshape(n, n)
     f = -2.0 * (EO - E * O)
     S = OO - np.outer(O, O)
-    idx = [k for k in range(5) if (active >> k) & 1]
-    dp = np.zeros(5)
+    idx = [k for k in range(n) if (active >> k) & 1]
+    dp = np.zeros(n)
     if idx:
         Sa = S[np.ix_(idx, idx)].copy()
         Sa[np.diag_indices_from(Sa)] *= 1.0 + eps

@@ -509,7 +509,7 @@ void o_jastrow(const osys* s, const double* x, double* U, double* gradU, double*
 }
 
 /* ------------------------------------------------- variational parameters -- */
-/* O_k = d ln psi / d p_k for the Jastrow parameters p = (b, b_1, f_11, f_12, f_22): the
+/* O_k = d ln psi / d p_k for the Jastrow parameters p = (b, b_1, f_11, f_12, f_22, f_1, f_2): the
  * logarithmic derivatives that stochastic reconfiguration (Sorella, PRB 64, 024512 (2001); the
  * paper re-optimises the wavefunction before each ionic step) uses.  Each is the derivative of
  * the term's own definition, summed pair by pair:
@@ -518,11 +518,12 @@ void o_jastrow(const osys* s, const double* x, double* U, double* gradU, double*
  *        d u_1 / d b_1 = [b_1 y e^{-b_1 y} - (1 - e^{-b_1 y})] / (2 b_1^2), summed over (i, a)
  *   f_qr three-body (Eq. e:j33) with f_12 = f_21:  sum_a sum_{i<j} chi_q(r_ia) chi_r(r_ja)
  *        (+ chi_r(r_ia) chi_q(r_ja) for q != r).
+ *   f_q  one-body orbital part (Eq. e:j1):  sum_a sum_i chi_q(r_ia).
  * O_b1 is 0 without the one-body term (b_1 = 0 means no term); the three-body derivatives do not
  * depend on F and are formed for any F, zero included. */
-void o_param_derivs(const osys* s, const double* x, double O[5]) {
+void o_param_derivs(const osys* s, const double* x, double O[O_NPAR]) {
   const int ne = s->n_up + s->n_dn;
-  for (int k = 0; k < 5; ++k) O[k] = 0.0;
+  for (int k = 0; k < O_NPAR; ++k) O[k] = 0.0;
   if (s->jastrow_on)
     for (int i = 0; i < ne; ++i)
       for (int j = i + 1; j < ne; ++j) {
@@ -548,6 +549,8 @@ void o_param_derivs(const osys* s, const double* x, double O[5]) {
       o_j3_orbitals(s, a, x + 3 * i, ci);
       v1[i] = ci[0];
       v2[i] = ci[14];
+      O[5] += ci[0];
+      O[6] += ci[14];
     }
     for (int i = 0; i < ne; ++i)
       for (int j = i + 1; j < ne; ++j) {
@@ -1147,13 +1150,13 @@ int o_vmc_run_opt(const osys* s, int W, uint32_t w0, double* x, int n_equil, int
           sw[2 + 2 * n3 + t] += el * dg[t];
         }
         if (pw) {
-          double O[5];
+          double O[O_NPAR];
           o_param_derivs(s, xw, O);
           pw[0] += el;
-          for (int k = 0; k < 5; ++k) {
+          for (int k = 0; k < O_NPAR; ++k) {
             pw[1 + k] += O[k];
-            pw[6 + k] += el * O[k];
-            for (int l = 0; l < 5; ++l) pw[11 + 5 * k + l] += O[k] * O[l];
+            pw[1 + O_NPAR + k] += el * O[k];
+            for (int l = 0; l < O_NPAR; ++l) pw[1 + 2 * O_NPAR + O_NPAR * k + l] += O[k] * O[l];
           }
         }
       }

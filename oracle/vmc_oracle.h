@@ -83,12 +83,14 @@ int o_huckel_contracted(int n_p, double L, const double* R, double eta, int n_or
 void o_overlap_contracted(int n_p, double L, const double* R, double eta, double* S);
 int o_huckel_twist(int n_p, double L, const double* R, const double* zeta, int n_orb, int twist,
                    double* C, double* evals);
-/* d ln psi / d p for the Jastrow parameters p = (b, b_1, f_11, f_12, f_22); the b_1 entry is 0
- * without the one-body term, the three-body entries are formed for any F. */
-void o_param_derivs(const osys* s, const double* x, double O[5]);
-/* Per walker, the parameter statistics of the measured samples: [sum E_L, sum O (5),
- * sum E_L O (5), sum O O^T (5 x 5, row-major)]. */
-#define O_NOPT 36
+/* d ln psi / d p for the Jastrow parameters p = (b, b_1, f_11, f_12, f_22, f_1, f_2) (O_NPAR of
+ * them); the b_1 entry is 0 without the one-body cusp part, the three-body entries and those of
+ * the one-body orbital part are formed for any F and f. */
+#define O_NPAR 7
+void o_param_derivs(const osys* s, const double* x, double O[O_NPAR]);
+/* Per walker, the parameter statistics of the measured samples: [sum E_L, sum O (O_NPAR),
+ * sum E_L O (O_NPAR), sum O O^T (O_NPAR x O_NPAR, row-major)]. */
+#define O_NOPT (1 + 2 * O_NPAR + O_NPAR * O_NPAR)
 /* o_vmc_run_from that also writes W x O_NOPT parameter sums to popt (NULL: none). */
 int o_vmc_run_opt(const osys* s, int W, uint32_t w0, double* x, int n_equil, int n_meas, double delta,
                   uint32_t seed, uint32_t traj, uint32_t step, double* sums, int64_t* n_acc, double* popt,

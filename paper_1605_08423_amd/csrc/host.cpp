@@ -534,24 +534,25 @@ extern "C" int vmc_server_admit_count(size_t budget, size_t resident, int n_queu
 // [E, <O> (5), <E_L O> (5), <O O^T> (25)]: f_k = -2 (<E_L O_k> - E <O_k>), S_kl = <O_k O_l> -
 // <O_k><O_l> over the active parameters, S_kk scaled by (1 + eps), dp = tau S^-1 f by Cholesky.
 extern "C" int vmc_sr_update(const double* stats, int active, double eps, double tau, double* dp) {
-  if (!stats || !dp || (active & ~31) || !(eps >= 0.0) || !std::isfinite(eps) || !std::isfinite(tau))
+  constexpr int P = 7;   // (b, b_1, f_11, f_12, f_22, f_1, f_2)
+  if (!stats || !dp || (active & ~((1 << P) - 1)) || !(eps >= 0.0) || !std::isfinite(eps) || !std::isfinite(tau))
     return VMC_EINVAL;
-  for (int q = 0; q < 36; ++q)
+  for (int q = 0; q < 1 + 2 * P + P * P; ++q)
     if (!std::isfinite(stats[q])) return VMC_EINVAL;
   const double E = stats[0];
   const double* O = stats + 1;
-  const double* EO = stats + 6;
-  const double* OO = stats + 11;
-  int idx[5], n = 0;
-  for (int k = 0; k < 5; ++k)
+  const double* EO = stats + 1 + P;
+  const double* OO = stats + 1 + 2 * P;
+  int idx[P], n = 0;
+  for (int k = 0; k < P; ++k)
     if ((active >> k) & 1) idx[n++] = k;
-  double L[5][5] = {}, f[5], y[5];
+  double L[P][P] = {}, f[P], y[P];
   for (int a = 0; a < n; ++a) {
     const int k = idx[a];
     f[a] = -2.0 * (EO[k] - E * O[k]);
     for (int b = 0; b <= a; ++b) {
       const int l = idx[b];
-      double s = OO[5 * k + l] - O[k] * O[l];
+      double s = OO[P * k + l] - O[k] * O[l];
       if (a == b) s *= 1.0 + eps;
       for (int c = 0; c < b; ++c) s -= L[a][c] * L[b][c];
       if (a == b) {
@@ -567,7 +568,7 @@ extern "C" int vmc_sr_update(const double* stats, int active, double eps, double
     for (int c = 0; c < a; ++c) s -= L[a][c] * y[c];
     y[a] = s / L[a][a];
   }
-  for (int k = 0; k < 5; ++k) dp[k] = 0.0;
+  for (int k = 0; k < P; ++k) dp[k] = 0.0;
   for (int a = n - 1; a >= 0; --a) {
     double s = y[a];
     for (int c = a + 1; c < n; ++c) s -= L[c][a] * dp[idx[c]];

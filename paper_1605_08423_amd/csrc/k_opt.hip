@@ -2,14 +2,15 @@
 // ionic step and cites its optimiser, stochastic reconfiguration (SR; Sorella, PRB 64, 024512
 // (2001)).  SR needs, over the sampled configurations, the local energy and the logarithmic
 // derivatives O_k = d ln psi / d p_k of the variational parameters; here the Jastrow parameters
-// p = (b, b_1, f_11, f_12, f_22):
+// p = (b, b_1, f_11, f_12, f_22, f_1, f_2):
 //   b    two-body u = a rho / (1 + b rho):  O = sum_{i<j} -a_ij rho_ij^2 / (1 + b rho_ij)^2
 //   b_1  one-body f(rho) = -(1 - e^{-beta rho}) / beta, beta = b_1 2^{1/4} (Eq. e:j1 with Z = 1):
 //        O = sum_{i,a} 2^{1/4} [(1 - e^{-beta rho}) / beta^2 - rho e^{-beta rho} / beta]
 //   F    three-body (Eq. e:j33): with G_q = sum_i chi_q(r_ia) and T_qr = sum_i chi_q chi_r per
 //        proton, O_11 = 1/2 sum_a (G_1^2 - T_11), O_12 = sum_a (G_1 G_2 - T_12),
 //        O_22 = 1/2 sum_a (G_2^2 - T_22)  (the pair sums sum_{i<j}, for any F).
-// k_opt_sample adds [E_L, O (5), E_L O (5), O O^T (25)] of every measured sample to its walker's
+//   f    one-body orbital part (Eq. e:j1): O_1 = sum_a G_1, O_2 = sum_a G_2 (for any f).
+// k_opt_sample adds [E_L, O (7), E_L O (7), O O^T (49)] of every measured sample to its walker's
 // sums; k_opt_reduce forms the means over walkers and samples in a fixed order.
 #include "common.hpp"
 #include "kernels.hpp"
@@ -33,8 +34,9 @@ __global__ __launch_bounds__(256) void k_opt_sample(MeasureArgs m) {
   Real* te = reinterpret_cast<Real*>(smraw);   // N x 6: electrons' sin x3, cos x3 of pi x / L
   Real* ta = te + 6 * m.N;                     // N x 6: protons
   const int N = m.N, NS = m.NS, w = blockIdx.x, t = threadIdx.x, T = blockDim.x;
-  __shared__ double red[4][5];
-  __shared__ double Ob[5];
+  constexpr int P = kOptPar;
+  __shared__ double red[4][P];
+  __shared__ double Ob[P];
   const double* pos = m.pos + (size_t)w * 3 * N;
   for (int u = t; u < 3 * N; u += T) {
     const int i = u / 3, c = u % 3;
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(256) void k_opt_sample(MeasureArgs m) {
   }
   __syncthreads();
   const Real LoP = (Real)(m.L / VMC_PI), bb = (Real)m.b, ap = (Real)m.a_par, aa = (Real)m.a_anti;
-  Real o[5] = {Real(0), Real(0), Real(0), Real(0), Real(0)};
+  Real o[P] = {Real(0), Real(0), Real(0), Real(0), Real(0), Real(0), Real(0)};
   const int half = N / 2;
   for (int i = t; i < N; i += T) {
     const Real* si = te + 6 * i;
@@ -103,15 +105,17 @@ __global__ __launch_bounds__(256) void k_opt_sample(MeasureArgs m) {
     o[2] += (Real)(0.5 * (G1 * G1 - (double)t11));
     o[3] += (Real)(G1 * G2 - (double)t12);
     o[4] += (Real)(0.5 * (G2 * G2 - (double)t22));
+    o[5] += g1;
+    o[6] += g2;
   }
   // fixed-order block sums in FP64
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < P; ++k) {
     const double v = wave_allsum((double)o[k]);
     if ((t & 63) == 0) red[t >> 6][k] = v;
   }
   __syncthreads();
-  if (t < 5) {
+  if (t < P) {
     double s = red[0][t];
     for (int q = 1; q < T / 64; ++q) s += red[q][t];
     Ob[t] = s;
@@ -120,11 +124,11 @@ __global__ __launch_bounds__(256) void k_opt_sample(MeasureArgs m) {
   const double EL = m.ELs[w];
   double* out = m.popt + (size_t)w * kOptStats;
   if (t == 0) out[0] += EL;
-  if (t < 5) {
+  if (t < P) {
     out[1 + t] += Ob[t];
-    out[6 + t] += EL * Ob[t];
+    out[1 + P + t] += EL * Ob[t];
   }
-  if (t < 25) out[11 + t] += Ob[t / 5] * Ob[t % 5];
+  if (t < P * P) out[1 + 2 * P + t] += Ob[t / P] * Ob[t % P];
 }
 
 // Means over W walkers and M samples each: column q of the per-walker sums, one block per column,

@@ -167,9 +167,11 @@ hipError_t launch_twist_average(int n_tw, int n3, const double* f_stack, const d
 // its d/dR terms after, from the full grad U, grad ln|D| and E_L the Slater pass leaves).
 constexpr size_t j3_measure_doubles(int N) { return (size_t)10 * N + 2; }
 hipError_t launch_j3_init(const WalkerArgs& a, hipStream_t st);
-// Wavefunction optimisation: per walker [sum E_L, sum O (5), sum E_L O (5), sum O O^T (25)] of the
-// logarithmic derivatives O of the Jastrow parameters (b, b_1, f_11, f_12, f_22), and their means.
-constexpr int kOptStats = 36;
+// Wavefunction optimisation: per walker [sum E_L, sum O (P), sum E_L O (P), sum O O^T (P x P)] of the
+// logarithmic derivatives O of the P = 7 Jastrow parameters (b, b_1, f_11, f_12, f_22, f_1, f_2),
+// and their means.
+constexpr int kOptPar = 7;
+constexpr int kOptStats = 1 + 2 * kOptPar + kOptPar * kOptPar;
 hipError_t launch_opt_sample(const MeasureArgs& m, int mixed, hipStream_t st);
 hipError_t launch_opt_reduce(int W, int M, const double* popt, double* out, hipStream_t st);
 hipError_t launch_j3_grad(const MeasureArgs& m, int mixed, hipStream_t st);

@@ -615,7 +615,7 @@ static int traj_load(vmc_traj* t, const void* buf, size_t len, bool rescale) {
   vmc_host::CkptHeader h;
   if (vmc_host::ckpt_validate(buf, len, &h) != VMC_OK) return VMC_EINVAL;
   const vmc_system& s = t->sys;
-  // the system must match; the variational Jastrow parameters (b, b_1, F) come from the
+  // the system must match; the variational Jastrow parameters (b, b_1, F, f) come from the
   // checkpoint, as vmc_traj_set_jastrow would set them (an optimised wavefunction resumes)
   if (h.n != t->N || h.w != t->W || h.precision != s.precision || h.nmax != s.ewald_nmax || h.twist != s.twist ||
       h.general_twist != s.general_twist || h.contracted != s.contracted || h.a_par != s.a_par ||
@@ -827,12 +827,14 @@ int vmc_traj_param_stats(vmc_traj* t, double* stats_dev) {
   return VMC_OK;
 }
 
-int vmc_traj_set_jastrow(vmc_traj* t, double b, double j1_b1, const double* j3_f) {
+int vmc_traj_set_jastrow(vmc_traj* t, double b, double j1_b1, const double* j3_f, const double* j1_f) {
   if (!t || !j3_f) return VMC_EINVAL;
   vmc_system s = t->sys;
   s.b = b;
   s.j1_b1 = j1_b1;
   for (int q = 0; q < 3; ++q) s.j3_f[q] = j3_f[q];
+  if (j1_f)
+    for (int q = 0; q < 2; ++q) s.j1_f[q] = j1_f[q];
   if (check_sys(&s)) return VMC_EINVAL;
   // the one-body term stays on or off; the three-body term may change freely only where its
   // per-walker memory exists (it was on at creation)

@@ -17,6 +17,10 @@ VMC_ECANCELLED, VMC_ENOCONV = -7, -8
 VMC_STEP_TRAJ = 0xFFFFFFFF
 VMC_FP64, VMC_MIXED = 0, 1
 VMC_STEP_CFOLD, VMC_STEP_NOISE_CORR, VMC_STEP_NO_SCORR = 1, 2, 4
+# the Jastrow parameters that stochastic reconfiguration covers, (b, b_1, f_11, f_12, f_22, f_1, f_2),
+# and the length of the statistics vector [E, <O>, <E_L O>, <O O^T>]
+OPT_PAR = 7
+OPT_STATS = 1 + 2 * OPT_PAR + OPT_PAR * OPT_PAR
 
 EXPORTED = ["vmc_create", "vmc_destroy", "vmc_set_stream", "vmc_strerror", "vmc_supported_n",
             "vmc_set_profiling", "vmc_kernel_times", "vmc_reset_kernel_times", "vmc_traj_create",
@@ -102,7 +106,7 @@ def _declare(l):
     l.vmc_huckel_params_contracted.argtypes = [i, d, d, P(d), P(d)]
     l.vmc_traj_set_param_stats.argtypes = [vp, i]
     l.vmc_traj_param_stats.argtypes = [vp, vp]
-    l.vmc_traj_set_jastrow.argtypes = [vp, d, d, P(d)]
+    l.vmc_traj_set_jastrow.argtypes = [vp, d, d, P(d), P(d)]
     l.vmc_sr_update.argtypes = [P(d), i, d, d, P(d)]
     l.vmc_huckel_params_theta_contracted.argtypes = [i, d, P(d), d, P(d), P(d)]
     l.vmc_twist_average.argtypes = [vp, i, i, vp, vp, vp, vp]
@@ -259,15 +263,18 @@ class Trajectory:
         _check(_lib().vmc_traj_set_param_stats(self.h, int(bool(on))), "vmc_traj_set_param_stats")
 
     def param_stats(self):
-        """[E, <O> (5), <E_L O> (5), <O O^T> (25)] of the last energy_forces call (device tensor)."""
+        """[E, <O> (7), <E_L O> (7), <O O^T> (49)] of the last energy_forces call (device tensor);
+        the parameters are (b, b_1, f_11, f_12, f_22, f_1, f_2)."""
         import torch
-        out = torch.empty(36, dtype=torch.float64, device="cuda")
+        out = torch.empty(OPT_STATS, dtype=torch.float64, device="cuda")
         _check(_lib().vmc_traj_param_stats(self.h, C.c_void_p(out.data_ptr())), "vmc_traj_param_stats")
         return out
 
-    def set_jastrow(self, b, b1, j3):
-        """New Jastrow parameters (Pade b, one-body b_1, three-body (f11, f12, f22)) for later calls."""
-        _check(_lib().vmc_traj_set_jastrow(self.h, float(b), float(b1), (C.c_double * 3)(*j3)),
+    def set_jastrow(self, b, b1, j3, j1f=None):
+        """New Jastrow parameters (Pade b, one-body b_1, three-body (f11, f12, f22), one-body orbital
+        part (f1, f2); None keeps the current f) for later calls."""
+        _check(_lib().vmc_traj_set_jastrow(self.h, float(b), float(b1), (C.c_double * 3)(*j3),
+                                           None if j1f is None else (C.c_double * 2)(*j1f)),
                "vmc_traj_set_jastrow")
 
     def build_S(self, S=None, keep_only=False):
@@ -437,11 +444,12 @@ def vmc_huckel_params(R, zeta, L, twist=0):
 
 
 def vmc_sr_update(stats, active, eps, tau):
-    """Host helper: one stochastic-reconfiguration step dp (numpy, 5) from the 36 means of
+    """Host helper: one stochastic-reconfiguration step dp (numpy, 7) from the 64 means of
     Trajectory.param_stats (a tensor or an array)."""
     import numpy as np
     st = np.ascontiguousarray(stats.cpu().numpy() if hasattr(stats, "cpu") else stats, dtype=np.float64)
-    dp = np.zeros(5)
+    assert st.shape == (OPT_STATS,)
+    dp = np.zeros(OPT_PAR)
     P = C.POINTER(C.c_double)
     _check(_lib().vmc_sr_update(st.ctypes.data_as(P), int(active), float(eps), float(tau), dp.ctypes.data_as(P)),
            "vmc_sr_update")

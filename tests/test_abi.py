@@ -95,23 +95,25 @@ def test_host_sr_update_matches_the_oracle(oracle):
     and EINVAL on bad arguments."""
     from paper_1605_08423_amd import vmc
     rng = np.random.default_rng(11)
-    O = rng.normal(size=(500, 5)) @ rng.normal(size=(5, 5)) + rng.normal(size=5)
-    E = -7.0 + O @ rng.normal(size=5) + 0.5 * rng.normal(size=500)
+    n = vmc.OPT_PAR
+    O = rng.normal(size=(500, n)) @ rng.normal(size=(n, n)) + rng.normal(size=n)
+    E = -7.0 + O @ rng.normal(size=n) + 0.5 * rng.normal(size=500)
     st = np.concatenate([[E.mean()], O.mean(0), (E[:, None] * O).mean(0),
                          (O[:, :, None] * O[:, None, :]).mean(0).ravel()])
-    for mask in range(32):
+    assert st.shape == (vmc.OPT_STATS,)
+    for mask in range(1 << n):
         for eps, tau in ((0.0, 1.0), (0.05, 0.2)):
             dp = vmc.vmc_sr_update(st, mask, eps, tau)
             ref, _, _ = oracle.sr_step(st, mask, eps, tau)
             np.testing.assert_allclose(dp, ref, rtol=1e-10, atol=1e-14)
     flat = st.copy()
-    flat[11 + 6] = flat[2] ** 2           # O_b1 without fluctuation
+    flat[1 + 2 * n + n + 1] = flat[2] ** 2   # O_b1 without fluctuation: <O_b1^2> = <O_b1>^2
     with pytest.raises(vmc.VMCError) as ei:
         vmc.vmc_sr_update(flat, 0b00010, 0.1, 0.1)
     assert ei.value.code == vmc.VMC_ENOTSPD
     bad = st.copy()
     bad[3] = np.nan
-    for args in ((bad, 1, 0.1, 0.1), (st, 32, 0.1, 0.1), (st, 1, -0.1, 0.1), (st, 1, 0.1, np.inf)):
+    for args in ((bad, 1, 0.1, 0.1), (st, 1 << n, 0.1, 0.1), (st, 1, -0.1, 0.1), (st, 1, 0.1, np.inf)):
         with pytest.raises(vmc.VMCError) as ei:
             vmc.vmc_sr_update(*args)
         assert ei.value.code == vmc.VMC_EINVAL

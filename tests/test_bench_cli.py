@@ -102,11 +102,11 @@ def test_three_body_work_model_and_arguments():
 
 def test_optimisation_work_model():
     """The SR statistics kernel's count: the two-body pairs once each, the one-body pairs only with
-    the term, the three-body sums always, in the working precision; the moments in FP64."""
+    the term, the three-body sums always, in the working precision; the 64 moments of the seven parameters in FP64 (two flops each)."""
     sys.path.insert(0, ROOT)
     import bench
     N = 128
     a = bench.work_model("opt_sample", N, 0, 0, 1, True, one_body=True)
     b = bench.work_model("opt_sample", N, 0, 0, 1, False, one_body=False)
-    assert a == {"f64": 72, "f32": N * (N - 1) // 2 * 25 + N * N * 25 + N * N * 24}
-    assert b == {"f64": N * (N - 1) // 2 * 25 + N * N * 24 + 72}
+    assert a == {"f64": 128, "f32": N * (N - 1) // 2 * 25 + N * N * 25 + N * N * 24}
+    assert b == {"f64": N * (N - 1) // 2 * 25 + N * N * 24 + 128}

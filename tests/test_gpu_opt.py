@@ -3,6 +3,7 @@ statistics of stochastic reconfiguration (E_L and the logarithmic derivatives O 
 parameters b, b_1, F) on same-seed chains in FP64 (bar 1e-10) and mixed precision, the setter of
 the parameters against a trajectory created with them, the argument checks, and an SR loop that
 lowers the energy."""
+import ctypes
 import sys
 
 import numpy as np
@@ -39,35 +40,44 @@ def _wl(name):
     return workload(name) if name in ("h16", "h54", "h128") else small_system(int(name[1:]), 1.35, seed=21)
 
 
-def _run(oracle, dev, name, W, ne, ns, prec, b1, j3, seed=11, traj=3, step=2):
+def _run(oracle, dev, name, W, ne, ns, prec, b1, j3, seed=11, traj=3, step=2, j1f=None):
     torch, vmc, ctx = dev
     wl = _wl(name)
     Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
     pos = wl.electrons(W=W, seed_offset=7)
-    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=prec, b1=b1, j3=j3), W, seed=seed, traj_id=traj)
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=prec, b1=b1, j3=j3, j1f=j1f), W, seed=seed,
+                        traj_id=traj)
     tr.set_walkers(_T(torch, pos))
     tr.set_param_stats(True)
     tr.energy_forces(_T(torch, wl.R.reshape(-1)), _T(torch, Cm), _T(torch, wl.zeta), ne, ns, wl.delta, step)
     st = tr.param_stats().cpu().numpy()
     acc = tr.accepts().cpu().numpy()
     tr.close()
-    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1, j3=j3)
+    s = oracle.System(wl.R, wl.zeta, Cm, L=wl.L, b1=b1, j3=j3, j1f=j1f)
     xo = pos.copy()
     _, nacc, popt = s.vmc_run(xo, ne, ns, wl.delta, seed=seed, traj=traj, step=step, params=True)
     return st, oracle.param_stats(popt, ns), int(np.sum(acc != nacc))
 
 
-@pytest.mark.parametrize("name,W,ne,ns,b1,j3", [("h16", 16, 2, 4, 0.0, None), ("h16", 16, 2, 4, 2.5, F3),
-                                                ("h54", 4, 1, 3, 2.5, F3), ("h32", 8, 1, 2, 0.0, F3),
-                                                ("h128", 2, 0, 2, 2.5, F3)])
-def test_param_stats_chain_fp64(oracle, dev, name, W, ne, ns, b1, j3):
-    say(f"[opt stats fp64] {name} W={W} b1={b1} j3={j3 is not None}")
-    st, ref, flips = _run(oracle, dev, name, W, ne, ns, 0, b1, j3)
+NP = 7   # (b, b_1, f_11, f_12, f_22, f_1, f_2); statistics [E, <O> (7), <E_L O> (7), <O O^T> (49)]
+F1 = (0.35, -0.6)
+
+
+@pytest.mark.parametrize("name,W,ne,ns,b1,j3,j1f", [("h16", 16, 2, 4, 0.0, None, None), ("h16", 16, 2, 4, 2.5, F3, None),
+                                                    ("h54", 4, 1, 3, 2.5, F3, F1), ("h32", 8, 1, 2, 0.0, F3, None),
+                                                    ("h128", 2, 0, 2, 2.5, F3, F1), ("h16", 16, 2, 4, 0.0, None, F1)])
+def test_param_stats_chain_fp64(oracle, dev, name, W, ne, ns, b1, j3, j1f):
+    say(f"[opt stats fp64] {name} W={W} b1={b1} j3={j3 is not None} j1f={j1f}")
+    st, ref, flips = _run(oracle, dev, name, W, ne, ns, 0, b1, j3, j1f=j1f)
     say("  flipped walkers", flips, " worst element-wise error", f"{elem(st, ref):.3e}")
     assert flips == 0
+    assert st.shape == (1 + 2 * NP + NP * NP,)
     assert elem(st, ref) < 1e-10
     if b1 == 0.0:
-        assert np.all(st[[2, 7]] == 0.0) and np.all(st[11 + 5:11 + 10] == 0.0)
+        # no cusp part: b_1 is not a parameter, its O and every moment with it vanish
+        assert st[2] == 0.0 and st[2 + NP] == 0.0
+        OO = st[1 + 2 * NP:].reshape(NP, NP)
+        assert np.all(OO[1] == 0.0) and np.all(OO[:, 1] == 0.0)
 
 
 @pytest.mark.parametrize("name,W,ne,ns", [("h16", 64, 4, 8), ("h54", 64, 2, 3)])
@@ -77,8 +87,8 @@ def test_param_stats_chain_mixed(oracle, dev, name, W, ne, ns):
     bar of the proton derivatives (2e-5), the E_L moments within 1e-5."""
     say(f"[opt stats mixed] {name} W={W}")
     st, ref, flips = _run(oracle, dev, name, W, ne, ns, 1, 2.5, F3, seed=5, traj=1, step=0)
-    o_only = [1, 2, 3, 4, 5] + list(range(11, 36))
-    e_part = [0] + list(range(6, 11))
+    o_only = list(range(1, 1 + NP)) + list(range(1 + 2 * NP, 1 + 2 * NP + NP * NP))
+    e_part = [0] + list(range(1 + NP, 1 + 2 * NP))
     say("  flipped walkers", flips, f" O moments {elem(st[o_only], ref[o_only]):.3e}",
         f" E_L moments {elem(st[e_part], ref[e_part]):.3e}")
     # a flipped decision sends a walker along another path; the moments are then compared only
@@ -91,8 +101,9 @@ def test_param_stats_chain_mixed(oracle, dev, name, W, ne, ns):
 
 def test_sr_update_on_gpu_statistics_matches_the_oracle(oracle, dev):
     torch, vmc, ctx = dev
-    st, _, _ = _run(oracle, dev, "h16", 32, 2, 6, 0, 2.5, F3)
-    for mask, eps, tau in ((0b11111, 1e-3, 0.1), (0b11100, 0.1, 0.2), (0b00001, 0.0, 1.0)):
+    st, _, _ = _run(oracle, dev, "h16", 32, 2, 6, 0, 2.5, F3, j1f=F1)
+    for mask, eps, tau in ((0b1111111, 1e-3, 0.1), (0b0011100, 0.1, 0.2), (0b0000001, 0.0, 1.0),
+                           (0b1100000, 0.1, 0.3)):
         dp = vmc.vmc_sr_update(st, mask, eps, tau)
         ref, _, _ = oracle.sr_step(st, mask, eps, tau)
         np.testing.assert_allclose(dp, ref, rtol=1e-11, atol=1e-14)
@@ -105,15 +116,16 @@ def test_set_jastrow_equals_a_trajectory_created_with_the_parameters(oracle, dev
     Cm, _ = oracle.huckel(wl.R, wl.zeta, wl.L, wl.n // 2)
     pos = _T(torch, wl.electrons(W=32))
     args = (_T(torch, wl.R.reshape(-1)), _T(torch, Cm), _T(torch, wl.zeta), 2, 3, wl.delta, 1)
-    new = (0.8, 2.0, (-0.2, 0.05, 0.1))
+    new = (0.8, 2.0, (-0.2, 0.05, 0.1), (0.2, -0.3))
     outs = []
     for how in ("setter", "created"):
         if how == "setter":
-            tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, b=1.0, b1=2.5, j3=F3), 32, seed=4, traj_id=0)
+            tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, b=1.0, b1=2.5, j3=F3, j1f=F1), 32, seed=4,
+                                traj_id=0)
             tr.set_jastrow(*new)
         else:
-            tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, b=new[0], b1=new[1], j3=new[2]), 32, seed=4,
-                                traj_id=0)
+            tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, b=new[0], b1=new[1], j3=new[2], j1f=new[3]), 32,
+                                seed=4, traj_id=0)
         tr.set_walkers(pos)
         tr.set_param_stats(True)
         outs.append((tr.energy_forces(*args).cpu().numpy(), tr.param_stats().cpu().numpy()))
@@ -132,18 +144,25 @@ def test_argument_checks(dev):
                      lambda: plain.set_jastrow(1.0, 2.5, (0, 0, 0)),    # one-body term switched on
                      lambda: plain.set_jastrow(1.0, 0.0, F3),           # no three-body memory
                      lambda: full.set_jastrow(1.0, 0.0, F3),            # one-body term switched off
-                     lambda: full.set_jastrow(1.0, 2.5, (np.nan, 0, 0))):
+                     lambda: full.set_jastrow(1.0, 2.5, (np.nan, 0, 0)),
+                     lambda: plain.set_jastrow(1.0, 0.0, (0, 0, 0), F1),  # no orbital-term memory
+                     lambda: full.set_jastrow(1.0, 2.5, F3, (np.inf, 0.0))):
             with pytest.raises(vmc.VMCError) as ei:
                 call()
             assert ei.value.code == vmc.VMC_EINVAL
         assert vmc._lib().vmc_traj_set_param_stats(full.h, 2) == vmc.VMC_EINVAL
         full.set_jastrow(1.0, 2.5, (0.0, 0.0, 0.0))      # the term off, its memory kept
         full.set_jastrow(1.0, 2.5, F3)
-        st = np.zeros(36)
+        full.set_jastrow(1.0, 2.5, F3, F1)                # the orbital part shares the three-body memory
+        st = np.zeros(1 + 2 * NP + NP * NP)
         st[0] = -1.0
         with pytest.raises(vmc.VMCError) as ei:           # no fluctuation: S = 0
             vmc.vmc_sr_update(st, 0b00001, 0.1, 0.1)
         assert ei.value.code == vmc.VMC_ENOTSPD
+        dp = np.zeros(NP)
+        P = ctypes.POINTER(ctypes.c_double)
+        assert vmc._lib().vmc_sr_update(st.ctypes.data_as(P), 1 << NP, 0.1, 0.1,
+                                        dp.ctypes.data_as(P)) == vmc.VMC_EINVAL   # no parameter 7
     finally:
         for t in (plain, full):
             t.close()
@@ -157,8 +176,8 @@ def test_sr_loop_lowers_the_energy(dev):
     Cm = vmc.vmc_huckel_params(wl.R, wl.zeta, wl.L)
     R, Cd, z = _T(torch, wl.R.reshape(-1)), _T(torch, Cm), _T(torch, wl.zeta)
     W = 2048
-    p = np.array([1.0, 2.5, 0.3, 0.0, 0.0])
-    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=vmc.VMC_MIXED, b1=2.5, j3=tuple(p[2:])), W,
+    p = np.array([1.0, 2.5, 0.3, 0.0, 0.0, 0.0, 0.0])
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=vmc.VMC_MIXED, b1=2.5, j3=tuple(p[2:5])), W,
                         seed=3, traj_id=0)
     tr.set_walkers(_T(torch, wl.electrons(W=W)))
     e0 = tr.energy_forces(R, Cd, z, 20, 20, wl.delta, 0).cpu().numpy()
@@ -167,11 +186,42 @@ def test_sr_loop_lowers_the_energy(dev):
         tr.energy_forces(R, Cd, z, 5, 10, wl.delta, 1 + it)
         dp = vmc.vmc_sr_update(tr.param_stats(), 0b11100, 0.1, 0.2)
         p = p + dp
-        tr.set_jastrow(p[0], p[1], tuple(p[2:]))
-        say(f"  SR step {it}: F = {np.round(p[2:], 4)}")
+        tr.set_jastrow(p[0], p[1], tuple(p[2:5]))
+        say(f"  SR step {it}: F = {np.round(p[2:5], 4)}")
     tr.set_param_stats(False)
     e1 = tr.energy_forces(R, Cd, z, 5, 20, wl.delta, 100).cpu().numpy()
     tr.close()
     say(f"  E {e0[0]:.4f} +- {e0[1]:.4f} -> {e1[0]:.4f} +- {e1[1]:.4f}")
     assert p[2] < 0.1
+    assert e1[0] < e0[0] - 5 * np.hypot(e0[1], e1[1])
+
+
+def test_sr_on_the_orbital_part_lowers_the_energy(dev):
+    """h54 in mixed precision with the cusp and three-body terms fixed: SR on the one-body orbital
+    part (f_1, f_2) alone, from f = (+0.6, 0) (electrons piled onto the protons), for 6 steps of
+    2048 walkers x 10 sweeps; the other parameters do not move and the energy falls by many
+    standard errors."""
+    torch, vmc, ctx = dev
+    wl = workload("h54")
+    Cm = vmc.vmc_huckel_params(wl.R, wl.zeta, wl.L)
+    R, Cd, z = _T(torch, wl.R.reshape(-1)), _T(torch, Cm), _T(torch, wl.zeta)
+    W = 2048
+    p = np.array([1.0, 2.5, *F3, 0.6, 0.0])
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, precision=vmc.VMC_MIXED, b1=2.5, j3=F3, j1f=tuple(p[5:])),
+                        W, seed=3, traj_id=0)
+    tr.set_walkers(_T(torch, wl.electrons(W=W)))
+    e0 = tr.energy_forces(R, Cd, z, 20, 20, wl.delta, 0).cpu().numpy()
+    tr.set_param_stats(True)
+    for it in range(6):
+        tr.energy_forces(R, Cd, z, 5, 10, wl.delta, 1 + it)
+        dp = vmc.vmc_sr_update(tr.param_stats(), 0b1100000, 0.1, 0.2)
+        assert np.all(dp[:5] == 0.0)
+        p = p + dp
+        tr.set_jastrow(p[0], p[1], tuple(p[2:5]), tuple(p[5:]))
+        say(f"  SR step {it}: f = {np.round(p[5:], 4)}")
+    tr.set_param_stats(False)
+    e1 = tr.energy_forces(R, Cd, z, 5, 20, wl.delta, 100).cpu().numpy()
+    tr.close()
+    say(f"  E {e0[0]:.4f} +- {e0[1]:.4f} -> {e1[0]:.4f} +- {e1[1]:.4f}")
+    assert p[5] < 0.6
     assert e1[0] < e0[0] - 5 * np.hypot(e0[1], e1[1])
