@@ -113,6 +113,9 @@ def work_model(cls: str, N: int, nk: int, nslot: int, nimg: int, mixed: bool, on
 CREFRESH = 4
 # F of the three-body leg: the lowest VMC energy of a scan at 54 protons with b_1 = 2.5
 J3_LEG_F = (-0.2, 0.0, 0.05)
+# f of the one-body term's orbital part in the paper-wavefunction leg: ten SR iterations on f at 54
+# protons with b_1 = 2.5 and the F above (the energy is flat within 0.03 Ha between f = 0 and here)
+J1F_LEG = (0.011, 0.053)
 
 
 def _f3(text: str):
@@ -524,7 +527,7 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, w
     ctx = vmc.Context(0)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     paper = wavefunction == "paper"
-    wkw = dict(eta=0.1, b1=2.5, j3=J3_LEG_F) if paper else {}
+    wkw = dict(eta=0.1, b1=2.5, j3=J3_LEG_F, j1f=J1F_LEG) if paper else {}
     ns = max(1, min(streams, n_tw))
     strs = [torch.cuda.Stream() for _ in range(ns)] if ns > 1 else [torch.cuda.current_stream()]
     ctxs = []
@@ -625,7 +628,8 @@ def twist_mesh_leg(name: str, q: int, W: int, M: int, steps: int, warmup: int, w
     return {"value": round(W * n_tw * M * steps / elapsed, 1), "unit": "walker-sweeps/s",
             "workload": f"{name}: {N} H, r_s={wl.rs}, {q}x{q}x{q} Monkhorst-Pack twists x {W} walkers x {M} measured "
                         f"(+5 re-equilibration) sweeps per Langevin step, complex orbitals, FP64"
-                        + (", contracted basis eta=0.1, one-body b_1=2.5, three-body F="
+                        + (", contracted basis eta=0.1, one-body b_1=2.5 and f="
+                           + ",".join(f"{x:g}" for x in J1F_LEG) + ", three-body F="
                            + ",".join(f"{x:g}" for x in J3_LEG_F) if paper else ""),
             "twists": n_tw, "walkers_per_twist": W, "sweeps": M, "steps": steps, "warmup": warmup,
             "ms_per_step": round(1e3 * elapsed / steps, 1), "langevin_steps_per_s": round(steps / elapsed, 4),

@@ -109,7 +109,9 @@ def test_full_size_one_twist_of_the_paper_mesh(oracle, dev):
     say(f"[full size] h128 paper-mesh twist {th}: W={W} sweeps={ne}+{ns}")
     Cc, _ = oracle.chuckel_contracted(wl.R, wl.L, wl.n // 2, ETA, th)
     x0 = wl.electrons(W=W, seed_offset=29)
-    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, theta=th, eta=ETA, b1=2.5), W, seed=wl.seed, traj_id=4)
+    # the leg's wavefunction terms: contracted basis, one-body cusp and orbital part, three-body F
+    jas = dict(b1=2.5, j3=(-0.2, 0.0, 0.05), j1f=(0.011, 0.053))
+    tr = vmc.Trajectory(ctx, vmc.make_system(wl.n, wl.L, theta=th, eta=ETA, **jas), W, seed=wl.seed, traj_id=4)
     tr.set_walkers(T(torch, x0))
     Cpairs = np.ascontiguousarray(np.asarray(Cc, dtype=np.complex128)).view(np.float64)
     out_h = tr.energy_forces(T(torch, wl.R.reshape(-1)), T(torch, Cpairs), T(torch, wl.zeta), ne, ns, wl.delta,
@@ -117,6 +119,6 @@ def test_full_size_one_twist_of_the_paper_mesh(oracle, dev):
     means, fw = tr.walker_means().cpu().numpy(), tr.walker_forces().cpu().numpy()
     acc, pos = tr.accepts().cpu().numpy(), tr.get_walkers().cpu().numpy()
     tr.close()
-    s = oracle.CSystem(wl.R, wl.zeta, Cc, th, wl.L, eta=ETA, b1=2.5)
+    s = oracle.CSystem(wl.R, wl.zeta, Cc, th, wl.L, eta=ETA, **jas)
     _check(oracle, s, wl, x0, out_h, means, fw, acc, pos, W, ne, ns, 0, (0, 255),
            lambda xo, w: s.vmc_run(xo, ne, ns, wl.delta, seed=wl.seed, traj=4, step=6, walker0=w))
