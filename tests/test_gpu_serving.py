@@ -188,6 +188,14 @@ def test_refusals_cancel_and_failure_isolation(dev):
     with pytest.raises(vmc.VMCError) as e:                      # W <= 3N: S would be singular
         srv.submit(make_req(vmc, spec("h16", 48, 0)))
     assert e.value.code == vmc.VMC_EINVAL
+    wl = s_ok["wl"]
+    for kw in (dict(j3=(-0.3, 0.1, 0.05)), dict(j1f=(0.35, -0.6))):   # Jastrow-orbital terms: single trajectories only
+        r = vmc.make_request(vmc.make_system(wl.n, wl.L, **kw), 64, wl.R, wl.zeta, wl.electrons(W=64), n_steps=1,
+                             n_sweeps=2, T=wl.T_hartree, Delta=1.0 / s_ok["alpha"], alpha=s_ok["alpha"],
+                             n_equil_first=1, n_equil=1, step_delta=wl.delta, flags=0, seed=1, traj_id=40)
+        with pytest.raises(vmc.VMCError) as e:
+            srv.submit(r)
+        assert e.value.code == vmc.VMC_EINVAL
     # noise correction with a temperature too low for it: the Langevin update fails (corrected T < 0)
     s_fail = spec("h16", 64, 0, traj=31, flags=vmc.VMC_STEP_NOISE_CORR, Tfac=1e-9)
     ids = [srv.submit(make_req(vmc, s)) for s in (s_ok, s_fail, spec("h16", 64, 0, traj=32), spec("h16", 64, 0, traj=33))]
