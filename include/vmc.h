@@ -149,7 +149,8 @@ int vmc_cancel(vmc_ctx* ctx);
 /* hip_stream: a hipStream_t (NULL = null stream).  Not owned. */
 int vmc_set_stream(vmc_ctx* ctx, void* hip_stream);
 const char* vmc_strerror(int code);
-/* Whether N is supported: N = 2 N_sigma with N_sigma in {8, 16, 27, 32, 64, 128}.
+/* Whether N is supported: N = 2 N_sigma with N_sigma in {8, 12, 16, 20, 24, 27, 32, 64, 128}
+ * (N = 16, 24, 32, 40, 48, 54, 64, 128, 256; each size is a compiled kernel variant).
  * Up to N_sigma = 64 a spin's inverse is held in one wavefront's registers during a
  * sweep; at 128 it stays in device memory. */
 int vmc_supported_n(int n_protons);

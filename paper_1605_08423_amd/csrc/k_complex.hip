@@ -1194,7 +1194,10 @@ __global__ __launch_bounds__(256, CB ? 1 : 2) void k_cslater_sample(MeasureArgs 
 size_t cslater_scratch_bytes(int NS) {
   switch (NS) {
     case 8: return 16 * CSlaterLay<8>::scr_elems;
+    case 12: return 16 * CSlaterLay<12>::scr_elems;
     case 16: return 16 * CSlaterLay<16>::scr_elems;
+    case 20: return 16 * CSlaterLay<20>::scr_elems;
+    case 24: return 16 * CSlaterLay<24>::scr_elems;
     case 27: return 16 * CSlaterLay<27>::scr_elems;
     case 32: return 16 * CSlaterLay<32>::scr_elems;
     case 64: return 16 * CSlaterLay<64>::scr_elems;
@@ -1232,7 +1235,10 @@ hipError_t launch_cslater_t(const MeasureArgs& m, const TwistArgs& tw, hipStream
 #define VMC_CDISPATCH(ns, CALL)                  \
   switch (ns) {                                  \
     case 8: { constexpr int NSV = 8; CALL; }     \
+    case 12: { constexpr int NSV = 12; CALL; }   \
     case 16: { constexpr int NSV = 16; CALL; }   \
+    case 20: { constexpr int NSV = 20; CALL; }   \
+    case 24: { constexpr int NSV = 24; CALL; }   \
     case 27: { constexpr int NSV = 27; CALL; }   \
     case 32: { constexpr int NSV = 32; CALL; }   \
     case 64: { constexpr int NSV = 64; CALL; }   \

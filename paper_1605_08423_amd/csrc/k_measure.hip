@@ -1020,7 +1020,10 @@ hipError_t launch_slater_t(const MeasureArgs& m, hipStream_t st, const Batch* bt
 #define VMC_DISPATCH_NS2(ns, CALL) \
   switch (ns) {                   \
     case 8: { constexpr int NSV = 8; CALL; } \
+    case 12: { constexpr int NSV = 12; CALL; } \
     case 16: { constexpr int NSV = 16; CALL; } \
+    case 20: { constexpr int NSV = 20; CALL; } \
+    case 24: { constexpr int NSV = 24; CALL; } \
     case 27: { constexpr int NSV = 27; CALL; } \
     case 32: { constexpr int NSV = 32; CALL; } \
     case 64: { constexpr int NSV = 64; CALL; } \

@@ -167,7 +167,9 @@ int dalloc(T** p, size_t n) {
   return e == hipSuccess ? VMC_OK : map_err(e);
 }
 
-bool supported_ns(int ns) { return ns == 8 || ns == 16 || ns == 27 || ns == 32 || ns == 64 || ns == 128; }
+bool supported_ns(int ns) {
+  return ns == 8 || ns == 12 || ns == 16 || ns == 20 || ns == 24 || ns == 27 || ns == 32 || ns == 64 || ns == 128;
+}
 
 constexpr double kContractedZ2 = 0.3382168;   // the smaller exponent of the contracted orbital
 
